@@ -1,0 +1,125 @@
+"""Seeded synthetic workloads.
+
+* hydrogen: one proton (V = -1/r) at a vertex in the centre of a Dirichlet
+  cube, with the hydrogen 1s and 2s radials as enrichments.
+* si_cluster: the n sites of a diamond lattice (a = 10.26 Bohr, an atom at
+  the origin) nearest the origin, each jittered, with a softened nuclear
+  potential -14/sqrt(r^2 + 0.01) per site and nine Slater-type enrichments
+  per atom (1s, 2s, 2p, 3s, 3p).
+* box: no potential and no enrichment (particle in a box).
+
+Random numbers come from numpy's PCG64 `default_rng(seed)`, drawn in the
+order: site jitter, Slater exponents, initial block.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .assemble import assemble
+from .enrich import EnrichmentSet, Radial
+from .mesh import build_mesh
+from .problem import Problem
+
+SI_LATTICE = 10.26
+SI_Z = 14.0
+SOFTEN = 0.01
+
+
+def diamond_sites(n_atoms: int, a: float = SI_LATTICE) -> np.ndarray:
+    """The n_atoms diamond-lattice sites nearest the origin (an atom sits there).
+
+    Sites are ordered by (distance rounded to 1e-9, x, y, z); ties on the last
+    shell are broken by that order.
+    """
+    fcc = np.array([[0, 0, 0], [0, 0.5, 0.5], [0.5, 0, 0.5], [0.5, 0.5, 0]])
+    basis = np.concatenate([fcc, fcc + 0.25])
+    reach = int(np.ceil((3.0 * n_atoms / (4.0 * np.pi * 8.0)) ** (1.0 / 3.0))) + 2
+    r = np.arange(-reach, reach + 1)
+    cz, cy, cx = np.meshgrid(r, r, r, indexing="ij")
+    cells = np.stack([cx.ravel(), cy.ravel(), cz.ravel()], axis=1).astype(np.float64)
+    pts = (cells[:, None, :] + basis[None, :, :]).reshape(-1, 3) * a
+    d = np.round(np.sqrt((pts ** 2).sum(axis=1)), 9)
+    order = np.lexsort((pts[:, 2], pts[:, 1], pts[:, 0], d))
+    return pts[order[:n_atoms]]
+
+
+def softened_potential(centers: np.ndarray, z: float = SI_Z, eps: float = SOFTEN):
+    def V(x: np.ndarray) -> np.ndarray:
+        out = np.zeros(x.shape[0])
+        for c in centers:
+            d = x - c[None, :]
+            out -= z / np.sqrt(np.einsum("qi,qi->q", d, d) + eps)
+        return out
+    return V
+
+
+def coulomb_potential(center, z: float = 1.0):
+    c = np.asarray(center, dtype=np.float64)
+
+    def V(x: np.ndarray) -> np.ndarray:
+        d = x - c[None, :]
+        return -z / np.sqrt(np.einsum("qi,qi->q", d, d))
+    return V
+
+
+def zero_potential(x: np.ndarray) -> np.ndarray:
+    return np.zeros(x.shape[0])
+
+
+def hydrogen(nc: int = 8, length: float = 20.0, p: int = 4, r_c: float = 6.0,
+             enrich: bool = True, **kw) -> Problem:
+    mesh = build_mesh(p, nc, -0.5 * length, length)
+    enr = None
+    if enrich:
+        enr = EnrichmentSet(centers=np.zeros((1, 3)),
+                            shells=[Radial("h1s"), Radial("h2s")], r_c=r_c)
+    prob = assemble(mesh, coulomb_potential([0.0, 0.0, 0.0]), enr, **kw)
+    prob.meta.update(kind="hydrogen", r_c=r_c, mesh=mesh, enr=enr)
+    return prob
+
+
+def box(nc: int = 2, length: float = 2.0, p: int = 4, **kw) -> Problem:
+    mesh = build_mesh(p, nc, -0.5 * length, length)
+    prob = assemble(mesh, zero_potential, None, **kw)
+    prob.meta.update(kind="box", mesh=mesh)
+    return prob
+
+
+def si_shells(rng: np.random.Generator, lo: float = 0.5, hi: float = 14.0) -> list:
+    z = np.sort(rng.uniform(lo, hi, 5))[::-1]
+    return [Radial("slater", n=1, zeta=float(z[0]), l=0),
+            Radial("slater", n=2, zeta=float(z[1]), l=0),
+            Radial("slater", n=2, zeta=float(z[2]), l=1),
+            Radial("slater", n=3, zeta=float(z[3]), l=0),
+            Radial("slater", n=3, zeta=float(z[4]), l=1)]
+
+
+def si_cluster(n_atoms: int = 30, length: float = 48.0, nc: int = 24, p: int = 4,
+               r_c: float = 8.0, seed: int = 0, jitter: float = 0.05, **kw) -> Problem:
+    rng = np.random.default_rng(seed)
+    sites = diamond_sites(n_atoms)
+    sites = sites + rng.uniform(-jitter, jitter, sites.shape)
+    shells = si_shells(rng)
+    mesh = build_mesh(p, nc, -0.5 * length, length)
+    enr = EnrichmentSet(centers=sites, shells=shells, r_c=r_c)
+    prob = assemble(mesh, softened_potential(sites), enr, **kw)
+    prob.meta.update(kind="si", sites=sites, shells=shells, r_c=r_c, mesh=mesh, enr=enr,
+                     seed=seed, rng=rng)
+    return prob
+
+
+# Named workloads (sizes of the paper-shaped synthetic configurations).
+def config1(**kw) -> Problem:
+    """Hydrogen, 20 Bohr cube, 8^3 cells of degree 4, r_c = 6 (N = 16, m = 20)."""
+    return hydrogen(nc=8, length=20.0, p=4, r_c=6.0, **kw)
+
+
+def config2(seed: int = 0, **kw) -> Problem:
+    """30-atom Si cluster, 48 Bohr cube, 24^3 cells of degree 4, r_c = 8 (N = 260, m = 40)."""
+    return si_cluster(n_atoms=30, length=48.0, nc=24, p=4, r_c=8.0, seed=seed, **kw)
+
+
+WORKLOADS = {
+    "hydrogen-8c": dict(N=16, m=20, wanted=14),
+    "si30-24c": dict(N=260, m=40, wanted=210),
+}

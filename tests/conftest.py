@@ -1,0 +1,56 @@
+import os
+import sys
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X (runs through the HIP library)")
+    config.addinivalue_line("markers", "slow: several seconds of CPU work")
+
+
+_CACHE = {}
+
+
+def cached(key, fn):
+    if key not in _CACHE:
+        _CACHE[key] = fn()
+    return _CACHE[key]
+
+
+@pytest.fixture(scope="session")
+def hydrogen_small():
+    """Hydrogen on 4^3 cells of degree 4 (n ~ 4k), enriched."""
+    from synth import configs
+    return cached("h4", lambda: configs.hydrogen(nc=4, length=20.0, p=4, r_c=6.0))
+
+
+@pytest.fixture(scope="session")
+def hydrogen_cfg1():
+    """The 8^3-cell hydrogen workload (n = 29,793)."""
+    from synth import configs
+    return cached("h8", lambda: configs.config1())
+
+
+@pytest.fixture(scope="session")
+def si_small():
+    """Small Si cluster: 5 atoms, 26 Bohr cube, 8^3 cells (n ~ 33k, n_e = 45)."""
+    from synth import configs
+    return cached("si5", lambda: configs.si_cluster(n_atoms=5, length=26.0, nc=8, p=4, r_c=8.0,
+                                                    seed=3))
+
+
+@pytest.fixture(scope="session")
+def tiny_enriched():
+    """Brute-force sized problem: 2^3 cells of degree 2, one atom, 2 enrichments (n ~ 30)."""
+    from synth import configs
+    return cached("tiny", lambda: configs.hydrogen(nc=2, length=8.0, p=2, r_c=3.0))
+
+
+def rng(seed=0):
+    return np.random.default_rng(seed)

@@ -1,0 +1,152 @@
+/*
+ * chebfilter.h - C ABI of the MI355X (gfx950) Chebyshev-filtered subspace
+ * iteration for the enriched spectral finite-element Kohn-Sham problem
+ * (Kanungo & Gavini, "Large-scale all-electron density functional theory
+ * calculations using an enriched finite element basis").
+ *
+ * Discrete problem (Sec. IV.A, Eq. SEPEFEM, H2x2, M2x2):
+ *   H^E = [[H^cc, H^ec^T], [H^ec, H^ee]],  M^E = [[M^cc, M^ec^T], [M^ec, M^ee]]
+ * with the free classical DOFs first (n_h of them) and the enrichment DOFs
+ * last (n_e).  M^cc is the GLL-lumped diagonal (Sec. III.B).  The library
+ * works on the standard form H~ = (M^E)^-1 H^E (Sec. V) and never assembles
+ * a global matrix: H^cc and H^ec/M^ec enter only as per-cell blocks
+ * (Sec. V, matrix-free elemental products followed by assembly).
+ *
+ * Conventions for every entry point:
+ *  - Return value is cf_status; CF_OK = 0.  Nothing aborts, throws or prints;
+ *    chebfilter_last_error() returns a message for the last failure.
+ *  - Block arguments (X, Y) are DEVICE pointers to FP64 matrices, row-major
+ *    [n][ld] with n = n_h + n_e rows (classical rows first) and ld >= N
+ *    columns; the caller owns them.  Y must not overlap X.
+ *  - Work is enqueued on the context's stream and is asynchronous unless an
+ *    entry point says it synchronises.  Calls on one context must not
+ *    overlap (the context is not thread-safe).
+ *  - The library keeps no caller pointer after a call returns.
+ */
+#ifndef CHEBFILTER_H
+#define CHEBFILTER_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cf_ctx cf_ctx;
+
+typedef enum {
+  CF_OK = 0,
+  CF_EINVAL = 1,     /* invalid argument (sizes, indices, bounds, pointers)   */
+  CF_ENOMEM = 2,     /* device allocation failed or N above max_cols          */
+  CF_ENOTSPD = 3,    /* Schur complement / Gram / projected overlap not SPD   */
+  CF_ENUMERIC = 4,   /* NaN/Inf detected                                      */
+  CF_EDEVICE = 5,    /* HIP runtime or library error                          */
+  CF_ENOTCONV = 6    /* eigensolver did not converge                          */
+} cf_status;
+
+typedef enum { CF_FP64 = 0, CF_FP32 = 1, CF_BF16 = 2 } cf_prec;
+
+/* Discrete problem.  HOST pointers, read during chebfilter_init only.
+ * npc = (p+1)^3 local nodes per cell, x fastest. */
+typedef struct {
+  int32_t p;                 /* element degree; this build supports 1 <= p <= 4       */
+  int64_t n_cells;           /* E                                                      */
+  int64_t n_h;               /* free classical DOFs                                    */
+  int64_t n_e;               /* enrichment DOFs                                        */
+  const int64_t *cell_dof;   /* [E*npc] free classical DOF of each local node, -1 marks
+                                a Dirichlet node (Sec. III.A, homogeneous Dirichlet)  */
+  const double *H_cc;        /* [E*npc*npc] elemental H^cc_e, row-major, symmetric
+                                (Eq. Hcc)                                              */
+  const double *M_cc_diag;   /* [n_h] assembled GLL-lumped M^cc, all > 0 (Sec. III.B) */
+  const int64_t *enr_ptr;    /* [E+1] CSR over cells: enrichment functions whose support
+                                meets the cell                                         */
+  const int64_t *enr_idx;    /* [enr_ptr[E]] alpha in [0, n_e), distinct within a cell */
+  const double *H_ec;        /* [enr_ptr[E]*npc] per-cell H^ec_e rows (row alpha,
+                                column local node) (Eq. Hec)                           */
+  const double *M_ec;        /* [enr_ptr[E]*npc] per-cell M^ec_e rows (Eq. Mec)        */
+  const double *H_ee;        /* [n_e*n_e] assembled H^ee, symmetric (Eq. Hee)          */
+  const double *M_ee;        /* [n_e*n_e] assembled M^ee, symmetric (Eq. Mee)          */
+} cf_problem;
+
+typedef struct {
+  int32_t device;            /* HIP device ordinal                                     */
+  void *stream;              /* hipStream_t to enqueue on (NULL = default stream)      */
+  int64_t max_cols;          /* largest block width N any later call may pass          */
+  int32_t check_finite;      /* nonzero: filter/rayleigh_ritz check outputs for NaN/Inf */
+} cf_options;
+
+/* Build a context: validate the problem, upload element data, colour cells so
+ * that cells of one colour share no DOF, form the Schur complement
+ * S = M^ee - M^ec (M^cc)^-1 M^ec^T (Sec. IV.D) in FP64 on the device and
+ * factor it.  Returns CF_ENOTSPD if S is not positive definite, CF_EINVAL for
+ * malformed input, CF_ENOMEM if workspace for max_cols columns does not fit.
+ * Synchronises.  On failure *out is NULL. */
+cf_status chebfilter_init(const cf_problem *prob, const cf_options *opt, cf_ctx **out);
+
+/* Release every device buffer of the context.  NULL is accepted. */
+cf_status chebfilter_destroy(cf_ctx *ctx);
+
+/* Message describing the last failure on ctx (or of the last failed init when
+ * ctx is NULL).  Valid until the next call on the same context. */
+const char *chebfilter_last_error(const cf_ctx *ctx);
+
+/* Problem sizes as seen by the library (n = n_h + n_e). */
+cf_status chebfilter_sizes(const cf_ctx *ctx, int64_t *n_h, int64_t *n_e, int64_t *max_cols);
+
+/* Y = H^E X  (Eq. H2x2; elemental products + assembly, Sec. V).  0 <= N <= max_cols. */
+cf_status chebfilter_apply_H(cf_ctx *ctx, const double *X, int64_t ldx, double *Y, int64_t ldy,
+                             int64_t N);
+
+/* Y = M^E X  (Eq. M2x2). */
+cf_status chebfilter_apply_M(cf_ctx *ctx, const double *X, int64_t ldx, double *Y, int64_t ldy,
+                             int64_t N);
+
+/* Y = (M^E)^-1 X by the block-wise (Banachiewicz) inverse of Sec. IV.D:
+ * u = D^-1 x_c, w = x_e - M^ec u, z = S^-1 w, y_e = z, y_c = u - D^-1 M^ec^T z,
+ * with D = M^cc diagonal and S the Schur complement.  The S solve is FP64. */
+cf_status chebfilter_apply_Sinv(cf_ctx *ctx, const double *X, int64_t ldx, double *Y,
+                                int64_t ldy, int64_t N);
+
+/* Y = T_m(t(H~)) X, t(x) = (2x - a - b)/(b - a), H~ = (M^E)^-1 H^E, by the
+ * three-term Chebyshev recurrence (Sec. V).  m = 0 copies X.  Requires b > a,
+ * both finite, m >= 0.  prec selects the arithmetic of the elemental products
+ * (CF_FP64 only in this build; other values return CF_EINVAL). */
+cf_status chebfilter_filter(cf_ctx *ctx, const double *X, int64_t ldx, double *Y, int64_t ldy,
+                            int64_t N, int32_t m, double a, double b, int32_t prec);
+
+/* In place: Y <- Q with Q^T Q = I and span(Q) = span(Y), by Cholesky-QR
+ * applied twice after scaling columns to unit length (the orthonormalisation
+ * step of Sec. V).  Falls back to a shifted first pass if the Gram matrix is
+ * not numerically positive definite.  Synchronises; CF_ENOTSPD if even the
+ * shifted pass fails (e.g. a zero column). */
+cf_status chebfilter_cholqr(cf_ctx *ctx, double *Y, int64_t ldy, int64_t N);
+
+/* In place Rayleigh-Ritz (Sec. V): orthonormalise Y (as chebfilter_cholqr),
+ * project H^E and M^E onto it, solve the N x N generalized symmetric problem
+ * Q^T H Q c = theta Q^T M Q c and rotate: Y <- Q C.  On return Y holds
+ * M-orthonormal Ritz vectors and theta_host[0..N) the Ritz values in
+ * ascending order (host memory).  Synchronises. */
+cf_status chebfilter_rayleigh_ritz(cf_ctx *ctx, double *Y, int64_t ldy, int64_t N,
+                                   double *theta_host);
+
+/* k-step Lanczos on H~ in the M^E inner product (H~ is self-adjoint there,
+ * so the "few Arnoldi iterations" of Sec. V reduce to Lanczos), started from
+ * the device vector v0[n].  Returns on the host the smallest Ritz value of the
+ * k x k tridiagonal (*lmin_est) and the upper bound theta_max + ||f_k||_M
+ * (*b_upper).  1 <= k <= 64.  Synchronises. */
+cf_status chebfilter_lanczos_bounds(cf_ctx *ctx, const double *v0, int32_t k, double *lmin_est,
+                                    double *b_upper);
+
+/* Per-kernel timing with HIP events on the context's stream.  enable != 0
+ * starts recording (and clears the totals); name selects a kernel family
+ * ("cell_gemm", "enr_gemm", "gram", "rotate", "epilogue").  Synchronises on
+ * query. */
+cf_status chebfilter_profile(cf_ctx *ctx, int32_t enable);
+cf_status chebfilter_profile_query(cf_ctx *ctx, const char *name, int64_t *launches,
+                                   double *total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CHEBFILTER_H */

@@ -1,0 +1,11 @@
+"""MI355X (gfx950) Chebyshev-filtered subspace iteration for the enriched
+spectral finite-element Kohn-Sham problem.
+
+The compute path is the HIP library `libchebfilter.so` (C ABI in
+include/chebfilter.h); this package only binds it.  Importing the binding
+never falls back to any other implementation: if the library is missing,
+`load_library()` raises.
+"""
+from .binding import ChebFilterError, Context, load_library  # noqa: F401
+
+__all__ = ["Context", "ChebFilterError", "load_library"]

@@ -1,0 +1,198 @@
+"""ctypes binding of libchebfilter.so: argument marshalling only.
+
+Every entry point forwards to the C ABI declared in include/chebfilter.h; all
+arithmetic runs in the library's HIP kernels.  Blocks are torch float64 CUDA
+(HIP) tensors of shape [n, N] whose rows are contiguous (stride(1) == 1); the
+row stride is passed as the leading dimension.  The library enqueues on the
+torch stream that was current when the context was created.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libchebfilter.so")
+
+CF_STATUS = {0: "CF_OK", 1: "CF_EINVAL", 2: "CF_ENOMEM", 3: "CF_ENOTSPD", 4: "CF_ENUMERIC",
+             5: "CF_EDEVICE", 6: "CF_ENOTCONV"}
+PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
+
+EXPORTS = ["chebfilter_init", "chebfilter_destroy", "chebfilter_last_error", "chebfilter_sizes",
+           "chebfilter_apply_H", "chebfilter_apply_M", "chebfilter_apply_Sinv",
+           "chebfilter_filter", "chebfilter_cholqr", "chebfilter_rayleigh_ritz",
+           "chebfilter_lanczos_bounds", "chebfilter_profile", "chebfilter_profile_query"]
+
+
+class CfProblem(C.Structure):
+    _fields_ = [("p", C.c_int32), ("n_cells", C.c_int64), ("n_h", C.c_int64), ("n_e", C.c_int64),
+                ("cell_dof", C.c_void_p), ("H_cc", C.c_void_p), ("M_cc_diag", C.c_void_p),
+                ("enr_ptr", C.c_void_p), ("enr_idx", C.c_void_p), ("H_ec", C.c_void_p),
+                ("M_ec", C.c_void_p), ("H_ee", C.c_void_p), ("M_ee", C.c_void_p)]
+
+
+class CfOptions(C.Structure):
+    _fields_ = [("device", C.c_int32), ("stream", C.c_void_p), ("max_cols", C.c_int64),
+                ("check_finite", C.c_int32)]
+
+
+class ChebFilterError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{CF_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load_library() -> C.CDLL:
+    """Load the built library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_1610_02121_amd/build.py")
+    lib = C.CDLL(LIB_PATH)
+    vp, i64, i32, dbl = C.c_void_p, C.c_int64, C.c_int32, C.c_double
+    lib.chebfilter_init.argtypes = [C.POINTER(CfProblem), C.POINTER(CfOptions), C.POINTER(vp)]
+    lib.chebfilter_destroy.argtypes = [vp]
+    lib.chebfilter_last_error.argtypes = [vp]
+    lib.chebfilter_last_error.restype = C.c_char_p
+    lib.chebfilter_sizes.argtypes = [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)]
+    for nm in ("chebfilter_apply_H", "chebfilter_apply_M", "chebfilter_apply_Sinv"):
+        getattr(lib, nm).argtypes = [vp, vp, i64, vp, i64, i64]
+    lib.chebfilter_filter.argtypes = [vp, vp, i64, vp, i64, i64, i32, dbl, dbl, i32]
+    lib.chebfilter_cholqr.argtypes = [vp, vp, i64, i64]
+    lib.chebfilter_rayleigh_ritz.argtypes = [vp, vp, i64, i64, vp]
+    lib.chebfilter_lanczos_bounds.argtypes = [vp, vp, i32, C.POINTER(dbl), C.POINTER(dbl)]
+    lib.chebfilter_profile.argtypes = [vp, i32]
+    lib.chebfilter_profile_query.argtypes = [vp, C.c_char_p, C.POINTER(i64), C.POINTER(dbl)]
+    for nm in EXPORTS:
+        if nm != "chebfilter_last_error":
+            getattr(lib, nm).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def _np(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def _block(t, name: str):
+    import torch
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda:
+        raise TypeError(f"{name} must be a float64 CUDA tensor")
+    if t.dim() != 2 or (t.shape[1] > 1 and t.stride(1) != 1):
+        raise ValueError(f"{name} must be 2-D with contiguous rows")
+    return t.data_ptr(), t.stride(0) if t.shape[1] > 1 else max(t.stride(0), 1)
+
+
+class Context:
+    """One discrete problem resident on one GPU (wraps cf_ctx)."""
+
+    def __init__(self, prob, max_cols: int, device: int = 0, check_finite: bool = False):
+        import torch
+        self.lib = load_library()
+        self._keep = {
+            "cell_dof": _np(prob.cell_dof, np.int64), "H_cc": _np(prob.H_cc, np.float64),
+            "M_cc_diag": _np(prob.M_cc_diag, np.float64), "enr_ptr": _np(prob.enr_ptr, np.int64),
+            "enr_idx": _np(prob.enr_idx, np.int64), "H_ec": _np(prob.H_ec, np.float64),
+            "M_ec": _np(prob.M_ec, np.float64), "H_ee": _np(prob.H_ee, np.float64),
+            "M_ee": _np(prob.M_ee, np.float64)}
+        k = self._keep
+        n_cells = k["cell_dof"].shape[0]
+        cp = CfProblem(int(prob.p), n_cells, k["M_cc_diag"].shape[0], k["H_ee"].shape[0],
+                       *[k[f].ctypes.data for f in ("cell_dof", "H_cc", "M_cc_diag", "enr_ptr",
+                                                    "enr_idx", "H_ec", "M_ec", "H_ee", "M_ee")])
+        self.device = torch.device("cuda", device)
+        stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        opt = CfOptions(device, C.c_void_p(stream.cuda_stream), int(max_cols), int(check_finite))
+        h = C.c_void_p()
+        st = self.lib.chebfilter_init(C.byref(cp), C.byref(opt), C.byref(h))
+        if st != 0:
+            raise ChebFilterError(st, self.lib.chebfilter_last_error(None).decode())
+        self._h = h
+        self._keep = None
+        nh, ne, mc = C.c_int64(), C.c_int64(), C.c_int64()
+        self.lib.chebfilter_sizes(h, C.byref(nh), C.byref(ne), C.byref(mc))
+        self.n_h, self.n_e, self.max_cols = nh.value, ne.value, mc.value
+        self.n = self.n_h + self.n_e
+
+    def _check(self, st: int):
+        if st != 0:
+            raise ChebFilterError(st, self.lib.chebfilter_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.lib.chebfilter_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _out(self, X, Y):
+        import torch
+        if Y is None:
+            Y = torch.empty_like(X)
+        return Y
+
+    def apply_H(self, X, Y=None):
+        Y = self._out(X, Y)
+        (xp, ldx), (yp, ldy) = _block(X, "X"), _block(Y, "Y")
+        self._check(self.lib.chebfilter_apply_H(self._h, xp, ldx, yp, ldy, X.shape[1]))
+        return Y
+
+    def apply_M(self, X, Y=None):
+        Y = self._out(X, Y)
+        (xp, ldx), (yp, ldy) = _block(X, "X"), _block(Y, "Y")
+        self._check(self.lib.chebfilter_apply_M(self._h, xp, ldx, yp, ldy, X.shape[1]))
+        return Y
+
+    def apply_Sinv(self, X, Y=None):
+        Y = self._out(X, Y)
+        (xp, ldx), (yp, ldy) = _block(X, "X"), _block(Y, "Y")
+        self._check(self.lib.chebfilter_apply_Sinv(self._h, xp, ldx, yp, ldy, X.shape[1]))
+        return Y
+
+    def filter(self, X, m: int, a: float, b: float, Y=None, prec: str = "fp64"):
+        Y = self._out(X, Y)
+        (xp, ldx), (yp, ldy) = _block(X, "X"), _block(Y, "Y")
+        self._check(self.lib.chebfilter_filter(self._h, xp, ldx, yp, ldy, X.shape[1], int(m),
+                                               float(a), float(b), PREC[prec]))
+        return Y
+
+    def cholqr(self, Y):
+        yp, ldy = _block(Y, "Y")
+        self._check(self.lib.chebfilter_cholqr(self._h, yp, ldy, Y.shape[1]))
+        return Y
+
+    def rayleigh_ritz(self, Y) -> np.ndarray:
+        yp, ldy = _block(Y, "Y")
+        theta = np.zeros(max(Y.shape[1], 1), dtype=np.float64)
+        self._check(self.lib.chebfilter_rayleigh_ritz(self._h, yp, ldy, Y.shape[1],
+                                                      theta.ctypes.data))
+        return theta[:Y.shape[1]]
+
+    def lanczos_bounds(self, v0, k: int = 10) -> tuple[float, float]:
+        import torch
+        if v0.dtype != torch.float64 or not v0.is_cuda or not v0.is_contiguous():
+            raise TypeError("v0 must be a contiguous float64 CUDA tensor")
+        lo, hi = C.c_double(), C.c_double()
+        self._check(self.lib.chebfilter_lanczos_bounds(self._h, v0.data_ptr(), int(k),
+                                                       C.byref(lo), C.byref(hi)))
+        return lo.value, hi.value
+
+    def profile(self, enable: bool):
+        self._check(self.lib.chebfilter_profile(self._h, int(enable)))
+
+    def profile_query(self, name: str) -> tuple[int, float]:
+        n, ms = C.c_int64(), C.c_double()
+        self._check(self.lib.chebfilter_profile_query(self._h, name.encode(), C.byref(n),
+                                                      C.byref(ms)))
+        return n.value, ms.value

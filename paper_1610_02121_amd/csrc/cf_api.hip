@@ -1,0 +1,845 @@
+// C ABI of the Chebyshev-filter library: validation, device data layout,
+// colouring, Schur-complement setup and the drivers of the hot path
+// (H X, M X, (M^E)^-1 X, the Chebyshev filter, Cholesky-QR, Rayleigh-Ritz,
+// Lanczos bounds).  Every arithmetic step runs in the kernels of cf_ops.hip
+// and cf_dense.hip; the small dense generalized eigenproblem of the
+// Rayleigh-Ritz step is solved on the device by rocSOLVER (dsygvd).
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "chebfilter.h"
+#include "cf_kernels.h"
+
+using namespace cf;
+
+namespace {
+
+struct ProfEntry {
+  int64_t launches = 0;
+  double ms = 0.0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+};
+
+thread_local std::string g_init_error;
+
+}  // namespace
+
+struct cf_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int p = 0, npc = 0;
+  int64_t E = 0, n_h = 0, n_e = 0, n = 0, max_cols = 0;
+  int check_finite = 0;
+  // classical cells
+  double *Hp = nullptr;
+  int32_t *dofp = nullptr;
+  uint8_t *firstp = nullptr;
+  double *dvec = nullptr, *dinv = nullptr;
+  int32_t *cells = nullptr;
+  std::vector<int> col_off;
+  // enrichment
+  int64_t nnz = 0;
+  int kmax = 0;
+  double *Hec = nullptr, *Mec = nullptr;
+  int64_t *eptr = nullptr;
+  int32_t *eidx = nullptr;
+  int32_t *ecells = nullptr;
+  std::vector<int> ecol_off;
+  int64_t *aptr = nullptr;
+  int32_t *alist = nullptr;
+  double *Hee = nullptr, *Mee = nullptr, *Sinv = nullptr;
+  // block workspace, leading dimension max_cols
+  double *R = nullptr, *P = nullptr, *Wb = nullptr, *Zb = nullptr, *B2 = nullptr, *T = nullptr,
+         *U = nullptr;
+  // small dense workspace
+  double *G = nullptr, *Gp = nullptr, *Wm = nullptr, *Wt = nullptr, *sv = nullptr, *Hh = nullptr,
+         *Mh = nullptr, *theta = nullptr, *evE = nullptr;
+  int gp_chunks = 8;
+  int *flag = nullptr;
+  rocblas_int *info = nullptr;
+  // Lanczos
+  double *lzv = nullptr, *lzcoef = nullptr, *lzpart = nullptr;
+  rocblas_handle rb = nullptr;
+  std::string err;
+  bool profiling = false;
+  std::map<std::string, ProfEntry> prof;
+  std::vector<void *> allocs;
+};
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+static cf_status set_err(cf_ctx *c, cf_status st, const std::string &msg) {
+  if (c) c->err = msg; else g_init_error = msg;
+  return st;
+}
+
+#define HIPCHK(ctx, call)                                                                     \
+  do {                                                                                        \
+    hipError_t e_ = (call);                                                                   \
+    if (e_ != hipSuccess)                                                                     \
+      return set_err(ctx, CF_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));     \
+  } while (0)
+
+#define STCHK(call)                     \
+  do {                                  \
+    cf_status s_ = (call);              \
+    if (s_ != CF_OK) return s_;         \
+  } while (0)
+
+template <typename T>
+static cf_status dalloc(cf_ctx *c, T **p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  void *q = nullptr;
+  hipError_t e = hipMalloc(&q, count * sizeof(T));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return set_err(c, CF_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+  }
+  c->allocs.push_back(q);
+  *p = static_cast<T *>(q);
+  return CF_OK;
+}
+
+// Event-timed kernel family (only when profiling is on).
+struct Scope {
+  cf_ctx *c;
+  const char *name;
+  hipEvent_t a = nullptr, b = nullptr;
+  Scope(cf_ctx *c_, const char *n) : c(c_), name(n) {
+    if (c->profiling && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess)
+      (void)hipEventRecord(a, c->stream);
+  }
+  ~Scope() {
+    if (c->profiling && a && b) {
+      (void)hipEventRecord(b, c->stream);
+      c->prof[name].pending.emplace_back(a, b);
+    }
+  }
+};
+
+static cf_status check_block(cf_ctx *c, const void *X, int64_t ldx, int64_t N, const char *nm) {
+  if (N < 0 || N > c->max_cols)
+    return set_err(c, N < 0 ? CF_EINVAL : CF_ENOMEM,
+                   std::string(nm) + ": N out of range [0, max_cols]");
+  if (N > 0 && (X == nullptr || ldx < N))
+    return set_err(c, CF_EINVAL, std::string(nm) + ": null block or ld < N");
+  return CF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// operator cores (all enqueue on c->stream)
+// ---------------------------------------------------------------------------
+// Y = H^E X (Y rows: n, ld ldy)
+static cf_status core_apply_H(cf_ctx *c, const double *X, int64_t ldx, double *Y, int64_t ldy,
+                              int N) {
+  for (size_t k = 0; k + 1 < c->col_off.size(); ++k) {
+    Scope sc(c, "cell_gemm");
+    HIPCHK(c, launch_cell_gemm(c->stream, c->Hp, c->dofp, c->firstp, c->cells + c->col_off[k],
+                               c->col_off[k + 1] - c->col_off[k], X, ldx, Y, ldy, N));
+  }
+  if (c->n_e == 0) return CF_OK;
+  const double *Xe = X + c->n_h * ldx;
+  Scope sc(c, "enr_gemm");
+  for (size_t k = 0; k + 1 < c->ecol_off.size(); ++k)
+    HIPCHK(c, launch_enr_T(c->stream, c->Hec, c->eptr, c->eidx, c->dofp, c->ecells + c->ecol_off[k],
+                           c->ecol_off[k + 1] - c->ecol_off[k], c->kmax, Xe, ldx, Y, ldy, N, 1.0));
+  const int ne_cells = c->ecol_off.back();
+  HIPCHK(c, launch_enr_N(c->stream, c->Hec, c->eptr, c->dofp, c->ecells, ne_cells, X, ldx, nullptr,
+                         c->P, c->max_cols, N));
+  HIPCHK(c, launch_enr_reduce(c->stream, (int)c->n_e, c->aptr, c->alist, c->P, c->max_cols, 1.0,
+                              nullptr, 0, 0.0, c->Hee, Xe, ldx, Y + c->n_h * ldy, ldy, N));
+  return CF_OK;
+}
+
+// Y = M^E X
+static cf_status core_apply_M(cf_ctx *c, const double *X, int64_t ldx, double *Y, int64_t ldy,
+                              int N) {
+  HIPCHK(c, launch_diag_scale(c->stream, c->n_h, c->dvec, X, ldx, Y, ldy, N));
+  if (c->n_e == 0) return CF_OK;
+  const double *Xe = X + c->n_h * ldx;
+  Scope sc(c, "enr_gemm");
+  for (size_t k = 0; k + 1 < c->ecol_off.size(); ++k)
+    HIPCHK(c, launch_enr_T(c->stream, c->Mec, c->eptr, c->eidx, c->dofp, c->ecells + c->ecol_off[k],
+                           c->ecol_off[k + 1] - c->ecol_off[k], c->kmax, Xe, ldx, Y, ldy, N, 1.0));
+  const int ne_cells = c->ecol_off.back();
+  HIPCHK(c, launch_enr_N(c->stream, c->Mec, c->eptr, c->dofp, c->ecells, ne_cells, X, ldx, nullptr,
+                         c->P, c->max_cols, N));
+  HIPCHK(c, launch_enr_reduce(c->stream, (int)c->n_e, c->aptr, c->alist, c->P, c->max_cols, 1.0,
+                              nullptr, 0, 0.0, c->Mee, Xe, ldx, Y + c->n_h * ldy, ldy, N));
+  return CF_OK;
+}
+
+// Block-wise inverse (Sec. IV.D) on R (n rows, ld ldr), in place on the
+// classical rows: afterwards (M^E)^-1 r = [dinv .* R_c ; z] with z in Zb
+// (ld max_cols).  Steps: u = D^-1 r_c; w = r_e - M^ec u; z = S^-1 w;
+// r_c <- r_c - M^ec^T z (the final D^-1 is applied by the caller's epilogue).
+static cf_status core_sinv(cf_ctx *c, double *R, int64_t ldr, int N) {
+  if (c->n_e == 0) return CF_OK;
+  Scope sc(c, "enr_gemm");
+  const int ne_cells = c->ecol_off.back();
+  HIPCHK(c, launch_enr_N(c->stream, c->Mec, c->eptr, c->dofp, c->ecells, ne_cells, R, ldr, c->dinv,
+                         c->P, c->max_cols, N));
+  HIPCHK(c, launch_enr_reduce(c->stream, (int)c->n_e, c->aptr, c->alist, c->P, c->max_cols, -1.0,
+                              R + c->n_h * ldr, ldr, 1.0, nullptr, nullptr, 0, c->Wb, c->max_cols,
+                              N));
+  HIPCHK(c, launch_enr_reduce(c->stream, (int)c->n_e, c->aptr, c->alist, nullptr, 0, 0.0, nullptr, 0,
+                              0.0, c->Sinv, c->Wb, c->max_cols, c->Zb, c->max_cols, N));
+  for (size_t k = 0; k + 1 < c->ecol_off.size(); ++k)
+    HIPCHK(c, launch_enr_T(c->stream, c->Mec, c->eptr, c->eidx, c->dofp, c->ecells + c->ecol_off[k],
+                           c->ecol_off[k + 1] - c->ecol_off[k], c->kmax, c->Zb, c->max_cols, R, ldr,
+                           N, -1.0));
+  return CF_OK;
+}
+
+// Out = c1 * H~ Xin + c2 * Yk + c3 * Yp   (H~ = (M^E)^-1 H^E), via R and Zb.
+static cf_status core_htilde_step(cf_ctx *c, const double *Xin, int64_t ldxin, int N, double c1,
+                                  const double *Yk, int64_t ldyk, double c2, const double *Yp,
+                                  int64_t ldyp, double c3, double *Out, int64_t ldo) {
+  const int64_t ldr = c->max_cols;
+  STCHK(core_apply_H(c, Xin, ldxin, c->R, ldr, N));
+  STCHK(core_sinv(c, c->R, ldr, N));
+  Scope sc(c, "epilogue");
+  HIPCHK(c, launch_epilogue(c->stream, c->n_h, c->n_e, c->dinv, c->R, ldr, c->Zb, c->max_cols, c1,
+                            Yk, ldyk, c2, Yp, ldyp, c3, Out, ldo, N));
+  return CF_OK;
+}
+
+// Gram G = A^T B (N x N, ld N) through the chunked partial kernel.
+static cf_status core_gram(cf_ctx *c, const double *A, int64_t lda, const double *B, int64_t ldb,
+                           int64_t nrows, int N, double *Gout, int upper) {
+  Scope sc(c, "gram");
+  const int nch = c->gp_chunks;
+  const int64_t chunk_rows = (nrows + nch - 1) / nch;
+  HIPCHK(c, launch_gram_partial(c->stream, A, lda, B, ldb, nrows, N, nch, chunk_rows, c->Gp, upper));
+  HIPCHK(c, launch_gram_reduce(c->stream, c->Gp, nch, N, Gout, upper));
+  return CF_OK;
+}
+
+// One Cholesky-QR pass In -> Out (Out = In * S * L^-T, G' = S In^T In S = L L^T).
+static cf_status core_cholqr_pass(cf_ctx *c, const double *In, int64_t ldi, double *Out,
+                                  int64_t ldo, int N, double shift, int *failed) {
+  STCHK(core_gram(c, In, ldi, In, ldi, c->n, N, c->G, 1));
+  HIPCHK(c, hipMemsetAsync(c->flag, 0, sizeof(int), c->stream));
+  HIPCHK(c, launch_cholesky(c->stream, c->G, N, 1, shift, c->sv, c->flag));
+  int h_flag = 0;
+  HIPCHK(c, hipMemcpyAsync(&h_flag, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  *failed = h_flag;
+  if (h_flag) return CF_OK;
+  HIPCHK(c, launch_tri_inv_T(c->stream, c->G, c->sv, N, c->Wm));
+  Scope sc(c, "rotate");
+  HIPCHK(c, launch_rotate(c->stream, In, ldi, c->n, N, c->Wm, N, 1, Out, ldo));
+  return CF_OK;
+}
+
+// Orthonormalise In into Out through the scratch blocks T and R (In may equal
+// Out; Out must not be T or R).
+static cf_status core_cholqr(cf_ctx *c, const double *In, int64_t ldi, double *Out, int64_t ldo,
+                             int N) {
+  const int64_t ldt = c->max_cols;
+  int failed = 0;
+  STCHK(core_cholqr_pass(c, In, ldi, c->T, ldt, N, 0.0, &failed));
+  if (failed) {
+    // shifted Cholesky-QR: shift of the unit-diagonal Gram by 11 (nN + N(N+1)) u N
+    const double u = 1.1102230246251565e-16;
+    const double shift = 11.0 * ((double)c->n * N + (double)N * (N + 1)) * u * N;
+    STCHK(core_cholqr_pass(c, In, ldi, c->T, ldt, N, shift, &failed));
+    if (failed)
+      return set_err(c, CF_ENOTSPD, "cholqr: Gram matrix not positive definite even with shift");
+    STCHK(core_cholqr_pass(c, c->T, ldt, c->R, ldt, N, 0.0, &failed));
+    if (failed) return set_err(c, CF_ENOTSPD, "cholqr: second pass failed after shift");
+    STCHK(core_cholqr_pass(c, c->R, ldt, Out, ldo, N, 0.0, &failed));
+  } else {
+    STCHK(core_cholqr_pass(c, c->T, ldt, Out, ldo, N, 0.0, &failed));
+  }
+  if (failed) return set_err(c, CF_ENOTSPD, "cholqr: second pass not positive definite");
+  return CF_OK;
+}
+
+static cf_status check_out_finite(cf_ctx *c, const double *Y, int64_t ldy, int N, const char *nm) {
+  if (!c->check_finite || N == 0) return CF_OK;
+  HIPCHK(c, hipMemsetAsync(c->flag, 0, sizeof(int), c->stream));
+  HIPCHK(c, launch_check_finite(c->stream, Y, ldy, c->n, N, c->flag));
+  int h = 0;
+  HIPCHK(c, hipMemcpyAsync(&h, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (h) return set_err(c, CF_ENUMERIC, std::string(nm) + ": non-finite values in the output");
+  return CF_OK;
+}
+
+static void free_ctx(cf_ctx *c) {
+  if (!c) return;
+  if (c->rb) rocblas_destroy_handle(c->rb);
+  for (auto &kv : c->prof)
+    for (auto &ev : kv.second.pending) {
+      (void)hipEventDestroy(ev.first);
+      (void)hipEventDestroy(ev.second);
+    }
+  for (void *q : c->allocs) (void)hipFree(q);
+  delete c;
+}
+
+// ---------------------------------------------------------------------------
+// init
+// ---------------------------------------------------------------------------
+static cf_status do_init(const cf_problem *pr, const cf_options *opt, cf_ctx *c) {
+  if (!pr || !opt) return set_err(c, CF_EINVAL, "init: null problem or options");
+  if (pr->p < 1 || pr->p > 4) return set_err(c, CF_EINVAL, "init: element degree must be 1..4");
+  const int npc = (pr->p + 1) * (pr->p + 1) * (pr->p + 1);
+  if (pr->n_cells < 1 || pr->n_h < 1 || pr->n_e < 0 || pr->n_h > (int64_t)INT32_MAX - 1 ||
+      pr->n_cells > (int64_t)INT32_MAX)
+    return set_err(c, CF_EINVAL, "init: bad sizes");
+  if (!pr->cell_dof || !pr->H_cc || !pr->M_cc_diag)
+    return set_err(c, CF_EINVAL, "init: null classical arrays");
+  if (pr->n_e > 0 && (!pr->enr_ptr || !pr->enr_idx || !pr->H_ec || !pr->M_ec || !pr->H_ee || !pr->M_ee))
+    return set_err(c, CF_EINVAL, "init: null enrichment arrays");
+  if (opt->max_cols < 1) return set_err(c, CF_EINVAL, "init: max_cols must be >= 1");
+  c->device = opt->device;
+  c->stream = (hipStream_t)opt->stream;
+  c->check_finite = opt->check_finite;
+  c->p = pr->p;
+  c->npc = npc;
+  c->E = pr->n_cells;
+  c->n_h = pr->n_h;
+  c->n_e = pr->n_e;
+  c->n = pr->n_h + pr->n_e;
+  c->max_cols = opt->max_cols;
+  HIPCHK(c, hipSetDevice(c->device));
+  const int64_t E = c->E, n_h = c->n_h, n_e = c->n_e;
+
+  // ---- classical validation, colouring and first-touch flags
+  std::vector<int32_t> dof((size_t)E * NPAD, -1);
+  std::vector<int> cover(n_h, 0);
+  for (int64_t e = 0; e < E; ++e) {
+    for (int a = 0; a < npc; ++a) {
+      const int64_t d = pr->cell_dof[e * npc + a];
+      if (d < -1 || d >= n_h) return set_err(c, CF_EINVAL, "init: cell_dof out of range");
+      dof[e * NPAD + a] = (int32_t)d;
+      if (d >= 0) {
+        if (cover[d] == (int)e + 1) return set_err(c, CF_EINVAL, "init: repeated DOF within a cell");
+        cover[d] = (int)e + 1;
+      }
+    }
+  }
+  for (int64_t d = 0; d < n_h; ++d)
+    if (cover[d] == 0) return set_err(c, CF_EINVAL, "init: a free DOF belongs to no cell");
+  for (int64_t d = 0; d < n_h; ++d) {
+    const double v = pr->M_cc_diag[d];
+    if (!(v > 0.0) || !std::isfinite(v)) return set_err(c, CF_EINVAL, "init: M_cc_diag must be > 0");
+  }
+  std::vector<uint64_t> used(n_h, 0);
+  std::vector<int> colour(E);
+  int ncol = 0;
+  for (int64_t e = 0; e < E; ++e) {
+    uint64_t mask = 0;
+    for (int a = 0; a < npc; ++a) {
+      const int32_t d = dof[e * NPAD + a];
+      if (d >= 0) mask |= used[d];
+    }
+    if (~mask == 0) return set_err(c, CF_EINVAL, "init: cell graph needs more than 64 colours");
+    const int col = __builtin_ctzll(~mask);
+    colour[e] = col;
+    ncol = std::max(ncol, col + 1);
+    for (int a = 0; a < npc; ++a) {
+      const int32_t d = dof[e * NPAD + a];
+      if (d >= 0) used[d] |= (1ull << col);
+    }
+  }
+  std::vector<int32_t> order;
+  order.reserve(E);
+  c->col_off.assign(1, 0);
+  for (int col = 0; col < ncol; ++col) {
+    for (int64_t e = 0; e < E; ++e)
+      if (colour[e] == col) order.push_back((int32_t)e);
+    c->col_off.push_back((int)order.size());
+  }
+  std::vector<uint8_t> first((size_t)E * NPAD, 0);
+  {
+    std::vector<uint8_t> touched(n_h, 0);
+    for (int32_t e : order)
+      for (int a = 0; a < npc; ++a) {
+        const int32_t d = dof[(int64_t)e * NPAD + a];
+        if (d >= 0 && !touched[d]) { touched[d] = 1; first[(int64_t)e * NPAD + a] = 1; }
+      }
+  }
+  STCHK(dalloc(c, &c->dofp, dof.size()));
+  STCHK(dalloc(c, &c->firstp, first.size()));
+  STCHK(dalloc(c, &c->cells, order.size()));
+  HIPCHK(c, hipMemcpy(c->dofp, dof.data(), dof.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->firstp, first.data(), first.size(), hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->cells, order.data(), order.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+
+  // ---- cell matrices: padded to NPAD x NPAD, symmetrised, checked
+  STCHK(dalloc(c, &c->Hp, (size_t)E * NPAD * NPAD));
+  {
+    const int64_t batch = 256;
+    std::vector<double> buf((size_t)batch * NPAD * NPAD);
+    for (int64_t e0 = 0; e0 < E; e0 += batch) {
+      const int64_t nb = std::min(batch, E - e0);
+      std::fill(buf.begin(), buf.begin() + nb * NPAD * NPAD, 0.0);
+      for (int64_t b = 0; b < nb; ++b) {
+        const double *H = pr->H_cc + (e0 + b) * npc * npc;
+        double *o = buf.data() + b * NPAD * NPAD;
+        double hmax = 0.0;
+        for (int64_t q = 0; q < (int64_t)npc * npc; ++q) {
+          if (!std::isfinite(H[q])) return set_err(c, CF_EINVAL, "init: non-finite H_cc");
+          hmax = std::max(hmax, std::fabs(H[q]));
+        }
+        for (int a = 0; a < npc; ++a)
+          for (int bb = 0; bb < npc; ++bb) {
+            const double x = H[a * npc + bb], y = H[bb * npc + a];
+            if (std::fabs(x - y) > 1e-10 * hmax)
+              return set_err(c, CF_EINVAL, "init: H_cc block not symmetric");
+            o[a * NPAD + bb] = 0.5 * (x + y);
+          }
+      }
+      HIPCHK(c, hipMemcpy(c->Hp + e0 * NPAD * NPAD, buf.data(), nb * NPAD * NPAD * sizeof(double),
+                          hipMemcpyHostToDevice));
+    }
+  }
+  {
+    std::vector<double> dv(pr->M_cc_diag, pr->M_cc_diag + n_h), di(n_h);
+    for (int64_t d = 0; d < n_h; ++d) di[d] = 1.0 / dv[d];
+    STCHK(dalloc(c, &c->dvec, n_h));
+    STCHK(dalloc(c, &c->dinv, n_h));
+    HIPCHK(c, hipMemcpy(c->dvec, dv.data(), n_h * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->dinv, di.data(), n_h * sizeof(double), hipMemcpyHostToDevice));
+  }
+
+  // ---- workspace (ld = max_cols)
+  const int64_t mc = c->max_cols;
+  STCHK(dalloc(c, &c->R, (size_t)c->n * mc));
+  STCHK(dalloc(c, &c->B2, (size_t)c->n * mc));
+  STCHK(dalloc(c, &c->T, (size_t)c->n * mc));
+  STCHK(dalloc(c, &c->U, (size_t)c->n * mc));
+  {
+    // Gram partial buffer: multiple of 8 chunks, at most 256, at most ~512 MB
+    int64_t nch = std::max<int64_t>(8, std::min<int64_t>(256, (c->n + 4095) / 4096));
+    const int64_t cap = (int64_t)(512ll << 20) / (8 * mc * mc);
+    nch = std::min<int64_t>(nch, std::max<int64_t>(8, cap));
+    nch = (nch + 7) / 8 * 8;
+    c->gp_chunks = (int)nch;
+    STCHK(dalloc(c, &c->Gp, (size_t)nch * mc * mc));
+  }
+  STCHK(dalloc(c, &c->G, (size_t)mc * mc));
+  STCHK(dalloc(c, &c->Wm, (size_t)mc * mc));
+  STCHK(dalloc(c, &c->Wt, (size_t)mc * mc));
+  STCHK(dalloc(c, &c->Hh, (size_t)mc * mc));
+  STCHK(dalloc(c, &c->Mh, (size_t)mc * mc));
+  STCHK(dalloc(c, &c->sv, (size_t)std::max<int64_t>(mc, n_e)));
+  STCHK(dalloc(c, &c->theta, (size_t)mc));
+  STCHK(dalloc(c, &c->evE, (size_t)mc));
+  STCHK(dalloc(c, &c->flag, 4));
+  STCHK(dalloc(c, &c->info, 4));
+  STCHK(dalloc(c, &c->lzv, (size_t)c->n * 4));
+  STCHK(dalloc(c, &c->lzcoef, 2 * 64 + 8));
+  STCHK(dalloc(c, &c->lzpart, 1024));
+  if (rocblas_create_handle(&c->rb) != rocblas_status_success)
+    return set_err(c, CF_EDEVICE, "init: rocblas_create_handle failed");
+  rocblas_set_stream(c->rb, c->stream);
+
+  // ---- enrichment data
+  c->col_off.shrink_to_fit();
+  c->ecol_off.assign(1, 0);
+  if (n_e > 0) {
+    const int64_t *ep = pr->enr_ptr;
+    if (ep[0] != 0) return set_err(c, CF_EINVAL, "init: enr_ptr[0] must be 0");
+    int kmax = 0;
+    for (int64_t e = 0; e < E; ++e) {
+      if (ep[e + 1] < ep[e]) return set_err(c, CF_EINVAL, "init: enr_ptr not monotone");
+      kmax = std::max<int>(kmax, (int)(ep[e + 1] - ep[e]));
+    }
+    if (kmax > 416) return set_err(c, CF_EINVAL, "init: more than 416 enrichment functions in a cell");
+    c->kmax = kmax;
+    const int64_t nnz = ep[E];
+    c->nnz = nnz;
+    std::vector<int32_t> eidx(nnz);
+    std::vector<int64_t> seen(n_e, -1);
+    for (int64_t e = 0; e < E; ++e)
+      for (int64_t k = ep[e]; k < ep[e + 1]; ++k) {
+        const int64_t al = pr->enr_idx[k];
+        if (al < 0 || al >= n_e) return set_err(c, CF_EINVAL, "init: enr_idx out of range");
+        if (seen[al] == e) return set_err(c, CF_EINVAL, "init: repeated enrichment index in a cell");
+        seen[al] = e;
+        eidx[k] = (int32_t)al;
+      }
+    // rows padded to NPAD
+    STCHK(dalloc(c, &c->Hec, (size_t)std::max<int64_t>(nnz, 1) * NPAD));
+    STCHK(dalloc(c, &c->Mec, (size_t)std::max<int64_t>(nnz, 1) * NPAD));
+    {
+      const int64_t batch = 4096;
+      std::vector<double> hb((size_t)batch * NPAD), mb((size_t)batch * NPAD);
+      for (int64_t k0 = 0; k0 < nnz; k0 += batch) {
+        const int64_t nb = std::min(batch, nnz - k0);
+        std::fill(hb.begin(), hb.end(), 0.0);
+        std::fill(mb.begin(), mb.end(), 0.0);
+        for (int64_t k = 0; k < nb; ++k)
+          for (int a = 0; a < npc; ++a) {
+            const double hv = pr->H_ec[(k0 + k) * npc + a], mv = pr->M_ec[(k0 + k) * npc + a];
+            if (!std::isfinite(hv) || !std::isfinite(mv))
+              return set_err(c, CF_EINVAL, "init: non-finite H_ec / M_ec");
+            hb[k * NPAD + a] = hv;
+            mb[k * NPAD + a] = mv;
+          }
+        HIPCHK(c, hipMemcpy(c->Hec + k0 * NPAD, hb.data(), nb * NPAD * sizeof(double), hipMemcpyHostToDevice));
+        HIPCHK(c, hipMemcpy(c->Mec + k0 * NPAD, mb.data(), nb * NPAD * sizeof(double), hipMemcpyHostToDevice));
+      }
+    }
+    STCHK(dalloc(c, &c->eptr, E + 1));
+    STCHK(dalloc(c, &c->eidx, std::max<int64_t>(nnz, 1)));
+    HIPCHK(c, hipMemcpy(c->eptr, ep, (E + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
+    if (nnz) HIPCHK(c, hipMemcpy(c->eidx, eidx.data(), nnz * sizeof(int32_t), hipMemcpyHostToDevice));
+    // enriched cells grouped by colour (same colouring as the classical pass)
+    std::vector<int32_t> eorder;
+    for (int col = 0; col < ncol; ++col) {
+      for (int i = c->col_off[col]; i < c->col_off[col + 1]; ++i) {
+        const int32_t e = order[i];
+        if (ep[e + 1] > ep[e]) eorder.push_back(e);
+      }
+      c->ecol_off.push_back((int)eorder.size());
+    }
+    STCHK(dalloc(c, &c->ecells, std::max<size_t>(eorder.size(), 1)));
+    if (!eorder.empty())
+      HIPCHK(c, hipMemcpy(c->ecells, eorder.data(), eorder.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    // alpha -> list of partial rows, increasing row index
+    std::vector<int64_t> aptr(n_e + 1, 0);
+    for (int64_t k = 0; k < nnz; ++k) aptr[eidx[k] + 1]++;
+    for (int64_t a = 0; a < n_e; ++a) aptr[a + 1] += aptr[a];
+    std::vector<int32_t> alist(std::max<int64_t>(nnz, 1));
+    {
+      std::vector<int64_t> fill(aptr.begin(), aptr.end() - 1);
+      for (int64_t k = 0; k < nnz; ++k) alist[fill[eidx[k]]++] = (int32_t)k;
+    }
+    STCHK(dalloc(c, &c->aptr, n_e + 1));
+    STCHK(dalloc(c, &c->alist, alist.size()));
+    HIPCHK(c, hipMemcpy(c->aptr, aptr.data(), (n_e + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->alist, alist.data(), alist.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    // dense enrichment blocks
+    for (int64_t q = 0; q < n_e * n_e; ++q)
+      if (!std::isfinite(pr->H_ee[q]) || !std::isfinite(pr->M_ee[q]))
+        return set_err(c, CF_EINVAL, "init: non-finite H_ee / M_ee");
+    STCHK(dalloc(c, &c->Hee, n_e * n_e));
+    STCHK(dalloc(c, &c->Mee, n_e * n_e));
+    STCHK(dalloc(c, &c->Sinv, n_e * n_e));
+    HIPCHK(c, hipMemcpy(c->Hee, pr->H_ee, n_e * n_e * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->Mee, pr->M_ee, n_e * n_e * sizeof(double), hipMemcpyHostToDevice));
+    STCHK(dalloc(c, &c->P, (size_t)std::max<int64_t>(nnz, 1) * mc));
+    STCHK(dalloc(c, &c->Wb, (size_t)n_e * mc));
+    STCHK(dalloc(c, &c->Zb, (size_t)n_e * mc));
+
+    // ---- Schur complement S = M^ee - M^ec D^-1 M^ec^T (Sec. IV.D), FP64, on the device.
+    // Assemble Bt = (M^ec)^T restricted to DOFs of enriched cells, scale rows by
+    // D^-1/2, Gram -> M^ec D^-1 M^ec^T, subtract, Cholesky, S^-1 = L^-T L^-1.
+    std::vector<int32_t> dof2reg(n_h, -1), regdof;
+    for (int32_t e : eorder)
+      for (int a = 0; a < npc; ++a) {
+        const int32_t d = dof[(int64_t)e * NPAD + a];
+        if (d >= 0 && dof2reg[d] < 0) { dof2reg[d] = (int32_t)regdof.size(); regdof.push_back(d); }
+      }
+    const int64_t nreg = (int64_t)regdof.size();
+    int32_t *d_dof2reg = nullptr, *d_regdof = nullptr;
+    double *Bt = nullptr, *Sw = nullptr, *Gtmp = nullptr, *GpS = nullptr, *svS = nullptr, *WS = nullptr, *WST = nullptr;
+    int nchS = 8;
+    {
+      const int64_t cap = (int64_t)(512ll << 20) / (8 * n_e * n_e);
+      nchS = (int)std::max<int64_t>(8, std::min<int64_t>(256, cap) / 8 * 8);
+    }
+    auto cleanup = [&]() {
+      for (void *q : {(void *)d_dof2reg, (void *)d_regdof, (void *)Bt, (void *)Sw, (void *)Gtmp,
+                      (void *)GpS, (void *)svS, (void *)WS, (void *)WST}) {
+        if (!q) continue;
+        auto it = std::find(c->allocs.begin(), c->allocs.end(), q);
+        if (it != c->allocs.end()) c->allocs.erase(it);
+        (void)hipFree(q);
+      }
+    };
+    cf_status st = CF_OK;
+    do {
+      if ((st = dalloc(c, &d_dof2reg, n_h)) != CF_OK) break;
+      if ((st = dalloc(c, &d_regdof, std::max<int64_t>(nreg, 1))) != CF_OK) break;
+      if ((st = dalloc(c, &Bt, (size_t)std::max<int64_t>(nreg, 1) * n_e)) != CF_OK) break;
+      if ((st = dalloc(c, &Gtmp, (size_t)n_e * n_e)) != CF_OK) break;
+      if ((st = dalloc(c, &Sw, (size_t)n_e * n_e)) != CF_OK) break;
+      if ((st = dalloc(c, &GpS, (size_t)nchS * n_e * n_e)) != CF_OK) break;
+      if ((st = dalloc(c, &svS, (size_t)n_e)) != CF_OK) break;
+      if ((st = dalloc(c, &WS, (size_t)n_e * n_e)) != CF_OK) break;
+      if ((st = dalloc(c, &WST, (size_t)n_e * n_e)) != CF_OK) break;
+      hipError_t he = hipSuccess;
+#define SCH(call) if ((he = (call)) != hipSuccess) { st = set_err(c, CF_EDEVICE, std::string(#call) + ": " + hipGetErrorString(he)); break; }
+      SCH(hipMemcpy(d_dof2reg, dof2reg.data(), n_h * sizeof(int32_t), hipMemcpyHostToDevice));
+      if (nreg) SCH(hipMemcpy(d_regdof, regdof.data(), nreg * sizeof(int32_t), hipMemcpyHostToDevice));
+      SCH(hipMemsetAsync(Bt, 0, (size_t)std::max<int64_t>(nreg, 1) * n_e * sizeof(double), c->stream));
+      for (int col = 0; col < ncol; ++col)
+        SCH(launch_scatter_coupling(c->stream, c->Mec, c->eptr, c->eidx, c->dofp,
+                                    d_dof2reg, c->ecells + c->ecol_off[col],
+                                    c->ecol_off[col + 1] - c->ecol_off[col], Bt, n_e));
+      if (he != hipSuccess) break;
+      SCH(launch_scale_rows_sqrt(c->stream, nreg, d_regdof, c->dinv, Bt, n_e, (int)n_e));
+      const int64_t crow = (nreg + nchS - 1) / nchS;
+      SCH(launch_gram_partial(c->stream, Bt, n_e, Bt, n_e, nreg, (int)n_e, nchS, crow, GpS, 1));
+      SCH(launch_gram_reduce(c->stream, GpS, nchS, (int)n_e, Gtmp, 1));
+      SCH(launch_sub(c->stream, n_e * n_e, c->Mee, Gtmp, Sw));
+      SCH(hipMemsetAsync(c->flag, 0, sizeof(int), c->stream));
+      SCH(launch_cholesky(c->stream, Sw, (int)n_e, 0, 0.0, svS, c->flag));
+      int h_flag = 0;
+      SCH(hipMemcpyAsync(&h_flag, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+      SCH(hipStreamSynchronize(c->stream));
+      if (h_flag) {
+        st = set_err(c, CF_ENOTSPD, "init: Schur complement not positive definite (pivot " +
+                                        std::to_string(h_flag - 1) + ")");
+        break;
+      }
+      SCH(launch_tri_inv_T(c->stream, Sw, svS, (int)n_e, WS));          // WS = L^-T
+      SCH(launch_transpose(c->stream, (int)n_e, WS, n_e, WST));         // WST = L^-1
+      SCH(launch_small_gemm(c->stream, (int)n_e, (int)n_e, (int)n_e, WS, n_e, WST, n_e, c->Sinv, n_e));
+      SCH(hipStreamSynchronize(c->stream));
+#undef SCH
+    } while (0);
+    cleanup();
+    if (st != CF_OK) return st;
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return CF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// public entry points
+// ---------------------------------------------------------------------------
+extern "C" {
+
+cf_status chebfilter_init(const cf_problem *prob, const cf_options *opt, cf_ctx **out) {
+  if (!out) return set_err(nullptr, CF_EINVAL, "init: null output pointer");
+  *out = nullptr;
+  cf_ctx *c = new (std::nothrow) cf_ctx();
+  if (!c) return set_err(nullptr, CF_ENOMEM, "init: host allocation failed");
+  cf_status st = do_init(prob, opt, c);
+  if (st != CF_OK) {
+    g_init_error = c->err;
+    free_ctx(c);
+    return st;
+  }
+  *out = c;
+  return CF_OK;
+}
+
+cf_status chebfilter_destroy(cf_ctx *ctx) {
+  if (!ctx) return CF_OK;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  free_ctx(ctx);
+  return CF_OK;
+}
+
+const char *chebfilter_last_error(const cf_ctx *ctx) {
+  return ctx ? ctx->err.c_str() : g_init_error.c_str();
+}
+
+cf_status chebfilter_sizes(const cf_ctx *ctx, int64_t *n_h, int64_t *n_e, int64_t *max_cols) {
+  if (!ctx) return CF_EINVAL;
+  if (n_h) *n_h = ctx->n_h;
+  if (n_e) *n_e = ctx->n_e;
+  if (max_cols) *max_cols = ctx->max_cols;
+  return CF_OK;
+}
+
+cf_status chebfilter_apply_H(cf_ctx *c, const double *X, int64_t ldx, double *Y, int64_t ldy,
+                             int64_t N) {
+  if (!c) return CF_EINVAL;
+  STCHK(check_block(c, X, ldx, N, "apply_H X"));
+  STCHK(check_block(c, Y, ldy, N, "apply_H Y"));
+  if (N == 0) return CF_OK;
+  HIPCHK(c, hipSetDevice(c->device));
+  return core_apply_H(c, X, ldx, Y, ldy, (int)N);
+}
+
+cf_status chebfilter_apply_M(cf_ctx *c, const double *X, int64_t ldx, double *Y, int64_t ldy,
+                             int64_t N) {
+  if (!c) return CF_EINVAL;
+  STCHK(check_block(c, X, ldx, N, "apply_M X"));
+  STCHK(check_block(c, Y, ldy, N, "apply_M Y"));
+  if (N == 0) return CF_OK;
+  HIPCHK(c, hipSetDevice(c->device));
+  return core_apply_M(c, X, ldx, Y, ldy, (int)N);
+}
+
+cf_status chebfilter_apply_Sinv(cf_ctx *c, const double *X, int64_t ldx, double *Y, int64_t ldy,
+                                int64_t N) {
+  if (!c) return CF_EINVAL;
+  STCHK(check_block(c, X, ldx, N, "apply_Sinv X"));
+  STCHK(check_block(c, Y, ldy, N, "apply_Sinv Y"));
+  if (N == 0) return CF_OK;
+  HIPCHK(c, hipSetDevice(c->device));
+  const int64_t ldr = c->max_cols;
+  HIPCHK(c, launch_copy(c->stream, c->n, (int)N, X, ldx, c->R, ldr));
+  STCHK(core_sinv(c, c->R, ldr, (int)N));
+  HIPCHK(c, launch_epilogue(c->stream, c->n_h, c->n_e, c->dinv, c->R, ldr, c->Zb, c->max_cols, 1.0,
+                            nullptr, 0, 0.0, nullptr, 0, 0.0, Y, ldy, (int)N));
+  return CF_OK;
+}
+
+cf_status chebfilter_filter(cf_ctx *c, const double *X, int64_t ldx, double *Y, int64_t ldy,
+                            int64_t N, int32_t m, double a, double b, int32_t prec) {
+  if (!c) return CF_EINVAL;
+  STCHK(check_block(c, X, ldx, N, "filter X"));
+  STCHK(check_block(c, Y, ldy, N, "filter Y"));
+  if (m < 0) return set_err(c, CF_EINVAL, "filter: m < 0");
+  if (!std::isfinite(a) || !std::isfinite(b) || !(b > a))
+    return set_err(c, CF_EINVAL, "filter: need finite a < b");
+  if (prec != CF_FP64) return set_err(c, CF_EINVAL, "filter: only CF_FP64 is built");
+  if (N == 0) return CF_OK;
+  if (X == Y) return set_err(c, CF_EINVAL, "filter: Y must not alias X");
+  HIPCHK(c, hipSetDevice(c->device));
+  const int n = (int)N;
+  if (m == 0) {
+    HIPCHK(c, launch_copy(c->stream, c->n, n, X, ldx, Y, ldy));
+    return CF_OK;
+  }
+  // t(H~) = e H~ - cc I with e = 2/(b-a), cc = (a+b)/(b-a)
+  const double e = 2.0 / (b - a), cc = (a + b) / (b - a);
+  // Y_k lives in Y when (m - k) is even, else in the internal block B2.
+  auto buf = [&](int k) -> double * { return ((m - k) % 2 == 0) ? Y : c->B2; };
+  auto ldb = [&](int k) -> int64_t { return ((m - k) % 2 == 0) ? ldy : c->max_cols; };
+  STCHK(core_htilde_step(c, X, ldx, n, e, X, ldx, -cc, nullptr, 0, 0.0, buf(1), ldb(1)));
+  for (int k = 1; k < m; ++k) {
+    const double *prev = (k == 1) ? X : buf(k - 1);
+    const int64_t ldp = (k == 1) ? ldx : ldb(k - 1);
+    STCHK(core_htilde_step(c, buf(k), ldb(k), n, 2.0 * e, buf(k), ldb(k), -2.0 * cc, prev, ldp, -1.0,
+                           buf(k + 1), ldb(k + 1)));
+  }
+  return check_out_finite(c, Y, ldy, n, "filter");
+}
+
+cf_status chebfilter_cholqr(cf_ctx *c, double *Y, int64_t ldy, int64_t N) {
+  if (!c) return CF_EINVAL;
+  STCHK(check_block(c, Y, ldy, N, "cholqr Y"));
+  if (N == 0) return CF_OK;
+  HIPCHK(c, hipSetDevice(c->device));
+  STCHK(core_cholqr(c, Y, ldy, Y, ldy, (int)N));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return CF_OK;
+}
+
+cf_status chebfilter_rayleigh_ritz(cf_ctx *c, double *Y, int64_t ldy, int64_t N,
+                                   double *theta_host) {
+  if (!c) return CF_EINVAL;
+  STCHK(check_block(c, Y, ldy, N, "rayleigh_ritz Y"));
+  if (N > 0 && !theta_host) return set_err(c, CF_EINVAL, "rayleigh_ritz: null theta");
+  if (N == 0) return CF_OK;
+  HIPCHK(c, hipSetDevice(c->device));
+  const int n = (int)N;
+  const int64_t ld = c->max_cols;
+  // Q (Euclidean-orthonormal) into U
+  STCHK(core_cholqr(c, Y, ldy, c->U, ld, n));
+  // projected pencil
+  STCHK(core_apply_H(c, c->U, ld, c->T, ld, n));
+  STCHK(core_gram(c, c->U, ld, c->T, ld, c->n, n, c->Hh, 0));
+  STCHK(core_apply_M(c, c->U, ld, c->T, ld, n));
+  STCHK(core_gram(c, c->U, ld, c->T, ld, c->n, n, c->Mh, 0));
+  // dense generalized eigensolve on the device (eigenvectors column-major in Hh)
+  if (rocsolver_dsygvd(c->rb, rocblas_eform_ax, rocblas_evect_original, rocblas_fill_upper, n, c->Hh,
+                       n, c->Mh, n, c->theta, c->evE, c->info) != rocblas_status_success)
+    return set_err(c, CF_EDEVICE, "rayleigh_ritz: rocsolver_dsygvd failed");
+  rocblas_int h_info = 0;
+  HIPCHK(c, hipMemcpyAsync(&h_info, c->info, sizeof(rocblas_int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(theta_host, c->theta, N * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  // C row-major: C[k][j] = V(k, j) = Hh[k + j n]
+  HIPCHK(c, launch_transpose(c->stream, n, c->Hh, n, c->Wm));
+  {
+    Scope sc(c, "rotate");
+    HIPCHK(c, launch_rotate(c->stream, c->U, ld, c->n, n, c->Wm, n, 1, Y, ldy));
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (h_info > 0 && h_info <= n)
+    return set_err(c, CF_ENOTCONV, "rayleigh_ritz: eigensolver did not converge");
+  if (h_info > n) return set_err(c, CF_ENOTSPD, "rayleigh_ritz: projected overlap not SPD");
+  return check_out_finite(c, Y, ldy, n, "rayleigh_ritz");
+}
+
+cf_status chebfilter_lanczos_bounds(cf_ctx *c, const double *v0, int32_t k, double *lmin_est,
+                                    double *b_upper) {
+  if (!c) return CF_EINVAL;
+  if (!v0 || !lmin_est || !b_upper) return set_err(c, CF_EINVAL, "lanczos: null argument");
+  if (k < 1 || k > 64) return set_err(c, CF_EINVAL, "lanczos: k must be 1..64");
+  HIPCHK(c, hipSetDevice(c->device));
+  const int64_t n = c->n;
+  double *vprev = c->lzv, *v = c->lzv + n, *w = c->lzv + 2 * n, *mv = c->lzv + 3 * n;
+  double *coef = c->lzcoef;
+  const int nblk = 512;
+  HIPCHK(c, hipMemsetAsync(coef, 0, (2 * 64 + 8) * sizeof(double), c->stream));
+  STCHK(core_apply_M(c, v0, 1, mv, 1, 1));
+  HIPCHK(c, launch_dot(c->stream, n, v0, mv, coef, c->lzpart, nblk));
+  HIPCHK(c, launch_lanczos_update(c->stream, n, 0, const_cast<double *>(v0), nullptr, nullptr, coef,
+                                  v, nullptr, nblk, 0));
+  for (int j = 0; j < k; ++j) {
+    STCHK(core_htilde_step(c, v, 1, 1, 1.0, nullptr, 0, 0.0, nullptr, 0, 0.0, w, 1));
+    if (j > 0)
+      HIPCHK(c, launch_lanczos_update(c->stream, n, j, w, v, vprev, coef, nullptr, nullptr, nblk, 1));
+    STCHK(core_apply_M(c, v, 1, mv, 1, 1));
+    HIPCHK(c, launch_dot(c->stream, n, w, mv, coef + 1 + 2 * j, c->lzpart, nblk));
+    HIPCHK(c, launch_lanczos_update(c->stream, n, j, w, v, vprev, coef, nullptr, nullptr, nblk, 2));
+    STCHK(core_apply_M(c, w, 1, mv, 1, 1));
+    HIPCHK(c, launch_dot(c->stream, n, w, mv, coef + 2 + 2 * j, c->lzpart, nblk));
+    if (j + 1 < k) {
+      HIPCHK(c, launch_lanczos_update(c->stream, n, j, w, v, vprev, coef, vprev, nullptr, nblk, 3));
+      std::swap(vprev, v);   // vprev <- old v, v <- new vector
+    }
+  }
+  HIPCHK(c, launch_tridiag_bounds(c->stream, coef, nullptr, k, coef + 2 * 64 + 2));
+  double out2[2] = {0.0, 0.0};
+  HIPCHK(c, hipMemcpyAsync(out2, coef + 2 * 64 + 2, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  *lmin_est = out2[0];
+  *b_upper = out2[1];
+  if (!std::isfinite(out2[0]) || !std::isfinite(out2[1]))
+    return set_err(c, CF_ENUMERIC, "lanczos: non-finite bound (breakdown?)");
+  return CF_OK;
+}
+
+cf_status chebfilter_profile(cf_ctx *c, int32_t enable) {
+  if (!c) return CF_EINVAL;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (auto &kv : c->prof)
+    for (auto &ev : kv.second.pending) {
+      (void)hipEventDestroy(ev.first);
+      (void)hipEventDestroy(ev.second);
+    }
+  c->prof.clear();
+  c->profiling = enable != 0;
+  return CF_OK;
+}
+
+cf_status chebfilter_profile_query(cf_ctx *c, const char *name, int64_t *launches,
+                                   double *total_ms) {
+  if (!c || !name) return CF_EINVAL;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  auto it = c->prof.find(name);
+  if (it == c->prof.end()) {
+    if (launches) *launches = 0;
+    if (total_ms) *total_ms = 0.0;
+    return CF_OK;
+  }
+  ProfEntry &pe = it->second;
+  for (auto &ev : pe.pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, ev.first, ev.second) == hipSuccess) pe.ms += ms;
+    pe.launches += 1;
+    (void)hipEventDestroy(ev.first);
+    (void)hipEventDestroy(ev.second);
+  }
+  pe.pending.clear();
+  if (launches) *launches = pe.launches;
+  if (total_ms) *total_ms = pe.ms;
+  return CF_OK;
+}
+
+}  // extern "C"

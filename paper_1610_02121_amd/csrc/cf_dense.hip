@@ -1,0 +1,549 @@
+// Dense kernels of the subspace step (Sec. V): tall-skinny Gram matrices and
+// block rotations on FP64 MFMA, a small Cholesky factorisation, triangular
+// inverse, small products, reductions and the Lanczos helpers.
+#include <math.h>
+
+#include "cf_kernels.h"
+
+namespace cf {
+
+// v_mfma_f64_16x16x4f64 lane layout: A[l % 16][l / 16], B[l / 16][l % 16],
+// D[4 * r + l / 16][l % 16] for element r of lane l.
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ d4 mfma_f64(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ d4 d4zero() { d4 z = {0.0, 0.0, 0.0, 0.0}; return z; }
+
+// Number of 64 x 64 output tiles of an N x N product and the (ti, tj) of tile t.
+__host__ __device__ inline int ntiles_of(int N, int upper) {
+  const int T = (N + GT - 1) / GT;
+  return upper ? T * (T + 1) / 2 : T * T;
+}
+__device__ inline void tile_of(int t, int N, int upper, int &ti, int &tj) {
+  const int T = (N + GT - 1) / GT;
+  if (!upper) { ti = t / T; tj = t % T; return; }
+  int i = 0;
+  while (t >= T - i) { t -= T - i; ++i; }
+  ti = i;
+  tj = i + t;
+}
+
+// ---------------------------------------------------------------------------
+// Partial Gram: Gp[c][i][j] = sum over rows r of chunk c of A[r][i] B[r][j].
+// 1-D grid of nchunks * ntiles workgroups.  Workgroups that share a row chunk
+// are mapped to the same XCD (workgroups are dealt round-robin to the 8 XCDs
+// by index), so the chunk is fetched from HBM once into that XCD's L2.  Each
+// wave computes a 32 x 32 quarter of the 64 x 64 tile; both operands are read
+// straight from global memory (16 consecutive doubles per fragment row).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_gram_partial(
+    const double *__restrict__ A, int64_t lda, const double *__restrict__ B, int64_t ldb,
+    int64_t n, int N, int nchunks, int64_t chunk_rows, int upper, double *__restrict__ Gp) {
+  const int ntl = ntiles_of(N, upper);
+  const int bid = blockIdx.x;
+  const int xcd = bid & 7, slot = bid >> 3;
+  const int chunk = (slot / ntl) * 8 + xcd;
+  const int t = slot % ntl;
+  if (chunk >= nchunks) return;
+  int ti, tj;
+  tile_of(t, N, upper, ti, tj);
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int li = lane & 15, kq = lane >> 4;
+  const int i0 = ti * GT + 32 * (w & 1), j0 = tj * GT + 32 * (w >> 1);
+  const int64_t r0 = (int64_t)chunk * chunk_rows;
+  const int64_t r1 = min(n, r0 + chunk_rows);
+  d4 acc[2][2];
+  acc[0][0] = acc[0][1] = acc[1][0] = acc[1][1] = d4zero();
+  const bool iv0 = i0 + li < N, iv1 = i0 + 16 + li < N;
+  const bool jv0 = j0 + li < N, jv1 = j0 + 16 + li < N;
+  if (i0 < N && j0 < N) {
+#pragma unroll 4
+    for (int64_t r = r0 + kq; r < r0 + ((r1 - r0 + 3) & ~(int64_t)3); r += 4) {
+      const bool rv = r < r1;
+      const double *ar = A + r * lda + i0 + li;
+      const double *br = B + r * ldb + j0 + li;
+      const double a0 = (rv && iv0) ? ar[0] : 0.0;
+      const double a1 = (rv && iv1) ? ar[16] : 0.0;
+      const double b0 = (rv && jv0) ? br[0] : 0.0;
+      const double b1 = (rv && jv1) ? br[16] : 0.0;
+      acc[0][0] = mfma_f64(a0, b0, acc[0][0]);
+      acc[0][1] = mfma_f64(a0, b1, acc[0][1]);
+      acc[1][0] = mfma_f64(a1, b0, acc[1][0]);
+      acc[1][1] = mfma_f64(a1, b1, acc[1][1]);
+    }
+  }
+  double *g = Gp + (int64_t)chunk * N * N;
+#pragma unroll
+  for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+    for (int jb = 0; jb < 2; ++jb) {
+      const int j = j0 + 16 * jb + li;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0 + 16 * ib + kq + 4 * r;
+        if (i < N && j < N) g[(int64_t)i * N + j] = acc[ib][jb][r];
+      }
+    }
+}
+
+hipError_t launch_gram_partial(hipStream_t s, const double *A, int64_t lda, const double *B,
+                               int64_t ldb, int64_t n, int N, int nchunks, int64_t chunk_rows,
+                               double *Gp, int upper_only) {
+  if (N <= 0) return hipSuccess;
+  const int ntl = ntiles_of(N, upper_only);
+  const int nch8 = (nchunks + 7) / 8 * 8;
+  hipLaunchKernelGGL(k_gram_partial, dim3(nch8 * ntl), dim3(256), 0, s, A, lda, B, ldb, n, N,
+                     nchunks, chunk_rows, upper_only, Gp);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_gram_reduce(const double *__restrict__ Gp, int nchunks,
+                                                     int N, double *__restrict__ G, int upper) {
+  const int64_t NN = (int64_t)N * N;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < NN; e += (int64_t)gridDim.x * 256) {
+    const int i = (int)(e / N), j = (int)(e % N);
+    if (j < i) continue;
+    double sij = 0.0, sji = 0.0;
+    for (int c = 0; c < nchunks; ++c) {
+      sij += Gp[c * NN + (int64_t)i * N + j];
+      if (!upper) sji += Gp[c * NN + (int64_t)j * N + i];
+    }
+    const double v = upper ? sij : 0.5 * (sij + sji);
+    G[(int64_t)i * N + j] = v;
+    G[(int64_t)j * N + i] = v;
+  }
+}
+
+hipError_t launch_gram_reduce(hipStream_t s, const double *Gp, int nchunks, int N, double *G,
+                              int upper_only) {
+  if (N <= 0) return hipSuccess;
+  int64_t blocks = ((int64_t)N * N + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)blocks), dim3(256), 0, s, Gp, nchunks, N, G,
+                     upper_only);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Rotation Out = In * W (In: n x N row-major, W: N x N with strides).  Tile of
+// 64 rows x 64 columns per workgroup; In is staged through LDS in k-slabs of
+// 32 columns (row stride 34 doubles: conflict-free A-fragment reads), W is
+// read from global memory (it stays in L2).  Workgroups of one row block are
+// kept on one XCD.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_rotate(const double *__restrict__ In, int64_t ldi,
+                                                int64_t n, int N, const double *__restrict__ W,
+                                                int64_t wsk, int64_t wsj,
+                                                double *__restrict__ Out, int64_t ldo,
+                                                int nrb) {
+  constexpr int KS = 32, LDA = 34;
+  __shared__ double as[64 * LDA];
+  const int T = (N + GT - 1) / GT;
+  const int bid = blockIdx.x;
+  const int xcd = bid & 7, slot = bid >> 3;
+  const int rb = (slot / T) * 8 + xcd;
+  const int tj = slot % T;
+  if (rb >= nrb) return;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int li = lane & 15, kq = lane >> 4;
+  const int64_t r0 = (int64_t)rb * 64;
+  const int wi = 32 * (w & 1), j0 = tj * GT + 32 * (w >> 1);
+  d4 acc[2][2];
+  acc[0][0] = acc[0][1] = acc[1][0] = acc[1][1] = d4zero();
+  const bool jv0 = j0 + li < N, jv1 = j0 + 16 + li < N;
+  for (int kc = 0; kc < N; kc += KS) {
+    for (int idx = tid; idx < 64 * KS; idx += 256) {
+      const int r = idx / KS, k = idx % KS;
+      double v = 0.0;
+      if (r0 + r < n && kc + k < N) v = In[(r0 + r) * ldi + kc + k];
+      as[r * LDA + k] = v;
+    }
+    __syncthreads();
+    if (j0 < N) {
+#pragma unroll
+      for (int ks = 0; ks < KS / 4; ++ks) {
+        const int k = kc + 4 * ks + kq;
+        const bool kv = k < N;
+        const double a0 = as[(wi + li) * LDA + 4 * ks + kq];
+        const double a1 = as[(wi + 16 + li) * LDA + 4 * ks + kq];
+        const double b0 = (kv && jv0) ? W[k * wsk + (j0 + li) * wsj] : 0.0;
+        const double b1 = (kv && jv1) ? W[k * wsk + (j0 + 16 + li) * wsj] : 0.0;
+        acc[0][0] = mfma_f64(a0, b0, acc[0][0]);
+        acc[0][1] = mfma_f64(a0, b1, acc[0][1]);
+        acc[1][0] = mfma_f64(a1, b0, acc[1][0]);
+        acc[1][1] = mfma_f64(a1, b1, acc[1][1]);
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+    for (int jb = 0; jb < 2; ++jb) {
+      const int j = j0 + 16 * jb + li;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = r0 + wi + 16 * ib + kq + 4 * r;
+        if (row < n && j < N) Out[row * ldo + j] = acc[ib][jb][r];
+      }
+    }
+}
+
+hipError_t launch_rotate(hipStream_t s, const double *In, int64_t ldi, int64_t n, int N,
+                         const double *W, int64_t wsk, int64_t wsj, double *Out, int64_t ldo) {
+  if (n <= 0 || N <= 0) return hipSuccess;
+  const int T = (N + GT - 1) / GT;
+  const int nrb = (int)((n + 63) / 64);
+  const int nrb8 = (nrb + 7) / 8 * 8;
+  hipLaunchKernelGGL(k_rotate, dim3(nrb8 * T), dim3(256), 0, s, In, ldi, n, N, W, wsk, wsj, Out,
+                     ldo, nrb);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Lower Cholesky of a small SPD matrix, one workgroup, right-looking.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_cholesky(double *A, int N, int scale, double shift,
+                                                   double *sv, int *flag) {
+  __shared__ double piv;
+  __shared__ int bad;
+  const int tid = threadIdx.x;
+  if (tid == 0) bad = 0;
+  __syncthreads();
+  for (int i = tid; i < N; i += 1024) {
+    double s = 1.0;
+    if (scale) {
+      const double d = A[(int64_t)i * N + i];
+      if (d > 0.0 && isfinite(d)) s = 1.0 / sqrt(d);
+      else atomicExch(&bad, i + 1);   // LDS flag only
+    }
+    sv[i] = s;
+  }
+  __syncthreads();
+  if (bad) { if (tid == 0) flag[0] = bad; return; }
+  const int64_t NN = (int64_t)N * N;
+  for (int64_t e = tid; e < NN; e += 1024) {
+    const int i = (int)(e / N), j = (int)(e % N);
+    double v = A[e] * sv[i] * sv[j];
+    if (i == j) v += shift;
+    A[e] = v;
+  }
+  __syncthreads();
+  for (int k = 0; k < N; ++k) {
+    if (tid == 0) {
+      const double d = A[(int64_t)k * N + k];
+      if (!(d > 0.0) || !isfinite(d)) { bad = k + 1; piv = 1.0; }
+      else { piv = sqrt(d); A[(int64_t)k * N + k] = piv; }
+    }
+    __syncthreads();
+    if (bad) { if (tid == 0) flag[0] = bad; return; }
+    const double p = piv;
+    for (int i = k + 1 + tid; i < N; i += 1024) A[(int64_t)i * N + k] /= p;
+    __syncthreads();
+    const int m = N - k - 1;
+    const int64_t mm = (int64_t)m * m;
+    for (int64_t e = tid; e < mm; e += 1024) {
+      const int i = k + 1 + (int)(e / m), j = k + 1 + (int)(e % m);
+      if (j <= i) A[(int64_t)i * N + j] -= A[(int64_t)i * N + k] * A[(int64_t)j * N + k];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) flag[0] = 0;
+}
+
+hipError_t launch_cholesky(hipStream_t s, double *A, int N, int scale, double shift_rel,
+                           double *s_out, int *flag) {
+  if (N <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(1024), 0, s, A, N, scale, shift_rel, s_out, flag);
+  return hipGetLastError();
+}
+
+// W = diag(sv) L^-T: thread c forward-substitutes column c of L^-1 and writes
+// it as row c of W (upper triangular); zeros below the diagonal.
+__global__ __launch_bounds__(256) void k_tri_inv_T(const double *__restrict__ L,
+                                                   const double *__restrict__ sv, int N,
+                                                   double *__restrict__ W) {
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  if (c >= N) return;
+  double *x = W + (int64_t)c * N;
+  for (int i = 0; i < c; ++i) x[i] = 0.0;
+  for (int i = c; i < N; ++i) {
+    double acc = (i == c) ? 1.0 : 0.0;
+    const double *Li = L + (int64_t)i * N;
+    for (int k = c; k < i; ++k) acc -= Li[k] * x[k];
+    x[i] = acc / Li[i];
+  }
+  const double s = sv[c];
+  for (int i = c; i < N; ++i) x[i] *= s;
+}
+
+hipError_t launch_tri_inv_T(hipStream_t s, const double *L, const double *sv, int N, double *W) {
+  if (N <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_tri_inv_T, dim3((N + 255) / 256), dim3(256), 0, s, L, sv, N, W);
+  return hipGetLastError();
+}
+
+// C[M x N] = A[M x K] B[K x N], row-major; one thread per output element.
+__global__ __launch_bounds__(256) void k_small_gemm(int M, int K, int N,
+                                                    const double *__restrict__ A, int64_t lda,
+                                                    const double *__restrict__ B, int64_t ldb,
+                                                    double *__restrict__ C, int64_t ldc) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)M * N) return;
+  const int i = (int)(e / N), j = (int)(e % N);
+  double acc = 0.0;
+  const double *a = A + (int64_t)i * lda;
+  for (int k = 0; k < K; ++k) acc += a[k] * B[(int64_t)k * ldb + j];
+  C[(int64_t)i * ldc + j] = acc;
+}
+
+hipError_t launch_small_gemm(hipStream_t s, int M, int K, int N, const double *A, int64_t lda,
+                             const double *B, int64_t ldb, double *C, int64_t ldc) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  const int64_t tot = (int64_t)M * N;
+  hipLaunchKernelGGL(k_small_gemm, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, M, K, N,
+                     A, lda, B, ldb, C, ldc);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Deterministic dot product: per-block partial sums, then one block.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_dot_partial(int64_t n, const double *__restrict__ x,
+                                                     const double *__restrict__ y,
+                                                     double *__restrict__ part) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    acc += x[i] * y[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void k_sum_final(int nblk, const double *__restrict__ part,
+                                                   double *__restrict__ out) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += 256) acc += part[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = red[0];
+}
+
+hipError_t launch_dot(hipStream_t s, int64_t n, const double *x, const double *y, double *out,
+                      double *scratch, int nblk) {
+  hipLaunchKernelGGL(k_dot_partial, dim3(nblk), dim3(256), 0, s, n, x, y, scratch);
+  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, s, nblk, scratch, out);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_check_finite(const double *__restrict__ X, int64_t ldx,
+                                                      int64_t n, int N, int *flag) {
+  int bad = 0;
+  for (int64_t i = (int64_t)blockIdx.x * 4 + threadIdx.y; i < n; i += (int64_t)gridDim.x * 4)
+    for (int j = threadIdx.x; j < N; j += 64)
+      if (!isfinite(X[i * ldx + j])) bad = 1;
+  if (bad) atomicOr(flag, 1);
+}
+
+hipError_t launch_check_finite(hipStream_t s, const double *X, int64_t ldx, int64_t n, int N,
+                               int *flag) {
+  if (n <= 0 || N <= 0) return hipSuccess;
+  int64_t blocks = (n + 3) / 4;
+  if (blocks > 16384) blocks = 16384;
+  hipLaunchKernelGGL(k_check_finite, dim3((unsigned)blocks), dim3(64, 4), 0, s, X, ldx, n, N,
+                     flag);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Lanczos helpers.  coef[] holds the device-side scalars of the run:
+//   coef[0]            squared M-norm of the start vector
+//   coef[1 + 2j]       alpha_j
+//   coef[2 + 2j]       beta_j^2
+// phase 0: v = w / sqrt(coef[0])                                  (normalise start)
+// phase 1: w -= sqrt(coef[2j]) * vprev   (j > 0)                  (three-term part)
+// phase 2: w -= coef[1+2j] * v                                    (alpha part)
+// phase 3: vnext = w / sqrt(coef[2+2j])                           (normalise)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_lanczos_update(int64_t n, int j, int phase, double *w,
+                                                        const double *v, const double *vprev,
+                                                        const double *coef, double *vnext) {
+  double c = 0.0;
+  if (phase == 0) c = 1.0 / sqrt(coef[0]);
+  else if (phase == 1) c = sqrt(coef[2 * j]);
+  else if (phase == 2) c = coef[1 + 2 * j];
+  else c = 1.0 / sqrt(coef[2 + 2 * j]);
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    if (phase == 0) vnext[i] = w[i] * c;
+    else if (phase == 1) w[i] -= c * vprev[i];
+    else if (phase == 2) w[i] -= c * v[i];
+    else vnext[i] = w[i] * c;
+  }
+}
+
+hipError_t launch_lanczos_update(hipStream_t s, int64_t n, int j, double *w, const double *v,
+                                 const double *vprev, double *coef, double *vnext,
+                                 double * /*scratch*/, int nblk, int phase) {
+  hipLaunchKernelGGL(k_lanczos_update, dim3(nblk), dim3(256), 0, s, n, j, phase, w, v, vprev, coef,
+                     vnext);
+  return hipGetLastError();
+}
+
+// Extreme eigenvalues of the k x k Lanczos tridiagonal by Sturm-sequence
+// bisection (one thread).  out2[0] = lambda_min, out2[1] = lambda_max + beta_k.
+__device__ int sturm_count(const double *alpha, const double *beta2, int k, double x) {
+  int cnt = 0;
+  double q = alpha[0] - x;
+  if (q < 0.0) ++cnt;
+  for (int i = 1; i < k; ++i) {
+    const double qq = (q == 0.0) ? 1e-300 : q;
+    q = alpha[i] - x - beta2[i - 1] / qq;
+    if (q < 0.0) ++cnt;
+  }
+  return cnt;
+}
+
+__global__ void k_tridiag_bounds(const double *coef, int k, double *out2) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double alpha[64], beta2[64];
+  for (int i = 0; i < k; ++i) { alpha[i] = coef[1 + 2 * i]; beta2[i] = coef[2 + 2 * i]; }
+  // Gershgorin interval
+  double lo = 1e300, hi = -1e300;
+  for (int i = 0; i < k; ++i) {
+    double r = 0.0;
+    if (i > 0) r += sqrt(beta2[i - 1]);
+    if (i < k - 1) r += sqrt(beta2[i]);
+    lo = fmin(lo, alpha[i] - r);
+    hi = fmax(hi, alpha[i] + r);
+  }
+  double res[2];
+  for (int which = 0; which < 2; ++which) {
+    // which 0: smallest (count >= 1), which 1: largest (count >= k)
+    const int target = which == 0 ? 1 : k;
+    double a = lo, b = hi;
+    for (int it = 0; it < 200; ++it) {
+      const double mid = 0.5 * (a + b);
+      if (mid == a || mid == b) break;
+      if (sturm_count(alpha, beta2, k, mid) >= target) b = mid; else a = mid;
+    }
+    res[which] = 0.5 * (a + b);
+  }
+  out2[0] = res[0];
+  out2[1] = res[1] + sqrt(beta2[k - 1]);
+}
+
+hipError_t launch_tridiag_bounds(hipStream_t s, const double *coef, const double * /*unused*/,
+                                 int k, double *out2) {
+  hipLaunchKernelGGL(k_tridiag_bounds, dim3(1), dim3(64), 0, s, coef, k, out2);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Setup helpers for the Schur complement.
+// ---------------------------------------------------------------------------
+// Bt[reg(dof(e,a))][idx[k]] += M[k][a] for the enriched cells of one colour
+// (no two cells of a colour share a DOF, so targets are distinct).
+__global__ __launch_bounds__(128) void k_scatter_coupling(
+    const double *__restrict__ Bp, const int64_t *__restrict__ eptr,
+    const int32_t *__restrict__ eidx, const int32_t *__restrict__ dofp,
+    const int32_t *__restrict__ dof2reg, const int32_t *__restrict__ cells, double *Bt,
+    int64_t ldb) {
+  const int cell = cells[blockIdx.x];
+  const int a = threadIdx.x;
+  const int d = dofp[(int64_t)cell * NPAD + a];
+  if (d < 0) return;
+  const int64_t reg = dof2reg[d];
+  for (int64_t k = eptr[cell]; k < eptr[cell + 1]; ++k)
+    Bt[reg * ldb + eidx[k]] += Bp[k * NPAD + a];
+}
+
+hipError_t launch_scatter_coupling(hipStream_t s, const double *Bp, const int64_t *eptr,
+                                   const int32_t *eidx, const int32_t *dofp,
+                                   const int32_t *dof2reg, const int32_t *cells, int ncells,
+                                   double *Bt, int64_t ldb) {
+  if (ncells <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scatter_coupling, dim3(ncells), dim3(NPAD), 0, s, Bp, eptr, eidx, dofp,
+                     dof2reg, cells, Bt, ldb);
+  return hipGetLastError();
+}
+
+// Bt[r][:] *= sqrt(dinv[regdof[r]])
+__global__ __launch_bounds__(256) void k_scale_rows_sqrt(int64_t rows, const int32_t *regdof,
+                                                         const double *dinv, double *Bt,
+                                                         int64_t ldb, int ncol) {
+  for (int64_t r = (int64_t)blockIdx.x * 4 + threadIdx.y; r < rows; r += (int64_t)gridDim.x * 4) {
+    const double s = sqrt(dinv[regdof[r]]);
+    for (int j = threadIdx.x; j < ncol; j += 64) Bt[r * ldb + j] *= s;
+  }
+}
+
+hipError_t launch_scale_rows_sqrt(hipStream_t s, int64_t rows, const int32_t *regdof,
+                                  const double *dinv, double *Bt, int64_t ldb, int ncol) {
+  if (rows <= 0) return hipSuccess;
+  int64_t blocks = (rows + 3) / 4;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_scale_rows_sqrt, dim3((unsigned)blocks), dim3(64, 4), 0, s, rows, regdof,
+                     dinv, Bt, ldb, ncol);
+  return hipGetLastError();
+}
+
+// C = A - B (elementwise, n values)
+__global__ __launch_bounds__(256) void k_sub(int64_t n, const double *A, const double *B,
+                                             double *C) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    C[i] = A[i] - B[i];
+}
+
+hipError_t launch_sub(hipStream_t s, int64_t n, const double *A, const double *B, double *C) {
+  if (n <= 0) return hipSuccess;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_sub, dim3((unsigned)blocks), dim3(256), 0, s, n, A, B, C);
+  return hipGetLastError();
+}
+
+// Out[i][j] = In[j][i] for an N x N matrix (Out row-major, ld N).
+__global__ __launch_bounds__(256) void k_transpose(int N, const double *In, int64_t ldi,
+                                                   double *Out) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)N * N) return;
+  const int i = (int)(e / N), j = (int)(e % N);
+  Out[(int64_t)i * N + j] = In[(int64_t)j * ldi + i];
+}
+
+hipError_t launch_transpose(hipStream_t s, int N, const double *In, int64_t ldi, double *Out) {
+  if (N <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_transpose, dim3((unsigned)(((int64_t)N * N + 255) / 256)), dim3(256), 0, s,
+                     N, In, ldi, Out);
+  return hipGetLastError();
+}
+
+// Y[i][j] = X[i][j] for an n x N block (copy with leading dimensions).
+__global__ __launch_bounds__(256) void k_copy(int64_t n, int N, const double *X, int64_t ldx,
+                                              double *Y, int64_t ldy) {
+  for (int64_t i = (int64_t)blockIdx.x * 4 + threadIdx.y; i < n; i += (int64_t)gridDim.x * 4)
+    for (int j = threadIdx.x; j < N; j += 64) Y[i * ldy + j] = X[i * ldx + j];
+}
+
+hipError_t launch_copy(hipStream_t s, int64_t n, int N, const double *X, int64_t ldx, double *Y,
+                       int64_t ldy) {
+  if (n <= 0 || N <= 0) return hipSuccess;
+  int64_t blocks = (n + 3) / 4;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(64, 4), 0, s, n, N, X, ldx, Y, ldy);
+  return hipGetLastError();
+}
+
+}  // namespace cf

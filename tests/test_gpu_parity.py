@@ -1,0 +1,257 @@
+"""GPU-vs-oracle parity through the C ABI (element by element, FP64).
+
+Tolerances (relative to the largest magnitude of the oracle result):
+* H X, M X: 1e-12.  Both sides sum the same elemental products in a
+  different order; rows collect at most 8 cells x 125 terms plus the
+  enrichment terms, so the rounding difference is a few hundred ulps of the
+  largest partial sum.
+* (M^E)^-1 X: 10 u kappa(M^E), the forward-error scale of a backward-stable
+  solve (u = 2^-53; kappa from the extreme eigenvalues of M^E); the device
+  applies S^-1 explicitly, the oracle factors M^E by sparse LU.
+* filter: 10 u kappa(M^E) per Chebyshev step (m applications of H~).
+* Ritz values: 1e-8 Ha absolute (the target accuracy of the method).
+"""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+from oracle.filters import recurrence_filter
+from oracle.operators import Operators
+from oracle.subspace import cholqr, lanczos, lanczos_bounds, rayleigh_ritz
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def dev(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def relerr(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+_CTX = {}
+_KAPPA = {}
+U = 2.0 ** -53
+
+
+def kappa_M(name, ops):
+    """Condition number of M^E from its extreme eigenvalues."""
+    import scipy.sparse.linalg as spla
+    if name not in _KAPPA:
+        lmax = spla.eigsh(ops.M, k=1, which="LA", return_eigenvectors=False)[0]
+        lmin = spla.eigsh(ops.M, k=1, sigma=0, which="LM", return_eigenvectors=False)[0]
+        _KAPPA[name] = lmax / lmin
+    return _KAPPA[name]
+
+
+def context(name, prob, max_cols=96):
+    from paper_1610_02121_amd import Context
+    key = (name, max_cols)
+    if key not in _CTX:
+        _CTX[key] = (Context(prob, max_cols=max_cols), Operators(prob))
+    return _CTX[key]
+
+
+FIXTURES = ["tiny_enriched", "hydrogen_small", "si_small"]
+WIDTHS = [1, 5, 16, 37, 70]
+
+
+@pytest.mark.parametrize("fix", FIXTURES)
+@pytest.mark.parametrize("N", WIDTHS)
+def test_apply_H_M(fix, N, request):
+    print(f"[apply_H/M] {fix} N={N}", flush=True)
+    ctx, ops = context(fix, request.getfixturevalue(fix))
+    X = np.random.default_rng(N).standard_normal((ops.n, N))
+    Xd = dev(X)
+    assert relerr(host(ctx.apply_H(Xd)), ops.apply_H(X)) < 1e-12
+    assert relerr(host(ctx.apply_M(Xd)), ops.apply_M(X)) < 1e-12
+
+
+@pytest.mark.parametrize("fix", FIXTURES)
+@pytest.mark.parametrize("N", [1, 16, 37])
+def test_apply_Sinv(fix, N, request):
+    print(f"[apply_Sinv] {fix} N={N}", flush=True)
+    ctx, ops = context(fix, request.getfixturevalue(fix))
+    X = np.random.default_rng(10 + N).standard_normal((ops.n, N))
+    Y = host(ctx.apply_Sinv(dev(X)))
+    Yo = ops.solve_M(X)
+    tol = 10 * U * kappa_M(fix, ops)
+    assert relerr(Y, Yo) < tol
+    # residual of M (M^-1 X) = X
+    assert relerr(ops.apply_M(Y), X) < tol
+
+
+def test_strided_blocks(si_small):
+    """Leading dimensions larger than N (column views of a wider block)."""
+    print("[strided] si_small", flush=True)
+    ctx, ops = context("si_small", si_small)
+    W = np.random.default_rng(3).standard_normal((ops.n, 40))
+    Wd = dev(W)
+    Xv = Wd[:, 3:24]
+    Out = torch.zeros((ops.n, 50), dtype=torch.float64, device="cuda")
+    ctx.apply_H(Xv, Out[:, 7:28])
+    o = host(Out)
+    assert relerr(o[:, 7:28], ops.apply_H(W[:, 3:24])) < 1e-12
+    assert np.all(o[:, :7] == 0) and np.all(o[:, 28:] == 0)
+
+
+@pytest.mark.parametrize("fix,m", [("tiny_enriched", 7), ("hydrogen_small", 12), ("si_small", 10)])
+def test_filter(fix, m, request):
+    print(f"[filter] {fix} m={m}", flush=True)
+    ctx, ops = context(fix, request.getfixturevalue(fix))
+    H, M = None, None
+    v0 = np.random.default_rng(5).standard_normal(ops.n)
+    al, be = lanczos(ops.apply_Htilde, ops.apply_M, v0, 10)
+    lo, hi = lanczos_bounds(al, be)
+    a = lo + 0.05 * (hi - lo)
+    X = np.random.default_rng(6).standard_normal((ops.n, 21))
+    Y = host(ctx.filter(dev(X), m, a, hi))
+    Yo = recurrence_filter(lambda Z: ops.apply_Htilde(Z), X, m, a, hi)
+    assert relerr(Y, Yo) < 10 * U * kappa_M(fix, ops) * m
+
+
+def test_filter_degree_zero_and_one(si_small):
+    ctx, ops = context("si_small", si_small)
+    X = np.random.default_rng(8).standard_normal((ops.n, 9))
+    assert np.array_equal(host(ctx.filter(dev(X), 0, -1.0, 5.0)), X)
+    Y1 = host(ctx.filter(dev(X), 1, -1.0, 5.0))
+    e, c = 2.0 / 6.0, 4.0 / 6.0
+    Yo = e * ops.apply_Htilde(X, "solve") - c * X
+    assert relerr(Y1, Yo) < 10 * U * kappa_M("si_small", ops)
+
+
+def test_cholqr(si_small):
+    print("[cholqr] si_small", flush=True)
+    ctx, ops = context("si_small", si_small)
+    X = np.random.default_rng(9).standard_normal((ops.n, 40)) @ np.diag(np.logspace(0, 5, 40))
+    Q = host(ctx.cholqr(dev(X)))
+    assert np.abs(Q.T @ Q - np.eye(40)).max() < 1e-13
+    Qo = cholqr(X)
+    # same span: projectors agree
+    assert np.abs(Q @ (Q.T @ Qo) - Qo).max() < 1e-11
+    # same columns (no sign freedom: both take R with positive diagonal)
+    assert relerr(Q, Qo) < 1e-10
+
+
+@pytest.mark.parametrize("fix,N", [("hydrogen_small", 16), ("si_small", 50), ("tiny_enriched", 7)])
+def test_rayleigh_ritz(fix, N, request):
+    print(f"[rayleigh_ritz] {fix} N={N}", flush=True)
+    ctx, ops = context(fix, request.getfixturevalue(fix))
+    v0 = np.random.default_rng(11).standard_normal(ops.n)
+    al, be = lanczos(ops.apply_Htilde, ops.apply_M, v0, 10)
+    lo, hi = lanczos_bounds(al, be)
+    X = np.random.default_rng(12).standard_normal((ops.n, N))
+    # a filtered block, as in the method (moderate degree keeps it well conditioned)
+    Xf = recurrence_filter(lambda Z: ops.apply_Htilde(Z), X, 6, lo + 0.2 * (hi - lo), hi)
+    Yd = dev(Xf)
+    theta = ctx.rayleigh_ritz(Yd)
+    Q = cholqr(Xf)
+    th_o, C = rayleigh_ritz(Q, ops.apply_H(Q), ops.apply_M(Q))
+    assert np.abs(theta - th_o).max() < 1e-8
+    Z = host(Yd)
+    MZ = ops.apply_M(Z)
+    assert np.abs(Z.T @ MZ - np.eye(N)).max() < 1e-10
+    # Ritz pairs: Z^T H Z = diag(theta)
+    assert np.abs(Z.T @ ops.apply_H(Z) - np.diag(theta)).max() < 1e-8 * max(1.0, np.abs(theta).max())
+
+
+@pytest.mark.parametrize("fix", FIXTURES)
+def test_lanczos_bounds(fix, request):
+    print(f"[lanczos] {fix}", flush=True)
+    ctx, ops = context(fix, request.getfixturevalue(fix))
+    v0 = np.random.default_rng(13).standard_normal(ops.n)
+    lo, hi = ctx.lanczos_bounds(dev(v0).reshape(-1), 10)
+    al, be = lanczos(ops.apply_Htilde, ops.apply_M, v0, 10)
+    lo_o, hi_o = lanczos_bounds(al, be)
+    assert abs(lo - lo_o) < 1e-9 * abs(hi_o) and abs(hi - hi_o) < 1e-9 * abs(hi_o)
+
+
+def test_determinism(si_small):
+    ctx, ops = context("si_small", si_small)
+    X = dev(np.random.default_rng(14).standard_normal((ops.n, 33)))
+    a = host(ctx.filter(X, 4, -2.0, 50.0))
+    b = host(ctx.filter(X, 4, -2.0, 50.0))
+    assert np.array_equal(a, b)
+
+
+def test_scf_steps_match_oracle(hydrogen_cfg1):
+    """Two subspace-iteration steps (filter m = 20, Rayleigh-Ritz) from the same
+    start: GPU and oracle Ritz values agree to 1e-8 Ha at every step."""
+    print("[scf] hydrogen 8^3", flush=True)
+    ctx, ops = context("hydrogen_cfg1", hydrogen_cfg1, max_cols=16)
+    N, m = 16, 20
+    X = np.random.default_rng(0).standard_normal((ops.n, N))
+    v0 = np.random.default_rng(1).standard_normal(ops.n)
+    lo, b = ctx.lanczos_bounds(dev(v0).reshape(-1), 10)
+    Xd = dev(X)
+    th = ctx.rayleigh_ritz(Xd)
+    Q = cholqr(X)
+    th_o, C = rayleigh_ritz(Q, ops.apply_H(Q), ops.apply_M(Q))
+    Xo = Q @ C
+    assert np.abs(th - th_o).max() < 1e-8
+    for step in range(2):
+        a = th[-1]
+        Yd = ctx.filter(Xd, m, a, b)
+        th = ctx.rayleigh_ritz(Yd)
+        Yo = recurrence_filter(lambda Z: ops.apply_Htilde(Z), Xo, m, th_o[-1], b)
+        Q = cholqr(Yo)
+        th_o, C = rayleigh_ritz(Q, ops.apply_H(Q), ops.apply_M(Q))
+        Xo = Q @ C
+        Xd = Yd
+        assert np.abs(th - th_o).max() < 1e-8, step
+
+
+# ---------------------------------------------------------------- error paths
+def test_invalid_arguments(si_small):
+    from paper_1610_02121_amd import ChebFilterError
+    ctx, ops = context("si_small", si_small)
+    X = dev(np.ones((ops.n, 4)))
+    with pytest.raises(ChebFilterError, match="CF_EINVAL"):
+        ctx.filter(X, 3, 1.0, 1.0)
+    with pytest.raises(ChebFilterError, match="CF_EINVAL"):
+        ctx.filter(X, -1, 0.0, 1.0)
+    with pytest.raises(ChebFilterError, match="CF_EINVAL"):
+        ctx.filter(X, 2, 0.0, float("nan"))
+    with pytest.raises(ChebFilterError, match="CF_EINVAL"):
+        ctx.filter(X, 2, 0.0, 1.0, Y=X)
+    with pytest.raises(ChebFilterError, match="CF_EINVAL"):
+        ctx.filter(X, 2, 0.0, 1.0, prec="bf16")
+    big = dev(np.ones((ops.n, ctx.max_cols + 1)))
+    with pytest.raises(ChebFilterError, match="CF_ENOMEM"):
+        ctx.apply_H(big)
+    with pytest.raises(ChebFilterError, match="CF_ENOTSPD"):
+        ctx.cholqr(dev(np.zeros((ops.n, 3))))
+    empty = dev(np.ones((ops.n, 0)))
+    assert ctx.apply_H(empty).shape == (ops.n, 0)
+
+
+def test_init_rejects_bad_problems(tiny_enriched):
+    import copy
+    from paper_1610_02121_amd import ChebFilterError, Context
+    P = copy.deepcopy(tiny_enriched)
+    P.M_ee = np.zeros_like(P.M_ee)                # Schur complement negative definite
+    with pytest.raises(ChebFilterError, match="CF_ENOTSPD"):
+        Context(P, max_cols=4)
+    Q = copy.deepcopy(tiny_enriched)
+    Q.H_cc = Q.H_cc.copy()
+    Q.H_cc[0, 0, 1] += 1.0                        # not symmetric
+    with pytest.raises(ChebFilterError, match="CF_EINVAL"):
+        Context(Q, max_cols=4)
+    R = copy.deepcopy(tiny_enriched)
+    R.cell_dof = R.cell_dof.copy()
+    R.cell_dof[0, 0] = R.n_h + 5                  # out of range
+    with pytest.raises(ChebFilterError, match="CF_EINVAL"):
+        Context(R, max_cols=4)
+    S = copy.deepcopy(tiny_enriched)
+    S.enr_idx = S.enr_idx.copy()
+    S.enr_idx[0] = 7                              # alpha >= n_e
+    with pytest.raises(ChebFilterError, match="CF_EINVAL"):
+        Context(S, max_cols=4)

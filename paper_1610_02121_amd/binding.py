@@ -68,7 +68,8 @@ def load_library() -> C.CDLL:
     lib.chebfilter_rayleigh_ritz.argtypes = [vp, vp, i64, i64, vp]
     lib.chebfilter_lanczos_bounds.argtypes = [vp, vp, i32, C.POINTER(dbl), C.POINTER(dbl)]
     lib.chebfilter_profile.argtypes = [vp, i32]
-    lib.chebfilter_profile_query.argtypes = [vp, C.c_char_p, C.POINTER(i64), C.POINTER(dbl)]
+    lib.chebfilter_profile_query.argtypes = [vp, C.c_char_p, C.POINTER(i64), C.POINTER(dbl),
+                                             C.POINTER(dbl)]
     for nm in EXPORTS:
         if nm != "chebfilter_last_error":
             getattr(lib, nm).restype = C.c_int
@@ -191,8 +192,9 @@ class Context:
     def profile(self, enable: bool):
         self._check(self.lib.chebfilter_profile(self._h, int(enable)))
 
-    def profile_query(self, name: str) -> tuple[int, float]:
-        n, ms = C.c_int64(), C.c_double()
+    def profile_query(self, name: str) -> tuple[int, float, float]:
+        """(launches, total milliseconds, total algorithmic flops) of a kernel family."""
+        n, ms, fl = C.c_int64(), C.c_double(), C.c_double()
         self._check(self.lib.chebfilter_profile_query(self._h, name.encode(), C.byref(n),
-                                                      C.byref(ms)))
-        return n.value, ms.value
+                                                      C.byref(ms), C.byref(fl)))
+        return n.value, ms.value, fl.value

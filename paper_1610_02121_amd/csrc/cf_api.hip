@@ -25,6 +25,7 @@ namespace {
 struct ProfEntry {
   int64_t launches = 0;
   double ms = 0.0;
+  double flops = 0.0;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
 };
 
@@ -110,19 +111,23 @@ static cf_status dalloc(cf_ctx *c, T **p, size_t count) {
   return CF_OK;
 }
 
-// Event-timed kernel family (only when profiling is on).
+// Event-timed kernel family (only when profiling is on); `flops` is the
+// algorithmic work credited to the bracketed launches.
 struct Scope {
   cf_ctx *c;
   const char *name;
+  double flops;
   hipEvent_t a = nullptr, b = nullptr;
-  Scope(cf_ctx *c_, const char *n) : c(c_), name(n) {
+  Scope(cf_ctx *c_, const char *n, double f = 0.0) : c(c_), name(n), flops(f) {
     if (c->profiling && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess)
       (void)hipEventRecord(a, c->stream);
   }
   ~Scope() {
     if (c->profiling && a && b) {
       (void)hipEventRecord(b, c->stream);
-      c->prof[name].pending.emplace_back(a, b);
+      ProfEntry &pe = c->prof[name];
+      pe.pending.emplace_back(a, b);
+      pe.flops += flops;
     }
   }
 };
@@ -143,7 +148,9 @@ static cf_status check_block(cf_ctx *c, const void *X, int64_t ldx, int64_t N, c
 static cf_status core_apply_H(cf_ctx *c, const double *X, int64_t ldx, double *Y, int64_t ldy,
                               int N) {
   for (size_t k = 0; k + 1 < c->col_off.size(); ++k) {
-    Scope sc(c, "cell_gemm");
+    // elemental dense product: 2 npc^2 N flops per cell
+    Scope sc(c, "cell_gemm",
+             2.0 * c->npc * c->npc * (double)N * (c->col_off[k + 1] - c->col_off[k]));
     HIPCHK(c, launch_cell_gemm(c->stream, c->Hp, c->dofp, c->firstp, c->cells + c->col_off[k],
                                c->col_off[k + 1] - c->col_off[k], X, ldx, Y, ldy, N));
   }
@@ -819,13 +826,14 @@ cf_status chebfilter_profile(cf_ctx *c, int32_t enable) {
 }
 
 cf_status chebfilter_profile_query(cf_ctx *c, const char *name, int64_t *launches,
-                                   double *total_ms) {
+                                   double *total_ms, double *total_flops) {
   if (!c || !name) return CF_EINVAL;
   HIPCHK(c, hipStreamSynchronize(c->stream));
   auto it = c->prof.find(name);
   if (it == c->prof.end()) {
     if (launches) *launches = 0;
     if (total_ms) *total_ms = 0.0;
+    if (total_flops) *total_flops = 0.0;
     return CF_OK;
   }
   ProfEntry &pe = it->second;
@@ -839,6 +847,7 @@ cf_status chebfilter_profile_query(cf_ctx *c, const char *name, int64_t *launche
   pe.pending.clear();
   if (launches) *launches = pe.launches;
   if (total_ms) *total_ms = pe.ms;
+  if (total_flops) *total_flops = pe.flops;
   return CF_OK;
 }
 

@@ -108,8 +108,13 @@ hipError_t launch_cell_gemm(hipStream_t s, const double *Hp, const int32_t *dofp
                             const uint8_t *firstp, const int32_t *cells, int ncells,
                             const double *X, int64_t ldx, double *Y, int64_t ldy, int N) {
   if (ncells <= 0 || N <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_cell_gemm<CT>, dim3(ncells), dim3(256), 0, s, Hp, dofp, firstp, cells, X,
-                     ldx, Y, ldy, N);
+  // narrow blocks (a single vector in the Lanczos run) use a 16-column instance
+  if (N <= 16)
+    hipLaunchKernelGGL(k_cell_gemm<16>, dim3(ncells), dim3(256), 0, s, Hp, dofp, firstp, cells, X,
+                       ldx, Y, ldy, N);
+  else
+    hipLaunchKernelGGL(k_cell_gemm<CT>, dim3(ncells), dim3(256), 0, s, Hp, dofp, firstp, cells, X,
+                       ldx, Y, ldy, N);
   return hipGetLastError();
 }
 

@@ -108,6 +108,25 @@ def si_cluster(n_atoms: int = 30, length: float = 48.0, nc: int = 24, p: int = 4
     return prob
 
 
+def initial_block(prob: Problem, N: int, seed: int = 0) -> np.ndarray:
+    """Starting subspace built from the atomic orbitals (the enrichment functions).
+
+    The lowest N generalized eigenvectors of the enrichment pencil
+    (H^ee, M^ee) are placed in the enrichment rows (classical rows zero);
+    columns beyond n_e, or every column when there is no enrichment, are
+    drawn N(0, 1) from `seed`.
+    """
+    import scipy.linalg as sla
+    X = np.zeros((prob.n, N))
+    k = min(N, prob.n_e)
+    if k:
+        _, V = sla.eigh(prob.H_ee, prob.M_ee)
+        X[prob.n_h:, :k] = V[:, :k]
+    if k < N:
+        X[:, k:] = np.random.default_rng(seed).standard_normal((prob.n, N - k))
+    return X
+
+
 # Named workloads (sizes of the paper-shaped synthetic configurations).
 def config1(**kw) -> Problem:
     """Hydrogen, 20 Bohr cube, 8^3 cells of degree 4, r_c = 6 (N = 16, m = 20)."""

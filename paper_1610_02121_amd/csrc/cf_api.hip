@@ -46,17 +46,24 @@ struct cf_ctx {
   double *dvec = nullptr, *dinv = nullptr;
   int32_t *cells = nullptr;
   std::vector<int> col_off;
-  // enrichment
+  // enrichment: per-cell blocks (transposed, for the partial products), the
+  // node-major assembled coupling (CSR over classical DOFs) and dense blocks
   int64_t nnz = 0;
   int kmax = 0;
-  double *Hec = nullptr, *Mec = nullptr;
+  double *HT = nullptr, *MT = nullptr;
+  int64_t *toff = nullptr;
+  int32_t *tld = nullptr;
   int64_t *eptr = nullptr;
-  int32_t *eidx = nullptr;
   int32_t *ecells = nullptr;
-  std::vector<int> ecol_off;
+  int necells = 0;
   int64_t *aptr = nullptr;
   int32_t *alist = nullptr;
-  double *Hee = nullptr, *Mee = nullptr, *Sinv = nullptr;
+  double *Hec = nullptr, *Mec = nullptr;   // per-cell blocks, rows padded to NPAD
+  int32_t *eidx = nullptr;
+  int32_t *qptr = nullptr, *qidx = nullptr; // classical DOF -> rows of the cell buffer Q
+  double *Q = nullptr;                      // [necells * NPAD][max_cols]
+  int64_t csr_nnz = 0, nreg = 0;
+  double *Hee = nullptr, *Mee = nullptr, *Sinv = nullptr, *Hmod = nullptr;
   // block workspace, leading dimension max_cols
   double *R = nullptr, *P = nullptr, *Wb = nullptr, *Zb = nullptr, *B2 = nullptr, *T = nullptr,
          *U = nullptr;
@@ -144,9 +151,8 @@ static cf_status check_block(cf_ctx *c, const void *X, int64_t ldx, int64_t N, c
 // ---------------------------------------------------------------------------
 // operator cores (all enqueue on c->stream)
 // ---------------------------------------------------------------------------
-// Y = H^E X (Y rows: n, ld ldy)
-static cf_status core_apply_H(cf_ctx *c, const double *X, int64_t ldx, double *Y, int64_t ldy,
-                              int N) {
+// Classical elemental products R' = H^cc X over all colours (Y rows 0..n_h).
+static cf_status core_cells(cf_ctx *c, const double *X, int64_t ldx, double *Y, int64_t ldy, int N) {
   for (size_t k = 0; k + 1 < c->col_off.size(); ++k) {
     // elemental dense product: 2 npc^2 N flops per cell
     Scope sc(c, "cell_gemm",
@@ -154,88 +160,136 @@ static cf_status core_apply_H(cf_ctx *c, const double *X, int64_t ldx, double *Y
     HIPCHK(c, launch_cell_gemm(c->stream, c->Hp, c->dofp, c->firstp, c->cells + c->col_off[k],
                                c->col_off[k + 1] - c->col_off[k], X, ldx, Y, ldy, N));
   }
-  if (c->n_e == 0) return CF_OK;
-  const double *Xe = X + c->n_h * ldx;
-  Scope sc(c, "enr_gemm");
-  for (size_t k = 0; k + 1 < c->ecol_off.size(); ++k)
-    HIPCHK(c, launch_enr_T(c->stream, c->Hec, c->eptr, c->eidx, c->dofp, c->ecells + c->ecol_off[k],
-                           c->ecol_off[k + 1] - c->ecol_off[k], c->kmax, Xe, ldx, Y, ldy, N, 1.0));
-  const int ne_cells = c->ecol_off.back();
-  HIPCHK(c, launch_enr_N(c->stream, c->Hec, c->eptr, c->dofp, c->ecells, ne_cells, X, ldx, nullptr,
-                         c->P, c->max_cols, N));
-  HIPCHK(c, launch_enr_reduce(c->stream, (int)c->n_e, c->aptr, c->alist, c->P, c->max_cols, 1.0,
-                              nullptr, 0, 0.0, c->Hee, Xe, ldx, Y + c->n_h * ldy, ldy, N));
   return CF_OK;
 }
 
-// Y = M^E X
+static EpiArgs epi_base(cf_ctx *c, int N) {
+  EpiArgs g;
+  g.n_h = c->n_h;
+  g.n_e = c->n_e;
+  g.N = N;
+  if (c->n_e > 0) {
+    g.qptr = c->qptr;
+    g.qidx = c->qidx;
+    g.Q = c->Q;
+    g.ldq = c->max_cols;
+  }
+  return g;
+}
+
+// Q = cell-local transposed coupling products (see k_enr_q).
+static cf_status core_enr_q(cf_ctx *c, const double *U, int64_t ldu, double cU, const double *V,
+                            int64_t ldv, double cV, int N) {
+  Scope sc(c, "enr_gemm");
+  HIPCHK(c, launch_enr_q(c->stream, c->Hec, c->Mec, c->eptr, c->eidx, c->ecells, c->necells, c->kmax,
+                         U, ldu, cU, V, ldv, cV, c->Q, c->max_cols, N));
+  return CF_OK;
+}
+
+// Y = H^E X (Eq. H2x2): Y_c = H^cc X_c + H^ec^T X_e, Y_e = H^ec X_c + H^ee X_e.
+static cf_status core_apply_H(cf_ctx *c, const double *X, int64_t ldx, double *Y, int64_t ldy,
+                              int N) {
+  STCHK(core_cells(c, X, ldx, Y, ldy, N));
+  if (c->n_e == 0) return CF_OK;
+  const double *Xe = X + c->n_h * ldx;
+  double *Ye = Y + c->n_h * ldy;
+  {
+    Scope sc(c, "enr_gemm");
+    HIPCHK(c, launch_enr_part(c->stream, c->HT, c->MT, c->toff, c->tld, c->eptr, c->dofp, c->ecells,
+                              c->necells, X, ldx, 1.0, nullptr, 0, nullptr, 0.0, c->P, c->max_cols,
+                              N));
+    HIPCHK(c, launch_enr_reduce(c->stream, (int)c->n_e, c->aptr, c->alist, c->P, c->max_cols, 1.0,
+                                nullptr, 0, 0.0, c->Hee, Xe, ldx, Ye, ldy, N));
+  }
+  STCHK(core_enr_q(c, Xe, ldx, 1.0, nullptr, 0, 0.0, N));
+  EpiArgs g = epi_base(c, N);
+  g.R = Y; g.ldr = ldy;
+  g.Ee = Ye; g.lde = ldy;
+  g.Out = Y; g.ldo = ldy;
+  Scope sc(c, "epilogue");
+  HIPCHK(c, launch_epilogue(c->stream, g));
+  return CF_OK;
+}
+
+// Y = M^E X (Eq. M2x2): Y_c = D X_c + M^ec^T X_e, Y_e = M^ec X_c + M^ee X_e.
 static cf_status core_apply_M(cf_ctx *c, const double *X, int64_t ldx, double *Y, int64_t ldy,
                               int N) {
-  HIPCHK(c, launch_diag_scale(c->stream, c->n_h, c->dvec, X, ldx, Y, ldy, N));
-  if (c->n_e == 0) return CF_OK;
   const double *Xe = X + c->n_h * ldx;
-  Scope sc(c, "enr_gemm");
-  for (size_t k = 0; k + 1 < c->ecol_off.size(); ++k)
-    HIPCHK(c, launch_enr_T(c->stream, c->Mec, c->eptr, c->eidx, c->dofp, c->ecells + c->ecol_off[k],
-                           c->ecol_off[k + 1] - c->ecol_off[k], c->kmax, Xe, ldx, Y, ldy, N, 1.0));
-  const int ne_cells = c->ecol_off.back();
-  HIPCHK(c, launch_enr_N(c->stream, c->Mec, c->eptr, c->dofp, c->ecells, ne_cells, X, ldx, nullptr,
-                         c->P, c->max_cols, N));
-  HIPCHK(c, launch_enr_reduce(c->stream, (int)c->n_e, c->aptr, c->alist, c->P, c->max_cols, 1.0,
-                              nullptr, 0, 0.0, c->Mee, Xe, ldx, Y + c->n_h * ldy, ldy, N));
+  double *Ye = Y + c->n_h * ldy;
+  if (c->n_e > 0) {
+    Scope sc(c, "enr_gemm");
+    HIPCHK(c, launch_enr_part(c->stream, c->HT, c->MT, c->toff, c->tld, c->eptr, c->dofp, c->ecells,
+                              c->necells, nullptr, 0, 0.0, X, ldx, nullptr, 1.0, c->P, c->max_cols,
+                              N));
+    HIPCHK(c, launch_enr_reduce(c->stream, (int)c->n_e, c->aptr, c->alist, c->P, c->max_cols, 1.0,
+                                nullptr, 0, 0.0, c->Mee, Xe, ldx, Ye, ldy, N));
+    STCHK(core_enr_q(c, nullptr, 0, 0.0, Xe, ldx, 1.0, N));
+  }
+  EpiArgs g = epi_base(c, N);
+  g.R = X; g.ldr = ldx; g.dR = c->dvec;
+  g.Ee = Ye; g.lde = ldy;
+  g.Out = Y; g.ldo = ldy;
+  Scope sc(c, "epilogue");
+  HIPCHK(c, launch_epilogue(c->stream, g));
   return CF_OK;
 }
 
-// Block-wise inverse (Sec. IV.D) on R (n rows, ld ldr), in place on the
-// classical rows: afterwards (M^E)^-1 r = [dinv .* R_c ; z] with z in Zb
-// (ld max_cols).  Steps: u = D^-1 r_c; w = r_e - M^ec u; z = S^-1 w;
-// r_c <- r_c - M^ec^T z (the final D^-1 is applied by the caller's epilogue).
-static cf_status core_sinv(cf_ctx *c, double *R, int64_t ldr, int N) {
-  if (c->n_e == 0) return CF_OK;
+// z = S^-1 w into Zb, where w (in Wb) has been formed by the caller.
+static cf_status core_schur_solve(cf_ctx *c, int N) {
   Scope sc(c, "enr_gemm");
-  const int ne_cells = c->ecol_off.back();
-  HIPCHK(c, launch_enr_N(c->stream, c->Mec, c->eptr, c->dofp, c->ecells, ne_cells, R, ldr, c->dinv,
-                         c->P, c->max_cols, N));
-  HIPCHK(c, launch_enr_reduce(c->stream, (int)c->n_e, c->aptr, c->alist, c->P, c->max_cols, -1.0,
-                              R + c->n_h * ldr, ldr, 1.0, nullptr, nullptr, 0, c->Wb, c->max_cols,
-                              N));
   HIPCHK(c, launch_enr_reduce(c->stream, (int)c->n_e, c->aptr, c->alist, nullptr, 0, 0.0, nullptr, 0,
                               0.0, c->Sinv, c->Wb, c->max_cols, c->Zb, c->max_cols, N));
-  for (size_t k = 0; k + 1 < c->ecol_off.size(); ++k)
-    HIPCHK(c, launch_enr_T(c->stream, c->Mec, c->eptr, c->eidx, c->dofp, c->ecells + c->ecol_off[k],
-                           c->ecol_off[k + 1] - c->ecol_off[k], c->kmax, c->Zb, c->max_cols, R, ldr,
-                           N, -1.0));
   return CF_OK;
 }
 
-// Out = c1 * H~ Xin + c2 * Yk + c3 * Yp   (H~ = (M^E)^-1 H^E), via R and Zb.
+// Out = c1 * H~ Xin + c2 * Yk + c3 * Yp, H~ = (M^E)^-1 H^E, with the block-wise
+// inverse of Sec. IV.D.  With R' = H^cc X_c and K = M^ec D^-1 H^ec^T (formed
+// at init):  w = H^ec X_c - M^ec D^-1 R' + (H^ee - K) X_e,  z = S^-1 w,
+// y_c = D^-1 (R' + H^ec^T X_e - M^ec^T z),  y_e = z; the two transposed
+// coupling products go through the enriched-cell buffer Q.
 static cf_status core_htilde_step(cf_ctx *c, const double *Xin, int64_t ldxin, int N, double c1,
                                   const double *Yk, int64_t ldyk, double c2, const double *Yp,
                                   int64_t ldyp, double c3, double *Out, int64_t ldo) {
   const int64_t ldr = c->max_cols;
-  STCHK(core_apply_H(c, Xin, ldxin, c->R, ldr, N));
-  STCHK(core_sinv(c, c->R, ldr, N));
+  STCHK(core_cells(c, Xin, ldxin, c->R, ldr, N));
+  const double *Xe = Xin + c->n_h * ldxin;
+  if (c->n_e > 0) {
+    {
+      Scope sc(c, "enr_gemm");
+      HIPCHK(c, launch_enr_part(c->stream, c->HT, c->MT, c->toff, c->tld, c->eptr, c->dofp,
+                                c->ecells, c->necells, Xin, ldxin, 1.0, c->R, ldr, c->dinv, -1.0,
+                                c->P, c->max_cols, N));
+      HIPCHK(c, launch_enr_reduce(c->stream, (int)c->n_e, c->aptr, c->alist, c->P, c->max_cols, 1.0,
+                                  nullptr, 0, 0.0, c->Hmod, Xe, ldxin, c->Wb, c->max_cols, N));
+    }
+    STCHK(core_schur_solve(c, N));
+    STCHK(core_enr_q(c, Xe, ldxin, 1.0, c->Zb, c->max_cols, -1.0, N));
+  }
+  EpiArgs g = epi_base(c, N);
+  g.R = c->R; g.ldr = ldr; g.dR = c->dinv; g.dC = c->dinv;
+  g.Ee = c->Zb; g.lde = c->max_cols;
+  g.c1 = c1; g.Yk = Yk; g.ldyk = ldyk; g.c2 = c2; g.Yp = Yp; g.ldyp = ldyp; g.c3 = c3;
+  g.Out = Out; g.ldo = ldo;
   Scope sc(c, "epilogue");
-  HIPCHK(c, launch_epilogue(c->stream, c->n_h, c->n_e, c->dinv, c->R, ldr, c->Zb, c->max_cols, c1,
-                            Yk, ldyk, c2, Yp, ldyp, c3, Out, ldo, N));
+  HIPCHK(c, launch_epilogue(c->stream, g));
   return CF_OK;
 }
 
 // Gram G = A^T B (N x N, ld N) through the chunked partial kernel.
 static cf_status core_gram(cf_ctx *c, const double *A, int64_t lda, const double *B, int64_t ldb,
-                           int64_t nrows, int N, double *Gout, int upper) {
+                           int64_t nrows, int N, double *Gout, int mode) {
   Scope sc(c, "gram");
   const int nch = c->gp_chunks;
   const int64_t chunk_rows = (nrows + nch - 1) / nch;
-  HIPCHK(c, launch_gram_partial(c->stream, A, lda, B, ldb, nrows, N, nch, chunk_rows, c->Gp, upper));
-  HIPCHK(c, launch_gram_reduce(c->stream, c->Gp, nch, N, Gout, upper));
+  HIPCHK(c, launch_gram_partial(c->stream, A, lda, B, ldb, nrows, N, nch, chunk_rows, c->Gp, mode));
+  HIPCHK(c, launch_gram_reduce(c->stream, c->Gp, nch, N, Gout, mode));
   return CF_OK;
 }
 
 // One Cholesky-QR pass In -> Out (Out = In * S * L^-T, G' = S In^T In S = L L^T).
 static cf_status core_cholqr_pass(cf_ctx *c, const double *In, int64_t ldi, double *Out,
                                   int64_t ldo, int N, double shift, int *failed) {
-  STCHK(core_gram(c, In, ldi, In, ldi, c->n, N, c->G, 1));
+  STCHK(core_gram(c, In, ldi, In, ldi, c->n, N, c->G, GRAM_UPPER));
   HIPCHK(c, hipMemsetAsync(c->flag, 0, sizeof(int), c->stream));
   HIPCHK(c, launch_cholesky(c->stream, c->G, N, 1, shift, c->sv, c->flag));
   int h_flag = 0;
@@ -457,7 +511,6 @@ static cf_status do_init(const cf_problem *pr, const cf_options *opt, cf_ctx *c)
 
   // ---- enrichment data
   c->col_off.shrink_to_fit();
-  c->ecol_off.assign(1, 0);
   if (n_e > 0) {
     const int64_t *ep = pr->enr_ptr;
     if (ep[0] != 0) return set_err(c, CF_EINVAL, "init: enr_ptr[0] must be 0");
@@ -466,59 +519,90 @@ static cf_status do_init(const cf_problem *pr, const cf_options *opt, cf_ctx *c)
       if (ep[e + 1] < ep[e]) return set_err(c, CF_EINVAL, "init: enr_ptr not monotone");
       kmax = std::max<int>(kmax, (int)(ep[e + 1] - ep[e]));
     }
-    if (kmax > 416) return set_err(c, CF_EINVAL, "init: more than 416 enrichment functions in a cell");
     c->kmax = kmax;
     const int64_t nnz = ep[E];
     c->nnz = nnz;
-    std::vector<int32_t> eidx(nnz);
-    std::vector<int64_t> seen(n_e, -1);
-    for (int64_t e = 0; e < E; ++e)
-      for (int64_t k = ep[e]; k < ep[e + 1]; ++k) {
-        const int64_t al = pr->enr_idx[k];
-        if (al < 0 || al >= n_e) return set_err(c, CF_EINVAL, "init: enr_idx out of range");
-        if (seen[al] == e) return set_err(c, CF_EINVAL, "init: repeated enrichment index in a cell");
-        seen[al] = e;
-        eidx[k] = (int32_t)al;
-      }
-    // rows padded to NPAD
-    STCHK(dalloc(c, &c->Hec, (size_t)std::max<int64_t>(nnz, 1) * NPAD));
-    STCHK(dalloc(c, &c->Mec, (size_t)std::max<int64_t>(nnz, 1) * NPAD));
+    std::vector<int32_t> eidx(std::max<int64_t>(nnz, 1));
     {
-      const int64_t batch = 4096;
-      std::vector<double> hb((size_t)batch * NPAD), mb((size_t)batch * NPAD);
-      for (int64_t k0 = 0; k0 < nnz; k0 += batch) {
-        const int64_t nb = std::min(batch, nnz - k0);
-        std::fill(hb.begin(), hb.end(), 0.0);
-        std::fill(mb.begin(), mb.end(), 0.0);
-        for (int64_t k = 0; k < nb; ++k)
-          for (int a = 0; a < npc; ++a) {
-            const double hv = pr->H_ec[(k0 + k) * npc + a], mv = pr->M_ec[(k0 + k) * npc + a];
-            if (!std::isfinite(hv) || !std::isfinite(mv))
-              return set_err(c, CF_EINVAL, "init: non-finite H_ec / M_ec");
-            hb[k * NPAD + a] = hv;
-            mb[k * NPAD + a] = mv;
-          }
-        HIPCHK(c, hipMemcpy(c->Hec + k0 * NPAD, hb.data(), nb * NPAD * sizeof(double), hipMemcpyHostToDevice));
-        HIPCHK(c, hipMemcpy(c->Mec + k0 * NPAD, mb.data(), nb * NPAD * sizeof(double), hipMemcpyHostToDevice));
+      std::vector<int64_t> seen(n_e, -1);
+      for (int64_t e = 0; e < E; ++e)
+        for (int64_t k = ep[e]; k < ep[e + 1]; ++k) {
+          const int64_t al = pr->enr_idx[k];
+          if (al < 0 || al >= n_e) return set_err(c, CF_EINVAL, "init: enr_idx out of range");
+          if (seen[al] == e) return set_err(c, CF_EINVAL, "init: repeated enrichment index in a cell");
+          seen[al] = e;
+          eidx[k] = (int32_t)al;
+        }
+    }
+    for (int64_t q = 0; q < nnz * npc; ++q)
+      if (!std::isfinite(pr->H_ec[q]) || !std::isfinite(pr->M_ec[q]))
+        return set_err(c, CF_EINVAL, "init: non-finite H_ec / M_ec");
+    for (int64_t q = 0; q < n_e * n_e; ++q)
+      if (!std::isfinite(pr->H_ee[q]) || !std::isfinite(pr->M_ee[q]))
+        return set_err(c, CF_EINVAL, "init: non-finite H_ee / M_ee");
+
+    // enriched cells in cell order, and grouped by colour for the setup scatter
+    std::vector<int32_t> elist;
+    std::vector<std::vector<int32_t>> ebycol(ncol);
+    for (int64_t e = 0; e < E; ++e)
+      if (ep[e + 1] > ep[e]) {
+        elist.push_back((int32_t)e);
+        ebycol[colour[e]].push_back((int32_t)e);
+      }
+    c->necells = (int)elist.size();
+
+    // transposed per-cell blocks [NPAD][nap], nap = count padded to 16
+    std::vector<int64_t> toff(E, 0);
+    std::vector<int32_t> tld(E, 0);
+    int64_t ttot = 0;
+    for (int32_t e : elist) {
+      const int na = (int)(ep[e + 1] - ep[e]);
+      tld[e] = (na + 15) & ~15;
+      toff[e] = ttot;
+      ttot += (int64_t)NPAD * tld[e];
+    }
+    STCHK(dalloc(c, &c->HT, (size_t)std::max<int64_t>(ttot, 1)));
+    STCHK(dalloc(c, &c->MT, (size_t)std::max<int64_t>(ttot, 1)));
+    {
+      std::vector<double> hb, mb;
+      size_t ci0 = 0;
+      while (ci0 < elist.size()) {
+        // stage up to ~32 MB of blocks per copy
+        size_t ci1 = ci0;
+        int64_t len = 0;
+        while (ci1 < elist.size() && (len == 0 || len + (int64_t)NPAD * tld[elist[ci1]] <= (4ll << 20))) {
+          len += (int64_t)NPAD * tld[elist[ci1]];
+          ++ci1;
+        }
+        hb.assign(len, 0.0);
+        mb.assign(len, 0.0);
+        const int64_t base = toff[elist[ci0]];
+        for (size_t q = ci0; q < ci1; ++q) {
+          const int32_t e = elist[q];
+          const int nap = tld[e];
+          double *ho = hb.data() + (toff[e] - base), *mo = mb.data() + (toff[e] - base);
+          for (int64_t k = ep[e]; k < ep[e + 1]; ++k)
+            for (int a = 0; a < npc; ++a) {
+              ho[(int64_t)a * nap + (k - ep[e])] = pr->H_ec[k * npc + a];
+              mo[(int64_t)a * nap + (k - ep[e])] = pr->M_ec[k * npc + a];
+            }
+        }
+        HIPCHK(c, hipMemcpy(c->HT + base, hb.data(), len * sizeof(double), hipMemcpyHostToDevice));
+        HIPCHK(c, hipMemcpy(c->MT + base, mb.data(), len * sizeof(double), hipMemcpyHostToDevice));
+        ci0 = ci1;
       }
     }
+    STCHK(dalloc(c, &c->toff, E));
+    STCHK(dalloc(c, &c->tld, E));
     STCHK(dalloc(c, &c->eptr, E + 1));
-    STCHK(dalloc(c, &c->eidx, std::max<int64_t>(nnz, 1)));
+    STCHK(dalloc(c, &c->ecells, std::max<size_t>(elist.size(), 1)));
+    HIPCHK(c, hipMemcpy(c->toff, toff.data(), E * sizeof(int64_t), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->tld, tld.data(), E * sizeof(int32_t), hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(c->eptr, ep, (E + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
-    if (nnz) HIPCHK(c, hipMemcpy(c->eidx, eidx.data(), nnz * sizeof(int32_t), hipMemcpyHostToDevice));
-    // enriched cells grouped by colour (same colouring as the classical pass)
-    std::vector<int32_t> eorder;
-    for (int col = 0; col < ncol; ++col) {
-      for (int i = c->col_off[col]; i < c->col_off[col + 1]; ++i) {
-        const int32_t e = order[i];
-        if (ep[e + 1] > ep[e]) eorder.push_back(e);
-      }
-      c->ecol_off.push_back((int)eorder.size());
-    }
-    STCHK(dalloc(c, &c->ecells, std::max<size_t>(eorder.size(), 1)));
-    if (!eorder.empty())
-      HIPCHK(c, hipMemcpy(c->ecells, eorder.data(), eorder.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-    // alpha -> list of partial rows, increasing row index
+    if (!elist.empty())
+      HIPCHK(c, hipMemcpy(c->ecells, elist.data(), elist.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+
+    // alpha -> list of partial rows, increasing row index (fixed summation order)
     std::vector<int64_t> aptr(n_e + 1, 0);
     for (int64_t k = 0; k < nnz; ++k) aptr[eidx[k] + 1]++;
     for (int64_t a = 0; a < n_e; ++a) aptr[a + 1] += aptr[a];
@@ -531,71 +615,167 @@ static cf_status do_init(const cf_problem *pr, const cf_options *opt, cf_ctx *c)
     STCHK(dalloc(c, &c->alist, alist.size()));
     HIPCHK(c, hipMemcpy(c->aptr, aptr.data(), (n_e + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(c->alist, alist.data(), alist.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-    // dense enrichment blocks
-    for (int64_t q = 0; q < n_e * n_e; ++q)
-      if (!std::isfinite(pr->H_ee[q]) || !std::isfinite(pr->M_ee[q]))
-        return set_err(c, CF_EINVAL, "init: non-finite H_ee / M_ee");
+
+    // node-major coupling: CSR pattern over classical DOFs (columns = alpha)
+    std::vector<int64_t> keys;
+    for (int32_t e : elist)
+      for (int a = 0; a < npc; ++a) {
+        const int32_t d = dof[(int64_t)e * NPAD + a];
+        if (d < 0) continue;
+        for (int64_t k = ep[e]; k < ep[e + 1]; ++k) keys.push_back((int64_t)d * n_e + eidx[k]);
+      }
+    std::sort(keys.begin(), keys.end());
+    keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
+    if ((int64_t)keys.size() >= (int64_t)INT32_MAX)
+      return set_err(c, CF_EINVAL, "init: coupling pattern too large");
+    c->csr_nnz = (int64_t)keys.size();
+    std::vector<int32_t> rowptr(n_h + 1, 0), ci(std::max<size_t>(keys.size(), 1));
+    for (size_t q = 0; q < keys.size(); ++q) {
+      rowptr[keys[q] / n_e + 1]++;
+      ci[q] = (int32_t)(keys[q] % n_e);
+    }
+    for (int64_t d = 0; d < n_h; ++d) rowptr[d + 1] += rowptr[d];
+    std::vector<int32_t> smap((size_t)std::max<int64_t>(nnz, 1) * NPAD, -1);
+    for (int32_t e : elist)
+      for (int a = 0; a < npc; ++a) {
+        const int32_t d = dof[(int64_t)e * NPAD + a];
+        if (d < 0) continue;
+        const int64_t *row = keys.data();
+        for (int64_t k = ep[e]; k < ep[e + 1]; ++k) {
+          const int64_t key = (int64_t)d * n_e + eidx[k];
+          const int64_t pos = std::lower_bound(row + rowptr[d], row + rowptr[d + 1], key) - row;
+          smap[k * NPAD + a] = (int32_t)pos;
+        }
+      }
+    std::vector<int32_t> regrow;
+    for (int64_t d = 0; d < n_h; ++d)
+      if (rowptr[d + 1] > rowptr[d]) regrow.push_back((int32_t)d);
+    const int64_t nreg = (int64_t)regrow.size();
+    c->nreg = nreg;
+    // classical DOF -> rows 128 e' + a of the enriched-cell buffer
+    {
+      std::vector<int32_t> qptr(n_h + 1, 0);
+      for (size_t q = 0; q < elist.size(); ++q)
+        for (int a = 0; a < npc; ++a) {
+          const int32_t d = dof[(int64_t)elist[q] * NPAD + a];
+          if (d >= 0) qptr[d + 1]++;
+        }
+      for (int64_t d = 0; d < n_h; ++d) qptr[d + 1] += qptr[d];
+      std::vector<int32_t> qidx(std::max<int32_t>(qptr[n_h], 1));
+      std::vector<int32_t> fill(qptr.begin(), qptr.end() - 1);
+      for (size_t q = 0; q < elist.size(); ++q)
+        for (int a = 0; a < npc; ++a) {
+          const int32_t d = dof[(int64_t)elist[q] * NPAD + a];
+          if (d >= 0) qidx[fill[d]++] = (int32_t)(q * NPAD + a);
+        }
+      STCHK(dalloc(c, &c->qptr, n_h + 1));
+      STCHK(dalloc(c, &c->qidx, qidx.size()));
+      HIPCHK(c, hipMemcpy(c->qptr, qptr.data(), (n_h + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
+      HIPCHK(c, hipMemcpy(c->qidx, qidx.data(), qidx.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    }
+    STCHK(dalloc(c, &c->Q, (size_t)std::max<int>(c->necells, 1) * NPAD * mc));
+    // per-cell coupling rows padded to NPAD, kept for the transposed products
+    STCHK(dalloc(c, &c->Hec, (size_t)std::max<int64_t>(nnz, 1) * NPAD));
+    STCHK(dalloc(c, &c->Mec, (size_t)std::max<int64_t>(nnz, 1) * NPAD));
+    STCHK(dalloc(c, &c->eidx, std::max<int64_t>(nnz, 1)));
+    HIPCHK(c, hipMemcpy(c->eidx, eidx.data(), std::max<int64_t>(nnz, 1) * sizeof(int32_t), hipMemcpyHostToDevice));
+    {
+      const int64_t batch = 4096;
+      std::vector<double> hb((size_t)batch * NPAD), mb2((size_t)batch * NPAD);
+      for (int64_t k0 = 0; k0 < nnz; k0 += batch) {
+        const int64_t nbk = std::min(batch, nnz - k0);
+        std::fill(hb.begin(), hb.end(), 0.0);
+        std::fill(mb2.begin(), mb2.end(), 0.0);
+        for (int64_t k = 0; k < nbk; ++k)
+          for (int a = 0; a < npc; ++a) {
+            hb[k * NPAD + a] = pr->H_ec[(k0 + k) * npc + a];
+            mb2[k * NPAD + a] = pr->M_ec[(k0 + k) * npc + a];
+          }
+        HIPCHK(c, hipMemcpy(c->Hec + k0 * NPAD, hb.data(), nbk * NPAD * sizeof(double), hipMemcpyHostToDevice));
+        HIPCHK(c, hipMemcpy(c->Mec + k0 * NPAD, mb2.data(), nbk * NPAD * sizeof(double), hipMemcpyHostToDevice));
+      }
+    }
+
     STCHK(dalloc(c, &c->Hee, n_e * n_e));
     STCHK(dalloc(c, &c->Mee, n_e * n_e));
     STCHK(dalloc(c, &c->Sinv, n_e * n_e));
+    STCHK(dalloc(c, &c->Hmod, n_e * n_e));
     HIPCHK(c, hipMemcpy(c->Hee, pr->H_ee, n_e * n_e * sizeof(double), hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(c->Mee, pr->M_ee, n_e * n_e * sizeof(double), hipMemcpyHostToDevice));
     STCHK(dalloc(c, &c->P, (size_t)std::max<int64_t>(nnz, 1) * mc));
     STCHK(dalloc(c, &c->Wb, (size_t)n_e * mc));
     STCHK(dalloc(c, &c->Zb, (size_t)n_e * mc));
 
-    // ---- Schur complement S = M^ee - M^ec D^-1 M^ec^T (Sec. IV.D), FP64, on the device.
-    // Assemble Bt = (M^ec)^T restricted to DOFs of enriched cells, scale rows by
-    // D^-1/2, Gram -> M^ec D^-1 M^ec^T, subtract, Cholesky, S^-1 = L^-T L^-1.
-    std::vector<int32_t> dof2reg(n_h, -1), regdof;
-    for (int32_t e : eorder)
-      for (int a = 0; a < npc; ++a) {
-        const int32_t d = dof[(int64_t)e * NPAD + a];
-        if (d >= 0 && dof2reg[d] < 0) { dof2reg[d] = (int32_t)regdof.size(); regdof.push_back(d); }
+    // ---- setup on the device (temporaries released at the end):
+    //  CSR values (assembly of the per-cell coupling blocks by colour),
+    //  S = M^ee - M^ec D^-1 M^ec^T (Sec. IV.D), its Cholesky factor and S^-1,
+    //  K = M^ec D^-1 H^ec^T and H^ee - K.
+    std::vector<void *> temps;
+    auto tmp_alloc = [&](void **p, size_t bytes) -> cf_status {
+      *p = nullptr;
+      if (hipMalloc(p, std::max<size_t>(bytes, 8)) != hipSuccess) {
+        (void)hipGetLastError();
+        return set_err(c, CF_ENOMEM, "init: temporary allocation of " + std::to_string(bytes) + " bytes failed");
       }
-    const int64_t nreg = (int64_t)regdof.size();
-    int32_t *d_dof2reg = nullptr, *d_regdof = nullptr;
-    double *Bt = nullptr, *Sw = nullptr, *Gtmp = nullptr, *GpS = nullptr, *svS = nullptr, *WS = nullptr, *WST = nullptr;
-    int nchS = 8;
-    {
-      const int64_t cap = (int64_t)(512ll << 20) / (8 * n_e * n_e);
-      nchS = (int)std::max<int64_t>(8, std::min<int64_t>(256, cap) / 8 * 8);
-    }
-    auto cleanup = [&]() {
-      for (void *q : {(void *)d_dof2reg, (void *)d_regdof, (void *)Bt, (void *)Sw, (void *)Gtmp,
-                      (void *)GpS, (void *)svS, (void *)WS, (void *)WST}) {
-        if (!q) continue;
-        auto it = std::find(c->allocs.begin(), c->allocs.end(), q);
-        if (it != c->allocs.end()) c->allocs.erase(it);
-        (void)hipFree(q);
-      }
+      temps.push_back(*p);
+      return CF_OK;
     };
+    auto tmp_free = [&]() { for (void *q : temps) (void)hipFree(q); temps.clear(); };
     cf_status st = CF_OK;
     do {
-      if ((st = dalloc(c, &d_dof2reg, n_h)) != CF_OK) break;
-      if ((st = dalloc(c, &d_regdof, std::max<int64_t>(nreg, 1))) != CF_OK) break;
-      if ((st = dalloc(c, &Bt, (size_t)std::max<int64_t>(nreg, 1) * n_e)) != CF_OK) break;
-      if ((st = dalloc(c, &Gtmp, (size_t)n_e * n_e)) != CF_OK) break;
-      if ((st = dalloc(c, &Sw, (size_t)n_e * n_e)) != CF_OK) break;
-      if ((st = dalloc(c, &GpS, (size_t)nchS * n_e * n_e)) != CF_OK) break;
-      if ((st = dalloc(c, &svS, (size_t)n_e)) != CF_OK) break;
-      if ((st = dalloc(c, &WS, (size_t)n_e * n_e)) != CF_OK) break;
-      if ((st = dalloc(c, &WST, (size_t)n_e * n_e)) != CF_OK) break;
+      double *BM = nullptr, *BH = nullptr, *Gt = nullptr, *Sw = nullptr, *GpS = nullptr,
+             *svS = nullptr, *WS = nullptr, *WST = nullptr, *hv = nullptr, *mv = nullptr;
+      int32_t *dsmap = nullptr, *dcol = nullptr, *dreg = nullptr, *drow = nullptr, *dci = nullptr;
+      const size_t nb = (size_t)std::max<int64_t>(nnz, 1) * NPAD;
+      int nchS;
+      {
+        const int64_t cap = (int64_t)(512ll << 20) / (8 * n_e * n_e);
+        nchS = (int)std::max<int64_t>(8, std::min<int64_t>(256, cap) / 8 * 8);
+      }
+      if ((st = tmp_alloc((void **)&dsmap, nb * sizeof(int32_t))) != CF_OK) break;
+      if ((st = tmp_alloc((void **)&dcol, std::max<size_t>(elist.size(), 1) * sizeof(int32_t))) != CF_OK) break;
+      if ((st = tmp_alloc((void **)&dreg, std::max<int64_t>(nreg, 1) * sizeof(int32_t))) != CF_OK) break;
+      if ((st = tmp_alloc((void **)&drow, (n_h + 1) * sizeof(int32_t))) != CF_OK) break;
+      if ((st = tmp_alloc((void **)&dci, ci.size() * sizeof(int32_t))) != CF_OK) break;
+      if ((st = tmp_alloc((void **)&hv, ci.size() * sizeof(double))) != CF_OK) break;
+      if ((st = tmp_alloc((void **)&mv, ci.size() * sizeof(double))) != CF_OK) break;
+      if ((st = tmp_alloc((void **)&BM, (size_t)std::max<int64_t>(nreg, 1) * n_e * sizeof(double))) != CF_OK) break;
+      if ((st = tmp_alloc((void **)&BH, (size_t)std::max<int64_t>(nreg, 1) * n_e * sizeof(double))) != CF_OK) break;
+      if ((st = tmp_alloc((void **)&Gt, (size_t)n_e * n_e * sizeof(double))) != CF_OK) break;
+      if ((st = tmp_alloc((void **)&Sw, (size_t)n_e * n_e * sizeof(double))) != CF_OK) break;
+      if ((st = tmp_alloc((void **)&GpS, (size_t)nchS * n_e * n_e * sizeof(double))) != CF_OK) break;
+      if ((st = tmp_alloc((void **)&svS, (size_t)n_e * sizeof(double))) != CF_OK) break;
+      if ((st = tmp_alloc((void **)&WS, (size_t)n_e * n_e * sizeof(double))) != CF_OK) break;
+      if ((st = tmp_alloc((void **)&WST, (size_t)n_e * n_e * sizeof(double))) != CF_OK) break;
       hipError_t he = hipSuccess;
 #define SCH(call) if ((he = (call)) != hipSuccess) { st = set_err(c, CF_EDEVICE, std::string(#call) + ": " + hipGetErrorString(he)); break; }
-      SCH(hipMemcpy(d_dof2reg, dof2reg.data(), n_h * sizeof(int32_t), hipMemcpyHostToDevice));
-      if (nreg) SCH(hipMemcpy(d_regdof, regdof.data(), nreg * sizeof(int32_t), hipMemcpyHostToDevice));
-      SCH(hipMemsetAsync(Bt, 0, (size_t)std::max<int64_t>(nreg, 1) * n_e * sizeof(double), c->stream));
-      for (int col = 0; col < ncol; ++col)
-        SCH(launch_scatter_coupling(c->stream, c->Mec, c->eptr, c->eidx, c->dofp,
-                                    d_dof2reg, c->ecells + c->ecol_off[col],
-                                    c->ecol_off[col + 1] - c->ecol_off[col], Bt, n_e));
-      if (he != hipSuccess) break;
-      SCH(launch_scale_rows_sqrt(c->stream, nreg, d_regdof, c->dinv, Bt, n_e, (int)n_e));
-      const int64_t crow = (nreg + nchS - 1) / nchS;
-      SCH(launch_gram_partial(c->stream, Bt, n_e, Bt, n_e, nreg, (int)n_e, nchS, crow, GpS, 1));
-      SCH(launch_gram_reduce(c->stream, GpS, nchS, (int)n_e, Gtmp, 1));
-      SCH(launch_sub(c->stream, n_e * n_e, c->Mee, Gtmp, Sw));
+      SCH(hipMemcpy(drow, rowptr.data(), (n_h + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
+      SCH(hipMemcpy(dci, ci.data(), ci.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+      SCH(hipMemsetAsync(hv, 0, ci.size() * sizeof(double), c->stream));
+      SCH(hipMemsetAsync(mv, 0, ci.size() * sizeof(double), c->stream));
+      SCH(hipMemcpy(dsmap, smap.data(), nb * sizeof(int32_t), hipMemcpyHostToDevice));
+      {
+        std::vector<int32_t> cat;
+        std::vector<int> off(1, 0);
+        for (int col = 0; col < ncol; ++col) {
+          cat.insert(cat.end(), ebycol[col].begin(), ebycol[col].end());
+          off.push_back((int)cat.size());
+        }
+        if (!cat.empty()) SCH(hipMemcpy(dcol, cat.data(), cat.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+        for (int col = 0; col < ncol && he == hipSuccess; ++col)
+          he = launch_csr_fill(c->stream, c->Hec, c->Mec, c->eptr, dsmap, dcol + off[col],
+                               off[col + 1] - off[col], hv, mv);
+        if (he != hipSuccess) { st = set_err(c, CF_EDEVICE, std::string("csr_fill: ") + hipGetErrorString(he)); break; }
+      }
+      if (nreg) SCH(hipMemcpy(dreg, regrow.data(), nreg * sizeof(int32_t), hipMemcpyHostToDevice));
+      SCH(hipMemsetAsync(BM, 0, (size_t)std::max<int64_t>(nreg, 1) * n_e * sizeof(double), c->stream));
+      SCH(hipMemsetAsync(BH, 0, (size_t)std::max<int64_t>(nreg, 1) * n_e * sizeof(double), c->stream));
+      SCH(launch_csr_dense(c->stream, nreg, dreg, drow, dci, hv, mv, c->dinv, BM, BH, n_e));
+      const int64_t crow = (std::max<int64_t>(nreg, 1) + nchS - 1) / nchS;
+      // S = M^ee - (D^-1/2 M^ec^T)^T (D^-1/2 M^ec^T)
+      SCH(launch_gram_partial(c->stream, BM, n_e, BM, n_e, nreg, (int)n_e, nchS, crow, GpS, GRAM_UPPER));
+      SCH(launch_gram_reduce(c->stream, GpS, nchS, (int)n_e, Gt, GRAM_UPPER));
+      SCH(launch_sub(c->stream, n_e * n_e, c->Mee, Gt, Sw));
       SCH(hipMemsetAsync(c->flag, 0, sizeof(int), c->stream));
       SCH(launch_cholesky(c->stream, Sw, (int)n_e, 0, 0.0, svS, c->flag));
       int h_flag = 0;
@@ -609,10 +789,15 @@ static cf_status do_init(const cf_problem *pr, const cf_options *opt, cf_ctx *c)
       SCH(launch_tri_inv_T(c->stream, Sw, svS, (int)n_e, WS));          // WS = L^-T
       SCH(launch_transpose(c->stream, (int)n_e, WS, n_e, WST));         // WST = L^-1
       SCH(launch_small_gemm(c->stream, (int)n_e, (int)n_e, (int)n_e, WS, n_e, WST, n_e, c->Sinv, n_e));
+      // K = M^ec D^-1 H^ec^T, H^ee - K
+      SCH(launch_gram_partial(c->stream, BM, n_e, BH, n_e, nreg, (int)n_e, nchS, crow, GpS, GRAM_FULL));
+      SCH(launch_gram_reduce(c->stream, GpS, nchS, (int)n_e, Gt, GRAM_FULL));
+      SCH(launch_sub(c->stream, n_e * n_e, c->Hee, Gt, c->Hmod));
       SCH(hipStreamSynchronize(c->stream));
 #undef SCH
     } while (0);
-    cleanup();
+    (void)hipStreamSynchronize(c->stream);
+    tmp_free();
     if (st != CF_OK) return st;
   }
   HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -686,11 +871,25 @@ cf_status chebfilter_apply_Sinv(cf_ctx *c, const double *X, int64_t ldx, double 
   STCHK(check_block(c, Y, ldy, N, "apply_Sinv Y"));
   if (N == 0) return CF_OK;
   HIPCHK(c, hipSetDevice(c->device));
-  const int64_t ldr = c->max_cols;
-  HIPCHK(c, launch_copy(c->stream, c->n, (int)N, X, ldx, c->R, ldr));
-  STCHK(core_sinv(c, c->R, ldr, (int)N));
-  HIPCHK(c, launch_epilogue(c->stream, c->n_h, c->n_e, c->dinv, c->R, ldr, c->Zb, c->max_cols, 1.0,
-                            nullptr, 0, 0.0, nullptr, 0, 0.0, Y, ldy, (int)N));
+  const int n = (int)N;
+  if (c->n_e > 0) {
+    // w = x_e - M^ec D^-1 x_c ; z = S^-1 w
+    Scope sc(c, "enr_gemm");
+    HIPCHK(c, launch_enr_part(c->stream, c->HT, c->MT, c->toff, c->tld, c->eptr, c->dofp, c->ecells,
+                              c->necells, nullptr, 0, 0.0, X, ldx, c->dinv, -1.0, c->P, c->max_cols,
+                              n));
+    HIPCHK(c, launch_enr_reduce(c->stream, (int)c->n_e, c->aptr, c->alist, c->P, c->max_cols, 1.0,
+                                X + c->n_h * ldx, ldx, 1.0, nullptr, nullptr, 0, c->Wb, c->max_cols,
+                                n));
+    STCHK(core_schur_solve(c, n));
+    STCHK(core_enr_q(c, nullptr, 0, 0.0, c->Zb, c->max_cols, -1.0, n));
+  }
+  // y_c = D^-1 (x_c - M^ec^T z), y_e = z
+  EpiArgs g = epi_base(c, n);
+  g.R = X; g.ldr = ldx; g.dR = c->dinv; g.dC = c->dinv;
+  g.Ee = c->Zb; g.lde = c->max_cols;
+  g.Out = Y; g.ldo = ldy;
+  HIPCHK(c, launch_epilogue(c->stream, g));
   return CF_OK;
 }
 
@@ -749,9 +948,9 @@ cf_status chebfilter_rayleigh_ritz(cf_ctx *c, double *Y, int64_t ldy, int64_t N,
   STCHK(core_cholqr(c, Y, ldy, c->U, ld, n));
   // projected pencil
   STCHK(core_apply_H(c, c->U, ld, c->T, ld, n));
-  STCHK(core_gram(c, c->U, ld, c->T, ld, c->n, n, c->Hh, 0));
+  STCHK(core_gram(c, c->U, ld, c->T, ld, c->n, n, c->Hh, GRAM_SYM));
   STCHK(core_apply_M(c, c->U, ld, c->T, ld, n));
-  STCHK(core_gram(c, c->U, ld, c->T, ld, c->n, n, c->Mh, 0));
+  STCHK(core_gram(c, c->U, ld, c->T, ld, c->n, n, c->Mh, GRAM_SYM));
   // dense generalized eigensolve on the device (eigenvectors column-major in Hh)
   if (rocsolver_dsygvd(c->rb, rocblas_eform_ax, rocblas_evect_original, rocblas_fill_upper, n, c->Hh,
                        n, c->Mh, n, c->theta, c->evE, c->info) != rocblas_status_success)

@@ -41,7 +41,7 @@ __device__ inline void tile_of(int t, int N, int upper, int &ti, int &tj) {
 __global__ __launch_bounds__(256) void k_gram_partial(
     const double *__restrict__ A, int64_t lda, const double *__restrict__ B, int64_t ldb,
     int64_t n, int N, int nchunks, int64_t chunk_rows, int upper, double *__restrict__ Gp) {
-  const int ntl = ntiles_of(N, upper);
+  const int ntl = ntiles_of(N, upper);   // upper != 0: only tiles with ti <= tj
   const int bid = blockIdx.x;
   const int xcd = bid & 7, slot = bid >> 3;
   const int chunk = (slot / ntl) * 8 + xcd;
@@ -90,39 +90,46 @@ __global__ __launch_bounds__(256) void k_gram_partial(
 
 hipError_t launch_gram_partial(hipStream_t s, const double *A, int64_t lda, const double *B,
                                int64_t ldb, int64_t n, int N, int nchunks, int64_t chunk_rows,
-                               double *Gp, int upper_only) {
+                               double *Gp, int mode) {
   if (N <= 0) return hipSuccess;
-  const int ntl = ntiles_of(N, upper_only);
+  const int upper = mode == GRAM_UPPER;
+  const int ntl = ntiles_of(N, upper);
   const int nch8 = (nchunks + 7) / 8 * 8;
   hipLaunchKernelGGL(k_gram_partial, dim3(nch8 * ntl), dim3(256), 0, s, A, lda, B, ldb, n, N,
-                     nchunks, chunk_rows, upper_only, Gp);
+                     nchunks, chunk_rows, upper, Gp);
   return hipGetLastError();
 }
 
 __global__ __launch_bounds__(256) void k_gram_reduce(const double *__restrict__ Gp, int nchunks,
-                                                     int N, double *__restrict__ G, int upper) {
+                                                     int N, double *__restrict__ G, int mode) {
   const int64_t NN = (int64_t)N * N;
   for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < NN; e += (int64_t)gridDim.x * 256) {
     const int i = (int)(e / N), j = (int)(e % N);
+    if (mode == GRAM_FULL) {
+      double sij = 0.0;
+      for (int c = 0; c < nchunks; ++c) sij += Gp[c * NN + (int64_t)i * N + j];
+      G[(int64_t)i * N + j] = sij;
+      continue;
+    }
     if (j < i) continue;
     double sij = 0.0, sji = 0.0;
     for (int c = 0; c < nchunks; ++c) {
       sij += Gp[c * NN + (int64_t)i * N + j];
-      if (!upper) sji += Gp[c * NN + (int64_t)j * N + i];
+      if (mode == GRAM_SYM) sji += Gp[c * NN + (int64_t)j * N + i];
     }
-    const double v = upper ? sij : 0.5 * (sij + sji);
+    const double v = (mode == GRAM_UPPER) ? sij : 0.5 * (sij + sji);
     G[(int64_t)i * N + j] = v;
     G[(int64_t)j * N + i] = v;
   }
 }
 
 hipError_t launch_gram_reduce(hipStream_t s, const double *Gp, int nchunks, int N, double *G,
-                              int upper_only) {
+                              int mode) {
   if (N <= 0) return hipSuccess;
   int64_t blocks = ((int64_t)N * N + 255) / 256;
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)blocks), dim3(256), 0, s, Gp, nchunks, N, G,
-                     upper_only);
+                     mode);
   return hipGetLastError();
 }
 
@@ -447,55 +454,6 @@ __global__ void k_tridiag_bounds(const double *coef, int k, double *out2) {
 hipError_t launch_tridiag_bounds(hipStream_t s, const double *coef, const double * /*unused*/,
                                  int k, double *out2) {
   hipLaunchKernelGGL(k_tridiag_bounds, dim3(1), dim3(64), 0, s, coef, k, out2);
-  return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// Setup helpers for the Schur complement.
-// ---------------------------------------------------------------------------
-// Bt[reg(dof(e,a))][idx[k]] += M[k][a] for the enriched cells of one colour
-// (no two cells of a colour share a DOF, so targets are distinct).
-__global__ __launch_bounds__(128) void k_scatter_coupling(
-    const double *__restrict__ Bp, const int64_t *__restrict__ eptr,
-    const int32_t *__restrict__ eidx, const int32_t *__restrict__ dofp,
-    const int32_t *__restrict__ dof2reg, const int32_t *__restrict__ cells, double *Bt,
-    int64_t ldb) {
-  const int cell = cells[blockIdx.x];
-  const int a = threadIdx.x;
-  const int d = dofp[(int64_t)cell * NPAD + a];
-  if (d < 0) return;
-  const int64_t reg = dof2reg[d];
-  for (int64_t k = eptr[cell]; k < eptr[cell + 1]; ++k)
-    Bt[reg * ldb + eidx[k]] += Bp[k * NPAD + a];
-}
-
-hipError_t launch_scatter_coupling(hipStream_t s, const double *Bp, const int64_t *eptr,
-                                   const int32_t *eidx, const int32_t *dofp,
-                                   const int32_t *dof2reg, const int32_t *cells, int ncells,
-                                   double *Bt, int64_t ldb) {
-  if (ncells <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_scatter_coupling, dim3(ncells), dim3(NPAD), 0, s, Bp, eptr, eidx, dofp,
-                     dof2reg, cells, Bt, ldb);
-  return hipGetLastError();
-}
-
-// Bt[r][:] *= sqrt(dinv[regdof[r]])
-__global__ __launch_bounds__(256) void k_scale_rows_sqrt(int64_t rows, const int32_t *regdof,
-                                                         const double *dinv, double *Bt,
-                                                         int64_t ldb, int ncol) {
-  for (int64_t r = (int64_t)blockIdx.x * 4 + threadIdx.y; r < rows; r += (int64_t)gridDim.x * 4) {
-    const double s = sqrt(dinv[regdof[r]]);
-    for (int j = threadIdx.x; j < ncol; j += 64) Bt[r * ldb + j] *= s;
-  }
-}
-
-hipError_t launch_scale_rows_sqrt(hipStream_t s, int64_t rows, const int32_t *regdof,
-                                  const double *dinv, double *Bt, int64_t ldb, int ncol) {
-  if (rows <= 0) return hipSuccess;
-  int64_t blocks = (rows + 3) / 4;
-  if (blocks > 65536) blocks = 65536;
-  hipLaunchKernelGGL(k_scale_rows_sqrt, dim3((unsigned)blocks), dim3(64, 4), 0, s, rows, regdof,
-                     dinv, Bt, ldb, ncol);
   return hipGetLastError();
 }
 

@@ -9,8 +9,33 @@
 namespace cf {
 
 constexpr int NPAD = 128;     // local nodes per cell padded to a multiple of 16 (npc <= 128)
-constexpr int CT = 32;        // column tile of the cell and enrichment kernels
+constexpr int CELL_NT = 16;   // column tile of the cell-product kernel
 constexpr int GT = 64;        // output tile of the Gram / rotation kernels
+
+// Arguments of the recurrence epilogue (see k_epilogue in cf_ops.hip).
+struct EpiArgs {
+  int64_t n_h = 0, n_e = 0;
+  int N = 0;
+  const double *R = nullptr;        // classical rows [n_h][ldr]
+  int64_t ldr = 0;
+  const double *dR = nullptr;       // per-row scale of R (null = 1)
+  const int32_t *qptr = nullptr;    // per classical DOF: range of its enriched-cell
+  const int32_t *qidx = nullptr;    //   buffer rows (null = no coupling term)
+  const double *Q = nullptr;        // enriched-cell buffer [rows][ldq]
+  int64_t ldq = 0;
+  const double *dC = nullptr;       // per-row scale of the coupling sum (null = 1)
+  const double *Ee = nullptr;       // enrichment rows of the result [n_e][lde]
+  int64_t lde = 0;
+  double c1 = 1.0;
+  const double *Yk = nullptr;
+  int64_t ldyk = 0;
+  double c2 = 0.0;
+  const double *Yp = nullptr;
+  int64_t ldyp = 0;
+  double c3 = 0.0;
+  double *Out = nullptr;
+  int64_t ldo = 0;
+};
 
 // ---- elemental operator kernels (cf_ops.hip)
 // Classical elemental products for the cells of one colour:
@@ -20,19 +45,21 @@ hipError_t launch_cell_gemm(hipStream_t s, const double *Hp, const int32_t *dofp
                             const uint8_t *firstp, const int32_t *cells, int ncells,
                             const double *X, int64_t ldx, double *Y, int64_t ldy, int N);
 
-// Transposed coupling for the enriched cells of one colour:
-//   Y[dof(e,a), :] += sign * sum_k B[k0+k, a] * Z[idx[k0+k], :]
-hipError_t launch_enr_T(hipStream_t s, const double *Bp, const int64_t *eptr,
-                        const int32_t *eidx, const int32_t *dofp, const int32_t *cells,
-                        int ncells, int kmax, const double *Z, int64_t ldz, double *Y,
-                        int64_t ldy, int N, double sign);
+// Coupling partials of the enriched cells (transposed per-cell blocks HT, MT at
+// offsets toff with row length tld):
+//   P[k0+k, :] = cH sum_a H^ec_e[k,a] X[dof(e,a), :] + cM sum_a M^ec_e[k,a] rs[dof] R[dof(e,a), :]
+hipError_t launch_enr_part(hipStream_t s, const double *HT, const double *MT, const int64_t *toff,
+                           const int32_t *tld, const int64_t *eptr, const int32_t *dofp,
+                           const int32_t *cells, int ncells, const double *X, int64_t ldx,
+                           double cH, const double *R, int64_t ldr, const double *rs, double cM,
+                           double *P, int64_t ldp, int N);
 
-// Coupling partials for all enriched cells:
-//   P[k0+k, :] = sum_a B[k0+k, a] * scale(dof) * Zc[dof(e,a), :]   (scale = 1 if dscale null)
-hipError_t launch_enr_N(hipStream_t s, const double *Bp, const int64_t *eptr,
-                        const int32_t *dofp, const int32_t *cells, int ncells,
-                        const double *Zc, int64_t ldz, const double *dscale, double *P,
-                        int64_t ldp, int N);
+// Transposed coupling products of the enriched cells into the cell-local buffer:
+//   Q[128 e' + a, :] = sum_k (cU H^ec_e[k,a] U[idx_k, :] + cV M^ec_e[k,a] V[idx_k, :])
+hipError_t launch_enr_q(hipStream_t s, const double *Hec, const double *Mec, const int64_t *eptr,
+                        const int32_t *eidx, const int32_t *cells, int ncells, int kmax,
+                        const double *U, int64_t ldu, double cU, const double *V, int64_t ldv,
+                        double cV, double *Q, int64_t ldq, int N);
 
 // Enrichment rows: out[al,:] = s_p * sum_{k in list(al)} P[k,:] + s_r * R0[al,:]
 //                              + sum_be Dn[al,be] * Zd[be,:]     (terms with null pointers skipped)
@@ -41,28 +68,31 @@ hipError_t launch_enr_reduce(hipStream_t s, int n_e, const int64_t *aptr, const 
                              int64_t ldr0, double s_r, const double *Dn, const double *Zd,
                              int64_t ldzd, double *out, int64_t ldo, int N);
 
-// Chebyshev step epilogue over all n = n_h + n_e rows:
-//   v = (i < n_h) ? dinv[i] * R[i,:] : Ze[i-n_h,:]
-//   Out[i,:] = c1 * v + c2 * Yk[i,:] + c3 * Yp[i,:]      (Yk / Yp may be null)
-// Out may alias Yp (each element is read before it is written by one thread).
-hipError_t launch_epilogue(hipStream_t s, int64_t n_h, int64_t n_e, const double *dinv,
-                           const double *R, int64_t ldr, const double *Ze, int64_t ldze,
-                           double c1, const double *Yk, int64_t ldyk, double c2,
-                           const double *Yp, int64_t ldyp, double c3, double *Out,
-                           int64_t ldo, int N);
+// Recurrence epilogue with the node-major coupling (see EpiArgs).
+hipError_t launch_epilogue(hipStream_t s, const EpiArgs &g);
 
-// Out[i,:] = d[i] * X[i,:] for i < rows (diagonal scaling, Out may alias X).
-hipError_t launch_diag_scale(hipStream_t s, int64_t rows, const double *d, const double *X,
-                             int64_t ldx, double *Out, int64_t ldo, int N);
+// Setup: node-major coupling values of the enriched cells of one colour.
+hipError_t launch_csr_fill(hipStream_t s, const double *Hec, const double *Mec,
+                           const int64_t *eptr, const int32_t *smap, const int32_t *cells,
+                           int ncells, double *hv, double *mv);
+// Setup: dense D^-1/2-scaled coupling rows of the enriched region.
+hipError_t launch_csr_dense(hipStream_t s, int64_t nreg, const int32_t *regrow,
+                            const int32_t *rowptr, const int32_t *ci, const double *hv,
+                            const double *mv, const double *dinv, double *BM, double *BH,
+                            int64_t ldb);
 
 // ---- dense kernels (cf_dense.hip)
-// Partial Gram matrices: Gp[c][i*ldg+j] = sum_{rows of chunk c} A[r,i] * B[r,j]
+// Gram modes: GRAM_SYM  full product, result symmetrised (G + G^T)/2
+//             GRAM_UPPER upper tiles only (A = B), mirrored
+//             GRAM_FULL  full product, no symmetrisation
+enum { GRAM_SYM = 0, GRAM_UPPER = 1, GRAM_FULL = 2 };
+// Partial Gram matrices: Gp[c][i*N+j] = sum_{rows of chunk c} A[r,i] * B[r,j]
 hipError_t launch_gram_partial(hipStream_t s, const double *A, int64_t lda, const double *B,
                                int64_t ldb, int64_t n, int N, int nchunks, int64_t chunk_rows,
-                               double *Gp, int upper_only);
-// G[i][j] = sum_c Gp[c][i][j], symmetrised: G = (G + G^T)/2 (or mirrored when upper_only).
+                               double *Gp, int mode);
+// G[i][j] = sum_c Gp[c][i][j], combined as the mode says.
 hipError_t launch_gram_reduce(hipStream_t s, const double *Gp, int nchunks, int N, double *G,
-                              int upper_only);
+                              int mode);
 // Out[r, j] = sum_k In[r, k] * W[k*wsk + j*wsj]     (out of place)
 hipError_t launch_rotate(hipStream_t s, const double *In, int64_t ldi, int64_t n, int N,
                          const double *W, int64_t wsk, int64_t wsj, double *Out, int64_t ldo);
@@ -91,13 +121,7 @@ hipError_t launch_lanczos_update(hipStream_t s, int64_t n, int j, double *w, con
 hipError_t launch_tridiag_bounds(hipStream_t s, const double *coef, const double *unused, int k,
                                  double *out2);
 
-// ---- setup and data-movement helpers (cf_dense.hip)
-hipError_t launch_scatter_coupling(hipStream_t s, const double *Bp, const int64_t *eptr,
-                                   const int32_t *eidx, const int32_t *dofp,
-                                   const int32_t *dof2reg, const int32_t *cells, int ncells,
-                                   double *Bt, int64_t ldb);
-hipError_t launch_scale_rows_sqrt(hipStream_t s, int64_t rows, const int32_t *regdof,
-                                  const double *dinv, double *Bt, int64_t ldb, int ncol);
+// ---- data-movement helpers (cf_dense.hip)
 hipError_t launch_sub(hipStream_t s, int64_t n, const double *A, const double *B, double *C);
 hipError_t launch_transpose(hipStream_t s, int N, const double *In, int64_t ldi, double *Out);
 hipError_t launch_copy(hipStream_t s, int64_t n, int N, const double *X, int64_t ldx, double *Y,

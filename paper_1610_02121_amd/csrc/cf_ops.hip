@@ -1,6 +1,6 @@
-// Elemental operator kernels: classical cell products on FP64 MFMA, the
-// enriched-classical coupling products, enrichment-row reductions and the
-// Chebyshev recurrence epilogue (Sec. IV.D, Sec. V).
+// Elemental operator kernels (Sec. IV.D, Sec. V): classical cell products on
+// FP64 MFMA, the enriched-cell coupling products (both directions), the
+// enrichment-row reductions and the Chebyshev recurrence epilogue.
 //
 // MFMA fragment layout of v_mfma_f64_16x16x4f64 (wave of 64 lanes):
 //   A (16 x 4):  lane l holds A[l % 16][l / 16]
@@ -19,20 +19,26 @@ __device__ __forceinline__ d4 mfma_f64(double a, double b, d4 c) {
 __device__ __forceinline__ d4 d4zero() { d4 z = {0.0, 0.0, 0.0, 0.0}; return z; }
 
 // ---------------------------------------------------------------------------
-// Classical cell products.  One workgroup (4 waves) per cell of the colour.
-// The cell matrix (padded to 128 x 128, symmetric) lives in registers as MFMA
-// A fragments for the whole call: wave w owns output rows [32w, 32w+32).  The
-// block is walked in column tiles of CT: the gathered X rows of the cell are
-// staged in LDS (Dirichlet and padding rows are zero), multiplied, and the
-// result is written (first touch) or added to the cell's DOF rows of Y.  No
-// two cells of one colour share a DOF, so the read-modify-write is race free.
+// Classical cell products for the cells of one colour:
+//   Y[dof(e,a)] (=|+=) sum_b H_e[a][b] X[dof(e,b)]
+// One workgroup of 8 waves per cell; wave w owns the 16 output rows
+// [16w, 16w+16) and keeps that slice of the (padded, symmetric) cell matrix in
+// registers as MFMA A fragments for the whole call.  Columns are walked in
+// tiles of CELL_NT: the next tile's gathered X rows and this tile's old Y
+// values are loaded into registers before the MFMA loop, so their latency
+// overlaps the matrix work; the current tile sits in LDS.  Dirichlet and
+// padding rows are zero.  Cells of one colour share no DOF, so the
+// read-modify-write of Y is race free; the first cell (in launch order) to
+// touch a DOF writes instead of adding.
 // ---------------------------------------------------------------------------
-template <int NTILE>
-__global__ __launch_bounds__(256, 2) void k_cell_gemm(
+__global__ __launch_bounds__(512, 2) void k_cell_gemm(
     const double *__restrict__ Hp, const int32_t *__restrict__ dofp,
     const uint8_t *__restrict__ firstp, const int32_t *__restrict__ cells,
     const double *__restrict__ X, int64_t ldx, double *__restrict__ Y, int64_t ldy, int N) {
-  constexpr int LDX = NTILE + 16;   // row stride: 16-double pad keeps B-fragment reads conflict free
+  constexpr int NT = CELL_NT;
+  constexpr int LDX = NT + 16;
+  constexpr int PF = NPAD * NT / 512;        // gathered doubles per thread per tile
+  constexpr int RPP = 512 / NT;              // gathered rows per pass
   __shared__ double xs[NPAD * LDX];
   __shared__ int32_t sdof[NPAD];
   __shared__ uint8_t sfirst[NPAD];
@@ -44,61 +50,51 @@ __global__ __launch_bounds__(256, 2) void k_cell_gemm(
     sdof[tid] = dofp[(int64_t)cell * NPAD + tid];
     sfirst[tid] = firstp[(int64_t)cell * NPAD + tid];
   }
+  // A[i][k] = H[i][k] = H[k][i]: lane reads H[4ks + kq][16w + li] (contiguous)
   const double *Hc = Hp + (int64_t)cell * NPAD * NPAD;
-  // A[i][k] = H[i][k] = H[k][i]: lane reads H[4ks + kq][row] (contiguous in row)
-  double a0[32], a1[32];
+  double a[32];
 #pragma unroll
-  for (int ks = 0; ks < 32; ++ks) {
-    a0[ks] = Hc[(4 * ks + kq) * NPAD + 32 * w + li];
-    a1[ks] = Hc[(4 * ks + kq) * NPAD + 32 * w + 16 + li];
-  }
+  for (int ks = 0; ks < 32; ++ks) a[ks] = Hc[(4 * ks + kq) * NPAD + 16 * w + li];
   __syncthreads();
 
-  for (int c0 = 0; c0 < N; c0 += NTILE) {
-    const int ncol = min(NTILE, N - c0);
-    for (int idx = tid; idx < NPAD * NTILE; idx += 256) {
-      const int r = idx / NTILE, j = idx % NTILE;
-      const int d = sdof[r];
-      double v = 0.0;
-      if (d >= 0 && j < ncol) v = X[(int64_t)d * ldx + c0 + j];
-      xs[r * LDX + j] = v;
-    }
+  const int gj = tid % NT, gr = tid / NT;
+  int gd[PF];
+#pragma unroll
+  for (int p = 0; p < PF; ++p) gd[p] = sdof[gr + p * RPP];
+  double pf[PF];
+#pragma unroll
+  for (int p = 0; p < PF; ++p) pf[p] = (gd[p] >= 0 && gj < N) ? X[(int64_t)gd[p] * ldx + gj] : 0.0;
+  int od[4];
+  bool ofirst[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    od[r] = sdof[16 * w + kq + 4 * r];
+    ofirst[r] = sfirst[16 * w + kq + 4 * r] != 0;
+  }
+
+  for (int c0 = 0; c0 < N; c0 += NT) {
+    const int ncol = min(NT, N - c0);
+#pragma unroll
+    for (int p = 0; p < PF; ++p) xs[(gr + p * RPP) * LDX + gj] = pf[p];
     __syncthreads();
-    const int ncb = (ncol + 15) >> 4;
-    d4 acc0[NTILE / 16], acc1[NTILE / 16];
+    const int c1 = c0 + NT;
+    if (c1 < N) {
 #pragma unroll
-    for (int cb = 0; cb < NTILE / 16; ++cb) { acc0[cb] = d4zero(); acc1[cb] = d4zero(); }
-#pragma unroll
-    for (int ks = 0; ks < 32; ++ks) {
-#pragma unroll
-      for (int cb = 0; cb < NTILE / 16; ++cb) {
-        if (cb < ncb) {
-          const double b = xs[(4 * ks + kq) * LDX + 16 * cb + li];
-          acc0[cb] = mfma_f64(a0[ks], b, acc0[cb]);
-          acc1[cb] = mfma_f64(a1[ks], b, acc1[cb]);
-        }
-      }
+      for (int p = 0; p < PF; ++p)
+        pf[p] = (gd[p] >= 0 && c1 + gj < N) ? X[(int64_t)gd[p] * ldx + c1 + gj] : 0.0;
     }
+    const bool cv = li < ncol;
+    double yo[4];
 #pragma unroll
-    for (int cb = 0; cb < NTILE / 16; ++cb) {
-      const int col = 16 * cb + li;
-      if (cb < ncb && col < ncol) {
+    for (int r = 0; r < 4; ++r)
+      yo[r] = (od[r] >= 0 && !ofirst[r] && cv) ? Y[(int64_t)od[r] * ldy + c0 + li] : 0.0;
+    d4 acc = d4zero();
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int row0 = 32 * w + kq + 4 * r;
-          const int d0 = sdof[row0];
-          if (d0 >= 0) {
-            double *p = Y + (int64_t)d0 * ldy + c0 + col;
-            *p = sfirst[row0] ? acc0[cb][r] : *p + acc0[cb][r];
-          }
-          const int row1 = row0 + 16;
-          const int d1 = sdof[row1];
-          if (d1 >= 0) {
-            double *p = Y + (int64_t)d1 * ldy + c0 + col;
-            *p = sfirst[row1] ? acc1[cb][r] : *p + acc1[cb][r];
-          }
-        }
-      }
+    for (int ks = 0; ks < 32; ++ks) acc = mfma_f64(a[ks], xs[(4 * ks + kq) * LDX + li], acc);
+    if (cv) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (od[r] >= 0) Y[(int64_t)od[r] * ldy + c0 + li] = acc[r] + yo[r];
     }
     __syncthreads();
   }
@@ -108,167 +104,166 @@ hipError_t launch_cell_gemm(hipStream_t s, const double *Hp, const int32_t *dofp
                             const uint8_t *firstp, const int32_t *cells, int ncells,
                             const double *X, int64_t ldx, double *Y, int64_t ldy, int N) {
   if (ncells <= 0 || N <= 0) return hipSuccess;
-  // narrow blocks (a single vector in the Lanczos run) use a 16-column instance
-  if (N <= 16)
-    hipLaunchKernelGGL(k_cell_gemm<16>, dim3(ncells), dim3(256), 0, s, Hp, dofp, firstp, cells, X,
-                       ldx, Y, ldy, N);
-  else
-    hipLaunchKernelGGL(k_cell_gemm<CT>, dim3(ncells), dim3(256), 0, s, Hp, dofp, firstp, cells, X,
-                       ldx, Y, ldy, N);
+  hipLaunchKernelGGL(k_cell_gemm, dim3(ncells), dim3(512), 0, s, Hp, dofp, firstp, cells, X, ldx,
+                     Y, ldy, N);
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// Transposed coupling for enriched cells of one colour (grid: cells x column
-// tiles): Y[dof(e,a)] += sign * sum_k B[k0+k][a] Z[idx[k0+k]].  The gathered
-// enrichment rows sit in LDS (dynamic size: kmax rounded to 4 rows).
+// Enriched-cell coupling partials (grid: enriched cells x column tiles of 16):
+//   P[k0+k] = cH * sum_a H^ec_e[k][a] X[dof(e,a)]
+//           + cM * sum_a M^ec_e[k][a] s(dof) R[dof(e,a)]
+// The cell blocks are stored transposed, [NPAD][nap] with nap = the cell's
+// enrichment count padded to 16, so A-fragment loads are contiguous.  Either
+// term is skipped when its input block is null.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_enr_T(
-    const double *__restrict__ Bp, const int64_t *__restrict__ eptr,
-    const int32_t *__restrict__ eidx, const int32_t *__restrict__ dofp,
-    const int32_t *__restrict__ cells, const double *__restrict__ Z, int64_t ldz,
-    double *__restrict__ Y, int64_t ldy, int N, double sign) {
-  extern __shared__ double zs[];
-  constexpr int LDZ = CT + 16;
-  __shared__ int32_t sdof[NPAD];
+__global__ __launch_bounds__(256) void k_enr_part(
+    const double *__restrict__ HT, const double *__restrict__ MT,
+    const int64_t *__restrict__ toff, const int32_t *__restrict__ tld,
+    const int64_t *__restrict__ eptr, const int32_t *__restrict__ dofp,
+    const int32_t *__restrict__ cells, const double *__restrict__ X, int64_t ldx, double cH,
+    const double *__restrict__ R, int64_t ldr, const double *__restrict__ rs, double cM,
+    double *__restrict__ P, int64_t ldp, int N) {
+  constexpr int PT = 16, LDX = 32;
+  __shared__ double xs[NPAD * LDX];
+  __shared__ double rsm[NPAD * LDX];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, kq = lane >> 4;
   const int cell = cells[blockIdx.x];
-  const int c0 = blockIdx.y * CT;
-  const int ncol = min(CT, N - c0);
-  const int64_t k0 = eptr[cell];
-  const int na = (int)(eptr[cell + 1] - k0);
-  const int K4 = (na + 3) & ~3;
-  if (tid < NPAD) sdof[tid] = dofp[(int64_t)cell * NPAD + tid];
-  for (int idx = tid; idx < K4 * CT; idx += 256) {
-    const int k = idx / CT, j = idx % CT;
-    double v = 0.0;
-    if (k < na && j < ncol) v = Z[(int64_t)eidx[k0 + k] * ldz + c0 + j];
-    zs[k * LDZ + j] = v;
+  const int c0 = blockIdx.y * PT;
+  const int ncol = min(PT, N - c0);
+  for (int idx = tid; idx < NPAD * PT; idx += 256) {
+    const int r = idx / PT, j = idx % PT;
+    const int d = dofp[(int64_t)cell * NPAD + r];
+    const bool v = d >= 0 && j < ncol;
+    xs[r * LDX + j] = (X && v) ? X[(int64_t)d * ldx + c0 + j] : 0.0;
+    rsm[r * LDX + j] = (R && v) ? R[(int64_t)d * ldr + c0 + j] * (rs ? rs[d] : 1.0) : 0.0;
   }
   __syncthreads();
-  d4 acc0[CT / 16], acc1[CT / 16];
-#pragma unroll
-  for (int cb = 0; cb < CT / 16; ++cb) { acc0[cb] = d4zero(); acc1[cb] = d4zero(); }
-  for (int ks = 0; ks < K4 / 4; ++ks) {
-    const int k = 4 * ks + kq;
-    double a0 = 0.0, a1 = 0.0;
-    if (k < na) {
-      const double *brow = Bp + (k0 + k) * NPAD + 32 * w;
-      a0 = brow[li];
-      a1 = brow[16 + li];
+  const int64_t k0 = eptr[cell];
+  const int na = (int)(eptr[cell + 1] - k0);
+  const int nap = tld[cell];
+  const int nmb = nap >> 4;
+  const double *ht = X ? HT + toff[cell] : nullptr;
+  const double *mt = R ? MT + toff[cell] : nullptr;
+  for (int mb = w; mb < nmb; mb += 4) {
+    d4 accH = d4zero(), accM = d4zero();
+    if (ht) {
+#pragma unroll 8
+      for (int ks = 0; ks < 32; ++ks)
+        accH = mfma_f64(ht[(int64_t)(4 * ks + kq) * nap + 16 * mb + li],
+                        xs[(4 * ks + kq) * LDX + li], accH);
     }
-#pragma unroll
-    for (int cb = 0; cb < CT / 16; ++cb) {
-      const double b = zs[k * LDZ + 16 * cb + li];
-      acc0[cb] = mfma_f64(a0, b, acc0[cb]);
-      acc1[cb] = mfma_f64(a1, b, acc1[cb]);
+    if (mt) {
+#pragma unroll 8
+      for (int ks = 0; ks < 32; ++ks)
+        accM = mfma_f64(mt[(int64_t)(4 * ks + kq) * nap + 16 * mb + li],
+                        rsm[(4 * ks + kq) * LDX + li], accM);
     }
-  }
-#pragma unroll
-  for (int cb = 0; cb < CT / 16; ++cb) {
-    const int col = 16 * cb + li;
-    if (col < ncol) {
+    if (li < ncol) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row0 = 32 * w + kq + 4 * r;
-        const int d0 = sdof[row0];
-        if (d0 >= 0) Y[(int64_t)d0 * ldy + c0 + col] += sign * acc0[cb][r];
-        const int d1 = sdof[row0 + 16];
-        if (d1 >= 0) Y[(int64_t)d1 * ldy + c0 + col] += sign * acc1[cb][r];
+        const int orow = 16 * mb + kq + 4 * r;
+        if (orow < na) P[(k0 + orow) * ldp + c0 + li] = cH * accH[r] + cM * accM[r];
       }
     }
   }
 }
 
-hipError_t launch_enr_T(hipStream_t s, const double *Bp, const int64_t *eptr,
-                        const int32_t *eidx, const int32_t *dofp, const int32_t *cells,
-                        int ncells, int kmax, const double *Z, int64_t ldz, double *Y,
-                        int64_t ldy, int N, double sign) {
+hipError_t launch_enr_part(hipStream_t s, const double *HT, const double *MT, const int64_t *toff,
+                           const int32_t *tld, const int64_t *eptr, const int32_t *dofp,
+                           const int32_t *cells, int ncells, const double *X, int64_t ldx,
+                           double cH, const double *R, int64_t ldr, const double *rs, double cM,
+                           double *P, int64_t ldp, int N) {
   if (ncells <= 0 || N <= 0) return hipSuccess;
-  const size_t shm = (size_t)((kmax + 3) & ~3) * (CT + 16) * sizeof(double);
+  dim3 grid(ncells, (N + 15) / 16);
+  hipLaunchKernelGGL(k_enr_part, grid, dim3(256), 0, s, HT, MT, toff, tld, eptr, dofp, cells, X,
+                     ldx, cH, R, ldr, rs, cM, P, ldp, N);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Transposed coupling products of the enriched cells, into a cell-local buffer
+// (grid: enriched cells x column tiles of 16; no read-modify-write):
+//   Q[128 e' + a] = sum_k (cU H^ec_e[k][a] U[idx_k] + cV M^ec_e[k][a] V[idx_k])
+// e' is the position of the cell in the enriched-cell list, a its local node.
+// The gathered rows cU U[idx_k] and cV V[idx_k] sit in LDS (dynamic size:
+// 2 K4 rows of 16 columns, K4 = count rounded up to 4); either term is
+// skipped when its input is null.  The epilogue sums, for each classical DOF,
+// the (at most 8) Q rows of the enriched cells that contain it.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_enr_q(
+    const double *__restrict__ Hec, const double *__restrict__ Mec,
+    const int64_t *__restrict__ eptr, const int32_t *__restrict__ eidx,
+    const int32_t *__restrict__ cells, const double *__restrict__ U, int64_t ldu, double cU,
+    const double *__restrict__ V, int64_t ldv, double cV, double *__restrict__ Q, int64_t ldq,
+    int N) {
+  extern __shared__ double zs[];
+  constexpr int PT = 16, LDZ = 16;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int li = lane & 15, kq = lane >> 4;
+  const int cell = cells[blockIdx.x];
+  const int c0 = blockIdx.y * PT;
+  const int ncol = min(PT, N - c0);
+  const int64_t k0 = eptr[cell];
+  const int na = (int)(eptr[cell + 1] - k0);
+  const int K4 = (na + 3) & ~3;
+  for (int idx = tid; idx < K4 * PT; idx += 256) {
+    const int k = idx / PT, j = idx % PT;
+    const bool v = k < na && j < ncol;
+    const int64_t al = v ? eidx[k0 + k] : 0;
+    zs[k * LDZ + j] = (U && v) ? cU * U[al * ldu + c0 + j] : 0.0;
+    zs[(K4 + k) * LDZ + j] = (V && v) ? cV * V[al * ldv + c0 + j] : 0.0;
+  }
+  __syncthreads();
+  d4 acc0 = d4zero(), acc1 = d4zero();
+  const int nks = K4 / 4;
+  if (U) {
+    for (int ks = 0; ks < nks; ++ks) {
+      const int k = 4 * ks + kq;
+      const double *row = Hec + (k0 + min(k, na - 1)) * NPAD + 32 * w;
+      const double a0 = k < na ? row[li] : 0.0, a1 = k < na ? row[16 + li] : 0.0;
+      const double b = zs[k * LDZ + li];
+      acc0 = mfma_f64(a0, b, acc0);
+      acc1 = mfma_f64(a1, b, acc1);
+    }
+  }
+  if (V) {
+    for (int ks = 0; ks < nks; ++ks) {
+      const int k = 4 * ks + kq;
+      const double *row = Mec + (k0 + min(k, na - 1)) * NPAD + 32 * w;
+      const double a0 = k < na ? row[li] : 0.0, a1 = k < na ? row[16 + li] : 0.0;
+      const double b = zs[(K4 + k) * LDZ + li];
+      acc0 = mfma_f64(a0, b, acc0);
+      acc1 = mfma_f64(a1, b, acc1);
+    }
+  }
+  if (li < ncol) {
+    double *q = Q + ((int64_t)blockIdx.x * NPAD) * ldq + c0 + li;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      q[(int64_t)(32 * w + kq + 4 * r) * ldq] = acc0[r];
+      q[(int64_t)(32 * w + 16 + kq + 4 * r) * ldq] = acc1[r];
+    }
+  }
+}
+
+hipError_t launch_enr_q(hipStream_t s, const double *Hec, const double *Mec, const int64_t *eptr,
+                        const int32_t *eidx, const int32_t *cells, int ncells, int kmax,
+                        const double *U, int64_t ldu, double cU, const double *V, int64_t ldv,
+                        double cV, double *Q, int64_t ldq, int N) {
+  if (ncells <= 0 || N <= 0) return hipSuccess;
+  const size_t shm = (size_t)2 * ((kmax + 3) & ~3) * 16 * sizeof(double);
   static size_t shm_set = 0;
   if (shm > 65536 && shm > shm_set) {
-    hipError_t e = hipFuncSetAttribute((const void *)k_enr_T,
+    hipError_t e = hipFuncSetAttribute((const void *)k_enr_q,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     if (e != hipSuccess) return e;
     shm_set = shm;
   }
-  dim3 grid(ncells, (N + CT - 1) / CT);
-  hipLaunchKernelGGL(k_enr_T, grid, dim3(256), shm, s, Bp, eptr, eidx, dofp, cells, Z, ldz, Y,
-                     ldy, N, sign);
-  return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// Coupling partials for enriched cells (grid: cells x column tiles):
-//   P[k0+k] = sum_a B[k0+k][a] * scale(dof) * Zc[dof(e,a)]
-// Each wave takes 16-row blocks of the cell's enrichment rows.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_enr_N(
-    const double *__restrict__ Bp, const int64_t *__restrict__ eptr,
-    const int32_t *__restrict__ dofp, const int32_t *__restrict__ cells,
-    const double *__restrict__ Zc, int64_t ldz, const double *__restrict__ dscale,
-    double *__restrict__ P, int64_t ldp, int N) {
-  constexpr int LDX = CT + 16;
-  __shared__ double xs[NPAD * LDX];
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int li = lane & 15, kq = lane >> 4;
-  const int cell = cells[blockIdx.x];
-  const int c0 = blockIdx.y * CT;
-  const int ncol = min(CT, N - c0);
-  for (int idx = tid; idx < NPAD * CT; idx += 256) {
-    const int r = idx / CT, j = idx % CT;
-    const int d = dofp[(int64_t)cell * NPAD + r];
-    double v = 0.0;
-    if (d >= 0 && j < ncol) {
-      v = Zc[(int64_t)d * ldz + c0 + j];
-      if (dscale) v *= dscale[d];
-    }
-    xs[r * LDX + j] = v;
-  }
-  __syncthreads();
-  const int64_t k0 = eptr[cell];
-  const int na = (int)(eptr[cell + 1] - k0);
-  const int nmb = (na + 15) >> 4;
-  for (int mb = w; mb < nmb; mb += 4) {
-    d4 acc[CT / 16];
-#pragma unroll
-    for (int cb = 0; cb < CT / 16; ++cb) acc[cb] = d4zero();
-    const int arow = 16 * mb + li;
-    const bool valid = arow < na;
-    const double *brow = Bp + (k0 + (valid ? arow : 0)) * NPAD;
-#pragma unroll 8
-    for (int ks = 0; ks < 32; ++ks) {
-      const double a = valid ? brow[4 * ks + kq] : 0.0;
-#pragma unroll
-      for (int cb = 0; cb < CT / 16; ++cb) {
-        const double b = xs[(4 * ks + kq) * LDX + 16 * cb + li];
-        acc[cb] = mfma_f64(a, b, acc[cb]);
-      }
-    }
-#pragma unroll
-    for (int cb = 0; cb < CT / 16; ++cb) {
-      const int col = 16 * cb + li;
-      if (col < ncol) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int orow = 16 * mb + kq + 4 * r;
-          if (orow < na) P[(k0 + orow) * ldp + c0 + col] = acc[cb][r];
-        }
-      }
-    }
-  }
-}
-
-hipError_t launch_enr_N(hipStream_t s, const double *Bp, const int64_t *eptr,
-                        const int32_t *dofp, const int32_t *cells, int ncells,
-                        const double *Zc, int64_t ldz, const double *dscale, double *P,
-                        int64_t ldp, int N) {
-  if (ncells <= 0 || N <= 0) return hipSuccess;
-  dim3 grid(ncells, (N + CT - 1) / CT);
-  hipLaunchKernelGGL(k_enr_N, grid, dim3(256), 0, s, Bp, eptr, dofp, cells, Zc, ldz, dscale, P,
-                     ldp, N);
+  dim3 grid(ncells, (N + 15) / 16);
+  hipLaunchKernelGGL(k_enr_q, grid, dim3(256), shm, s, Hec, Mec, eptr, eidx, cells, U, ldu, cU, V,
+                     ldv, cV, Q, ldq, N);
   return hipGetLastError();
 }
 
@@ -313,57 +308,114 @@ hipError_t launch_enr_reduce(hipStream_t s, int n_e, const int64_t *aptr, const 
 }
 
 // ---------------------------------------------------------------------------
-// Recurrence epilogue: block (64 columns x 4 rows), grid-stride over rows.
+// Epilogue over all n = n_h + n_e rows (block: 64 columns x 4 rows):
+//   classical row i:  v = dR_i R[i] + dC_i sum_p Q[qidx[p]]   (p over qptr[i]..qptr[i+1];
+//                     the rows of the enriched-cell buffer holding DOF i; null
+//                     scales mean 1)
+//   enrichment row:   v = Ee[i - n_h]
+//   Out[i] = c1 v + c2 Yk[i] + c3 Yp[i]       (null Yk / Yp skipped)
+// Out may alias R or Yp: each element is read before the same thread writes it.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_epilogue(
-    int64_t n_h, int64_t n_e, const double *__restrict__ dinv, const double *__restrict__ R,
-    int64_t ldr, const double *__restrict__ Ze, int64_t ldze, double c1,
-    const double *__restrict__ Yk, int64_t ldyk, double c2, const double *Yp, int64_t ldyp,
-    double c3, double *Out, int64_t ldo, int N) {
-  const int64_t n = n_h + n_e;
+__global__ __launch_bounds__(256) void k_epilogue(const EpiArgs g) {
+  const int64_t n = g.n_h + g.n_e;
   for (int64_t i = (int64_t)blockIdx.x * 4 + threadIdx.y; i < n; i += (int64_t)gridDim.x * 4) {
-    const bool cls = i < n_h;
-    const double di = cls ? dinv[i] : 0.0;
-    for (int j = threadIdx.x; j < N; j += 64) {
-      double v = cls ? di * R[i * ldr + j] : Ze[(i - n_h) * ldze + j];
-      v *= c1;
-      if (Yk) v += c2 * Yk[i * ldyk + j];
-      if (Yp) v += c3 * Yp[i * ldyp + j];
-      Out[i * ldo + j] = v;
+    const bool cls = i < g.n_h;
+    double dr = 1.0, dc = 1.0;
+    int p0 = 0, p1 = 0;
+    if (cls) {
+      if (g.dR) dr = g.dR[i];
+      if (g.dC) dc = g.dC[i];
+      if (g.qptr) { p0 = g.qptr[i]; p1 = g.qptr[i + 1]; }
+    }
+    for (int j = threadIdx.x; j < g.N; j += 64) {
+      double v;
+      if (cls) {
+        v = dr * g.R[i * g.ldr + j];
+        if (p1 > p0) {
+          double sq = 0.0;
+          for (int p = p0; p < p1; ++p) sq += g.Q[(int64_t)g.qidx[p] * g.ldq + j];
+          v += dc * sq;
+        }
+      } else {
+        v = g.Ee[(i - g.n_h) * g.lde + j];
+      }
+      v *= g.c1;
+      if (g.Yk) v += g.c2 * g.Yk[i * g.ldyk + j];
+      if (g.Yp) v += g.c3 * g.Yp[i * g.ldyp + j];
+      g.Out[i * g.ldo + j] = v;
     }
   }
 }
 
-hipError_t launch_epilogue(hipStream_t s, int64_t n_h, int64_t n_e, const double *dinv,
-                           const double *R, int64_t ldr, const double *Ze, int64_t ldze,
-                           double c1, const double *Yk, int64_t ldyk, double c2,
-                           const double *Yp, int64_t ldyp, double c3, double *Out,
-                           int64_t ldo, int N) {
-  const int64_t n = n_h + n_e;
-  if (n <= 0 || N <= 0) return hipSuccess;
+hipError_t launch_epilogue(hipStream_t s, const EpiArgs &g) {
+  const int64_t n = g.n_h + g.n_e;
+  if (n <= 0 || g.N <= 0) return hipSuccess;
   int64_t blocks = (n + 3) / 4;
   if (blocks > 65536) blocks = 65536;
-  hipLaunchKernelGGL(k_epilogue, dim3((unsigned)blocks), dim3(64, 4), 0, s, n_h, n_e, dinv, R, ldr,
-                     Ze, ldze, c1, Yk, ldyk, c2, Yp, ldyp, c3, Out, ldo, N);
+  hipLaunchKernelGGL(k_epilogue, dim3((unsigned)blocks), dim3(64, 4), 0, s, g);
   return hipGetLastError();
 }
 
-__global__ __launch_bounds__(256) void k_diag_scale(int64_t rows, const double *__restrict__ d,
-                                                    const double *X, int64_t ldx, double *Out,
-                                                    int64_t ldo, int N) {
-  for (int64_t i = (int64_t)blockIdx.x * 4 + threadIdx.y; i < rows; i += (int64_t)gridDim.x * 4) {
-    const double di = d[i];
-    for (int j = threadIdx.x; j < N; j += 64) Out[i * ldo + j] = di * X[i * ldx + j];
+// ---------------------------------------------------------------------------
+// Setup: node-major coupling values.  For the enriched cells of one colour,
+// thread a of cell e adds every H^ec_e[k][a], M^ec_e[k][a] into the CSR slot
+// of (dof(e,a), alpha_k).  Cells of one colour share no DOF and one cell's
+// alphas are distinct, so no two threads of a launch hit the same slot.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(128) void k_csr_fill(const double *__restrict__ Hec,
+                                                  const double *__restrict__ Mec,
+                                                  const int64_t *__restrict__ eptr,
+                                                  const int32_t *__restrict__ smap,
+                                                  const int32_t *__restrict__ cells, double *hv,
+                                                  double *mv) {
+  const int cell = cells[blockIdx.x];
+  const int a = threadIdx.x;
+  for (int64_t k = eptr[cell]; k < eptr[cell + 1]; ++k) {
+    const int32_t slot = smap[k * NPAD + a];
+    if (slot < 0) continue;
+    hv[slot] += Hec[k * NPAD + a];
+    mv[slot] += Mec[k * NPAD + a];
   }
 }
 
-hipError_t launch_diag_scale(hipStream_t s, int64_t rows, const double *d, const double *X,
-                             int64_t ldx, double *Out, int64_t ldo, int N) {
-  if (rows <= 0 || N <= 0) return hipSuccess;
-  int64_t blocks = (rows + 3) / 4;
+hipError_t launch_csr_fill(hipStream_t s, const double *Hec, const double *Mec,
+                           const int64_t *eptr, const int32_t *smap, const int32_t *cells,
+                           int ncells, double *hv, double *mv) {
+  if (ncells <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_csr_fill, dim3(ncells), dim3(NPAD), 0, s, Hec, Mec, eptr, smap, cells, hv,
+                     mv);
+  return hipGetLastError();
+}
+
+// Dense coupling rows of the enriched region, scaled by D^-1/2:
+//   BM[r][ci[p]] = mv[p] / sqrt(D_i),  BH[r][ci[p]] = hv[p] / sqrt(D_i),  i = regrow[r]
+__global__ __launch_bounds__(256) void k_csr_dense(int64_t nreg, const int32_t *__restrict__ regrow,
+                                                   const int32_t *__restrict__ rowptr,
+                                                   const int32_t *__restrict__ ci,
+                                                   const double *__restrict__ hv,
+                                                   const double *__restrict__ mv,
+                                                   const double *__restrict__ dinv, double *BM,
+                                                   double *BH, int64_t ldb) {
+  for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < nreg;
+       r += (int64_t)gridDim.x * 256) {
+    const int i = regrow[r];
+    const double sc = sqrt(dinv[i]);
+    for (int p = rowptr[i]; p < rowptr[i + 1]; ++p) {
+      BM[r * ldb + ci[p]] = mv[p] * sc;
+      BH[r * ldb + ci[p]] = hv[p] * sc;
+    }
+  }
+}
+
+hipError_t launch_csr_dense(hipStream_t s, int64_t nreg, const int32_t *regrow,
+                            const int32_t *rowptr, const int32_t *ci, const double *hv,
+                            const double *mv, const double *dinv, double *BM, double *BH,
+                            int64_t ldb) {
+  if (nreg <= 0) return hipSuccess;
+  int64_t blocks = (nreg + 255) / 256;
   if (blocks > 65536) blocks = 65536;
-  hipLaunchKernelGGL(k_diag_scale, dim3((unsigned)blocks), dim3(64, 4), 0, s, rows, d, X, ldx, Out,
-                     ldo, N);
+  hipLaunchKernelGGL(k_csr_dense, dim3((unsigned)blocks), dim3(256), 0, s, nreg, regrow, rowptr, ci,
+                     hv, mv, dinv, BM, BH, ldb);
   return hipGetLastError();
 }
 

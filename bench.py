@@ -149,7 +149,7 @@ def main():
     # kernel timing over the timed region (HIP events on the library's stream)
     prof = {}
     if not args.no_profile:
-        for k in ("cell_gemm", "enr_gemm", "epilogue", "gram", "rotate"):
+        for k in ("cell_gemm", "enr_part", "enr_reduce", "enr_q", "enr_gemm", "epilogue", "gram", "rotate"):
             prof[k] = ctx.profile_query(k)
         ctx.profile(False)
 

@@ -42,7 +42,9 @@ struct cf_ctx {
   // classical cells
   double *Hp = nullptr;
   int32_t *dofp = nullptr;
-  uint8_t *firstp = nullptr;
+  uint8_t *flagp = nullptr;                 // CELL_FIRST / CELL_FINISH per (cell, local node)
+  int32_t *regrows = nullptr;               // classical DOFs inside enriched cells
+  int64_t nregrows = 0;
   double *dvec = nullptr, *dinv = nullptr;
   int32_t *cells = nullptr;
   std::vector<int> col_off;
@@ -152,13 +154,16 @@ static cf_status check_block(cf_ctx *c, const void *X, int64_t ldx, int64_t N, c
 // operator cores (all enqueue on c->stream)
 // ---------------------------------------------------------------------------
 // Classical elemental products R' = H^cc X over all colours (Y rows 0..n_h).
-static cf_status core_cells(cf_ctx *c, const double *X, int64_t ldx, double *Y, int64_t ldy, int N) {
+// With a finishing step, DOFs outside the enriched region take the recurrence
+// in the cell kernel and their rows of Y are not written.
+static cf_status core_cells(cf_ctx *c, const double *X, int64_t ldx, double *Y, int64_t ldy, int N,
+                            const CellFinish &f = CellFinish()) {
   for (size_t k = 0; k + 1 < c->col_off.size(); ++k) {
     // elemental dense product: 2 npc^2 N flops per cell
     Scope sc(c, "cell_gemm",
              2.0 * c->npc * c->npc * (double)N * (c->col_off[k + 1] - c->col_off[k]));
-    HIPCHK(c, launch_cell_gemm(c->stream, c->Hp, c->dofp, c->firstp, c->cells + c->col_off[k],
-                               c->col_off[k + 1] - c->col_off[k], X, ldx, Y, ldy, N));
+    HIPCHK(c, launch_cell_gemm(c->stream, c->Hp, c->dofp, c->flagp, c->cells + c->col_off[k],
+                               c->col_off[k + 1] - c->col_off[k], X, ldx, Y, ldy, N, f));
   }
   return CF_OK;
 }
@@ -180,7 +185,7 @@ static EpiArgs epi_base(cf_ctx *c, int N) {
 // Q = cell-local transposed coupling products (see k_enr_q).
 static cf_status core_enr_q(cf_ctx *c, const double *U, int64_t ldu, double cU, const double *V,
                             int64_t ldv, double cV, int N) {
-  Scope sc(c, "enr_gemm");
+  Scope sc(c, "enr_q");
   HIPCHK(c, launch_enr_q(c->stream, c->Hec, c->Mec, c->eptr, c->eidx, c->ecells, c->necells, c->kmax,
                          U, ldu, cU, V, ldv, cV, c->Q, c->max_cols, N));
   return CF_OK;
@@ -236,7 +241,7 @@ static cf_status core_apply_M(cf_ctx *c, const double *X, int64_t ldx, double *Y
 
 // z = S^-1 w into Zb, where w (in Wb) has been formed by the caller.
 static cf_status core_schur_solve(cf_ctx *c, int N) {
-  Scope sc(c, "enr_gemm");
+  Scope sc(c, "enr_reduce");
   HIPCHK(c, launch_enr_reduce(c->stream, (int)c->n_e, c->aptr, c->alist, nullptr, 0, 0.0, nullptr, 0,
                               0.0, c->Sinv, c->Wb, c->max_cols, c->Zb, c->max_cols, N));
   return CF_OK;
@@ -251,14 +256,27 @@ static cf_status core_htilde_step(cf_ctx *c, const double *Xin, int64_t ldxin, i
                                   const double *Yk, int64_t ldyk, double c2, const double *Yp,
                                   int64_t ldyp, double c3, double *Out, int64_t ldo) {
   const int64_t ldr = c->max_cols;
-  STCHK(core_cells(c, Xin, ldxin, c->R, ldr, N));
+  // rows outside the enriched region are finished by the cell kernel (it holds
+  // X = Y_k in LDS, so this needs Yk to be Xin or absent)
+  const bool finish = Yk == nullptr || (Yk == Xin && ldyk == ldxin);
+  CellFinish f;
+  if (finish) {
+    f.dinv = c->dinv;
+    f.c1 = c1; f.c2 = Yk ? c2 : 0.0; f.c3 = Yp ? c3 : 0.0;
+    f.Yp = Yp; f.ldyp = ldyp;
+    f.Out = Out; f.ldo = ldo;
+  }
+  STCHK(core_cells(c, Xin, ldxin, c->R, ldr, N, f));
   const double *Xe = Xin + c->n_h * ldxin;
   if (c->n_e > 0) {
     {
-      Scope sc(c, "enr_gemm");
+      Scope sc(c, "enr_part");
       HIPCHK(c, launch_enr_part(c->stream, c->HT, c->MT, c->toff, c->tld, c->eptr, c->dofp,
                                 c->ecells, c->necells, Xin, ldxin, 1.0, c->R, ldr, c->dinv, -1.0,
                                 c->P, c->max_cols, N));
+    }
+    {
+      Scope sc(c, "enr_reduce");
       HIPCHK(c, launch_enr_reduce(c->stream, (int)c->n_e, c->aptr, c->alist, c->P, c->max_cols, 1.0,
                                   nullptr, 0, 0.0, c->Hmod, Xe, ldxin, c->Wb, c->max_cols, N));
     }
@@ -270,6 +288,7 @@ static cf_status core_htilde_step(cf_ctx *c, const double *Xin, int64_t ldxin, i
   g.Ee = c->Zb; g.lde = c->max_cols;
   g.c1 = c1; g.Yk = Yk; g.ldyk = ldyk; g.c2 = c2; g.Yp = Yp; g.ldyp = ldyp; g.c3 = c3;
   g.Out = Out; g.ldo = ldo;
+  if (finish) { g.rows = c->regrows; g.nrows = c->nregrows; }
   Scope sc(c, "epilogue");
   HIPCHK(c, launch_epilogue(c->stream, g));
   return CF_OK;
@@ -433,11 +452,17 @@ static cf_status do_init(const cf_problem *pr, const cf_options *opt, cf_ctx *c)
         if (d >= 0 && !touched[d]) { touched[d] = 1; first[(int64_t)e * NPAD + a] = 1; }
       }
   }
+  // last touch of each DOF in launch order (for the finishing step)
+  std::vector<int64_t> last_slot(n_h, -1);
+  for (int32_t e : order)
+    for (int a = 0; a < npc; ++a) {
+      const int32_t d = dof[(int64_t)e * NPAD + a];
+      if (d >= 0) last_slot[d] = (int64_t)e * NPAD + a;
+    }
   STCHK(dalloc(c, &c->dofp, dof.size()));
-  STCHK(dalloc(c, &c->firstp, first.size()));
+  STCHK(dalloc(c, &c->flagp, first.size()));
   STCHK(dalloc(c, &c->cells, order.size()));
   HIPCHK(c, hipMemcpy(c->dofp, dof.data(), dof.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-  HIPCHK(c, hipMemcpy(c->firstp, first.data(), first.size(), hipMemcpyHostToDevice));
   HIPCHK(c, hipMemcpy(c->cells, order.data(), order.size() * sizeof(int32_t), hipMemcpyHostToDevice));
 
   // ---- cell matrices: padded to NPAD x NPAD, symmetrised, checked
@@ -799,6 +824,29 @@ static cf_status do_init(const cf_problem *pr, const cf_options *opt, cf_ctx *c)
     (void)hipStreamSynchronize(c->stream);
     tmp_free();
     if (st != CF_OK) return st;
+  }
+  // cell flags: first touch; last touch of a DOF no enriched cell contains
+  {
+    std::vector<uint8_t> inreg(n_h, 0);
+    if (n_e > 0)
+      for (int64_t e = 0; e < E; ++e)
+        if (pr->enr_ptr[e + 1] > pr->enr_ptr[e])
+          for (int a = 0; a < npc; ++a) {
+            const int32_t d = dof[e * NPAD + a];
+            if (d >= 0) inreg[d] = 1;
+          }
+    std::vector<uint8_t> flag(first.size(), 0);
+    for (size_t q = 0; q < first.size(); ++q) flag[q] = first[q] ? CELL_FIRST : 0;
+    std::vector<int32_t> rows;
+    for (int64_t d = 0; d < n_h; ++d) {
+      if (inreg[d]) rows.push_back((int32_t)d);
+      else flag[last_slot[d]] |= CELL_FINISH;
+    }
+    HIPCHK(c, hipMemcpy(c->flagp, flag.data(), flag.size(), hipMemcpyHostToDevice));
+    c->nregrows = (int64_t)rows.size();
+    STCHK(dalloc(c, &c->regrows, std::max<size_t>(rows.size(), 1)));
+    if (!rows.empty())
+      HIPCHK(c, hipMemcpy(c->regrows, rows.data(), rows.size() * sizeof(int32_t), hipMemcpyHostToDevice));
   }
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return CF_OK;

@@ -210,11 +210,19 @@ hipError_t launch_rotate(hipStream_t s, const double *In, int64_t ldi, int64_t n
 }
 
 // ---------------------------------------------------------------------------
-// Lower Cholesky of a small SPD matrix, one workgroup, right-looking.
+// Lower Cholesky of a small SPD matrix (row-major, ld N), one workgroup,
+// right-looking in panels of CB = 32 columns:
+//   1. the diagonal block is factored in LDS,
+//   2. the rows below it are solved against it (one thread per row),
+//   3. the trailing lower triangle is updated with the panel (dot products of
+//      length CB, one thread per element).
+// Optional symmetric scaling S A S with S = diag(A)^-1/2 and a diagonal shift
+// are applied first.  flag[0] = index+1 of the first non-positive pivot.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(1024) void k_cholesky(double *A, int N, int scale, double shift,
                                                    double *sv, int *flag) {
-  __shared__ double piv;
+  constexpr int CB = 32;
+  __shared__ double dblk[CB * (CB + 1)];
   __shared__ int bad;
   const int tid = threadIdx.x;
   if (tid == 0) bad = 0;
@@ -238,22 +246,56 @@ __global__ __launch_bounds__(1024) void k_cholesky(double *A, int N, int scale, 
     A[e] = v;
   }
   __syncthreads();
-  for (int k = 0; k < N; ++k) {
-    if (tid == 0) {
-      const double d = A[(int64_t)k * N + k];
-      if (!(d > 0.0) || !isfinite(d)) { bad = k + 1; piv = 1.0; }
-      else { piv = sqrt(d); A[(int64_t)k * N + k] = piv; }
+  for (int k0 = 0; k0 < N; k0 += CB) {
+    const int nb = min(CB, N - k0);
+    // 1. diagonal block
+    for (int e = tid; e < nb * nb; e += 1024) {
+      const int i = e / nb, j = e % nb;
+      dblk[i * (CB + 1) + j] = A[(int64_t)(k0 + i) * N + k0 + j];
     }
     __syncthreads();
-    if (bad) { if (tid == 0) flag[0] = bad; return; }
-    const double p = piv;
-    for (int i = k + 1 + tid; i < N; i += 1024) A[(int64_t)i * N + k] /= p;
+    for (int k = 0; k < nb; ++k) {
+      if (tid == 0) {
+        const double d = dblk[k * (CB + 1) + k];
+        if (!(d > 0.0) || !isfinite(d)) bad = k0 + k + 1;
+        else dblk[k * (CB + 1) + k] = sqrt(d);
+      }
+      __syncthreads();
+      if (bad) { if (tid == 0) flag[0] = bad; return; }
+      const double p = dblk[k * (CB + 1) + k];
+      if (tid > k && tid < nb) dblk[tid * (CB + 1) + k] /= p;
+      __syncthreads();
+      for (int e = tid; e < nb * nb; e += 1024) {
+        const int i = e / nb, j = e % nb;
+        if (j > k && j <= i) dblk[i * (CB + 1) + j] -= dblk[i * (CB + 1) + k] * dblk[j * (CB + 1) + k];
+      }
+      __syncthreads();
+    }
+    for (int e = tid; e < nb * nb; e += 1024) {
+      const int i = e / nb, j = e % nb;
+      if (j <= i) A[(int64_t)(k0 + i) * N + k0 + j] = dblk[i * (CB + 1) + j];
+    }
+    // 2. panel below: row r solves x L11^T = a in place (one thread per row)
+    for (int r = k0 + nb + tid; r < N; r += 1024) {
+      double *ar = A + (int64_t)r * N + k0;
+      for (int j = 0; j < nb; ++j) {
+        double v = ar[j];
+        for (int t = 0; t < j; ++t) v -= ar[t] * dblk[j * (CB + 1) + t];
+        ar[j] = v / dblk[j * (CB + 1) + j];
+      }
+    }
     __syncthreads();
-    const int m = N - k - 1;
+    // 3. trailing update of the lower triangle
+    const int m = N - k0 - nb;
     const int64_t mm = (int64_t)m * m;
     for (int64_t e = tid; e < mm; e += 1024) {
-      const int i = k + 1 + (int)(e / m), j = k + 1 + (int)(e % m);
-      if (j <= i) A[(int64_t)i * N + j] -= A[(int64_t)i * N + k] * A[(int64_t)j * N + k];
+      const int i = k0 + nb + (int)(e / m), j = k0 + nb + (int)(e % m);
+      if (j > i) continue;
+      const double *li = A + (int64_t)i * N + k0;
+      const double *lj = A + (int64_t)j * N + k0;
+      double acc = 0.0;
+      for (int t = 0; t < nb; ++t) acc += li[t] * lj[t];
+      A[(int64_t)i * N + j] -= acc;
     }
     __syncthreads();
   }
@@ -267,28 +309,34 @@ hipError_t launch_cholesky(hipStream_t s, double *A, int N, int scale, double sh
   return hipGetLastError();
 }
 
-// W = diag(sv) L^-T: thread c forward-substitutes column c of L^-1 and writes
-// it as row c of W (upper triangular); zeros below the diagonal.
-__global__ __launch_bounds__(256) void k_tri_inv_T(const double *__restrict__ L,
-                                                   const double *__restrict__ sv, int N,
-                                                   double *__restrict__ W) {
-  const int c = blockIdx.x * 256 + threadIdx.x;
-  if (c >= N) return;
+// W = diag(sv) L^-T: column c of L^-1 (forward substitution) becomes row c of
+// W (upper triangular, zeros below the diagonal).  One single-wave workgroup
+// per column: the 64 lanes split each inner product and reduce it with
+// cross-lane shuffles; lane 0 stores the solved entry in the output row and a
+// workgroup barrier makes it visible before the next inner product.
+__global__ __launch_bounds__(64) void k_tri_inv_T(const double *__restrict__ L,
+                                                  const double *__restrict__ sv, int N,
+                                                  double *__restrict__ W) {
+  const int c = blockIdx.x;
+  const int lane = threadIdx.x;
   double *x = W + (int64_t)c * N;
-  for (int i = 0; i < c; ++i) x[i] = 0.0;
+  for (int i = lane; i < c; i += 64) x[i] = 0.0;
   for (int i = c; i < N; ++i) {
-    double acc = (i == c) ? 1.0 : 0.0;
     const double *Li = L + (int64_t)i * N;
-    for (int k = c; k < i; ++k) acc -= Li[k] * x[k];
-    x[i] = acc / Li[i];
+    double acc = 0.0;
+    for (int k = c + lane; k < i; k += 64) acc += Li[k] * x[k];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (lane == 0) x[i] = ((i == c ? 1.0 : 0.0) - acc) / Li[i];
+    __syncthreads();
   }
   const double s = sv[c];
-  for (int i = c; i < N; ++i) x[i] *= s;
+  for (int i = c + lane; i < N; i += 64) x[i] *= s;
 }
 
 hipError_t launch_tri_inv_T(hipStream_t s, const double *L, const double *sv, int N, double *W) {
   if (N <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_tri_inv_T, dim3((N + 255) / 256), dim3(256), 0, s, L, sv, N, W);
+  hipLaunchKernelGGL(k_tri_inv_T, dim3(N), dim3(64), 0, s, L, sv, N, W);
   return hipGetLastError();
 }
 

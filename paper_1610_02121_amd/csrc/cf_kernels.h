@@ -12,10 +12,25 @@ constexpr int NPAD = 128;     // local nodes per cell padded to a multiple of 16
 constexpr int CELL_NT = 16;   // column tile of the cell-product kernel
 constexpr int GT = 64;        // output tile of the Gram / rotation kernels
 
+// Flags of a (cell, local node) pair for the cell-product kernel.
+enum : uint8_t { CELL_FIRST = 1, CELL_FINISH = 2 };
+
+// Optional finishing step of the cell-product kernel (see k_cell_gemm).
+struct CellFinish {
+  const double *dinv = nullptr;
+  double c1 = 0.0, c2 = 0.0, c3 = 0.0;
+  const double *Yp = nullptr;
+  int64_t ldyp = 0;
+  double *Out = nullptr;            // null: no finishing step
+  int64_t ldo = 0;
+};
+
 // Arguments of the recurrence epilogue (see k_epilogue in cf_ops.hip).
 struct EpiArgs {
   int64_t n_h = 0, n_e = 0;
   int N = 0;
+  const int32_t *rows = nullptr;    // classical rows to process (null = all n_h)
+  int64_t nrows = 0;
   const double *R = nullptr;        // classical rows [n_h][ldr]
   int64_t ldr = 0;
   const double *dR = nullptr;       // per-row scale of R (null = 1)
@@ -40,10 +55,13 @@ struct EpiArgs {
 // ---- elemental operator kernels (cf_ops.hip)
 // Classical elemental products for the cells of one colour:
 //   Y[dof(e,a), :] (=|+=) sum_b H_e[a,b] X[dof(e,b), :]
-// first[e*NPAD+a] != 0 selects "=" (first touch of that DOF), else "+=".
+// flag[e*NPAD+a] & CELL_FIRST selects "=" (first touch of that DOF), else "+=";
+// CELL_FINISH marks the last touch of a DOF outside the enriched region, which
+// takes the recurrence step of f when f.Out is set (see k_cell_gemm).
 hipError_t launch_cell_gemm(hipStream_t s, const double *Hp, const int32_t *dofp,
-                            const uint8_t *firstp, const int32_t *cells, int ncells,
-                            const double *X, int64_t ldx, double *Y, int64_t ldy, int N);
+                            const uint8_t *flagp, const int32_t *cells, int ncells,
+                            const double *X, int64_t ldx, double *Y, int64_t ldy, int N,
+                            const CellFinish &f);
 
 // Coupling partials of the enriched cells (transposed per-cell blocks HT, MT at
 // offsets toff with row length tld):

@@ -30,25 +30,32 @@ __device__ __forceinline__ d4 d4zero() { d4 z = {0.0, 0.0, 0.0, 0.0}; return z; 
 // padding rows are zero.  Cells of one colour share no DOF, so the
 // read-modify-write of Y is race free; the first cell (in launch order) to
 // touch a DOF writes instead of adding.
+//
+// With a finishing step f (f.Out != null), a row whose flag marks the last
+// touch of a DOF outside the enriched region is complete here and takes the
+// Chebyshev recurrence at once instead of being stored in Y:
+//   Out[d] = c1 dinv[d] (H X)[d] + c2 X[d] + c3 Yp[d]
+// (X[d] is read from the tile in LDS).  Those rows of Y are left untouched.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(512, 2) void k_cell_gemm(
     const double *__restrict__ Hp, const int32_t *__restrict__ dofp,
-    const uint8_t *__restrict__ firstp, const int32_t *__restrict__ cells,
-    const double *__restrict__ X, int64_t ldx, double *__restrict__ Y, int64_t ldy, int N) {
+    const uint8_t *__restrict__ flagp, const int32_t *__restrict__ cells,
+    const double *__restrict__ X, int64_t ldx, double *__restrict__ Y, int64_t ldy, int N,
+    const CellFinish f) {
   constexpr int NT = CELL_NT;
   constexpr int LDX = NT + 16;
   constexpr int PF = NPAD * NT / 512;        // gathered doubles per thread per tile
   constexpr int RPP = 512 / NT;              // gathered rows per pass
   __shared__ double xs[NPAD * LDX];
   __shared__ int32_t sdof[NPAD];
-  __shared__ uint8_t sfirst[NPAD];
+  __shared__ uint8_t sflag[NPAD];
 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, kq = lane >> 4;
   const int cell = cells[blockIdx.x];
   if (tid < NPAD) {
     sdof[tid] = dofp[(int64_t)cell * NPAD + tid];
-    sfirst[tid] = firstp[(int64_t)cell * NPAD + tid];
+    sflag[tid] = flagp[(int64_t)cell * NPAD + tid];
   }
   // A[i][k] = H[i][k] = H[k][i]: lane reads H[4ks + kq][16w + li] (contiguous)
   const double *Hc = Hp + (int64_t)cell * NPAD * NPAD;
@@ -64,12 +71,15 @@ __global__ __launch_bounds__(512, 2) void k_cell_gemm(
   double pf[PF];
 #pragma unroll
   for (int p = 0; p < PF; ++p) pf[p] = (gd[p] >= 0 && gj < N) ? X[(int64_t)gd[p] * ldx + gj] : 0.0;
+  const bool finish = f.Out != nullptr;
   int od[4];
-  bool ofirst[4];
+  bool ofirst[4], ofin[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    od[r] = sdof[16 * w + kq + 4 * r];
-    ofirst[r] = sfirst[16 * w + kq + 4 * r] != 0;
+    const int row = 16 * w + kq + 4 * r;
+    od[r] = sdof[row];
+    ofirst[r] = (sflag[row] & CELL_FIRST) != 0;
+    ofin[r] = finish && od[r] >= 0 && (sflag[row] & CELL_FINISH) != 0;
   }
 
   for (int c0 = 0; c0 < N; c0 += NT) {
@@ -84,38 +94,52 @@ __global__ __launch_bounds__(512, 2) void k_cell_gemm(
         pf[p] = (gd[p] >= 0 && c1 + gj < N) ? X[(int64_t)gd[p] * ldx + c1 + gj] : 0.0;
     }
     const bool cv = li < ncol;
-    double yo[4];
+    double yo[4], yp[4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+    for (int r = 0; r < 4; ++r) {
       yo[r] = (od[r] >= 0 && !ofirst[r] && cv) ? Y[(int64_t)od[r] * ldy + c0 + li] : 0.0;
+      yp[r] = (ofin[r] && f.Yp && cv) ? f.Yp[(int64_t)od[r] * f.ldyp + c0 + li] : 0.0;
+    }
     d4 acc = d4zero();
 #pragma unroll
     for (int ks = 0; ks < 32; ++ks) acc = mfma_f64(a[ks], xs[(4 * ks + kq) * LDX + li], acc);
     if (cv) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
-        if (od[r] >= 0) Y[(int64_t)od[r] * ldy + c0 + li] = acc[r] + yo[r];
+      for (int r = 0; r < 4; ++r) {
+        if (od[r] < 0) continue;
+        const double v = acc[r] + yo[r];
+        if (ofin[r]) {
+          const double xk = xs[(16 * w + kq + 4 * r) * LDX + li];
+          f.Out[(int64_t)od[r] * f.ldo + c0 + li] = f.c1 * f.dinv[od[r]] * v + f.c2 * xk + f.c3 * yp[r];
+        } else {
+          Y[(int64_t)od[r] * ldy + c0 + li] = v;
+        }
+      }
     }
     __syncthreads();
   }
 }
 
 hipError_t launch_cell_gemm(hipStream_t s, const double *Hp, const int32_t *dofp,
-                            const uint8_t *firstp, const int32_t *cells, int ncells,
-                            const double *X, int64_t ldx, double *Y, int64_t ldy, int N) {
+                            const uint8_t *flagp, const int32_t *cells, int ncells,
+                            const double *X, int64_t ldx, double *Y, int64_t ldy, int N,
+                            const CellFinish &f) {
   if (ncells <= 0 || N <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_cell_gemm, dim3(ncells), dim3(512), 0, s, Hp, dofp, firstp, cells, X, ldx,
-                     Y, ldy, N);
+  hipLaunchKernelGGL(k_cell_gemm, dim3(ncells), dim3(512), 0, s, Hp, dofp, flagp, cells, X, ldx,
+                     Y, ldy, N, f);
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// Enriched-cell coupling partials (grid: enriched cells x column tiles of 16):
+// Enriched-cell coupling partials (one workgroup per enriched cell, walking
+// column tiles of 16):
 //   P[k0+k] = cH * sum_a H^ec_e[k][a] X[dof(e,a)]
 //           + cM * sum_a M^ec_e[k][a] s(dof) R[dof(e,a)]
 // The cell blocks are stored transposed, [NPAD][nap] with nap = the cell's
-// enrichment count padded to 16, so A-fragment loads are contiguous.  Either
-// term is skipped when its input block is null.
+// enrichment count padded to 16, so A-fragment loads are contiguous; they are
+// fetched from HBM on the first tile and from L2 afterwards.  The next tile's
+// gathered rows are loaded into registers during the current tile's MFMAs.
+// Either term is skipped when its input block is null.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_enr_part(
     const double *__restrict__ HT, const double *__restrict__ MT,
@@ -125,48 +149,74 @@ __global__ __launch_bounds__(256) void k_enr_part(
     const double *__restrict__ R, int64_t ldr, const double *__restrict__ rs, double cM,
     double *__restrict__ P, int64_t ldp, int N) {
   constexpr int PT = 16, LDX = 32;
+  constexpr int PF = NPAD * PT / 256;     // 8 gathered values per thread per block
+  constexpr int RPP = 256 / PT;           // 16 rows per pass
   __shared__ double xs[NPAD * LDX];
   __shared__ double rsm[NPAD * LDX];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, kq = lane >> 4;
   const int cell = cells[blockIdx.x];
-  const int c0 = blockIdx.y * PT;
-  const int ncol = min(PT, N - c0);
-  for (int idx = tid; idx < NPAD * PT; idx += 256) {
-    const int r = idx / PT, j = idx % PT;
-    const int d = dofp[(int64_t)cell * NPAD + r];
-    const bool v = d >= 0 && j < ncol;
-    xs[r * LDX + j] = (X && v) ? X[(int64_t)d * ldx + c0 + j] : 0.0;
-    rsm[r * LDX + j] = (R && v) ? R[(int64_t)d * ldr + c0 + j] * (rs ? rs[d] : 1.0) : 0.0;
+  const int gj = tid % PT, gr = tid / PT;
+  int gd[PF];
+  double gsc[PF];
+#pragma unroll
+  for (int p = 0; p < PF; ++p) {
+    gd[p] = dofp[(int64_t)cell * NPAD + gr + p * RPP];
+    gsc[p] = (rs && gd[p] >= 0) ? rs[gd[p]] : 1.0;
   }
-  __syncthreads();
+  double px[PF], pr[PF];
+#pragma unroll
+  for (int p = 0; p < PF; ++p) {
+    const bool v = gd[p] >= 0 && gj < N;
+    px[p] = (X && v) ? X[(int64_t)gd[p] * ldx + gj] : 0.0;
+    pr[p] = (R && v) ? R[(int64_t)gd[p] * ldr + gj] * gsc[p] : 0.0;
+  }
   const int64_t k0 = eptr[cell];
   const int na = (int)(eptr[cell + 1] - k0);
   const int nap = tld[cell];
   const int nmb = nap >> 4;
   const double *ht = X ? HT + toff[cell] : nullptr;
   const double *mt = R ? MT + toff[cell] : nullptr;
-  for (int mb = w; mb < nmb; mb += 4) {
-    d4 accH = d4zero(), accM = d4zero();
-    if (ht) {
-#pragma unroll 8
-      for (int ks = 0; ks < 32; ++ks)
-        accH = mfma_f64(ht[(int64_t)(4 * ks + kq) * nap + 16 * mb + li],
-                        xs[(4 * ks + kq) * LDX + li], accH);
-    }
-    if (mt) {
-#pragma unroll 8
-      for (int ks = 0; ks < 32; ++ks)
-        accM = mfma_f64(mt[(int64_t)(4 * ks + kq) * nap + 16 * mb + li],
-                        rsm[(4 * ks + kq) * LDX + li], accM);
-    }
-    if (li < ncol) {
+  for (int c0 = 0; c0 < N; c0 += PT) {
+    const int ncol = min(PT, N - c0);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int orow = 16 * mb + kq + 4 * r;
-        if (orow < na) P[(k0 + orow) * ldp + c0 + li] = cH * accH[r] + cM * accM[r];
+    for (int p = 0; p < PF; ++p) {
+      xs[(gr + p * RPP) * LDX + gj] = px[p];
+      rsm[(gr + p * RPP) * LDX + gj] = pr[p];
+    }
+    __syncthreads();
+    const int c1 = c0 + PT;
+    if (c1 < N) {
+#pragma unroll
+      for (int p = 0; p < PF; ++p) {
+        const bool v = gd[p] >= 0 && c1 + gj < N;
+        px[p] = (X && v) ? X[(int64_t)gd[p] * ldx + c1 + gj] : 0.0;
+        pr[p] = (R && v) ? R[(int64_t)gd[p] * ldr + c1 + gj] * gsc[p] : 0.0;
       }
     }
+    for (int mb = w; mb < nmb; mb += 4) {
+      d4 accH = d4zero(), accM = d4zero();
+      if (ht) {
+#pragma unroll 8
+        for (int ks = 0; ks < 32; ++ks)
+          accH = mfma_f64(ht[(int64_t)(4 * ks + kq) * nap + 16 * mb + li],
+                          xs[(4 * ks + kq) * LDX + li], accH);
+      }
+      if (mt) {
+#pragma unroll 8
+        for (int ks = 0; ks < 32; ++ks)
+          accM = mfma_f64(mt[(int64_t)(4 * ks + kq) * nap + 16 * mb + li],
+                          rsm[(4 * ks + kq) * LDX + li], accM);
+      }
+      if (li < ncol) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int orow = 16 * mb + kq + 4 * r;
+          if (orow < na) P[(k0 + orow) * ldp + c0 + li] = cH * accH[r] + cM * accM[r];
+        }
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -176,21 +226,22 @@ hipError_t launch_enr_part(hipStream_t s, const double *HT, const double *MT, co
                            double cH, const double *R, int64_t ldr, const double *rs, double cM,
                            double *P, int64_t ldp, int N) {
   if (ncells <= 0 || N <= 0) return hipSuccess;
-  dim3 grid(ncells, (N + 15) / 16);
-  hipLaunchKernelGGL(k_enr_part, grid, dim3(256), 0, s, HT, MT, toff, tld, eptr, dofp, cells, X,
-                     ldx, cH, R, ldr, rs, cM, P, ldp, N);
+  hipLaunchKernelGGL(k_enr_part, dim3(ncells), dim3(256), 0, s, HT, MT, toff, tld, eptr, dofp, cells,
+                     X, ldx, cH, R, ldr, rs, cM, P, ldp, N);
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
 // Transposed coupling products of the enriched cells, into a cell-local buffer
-// (grid: enriched cells x column tiles of 16; no read-modify-write):
+// (one workgroup per enriched cell, walking column tiles of 16; no
+// read-modify-write):
 //   Q[128 e' + a] = sum_k (cU H^ec_e[k][a] U[idx_k] + cV M^ec_e[k][a] V[idx_k])
 // e' is the position of the cell in the enriched-cell list, a its local node.
 // The gathered rows cU U[idx_k] and cV V[idx_k] sit in LDS (dynamic size:
-// 2 K4 rows of 16 columns, K4 = count rounded up to 4); either term is
-// skipped when its input is null.  The epilogue sums, for each classical DOF,
-// the (at most 8) Q rows of the enriched cells that contain it.
+// 2 K4 rows of 16 columns, K4 = count rounded up to 4); the cell's coupling
+// rows are read from HBM on the first tile and from L2 afterwards.  Either
+// term is skipped when its input is null.  The epilogue sums, for each
+// classical DOF, the (at most 8) Q rows of the enriched cells that contain it.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_enr_q(
     const double *__restrict__ Hec, const double *__restrict__ Mec,
@@ -203,48 +254,51 @@ __global__ __launch_bounds__(256) void k_enr_q(
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, kq = lane >> 4;
   const int cell = cells[blockIdx.x];
-  const int c0 = blockIdx.y * PT;
-  const int ncol = min(PT, N - c0);
   const int64_t k0 = eptr[cell];
   const int na = (int)(eptr[cell + 1] - k0);
   const int K4 = (na + 3) & ~3;
-  for (int idx = tid; idx < K4 * PT; idx += 256) {
-    const int k = idx / PT, j = idx % PT;
-    const bool v = k < na && j < ncol;
-    const int64_t al = v ? eidx[k0 + k] : 0;
-    zs[k * LDZ + j] = (U && v) ? cU * U[al * ldu + c0 + j] : 0.0;
-    zs[(K4 + k) * LDZ + j] = (V && v) ? cV * V[al * ldv + c0 + j] : 0.0;
-  }
-  __syncthreads();
-  d4 acc0 = d4zero(), acc1 = d4zero();
   const int nks = K4 / 4;
-  if (U) {
-    for (int ks = 0; ks < nks; ++ks) {
-      const int k = 4 * ks + kq;
-      const double *row = Hec + (k0 + min(k, na - 1)) * NPAD + 32 * w;
-      const double a0 = k < na ? row[li] : 0.0, a1 = k < na ? row[16 + li] : 0.0;
-      const double b = zs[k * LDZ + li];
-      acc0 = mfma_f64(a0, b, acc0);
-      acc1 = mfma_f64(a1, b, acc1);
+  double *qb = Q + ((int64_t)blockIdx.x * NPAD) * ldq;
+  for (int c0 = 0; c0 < N; c0 += PT) {
+    const int ncol = min(PT, N - c0);
+    for (int idx = tid; idx < K4 * PT; idx += 256) {
+      const int k = idx / PT, j = idx % PT;
+      const bool v = k < na && j < ncol;
+      const int64_t al = v ? eidx[k0 + k] : 0;
+      zs[k * LDZ + j] = (U && v) ? cU * U[al * ldu + c0 + j] : 0.0;
+      zs[(K4 + k) * LDZ + j] = (V && v) ? cV * V[al * ldv + c0 + j] : 0.0;
     }
-  }
-  if (V) {
-    for (int ks = 0; ks < nks; ++ks) {
-      const int k = 4 * ks + kq;
-      const double *row = Mec + (k0 + min(k, na - 1)) * NPAD + 32 * w;
-      const double a0 = k < na ? row[li] : 0.0, a1 = k < na ? row[16 + li] : 0.0;
-      const double b = zs[(K4 + k) * LDZ + li];
-      acc0 = mfma_f64(a0, b, acc0);
-      acc1 = mfma_f64(a1, b, acc1);
+    __syncthreads();
+    d4 acc0 = d4zero(), acc1 = d4zero();
+    if (U) {
+      for (int ks = 0; ks < nks; ++ks) {
+        const int k = 4 * ks + kq;
+        const double *row = Hec + (k0 + min(k, na - 1)) * NPAD + 32 * w;
+        const double a0 = k < na ? row[li] : 0.0, a1 = k < na ? row[16 + li] : 0.0;
+        const double b = zs[k * LDZ + li];
+        acc0 = mfma_f64(a0, b, acc0);
+        acc1 = mfma_f64(a1, b, acc1);
+      }
     }
-  }
-  if (li < ncol) {
-    double *q = Q + ((int64_t)blockIdx.x * NPAD) * ldq + c0 + li;
+    if (V) {
+      for (int ks = 0; ks < nks; ++ks) {
+        const int k = 4 * ks + kq;
+        const double *row = Mec + (k0 + min(k, na - 1)) * NPAD + 32 * w;
+        const double a0 = k < na ? row[li] : 0.0, a1 = k < na ? row[16 + li] : 0.0;
+        const double b = zs[(K4 + k) * LDZ + li];
+        acc0 = mfma_f64(a0, b, acc0);
+        acc1 = mfma_f64(a1, b, acc1);
+      }
+    }
+    if (li < ncol) {
+      double *q = qb + c0 + li;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      q[(int64_t)(32 * w + kq + 4 * r) * ldq] = acc0[r];
-      q[(int64_t)(32 * w + 16 + kq + 4 * r) * ldq] = acc1[r];
+      for (int r = 0; r < 4; ++r) {
+        q[(int64_t)(32 * w + kq + 4 * r) * ldq] = acc0[r];
+        q[(int64_t)(32 * w + 16 + kq + 4 * r) * ldq] = acc1[r];
+      }
     }
+    __syncthreads();
   }
 }
 
@@ -261,9 +315,8 @@ hipError_t launch_enr_q(hipStream_t s, const double *Hec, const double *Mec, con
     if (e != hipSuccess) return e;
     shm_set = shm;
   }
-  dim3 grid(ncells, (N + 15) / 16);
-  hipLaunchKernelGGL(k_enr_q, grid, dim3(256), shm, s, Hec, Mec, eptr, eidx, cells, U, ldu, cU, V,
-                     ldv, cV, Q, ldq, N);
+  hipLaunchKernelGGL(k_enr_q, dim3(ncells), dim3(256), shm, s, Hec, Mec, eptr, eidx, cells, U, ldu,
+                     cU, V, ldv, cV, Q, ldq, N);
   return hipGetLastError();
 }
 
@@ -308,7 +361,8 @@ hipError_t launch_enr_reduce(hipStream_t s, int n_e, const int64_t *aptr, const 
 }
 
 // ---------------------------------------------------------------------------
-// Epilogue over all n = n_h + n_e rows (block: 64 columns x 4 rows):
+// Epilogue over all n = n_h + n_e rows, or over a list of classical rows and
+// the enrichment rows (block: 64 columns x 4 rows):
 //   classical row i:  v = dR_i R[i] + dC_i sum_p Q[qidx[p]]   (p over qptr[i]..qptr[i+1];
 //                     the rows of the enriched-cell buffer holding DOF i; null
 //                     scales mean 1)
@@ -317,9 +371,13 @@ hipError_t launch_enr_reduce(hipStream_t s, int n_e, const int64_t *aptr, const 
 // Out may alias R or Yp: each element is read before the same thread writes it.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_epilogue(const EpiArgs g) {
-  const int64_t n = g.n_h + g.n_e;
-  for (int64_t i = (int64_t)blockIdx.x * 4 + threadIdx.y; i < n; i += (int64_t)gridDim.x * 4) {
-    const bool cls = i < g.n_h;
+  // rows: all n_h + n_e rows, or the listed classical rows followed by the n_e
+  // enrichment rows
+  const int64_t ncls = g.rows ? g.nrows : g.n_h;
+  const int64_t nt = ncls + g.n_e;
+  for (int64_t t = (int64_t)blockIdx.x * 4 + threadIdx.y; t < nt; t += (int64_t)gridDim.x * 4) {
+    const bool cls = t < ncls;
+    const int64_t i = cls ? (g.rows ? (int64_t)g.rows[t] : t) : g.n_h + (t - ncls);
     double dr = 1.0, dc = 1.0;
     int p0 = 0, p1 = 0;
     if (cls) {
@@ -348,7 +406,7 @@ __global__ __launch_bounds__(256) void k_epilogue(const EpiArgs g) {
 }
 
 hipError_t launch_epilogue(hipStream_t s, const EpiArgs &g) {
-  const int64_t n = g.n_h + g.n_e;
+  const int64_t n = (g.rows ? g.nrows : g.n_h) + g.n_e;
   if (n <= 0 || g.N <= 0) return hipSuccess;
   int64_t blocks = (n + 3) / 4;
   if (blocks > 65536) blocks = 65536;

@@ -22,7 +22,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64_MFMA = 78.6e12          # MI355X dense FP64 matrix, FLOP/s
+PEAK_FP32_MFMA = 157.3e12         # MI355X dense FP32 matrix, FLOP/s
+PEAK_BF16_MFMA = 2.5e15           # MI355X dense BF16 matrix, FLOP/s
 PEAK_HBM = 8.0e12                 # MI355X HBM3E, B/s
+CELL_KERNEL = {"fp64": ("cell_gemm", "k_cell_gemm", PEAK_FP64_MFMA),
+               "fp32": ("cell_gemm_fp32", "k_cell_gemm_lp<fp32>", PEAK_FP32_MFMA),
+               "bf16": ("cell_gemm_bf16", "k_cell_gemm_lp<bf16>", PEAK_BF16_MFMA)}
+PROFILED = ("cell_gemm", "cell_gemm_fp32", "cell_gemm_bf16", "enr_part", "enr_reduce", "enr_q",
+            "enr_gemm", "epilogue", "gram", "rotate")
 
 WORKLOADS = {
     # name: (generator, N, m, wanted)
@@ -70,6 +77,120 @@ def cpu_baseline(prob, N_total, m, seed, budget_s=20.0):
                       f"scipy sparse products run on one thread; setup {t_setup:.1f}s untimed"}
 
 
+def precision_forms(ctx, X, Y, m, a, b, reps=3):
+    """Filter-only time of each precision form on the same block and interval,
+    with the cell-product kernel's event-timed launches."""
+    import torch
+    n, N = X.shape
+    res = {}
+    for prec in ("fp64", "fp32", "bf16"):
+        ctx.filter(X, m, a, b, Y=Y, prec=prec)          # first use builds the reduced copies
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ctx.filter(X, m, a, b, Y=Y, prec=prec)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        ctx.profile(True)
+        ctx.filter(X, m, a, b, Y=Y, prec=prec)
+        key, kname, peak = CELL_KERNEL[prec]
+        launches, ms, flops = ctx.profile_query(key)
+        ctx.profile(False)
+        res[prec] = {"filter_ms": 1e3 * dt, "dof_vec_deg_per_s": n * N * m / dt,
+                     "cell_kernel": kname, "cell_avg_launch_ms": ms / max(launches, 1),
+                     "cell_tflops": flops / (ms / 1e3) / 1e12 if ms > 0 else None,
+                     "cell_peak_tflops": peak / 1e12,
+                     "cell_frac": flops / (ms / 1e3) / peak if ms > 0 else None}
+    for prec in ("fp32", "bf16"):
+        res[prec]["speedup_vs_fp64"] = res["fp64"]["filter_ms"] / res[prec]["filter_ms"]
+    return res
+
+
+def mixed_study(ctx, prob, N, m, wanted, seed, m_lp, max_passes=30):
+    """Time to tolerance from the atomic-orbital start (seconds of device work
+    per form, counted over whole passes: bounds + filter + Rayleigh-Ritz).
+    Reference eigenvalues: an FP64 run continued until the wanted Ritz values
+    change by < 1e-12 Ha between passes.  FP64 form: passes until the Ritz
+    error <= 1e-8 Ha.  Mixed forms: reduced-precision passes of degree m_lp
+    until the wanted Ritz values stop improving (change between passes no
+    longer shrinks by 2x, or < 1e-7 Ha), then FP64 cleanup passes of degree m
+    until the Ritz error <= 1e-6 Ha."""
+    import numpy as np
+    import torch
+    from synth import configs
+    dev = torch.device("cuda", 0)
+    v0 = torch.tensor(np.random.default_rng(seed + 1).standard_normal(prob.n),
+                      dtype=torch.float64, device=dev)
+
+    def run(schedule):
+        X = torch.tensor(configs.initial_block(prob, N, seed=seed), dtype=torch.float64, device=dev)
+        Y = torch.empty_like(X)
+        th = ctx.rayleigh_ritz(X)
+        hist = []
+        t = 0.0
+        phase = "reduced"
+        for it in range(max_passes):
+            prec, deg, phase, stop = schedule(it, hist, phase)
+            if stop:
+                break
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, b = ctx.lanczos_bounds(v0, 10)
+            a = float(th[-1])
+            try:
+                ctx.filter(X, deg, a, b, Y=Y, prec=prec)
+                th_new = ctx.rayleigh_ritz(Y)
+            except Exception as exc:                     # reported, not hidden
+                log(f"study pass {it}: {prec} m={deg} a={a:.6f} b={b:.6f} failed: {exc}")
+                hist.append({"prec": prec, "degree": deg, "t": t, "failed": str(exc)})
+                break
+            torch.cuda.synchronize()
+            t += time.perf_counter() - t0
+            X, Y = Y, X
+            d = float(np.abs(th_new[:wanted] - th[:wanted]).max())
+            th = th_new
+            hist.append({"prec": prec, "degree": deg, "t": t, "dtheta": d, "theta": th.copy()})
+            log(f"study pass {it}: {prec} m={deg} a={a:.6f} b={b:.6f} dtheta={d:.3e} t={t:.3f}s")
+        return hist
+
+    # reference: FP64 passes until the wanted Ritz values settle at the FP64
+    # noise level (change < 1e-8 Ha on three passes in a row), at most max_passes
+    def settled(h):
+        return len(h) >= 3 and all(x.get("dtheta", 1.0) < 1e-8 for x in h[-3:])
+    ref = run(lambda it, h, ph: ("fp64", m, ph, settled(h)))
+    if "failed" in ref[-1]:
+        return {"failed": "reference run: " + ref[-1]["failed"]}
+    lam = ref[-1]["theta"][:wanted]
+
+    def err(h):
+        return float(np.abs(h["theta"][:wanted] - lam).max()) if "theta" in h else None
+
+    out = {"reference_passes": len(ref), "m": m, "m_reduced": m_lp}
+    hit = next((h for h in ref if err(h) <= 1e-8), None)
+    out["fp64"] = {"passes": ref.index(hit) + 1 if hit else None, "seconds": hit["t"] if hit else None,
+                   "tolerance": 1e-8, "errors": [err(h) for h in ref]}
+    for prec in ("fp32", "bf16"):
+        def sched(it, h, ph, prec=prec):
+            if h and h[-1]["prec"] == "fp64" and "theta" in h[-1] and err(h[-1]) <= 1e-6:
+                return None, None, ph, True
+            if ph == "reduced" and len(h) >= 3:
+                d1, d0 = h[-1]["dtheta"], h[-2]["dtheta"]
+                if d1 < 1e-7 or d1 > 0.5 * d0:
+                    ph = "cleanup"
+            return (prec, m_lp, ph, False) if ph == "reduced" else ("fp64", m, ph, False)
+        hist = run(sched)
+        last = hist[-1]
+        ok = last["prec"] == "fp64" and "theta" in last and err(last) <= 1e-6
+        out[prec] = {"passes": len(hist), "reduced_passes": sum(h["prec"] == prec for h in hist),
+                     "seconds": last["t"] if ok else None, "tolerance": 1e-6,
+                     "errors": [err(h) for h in hist], "reached": ok}
+        if "failed" in last:
+            out[prec]["failed"] = last["failed"]
+        if ok and out["fp64"]["seconds"]:
+            out[prec]["speedup_vs_fp64_time_to_tolerance"] = out["fp64"]["seconds"] / last["t"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -79,6 +200,14 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16"],
+                    help="arithmetic of the filter in the timed steps (Rayleigh-Ritz stays FP64)")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the filter-only timing of the three precision forms")
+    ap.add_argument("--mixed-study", action="store_true",
+                    help="run the time-to-tolerance study of the precision forms instead")
+    ap.add_argument("--m-reduced", type=int, default=20,
+                    help="filter degree of the reduced-precision passes in the study")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -100,13 +229,20 @@ def main():
         f"{time.time() - t0:.1f}s")
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
-    ctx = Context(prob, max_cols=N)
+    # the study checks every filter output for non-finite values
+    ctx = Context(prob, max_cols=N, check_finite=args.mixed_study)
     log(f"context ready ({time.time() - t0:.1f}s)")
     X0 = configs.initial_block(prob, N, seed=args.seed)
     X = torch.tensor(X0, dtype=torch.float64, device=dev)
     Y = torch.empty_like(X)
     v0 = torch.tensor(np.random.default_rng(args.seed + 1).standard_normal(prob.n),
                       dtype=torch.float64, device=dev)
+    if args.mixed_study:
+        study = mixed_study(ctx, prob, N, m, wanted, args.seed, args.m_reduced)
+        print(json.dumps({"study": "time to tolerance by precision form", "workload": name,
+                          "n_dof": prob.n, "vectors": N, "wanted": wanted, **study}), flush=True)
+        ctx.close()
+        return
     theta = ctx.rayleigh_ritz(X)
     log(f"initial Rayleigh-Ritz: theta[0]={theta[0]:.6f} theta[N-1]={theta[-1]:.6f}")
 
@@ -118,7 +254,7 @@ def main():
         lo, b = ctx.lanczos_bounds(v0, 10)          # synchronises
         s1 = time.perf_counter()
         a = float(state["theta"][-1])
-        ctx.filter(state["X"], m, a, b, Y=state["Y"])
+        ctx.filter(state["X"], m, a, b, Y=state["Y"], prec=args.prec)
         torch.cuda.synchronize()
         s2 = time.perf_counter()
         th = ctx.rayleigh_ritz(state["Y"])          # synchronises
@@ -149,7 +285,7 @@ def main():
     # kernel timing over the timed region (HIP events on the library's stream)
     prof = {}
     if not args.no_profile:
-        for k in ("cell_gemm", "enr_part", "enr_reduce", "enr_q", "enr_gemm", "epilogue", "gram", "rotate"):
+        for k in PROFILED:
             prof[k] = ctx.profile_query(k)
         ctx.profile(False)
 
@@ -174,10 +310,11 @@ def main():
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms_per_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64", "data": "synthetic",
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "bf16"}[args.prec], "data": "synthetic",
         "config": {"workload": name, "n_dof": n, "n_enrich": prob.n_e, "cells": prob.n_cells,
                    "degree_p": prob.p, "vectors": N, "cheb_degree": m, "wanted": wanted,
-                   "precision": "fp64"},
+                   "precision": args.prec if args.prec == "fp64" else
+                   f"{args.prec} filter, fp64 Schur solve and Rayleigh-Ritz"},
         "phases_ms": {"bounds": 1e3 * state["t_bounds"] / args.steps,
                       "filter": 1e3 * state["t_filter"] / args.steps,
                       "cholqr_rr": 1e3 * state["t_rr"] / args.steps},
@@ -186,17 +323,23 @@ def main():
                         "theta_min": float(state["theta"][0]),
                         "theta_wanted_max": float(state["theta"][wanted - 1])},
     }
-    if prof and prof["cell_gemm"][0] > 0:
-        # every cell-product launch of the timed region (N = 260 filter/RR launches and the
-        # single-vector Lanczos launches), credited 2 npc^2 N flops per cell
-        launches, ms, flops = prof["cell_gemm"]
+    key, kname, peak = CELL_KERNEL[args.prec]
+    if prof and prof[key][0] > 0:
+        # every cell-product launch of the timed region, credited 2 npc^2 N flops per
+        # cell (for fp64 this includes the single-vector Lanczos and the Rayleigh-Ritz
+        # launches)
+        launches, ms, flops = prof[key]
         achieved = flops / (ms / 1e3)
-        out["roofline"] = {"kernel": "k_cell_gemm", "bound": "mfma", "achieved": achieved / 1e12,
-                           "peak": PEAK_FP64_MFMA / 1e12, "unit": "TFLOP/s",
-                           "frac": achieved / PEAK_FP64_MFMA, "traffic": None,
+        out["roofline"] = {"kernel": kname, "bound": "mfma", "achieved": achieved / 1e12,
+                           "peak": peak / 1e12, "unit": "TFLOP/s",
+                           "frac": achieved / peak, "traffic": None,
                            "launches": launches, "avg_launch_ms": ms / launches,
                            "flops_per_launch": flops / launches}
-        out["kernel_ms_per_step"] = {k: v[1] / args.steps for k, v in prof.items()}
+        out["kernel_ms_per_step"] = {k: v[1] / args.steps for k, v in prof.items() if v[0] > 0}
+    if not args.no_forms:
+        log("timing the filter alone in the three precision forms")
+        out["precision_forms"] = precision_forms(ctx, state["X"], state["Y"], m,
+                                                 float(state["theta"][-1]), state["b"])
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(prob, N, m, args.seed)

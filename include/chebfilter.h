@@ -109,8 +109,18 @@ cf_status chebfilter_apply_Sinv(cf_ctx *ctx, const double *X, int64_t ldx, doubl
 
 /* Y = T_m(t(H~)) X, t(x) = (2x - a - b)/(b - a), H~ = (M^E)^-1 H^E, by the
  * three-term Chebyshev recurrence (Sec. V).  m = 0 copies X.  Requires b > a,
- * both finite, m >= 0.  prec selects the arithmetic of the elemental products
- * (CF_FP64 only in this build; other values return CF_EINVAL). */
+ * both finite, m >= 0.  prec selects the arithmetic of the recurrence:
+ *   CF_FP64  everything in FP64;
+ *   CF_FP32  recurrence blocks, elemental and coupling products in FP32 (FP32
+ *            MFMA); enrichment-row sums, the Schur-complement solve and its
+ *            output in FP64; X is rounded to FP32 on entry, Y widened to FP64;
+ *   CF_BF16  as CF_FP32, but the elemental products take the cell matrices and
+ *            the gathered vector tiles in BF16 (FP32 accumulation).
+ * The reduced forms keep FP32 copies of the operator (and BF16 cell matrices)
+ * on the device from their first use until chebfilter_destroy, plus two FP32
+ * blocks of n x max_cols.  Their results carry FP32 (or BF16) rounding: they
+ * are meant for filter passes followed by an FP64 cleanup pass.  Other prec
+ * values return CF_EINVAL. */
 cf_status chebfilter_filter(cf_ctx *ctx, const double *X, int64_t ldx, double *Y, int64_t ldy,
                             int64_t N, int32_t m, double a, double b, int32_t prec);
 

@@ -161,11 +161,13 @@ class Context:
         self._check(self.lib.chebfilter_apply_Sinv(self._h, xp, ldx, yp, ldy, X.shape[1]))
         return Y
 
-    def filter(self, X, m: int, a: float, b: float, Y=None, prec: str = "fp64"):
+    def filter(self, X, m: int, a: float, b: float, Y=None, prec="fp64"):
+        """Y = T_m(t(H~)) X; prec is "fp64", "fp32", "bf16" or a cf_prec code."""
         Y = self._out(X, Y)
         (xp, ldx), (yp, ldy) = _block(X, "X"), _block(Y, "Y")
+        code = PREC[prec] if isinstance(prec, str) else int(prec)
         self._check(self.lib.chebfilter_filter(self._h, xp, ldx, yp, ldy, X.shape[1], int(m),
-                                               float(a), float(b), PREC[prec]))
+                                               float(a), float(b), code))
         return Y
 
     def cholqr(self, Y):

@@ -77,6 +77,14 @@ struct cf_ctx {
   rocblas_int *info = nullptr;
   // Lanczos
   double *lzv = nullptr, *lzcoef = nullptr, *lzpart = nullptr;
+  // reduced-precision filter state, allocated on the first CF_FP32 / CF_BF16
+  // filter call: FP32 (or BF16) copies of the cell matrices, FP32 copies of
+  // the coupling blocks and FP32 recurrence blocks (ld = max_cols)
+  int64_t ttot = 0;
+  float *Hp32 = nullptr;
+  void *Hp16 = nullptr;
+  float *HT32 = nullptr, *MT32 = nullptr, *Hec32 = nullptr, *Mec32 = nullptr;
+  float *F0 = nullptr, *F1 = nullptr, *R32 = nullptr, *P32 = nullptr, *Q32 = nullptr;
   rocblas_handle rb = nullptr;
   std::string err;
   bool profiling = false;
@@ -291,6 +299,99 @@ static cf_status core_htilde_step(cf_ctx *c, const double *Xin, int64_t ldxin, i
   if (finish) { g.rows = c->regrows; g.nrows = c->nregrows; }
   Scope sc(c, "epilogue");
   HIPCHK(c, launch_epilogue(c->stream, g));
+  return CF_OK;
+}
+
+// Reduced-precision copies of the operator and FP32 workspace (once per
+// context and precision).
+static cf_status ensure_lowp(cf_ctx *c, bool bf16) {
+  const int64_t mc = c->max_cols;
+  if (!c->F0) {
+    STCHK(dalloc(c, &c->F0, (size_t)c->n * mc));
+    STCHK(dalloc(c, &c->F1, (size_t)c->n * mc));
+    STCHK(dalloc(c, &c->R32, (size_t)c->n_h * mc));
+    if (c->n_e > 0) {
+      STCHK(dalloc(c, &c->HT32, (size_t)std::max<int64_t>(c->ttot, 1)));
+      STCHK(dalloc(c, &c->MT32, (size_t)std::max<int64_t>(c->ttot, 1)));
+      STCHK(dalloc(c, &c->Hec32, (size_t)std::max<int64_t>(c->nnz, 1) * NPAD));
+      STCHK(dalloc(c, &c->Mec32, (size_t)std::max<int64_t>(c->nnz, 1) * NPAD));
+      STCHK(dalloc(c, &c->P32, (size_t)std::max<int64_t>(c->nnz, 1) * mc));
+      STCHK(dalloc(c, &c->Q32, (size_t)std::max<int>(c->necells, 1) * NPAD * mc));
+      HIPCHK(c, launch_to_f32(c->stream, c->ttot, c->HT, c->HT32));
+      HIPCHK(c, launch_to_f32(c->stream, c->ttot, c->MT, c->MT32));
+      HIPCHK(c, launch_to_f32(c->stream, c->nnz * NPAD, c->Hec, c->Hec32));
+      HIPCHK(c, launch_to_f32(c->stream, c->nnz * NPAD, c->Mec, c->Mec32));
+    }
+  }
+  const int64_t hsz = c->E * NPAD * NPAD;
+  if (bf16 && !c->Hp16) {
+    uint16_t *h = nullptr;
+    STCHK(dalloc(c, &h, (size_t)hsz));
+    c->Hp16 = h;
+    HIPCHK(c, launch_to_bf16(c->stream, hsz, c->Hp, c->Hp16));
+  }
+  if (!bf16 && !c->Hp32) {
+    STCHK(dalloc(c, &c->Hp32, (size_t)hsz));
+    HIPCHK(c, launch_to_f32(c->stream, hsz, c->Hp, c->Hp32));
+  }
+  return CF_OK;
+}
+
+// FP32 form of core_htilde_step with the finishing step always on:
+//   Out = c1 * H~ Xin + c2 * Xin + c3 * Yp
+// Elemental and coupling products in FP32 (cell matrices FP32 or BF16 with
+// FP32 accumulation); the enrichment-row sums, the Schur solve z = S^-1 w and
+// z itself stay FP64.  Out may be Yp (each element is read before it is
+// written, by the same thread).
+static cf_status core_htilde_step_lp(cf_ctx *c, bool bf16, const float *Xin, int64_t ldxin, int N,
+                                     float c1, float c2, const float *Yp, int64_t ldyp, float c3,
+                                     float *Out, int64_t ldo) {
+  const int64_t mc = c->max_cols;
+  CellFinishF f;
+  f.dinv = c->dinv;
+  f.c1 = c1; f.c2 = c2; f.c3 = Yp ? c3 : 0.f;
+  f.Yp = Yp; f.ldyp = ldyp;
+  f.Out = Out; f.ldo = ldo;
+  const void *Hv = bf16 ? c->Hp16 : (const void *)c->Hp32;
+  for (size_t k = 0; k + 1 < c->col_off.size(); ++k) {
+    Scope sc(c, bf16 ? "cell_gemm_bf16" : "cell_gemm_fp32",
+             2.0 * c->npc * c->npc * (double)N * (c->col_off[k + 1] - c->col_off[k]));
+    HIPCHK(c, launch_cell_gemm_lp(c->stream, bf16, Hv, c->dofp, c->flagp, c->cells + c->col_off[k],
+                                  c->col_off[k + 1] - c->col_off[k], Xin, ldxin, c->R32, mc, N, f));
+  }
+  const float *Xe = Xin + c->n_h * ldxin;
+  if (c->n_e > 0) {
+    {
+      Scope sc(c, "enr_part");
+      HIPCHK(c, launch_enr_part_f32(c->stream, c->HT32, c->MT32, c->toff, c->tld, c->eptr, c->dofp,
+                                    c->ecells, c->necells, Xin, ldxin, 1.f, c->R32, mc, c->dinv,
+                                    -1.f, c->P32, mc, N));
+    }
+    {
+      Scope sc(c, "enr_reduce");
+      HIPCHK(c, launch_enr_reduce_f32(c->stream, (int)c->n_e, c->aptr, c->alist, c->P32, mc,
+                                      c->Hmod, Xe, ldxin, c->Wb, mc, N));
+    }
+    STCHK(core_schur_solve(c, N));
+    {
+      Scope sc(c, "enr_q");
+      HIPCHK(c, launch_enr_q_f32(c->stream, c->Hec32, c->Mec32, c->eptr, c->eidx, c->ecells,
+                                 c->necells, c->kmax, Xe, ldxin, 1.f, c->Zb, mc, -1.f, c->Q32, mc,
+                                 N));
+    }
+  }
+  EpiArgsF g;
+  g.n_h = c->n_h; g.n_e = c->n_e; g.N = N;
+  g.rows = c->regrows; g.nrows = c->nregrows;
+  g.dinv = c->dinv;
+  g.R = c->R32; g.ldr = mc;
+  if (c->n_e > 0) { g.qptr = c->qptr; g.qidx = c->qidx; g.Q = c->Q32; g.ldq = mc; }
+  g.Ee = c->Zb; g.lde = mc;
+  g.c1 = c1; g.Yk = Xin; g.ldyk = ldxin; g.c2 = c2;
+  g.Yp = Yp; g.ldyp = ldyp; g.c3 = Yp ? c3 : 0.f;
+  g.Out = Out; g.ldo = ldo;
+  Scope sc(c, "epilogue");
+  HIPCHK(c, launch_epilogue_f32(c->stream, g));
   return CF_OK;
 }
 
@@ -579,7 +680,7 @@ static cf_status do_init(const cf_problem *pr, const cf_options *opt, cf_ctx *c)
     // transposed per-cell blocks [NPAD][nap], nap = count padded to 16
     std::vector<int64_t> toff(E, 0);
     std::vector<int32_t> tld(E, 0);
-    int64_t ttot = 0;
+    int64_t &ttot = c->ttot;
     for (int32_t e : elist) {
       const int na = (int)(ep[e + 1] - ep[e]);
       tld[e] = (na + 15) & ~15;
@@ -949,7 +1050,8 @@ cf_status chebfilter_filter(cf_ctx *c, const double *X, int64_t ldx, double *Y, 
   if (m < 0) return set_err(c, CF_EINVAL, "filter: m < 0");
   if (!std::isfinite(a) || !std::isfinite(b) || !(b > a))
     return set_err(c, CF_EINVAL, "filter: need finite a < b");
-  if (prec != CF_FP64) return set_err(c, CF_EINVAL, "filter: only CF_FP64 is built");
+  if (prec != CF_FP64 && prec != CF_FP32 && prec != CF_BF16)
+    return set_err(c, CF_EINVAL, "filter: prec must be CF_FP64, CF_FP32 or CF_BF16");
   if (N == 0) return CF_OK;
   if (X == Y) return set_err(c, CF_EINVAL, "filter: Y must not alias X");
   HIPCHK(c, hipSetDevice(c->device));
@@ -960,6 +1062,21 @@ cf_status chebfilter_filter(cf_ctx *c, const double *X, int64_t ldx, double *Y, 
   }
   // t(H~) = e H~ - cc I with e = 2/(b-a), cc = (a+b)/(b-a)
   const double e = 2.0 / (b - a), cc = (a + b) / (b - a);
+  if (prec != CF_FP64) {
+    // FP32 recurrence: Y_k lives in F0 (k even) or F1 (k odd); Y_{k+1}
+    // overwrites Y_{k-1} element by element
+    const bool bf16 = prec == CF_BF16;
+    STCHK(ensure_lowp(c, bf16));
+    const int64_t mc = c->max_cols;
+    float *F[2] = {c->F0, c->F1};
+    HIPCHK(c, launch_block_d2f(c->stream, c->n, n, X, ldx, c->F0, mc));
+    STCHK(core_htilde_step_lp(c, bf16, F[0], mc, n, (float)e, (float)-cc, nullptr, 0, 0.f, F[1], mc));
+    for (int k = 1; k < m; ++k)
+      STCHK(core_htilde_step_lp(c, bf16, F[k & 1], mc, n, (float)(2.0 * e), (float)(-2.0 * cc),
+                                F[(k - 1) & 1], mc, -1.f, F[(k + 1) & 1], mc));
+    HIPCHK(c, launch_block_f2d(c->stream, c->n, n, F[m & 1], mc, Y, ldy));
+    return check_out_finite(c, Y, ldy, n, "filter");
+  }
   // Y_k lives in Y when (m - k) is even, else in the internal block B2.
   auto buf = [&](int k) -> double * { return ((m - k) % 2 == 0) ? Y : c->B2; };
   auto ldb = [&](int k) -> int64_t { return ((m - k) % 2 == 0) ? ldy : c->max_cols; };

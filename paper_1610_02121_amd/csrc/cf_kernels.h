@@ -99,6 +99,76 @@ hipError_t launch_csr_dense(hipStream_t s, int64_t nreg, const int32_t *regrow,
                             const double *mv, const double *dinv, double *BM, double *BH,
                             int64_t ldb);
 
+// ---- reduced-precision operator kernels (cf_lowp.hip): FP32 vectors, FP32
+// or BF16 cell matrices, FP32 coupling blocks; enrichment-row sums in FP64.
+struct CellFinishF {
+  const double *dinv = nullptr;
+  float c1 = 0.f, c2 = 0.f, c3 = 0.f;
+  const float *Yp = nullptr;
+  int64_t ldyp = 0;
+  float *Out = nullptr;             // null: no finishing step
+  int64_t ldo = 0;
+};
+
+// Recurrence epilogue of the reduced-precision step:
+//   Out[i] = c1 * dinv[i] (R[i] + sum_p Q[qidx[p]]) + c2 Yk[i] + c3 Yp[i]  (listed classical rows)
+//   Out[i] = c1 * Ee[i - n_h] + c2 Yk[i] + c3 Yp[i]                        (enrichment rows)
+struct EpiArgsF {
+  int64_t n_h = 0, n_e = 0;
+  int N = 0;
+  const int32_t *rows = nullptr;
+  int64_t nrows = 0;
+  const double *dinv = nullptr;
+  const float *R = nullptr;
+  int64_t ldr = 0;
+  const int32_t *qptr = nullptr;
+  const int32_t *qidx = nullptr;
+  const float *Q = nullptr;
+  int64_t ldq = 0;
+  const double *Ee = nullptr;
+  int64_t lde = 0;
+  float c1 = 1.f;
+  const float *Yk = nullptr;
+  int64_t ldyk = 0;
+  float c2 = 0.f;
+  const float *Yp = nullptr;
+  int64_t ldyp = 0;
+  float c3 = 0.f;
+  float *Out = nullptr;
+  int64_t ldo = 0;
+};
+
+// As launch_cell_gemm; Hv is [E][NPAD][NPAD] float (bf16 = false) or __bf16 (bf16 = true).
+hipError_t launch_cell_gemm_lp(hipStream_t s, bool bf16, const void *Hv, const int32_t *dofp,
+                               const uint8_t *flagp, const int32_t *cells, int ncells,
+                               const float *X, int64_t ldx, float *Y, int64_t ldy, int N,
+                               const CellFinishF &f);
+// As launch_enr_part with FP32 blocks and vectors (rs stays FP64).
+hipError_t launch_enr_part_f32(hipStream_t s, const float *HT, const float *MT,
+                               const int64_t *toff, const int32_t *tld, const int64_t *eptr,
+                               const int32_t *dofp, const int32_t *cells, int ncells,
+                               const float *X, int64_t ldx, float cH, const float *R,
+                               int64_t ldr, const double *rs, float cM, float *P, int64_t ldp,
+                               int N);
+// As launch_enr_q with FP32 blocks; U rows FP32, V rows FP64.
+hipError_t launch_enr_q_f32(hipStream_t s, const float *Hec, const float *Mec,
+                            const int64_t *eptr, const int32_t *eidx, const int32_t *cells,
+                            int ncells, int kmax, const float *U, int64_t ldu, float cU,
+                            const double *V, int64_t ldv, float cV, float *Q, int64_t ldq, int N);
+// out[al,:] (FP64) = sum_{k in list(al)} P[k,:] + sum_be Dn[al,be] Zd[be,:]   (P, Zd FP32)
+hipError_t launch_enr_reduce_f32(hipStream_t s, int n_e, const int64_t *aptr,
+                                 const int32_t *alist, const float *P, int64_t ldp,
+                                 const double *Dn, const float *Zd, int64_t ldzd, double *out,
+                                 int64_t ldo, int N);
+hipError_t launch_epilogue_f32(hipStream_t s, const EpiArgsF &g);
+// Conversions: flat arrays and row blocks ([rows][ld], N columns).
+hipError_t launch_to_f32(hipStream_t s, int64_t n, const double *x, float *y);
+hipError_t launch_to_bf16(hipStream_t s, int64_t n, const double *x, void *y);
+hipError_t launch_block_d2f(hipStream_t s, int64_t rows, int N, const double *X, int64_t ldx,
+                            float *Y, int64_t ldy);
+hipError_t launch_block_f2d(hipStream_t s, int64_t rows, int N, const float *X, int64_t ldx,
+                            double *Y, int64_t ldy);
+
 // ---- dense kernels (cf_dense.hip)
 // Gram modes: GRAM_SYM  full product, result symmetrised (G + G^T)/2
 //             GRAM_UPPER upper tiles only (A = B), mirrored

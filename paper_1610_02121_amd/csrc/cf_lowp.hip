@@ -1,0 +1,468 @@
+// Reduced-precision operator kernels for the filter's matrix products (FP32
+// vectors; cell products on FP32 MFMA, or BF16 inputs with FP32 accumulation;
+// coupling products on FP32 MFMA).  The enrichment reductions accumulate in
+// FP64 and the Schur-complement solve stays FP64 (cf_ops.hip).  Structure,
+// flags and data layouts follow the FP64 kernels of cf_ops.hip.
+//
+// MFMA fragment layouts (wave of 64 lanes, l = lane):
+//   v_mfma_f32_16x16x4f32:   A[l%16][l/16], B[l/16][l%16], D[4(l/16)+r][l%16]
+//   v_mfma_f32_16x16x32_bf16: A[l%16][8(l/16)+i], B[8(l/16)+i][l%16] (i < 8),
+//                             D[4(l/16)+r][l%16]
+#include "cf_kernels.h"
+
+namespace cf {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ f4 mfma_f32(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4 mfma_bf16(bf8 a, bf8 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4 f4zero() { f4 z = {0.f, 0.f, 0.f, 0.f}; return z; }
+
+// ---------------------------------------------------------------------------
+// Cell products, FP32 vectors (same algorithm as k_cell_gemm):
+//   BF16 = false: cell matrices FP32, v_mfma_f32_16x16x4f32, 32 k-steps
+//   BF16 = true:  cell matrices BF16 (row-major), the gathered tile is converted
+//                 to BF16 in LDS (stored column-major so that a lane's 8
+//                 consecutive k values are contiguous), v_mfma_f32_16x16x32_bf16,
+//                 4 k-steps
+// ---------------------------------------------------------------------------
+template <bool BF16>
+__global__ __launch_bounds__(512, 2) void k_cell_gemm_lp(
+    const void *__restrict__ Hv, const int32_t *__restrict__ dofp,
+    const uint8_t *__restrict__ flagp, const int32_t *__restrict__ cells,
+    const float *__restrict__ X, int64_t ldx, float *__restrict__ Y, int64_t ldy, int N,
+    const CellFinishF f) {
+  constexpr int NT = CELL_NT;
+  constexpr int LDX = NT + 16;               // FP32 tile, row-major [k][col]
+  constexpr int LDT = NPAD + 8;              // BF16 tile, column-major [col][k]
+  constexpr int PF = NPAD * NT / 512;
+  constexpr int RPP = 512 / NT;
+  __shared__ float xs[BF16 ? 1 : NPAD * LDX];
+  __shared__ __bf16 xt[BF16 ? NT * LDT : 8];
+  __shared__ float xk_tile[BF16 ? NPAD * NT : 1];   // FP32 copy for the finishing step
+  __shared__ int32_t sdof[NPAD];
+  __shared__ uint8_t sflag[NPAD];
+
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int li = lane & 15, kq = lane >> 4;
+  const int cell = cells[blockIdx.x];
+  if (tid < NPAD) {
+    sdof[tid] = dofp[(int64_t)cell * NPAD + tid];
+    sflag[tid] = flagp[(int64_t)cell * NPAD + tid];
+  }
+  float a32[BF16 ? 1 : 32];
+  bf8 a16[BF16 ? 4 : 1];
+  if constexpr (BF16) {
+    const __bf16 *Hc = (const __bf16 *)Hv + (int64_t)cell * NPAD * NPAD;
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks)
+      a16[ks] = *(const bf8 *)(Hc + (16 * w + li) * NPAD + 32 * ks + 8 * kq);
+  } else {
+    const float *Hc = (const float *)Hv + (int64_t)cell * NPAD * NPAD;
+#pragma unroll
+    for (int ks = 0; ks < 32; ++ks) a32[ks] = Hc[(4 * ks + kq) * NPAD + 16 * w + li];
+  }
+  __syncthreads();
+
+  const int gj = tid % NT, gr = tid / NT;
+  int gd[PF];
+#pragma unroll
+  for (int p = 0; p < PF; ++p) gd[p] = sdof[gr + p * RPP];
+  float pf[PF];
+#pragma unroll
+  for (int p = 0; p < PF; ++p) pf[p] = (gd[p] >= 0 && gj < N) ? X[(int64_t)gd[p] * ldx + gj] : 0.f;
+  const bool finish = f.Out != nullptr;
+  int od[4];
+  bool ofirst[4], ofin[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int row = 16 * w + 4 * kq + r;
+    od[r] = sdof[row];
+    ofirst[r] = (sflag[row] & CELL_FIRST) != 0;
+    ofin[r] = finish && od[r] >= 0 && (sflag[row] & CELL_FINISH) != 0;
+  }
+
+  for (int c0 = 0; c0 < N; c0 += NT) {
+    const int ncol = min(NT, N - c0);
+#pragma unroll
+    for (int p = 0; p < PF; ++p) {
+      const int row = gr + p * RPP;
+      if constexpr (BF16) {
+        xt[gj * LDT + row] = (__bf16)pf[p];
+        xk_tile[row * NT + gj] = pf[p];
+      } else {
+        xs[row * LDX + gj] = pf[p];
+      }
+    }
+    __syncthreads();
+    const int c1 = c0 + NT;
+    if (c1 < N) {
+#pragma unroll
+      for (int p = 0; p < PF; ++p)
+        pf[p] = (gd[p] >= 0 && c1 + gj < N) ? X[(int64_t)gd[p] * ldx + c1 + gj] : 0.f;
+    }
+    const bool cv = li < ncol;
+    float yo[4], yp[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      yo[r] = (od[r] >= 0 && !ofirst[r] && cv) ? Y[(int64_t)od[r] * ldy + c0 + li] : 0.f;
+      yp[r] = (ofin[r] && f.Yp && cv) ? f.Yp[(int64_t)od[r] * f.ldyp + c0 + li] : 0.f;
+    }
+    f4 acc = f4zero();
+    if constexpr (BF16) {
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks)
+        acc = mfma_bf16(a16[ks], *(const bf8 *)(xt + li * LDT + 32 * ks + 8 * kq), acc);
+    } else {
+#pragma unroll
+      for (int ks = 0; ks < 32; ++ks) acc = mfma_f32(a32[ks], xs[(4 * ks + kq) * LDX + li], acc);
+    }
+    if (cv) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        if (od[r] < 0) continue;
+        const float v = acc[r] + yo[r];
+        if (ofin[r]) {
+          const int row = 16 * w + 4 * kq + r;
+          float xk;
+          if constexpr (BF16) xk = xk_tile[row * NT + li];
+          else xk = xs[row * LDX + li];
+          f.Out[(int64_t)od[r] * f.ldo + c0 + li] =
+              f.c1 * (float)f.dinv[od[r]] * v + f.c2 * xk + f.c3 * yp[r];
+        } else {
+          Y[(int64_t)od[r] * ldy + c0 + li] = v;
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_cell_gemm_lp(hipStream_t s, bool bf16, const void *Hv, const int32_t *dofp,
+                               const uint8_t *flagp, const int32_t *cells, int ncells,
+                               const float *X, int64_t ldx, float *Y, int64_t ldy, int N,
+                               const CellFinishF &f) {
+  if (ncells <= 0 || N <= 0) return hipSuccess;
+  if (bf16)
+    hipLaunchKernelGGL(k_cell_gemm_lp<true>, dim3(ncells), dim3(512), 0, s, Hv, dofp, flagp, cells,
+                       X, ldx, Y, ldy, N, f);
+  else
+    hipLaunchKernelGGL(k_cell_gemm_lp<false>, dim3(ncells), dim3(512), 0, s, Hv, dofp, flagp, cells,
+                       X, ldx, Y, ldy, N, f);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Coupling partials, FP32 (as k_enr_part; FP32 blocks HT, MT).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_enr_part_f32(
+    const float *__restrict__ HT, const float *__restrict__ MT,
+    const int64_t *__restrict__ toff, const int32_t *__restrict__ tld,
+    const int64_t *__restrict__ eptr, const int32_t *__restrict__ dofp,
+    const int32_t *__restrict__ cells, const float *__restrict__ X, int64_t ldx, float cH,
+    const float *__restrict__ R, int64_t ldr, const double *__restrict__ rs, float cM,
+    float *__restrict__ P, int64_t ldp, int N) {
+  constexpr int PT = 16, LDX = 32;
+  constexpr int PF = NPAD * PT / 256;
+  constexpr int RPP = 256 / PT;
+  __shared__ float xs[NPAD * LDX];
+  __shared__ float rsm[NPAD * LDX];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int li = lane & 15, kq = lane >> 4;
+  const int cell = cells[blockIdx.x];
+  const int gj = tid % PT, gr = tid / PT;
+  int gd[PF];
+  float gsc[PF];
+#pragma unroll
+  for (int p = 0; p < PF; ++p) {
+    gd[p] = dofp[(int64_t)cell * NPAD + gr + p * RPP];
+    gsc[p] = (rs && gd[p] >= 0) ? (float)rs[gd[p]] : 1.f;
+  }
+  float px[PF], pr[PF];
+#pragma unroll
+  for (int p = 0; p < PF; ++p) {
+    const bool v = gd[p] >= 0 && gj < N;
+    px[p] = (X && v) ? X[(int64_t)gd[p] * ldx + gj] : 0.f;
+    pr[p] = (R && v) ? R[(int64_t)gd[p] * ldr + gj] * gsc[p] : 0.f;
+  }
+  const int64_t k0 = eptr[cell];
+  const int na = (int)(eptr[cell + 1] - k0);
+  const int nap = tld[cell];
+  const int nmb = nap >> 4;
+  const float *ht = X ? HT + toff[cell] : nullptr;
+  const float *mt = R ? MT + toff[cell] : nullptr;
+  for (int c0 = 0; c0 < N; c0 += PT) {
+    const int ncol = min(PT, N - c0);
+#pragma unroll
+    for (int p = 0; p < PF; ++p) {
+      xs[(gr + p * RPP) * LDX + gj] = px[p];
+      rsm[(gr + p * RPP) * LDX + gj] = pr[p];
+    }
+    __syncthreads();
+    const int c1 = c0 + PT;
+    if (c1 < N) {
+#pragma unroll
+      for (int p = 0; p < PF; ++p) {
+        const bool v = gd[p] >= 0 && c1 + gj < N;
+        px[p] = (X && v) ? X[(int64_t)gd[p] * ldx + c1 + gj] : 0.f;
+        pr[p] = (R && v) ? R[(int64_t)gd[p] * ldr + c1 + gj] * gsc[p] : 0.f;
+      }
+    }
+    for (int mb = w; mb < nmb; mb += 4) {
+      f4 accH = f4zero(), accM = f4zero();
+      if (ht) {
+#pragma unroll 8
+        for (int ks = 0; ks < 32; ++ks)
+          accH = mfma_f32(ht[(int64_t)(4 * ks + kq) * nap + 16 * mb + li],
+                          xs[(4 * ks + kq) * LDX + li], accH);
+      }
+      if (mt) {
+#pragma unroll 8
+        for (int ks = 0; ks < 32; ++ks)
+          accM = mfma_f32(mt[(int64_t)(4 * ks + kq) * nap + 16 * mb + li],
+                          rsm[(4 * ks + kq) * LDX + li], accM);
+      }
+      if (li < ncol) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int orow = 16 * mb + 4 * kq + r;
+          if (orow < na) P[(k0 + orow) * ldp + c0 + li] = cH * accH[r] + cM * accM[r];
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_enr_part_f32(hipStream_t s, const float *HT, const float *MT,
+                               const int64_t *toff, const int32_t *tld, const int64_t *eptr,
+                               const int32_t *dofp, const int32_t *cells, int ncells,
+                               const float *X, int64_t ldx, float cH, const float *R,
+                               int64_t ldr, const double *rs, float cM, float *P, int64_t ldp,
+                               int N) {
+  if (ncells <= 0 || N <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_enr_part_f32, dim3(ncells), dim3(256), 0, s, HT, MT, toff, tld, eptr, dofp,
+                     cells, X, ldx, cH, R, ldr, rs, cM, P, ldp, N);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Transposed coupling products, FP32 (as k_enr_q): U rows FP32, V rows FP64
+// (the Schur-solve output), products in FP32.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_enr_q_f32(
+    const float *__restrict__ Hec, const float *__restrict__ Mec,
+    const int64_t *__restrict__ eptr, const int32_t *__restrict__ eidx,
+    const int32_t *__restrict__ cells, const float *__restrict__ U, int64_t ldu, float cU,
+    const double *__restrict__ V, int64_t ldv, float cV, float *__restrict__ Q, int64_t ldq,
+    int N) {
+  extern __shared__ float zsf[];
+  constexpr int PT = 16, LDZ = 16;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int li = lane & 15, kq = lane >> 4;
+  const int cell = cells[blockIdx.x];
+  const int64_t k0 = eptr[cell];
+  const int na = (int)(eptr[cell + 1] - k0);
+  const int K4 = (na + 3) & ~3;
+  const int nks = K4 / 4;
+  float *qb = Q + ((int64_t)blockIdx.x * NPAD) * ldq;
+  for (int c0 = 0; c0 < N; c0 += PT) {
+    const int ncol = min(PT, N - c0);
+    for (int idx = tid; idx < K4 * PT; idx += 256) {
+      const int k = idx / PT, j = idx % PT;
+      const bool v = k < na && j < ncol;
+      const int64_t al = v ? eidx[k0 + k] : 0;
+      zsf[k * LDZ + j] = (U && v) ? cU * U[al * ldu + c0 + j] : 0.f;
+      zsf[(K4 + k) * LDZ + j] = (V && v) ? cV * (float)V[al * ldv + c0 + j] : 0.f;
+    }
+    __syncthreads();
+    f4 acc0 = f4zero(), acc1 = f4zero();
+    if (U) {
+      for (int ks = 0; ks < nks; ++ks) {
+        const int k = 4 * ks + kq;
+        const float *row = Hec + (k0 + min(k, na - 1)) * NPAD + 32 * w;
+        const float a0 = k < na ? row[li] : 0.f, a1 = k < na ? row[16 + li] : 0.f;
+        const float b = zsf[k * LDZ + li];
+        acc0 = mfma_f32(a0, b, acc0);
+        acc1 = mfma_f32(a1, b, acc1);
+      }
+    }
+    if (V) {
+      for (int ks = 0; ks < nks; ++ks) {
+        const int k = 4 * ks + kq;
+        const float *row = Mec + (k0 + min(k, na - 1)) * NPAD + 32 * w;
+        const float a0 = k < na ? row[li] : 0.f, a1 = k < na ? row[16 + li] : 0.f;
+        const float b = zsf[(K4 + k) * LDZ + li];
+        acc0 = mfma_f32(a0, b, acc0);
+        acc1 = mfma_f32(a1, b, acc1);
+      }
+    }
+    if (li < ncol) {
+      float *q = qb + c0 + li;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        q[(int64_t)(32 * w + 4 * kq + r) * ldq] = acc0[r];
+        q[(int64_t)(32 * w + 16 + 4 * kq + r) * ldq] = acc1[r];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_enr_q_f32(hipStream_t s, const float *Hec, const float *Mec,
+                            const int64_t *eptr, const int32_t *eidx, const int32_t *cells,
+                            int ncells, int kmax, const float *U, int64_t ldu, float cU,
+                            const double *V, int64_t ldv, float cV, float *Q, int64_t ldq, int N) {
+  if (ncells <= 0 || N <= 0) return hipSuccess;
+  const size_t shm = (size_t)2 * ((kmax + 3) & ~3) * 16 * sizeof(float);
+  static size_t shm_set = 0;
+  if (shm > 65536 && shm > shm_set) {
+    hipError_t e = hipFuncSetAttribute((const void *)k_enr_q_f32,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    if (e != hipSuccess) return e;
+    shm_set = shm;
+  }
+  hipLaunchKernelGGL(k_enr_q_f32, dim3(ncells), dim3(256), shm, s, Hec, Mec, eptr, eidx, cells, U,
+                     ldu, cU, V, ldv, cV, Q, ldq, N);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Enrichment rows from FP32 partials, accumulated in FP64:
+//   out[al,:] = sum_{k in list(al)} P[k,:] + sum_be Dn[al,be] Zd[be,:]     (Zd FP32)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_enr_reduce_f32(
+    int n_e, const int64_t *__restrict__ aptr, const int32_t *__restrict__ alist,
+    const float *__restrict__ P, int64_t ldp, const double *__restrict__ Dn,
+    const float *__restrict__ Zd, int64_t ldzd, double *__restrict__ out, int64_t ldo, int N) {
+  const int col = blockIdx.x * 64 + threadIdx.x;
+  const int al = blockIdx.y;
+  if (col >= N) return;
+  double acc = 0.0;
+  for (int64_t k = aptr[al]; k < aptr[al + 1]; ++k) acc += (double)P[(int64_t)alist[k] * ldp + col];
+  const double *drow = Dn + (int64_t)al * n_e;
+  double sd = 0.0;
+  for (int be = 0; be < n_e; ++be) sd += drow[be] * (double)Zd[(int64_t)be * ldzd + col];
+  out[(int64_t)al * ldo + col] = acc + sd;
+}
+
+hipError_t launch_enr_reduce_f32(hipStream_t s, int n_e, const int64_t *aptr,
+                                 const int32_t *alist, const float *P, int64_t ldp,
+                                 const double *Dn, const float *Zd, int64_t ldzd, double *out,
+                                 int64_t ldo, int N) {
+  if (n_e <= 0 || N <= 0) return hipSuccess;
+  dim3 grid((N + 63) / 64, n_e);
+  hipLaunchKernelGGL(k_enr_reduce_f32, grid, dim3(64), 0, s, n_e, aptr, alist, P, ldp, Dn, Zd, ldzd,
+                     out, ldo, N);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Epilogue, FP32 blocks (as k_epilogue): rows = listed classical rows, then the
+// enrichment rows (Ee FP64, converted).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_epilogue_f32(const EpiArgsF g) {
+  const int64_t ncls = g.rows ? g.nrows : g.n_h;
+  const int64_t nt = ncls + g.n_e;
+  for (int64_t t = (int64_t)blockIdx.x * 4 + threadIdx.y; t < nt; t += (int64_t)gridDim.x * 4) {
+    const bool cls = t < ncls;
+    const int64_t i = cls ? (g.rows ? (int64_t)g.rows[t] : t) : g.n_h + (t - ncls);
+    float dr = 1.f;
+    int p0 = 0, p1 = 0;
+    if (cls) {
+      if (g.dinv) dr = (float)g.dinv[i];
+      if (g.qptr) { p0 = g.qptr[i]; p1 = g.qptr[i + 1]; }
+    }
+    for (int j = threadIdx.x; j < g.N; j += 64) {
+      float v;
+      if (cls) {
+        float s = g.R[i * g.ldr + j];
+        for (int p = p0; p < p1; ++p) s += g.Q[(int64_t)g.qidx[p] * g.ldq + j];
+        v = dr * s;
+      } else {
+        v = (float)g.Ee[(i - g.n_h) * g.lde + j];
+      }
+      v *= g.c1;
+      if (g.Yk) v += g.c2 * g.Yk[i * g.ldyk + j];
+      if (g.Yp) v += g.c3 * g.Yp[i * g.ldyp + j];
+      g.Out[i * g.ldo + j] = v;
+    }
+  }
+}
+
+hipError_t launch_epilogue_f32(hipStream_t s, const EpiArgsF &g) {
+  const int64_t n = (g.rows ? g.nrows : g.n_h) + g.n_e;
+  if (n <= 0 || g.N <= 0) return hipSuccess;
+  int64_t blocks = (n + 3) / 4;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_epilogue_f32, dim3((unsigned)blocks), dim3(64, 4), 0, s, g);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Conversions
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_to_f32(int64_t n, const double *__restrict__ x,
+                                                float *__restrict__ y) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    y[i] = (float)x[i];
+}
+// FP64 -> BF16 with one rounding (to nearest, ties to even) on the FP64 bits:
+// the significand is cut to BF16's 8 bits, after which the value is exact in
+// FP32 and in BF16 (finite values in BF16's normal range).
+__global__ __launch_bounds__(256) void k_to_bf16(int64_t n, const double *__restrict__ x,
+                                                 __bf16 *__restrict__ y) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    uint64_t b = (uint64_t)__double_as_longlong(x[i]);
+    b += ((uint64_t)1 << 44) - 1 + ((b >> 45) & 1);
+    b &= ~(((uint64_t)1 << 45) - 1);
+    y[i] = (__bf16)(float)__longlong_as_double((long long)b);
+  }
+}
+// Y (type To) [rows][ldy] <- X (type Ti) [rows][ldx], N columns
+template <typename Ti, typename To>
+__global__ __launch_bounds__(256) void k_block_convert(int64_t rows, int N, const Ti *__restrict__ X,
+                                                       int64_t ldx, To *__restrict__ Y, int64_t ldy) {
+  for (int64_t i = (int64_t)blockIdx.x * 4 + threadIdx.y; i < rows; i += (int64_t)gridDim.x * 4)
+    for (int j = threadIdx.x; j < N; j += 64) Y[i * ldy + j] = (To)X[i * ldx + j];
+}
+
+hipError_t launch_to_f32(hipStream_t s, int64_t n, const double *x, float *y) {
+  if (n <= 0) return hipSuccess;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_to_f32, dim3((unsigned)blocks), dim3(256), 0, s, n, x, y);
+  return hipGetLastError();
+}
+hipError_t launch_to_bf16(hipStream_t s, int64_t n, const double *x, void *y) {
+  if (n <= 0) return hipSuccess;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)blocks), dim3(256), 0, s, n, x, (__bf16 *)y);
+  return hipGetLastError();
+}
+hipError_t launch_block_d2f(hipStream_t s, int64_t rows, int N, const double *X, int64_t ldx,
+                            float *Y, int64_t ldy) {
+  if (rows <= 0 || N <= 0) return hipSuccess;
+  int64_t blocks = (rows + 3) / 4;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL((k_block_convert<double, float>), dim3((unsigned)blocks), dim3(64, 4), 0, s, rows,
+                     N, X, ldx, Y, ldy);
+  return hipGetLastError();
+}
+hipError_t launch_block_f2d(hipStream_t s, int64_t rows, int N, const float *X, int64_t ldx,
+                            double *Y, int64_t ldy) {
+  if (rows <= 0 || N <= 0) return hipSuccess;
+  int64_t blocks = (rows + 3) / 4;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL((k_block_convert<float, double>), dim3((unsigned)blocks), dim3(64, 4), 0, s, rows,
+                     N, X, ldx, Y, ldy);
+  return hipGetLastError();
+}
+
+}  // namespace cf

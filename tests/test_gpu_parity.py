@@ -223,7 +223,7 @@ def test_invalid_arguments(si_small):
     with pytest.raises(ChebFilterError, match="CF_EINVAL"):
         ctx.filter(X, 2, 0.0, 1.0, Y=X)
     with pytest.raises(ChebFilterError, match="CF_EINVAL"):
-        ctx.filter(X, 2, 0.0, 1.0, prec="bf16")
+        ctx.filter(X, 2, 0.0, 1.0, prec=7)
     big = dev(np.ones((ops.n, ctx.max_cols + 1)))
     with pytest.raises(ChebFilterError, match="CF_ENOMEM"):
         ctx.apply_H(big)

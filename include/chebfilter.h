@@ -114,8 +114,15 @@ cf_status chebfilter_apply_Sinv(cf_ctx *ctx, const double *X, int64_t ldx, doubl
  *   CF_FP32  recurrence blocks, elemental and coupling products in FP32 (FP32
  *            MFMA); enrichment-row sums, the Schur-complement solve and its
  *            output in FP64; X is rounded to FP32 on entry, Y widened to FP64;
- *   CF_BF16  as CF_FP32, but the elemental products take the cell matrices and
- *            the gathered vector tiles in BF16 (FP32 accumulation).
+ *   CF_BF16  as CF_FP32, but the elemental products of the cells with no DOF
+ *            in the enriched region take the cell matrices and the gathered
+ *            vector tiles in BF16 (FP32 accumulation); cells touching that
+ *            region stay FP32, because BF16 rounding there excites the
+ *            near-null space of M^E, which (M^E)^-1 amplifies.
+ * The reduced forms hold their iterates scaled by powers of two chosen on the
+ * device from the growth of the last two iterates, and return the unscaled
+ * T_m(t(H~)) X in FP64 (bit for bit the unscaled FP32 recurrence wherever that
+ * one stays inside FP32's normal range).
  * The reduced forms keep FP32 copies of the operator (and BF16 cell matrices)
  * on the device from their first use until chebfilter_destroy, plus two FP32
  * blocks of n x max_cols.  Their results carry FP32 (or BF16) rounding: they

@@ -85,6 +85,16 @@ struct cf_ctx {
   void *Hp16 = nullptr;
   float *HT32 = nullptr, *MT32 = nullptr, *Hec32 = nullptr, *Mec32 = nullptr;
   float *F0 = nullptr, *F1 = nullptr, *R32 = nullptr, *P32 = nullptr, *Q32 = nullptr;
+  // step scaling of the reduced recurrence: max slots, exponents, multipliers
+  unsigned *lp_mx = nullptr;
+  int32_t *lp_s = nullptr;
+  float *lp_mult = nullptr;
+  int lp_cap = 0;
+  // cells of each colour reordered: those sharing a DOF with an enriched cell
+  // first (near_cnt[k] of them), then the rest; the BF16 form keeps the near
+  // ones in FP32
+  int32_t *cells_split = nullptr;
+  std::vector<int> near_cnt;
   rocblas_handle rb = nullptr;
   std::string err;
   bool profiling = false;
@@ -330,10 +340,21 @@ static cf_status ensure_lowp(cf_ctx *c, bool bf16) {
     c->Hp16 = h;
     HIPCHK(c, launch_to_bf16(c->stream, hsz, c->Hp, c->Hp16));
   }
-  if (!bf16 && !c->Hp32) {
+  if (!c->Hp32) {   // both forms (the BF16 form for the cells near the enriched region)
     STCHK(dalloc(c, &c->Hp32, (size_t)hsz));
     HIPCHK(c, launch_to_f32(c->stream, hsz, c->Hp, c->Hp32));
   }
+  return CF_OK;
+}
+
+// Scale bookkeeping for a reduced filter of degree m.
+static cf_status ensure_lp_scale(cf_ctx *c, int m) {
+  if (m + 2 <= c->lp_cap) return CF_OK;
+  const int cap = std::max(256, m + 2);
+  STCHK(dalloc(c, &c->lp_mx, (size_t)cap * MX_SLOTS));
+  STCHK(dalloc(c, &c->lp_s, (size_t)cap));
+  STCHK(dalloc(c, &c->lp_mult, (size_t)2 * cap));
+  c->lp_cap = cap;
   return CF_OK;
 }
 
@@ -345,19 +366,30 @@ static cf_status ensure_lowp(cf_ctx *c, bool bf16) {
 // written, by the same thread).
 static cf_status core_htilde_step_lp(cf_ctx *c, bool bf16, const float *Xin, int64_t ldxin, int N,
                                      float c1, float c2, const float *Yp, int64_t ldyp, float c3,
-                                     float *Out, int64_t ldo) {
+                                     float *Out, int64_t ldo, const float *mult, unsigned *mx) {
   const int64_t mc = c->max_cols;
   CellFinishF f;
   f.dinv = c->dinv;
   f.c1 = c1; f.c2 = c2; f.c3 = Yp ? c3 : 0.f;
   f.Yp = Yp; f.ldyp = ldyp;
   f.Out = Out; f.ldo = ldo;
-  const void *Hv = bf16 ? c->Hp16 : (const void *)c->Hp32;
+  f.mult = mult; f.mx = mx;
+  const double fl = 2.0 * c->npc * c->npc * (double)N;
   for (size_t k = 0; k + 1 < c->col_off.size(); ++k) {
-    Scope sc(c, bf16 ? "cell_gemm_bf16" : "cell_gemm_fp32",
-             2.0 * c->npc * c->npc * (double)N * (c->col_off[k + 1] - c->col_off[k]));
-    HIPCHK(c, launch_cell_gemm_lp(c->stream, bf16, Hv, c->dofp, c->flagp, c->cells + c->col_off[k],
-                                  c->col_off[k + 1] - c->col_off[k], Xin, ldxin, c->R32, mc, N, f));
+    const int c0 = c->col_off[k], cnt = c->col_off[k + 1] - c0;
+    // cells of one colour share no DOF, so the colour may go in two launches
+    const int nfp = bf16 ? c->near_cnt[k] : cnt;
+    if (nfp > 0) {
+      Scope sc(c, "cell_gemm_fp32", fl * nfp);
+      HIPCHK(c, launch_cell_gemm_lp(c->stream, false, c->Hp32, c->dofp, c->flagp,
+                                    c->cells_split + c0, nfp, Xin, ldxin, c->R32, mc, N, f));
+    }
+    if (cnt - nfp > 0) {
+      Scope sc(c, "cell_gemm_bf16", fl * (cnt - nfp));
+      HIPCHK(c, launch_cell_gemm_lp(c->stream, true, c->Hp16, c->dofp, c->flagp,
+                                    c->cells_split + c0 + nfp, cnt - nfp, Xin, ldxin, c->R32, mc, N,
+                                    f));
+    }
   }
   const float *Xe = Xin + c->n_h * ldxin;
   if (c->n_e > 0) {
@@ -390,6 +422,7 @@ static cf_status core_htilde_step_lp(cf_ctx *c, bool bf16, const float *Xin, int
   g.c1 = c1; g.Yk = Xin; g.ldyk = ldxin; g.c2 = c2;
   g.Yp = Yp; g.ldyp = ldyp; g.c3 = Yp ? c3 : 0.f;
   g.Out = Out; g.ldo = ldo;
+  g.mult = mult; g.mx = mx;
   Scope sc(c, "epilogue");
   HIPCHK(c, launch_epilogue_f32(c->stream, g));
   return CF_OK;
@@ -944,6 +977,27 @@ static cf_status do_init(const cf_problem *pr, const cf_options *opt, cf_ctx *c)
       else flag[last_slot[d]] |= CELL_FINISH;
     }
     HIPCHK(c, hipMemcpy(c->flagp, flag.data(), flag.size(), hipMemcpyHostToDevice));
+    // per colour: cells with a DOF in the enriched region first
+    std::vector<int32_t> split;
+    split.reserve(order.size());
+    c->near_cnt.assign(c->col_off.size() - 1, 0);
+    for (size_t k = 0; k + 1 < c->col_off.size(); ++k) {
+      std::vector<int32_t> far;
+      for (int q = c->col_off[k]; q < c->col_off[k + 1]; ++q) {
+        const int32_t e = order[q];
+        bool near = false;
+        for (int a = 0; a < npc && !near; ++a) {
+          const int32_t d = dof[(int64_t)e * NPAD + a];
+          near = d >= 0 && inreg[d];
+        }
+        if (near) { split.push_back(e); ++c->near_cnt[k]; }
+        else far.push_back(e);
+      }
+      split.insert(split.end(), far.begin(), far.end());
+    }
+    STCHK(dalloc(c, &c->cells_split, split.size()));
+    HIPCHK(c, hipMemcpy(c->cells_split, split.data(), split.size() * sizeof(int32_t),
+                        hipMemcpyHostToDevice));
     c->nregrows = (int64_t)rows.size();
     STCHK(dalloc(c, &c->regrows, std::max<size_t>(rows.size(), 1)));
     if (!rows.empty())
@@ -1065,16 +1119,27 @@ cf_status chebfilter_filter(cf_ctx *c, const double *X, int64_t ldx, double *Y, 
   if (prec != CF_FP64) {
     // FP32 recurrence: Y_k lives in F0 (k even) or F1 (k odd); Y_{k+1}
     // overwrites Y_{k-1} element by element
+    // The iterates are held as Z_k = Y_k 2^-s_k with s_k chosen on the device
+    // from the growth of the last two iterates (powers of two: every rounding
+    // is that of the unscaled recurrence, which would leave FP32's range at
+    // high degree or wide damping intervals); Y = Z_m 2^s_m is formed in FP64.
     const bool bf16 = prec == CF_BF16;
     STCHK(ensure_lowp(c, bf16));
+    STCHK(ensure_lp_scale(c, m));
     const int64_t mc = c->max_cols;
     float *F[2] = {c->F0, c->F1};
-    HIPCHK(c, launch_block_d2f(c->stream, c->n, n, X, ldx, c->F0, mc));
-    STCHK(core_htilde_step_lp(c, bf16, F[0], mc, n, (float)e, (float)-cc, nullptr, 0, 0.f, F[1], mc));
-    for (int k = 1; k < m; ++k)
+    HIPCHK(c, launch_lp_reset(c->stream, c->lp_mx, (m + 2) * MX_SLOTS));
+    HIPCHK(c, launch_lp_input(c->stream, c->n, n, X, ldx, c->F0, mc, c->lp_mx));
+    HIPCHK(c, launch_lp_scale(c->stream, 0, c->lp_mx, c->lp_s, c->lp_mult));
+    STCHK(core_htilde_step_lp(c, bf16, F[0], mc, n, (float)e, (float)-cc, nullptr, 0, 0.f, F[1], mc,
+                              c->lp_mult, c->lp_mx + MX_SLOTS));
+    for (int k = 1; k < m; ++k) {
+      HIPCHK(c, launch_lp_scale(c->stream, k, c->lp_mx, c->lp_s, c->lp_mult));
       STCHK(core_htilde_step_lp(c, bf16, F[k & 1], mc, n, (float)(2.0 * e), (float)(-2.0 * cc),
-                                F[(k - 1) & 1], mc, -1.f, F[(k + 1) & 1], mc));
-    HIPCHK(c, launch_block_f2d(c->stream, c->n, n, F[m & 1], mc, Y, ldy));
+                                F[(k - 1) & 1], mc, -1.f, F[(k + 1) & 1], mc, c->lp_mult + 2 * k,
+                                c->lp_mx + (k + 1) * MX_SLOTS));
+    }
+    HIPCHK(c, launch_lp_output(c->stream, c->n, n, F[m & 1], mc, c->lp_s + m, Y, ldy));
     return check_out_finite(c, Y, ldy, n, "filter");
   }
   // Y_k lives in Y when (m - k) is even, else in the internal block B2.

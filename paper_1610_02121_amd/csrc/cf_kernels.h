@@ -101,6 +101,13 @@ hipError_t launch_csr_dense(hipStream_t s, int64_t nreg, const int32_t *regrow,
 
 // ---- reduced-precision operator kernels (cf_lowp.hip): FP32 vectors, FP32
 // or BF16 cell matrices, FP32 coupling blocks; enrichment-row sums in FP64.
+constexpr int MX_SLOTS = 64;  // words per iterate for the gathered max |Z_k|
+
+// Step scaling of the reduced recurrence: the iterates are kept as
+// Z_k = Y_k 2^-s_k, so a step multiplies (c1, c2) by mult[0] = 2^(s_k - s_k+1)
+// and c3 by mult[1] = 2^(s_k-1 - s_k+1) (exact: powers of two), and the largest
+// |Z_k+1| is gathered into mx[0..MX_SLOTS) (float bits, atomic max per block
+// into the block's slot) to choose s_k+2.
 struct CellFinishF {
   const double *dinv = nullptr;
   float c1 = 0.f, c2 = 0.f, c3 = 0.f;
@@ -108,6 +115,8 @@ struct CellFinishF {
   int64_t ldyp = 0;
   float *Out = nullptr;             // null: no finishing step
   int64_t ldo = 0;
+  const float *mult = nullptr;      // null: no scaling
+  unsigned *mx = nullptr;           // null: no max gathering
 };
 
 // Recurrence epilogue of the reduced-precision step:
@@ -136,6 +145,8 @@ struct EpiArgsF {
   float c3 = 0.f;
   float *Out = nullptr;
   int64_t ldo = 0;
+  const float *mult = nullptr;      // as in CellFinishF
+  unsigned *mx = nullptr;
 };
 
 // As launch_cell_gemm; Hv is [E][NPAD][NPAD] float (bf16 = false) or __bf16 (bf16 = true).
@@ -168,6 +179,16 @@ hipError_t launch_block_d2f(hipStream_t s, int64_t rows, int N, const double *X,
                             float *Y, int64_t ldy);
 hipError_t launch_block_f2d(hipStream_t s, int64_t rows, int N, const float *X, int64_t ldx,
                             double *Y, int64_t ldy);
+// Scaled recurrence bookkeeping (cf_lowp.hip): reset the max slots mx[0..nslots),
+// convert the input block to FP32 while gathering max|X| into mx[0..MX_SLOTS),
+// choose the scale of step k (max slots of iterate j at mx[j * MX_SLOTS]), and
+// widen Z_m 2^s[m] to FP64.
+hipError_t launch_lp_reset(hipStream_t s, unsigned *mx, int nslots);
+hipError_t launch_lp_input(hipStream_t s, int64_t rows, int N, const double *X, int64_t ldx,
+                           float *Z, int64_t ldz, unsigned *mx0);
+hipError_t launch_lp_scale(hipStream_t s, int k, const unsigned *mx, int32_t *sexp, float *mult);
+hipError_t launch_lp_output(hipStream_t s, int64_t rows, int N, const float *Z, int64_t ldz,
+                            const int32_t *sexp_m, double *Y, int64_t ldy);
 
 // ---- dense kernels (cf_dense.hip)
 // Gram modes: GRAM_SYM  full product, result symmetrised (G + G^T)/2

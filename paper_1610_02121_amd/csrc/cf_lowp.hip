@@ -23,6 +23,29 @@ __device__ __forceinline__ f4 mfma_bf16(bf8 a, bf8 b, f4 c) {
 }
 __device__ __forceinline__ f4 f4zero() { f4 z = {0.f, 0.f, 0.f, 0.f}; return z; }
 
+// max of |v| that keeps NaN (a NaN compares above every finite value and Inf
+// as unsigned float bits)
+__device__ __forceinline__ float absmax(float m, float v) {
+  const float a = fabsf(v);
+  return (a > m || a != a) ? a : m;
+}
+// Block-wide absmax of m, then one atomic max into mx[blockIdx.x % MX_SLOTS]
+// (non-negative floats order like their bit patterns; spreading the blocks
+// over MX_SLOTS words keeps the atomics from queueing on one address).  Every
+// thread of the block must call it; wbuf holds one float per wave.
+__device__ __forceinline__ void gather_max(unsigned *mx, float m, float *wbuf) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) m = absmax(m, __shfl_xor(m, off));
+  const int t = threadIdx.x + blockDim.x * threadIdx.y;
+  const int nw = (blockDim.x * blockDim.y) >> 6;
+  if ((t & 63) == 0) wbuf[t >> 6] = m;
+  __syncthreads();
+  if (t == 0) {
+    for (int i = 1; i < nw; ++i) m = absmax(m, wbuf[i]);
+    atomicMax(mx + (blockIdx.x % MX_SLOTS), __float_as_uint(m));
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Cell products, FP32 vectors (same algorithm as k_cell_gemm):
 //   BF16 = false: cell matrices FP32, v_mfma_f32_16x16x4f32, 32 k-steps
@@ -77,6 +100,12 @@ __global__ __launch_bounds__(512, 2) void k_cell_gemm_lp(
 #pragma unroll
   for (int p = 0; p < PF; ++p) pf[p] = (gd[p] >= 0 && gj < N) ? X[(int64_t)gd[p] * ldx + gj] : 0.f;
   const bool finish = f.Out != nullptr;
+  float fc1 = f.c1, fc2 = f.c2, fc3 = f.c3;
+  if (f.mult) {
+    const float al = f.mult[0], be = f.mult[1];
+    fc1 *= al; fc2 *= al; fc3 *= be;
+  }
+  float omax = 0.f;
   int od[4];
   bool ofirst[4], ofin[4];
 #pragma unroll
@@ -132,8 +161,9 @@ __global__ __launch_bounds__(512, 2) void k_cell_gemm_lp(
           float xk;
           if constexpr (BF16) xk = xk_tile[row * NT + li];
           else xk = xs[row * LDX + li];
-          f.Out[(int64_t)od[r] * f.ldo + c0 + li] =
-              f.c1 * (float)f.dinv[od[r]] * v + f.c2 * xk + f.c3 * yp[r];
+          const float o = fc1 * (float)f.dinv[od[r]] * v + fc2 * xk + fc3 * yp[r];
+          f.Out[(int64_t)od[r] * f.ldo + c0 + li] = o;
+          omax = absmax(omax, o);
         } else {
           Y[(int64_t)od[r] * ldy + c0 + li] = v;
         }
@@ -141,6 +171,7 @@ __global__ __launch_bounds__(512, 2) void k_cell_gemm_lp(
     }
     __syncthreads();
   }
+  if (f.mx) gather_max(f.mx, omax, (float *)sdof);   // sdof is free after the tile loop
 }
 
 hipError_t launch_cell_gemm_lp(hipStream_t s, bool bf16, const void *Hv, const int32_t *dofp,
@@ -369,6 +400,12 @@ hipError_t launch_enr_reduce_f32(hipStream_t s, int n_e, const int64_t *aptr,
 __global__ __launch_bounds__(256) void k_epilogue_f32(const EpiArgsF g) {
   const int64_t ncls = g.rows ? g.nrows : g.n_h;
   const int64_t nt = ncls + g.n_e;
+  float gc1 = g.c1, gc2 = g.c2, gc3 = g.c3;
+  if (g.mult) {
+    const float al = g.mult[0], be = g.mult[1];
+    gc1 *= al; gc2 *= al; gc3 *= be;
+  }
+  float omax = 0.f;
   for (int64_t t = (int64_t)blockIdx.x * 4 + threadIdx.y; t < nt; t += (int64_t)gridDim.x * 4) {
     const bool cls = t < ncls;
     const int64_t i = cls ? (g.rows ? (int64_t)g.rows[t] : t) : g.n_h + (t - ncls);
@@ -387,11 +424,17 @@ __global__ __launch_bounds__(256) void k_epilogue_f32(const EpiArgsF g) {
       } else {
         v = (float)g.Ee[(i - g.n_h) * g.lde + j];
       }
-      v *= g.c1;
-      if (g.Yk) v += g.c2 * g.Yk[i * g.ldyk + j];
-      if (g.Yp) v += g.c3 * g.Yp[i * g.ldyp + j];
+      v *= gc1;
+      if (g.Yk) v += gc2 * g.Yk[i * g.ldyk + j];
+      if (g.Yp) v += gc3 * g.Yp[i * g.ldyp + j];
       g.Out[i * g.ldo + j] = v;
+      omax = absmax(omax, v);
     }
+  }
+  if (g.mx) {
+    // every thread of the block reaches this point (the row loop has no early exit)
+    __shared__ float wbuf[4];
+    gather_max(g.mx, omax, wbuf);
   }
 }
 
@@ -462,6 +505,98 @@ hipError_t launch_block_f2d(hipStream_t s, int64_t rows, int N, const float *X, 
   if (blocks > 65536) blocks = 65536;
   hipLaunchKernelGGL((k_block_convert<float, double>), dim3((unsigned)blocks), dim3(64, 4), 0, s, rows,
                      N, X, ldx, Y, ldy);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Scaled recurrence bookkeeping
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_lp_reset(unsigned *__restrict__ mx, int nslots) {
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < nslots; i += gridDim.x * 256) mx[i] = 0u;
+}
+
+__global__ __launch_bounds__(256) void k_lp_input(int64_t rows, int N, const double *__restrict__ X,
+                                                  int64_t ldx, float *__restrict__ Z, int64_t ldz,
+                                                  unsigned *__restrict__ mx0) {
+  float m = 0.f;
+  for (int64_t i = (int64_t)blockIdx.x * 4 + threadIdx.y; i < rows; i += (int64_t)gridDim.x * 4)
+    for (int j = threadIdx.x; j < N; j += 64) {
+      const float z = (float)X[i * ldx + j];
+      Z[i * ldz + j] = z;
+      m = absmax(m, z);
+    }
+  __shared__ float wbuf[4];
+  gather_max(mx0, m, wbuf);
+}
+
+// Scale of step k (which forms Z_k+1 from Z_k, Z_k-1): the exponent of
+// max|Y_k+1| is predicted from the last two iterates, E_k+1 ~ 2 E_k - E_k-1
+// (Chebyshev growth per step settles to a constant), and s_k+1 is set to it,
+// so that max|Z_k+1| stays near 1; at most 60 binades from s_k.  Step 0 is not
+// scaled.  A zero or non-finite maximum keeps the previous scale.
+__global__ void k_lp_scale(int k, const unsigned *__restrict__ mx, int32_t *__restrict__ sexp,
+                           float *__restrict__ mult) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (k == 0) {
+    sexp[0] = 0;
+    sexp[1] = 0;
+    mult[0] = 1.f;
+    mult[1] = 1.f;
+    return;
+  }
+  const int sk = sexp[k], sp = sexp[k - 1];
+  unsigned uk = 0u, up = 0u;
+  for (int i = 0; i < MX_SLOTS; ++i) {
+    uk = max(uk, mx[k * MX_SLOTS + i]);
+    up = max(up, mx[(k - 1) * MX_SLOTS + i]);
+  }
+  const float mk = __uint_as_float(uk), mp = __uint_as_float(up);
+  int sn = sk;
+  if (mk > 0.f && mp > 0.f && isfinite(mk) && isfinite(mp)) {
+    int ek, ep;
+    (void)frexpf(mk, &ek);
+    (void)frexpf(mp, &ep);
+    const int pred = 2 * (ek + sk) - (ep + sp);
+    sn = min(max(pred, sk - 60), sk + 60);
+  }
+  sexp[k + 1] = sn;
+  mult[2 * k] = ldexpf(1.f, sk - sn);
+  mult[2 * k + 1] = ldexpf(1.f, sp - sn);
+}
+
+__global__ __launch_bounds__(256) void k_lp_output(int64_t rows, int N, const float *__restrict__ Z,
+                                                   int64_t ldz, const int32_t *__restrict__ sexp_m,
+                                                   double *__restrict__ Y, int64_t ldy) {
+  const int sm = *sexp_m;
+  for (int64_t i = (int64_t)blockIdx.x * 4 + threadIdx.y; i < rows; i += (int64_t)gridDim.x * 4)
+    for (int j = threadIdx.x; j < N; j += 64) Y[i * ldy + j] = ldexp((double)Z[i * ldz + j], sm);
+}
+
+hipError_t launch_lp_reset(hipStream_t s, unsigned *mx, int nslots) {
+  if (nslots <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_lp_reset, dim3((nslots + 255) / 256), dim3(256), 0, s, mx, nslots);
+  return hipGetLastError();
+}
+hipError_t launch_lp_input(hipStream_t s, int64_t rows, int N, const double *X, int64_t ldx,
+                           float *Z, int64_t ldz, unsigned *mx0) {
+  if (rows <= 0 || N <= 0) return hipSuccess;
+  int64_t blocks = (rows + 3) / 4;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_lp_input, dim3((unsigned)blocks), dim3(64, 4), 0, s, rows, N, X, ldx, Z, ldz,
+                     mx0);
+  return hipGetLastError();
+}
+hipError_t launch_lp_scale(hipStream_t s, int k, const unsigned *mx, int32_t *sexp, float *mult) {
+  hipLaunchKernelGGL(k_lp_scale, dim3(1), dim3(64), 0, s, k, mx, sexp, mult);
+  return hipGetLastError();
+}
+hipError_t launch_lp_output(hipStream_t s, int64_t rows, int N, const float *Z, int64_t ldz,
+                            const int32_t *sexp_m, double *Y, int64_t ldy) {
+  if (rows <= 0 || N <= 0) return hipSuccess;
+  int64_t blocks = (rows + 3) / 4;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_lp_output, dim3((unsigned)blocks), dim3(64, 4), 0, s, rows, N, Z, ldz, sexp_m,
+                     Y, ldy);
   return hipGetLastError();
 }
 

@@ -16,7 +16,8 @@ Tolerances (u32 = 2^-24, ub = 2^-8 unit roundoffs):
   in BF16, and for CF_BF16 the model H^cc is the device's BF16 rounding of the
   cell matrices (to nearest, ties to even, from FP64), so the bound holds for both
   forms with the FP32 constant: it pins the BF16 operand layout and rounding,
-  not just the magnitude of the error.
+  not just the magnitude of the error.  (The BF16 form takes BF16 products
+  only in cells with no DOF in the enriched region; the model does the same.)
 * All rows, each Chebyshev step k = 1..m: the device's Y_k against the model
   step applied to the device's own Y_{k-1}, Y_{k-2} (outputs of the filters
   of degree k-1 and k-2, which are the same FP32 iterates widened exactly):
@@ -25,6 +26,9 @@ Tolerances (u32 = 2^-24, ub = 2^-8 unit roundoffs):
   Y_{k-1} to BF16 as the device does, so the check stays at FP32 level.
 * All rows, whole filter (CF_FP32): 10 u32 kappa(M^E) per step against the
   FP64 oracle (the FP32 copy of the operator is within that).
+* Wide damping interval, m = 60 (iterates far beyond FP32's range unscaled):
+  the last step against the model, and for CF_FP32 the whole filter against
+  the oracle, with the bounds above.
 * Mixed subspace iteration: reduced-precision filter passes, then FP64
   passes (the cleanup); Ritz values of the wanted set within 1e-6 Ha of the
   eigenvalues of the discrete pencil.
@@ -86,26 +90,68 @@ def kappa_M(ops):
     return lmax / lmin
 
 
-def model_problem(prob, prec):
-    """The problem whose FP64 operator the reduced form approximates to FP32
-    rounding: for CF_BF16 the cell matrices are the device's BF16 values."""
-    if prec == "fp32":
-        return prob
-    P = copy.deepcopy(prob)
-    H = np.asarray(prob.H_cc, dtype=np.float64)
-    P.H_cc = bf16_round(0.5 * (H + H.transpose(0, 2, 1)))
-    return P
-
-
-def outside_rows(prob):
-    """Classical DOFs that belong to no enriched cell."""
+def region_dofs(prob):
+    """Mask of the classical DOFs that belong to an enriched cell."""
     cd = np.asarray(prob.cell_dof)
     ep = np.asarray(prob.enr_ptr)
     enriched = np.nonzero(ep[1:] > ep[:-1])[0]
     inside = np.zeros(prob.n_h, dtype=bool)
     d = cd[enriched].ravel()
     inside[d[d >= 0]] = True
-    return np.nonzero(~inside)[0]
+    return inside
+
+
+def far_cells(prob):
+    """Cells with no DOF in the enriched region: the only cells whose products
+    the BF16 form takes in BF16 (the others stay FP32)."""
+    inside = region_dofs(prob)
+    cd = np.asarray(prob.cell_dof)
+    return np.array([not inside[r[r >= 0]].any() for r in cd])
+
+
+def outside_rows(prob):
+    """Classical DOFs that belong to no enriched cell."""
+    return np.nonzero(~region_dofs(prob))[0]
+
+
+_MODEL = {}
+
+
+class Model:
+    """The FP64 operator the reduced form approximates to FP32 rounding.  For
+    CF_BF16 the far cells' matrices are the device's BF16 values, and the
+    classical rows of the vector enter those cells' products rounded to BF16."""
+
+    def __init__(self, prob, prec):
+        self.prec = prec
+        self.prob = prob
+        self.far = None
+        if prec == "bf16":
+            far = far_cells(prob)
+            H = np.asarray(prob.H_cc, dtype=np.float64)
+            Hs = 0.5 * (H + H.transpose(0, 2, 1))
+            Hm = np.where(far[:, None, None], bf16_round(Hs), Hs)
+            P = copy.deepcopy(prob)
+            P.H_cc = Hm
+            self.prob = P
+            if far.any():
+                F = copy.deepcopy(prob)
+                F.H_cc = np.where(far[:, None, None], Hm, 0.0)
+                self.far = Operators(F).H[:prob.n_h, :prob.n_h].tocsr()
+        self.ops = Operators(self.prob)
+
+    def htilde(self, X):
+        HX = np.asarray(self.ops.H @ X)
+        if self.far is not None:
+            n_h = self.ops.n_h
+            HX[:n_h] += np.asarray(self.far @ (bf16_round(X[:n_h]) - X[:n_h]))
+        return self.ops.block_inverse(HX)
+
+
+def model(name, prob, prec):
+    if (name, prec) not in _MODEL:
+        _MODEL[(name, prec)] = Model(prob, prec)
+    return _MODEL[(name, prec)]
 
 
 def abs_classical_product(prob, X):
@@ -117,7 +163,7 @@ def abs_classical_product(prob, X):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
-@pytest.mark.parametrize("fix", ["hydrogen_small", "si_small"])
+@pytest.mark.parametrize("fix", ["hydrogen_cfg1", "si_small"])
 def test_degree_one_outside_rows(fix, prec, request):
     print(f"[lowp m=1] {fix} {prec}", flush=True)
     prob = request.getfixturevalue(fix)
@@ -127,13 +173,13 @@ def test_degree_one_outside_rows(fix, prec, request):
     a, b = -1.0, 80.0
     e, c = 2.0 / (b - a), (a + b) / (b - a)
     Y = host(ctx.filter(dev(X), 1, a, b, prec=prec))
-    mops = Operators(model_problem(prob, prec))
-    HX = np.asarray(mops.H[:prob.n_h] @ X)
+    mod = model(fix, prob, prec)
+    HX = np.asarray(mod.ops.H[:prob.n_h] @ X)
     dinv = 1.0 / np.asarray(prob.M_cc_diag)
     rows = outside_rows(prob)
     assert rows.size > 0
     y_model = e * dinv[rows, None] * HX[rows] - c * X[rows]
-    absHX = abs_classical_product(model_problem(prob, prec), X)[rows]
+    absHX = abs_classical_product(mod.prob, X)[rows]
     K = 128 + 8
     bound = (e * dinv[rows, None] * (K + 2) * U32 * absHX
              + 4 * U32 * (e * dinv[rows, None] * np.abs(HX[rows]) + np.abs(c * X[rows])))
@@ -141,19 +187,10 @@ def test_degree_one_outside_rows(fix, prec, request):
     print(f"  max err/bound {float((err / bound).max()):.3e}", flush=True)
     assert np.all(err <= bound)
     if prec == "bf16":
-        # the BF16 rounding of H^cc is visible: the unrounded operator is further away
+        # the far cells' BF16 matrices are visible: the unrounded operator is further away
+        assert far_cells(prob).any()
         y64 = e * dinv[rows, None] * np.asarray(ops.H[:prob.n_h] @ X)[rows] - c * X[rows]
         assert np.abs(Y[rows] - y64).max() > 10 * err.max()
-
-
-def model_htilde(mops, X, prec):
-    """H~ of the model problem applied to X as the reduced form sees it: for
-    CF_BF16 the classical part of X enters the cell products rounded to BF16."""
-    HX = np.asarray(mops.H @ X)
-    if prec == "bf16":
-        n_h = mops.n_h
-        HX[:n_h] += np.asarray(mops.H[:n_h, :n_h] @ (bf16_round(X[:n_h]) - X[:n_h]))
-    return mops.block_inverse(HX)
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
@@ -166,7 +203,7 @@ def test_filter_steps(fix, m, prec, request):
     print(f"[lowp filter] {fix} m={m} {prec}", flush=True)
     prob = request.getfixturevalue(fix)
     ctx, ops = context(fix, prob)
-    mops = Operators(model_problem(prob, prec))
+    mod = model(fix, prob, prec)
     v0 = np.random.default_rng(5).standard_normal(ops.n)
     al, be = lanczos(ops.apply_Htilde, ops.apply_M, v0, 10)
     lo, hi = lanczos_bounds(al, be)
@@ -178,9 +215,9 @@ def test_filter_steps(fix, m, prec, request):
     kap = kappa_M(ops)
     for k in range(1, m + 1):
         if k == 1:
-            rhs = e * model_htilde(mops, X, prec) - c * X
+            rhs = e * mod.htilde(X) - c * X
         else:
-            rhs = 2.0 * (e * model_htilde(mops, Ys[k - 1], prec) - c * Ys[k - 1]) - Ys[k - 2]
+            rhs = 2.0 * (e * mod.htilde(Ys[k - 1]) - c * Ys[k - 1]) - Ys[k - 2]
         rel = float(np.abs(Ys[k] - rhs).max() / np.abs(rhs).max())
         print(f"  step {k}: rel err {rel:.3e} tol {10 * U32 * kap:.3e}", flush=True)
         assert rel < 10 * U32 * kap, k
@@ -188,6 +225,42 @@ def test_filter_steps(fix, m, prec, request):
         Yo = recurrence_filter(lambda Z: ops.apply_Htilde(Z), X, m, a, hi)
         rel = float(np.abs(Ys[m] - Yo).max() / np.abs(Yo).max())
         print(f"  whole filter: rel err {rel:.3e}", flush=True)
+        assert rel < 10 * U32 * kap * m
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("fix", ["hydrogen_small", "hydrogen_cfg1"])
+def test_wide_interval_high_degree(fix, prec, request):
+    """Damping interval [a, b] at the top of the spectrum and m = 60: the
+    unscaled iterates reach T_60(t(lambda_min)) ~ 1e130, far outside FP32's
+    range.  The reduced forms keep their iterates scaled by powers of two and
+    return the unscaled result: the last step against the model (as in
+    test_filter_steps) and, for CF_FP32, the whole filter against the FP64
+    oracle."""
+    print(f"[lowp wide] {fix} {prec}", flush=True)
+    prob = request.getfixturevalue(fix)
+    ctx, ops = context(fix, prob)
+    mod = model(fix, prob, prec)
+    v0 = np.random.default_rng(5).standard_normal(ops.n)
+    al, be = lanczos(ops.apply_Htilde, ops.apply_M, v0, 10)
+    lo, hi = lanczos_bounds(al, be)
+    a = hi - 0.02 * (hi - lo)
+    e, c = 2.0 / (hi - a), (a + hi) / (hi - a)
+    m = 60
+    X = bf16_block((ops.n, 12), 35)
+    Xd = dev(X)
+    Ym2, Ym1, Ym = (host(ctx.filter(Xd, k, a, hi, prec=prec)) for k in (m - 2, m - 1, m))
+    assert np.isfinite(Ym).all()
+    assert np.abs(Ym).max() > 1e60
+    kap = kappa_M(ops)
+    rhs = 2.0 * (e * mod.htilde(Ym1) - c * Ym1) - Ym2
+    rel = float(np.abs(Ym - rhs).max() / np.abs(rhs).max())
+    print(f"  max |Y| {np.abs(Ym).max():.3e}; last step rel err {rel:.3e}", flush=True)
+    assert rel < 10 * U32 * kap
+    if prec == "fp32":
+        Yo = recurrence_filter(lambda Z: ops.apply_Htilde(Z), X, m, a, hi)
+        rel = float(np.abs(Ym - Yo).max() / np.abs(Yo).max())
+        print(f"  whole filter rel err {rel:.3e}", flush=True)
         assert rel < 10 * U32 * kap * m
 
 

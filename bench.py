@@ -35,6 +35,8 @@ WORKLOADS = {
     # name: (generator, N, m, wanted)
     "si30-24c": ("config2", 260, 40, 210),
     "hydrogen-8c": ("config1", 16, 20, 14),
+    # 256 independent Si clusters of 1-8 atoms (N 16-64 each), batched form
+    "si-batch256": ("batch_workload", None, 40, None),
 }
 
 
@@ -191,6 +193,116 @@ def mixed_study(ctx, prob, N, m, wanted, seed, m_lp, max_passes=30):
     return out
 
 
+def run_batch(args):
+    """The batched form: 256 independent problems, one SCF step = per-entry
+    Lanczos bounds -> batched reduced-precision filter (one launch per kernel
+    family and step for all entries, replayed from a HIP graph) -> per-entry
+    Rayleigh-Ritz.  Also times the filter alone three ways: batched with the
+    graph, batched without it, and entry by entry through the single-problem
+    entry point."""
+    import numpy as np
+    import torch
+
+    from paper_1610_02121_amd import Batch, Context
+    from synth import configs
+    m = WORKLOADS["si-batch256"][2]
+    prec = "fp32" if args.prec == "fp64" else args.prec
+    t0 = time.time()
+    log("generating the batch pool (Si clusters of 1-8 atoms)")
+    pool, atoms, Ns = configs.batch_workload(256, seed=args.seed)
+    probs = [pool[a] for a in atoms]
+    maxc = max(Ns)
+    log(f"pool of {len(pool)} problems (n = {[pool[a].n for a in sorted(pool)]}) in "
+        f"{time.time() - t0:.1f}s; 256 entries, sum n*N = {sum(p.n * N for p, N in zip(probs, Ns))}")
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    batch = Batch(probs, max_cols=maxc)
+    log(f"batch ready ({time.time() - t0:.1f}s)")
+    X = [torch.tensor(configs.initial_block(p, N, seed=args.seed), dtype=torch.float64, device=dev)
+         for p, N in zip(probs, Ns)]
+    Y = [torch.empty_like(x) for x in X]
+    v0 = [torch.tensor(np.random.default_rng(args.seed + 1 + i).standard_normal(p.n),
+                       dtype=torch.float64, device=dev) for i, p in enumerate(probs)]
+    theta = batch.rayleigh_ritz(X)
+    st = {"X": X, "Y": Y, "theta": theta, "t": [0.0, 0.0, 0.0]}
+
+    def step(timed):
+        s0 = time.perf_counter()
+        _, b = batch.lanczos_bounds(v0, 10)
+        s1 = time.perf_counter()
+        a = [float(th[-1]) for th in st["theta"]]
+        batch.filter(st["X"], m, a, b, Y=st["Y"], prec=prec, use_graph=True)
+        torch.cuda.synchronize()
+        s2 = time.perf_counter()
+        th = batch.rayleigh_ritz(st["Y"])
+        s3 = time.perf_counter()
+        st["X"], st["Y"], st["theta"], st["b"], st["a"] = st["Y"], st["X"], th, b, a
+        if timed:
+            for i, d in enumerate((s1 - s0, s2 - s1, s3 - s2)):
+                st["t"][i] += d
+
+    for i in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        step(True)
+        log(f"step {i + 1}/{args.steps}")
+    torch.cuda.synchronize()
+    ms_per_step = 1e3 * (time.perf_counter() - t_start) / args.steps
+    work = sum(p.n * N for p, N in zip(probs, Ns)) * m
+
+    def time_filter(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t1) / reps
+
+    a, b = st["a"], st["b"]
+    t_graph = time_filter(lambda: batch.filter(st["X"], m, a, b, Y=st["Y"], prec=prec, use_graph=True))
+    t_nograph = time_filter(lambda: batch.filter(st["X"], m, a, b, Y=st["Y"], prec=prec,
+                                                 use_graph=False))
+    singles = {k: Context(pool[k], max_cols=maxc) for k in pool}
+
+    def sequential():
+        for i, k in enumerate(atoms):
+            singles[k].filter(st["X"][i], m, a[i], b[i], Y=st["Y"][i], prec=prec)
+    t_seq = time_filter(sequential)
+    # the batched result equals the entry-by-entry one bit for bit
+    Yb = [y.clone() for y in batch.filter(st["X"], m, a, b, prec=prec)]
+    sequential()
+    torch.cuda.synchronize()
+    same = all(torch.equal(yb, y) for yb, y in zip(Yb, st["Y"]))
+    out = {
+        "metric": "batched Chebyshev-filter DOF*vectors/s (per degree, whole SCF step), "
+                  "256 independent problems",
+        "value": work / (ms_per_step / 1e3),
+        "unit": "DOF*vectors*degree/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp32": "f32", "bf16": "bf16"}[prec], "data": "synthetic",
+        "config": {"workload": "si-batch256", "entries": 256, "distinct_problems": len(pool),
+                   "atoms_per_entry": "U{1..8}", "vectors": "16-64", "cheb_degree": m,
+                   "sum_n_times_N": work // m,
+                   "precision": f"{prec} filter, fp64 Schur solve and Rayleigh-Ritz"},
+        "phases_ms": {"bounds": 1e3 * st["t"][0] / args.steps,
+                      "filter": 1e3 * st["t"][1] / args.steps,
+                      "cholqr_rr": 1e3 * st["t"][2] / args.steps},
+        "filter_only_ms": {"batched_graph": 1e3 * t_graph, "batched_no_graph": 1e3 * t_nograph,
+                           "entry_by_entry": 1e3 * t_seq},
+        "filter_dof_vec_deg_per_s": work / t_graph,
+        "speedup_batched_vs_entry_by_entry": t_seq / t_graph,
+        "batched_equals_entry_by_entry": bool(same),
+    }
+    print(json.dumps(out), flush=True)
+    for c in singles.values():
+        c.close()
+    batch.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -221,6 +333,9 @@ def main():
     from synth import configs
 
     name = args.workload
+    if name == "si-batch256":
+        run_batch(args)
+        return
     _, N, m, wanted = WORKLOADS[name]
     t0 = time.time()
     log(f"generating {name} (seed {args.seed})")

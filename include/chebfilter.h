@@ -164,6 +164,53 @@ cf_status chebfilter_profile(cf_ctx *ctx, int32_t enable);
 cf_status chebfilter_profile_query(cf_ctx *ctx, const char *name, int64_t *launches,
                                    double *total_ms, double *total_flops);
 
+/* ---- Batches of independent problems ------------------------------------
+ * Many discrete problems (Sec. IV) filtered together: each problem is the
+ * method of Sec. V on its own, and the batch only changes how the work is
+ * launched.  Entries that point to the same cf_problem share one device copy
+ * of the operator; every entry has its own blocks, interval and workspace.
+ * The options (device, stream, max_cols, check_finite) apply to every entry.
+ * Array arguments are HOST arrays with one element per entry (device
+ * pointers for blocks).  Calls on one batch must not overlap. */
+typedef struct cf_batch cf_batch;
+
+/* Build the contexts of count entries (probs[i] as for chebfilter_init).
+ * On failure *out is null and chebfilter_batch_last_error(NULL) explains. */
+cf_status chebfilter_init_batch(const cf_problem *const *probs, int32_t count,
+                                const cf_options *opt, cf_batch **out);
+cf_status chebfilter_batch_destroy(cf_batch *batch);
+const char *chebfilter_batch_last_error(const cf_batch *batch);
+/* Row counts of entry i (its blocks have n_h + n_e rows). */
+cf_status chebfilter_batch_sizes(const cf_batch *batch, int32_t i, int64_t *n_h, int64_t *n_e);
+
+/* Y[i] = T_m(t_i(H~_i)) X[i] for every entry, t_i(x) = (2x - a[i] - b[i])/(b[i] - a[i])
+ * (Sec. V recurrence, per entry as chebfilter_filter).  1 <= N[i] <= max_cols.
+ * CF_FP32 and CF_BF16 run every entry in the same launches: per step one
+ * launch per cell colour (colour k of all entries together; BF16: two, cells
+ * near the enriched region in FP32), one per coupling/Schur/epilogue kernel,
+ * each work item addressing its entry through a device descriptor table; the
+ * result of each entry is bit for bit that of chebfilter_filter with the same
+ * prec.  With use_graph != 0 the launches of the whole filter are captured
+ * once per (m, prec) into a HIP graph on an internal stream and replayed (the
+ * descriptors, updated before each replay, carry the blocks and intervals).
+ * The work is ordered after prior work on the options' stream, and later work
+ * there waits for it.  CF_FP64 (and m = 0) runs chebfilter_filter entry by
+ * entry.  The first reduced call allocates the FP32 workspace of every entry
+ * (two n x max_cols FP32 blocks plus the per-call work blocks). */
+cf_status chebfilter_filter_batch(cf_batch *batch, const double *const *X, const int64_t *ldx,
+                                  double *const *Y, const int64_t *ldy, const int64_t *N,
+                                  int32_t m, const double *a, const double *b, int32_t prec,
+                                  int32_t use_graph);
+
+/* chebfilter_rayleigh_ritz for every entry, one after another (synchronises);
+ * theta_host[i] receives N[i] values. */
+cf_status chebfilter_rayleigh_ritz_batch(cf_batch *batch, double *const *Y, const int64_t *ldy,
+                                         const int64_t *N, double *const *theta_host);
+
+/* chebfilter_lanczos_bounds for every entry (synchronises); lmin_est[i], b_upper[i]. */
+cf_status chebfilter_lanczos_bounds_batch(cf_batch *batch, const double *const *v0, int32_t k,
+                                          double *lmin_est, double *b_upper);
+
 #ifdef __cplusplus
 }
 #endif

@@ -23,7 +23,10 @@ PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
 EXPORTS = ["chebfilter_init", "chebfilter_destroy", "chebfilter_last_error", "chebfilter_sizes",
            "chebfilter_apply_H", "chebfilter_apply_M", "chebfilter_apply_Sinv",
            "chebfilter_filter", "chebfilter_cholqr", "chebfilter_rayleigh_ritz",
-           "chebfilter_lanczos_bounds", "chebfilter_profile", "chebfilter_profile_query"]
+           "chebfilter_lanczos_bounds", "chebfilter_profile", "chebfilter_profile_query",
+           "chebfilter_init_batch", "chebfilter_batch_destroy", "chebfilter_batch_last_error",
+           "chebfilter_batch_sizes", "chebfilter_filter_batch", "chebfilter_rayleigh_ritz_batch",
+           "chebfilter_lanczos_bounds_batch"]
 
 
 class CfProblem(C.Structure):
@@ -70,8 +73,20 @@ def load_library() -> C.CDLL:
     lib.chebfilter_profile.argtypes = [vp, i32]
     lib.chebfilter_profile_query.argtypes = [vp, C.c_char_p, C.POINTER(i64), C.POINTER(dbl),
                                              C.POINTER(dbl)]
+    P64 = C.POINTER(i64)
+    lib.chebfilter_init_batch.argtypes = [C.POINTER(C.POINTER(CfProblem)), i32, C.POINTER(CfOptions),
+                                          C.POINTER(vp)]
+    lib.chebfilter_batch_destroy.argtypes = [vp]
+    lib.chebfilter_batch_last_error.argtypes = [vp]
+    lib.chebfilter_batch_last_error.restype = C.c_char_p
+    lib.chebfilter_batch_sizes.argtypes = [vp, i32, P64, P64]
+    lib.chebfilter_filter_batch.argtypes = [vp, C.POINTER(vp), P64, C.POINTER(vp), P64, P64, i32,
+                                            C.POINTER(dbl), C.POINTER(dbl), i32, i32]
+    lib.chebfilter_rayleigh_ritz_batch.argtypes = [vp, C.POINTER(vp), P64, P64, C.POINTER(vp)]
+    lib.chebfilter_lanczos_bounds_batch.argtypes = [vp, C.POINTER(vp), i32, C.POINTER(dbl),
+                                                    C.POINTER(dbl)]
     for nm in EXPORTS:
-        if nm != "chebfilter_last_error":
+        if nm not in ("chebfilter_last_error", "chebfilter_batch_last_error"):
             getattr(lib, nm).restype = C.c_int
     _lib = lib
     return lib
@@ -90,23 +105,28 @@ def _block(t, name: str):
     return t.data_ptr(), t.stride(0) if t.shape[1] > 1 else max(t.stride(0), 1)
 
 
+def _problem_struct(prob):
+    """(CfProblem, arrays it points into) for a synth Problem."""
+    keep = {
+        "cell_dof": _np(prob.cell_dof, np.int64), "H_cc": _np(prob.H_cc, np.float64),
+        "M_cc_diag": _np(prob.M_cc_diag, np.float64), "enr_ptr": _np(prob.enr_ptr, np.int64),
+        "enr_idx": _np(prob.enr_idx, np.int64), "H_ec": _np(prob.H_ec, np.float64),
+        "M_ec": _np(prob.M_ec, np.float64), "H_ee": _np(prob.H_ee, np.float64),
+        "M_ee": _np(prob.M_ee, np.float64)}
+    n_cells = keep["cell_dof"].shape[0]
+    cp = CfProblem(int(prob.p), n_cells, keep["M_cc_diag"].shape[0], keep["H_ee"].shape[0],
+                   *[keep[f].ctypes.data for f in ("cell_dof", "H_cc", "M_cc_diag", "enr_ptr",
+                                                   "enr_idx", "H_ec", "M_ec", "H_ee", "M_ee")])
+    return cp, keep
+
+
 class Context:
     """One discrete problem resident on one GPU (wraps cf_ctx)."""
 
     def __init__(self, prob, max_cols: int, device: int = 0, check_finite: bool = False):
         import torch
         self.lib = load_library()
-        self._keep = {
-            "cell_dof": _np(prob.cell_dof, np.int64), "H_cc": _np(prob.H_cc, np.float64),
-            "M_cc_diag": _np(prob.M_cc_diag, np.float64), "enr_ptr": _np(prob.enr_ptr, np.int64),
-            "enr_idx": _np(prob.enr_idx, np.int64), "H_ec": _np(prob.H_ec, np.float64),
-            "M_ec": _np(prob.M_ec, np.float64), "H_ee": _np(prob.H_ee, np.float64),
-            "M_ee": _np(prob.M_ee, np.float64)}
-        k = self._keep
-        n_cells = k["cell_dof"].shape[0]
-        cp = CfProblem(int(prob.p), n_cells, k["M_cc_diag"].shape[0], k["H_ee"].shape[0],
-                       *[k[f].ctypes.data for f in ("cell_dof", "H_cc", "M_cc_diag", "enr_ptr",
-                                                    "enr_idx", "H_ec", "M_ec", "H_ee", "M_ee")])
+        cp, self._keep = _problem_struct(prob)
         self.device = torch.device("cuda", device)
         stream = torch.cuda.current_stream(self.device)
         self.stream = stream
@@ -200,3 +220,98 @@ class Context:
         self._check(self.lib.chebfilter_profile_query(self._h, name.encode(), C.byref(n),
                                                       C.byref(ms), C.byref(fl)))
         return n.value, ms.value, fl.value
+
+
+class Batch:
+    """Independent problems filtered together (wraps cf_batch).  The same
+    Problem object appearing several times shares one device operator."""
+
+    def __init__(self, probs, max_cols: int, device: int = 0):
+        import torch
+        self.lib = load_library()
+        structs, keep, index = [], [], {}
+        ptrs = (C.POINTER(CfProblem) * len(probs))()
+        for i, p in enumerate(probs):
+            if id(p) not in index:
+                cp, arrs = _problem_struct(p)
+                structs.append(cp)
+                keep.append(arrs)
+                index[id(p)] = len(structs) - 1
+            ptrs[i] = C.pointer(structs[index[id(p)]])
+        self.device = torch.device("cuda", device)
+        stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        opt = CfOptions(device, C.c_void_p(stream.cuda_stream), int(max_cols), 0)
+        h = C.c_void_p()
+        st = self.lib.chebfilter_init_batch(ptrs, len(probs), C.byref(opt), C.byref(h))
+        if st != 0:
+            raise ChebFilterError(st, self.lib.chebfilter_batch_last_error(None).decode())
+        self._h = h
+        self.count = len(probs)
+        self.max_cols = int(max_cols)
+        self.sizes = []
+        for i in range(self.count):
+            nh, ne = C.c_int64(), C.c_int64()
+            self.lib.chebfilter_batch_sizes(h, i, C.byref(nh), C.byref(ne))
+            self.sizes.append((nh.value, ne.value))
+
+    def _check(self, st: int):
+        if st != 0:
+            raise ChebFilterError(st, self.lib.chebfilter_batch_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.lib.chebfilter_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _blocks(self, blocks, name):
+        n = self.count
+        if len(blocks) != n:
+            raise ValueError(f"{name}: need {n} blocks")
+        ptrs, lds, Ns = (C.c_void_p * n)(), (C.c_int64 * n)(), (C.c_int64 * n)()
+        for i, t in enumerate(blocks):
+            p, ld = _block(t, f"{name}[{i}]")
+            ptrs[i], lds[i], Ns[i] = p, ld, t.shape[1]
+        return ptrs, lds, Ns
+
+    def filter(self, X, m: int, a, b, Y=None, prec="fp32", use_graph: bool = True):
+        """Y[i] = T_m(t_i(H~_i)) X[i] for every entry (lists of blocks, a, b)."""
+        import torch
+        if Y is None:
+            Y = [torch.empty_like(x) for x in X]
+        xp, xl, xn = self._blocks(X, "X")
+        yp, yl, yn = self._blocks(Y, "Y")
+        if list(xn) != list(yn):
+            raise ValueError("X and Y column counts differ")
+        n = self.count
+        av = (C.c_double * n)(*[float(v) for v in a])
+        bv = (C.c_double * n)(*[float(v) for v in b])
+        code = PREC[prec] if isinstance(prec, str) else int(prec)
+        self._check(self.lib.chebfilter_filter_batch(self._h, xp, xl, yp, yl, xn, int(m), av, bv,
+                                                     code, int(bool(use_graph))))
+        return Y
+
+    def rayleigh_ritz(self, Y):
+        yp, yl, yn = self._blocks(Y, "Y")
+        thetas = [np.zeros(max(int(N), 1)) for N in yn]
+        tp = (C.c_void_p * self.count)(*[t.ctypes.data for t in thetas])
+        self._check(self.lib.chebfilter_rayleigh_ritz_batch(self._h, yp, yl, yn, tp))
+        return [t[:int(N)] for t, N in zip(thetas, yn)]
+
+    def lanczos_bounds(self, v0, k: int = 10):
+        import torch
+        n = self.count
+        vp = (C.c_void_p * n)()
+        for i, v in enumerate(v0):
+            if v.dtype != torch.float64 or not v.is_cuda or not v.is_contiguous():
+                raise TypeError("v0 entries must be contiguous float64 CUDA tensors")
+            vp[i] = v.data_ptr()
+        lo, hi = (C.c_double * n)(), (C.c_double * n)()
+        self._check(self.lib.chebfilter_lanczos_bounds_batch(self._h, vp, int(k), lo, hi))
+        return list(lo), list(hi)

@@ -1008,6 +1008,231 @@ static cf_status do_init(const cf_problem *pr, const cf_options *opt, cf_ctx *c)
 }
 
 // ---------------------------------------------------------------------------
+// batches of independent problems
+// ---------------------------------------------------------------------------
+// Entries that point to the same cf_problem share one context (its device
+// operator, and its FP64 workspace for the per-entry Rayleigh-Ritz and
+// Lanczos calls, which run one after another); every entry has its own FP32
+// recurrence workspace, so the batched filter runs all entries at once.
+struct cf_batch {
+  int device = 0;
+  hipStream_t caller = nullptr, bs = nullptr;
+  int count = 0;
+  int64_t max_cols = 0;
+  std::vector<cf_ctx *> uniq;
+  std::vector<int> which;                   // entry -> uniq index
+  // device descriptors and work lists
+  std::vector<BatchProb> h_bp;
+  BatchProb *stage = nullptr;               // pinned staging of the per-call descriptors
+  BatchProb *d_bp = nullptr;
+  std::vector<int> cell_off_all, cell_off_near, cell_off_far;   // per colour, into d_items
+  BatchItem *d_items = nullptr;
+  BatchItem *d_eitems = nullptr;
+  int neitems = 0, kmax = 0, ncolours = 0, lp_cap = 0;
+  int64_t *d_boff = nullptr, *d_aoff = nullptr, *d_eoff = nullptr;
+  int64_t nbblocks = 0, nalpha = 0, neblocks = 0;
+  bool lowp_ready = false, bf16_ready = false;
+  // graph of the batched filter, keyed by (m, prec)
+  hipGraphExec_t gexec = nullptr;
+  int g_m = -1, g_prec = -1;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_copy = nullptr;
+  bool copy_pending = false;
+  std::string err;
+  std::vector<void *> allocs;
+};
+
+static cf_status berr(cf_batch *b, cf_status st, const std::string &msg) {
+  if (b) b->err = msg; else g_init_error = msg;
+  return st;
+}
+
+#define BHIPCHK(b, call)                                                                      \
+  do {                                                                                        \
+    hipError_t e_ = (call);                                                                   \
+    if (e_ != hipSuccess)                                                                     \
+      return berr(b, CF_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));          \
+  } while (0)
+
+template <typename T>
+static cf_status balloc(cf_batch *b, T **p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  void *q = nullptr;
+  if (hipMalloc(&q, count * sizeof(T)) != hipSuccess) {
+    (void)hipGetLastError();
+    return berr(b, CF_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+  }
+  b->allocs.push_back(q);
+  *p = static_cast<T *>(q);
+  return CF_OK;
+}
+
+template <typename T>
+static cf_status bupload(cf_batch *b, T **p, const std::vector<T> &v) {
+  cf_status st = balloc(b, p, v.size());
+  if (st != CF_OK) return st;
+  if (!v.empty()) BHIPCHK(b, hipMemcpy(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  return CF_OK;
+}
+
+static void free_batch(cf_batch *b) {
+  if (!b) return;
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  for (cf_ctx *c : b->uniq) free_ctx(c);
+  for (void *q : b->allocs) (void)hipFree(q);
+  if (b->stage) (void)hipHostFree(b->stage);
+  if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+  if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+  if (b->ev_copy) (void)hipEventDestroy(b->ev_copy);
+  if (b->bs) (void)hipStreamDestroy(b->bs);
+  delete b;
+}
+
+// Reduced-precision operator copies of every problem, FP32 workspace of every
+// entry, descriptors and work lists (once; BF16 copies on first BF16 use).
+static cf_status batch_prepare_lowp(cf_batch *b, bool bf16, int m) {
+  for (cf_ctx *c : b->uniq) {
+    cf_status st = ensure_lowp(c, bf16);
+    if (st != CF_OK) return berr(b, st, c->err);
+  }
+  if (bf16) b->bf16_ready = true;
+  const int cap = std::max(256, m + 2);
+  const bool new_cap = cap > b->lp_cap;
+  if (b->lowp_ready && !new_cap) {
+    if (bf16)
+      for (int i = 0; i < b->count; ++i) b->h_bp[i].Hp16 = b->uniq[b->which[i]]->Hp16;
+    return CF_OK;
+  }
+  const int64_t mc = b->max_cols;
+  if (!b->lowp_ready) b->h_bp.assign(b->count, BatchProb());
+  for (int i = 0; i < b->count; ++i) {
+    cf_ctx *c = b->uniq[b->which[i]];
+    BatchProb &P = b->h_bp[i];
+    P.Hp32 = c->Hp32; P.Hp16 = c->Hp16; P.dofp = c->dofp; P.flagp = c->flagp;
+    P.HT32 = c->HT32; P.MT32 = c->MT32; P.toff = c->toff; P.tld = c->tld; P.eptr = c->eptr;
+    P.ecells = c->ecells; P.Hec32 = c->Hec32; P.Mec32 = c->Mec32; P.eidx = c->eidx;
+    P.aptr = c->aptr; P.alist = c->alist; P.Hmod = c->Hmod; P.Sinv = c->Sinv; P.dinv = c->dinv;
+    P.qptr = c->qptr; P.qidx = c->qidx; P.regrows = c->regrows;
+    P.nregrows = c->nregrows; P.n_h = c->n_h; P.n_e = c->n_e; P.n = c->n;
+    P.mc = mc;
+    if (!b->lowp_ready) {
+      STCHK(balloc(b, &P.F0, (size_t)c->n * mc));
+      STCHK(balloc(b, &P.F1, (size_t)c->n * mc));
+      STCHK(balloc(b, &P.R32, (size_t)c->n_h * mc));
+      if (c->n_e > 0) {
+        STCHK(balloc(b, &P.P32, (size_t)std::max<int64_t>(c->nnz, 1) * mc));
+        STCHK(balloc(b, &P.Q32, (size_t)std::max<int>(c->necells, 1) * NPAD * mc));
+        STCHK(balloc(b, &P.Wb, (size_t)c->n_e * mc));
+        STCHK(balloc(b, &P.Zb, (size_t)c->n_e * mc));
+      }
+    }
+    if (new_cap) {
+      STCHK(balloc(b, &P.lp_mx, (size_t)cap * MX_SLOTS));
+      STCHK(balloc(b, &P.lp_s, (size_t)cap));
+      STCHK(balloc(b, &P.lp_mult, (size_t)2 * cap));
+    }
+  }
+  b->lp_cap = std::max(b->lp_cap, cap);
+  if (!b->lowp_ready) {
+    STCHK(balloc(b, &b->d_bp, (size_t)b->count));
+    if (hipHostMalloc((void **)&b->stage, (size_t)b->count * sizeof(BatchProb)) != hipSuccess)
+      return berr(b, CF_ENOMEM, "hipHostMalloc of the descriptor staging failed");
+    // work lists: per colour all cells / near cells / far cells of every entry
+    std::vector<BatchItem> items;
+    b->ncolours = 0;
+    for (cf_ctx *c : b->uniq) b->ncolours = std::max(b->ncolours, (int)c->col_off.size() - 1);
+    std::vector<std::vector<int32_t>> split(b->uniq.size());
+    for (size_t u = 0; u < b->uniq.size(); ++u) {
+      cf_ctx *c = b->uniq[u];
+      split[u].resize(c->col_off.back());
+      BHIPCHK(b, hipMemcpy(split[u].data(), c->cells_split, split[u].size() * sizeof(int32_t),
+                           hipMemcpyDeviceToHost));
+    }
+    b->cell_off_all.assign(b->ncolours + 1, 0);
+    b->cell_off_near.assign(b->ncolours + 1, 0);
+    b->cell_off_far.assign(b->ncolours + 1, 0);
+    auto add = [&](int k, int part) {
+      for (int i = 0; i < b->count; ++i) {
+        const int u = b->which[i];
+        cf_ctx *c = b->uniq[u];
+        if (k + 1 >= (int)c->col_off.size()) continue;
+        const int c0 = c->col_off[k], cnt = c->col_off[k + 1] - c0, nn = c->near_cnt[k];
+        const int q0 = part == 2 ? c0 + nn : c0;
+        const int q1 = part == 1 ? c0 + nn : c0 + cnt;
+        for (int q = q0; q < q1; ++q) items.push_back({i, split[u][q]});
+      }
+    };
+    for (int k = 0; k < b->ncolours; ++k) {          // all cells (FP32 form)
+      b->cell_off_all[k] = (int)items.size();
+      add(k, 0);
+    }
+    b->cell_off_all[b->ncolours] = (int)items.size();
+    for (int k = 0; k < b->ncolours; ++k) {          // near cells (FP32 in the BF16 form)
+      b->cell_off_near[k] = (int)items.size();
+      add(k, 1);
+    }
+    b->cell_off_near[b->ncolours] = (int)items.size();
+    for (int k = 0; k < b->ncolours; ++k) {          // far cells (BF16)
+      b->cell_off_far[k] = (int)items.size();
+      add(k, 2);
+    }
+    b->cell_off_far[b->ncolours] = (int)items.size();
+    STCHK(bupload(b, &b->d_items, items));
+    std::vector<BatchItem> eitems;
+    std::vector<int64_t> boff(1, 0), aoff(1, 0), eoff(1, 0);
+    b->kmax = 0;
+    for (int i = 0; i < b->count; ++i) {
+      cf_ctx *c = b->uniq[b->which[i]];
+      for (int j = 0; j < c->necells; ++j) eitems.push_back({i, j});
+      b->kmax = std::max(b->kmax, c->kmax);
+      boff.push_back(boff.back() + std::max<int64_t>((c->n + 63) / 64, 1));
+      aoff.push_back(aoff.back() + c->n_e);
+      eoff.push_back(eoff.back() + std::max<int64_t>((c->nregrows + c->n_e + 15) / 16, 1));
+    }
+    b->neitems = (int)eitems.size();
+    b->nbblocks = boff.back();
+    b->nalpha = aoff.back();
+    b->neblocks = eoff.back();
+    STCHK(bupload(b, &b->d_eitems, eitems));
+    STCHK(bupload(b, &b->d_boff, boff));
+    STCHK(bupload(b, &b->d_aoff, aoff));
+    STCHK(bupload(b, &b->d_eoff, eoff));
+    BHIPCHK(b, prepare_b_enr(b->kmax));
+    b->lowp_ready = true;
+  }
+  if (new_cap && b->gexec) {           // descriptors of the captured graph moved
+    (void)hipGraphExecDestroy(b->gexec);
+    b->gexec = nullptr;
+  }
+  return CF_OK;
+}
+
+// The batched filter's launches (steps 0..m-1), enqueued on b->bs.
+static cf_status batch_enqueue_filter(cf_batch *b, int m, bool bf16) {
+  hipStream_t s = b->bs;
+  BHIPCHK(b, launch_b_lp_begin(s, b->d_bp, b->count, (m + 2) * MX_SLOTS, b->d_boff, b->nbblocks));
+  for (int k = 0; k < m; ++k) {
+    if (k > 0) BHIPCHK(b, launch_b_lp_scale(s, b->d_bp, b->count, k));
+    for (int col = 0; col < b->ncolours; ++col) {
+      if (bf16) {
+        const int n0 = b->cell_off_near[col], n1 = b->cell_off_near[col + 1];
+        const int f0 = b->cell_off_far[col], f1 = b->cell_off_far[col + 1];
+        BHIPCHK(b, launch_b_cell(s, false, b->d_bp, b->d_items + n0, n1 - n0, k));
+        BHIPCHK(b, launch_b_cell(s, true, b->d_bp, b->d_items + f0, f1 - f0, k));
+      } else {
+        const int a0 = b->cell_off_all[col], a1 = b->cell_off_all[col + 1];
+        BHIPCHK(b, launch_b_cell(s, false, b->d_bp, b->d_items + a0, a1 - a0, k));
+      }
+    }
+    BHIPCHK(b, launch_b_enr(s, b->d_bp, b->count, b->d_eitems, b->neitems, b->d_aoff, b->nalpha,
+                            (int)b->max_cols, b->kmax, k));
+    BHIPCHK(b, launch_b_epilogue(s, b->d_bp, b->count, b->d_eoff, b->neblocks, k));
+  }
+  BHIPCHK(b, launch_b_lp_output(s, b->d_bp, b->count, b->d_boff, b->nbblocks, m));
+  return CF_OK;
+}
+
+// ---------------------------------------------------------------------------
 // public entry points
 // ---------------------------------------------------------------------------
 extern "C" {
@@ -1277,6 +1502,166 @@ cf_status chebfilter_profile_query(cf_ctx *c, const char *name, int64_t *launche
   if (launches) *launches = pe.launches;
   if (total_ms) *total_ms = pe.ms;
   if (total_flops) *total_flops = pe.flops;
+  return CF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batches
+// ---------------------------------------------------------------------------
+cf_status chebfilter_init_batch(const cf_problem *const *probs, int32_t count, const cf_options *opt,
+                                cf_batch **out) {
+  if (!out) return berr(nullptr, CF_EINVAL, "init_batch: null output pointer");
+  *out = nullptr;
+  if (!probs || count < 1 || !opt) return berr(nullptr, CF_EINVAL, "init_batch: need count >= 1 problems");
+  cf_batch *b = new (std::nothrow) cf_batch();
+  if (!b) return berr(nullptr, CF_ENOMEM, "init_batch: host allocation failed");
+  b->device = opt->device;
+  b->caller = (hipStream_t)opt->stream;
+  b->count = count;
+  b->max_cols = opt->max_cols;
+  std::map<const cf_problem *, int> seen;
+  for (int i = 0; i < count; ++i) {
+    if (!probs[i]) { free_batch(b); return berr(nullptr, CF_EINVAL, "init_batch: null problem"); }
+    auto it = seen.find(probs[i]);
+    if (it != seen.end()) { b->which.push_back(it->second); continue; }
+    cf_ctx *c = new (std::nothrow) cf_ctx();
+    if (!c) { free_batch(b); return berr(nullptr, CF_ENOMEM, "init_batch: host allocation failed"); }
+    cf_status st = do_init(probs[i], opt, c);
+    if (st != CF_OK) {
+      g_init_error = "init_batch: problem " + std::to_string(i) + ": " + c->err;
+      free_ctx(c);
+      free_batch(b);
+      return st;
+    }
+    seen[probs[i]] = (int)b->uniq.size();
+    b->which.push_back((int)b->uniq.size());
+    b->uniq.push_back(c);
+  }
+  if (hipStreamCreateWithFlags(&b->bs, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&b->ev_copy, hipEventDisableTiming) != hipSuccess) {
+    free_batch(b);
+    return berr(nullptr, CF_EDEVICE, "init_batch: stream or event creation failed");
+  }
+  *out = b;
+  return CF_OK;
+}
+
+cf_status chebfilter_batch_destroy(cf_batch *b) {
+  if (!b) return CF_OK;
+  (void)hipSetDevice(b->device);
+  (void)hipStreamSynchronize(b->bs);
+  (void)hipStreamSynchronize(b->caller);
+  free_batch(b);
+  return CF_OK;
+}
+
+const char *chebfilter_batch_last_error(const cf_batch *b) {
+  return b ? b->err.c_str() : g_init_error.c_str();
+}
+
+cf_status chebfilter_batch_sizes(const cf_batch *b, int32_t i, int64_t *n_h, int64_t *n_e) {
+  if (!b || i < 0 || i >= b->count) return CF_EINVAL;
+  const cf_ctx *c = b->uniq[b->which[i]];
+  if (n_h) *n_h = c->n_h;
+  if (n_e) *n_e = c->n_e;
+  return CF_OK;
+}
+
+cf_status chebfilter_filter_batch(cf_batch *b, const double *const *X, const int64_t *ldx,
+                                  double *const *Y, const int64_t *ldy, const int64_t *N, int32_t m,
+                                  const double *a, const double *bu, int32_t prec, int32_t use_graph) {
+  if (!b) return CF_EINVAL;
+  if (!X || !ldx || !Y || !ldy || !N || !a || !bu)
+    return berr(b, CF_EINVAL, "filter_batch: null argument array");
+  if (m < 0) return berr(b, CF_EINVAL, "filter_batch: m < 0");
+  if (prec != CF_FP64 && prec != CF_FP32 && prec != CF_BF16)
+    return berr(b, CF_EINVAL, "filter_batch: prec must be CF_FP64, CF_FP32 or CF_BF16");
+  for (int i = 0; i < b->count; ++i) {
+    if (N[i] < 1 || N[i] > b->max_cols)
+      return berr(b, N[i] < 1 ? CF_EINVAL : CF_ENOMEM, "filter_batch: N[" + std::to_string(i) +
+                                                           "] out of range [1, max_cols]");
+    if (!X[i] || !Y[i] || ldx[i] < N[i] || ldy[i] < N[i] || X[i] == Y[i])
+      return berr(b, CF_EINVAL, "filter_batch: bad block " + std::to_string(i));
+    if (!std::isfinite(a[i]) || !std::isfinite(bu[i]) || !(bu[i] > a[i]))
+      return berr(b, CF_EINVAL, "filter_batch: need finite a < b for entry " + std::to_string(i));
+  }
+  BHIPCHK(b, hipSetDevice(b->device));
+  if (prec == CF_FP64 || m == 0) {
+    // FP64 (or degree 0): the single-problem path entry by entry
+    for (int i = 0; i < b->count; ++i) {
+      cf_ctx *c = b->uniq[b->which[i]];
+      cf_status st = chebfilter_filter(c, X[i], ldx[i], Y[i], ldy[i], N[i], m, a[i], bu[i], CF_FP64);
+      if (st != CF_OK) return berr(b, st, "entry " + std::to_string(i) + ": " + c->err);
+    }
+    return CF_OK;
+  }
+  const bool bf16 = prec == CF_BF16;
+  STCHK(batch_prepare_lowp(b, bf16, m));
+  // per-call descriptor fields, staged in pinned memory (wait for the previous copy)
+  if (b->copy_pending) BHIPCHK(b, hipEventSynchronize(b->ev_copy));
+  for (int i = 0; i < b->count; ++i) {
+    BatchProb P = b->h_bp[i];
+    P.X = X[i]; P.ldx = ldx[i]; P.Y = Y[i]; P.ldy = ldy[i]; P.N = (int)N[i];
+    P.e = 2.0 / (bu[i] - a[i]);
+    P.cc = (a[i] + bu[i]) / (bu[i] - a[i]);
+    b->stage[i] = P;
+  }
+  BHIPCHK(b, hipEventRecord(b->ev_in, b->caller));
+  BHIPCHK(b, hipStreamWaitEvent(b->bs, b->ev_in, 0));
+  BHIPCHK(b, hipMemcpyAsync(b->d_bp, b->stage, (size_t)b->count * sizeof(BatchProb),
+                            hipMemcpyHostToDevice, b->bs));
+  BHIPCHK(b, hipEventRecord(b->ev_copy, b->bs));
+  b->copy_pending = true;
+  if (use_graph) {
+    if (!b->gexec || b->g_m != m || b->g_prec != prec) {
+      if (b->gexec) { (void)hipGraphExecDestroy(b->gexec); b->gexec = nullptr; }
+      hipGraph_t g = nullptr;
+      BHIPCHK(b, hipStreamBeginCapture(b->bs, hipStreamCaptureModeThreadLocal));
+      cf_status st = batch_enqueue_filter(b, m, bf16);
+      hipError_t ec = hipStreamEndCapture(b->bs, &g);
+      if (st != CF_OK) { if (g) (void)hipGraphDestroy(g); return st; }
+      if (ec != hipSuccess) return berr(b, CF_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(ec));
+      ec = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (ec != hipSuccess) {
+        b->gexec = nullptr;
+        return berr(b, CF_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(ec));
+      }
+      b->g_m = m;
+      b->g_prec = prec;
+    }
+    BHIPCHK(b, hipGraphLaunch(b->gexec, b->bs));
+  } else {
+    STCHK(batch_enqueue_filter(b, m, bf16));
+  }
+  BHIPCHK(b, hipEventRecord(b->ev_out, b->bs));
+  BHIPCHK(b, hipStreamWaitEvent(b->caller, b->ev_out, 0));
+  return CF_OK;
+}
+
+cf_status chebfilter_rayleigh_ritz_batch(cf_batch *b, double *const *Y, const int64_t *ldy,
+                                         const int64_t *N, double *const *theta_host) {
+  if (!b) return CF_EINVAL;
+  if (!Y || !ldy || !N || !theta_host) return berr(b, CF_EINVAL, "rayleigh_ritz_batch: null argument array");
+  for (int i = 0; i < b->count; ++i) {
+    cf_ctx *c = b->uniq[b->which[i]];
+    cf_status st = chebfilter_rayleigh_ritz(c, Y[i], ldy[i], N[i], theta_host[i]);
+    if (st != CF_OK) return berr(b, st, "entry " + std::to_string(i) + ": " + c->err);
+  }
+  return CF_OK;
+}
+
+cf_status chebfilter_lanczos_bounds_batch(cf_batch *b, const double *const *v0, int32_t k,
+                                          double *lmin_est, double *b_upper) {
+  if (!b) return CF_EINVAL;
+  if (!v0 || !lmin_est || !b_upper) return berr(b, CF_EINVAL, "lanczos_bounds_batch: null argument array");
+  for (int i = 0; i < b->count; ++i) {
+    cf_ctx *c = b->uniq[b->which[i]];
+    cf_status st = chebfilter_lanczos_bounds(c, v0[i], k, lmin_est + i, b_upper + i);
+    if (st != CF_OK) return berr(b, st, "entry " + std::to_string(i) + ": " + c->err);
+  }
   return CF_OK;
 }
 

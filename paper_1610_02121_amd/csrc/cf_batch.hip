@@ -1,0 +1,217 @@
+// Batched reduced-precision Chebyshev recurrence: one launch per kernel
+// family and step covers every entry of a batch of independent problems.
+// Cells of different problems share no DOF, so colour k of all problems goes
+// in one cell-product launch; enrichment, Schur and epilogue work is indexed
+// through per-entry prefix sums.  Every work item runs the same device body as
+// the single-problem kernels (cf_lowp_body.h) on its entry's data, so a
+// batched filter returns exactly the single-problem results.
+#include "cf_lowp_body.h"
+
+namespace cf {
+
+using namespace lowp;
+
+// entry of global index g in a prefix array off[0..count] (off[0] = 0)
+__device__ __forceinline__ int entry_of(const int64_t *__restrict__ off, int count, int64_t g) {
+  int lo = 0, hi = count;   // off[lo] <= g < off[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (off[mid] <= g) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+struct StepBufs {
+  const float *Xin;
+  float *Out;
+  const float *Yp;
+  float c1, c2, c3;
+  const float *mult;
+  unsigned *mx;
+};
+
+// Buffers and coefficients of step k (forms Z_k+1), as the single-problem driver.
+__device__ __forceinline__ StepBufs step_bufs(const BatchProb &P, int k) {
+  StepBufs b;
+  b.Xin = (k & 1) ? P.F1 : P.F0;
+  b.Out = (k & 1) ? P.F0 : P.F1;
+  b.Yp = k ? b.Out : nullptr;
+  b.c1 = k ? (float)(2.0 * P.e) : (float)P.e;
+  b.c2 = k ? (float)(-2.0 * P.cc) : (float)(-P.cc);
+  b.c3 = k ? -1.f : 0.f;
+  b.mult = P.lp_mult + 2 * k;
+  b.mx = P.lp_mx + (int64_t)(k + 1) * MX_SLOTS;
+  return b;
+}
+
+__global__ __launch_bounds__(256) void kb_lp_reset(const BatchProb *__restrict__ bp, int nslots) {
+  unsigned *mx = bp[blockIdx.y].lp_mx;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < nslots; i += gridDim.x * 256) mx[i] = 0u;
+}
+
+__global__ __launch_bounds__(256) void kb_lp_input(const BatchProb *__restrict__ bp,
+                                                   const int64_t *__restrict__ boff, int count) {
+  const int p = entry_of(boff, count, blockIdx.x);
+  const BatchProb &P = bp[p];
+  const int64_t lb = blockIdx.x - boff[p], nb = boff[p + 1] - boff[p];
+  lp_input_body(P.n, P.N, P.X, P.ldx, P.F0, P.mc, P.lp_mx, lb, nb, (int)lb);
+}
+
+__global__ void kb_lp_scale(const BatchProb *__restrict__ bp, int count, int k) {
+  const int p = blockIdx.x * 64 + threadIdx.x;
+  if (p < count) lp_scale_body(k, bp[p].lp_mx, bp[p].lp_s, bp[p].lp_mult);
+}
+
+template <bool BF16>
+__global__ __launch_bounds__(512, 2) void kb_cell(const BatchProb *__restrict__ bp,
+                                                  const BatchItem *__restrict__ items, int k) {
+  const BatchItem it = items[blockIdx.x];
+  const BatchProb &P = bp[it.p];
+  const StepBufs b = step_bufs(P, k);
+  CellFinishF f;
+  f.dinv = P.dinv;
+  f.c1 = b.c1; f.c2 = b.c2; f.c3 = b.c3;
+  f.Yp = b.Yp; f.ldyp = P.mc;
+  f.Out = b.Out; f.ldo = P.mc;
+  f.mult = b.mult; f.mx = b.mx;
+  cell_gemm_lp_body<BF16>(BF16 ? P.Hp16 : (const void *)P.Hp32, P.dofp, P.flagp, it.c, b.Xin, P.mc,
+                          P.R32, P.mc, P.N, f, blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void kb_enr_part(const BatchProb *__restrict__ bp,
+                                                   const BatchItem *__restrict__ items, int k) {
+  const BatchItem it = items[blockIdx.x];
+  const BatchProb &P = bp[it.p];
+  const float *Xin = (k & 1) ? P.F1 : P.F0;
+  enr_part_f32_body(P.HT32, P.MT32, P.toff, P.tld, P.eptr, P.dofp, P.ecells[it.c], Xin, P.mc, 1.f,
+                    P.R32, P.mc, P.dinv, -1.f, P.P32, P.mc, P.N);
+}
+
+__global__ __launch_bounds__(64) void kb_enr_reduce(const BatchProb *__restrict__ bp,
+                                                    const int64_t *__restrict__ aoff, int count,
+                                                    int k) {
+  const int p = entry_of(aoff, count, blockIdx.y);
+  const BatchProb &P = bp[p];
+  const int col = blockIdx.x * 64 + threadIdx.x;
+  if (col >= P.N) return;
+  const float *Xin = (k & 1) ? P.F1 : P.F0;
+  enr_reduce_f32_elem((int)P.n_e, P.aptr, P.alist, P.P32, P.mc, P.Hmod, Xin + P.n_h * P.mc, P.mc,
+                      P.Wb, P.mc, (int)(blockIdx.y - aoff[p]), col);
+}
+
+// z = S^-1 w, in the summation order of the single-problem FP64 kernel
+__global__ __launch_bounds__(64) void kb_schur(const BatchProb *__restrict__ bp,
+                                               const int64_t *__restrict__ aoff, int count) {
+  const int p = entry_of(aoff, count, blockIdx.y);
+  const BatchProb &P = bp[p];
+  const int col = blockIdx.x * 64 + threadIdx.x;
+  if (col >= P.N) return;
+  const int al = (int)(blockIdx.y - aoff[p]);
+  const double *drow = P.Sinv + (int64_t)al * P.n_e;
+  double acc = 0.0, sd = 0.0;
+  for (int be = 0; be < P.n_e; ++be) sd += drow[be] * P.Wb[(int64_t)be * P.mc + col];
+  acc += sd;
+  P.Zb[(int64_t)al * P.mc + col] = acc;
+}
+
+__global__ __launch_bounds__(256) void kb_enr_q(const BatchProb *__restrict__ bp,
+                                                const BatchItem *__restrict__ items, int k) {
+  const BatchItem it = items[blockIdx.x];
+  const BatchProb &P = bp[it.p];
+  const float *Xin = (k & 1) ? P.F1 : P.F0;
+  enr_q_f32_body(P.Hec32, P.Mec32, P.eptr, P.eidx, P.ecells[it.c], it.c, Xin + P.n_h * P.mc, P.mc,
+                 1.f, P.Zb, P.mc, -1.f, P.Q32, P.mc, P.N);
+}
+
+__global__ __launch_bounds__(256) void kb_epilogue(const BatchProb *__restrict__ bp,
+                                                   const int64_t *__restrict__ eoff, int count,
+                                                   int k) {
+  const int p = entry_of(eoff, count, blockIdx.x);
+  const BatchProb &P = bp[p];
+  const StepBufs b = step_bufs(P, k);
+  EpiArgsF g;
+  g.n_h = P.n_h; g.n_e = P.n_e; g.N = P.N;
+  g.rows = P.regrows; g.nrows = P.nregrows;
+  g.dinv = P.dinv;
+  g.R = P.R32; g.ldr = P.mc;
+  if (P.n_e > 0) { g.qptr = P.qptr; g.qidx = P.qidx; g.Q = P.Q32; g.ldq = P.mc; }
+  g.Ee = P.Zb; g.lde = P.mc;
+  g.c1 = b.c1; g.Yk = b.Xin; g.ldyk = P.mc; g.c2 = b.c2;
+  g.Yp = b.Yp; g.ldyp = P.mc; g.c3 = b.c3;
+  g.Out = b.Out; g.ldo = P.mc;
+  g.mult = b.mult; g.mx = b.mx;
+  const int64_t lb = blockIdx.x - eoff[p], nb = eoff[p + 1] - eoff[p];
+  epilogue_f32_body(g, lb, nb, (int)lb);
+}
+
+__global__ __launch_bounds__(256) void kb_lp_output(const BatchProb *__restrict__ bp,
+                                                    const int64_t *__restrict__ boff, int count,
+                                                    int m) {
+  const int p = entry_of(boff, count, blockIdx.x);
+  const BatchProb &P = bp[p];
+  const int64_t lb = blockIdx.x - boff[p], nb = boff[p + 1] - boff[p];
+  lp_output_body(P.n, P.N, (m & 1) ? P.F1 : P.F0, P.mc, P.lp_s + m, P.Y, P.ldy, lb, nb);
+}
+
+// ---------------------------------------------------------------------------
+hipError_t launch_b_lp_begin(hipStream_t s, const BatchProb *bp, int count, int nslots,
+                             const int64_t *boff, int64_t nblocks) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(kb_lp_reset, dim3((nslots + 255) / 256, count), dim3(256), 0, s, bp, nslots);
+  if (nblocks > 0)
+    hipLaunchKernelGGL(kb_lp_input, dim3((unsigned)nblocks), dim3(64, 4), 0, s, bp, boff, count);
+  hipLaunchKernelGGL(kb_lp_scale, dim3((count + 63) / 64), dim3(64), 0, s, bp, count, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_b_lp_scale(hipStream_t s, const BatchProb *bp, int count, int k) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(kb_lp_scale, dim3((count + 63) / 64), dim3(64), 0, s, bp, count, k);
+  return hipGetLastError();
+}
+
+hipError_t launch_b_cell(hipStream_t s, bool bf16, const BatchProb *bp, const BatchItem *items,
+                         int nitems, int k) {
+  if (nitems <= 0) return hipSuccess;
+  if (bf16)
+    hipLaunchKernelGGL(kb_cell<true>, dim3(nitems), dim3(512), 0, s, bp, items, k);
+  else
+    hipLaunchKernelGGL(kb_cell<false>, dim3(nitems), dim3(512), 0, s, bp, items, k);
+  return hipGetLastError();
+}
+
+hipError_t launch_b_enr(hipStream_t s, const BatchProb *bp, int count, const BatchItem *eitems,
+                        int neitems, const int64_t *aoff, int64_t nalpha, int maxN, int kmax,
+                        int k) {
+  if (neitems <= 0 || nalpha <= 0 || maxN <= 0) return hipSuccess;
+  hipLaunchKernelGGL(kb_enr_part, dim3(neitems), dim3(256), 0, s, bp, eitems, k);
+  const dim3 rgrid((maxN + 63) / 64, (unsigned)nalpha);
+  hipLaunchKernelGGL(kb_enr_reduce, rgrid, dim3(64), 0, s, bp, aoff, count, k);
+  hipLaunchKernelGGL(kb_schur, rgrid, dim3(64), 0, s, bp, aoff, count);
+  const size_t shm = (size_t)2 * ((kmax + 3) & ~3) * 16 * sizeof(float);
+  hipLaunchKernelGGL(kb_enr_q, dim3(neitems), dim3(256), shm, s, bp, eitems, k);
+  return hipGetLastError();
+}
+
+hipError_t prepare_b_enr(int kmax) {
+  const size_t shm = (size_t)2 * ((kmax + 3) & ~3) * 16 * sizeof(float);
+  if (shm <= 65536) return hipSuccess;
+  return hipFuncSetAttribute((const void *)kb_enr_q, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)shm);
+}
+
+hipError_t launch_b_epilogue(hipStream_t s, const BatchProb *bp, int count, const int64_t *eoff,
+                             int64_t nblocks, int k) {
+  if (nblocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(kb_epilogue, dim3((unsigned)nblocks), dim3(64, 4), 0, s, bp, eoff, count, k);
+  return hipGetLastError();
+}
+
+hipError_t launch_b_lp_output(hipStream_t s, const BatchProb *bp, int count, const int64_t *boff,
+                              int64_t nblocks, int m) {
+  if (nblocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(kb_lp_output, dim3((unsigned)nblocks), dim3(64, 4), 0, s, bp, boff, count, m);
+  return hipGetLastError();
+}
+
+}  // namespace cf

@@ -190,6 +190,63 @@ hipError_t launch_lp_scale(hipStream_t s, int k, const unsigned *mx, int32_t *se
 hipError_t launch_lp_output(hipStream_t s, int64_t rows, int N, const float *Z, int64_t ldz,
                             const int32_t *sexp_m, double *Y, int64_t ldy);
 
+// ---- batched reduced-precision recurrence (cf_batch.hip)
+// One entry of a batch: the device operator of its problem (shared by the
+// entries of one problem), its own FP32 workspace (ld = mc) and the per-call
+// block pointers and interval.  The step-k buffers follow the single-problem
+// driver: Z_k in F0 (k even) or F1 (k odd).
+struct BatchProb {
+  const float *Hp32;
+  const void *Hp16;
+  const int32_t *dofp;
+  const uint8_t *flagp;
+  const float *HT32, *MT32;
+  const int64_t *toff;
+  const int32_t *tld;
+  const int64_t *eptr;
+  const int32_t *ecells;
+  const float *Hec32, *Mec32;
+  const int32_t *eidx;
+  const int64_t *aptr;
+  const int32_t *alist;
+  const double *Hmod, *Sinv, *dinv;
+  const int32_t *qptr, *qidx, *regrows;
+  int64_t nregrows, n_h, n_e, n;
+  float *R32, *P32, *Q32, *F0, *F1;
+  double *Wb, *Zb;
+  int64_t mc;
+  unsigned *lp_mx;
+  int32_t *lp_s;
+  float *lp_mult;
+  const double *X;
+  int64_t ldx;
+  double *Y;
+  int64_t ldy;
+  int N;
+  double e, cc;   // t(H~) = e H~ - cc I
+};
+// Work item of a batched launch: entry p and a cell (or enriched-cell position).
+struct BatchItem {
+  int32_t p, c;
+};
+// Launchers; boff / aoff / eoff are prefix sums (count + 1 entries) of the
+// row blocks (4 rows each), enrichment rows and epilogue blocks per entry.
+hipError_t launch_b_lp_begin(hipStream_t s, const BatchProb *bp, int count, int nslots,
+                             const int64_t *boff, int64_t nblocks);
+hipError_t launch_b_lp_scale(hipStream_t s, const BatchProb *bp, int count, int k);
+hipError_t launch_b_cell(hipStream_t s, bool bf16, const BatchProb *bp, const BatchItem *items,
+                         int nitems, int k);
+hipError_t launch_b_enr(hipStream_t s, const BatchProb *bp, int count, const BatchItem *eitems,
+                        int neitems, const int64_t *aoff, int64_t nalpha, int maxN, int kmax,
+                        int k);
+// Raise the dynamic-LDS limit of the batched transposed-coupling kernel for
+// the largest per-cell enrichment count (call before any launch or capture).
+hipError_t prepare_b_enr(int kmax);
+hipError_t launch_b_epilogue(hipStream_t s, const BatchProb *bp, int count, const int64_t *eoff,
+                             int64_t nblocks, int k);
+hipError_t launch_b_lp_output(hipStream_t s, const BatchProb *bp, int count, const int64_t *boff,
+                              int64_t nblocks, int m);
+
 // ---- dense kernels (cf_dense.hip)
 // Gram modes: GRAM_SYM  full product, result symmetrised (G + G^T)/2
 //             GRAM_UPPER upper tiles only (A = B), mirrored

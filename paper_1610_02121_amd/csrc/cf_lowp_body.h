@@ -1,0 +1,455 @@
+// Device bodies of the reduced-precision (FP32 / BF16-input) operator
+// kernels, shared by the single-problem kernels (cf_lowp.hip) and the batched
+// kernels (cf_batch.hip), so that both compute bit-identical results.  Each
+// body takes its work item (cell, row block) explicitly instead of reading
+// blockIdx.
+//
+// MFMA fragment layouts (wave of 64 lanes, l = lane):
+//   v_mfma_f32_16x16x4f32:   A[l%16][l/16], B[l/16][l%16], D[4(l/16)+r][l%16]
+//   v_mfma_f32_16x16x32_bf16: A[l%16][8(l/16)+i], B[8(l/16)+i][l%16] (i < 8),
+//                             D[4(l/16)+r][l%16]
+#pragma once
+
+#include "cf_kernels.h"
+
+namespace cf {
+namespace lowp {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ f4 mfma_f32(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4 mfma_bf16(bf8 a, bf8 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4 f4zero() { f4 z = {0.f, 0.f, 0.f, 0.f}; return z; }
+
+// max of |v| that keeps NaN (a NaN compares above every finite value and Inf
+// as unsigned float bits)
+__device__ __forceinline__ float absmax(float m, float v) {
+  const float a = fabsf(v);
+  return (a > m || a != a) ? a : m;
+}
+// Block-wide absmax of m, then one atomic max into mx[slot % MX_SLOTS]
+// (non-negative floats order like their bit patterns; spreading the blocks
+// over MX_SLOTS words keeps the atomics from queueing on one address).  Every
+// thread of the block must call it; wbuf holds one float per wave.
+__device__ __forceinline__ void gather_max(unsigned *mx, float m, float *wbuf, int slot) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) m = absmax(m, __shfl_xor(m, off));
+  const int t = threadIdx.x + blockDim.x * threadIdx.y;
+  const int nw = (blockDim.x * blockDim.y) >> 6;
+  if ((t & 63) == 0) wbuf[t >> 6] = m;
+  __syncthreads();
+  if (t == 0) {
+    for (int i = 1; i < nw; ++i) m = absmax(m, wbuf[i]);
+    atomicMax(mx + (slot % MX_SLOTS), __float_as_uint(m));
+  }
+}
+
+
+// ---------------------------------------------------------------------------
+// Cell products, FP32 vectors (same algorithm as k_cell_gemm):
+//   BF16 = false: cell matrices FP32, v_mfma_f32_16x16x4f32, 32 k-steps
+//   BF16 = true:  cell matrices BF16 (row-major), the gathered tile is converted
+//                 to BF16 in LDS (stored column-major so that a lane's 8
+//                 consecutive k values are contiguous), v_mfma_f32_16x16x32_bf16,
+//                 4 k-steps
+// ---------------------------------------------------------------------------
+// One cell per workgroup of 512 threads; slot picks the max-gathering word.
+template <bool BF16>
+__device__ __forceinline__ void cell_gemm_lp_body(
+    const void *__restrict__ Hv, const int32_t *__restrict__ dofp,
+    const uint8_t *__restrict__ flagp, const int cell,
+    const float *__restrict__ X, int64_t ldx, float *__restrict__ Y, int64_t ldy, int N,
+    const CellFinishF &f, int slot) {
+  constexpr int NT = CELL_NT;
+  constexpr int LDX = NT + 16;               // FP32 tile, row-major [k][col]
+  constexpr int LDT = NPAD + 8;              // BF16 tile, column-major [col][k]
+  constexpr int PF = NPAD * NT / 512;
+  constexpr int RPP = 512 / NT;
+  __shared__ float xs[BF16 ? 1 : NPAD * LDX];
+  __shared__ __bf16 xt[BF16 ? NT * LDT : 8];
+  __shared__ float xk_tile[BF16 ? NPAD * NT : 1];   // FP32 copy for the finishing step
+  __shared__ int32_t sdof[NPAD];
+  __shared__ uint8_t sflag[NPAD];
+
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int li = lane & 15, kq = lane >> 4;
+  if (tid < NPAD) {
+    sdof[tid] = dofp[(int64_t)cell * NPAD + tid];
+    sflag[tid] = flagp[(int64_t)cell * NPAD + tid];
+  }
+  float a32[BF16 ? 1 : 32];
+  bf8 a16[BF16 ? 4 : 1];
+  if constexpr (BF16) {
+    const __bf16 *Hc = (const __bf16 *)Hv + (int64_t)cell * NPAD * NPAD;
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks)
+      a16[ks] = *(const bf8 *)(Hc + (16 * w + li) * NPAD + 32 * ks + 8 * kq);
+  } else {
+    const float *Hc = (const float *)Hv + (int64_t)cell * NPAD * NPAD;
+#pragma unroll
+    for (int ks = 0; ks < 32; ++ks) a32[ks] = Hc[(4 * ks + kq) * NPAD + 16 * w + li];
+  }
+  __syncthreads();
+
+  const int gj = tid % NT, gr = tid / NT;
+  int gd[PF];
+#pragma unroll
+  for (int p = 0; p < PF; ++p) gd[p] = sdof[gr + p * RPP];
+  float pf[PF];
+#pragma unroll
+  for (int p = 0; p < PF; ++p) pf[p] = (gd[p] >= 0 && gj < N) ? X[(int64_t)gd[p] * ldx + gj] : 0.f;
+  const bool finish = f.Out != nullptr;
+  float fc1 = f.c1, fc2 = f.c2, fc3 = f.c3;
+  if (f.mult) {
+    const float al = f.mult[0], be = f.mult[1];
+    fc1 *= al; fc2 *= al; fc3 *= be;
+  }
+  float omax = 0.f;
+  int od[4];
+  bool ofirst[4], ofin[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int row = 16 * w + 4 * kq + r;
+    od[r] = sdof[row];
+    ofirst[r] = (sflag[row] & CELL_FIRST) != 0;
+    ofin[r] = finish && od[r] >= 0 && (sflag[row] & CELL_FINISH) != 0;
+  }
+
+  for (int c0 = 0; c0 < N; c0 += NT) {
+    const int ncol = min(NT, N - c0);
+#pragma unroll
+    for (int p = 0; p < PF; ++p) {
+      const int row = gr + p * RPP;
+      if constexpr (BF16) {
+        xt[gj * LDT + row] = (__bf16)pf[p];
+        xk_tile[row * NT + gj] = pf[p];
+      } else {
+        xs[row * LDX + gj] = pf[p];
+      }
+    }
+    __syncthreads();
+    const int c1 = c0 + NT;
+    if (c1 < N) {
+#pragma unroll
+      for (int p = 0; p < PF; ++p)
+        pf[p] = (gd[p] >= 0 && c1 + gj < N) ? X[(int64_t)gd[p] * ldx + c1 + gj] : 0.f;
+    }
+    const bool cv = li < ncol;
+    float yo[4], yp[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      yo[r] = (od[r] >= 0 && !ofirst[r] && cv) ? Y[(int64_t)od[r] * ldy + c0 + li] : 0.f;
+      yp[r] = (ofin[r] && f.Yp && cv) ? f.Yp[(int64_t)od[r] * f.ldyp + c0 + li] : 0.f;
+    }
+    f4 acc = f4zero();
+    if constexpr (BF16) {
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks)
+        acc = mfma_bf16(a16[ks], *(const bf8 *)(xt + li * LDT + 32 * ks + 8 * kq), acc);
+    } else {
+#pragma unroll
+      for (int ks = 0; ks < 32; ++ks) acc = mfma_f32(a32[ks], xs[(4 * ks + kq) * LDX + li], acc);
+    }
+    if (cv) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        if (od[r] < 0) continue;
+        const float v = acc[r] + yo[r];
+        if (ofin[r]) {
+          const int row = 16 * w + 4 * kq + r;
+          float xk;
+          if constexpr (BF16) xk = xk_tile[row * NT + li];
+          else xk = xs[row * LDX + li];
+          const float o = fc1 * (float)f.dinv[od[r]] * v + fc2 * xk + fc3 * yp[r];
+          f.Out[(int64_t)od[r] * f.ldo + c0 + li] = o;
+          omax = absmax(omax, o);
+        } else {
+          Y[(int64_t)od[r] * ldy + c0 + li] = v;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (f.mx) gather_max(f.mx, omax, (float *)sdof, slot);   // sdof is free after the tile loop
+}
+
+// ---------------------------------------------------------------------------
+// Coupling partials, FP32 (as k_enr_part; FP32 blocks HT, MT).
+// ---------------------------------------------------------------------------
+// One enriched cell per workgroup of 256 threads.
+__device__ __forceinline__ void enr_part_f32_body(
+    const float *__restrict__ HT, const float *__restrict__ MT,
+    const int64_t *__restrict__ toff, const int32_t *__restrict__ tld,
+    const int64_t *__restrict__ eptr, const int32_t *__restrict__ dofp,
+    const int cell, const float *__restrict__ X, int64_t ldx, float cH,
+    const float *__restrict__ R, int64_t ldr, const double *__restrict__ rs, float cM,
+    float *__restrict__ P, int64_t ldp, int N) {
+  constexpr int PT = 16, LDX = 32;
+  constexpr int PF = NPAD * PT / 256;
+  constexpr int RPP = 256 / PT;
+  __shared__ float xs[NPAD * LDX];
+  __shared__ float rsm[NPAD * LDX];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int li = lane & 15, kq = lane >> 4;
+  const int gj = tid % PT, gr = tid / PT;
+  int gd[PF];
+  float gsc[PF];
+#pragma unroll
+  for (int p = 0; p < PF; ++p) {
+    gd[p] = dofp[(int64_t)cell * NPAD + gr + p * RPP];
+    gsc[p] = (rs && gd[p] >= 0) ? (float)rs[gd[p]] : 1.f;
+  }
+  float px[PF], pr[PF];
+#pragma unroll
+  for (int p = 0; p < PF; ++p) {
+    const bool v = gd[p] >= 0 && gj < N;
+    px[p] = (X && v) ? X[(int64_t)gd[p] * ldx + gj] : 0.f;
+    pr[p] = (R && v) ? R[(int64_t)gd[p] * ldr + gj] * gsc[p] : 0.f;
+  }
+  const int64_t k0 = eptr[cell];
+  const int na = (int)(eptr[cell + 1] - k0);
+  const int nap = tld[cell];
+  const int nmb = nap >> 4;
+  const float *ht = X ? HT + toff[cell] : nullptr;
+  const float *mt = R ? MT + toff[cell] : nullptr;
+  for (int c0 = 0; c0 < N; c0 += PT) {
+    const int ncol = min(PT, N - c0);
+#pragma unroll
+    for (int p = 0; p < PF; ++p) {
+      xs[(gr + p * RPP) * LDX + gj] = px[p];
+      rsm[(gr + p * RPP) * LDX + gj] = pr[p];
+    }
+    __syncthreads();
+    const int c1 = c0 + PT;
+    if (c1 < N) {
+#pragma unroll
+      for (int p = 0; p < PF; ++p) {
+        const bool v = gd[p] >= 0 && c1 + gj < N;
+        px[p] = (X && v) ? X[(int64_t)gd[p] * ldx + c1 + gj] : 0.f;
+        pr[p] = (R && v) ? R[(int64_t)gd[p] * ldr + c1 + gj] * gsc[p] : 0.f;
+      }
+    }
+    for (int mb = w; mb < nmb; mb += 4) {
+      f4 accH = f4zero(), accM = f4zero();
+      if (ht) {
+#pragma unroll 8
+        for (int ks = 0; ks < 32; ++ks)
+          accH = mfma_f32(ht[(int64_t)(4 * ks + kq) * nap + 16 * mb + li],
+                          xs[(4 * ks + kq) * LDX + li], accH);
+      }
+      if (mt) {
+#pragma unroll 8
+        for (int ks = 0; ks < 32; ++ks)
+          accM = mfma_f32(mt[(int64_t)(4 * ks + kq) * nap + 16 * mb + li],
+                          rsm[(4 * ks + kq) * LDX + li], accM);
+      }
+      if (li < ncol) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int orow = 16 * mb + 4 * kq + r;
+          if (orow < na) P[(k0 + orow) * ldp + c0 + li] = cH * accH[r] + cM * accM[r];
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Transposed coupling products, FP32 (as k_enr_q): U rows FP32, V rows FP64
+// (the Schur-solve output), products in FP32.
+// ---------------------------------------------------------------------------
+// One enriched cell per workgroup of 256 threads; its rows of Q start at
+// 128 * qblock (the cell's position in the enriched-cell list).  Dynamic LDS:
+// 2 * round_up(kmax, 4) * 16 floats.
+__device__ __forceinline__ void enr_q_f32_body(
+    const float *__restrict__ Hec, const float *__restrict__ Mec,
+    const int64_t *__restrict__ eptr, const int32_t *__restrict__ eidx,
+    const int cell, const int qblock, const float *__restrict__ U, int64_t ldu, float cU,
+    const double *__restrict__ V, int64_t ldv, float cV, float *__restrict__ Q, int64_t ldq,
+    int N) {
+  extern __shared__ float zsf[];
+  constexpr int PT = 16, LDZ = 16;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int li = lane & 15, kq = lane >> 4;
+  const int64_t k0 = eptr[cell];
+  const int na = (int)(eptr[cell + 1] - k0);
+  const int K4 = (na + 3) & ~3;
+  const int nks = K4 / 4;
+  float *qb = Q + ((int64_t)qblock * NPAD) * ldq;
+  for (int c0 = 0; c0 < N; c0 += PT) {
+    const int ncol = min(PT, N - c0);
+    for (int idx = tid; idx < K4 * PT; idx += 256) {
+      const int k = idx / PT, j = idx % PT;
+      const bool v = k < na && j < ncol;
+      const int64_t al = v ? eidx[k0 + k] : 0;
+      zsf[k * LDZ + j] = (U && v) ? cU * U[al * ldu + c0 + j] : 0.f;
+      zsf[(K4 + k) * LDZ + j] = (V && v) ? cV * (float)V[al * ldv + c0 + j] : 0.f;
+    }
+    __syncthreads();
+    f4 acc0 = f4zero(), acc1 = f4zero();
+    if (U) {
+      for (int ks = 0; ks < nks; ++ks) {
+        const int k = 4 * ks + kq;
+        const float *row = Hec + (k0 + min(k, na - 1)) * NPAD + 32 * w;
+        const float a0 = k < na ? row[li] : 0.f, a1 = k < na ? row[16 + li] : 0.f;
+        const float b = zsf[k * LDZ + li];
+        acc0 = mfma_f32(a0, b, acc0);
+        acc1 = mfma_f32(a1, b, acc1);
+      }
+    }
+    if (V) {
+      for (int ks = 0; ks < nks; ++ks) {
+        const int k = 4 * ks + kq;
+        const float *row = Mec + (k0 + min(k, na - 1)) * NPAD + 32 * w;
+        const float a0 = k < na ? row[li] : 0.f, a1 = k < na ? row[16 + li] : 0.f;
+        const float b = zsf[(K4 + k) * LDZ + li];
+        acc0 = mfma_f32(a0, b, acc0);
+        acc1 = mfma_f32(a1, b, acc1);
+      }
+    }
+    if (li < ncol) {
+      float *q = qb + c0 + li;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        q[(int64_t)(32 * w + 4 * kq + r) * ldq] = acc0[r];
+        q[(int64_t)(32 * w + 16 + 4 * kq + r) * ldq] = acc1[r];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Enrichment rows from FP32 partials, accumulated in FP64:
+//   out[al,:] = sum_{k in list(al)} P[k,:] + sum_be Dn[al,be] Zd[be,:]     (Zd FP32)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void enr_reduce_f32_elem(
+    int n_e, const int64_t *__restrict__ aptr, const int32_t *__restrict__ alist,
+    const float *__restrict__ P, int64_t ldp, const double *__restrict__ Dn,
+    const float *__restrict__ Zd, int64_t ldzd, double *__restrict__ out, int64_t ldo, int al,
+    int col) {
+  double acc = 0.0;
+  for (int64_t k = aptr[al]; k < aptr[al + 1]; ++k) acc += (double)P[(int64_t)alist[k] * ldp + col];
+  const double *drow = Dn + (int64_t)al * n_e;
+  double sd = 0.0;
+  for (int be = 0; be < n_e; ++be) sd += drow[be] * (double)Zd[(int64_t)be * ldzd + col];
+  out[(int64_t)al * ldo + col] = acc + sd;
+}
+
+// ---------------------------------------------------------------------------
+// Epilogue, FP32 blocks (as k_epilogue): rows = listed classical rows, then the
+// enrichment rows (Ee FP64, converted).
+// ---------------------------------------------------------------------------
+// Block of 64 x 4 threads; this block takes rows t = 4 b0 + threadIdx.y,
+// t += 4 bstride.
+__device__ __forceinline__ void epilogue_f32_body(const EpiArgsF &g, int64_t b0, int64_t bstride,
+                                                  int slot) {
+  const int64_t ncls = g.rows ? g.nrows : g.n_h;
+  const int64_t nt = ncls + g.n_e;
+  float gc1 = g.c1, gc2 = g.c2, gc3 = g.c3;
+  if (g.mult) {
+    const float al = g.mult[0], be = g.mult[1];
+    gc1 *= al; gc2 *= al; gc3 *= be;
+  }
+  float omax = 0.f;
+  for (int64_t t = b0 * 4 + threadIdx.y; t < nt; t += bstride * 4) {
+    const bool cls = t < ncls;
+    const int64_t i = cls ? (g.rows ? (int64_t)g.rows[t] : t) : g.n_h + (t - ncls);
+    float dr = 1.f;
+    int p0 = 0, p1 = 0;
+    if (cls) {
+      if (g.dinv) dr = (float)g.dinv[i];
+      if (g.qptr) { p0 = g.qptr[i]; p1 = g.qptr[i + 1]; }
+    }
+    for (int j = threadIdx.x; j < g.N; j += 64) {
+      float v;
+      if (cls) {
+        float s = g.R[i * g.ldr + j];
+        for (int p = p0; p < p1; ++p) s += g.Q[(int64_t)g.qidx[p] * g.ldq + j];
+        v = dr * s;
+      } else {
+        v = (float)g.Ee[(i - g.n_h) * g.lde + j];
+      }
+      v *= gc1;
+      if (g.Yk) v += gc2 * g.Yk[i * g.ldyk + j];
+      if (g.Yp) v += gc3 * g.Yp[i * g.ldyp + j];
+      g.Out[i * g.ldo + j] = v;
+      omax = absmax(omax, v);
+    }
+  }
+  if (g.mx) {
+    // every thread of the block reaches this point (the row loop has no early exit)
+    __shared__ float wbuf[4];
+    gather_max(g.mx, omax, wbuf, slot);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Scaled recurrence bookkeeping
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void lp_input_body(int64_t rows, int N, const double *__restrict__ X,
+                                              int64_t ldx, float *__restrict__ Z, int64_t ldz,
+                                              unsigned *__restrict__ mx0, int64_t b0,
+                                              int64_t bstride, int slot) {
+  float m = 0.f;
+  for (int64_t i = b0 * 4 + threadIdx.y; i < rows; i += bstride * 4)
+    for (int j = threadIdx.x; j < N; j += 64) {
+      const float z = (float)X[i * ldx + j];
+      Z[i * ldz + j] = z;
+      m = absmax(m, z);
+    }
+  __shared__ float wbuf[4];
+  gather_max(mx0, m, wbuf, slot);
+}
+
+// Scale of step k (which forms Z_k+1 from Z_k, Z_k-1): the exponent of
+// max|Y_k+1| is predicted from the last two iterates, E_k+1 ~ 2 E_k - E_k-1
+// (Chebyshev growth per step settles to a constant), and s_k+1 is set to it,
+// so that max|Z_k+1| stays near 1; at most 60 binades from s_k.  Step 0 is not
+// scaled.  A zero or non-finite maximum keeps the previous scale.
+__device__ __forceinline__ void lp_scale_body(int k, const unsigned *__restrict__ mx,
+                                              int32_t *__restrict__ sexp, float *__restrict__ mult) {
+  if (k == 0) {
+    sexp[0] = 0;
+    sexp[1] = 0;
+    mult[0] = 1.f;
+    mult[1] = 1.f;
+    return;
+  }
+  const int sk = sexp[k], sp = sexp[k - 1];
+  unsigned uk = 0u, up = 0u;
+  for (int i = 0; i < MX_SLOTS; ++i) {
+    uk = max(uk, mx[k * MX_SLOTS + i]);
+    up = max(up, mx[(k - 1) * MX_SLOTS + i]);
+  }
+  const float mk = __uint_as_float(uk), mp = __uint_as_float(up);
+  int sn = sk;
+  if (mk > 0.f && mp > 0.f && isfinite(mk) && isfinite(mp)) {
+    int ek, ep;
+    (void)frexpf(mk, &ek);
+    (void)frexpf(mp, &ep);
+    const int pred = 2 * (ek + sk) - (ep + sp);
+    sn = min(max(pred, sk - 60), sk + 60);
+  }
+  sexp[k + 1] = sn;
+  mult[2 * k] = ldexpf(1.f, sk - sn);
+  mult[2 * k + 1] = ldexpf(1.f, sp - sn);
+}
+
+__device__ __forceinline__ void lp_output_body(int64_t rows, int N, const float *__restrict__ Z,
+                                               int64_t ldz, const int32_t *__restrict__ sexp_m,
+                                               double *__restrict__ Y, int64_t ldy, int64_t b0,
+                                               int64_t bstride) {
+  const int sm = *sexp_m;
+  for (int64_t i = b0 * 4 + threadIdx.y; i < rows; i += bstride * 4)
+    for (int j = threadIdx.x; j < N; j += 64) Y[i * ldy + j] = ldexp((double)Z[i * ldz + j], sm);
+}
+
+}  // namespace lowp
+}  // namespace cf

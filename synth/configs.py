@@ -142,3 +142,28 @@ WORKLOADS = {
     "hydrogen-8c": dict(N=16, m=20, wanted=14),
     "si30-24c": dict(N=260, m=40, wanted=210),
 }
+
+
+def batch_cluster(n_atoms: int, seed: int = 0) -> Problem:
+    """One problem of the batched workload: an n_atoms Si cluster (1..8) in a
+    cube of half-width R_cluster + 12 Bohr with 6 + round(6 (n_atoms - 1) / 7)
+    degree-4 cells per axis, r_c = 8, nine Slater enrichments per atom."""
+    sites = diamond_sites(n_atoms)
+    R = float(np.abs(sites).max()) if n_atoms > 1 else 0.0
+    nc = 6 + round(6 * (n_atoms - 1) / 7)
+    return si_cluster(n_atoms=n_atoms, length=2.0 * (R + 12.0), nc=nc, p=4, r_c=8.0,
+                      seed=1000 + n_atoms + seed)
+
+
+def batch_workload(count: int = 256, seed: int = 0, max_atoms: int = 8):
+    """Batched workload: `count` entries with atom counts drawn U{1..max_atoms}
+    (seeded), N = 16 + round(48 (n_atoms - 1) / 7) vectors, filter degree 40.
+    The entries of one atom count share one generated problem (the pool), so
+    the batch holds max_atoms distinct operators and `count` independent
+    blocks and intervals.  Returns (pool dict n_atoms -> Problem, list of
+    n_atoms per entry, list of N per entry)."""
+    rng = np.random.default_rng(seed)
+    atoms = [int(a) for a in rng.integers(1, max_atoms + 1, size=count)]
+    pool = {a: batch_cluster(a, seed) for a in sorted(set(atoms))}
+    Ns = [16 + round(48 * (a - 1) / 7) for a in atoms]
+    return pool, atoms, Ns

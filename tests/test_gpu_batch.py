@@ -1,0 +1,161 @@
+"""Batches of independent problems (chebfilter_*_batch) against the
+single-problem entry points and the oracle.
+
+The batched reduced-precision filter runs every entry through the same device
+bodies as the single-problem kernels, in merged launches; its result must be
+bit for bit the single-problem result of the same precision (which
+test_gpu_lowp pins to the oracle).  One entry is also checked against the FP64
+oracle directly, with the FP32 bound of test_gpu_lowp (10 u32 kappa(M^E) per
+step).  The batch mixes problems, repeats problems (shared operator, separate
+blocks), column counts and intervals.
+"""
+import numpy as np
+import pytest
+
+from oracle.filters import recurrence_filter
+from oracle.operators import Operators
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+U32 = 2.0 ** -24
+MAXC = 40
+
+
+def dev(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+_STATE = {}
+
+
+def state(tiny_enriched, hydrogen_small, si_small):
+    """(batch, entry problems, single contexts by problem id, N, intervals)."""
+    if "b" not in _STATE:
+        from paper_1610_02121_amd import Batch, Context
+        probs = [tiny_enriched, hydrogen_small, si_small, hydrogen_small, tiny_enriched, si_small,
+                 hydrogen_small]
+        Ns = [5, 16, 37, 1, 7, 40, 23]
+        singles = {}
+        for p in probs:
+            if id(p) not in singles:
+                singles[id(p)] = Context(p, max_cols=MAXC)
+        batch = Batch(probs, max_cols=MAXC)
+        # per-entry damping interval from the entry's Lanczos bound
+        v0 = [dev(np.random.default_rng(40 + i).standard_normal(p.n)).reshape(-1)
+              for i, p in enumerate(probs)]
+        lo, hi = batch.lanczos_bounds(v0, 10)
+        ab = [(l + (0.05 + 0.05 * i) * (h - l), h) for i, (l, h) in enumerate(zip(lo, hi))]
+        _STATE.update(b=batch, probs=probs, singles=singles, Ns=Ns, ab=ab, v0=v0)
+    s = _STATE
+    return s["b"], s["probs"], s["singles"], s["Ns"], s["ab"]
+
+
+def blocks(probs, Ns, seed):
+    return [np.random.default_rng(seed + i).standard_normal((p.n, N))
+            for i, (p, N) in enumerate(zip(probs, Ns))]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_batch_filter_equals_single(prec, use_graph, tiny_enriched, hydrogen_small, si_small):
+    print(f"[batch filter] {prec} graph={use_graph}", flush=True)
+    batch, probs, singles, Ns, ab = state(tiny_enriched, hydrogen_small, si_small)
+    m = 9
+    Xs = blocks(probs, Ns, 50)
+    Xd = [dev(x) for x in Xs]
+    Yb = batch.filter(Xd, m, [a for a, _ in ab], [b for _, b in ab], prec=prec, use_graph=use_graph)
+    Yb = [host(y) for y in Yb]
+    for i, p in enumerate(probs):
+        a, b = ab[i]
+        Ys = host(singles[id(p)].filter(Xd[i], m, a, b, prec=prec))
+        assert np.isfinite(Yb[i]).all()
+        assert np.array_equal(Yb[i], Ys), i
+
+
+def test_batch_graph_replays(tiny_enriched, hydrogen_small, si_small):
+    """One captured graph replayed with new blocks and intervals, eager work
+    and synchronisations between the replays; every replay checked."""
+    print("[batch graph replays]", flush=True)
+    batch, probs, singles, Ns, ab = state(tiny_enriched, hydrogen_small, si_small)
+    m = 12
+    for r in range(3):
+        Xs = blocks(probs, Ns, 60 + 10 * r)
+        Xd = [dev(x) for x in Xs]
+        shift = 0.03 * r
+        a = [lo + shift * (hi - lo) for lo, hi in ab]
+        b = [hi for _, hi in ab]
+        Yb = batch.filter(Xd, m, a, b, prec="fp32", use_graph=True)
+        junk = torch.randn(1000, 100, device="cuda", dtype=torch.float64).sum()   # eager work
+        torch.cuda.synchronize()
+        assert torch.isfinite(junk)
+        for i, p in enumerate(probs):
+            Ys = host(singles[id(p)].filter(Xd[i], m, a[i], b[i], prec="fp32"))
+            assert np.array_equal(host(Yb[i]), Ys), (r, i)
+
+
+def test_batch_entry_against_oracle(tiny_enriched, hydrogen_small, si_small):
+    print("[batch vs oracle]", flush=True)
+    import scipy.sparse.linalg as spla
+    batch, probs, singles, Ns, ab = state(tiny_enriched, hydrogen_small, si_small)
+    m = 6
+    Xs = blocks(probs, Ns, 70)
+    Yb = batch.filter([dev(x) for x in Xs], m, [a for a, _ in ab], [b for _, b in ab], prec="fp32")
+    i = 2                                   # si_small entry, N = 37
+    ops = Operators(probs[i])
+    a, b = ab[i]
+    Yo = recurrence_filter(lambda Z: ops.apply_Htilde(Z), Xs[i], m, a, b)
+    lmax = spla.eigsh(ops.M, k=1, which="LA", return_eigenvectors=False)[0]
+    lmin = spla.eigsh(ops.M, k=1, sigma=0, which="LM", return_eigenvectors=False)[0]
+    rel = float(np.abs(host(Yb[i]) - Yo).max() / np.abs(Yo).max())
+    print(f"  rel err {rel:.3e}", flush=True)
+    assert rel < 10 * U32 * (lmax / lmin) * m
+
+
+def test_batch_fp64_and_rayleigh_ritz(tiny_enriched, hydrogen_small, si_small):
+    """FP64 batch filter, Rayleigh-Ritz and Lanczos of every entry equal the
+    single-problem entry points."""
+    print("[batch fp64 + rr]", flush=True)
+    batch, probs, singles, Ns, ab = state(tiny_enriched, hydrogen_small, si_small)
+    m = 5
+    Xs = blocks(probs, Ns, 80)
+    Xd = [dev(x) for x in Xs]
+    Yb = batch.filter(Xd, m, [a for a, _ in ab], [b for _, b in ab], prec="fp64")
+    Ycopy = [y.clone() for y in Yb]
+    th_b = batch.rayleigh_ritz(Yb)
+    for i, p in enumerate(probs):
+        a, b = ab[i]
+        Ys = singles[id(p)].filter(Xd[i], m, a, b, prec="fp64")
+        assert np.array_equal(host(Ycopy[i]), host(Ys)), i
+        th_s = singles[id(p)].rayleigh_ritz(Ys)
+        assert np.array_equal(th_b[i], th_s), i
+        assert np.array_equal(host(Yb[i]), host(Ys)), i
+    lo_b, hi_b = batch.lanczos_bounds(_STATE["v0"], 10)
+    for i, p in enumerate(probs):
+        lo_s, hi_s = singles[id(p)].lanczos_bounds(_STATE["v0"][i], 10)
+        assert lo_b[i] == lo_s and hi_b[i] == hi_s, i
+
+
+def test_batch_errors(tiny_enriched, hydrogen_small, si_small):
+    from paper_1610_02121_amd import ChebFilterError
+    batch, probs, singles, Ns, ab = state(tiny_enriched, hydrogen_small, si_small)
+    Xd = [dev(np.ones((p.n, 3))) for p in probs]
+    a = [x for x, _ in ab]
+    b = [y for _, y in ab]
+    with pytest.raises(ChebFilterError, match="CF_EINVAL"):
+        batch.filter(Xd, 3, b, a, prec="fp32")                     # a > b
+    with pytest.raises(ChebFilterError, match="CF_EINVAL"):
+        batch.filter(Xd, -1, a, b, prec="fp32")
+    with pytest.raises(ChebFilterError, match="CF_EINVAL"):
+        batch.filter(Xd, 3, a, b, prec=9)
+    big = [dev(np.ones((p.n, MAXC + 1))) for p in probs]
+    with pytest.raises(ChebFilterError, match="CF_ENOMEM"):
+        batch.filter(big, 3, a, b, prec="fp32")
+    with pytest.raises(ValueError):
+        batch.filter(Xd[:-1], 3, a, b, prec="fp32")

@@ -303,6 +303,100 @@ def run_batch(args):
     batch.close()
 
 
+def learned_study(args):
+    """Learned bounds (the network with the guard) against the Lanczos bound on
+    a self-consistent-step sequence.  Training corpus: perturbation sequences
+    on Si clusters of 1-4 atoms (labels: theta_N, a 40-step Lanczos bound and
+    the degree rule), 2000 Adam steps.  Evaluation: 30 steps on the 8-atom
+    cluster with a new perturbation sequence, each step's Ritz values against
+    a reference from FP64 passes (Lanczos bound, degree rule) continued until
+    they settle."""
+    import numpy as np
+    import torch
+
+    from paper_1610_02121_amd import Context, Mlp
+    from paper_1610_02121_amd import learned as L
+    from synth import configs
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    t0 = time.time()
+    inputs, targets = [], []
+    for nat in (1, 2, 3, 4):
+        prob = configs.batch_cluster(nat, seed=args.seed)
+        N = 16 + round(48 * (nat - 1) / 7)
+        wanted = N - 8
+        ctx = Context(prob, max_cols=N)
+        v0 = torch.tensor(np.random.default_rng(args.seed + nat).standard_normal(prob.n),
+                          dtype=torch.float64, device=dev)
+        for sq in range(2):
+            recs, _ = L.run_sequence(ctx, prob, N, wanted, 40, seed=100 * nat + sq,
+                                     chooser=L.lanczos_chooser(ctx, v0, wanted), v0=v0, label_k=40)
+            inputs += [r["input"] for r in recs]
+            targets += [r["target"] for r in recs]
+        ctx.close()
+        log(f"corpus: {nat}-atom cluster done ({len(inputs)} samples, {time.time() - t0:.0f}s)")
+    inputs, targets = np.array(inputs), np.array(targets)
+    net = Mlp(L.N_IN, L.WIDTH, L.DEPTH, L.N_OUT, max_batch=64)
+    net.set_params(L.init_params(seed=args.seed))
+    t1 = time.time()
+    losses = L.train(net, inputs, targets, steps=2000, batch=32, lr=3e-4, seed=args.seed, log=log)
+    t_train = time.time() - t1
+    # evaluation
+    prob = configs.batch_cluster(8, seed=args.seed)
+    N, wanted, steps = 64, 56, 30
+    ctx = Context(prob, max_cols=N)
+    v0 = torch.tensor(np.random.default_rng(args.seed + 99).standard_normal(prob.n),
+                      dtype=torch.float64, device=dev)
+    runs = {}
+    for name, chooser in (("lanczos", L.lanczos_chooser(ctx, v0, wanted)),
+                          ("learned", L.mlp_chooser(ctx, net, v0))):
+        recs, _ = L.run_sequence(ctx, prob, N, wanted, steps, seed=777, chooser=chooser, v0=v0,
+                                 log=None, lanczos_fallback=L.lanczos_chooser(ctx, v0, wanted))
+        runs[name] = recs
+        log(f"{name}: done")
+    # reference per step: the same operator sequence, FP64 passes until settled
+    from synth import perturb
+    X = torch.tensor(configs.initial_block(prob, N, seed=777), dtype=torch.float64, device=dev)
+    Y = torch.empty_like(X)
+    ref = []
+    for s, Hs in enumerate(perturb.sequence(prob, steps, seed=777)):
+        ctx.update_H_cc(Hs)
+        th = ctx.rayleigh_ritz(X)
+        for it in range(40):
+            _, b = ctx.lanczos_bounds(v0, 10)
+            mref = L.degree_rule(float(th[0]), float(th[wanted - 1]), float(th[-1]), b)
+            ctx.filter(X, mref, float(th[-1]), b, Y=Y)
+            thn = ctx.rayleigh_ritz(Y)
+            X, Y = Y, X
+            d = float(np.abs(thn[:wanted] - th[:wanted]).max())
+            th = thn
+            if d < 1e-10 and it >= 2:
+                break
+        ref.append(th[:wanted].copy())
+    ctx.close()
+    out = {"study": "learned filter bounds vs Lanczos bound", "corpus_samples": int(len(inputs)),
+           "train_steps": 2000, "train_seconds": t_train, "train_loss_first": float(losses[:20].mean()),
+           "train_loss_last": float(losses[-20:].mean()),
+           "eval": {"workload": "8-atom Si cluster, 12^3 cells, n = %d, N = %d, wanted %d, %d steps"
+                                % (prob.n, N, wanted, steps)}}
+    for name, recs in runs.items():
+        errs = [float(np.abs(r["theta"][:wanted] - ref[i]).max()) for i, r in enumerate(recs)]
+        out["eval"][name] = {
+            "ritz_err_last10_max": max(errs[-10:]), "ritz_err_median": float(np.median(errs)),
+            "ritz_err_per_step": errs,
+            "bounds_ms_mean": 1e3 * float(np.mean([r["t_bounds"] for r in recs])),
+            "pass_ms_mean": 1e3 * float(np.mean([r["t_pass"] for r in recs])),
+            "degree_mean": float(np.mean([r["m"] for r in recs])),
+            "lanczos_fallbacks": int(sum(r["fallback"] for r in recs)) if name == "learned" else None,
+            "rescued_steps": int(sum(r["rescued"] for r in recs)),
+        }
+    bl = [r["b"] for r in runs["lanczos"]]
+    bm = [r["b"] for r in runs["learned"]]
+    out["eval"]["b_learned_over_lanczos"] = [float(x / y) for x, y in zip(bm, bl)]
+    print(json.dumps(out), flush=True)
+    net.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -318,6 +412,8 @@ def main():
                     help="skip the filter-only timing of the three precision forms")
     ap.add_argument("--mixed-study", action="store_true",
                     help="run the time-to-tolerance study of the precision forms instead")
+    ap.add_argument("--learned-study", action="store_true",
+                    help="train the bounds network and compare it with the Lanczos bound")
     ap.add_argument("--m-reduced", type=int, default=20,
                     help="filter degree of the reduced-precision passes in the study")
     args = ap.parse_args()
@@ -333,6 +429,9 @@ def main():
     from synth import configs
 
     name = args.workload
+    if args.learned_study:
+        learned_study(args)
+        return
     if name == "si-batch256":
         run_batch(args)
         return

@@ -211,6 +211,76 @@ cf_status chebfilter_rayleigh_ritz_batch(cf_batch *batch, double *const *Y, cons
 cf_status chebfilter_lanczos_bounds_batch(cf_batch *batch, const double *const *v0, int32_t k,
                                           double *lmin_est, double *b_upper);
 
+/* ---- Operator updates and Ritz residuals ---------------------------------- */
+
+/* Replace the elemental H^cc_e (same layout and checks as cf_problem.H_cc):
+ * the update of a self-consistent step, where only the potential changes.
+ * H^ec, H^ee, D, M^ec and the Schur complement are unchanged.  The reduced
+ * copies are refreshed.  Synchronises. */
+cf_status chebfilter_update_H_cc(cf_ctx *ctx, const double *H_cc);
+
+/* res_host[j] = || H^E z_j - theta_j M^E z_j ||_{(M^E)^-1} for the columns z_j of
+ * Z with theta_host[j] (the Ritz residual in the dual norm of Sec. V's
+ * generalized problem).  Uses the context's work blocks; synchronises. */
+cf_status chebfilter_residual_norms(cf_ctx *ctx, const double *Z, int64_t ldz, int64_t N,
+                                    const double *theta_host, double *res_host);
+
+/* ---- Learned filter bounds ---------------------------------------------------
+ * A fully connected network (FP32; depth hidden layers of width units with
+ * GELU, linear output) with hand-written forward, backward (mean squared
+ * error) and Adam kernels.  Parameters are a flat FP32 array: for each layer l,
+ * W_l [out_l][in_l] row-major then b_l [out_l]; the caller supplies the initial
+ * values.  Device arrays: X [B][n_in], targets and outputs [B][n_out]. */
+typedef struct cf_mlp cf_mlp;
+cf_status chebfilter_mlp_create(int32_t device, void *stream, int32_t n_in, int32_t width,
+                                int32_t depth, int32_t n_out, int32_t max_batch, cf_mlp **out);
+cf_status chebfilter_mlp_destroy(cf_mlp *mlp);
+const char *chebfilter_mlp_last_error(const cf_mlp *mlp);
+cf_status chebfilter_mlp_sizes(const cf_mlp *mlp, int64_t *nparams);
+/* host arrays of nparams floats; reset_adam zeroes the Adam moments and step count */
+cf_status chebfilter_mlp_set_params(cf_mlp *mlp, const float *host, int32_t reset_adam);
+cf_status chebfilter_mlp_get_params(cf_mlp *mlp, float *host);
+/* Y = net(X), 1 <= B <= max_batch */
+cf_status chebfilter_mlp_forward(cf_mlp *mlp, const float *X, int32_t B, float *Y);
+/* loss = mean over the B x n_out entries of (net(X) - T)^2 and its gradient
+ * (kept on the device for chebfilter_mlp_adam_step; copied to grad_host
+ * [nparams] if non-null).  Synchronises. */
+cf_status chebfilter_mlp_loss_grad(cf_mlp *mlp, const float *X, const float *T, int32_t B,
+                                   float *loss_host, float *grad_host);
+/* One Adam update (Kingma & Ba, bias-corrected) with the last gradient. */
+cf_status chebfilter_mlp_adam_step(cf_mlp *mlp, float lr, float beta1, float beta2, float eps);
+/* Affine normalisation used by chebfilter_bounds_predict: inputs (x - mean)/std,
+ * outputs mean + std * y.  Host arrays of n_in, n_in, n_out, n_out. */
+cf_status chebfilter_mlp_set_normalization(cf_mlp *mlp, const double *in_mean, const double *in_std,
+                                           const double *out_mean, const double *out_std);
+
+/* Scale-free network inputs from raw history: steps x 8 raw features, oldest
+ * first (theta_1, theta_Nw, theta_N, b used, m used, largest and median
+ * residual norm, largest change of the wanted Ritz values).  With theta_N and
+ * w = b - theta_N of the last step: energies (the first four) become
+ * (x - theta_N)/w, the degree m/100, the last three log10(x/w + 1e-30).
+ * CF_EINVAL if w <= 0.  Host arrays of 8 * steps. */
+cf_status chebfilter_bounds_features(const double *history, int32_t steps, double *out);
+
+/* Filter interval and degree for the next step (the bound b of Sec. V and
+ * the degree, whose choice the paper ties to the spectral width) from the
+ * network, fed chebfilter_bounds_features(history) (n_in = 8 x steps).  Its
+ * outputs, after the output normalisation, are (alpha, beta, m) with
+ * a = theta_N + alpha w and b = theta_N + beta w (theta_N, w of the last step).
+ * Guard: the prediction is used only if it is finite and beta lies within
+ * [0.98, 2]; b then gets a 5 % margin above theta_N (an overestimated b only
+ * damps less; an underestimated one would amplify the top of the spectrum),
+ * a is kept if it lies in [theta_Nw, theta_N + (b - theta_N)/4] (else
+ * theta_N), and m is rounded, capped at the degree where the filter amplifies
+ * theta_1 1e12 times more than theta_Nw (the dynamic range the FP64
+ * orthonormalisation resolves) and clamped to [m_min, m_max].  Otherwise the
+ * Lanczos bound (chebfilter_lanczos_bounds with v0, lanczos_k) is used, with
+ * a = theta_N and the last degree, and *fallback = 1.  Synchronises. */
+cf_status chebfilter_bounds_predict(cf_ctx *ctx, cf_mlp *mlp, const double *history,
+                                    const double *v0, int32_t lanczos_k, int32_t m_min,
+                                    int32_t m_max, double *a, double *b, int32_t *m,
+                                    int32_t *fallback);
+
 #ifdef __cplusplus
 }
 #endif

@@ -16,6 +16,8 @@ filters    Chebyshev polynomials, the three-term recurrence filter and the
            exact filter through the generalized eigendecomposition (Sec. V).
 subspace   Cholesky-QR, Rayleigh-Ritz, Lanczos spectrum bounds, one
            subspace-iteration step and the error metrics (Sec. V).
+mlp        the learned-bounds network: FP64 forward, backpropagated
+           mean-squared-error gradient, Adam.
 
 Parity pins: see the `-m "not gpu"` tests under tests/ (closed forms,
 textbook limits, library routines, brute force on tiny meshes).

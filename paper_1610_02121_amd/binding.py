@@ -26,7 +26,12 @@ EXPORTS = ["chebfilter_init", "chebfilter_destroy", "chebfilter_last_error", "ch
            "chebfilter_lanczos_bounds", "chebfilter_profile", "chebfilter_profile_query",
            "chebfilter_init_batch", "chebfilter_batch_destroy", "chebfilter_batch_last_error",
            "chebfilter_batch_sizes", "chebfilter_filter_batch", "chebfilter_rayleigh_ritz_batch",
-           "chebfilter_lanczos_bounds_batch"]
+           "chebfilter_lanczos_bounds_batch", "chebfilter_update_H_cc", "chebfilter_residual_norms",
+           "chebfilter_mlp_create", "chebfilter_mlp_destroy", "chebfilter_mlp_last_error",
+           "chebfilter_mlp_sizes", "chebfilter_mlp_set_params", "chebfilter_mlp_get_params",
+           "chebfilter_mlp_forward", "chebfilter_mlp_loss_grad", "chebfilter_mlp_adam_step",
+           "chebfilter_mlp_set_normalization", "chebfilter_bounds_features",
+           "chebfilter_bounds_predict"]
 
 
 class CfProblem(C.Structure):
@@ -85,8 +90,27 @@ def load_library() -> C.CDLL:
     lib.chebfilter_rayleigh_ritz_batch.argtypes = [vp, C.POINTER(vp), P64, P64, C.POINTER(vp)]
     lib.chebfilter_lanczos_bounds_batch.argtypes = [vp, C.POINTER(vp), i32, C.POINTER(dbl),
                                                     C.POINTER(dbl)]
+    f32 = C.c_float
+    PD = C.POINTER(dbl)
+    lib.chebfilter_update_H_cc.argtypes = [vp, vp]
+    lib.chebfilter_residual_norms.argtypes = [vp, vp, i64, i64, PD, PD]
+    lib.chebfilter_mlp_create.argtypes = [i32, vp, i32, i32, i32, i32, i32, C.POINTER(vp)]
+    lib.chebfilter_mlp_destroy.argtypes = [vp]
+    lib.chebfilter_mlp_last_error.argtypes = [vp]
+    lib.chebfilter_mlp_last_error.restype = C.c_char_p
+    lib.chebfilter_mlp_sizes.argtypes = [vp, P64]
+    lib.chebfilter_mlp_set_params.argtypes = [vp, vp, i32]
+    lib.chebfilter_mlp_get_params.argtypes = [vp, vp]
+    lib.chebfilter_mlp_forward.argtypes = [vp, vp, i32, vp]
+    lib.chebfilter_mlp_loss_grad.argtypes = [vp, vp, vp, i32, C.POINTER(f32), vp]
+    lib.chebfilter_mlp_adam_step.argtypes = [vp, f32, f32, f32, f32]
+    lib.chebfilter_mlp_set_normalization.argtypes = [vp, PD, PD, PD, PD]
+    lib.chebfilter_bounds_features.argtypes = [PD, i32, PD]
+    lib.chebfilter_bounds_predict.argtypes = [vp, vp, PD, vp, i32, i32, i32, PD, PD,
+                                              C.POINTER(i32), C.POINTER(i32)]
     for nm in EXPORTS:
-        if nm not in ("chebfilter_last_error", "chebfilter_batch_last_error"):
+        if nm not in ("chebfilter_last_error", "chebfilter_batch_last_error",
+                      "chebfilter_mlp_last_error"):
             getattr(lib, nm).restype = C.c_int
     _lib = lib
     return lib
@@ -211,6 +235,36 @@ class Context:
                                                        C.byref(lo), C.byref(hi)))
         return lo.value, hi.value
 
+    def update_H_cc(self, H_cc):
+        """Replace the elemental H^cc_e (host array [E, npc, npc])."""
+        H = _np(H_cc, np.float64)
+        self._check(self.lib.chebfilter_update_H_cc(self._h, H.ctypes.data))
+
+    def residual_norms(self, Z, theta) -> np.ndarray:
+        """||H z_j - theta_j M z_j||_{M^-1} per column of Z."""
+        zp, ldz = _block(Z, "Z")
+        N = Z.shape[1]
+        th = _np(theta, np.float64)[:N]
+        res = np.zeros(max(N, 1))
+        self._check(self.lib.chebfilter_residual_norms(
+            self._h, zp, ldz, N, th.ctypes.data_as(C.POINTER(C.c_double)),
+            res.ctypes.data_as(C.POINTER(C.c_double))))
+        return res[:N]
+
+    def bounds_predict(self, mlp, history, v0, lanczos_k: int = 10, m_min: int = 8,
+                       m_max: int = 120):
+        """(a, b, m, used_lanczos) for the next filter from the network and the guard."""
+        import torch
+        if v0.dtype != torch.float64 or not v0.is_cuda or not v0.is_contiguous():
+            raise TypeError("v0 must be a contiguous float64 CUDA tensor")
+        h = _np(history, np.float64).ravel()
+        a, b = C.c_double(), C.c_double()
+        m, fb = C.c_int32(), C.c_int32()
+        self._check(self.lib.chebfilter_bounds_predict(
+            self._h, mlp._h, h.ctypes.data_as(C.POINTER(C.c_double)), v0.data_ptr(), int(lanczos_k),
+            int(m_min), int(m_max), C.byref(a), C.byref(b), C.byref(m), C.byref(fb)))
+        return a.value, b.value, m.value, bool(fb.value)
+
     def profile(self, enable: bool):
         self._check(self.lib.chebfilter_profile(self._h, int(enable)))
 
@@ -315,3 +369,96 @@ class Batch:
         lo, hi = (C.c_double * n)(), (C.c_double * n)()
         self._check(self.lib.chebfilter_lanczos_bounds_batch(self._h, vp, int(k), lo, hi))
         return list(lo), list(hi)
+
+
+def bounds_features(history) -> np.ndarray:
+    """Scale-free network inputs of a raw history (chebfilter_bounds_features)."""
+    lib = load_library()
+    h = _np(history, np.float64).ravel()
+    out = np.zeros_like(h)
+    st = lib.chebfilter_bounds_features(h.ctypes.data_as(C.POINTER(C.c_double)), h.size // 8,
+                                        out.ctypes.data_as(C.POINTER(C.c_double)))
+    if st != 0:
+        raise ChebFilterError(st, "bounds_features: the last step's b - theta_N must be > 0")
+    return out
+
+
+class Mlp:
+    """The bounds network on the GPU (wraps cf_mlp): FP32 parameters, forward,
+    mean-squared-error gradient and Adam, all in the library's kernels."""
+
+    def __init__(self, n_in: int, width: int, depth: int, n_out: int, max_batch: int,
+                 device: int = 0):
+        import torch
+        self.lib = load_library()
+        self.device = torch.device("cuda", device)
+        stream = torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        st = self.lib.chebfilter_mlp_create(device, C.c_void_p(stream.cuda_stream), n_in, width, depth,
+                                            n_out, max_batch, C.byref(h))
+        if st != 0:
+            raise ChebFilterError(st, self.lib.chebfilter_mlp_last_error(None).decode())
+        self._h = h
+        self.n_in, self.width, self.depth, self.n_out = n_in, width, depth, n_out
+        self.max_batch = max_batch
+        npar = C.c_int64()
+        self.lib.chebfilter_mlp_sizes(h, C.byref(npar))
+        self.nparams = npar.value
+
+    def _check(self, st: int):
+        if st != 0:
+            raise ChebFilterError(st, self.lib.chebfilter_mlp_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.lib.chebfilter_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params, reset_adam: bool = True):
+        p = _np(params, np.float32)
+        if p.size != self.nparams:
+            raise ValueError(f"need {self.nparams} parameters")
+        self._check(self.lib.chebfilter_mlp_set_params(self._h, p.ctypes.data, int(reset_adam)))
+
+    def get_params(self) -> np.ndarray:
+        p = np.zeros(self.nparams, dtype=np.float32)
+        self._check(self.lib.chebfilter_mlp_get_params(self._h, p.ctypes.data))
+        return p
+
+    @staticmethod
+    def _dev32(t, name):
+        import torch
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.float32 or not t.is_cuda \
+                or not t.is_contiguous():
+            raise TypeError(f"{name} must be a contiguous float32 CUDA tensor")
+        return t.data_ptr()
+
+    def forward(self, X):
+        import torch
+        Y = torch.empty((X.shape[0], self.n_out), dtype=torch.float32, device=X.device)
+        self._check(self.lib.chebfilter_mlp_forward(self._h, self._dev32(X, "X"), X.shape[0],
+                                                    Y.data_ptr()))
+        return Y
+
+    def loss_grad(self, X, T, want_grad: bool = False):
+        loss = C.c_float()
+        g = np.zeros(self.nparams, dtype=np.float32) if want_grad else None
+        self._check(self.lib.chebfilter_mlp_loss_grad(
+            self._h, self._dev32(X, "X"), self._dev32(T, "T"), X.shape[0], C.byref(loss),
+            g.ctypes.data if want_grad else None))
+        return (loss.value, g) if want_grad else loss.value
+
+    def adam_step(self, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
+        self._check(self.lib.chebfilter_mlp_adam_step(self._h, lr, beta1, beta2, eps))
+
+    def set_normalization(self, in_mean, in_std, out_mean, out_std):
+        arrs = [_np(v, np.float64) for v in (in_mean, in_std, out_mean, out_std)]
+        self._keep_norm = arrs
+        self._check(self.lib.chebfilter_mlp_set_normalization(
+            self._h, *[a.ctypes.data_as(C.POINTER(C.c_double)) for a in arrs]))

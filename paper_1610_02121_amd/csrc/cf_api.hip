@@ -20,6 +20,12 @@
 
 using namespace cf;
 
+// cf_mlp.hip
+cf_status cf_mlp_predict_raw(cf_mlp *m, const double *x_raw, double *y_raw);
+int cf_mlp_n_in(const cf_mlp *m);
+int cf_mlp_n_out(const cf_mlp *m);
+const char *cf_mlp_err(const cf_mlp *m);
+
 namespace {
 
 struct ProfEntry {
@@ -503,6 +509,44 @@ static void free_ctx(cf_ctx *c) {
   delete c;
 }
 
+// Cell matrices H_cc (host, [E][npc][npc]) -> c->Hp, padded to NPAD x NPAD and
+// symmetrised after checking symmetry to 1e-10 of the block's largest entry;
+// refreshes the reduced-precision copies when they exist.
+static cf_status upload_cells(cf_ctx *c, const double *H_cc, const char *who) {
+  const int64_t E = c->E;
+  const int npc = c->npc;
+  const int64_t batch = 256;
+  std::vector<double> buf((size_t)batch * NPAD * NPAD);
+  for (int64_t e0 = 0; e0 < E; e0 += batch) {
+    const int64_t nb = std::min(batch, E - e0);
+    std::fill(buf.begin(), buf.begin() + nb * NPAD * NPAD, 0.0);
+    for (int64_t b = 0; b < nb; ++b) {
+      const double *H = H_cc + (e0 + b) * npc * npc;
+      double *o = buf.data() + b * NPAD * NPAD;
+      double hmax = 0.0;
+      for (int64_t q = 0; q < (int64_t)npc * npc; ++q) {
+        if (!std::isfinite(H[q])) return set_err(c, CF_EINVAL, std::string(who) + ": non-finite H_cc");
+        hmax = std::max(hmax, std::fabs(H[q]));
+      }
+      for (int a = 0; a < npc; ++a)
+        for (int bb = 0; bb < npc; ++bb) {
+          const double x = H[a * npc + bb], y = H[bb * npc + a];
+          if (std::fabs(x - y) > 1e-10 * hmax)
+            return set_err(c, CF_EINVAL, std::string(who) + ": H_cc block not symmetric");
+          o[a * NPAD + bb] = 0.5 * (x + y);
+        }
+    }
+    // ordered after earlier work on the context's stream that reads Hp
+    HIPCHK(c, hipMemcpyAsync(c->Hp + e0 * NPAD * NPAD, buf.data(), nb * NPAD * NPAD * sizeof(double),
+                             hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  const int64_t hsz = E * NPAD * NPAD;
+  if (c->Hp32) HIPCHK(c, launch_to_f32(c->stream, hsz, c->Hp, c->Hp32));
+  if (c->Hp16) HIPCHK(c, launch_to_bf16(c->stream, hsz, c->Hp, c->Hp16));
+  return CF_OK;
+}
+
 // ---------------------------------------------------------------------------
 // init
 // ---------------------------------------------------------------------------
@@ -601,32 +645,7 @@ static cf_status do_init(const cf_problem *pr, const cf_options *opt, cf_ctx *c)
 
   // ---- cell matrices: padded to NPAD x NPAD, symmetrised, checked
   STCHK(dalloc(c, &c->Hp, (size_t)E * NPAD * NPAD));
-  {
-    const int64_t batch = 256;
-    std::vector<double> buf((size_t)batch * NPAD * NPAD);
-    for (int64_t e0 = 0; e0 < E; e0 += batch) {
-      const int64_t nb = std::min(batch, E - e0);
-      std::fill(buf.begin(), buf.begin() + nb * NPAD * NPAD, 0.0);
-      for (int64_t b = 0; b < nb; ++b) {
-        const double *H = pr->H_cc + (e0 + b) * npc * npc;
-        double *o = buf.data() + b * NPAD * NPAD;
-        double hmax = 0.0;
-        for (int64_t q = 0; q < (int64_t)npc * npc; ++q) {
-          if (!std::isfinite(H[q])) return set_err(c, CF_EINVAL, "init: non-finite H_cc");
-          hmax = std::max(hmax, std::fabs(H[q]));
-        }
-        for (int a = 0; a < npc; ++a)
-          for (int bb = 0; bb < npc; ++bb) {
-            const double x = H[a * npc + bb], y = H[bb * npc + a];
-            if (std::fabs(x - y) > 1e-10 * hmax)
-              return set_err(c, CF_EINVAL, "init: H_cc block not symmetric");
-            o[a * NPAD + bb] = 0.5 * (x + y);
-          }
-      }
-      HIPCHK(c, hipMemcpy(c->Hp + e0 * NPAD * NPAD, buf.data(), nb * NPAD * NPAD * sizeof(double),
-                          hipMemcpyHostToDevice));
-    }
-  }
+  STCHK(upload_cells(c, pr->H_cc, "init"));
   {
     std::vector<double> dv(pr->M_cc_diag, pr->M_cc_diag + n_h), di(n_h);
     for (int64_t d = 0; d < n_h; ++d) di[d] = 1.0 / dv[d];
@@ -1662,6 +1681,117 @@ cf_status chebfilter_lanczos_bounds_batch(cf_batch *b, const double *const *v0, 
     cf_status st = chebfilter_lanczos_bounds(c, v0[i], k, lmin_est + i, b_upper + i);
     if (st != CF_OK) return berr(b, st, "entry " + std::to_string(i) + ": " + c->err);
   }
+  return CF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// operator updates, residuals, learned bounds
+// ---------------------------------------------------------------------------
+cf_status chebfilter_update_H_cc(cf_ctx *c, const double *H_cc) {
+  if (!c) return CF_EINVAL;
+  if (!H_cc) return set_err(c, CF_EINVAL, "update_H_cc: null H_cc");
+  HIPCHK(c, hipSetDevice(c->device));
+  return upload_cells(c, H_cc, "update_H_cc");
+}
+
+cf_status chebfilter_residual_norms(cf_ctx *c, const double *Z, int64_t ldz, int64_t N,
+                                    const double *theta_host, double *res_host) {
+  if (!c) return CF_EINVAL;
+  STCHK(check_block(c, Z, ldz, N, "residual_norms Z"));
+  if (N > 0 && (!theta_host || !res_host)) return set_err(c, CF_EINVAL, "residual_norms: null theta or res");
+  if (N == 0) return CF_OK;
+  HIPCHK(c, hipSetDevice(c->device));
+  const int n = (int)N;
+  const int64_t ld = c->max_cols;
+  // T = H Z - M Z diag(theta); U = (M^E)^-1 T; res_j = sqrt(T_j . U_j)
+  HIPCHK(c, hipMemcpyAsync(c->theta, theta_host, N * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  STCHK(core_apply_H(c, Z, ldz, c->T, ld, n));
+  STCHK(core_apply_M(c, Z, ldz, c->U, ld, n));
+  HIPCHK(c, launch_sub_colscale(c->stream, c->n, n, c->T, ld, c->U, ld, c->theta));
+  STCHK(chebfilter_apply_Sinv(c, c->T, ld, c->U, ld, N));
+  const int nchunks = (int)std::min<int64_t>(256, (int64_t)c->gp_chunks * c->max_cols);
+  HIPCHK(c, launch_coldot(c->stream, c->n, n, c->T, ld, c->U, ld, c->Gp, nchunks, c->evE));
+  std::vector<double> sq(N);
+  HIPCHK(c, hipMemcpyAsync(sq.data(), c->evE, N * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (int j = 0; j < n; ++j) res_host[j] = std::sqrt(std::max(sq[j], 0.0));
+  return CF_OK;
+}
+
+// Learned bounds.  history: the raw features of the last steps, oldest
+// first, 8 per step: theta_1, theta_Nw, theta_N, b used, m used, largest and
+// median residual norm, largest change of the wanted Ritz values.
+cf_status chebfilter_bounds_features(const double *history, int32_t steps, double *out) {
+  if (!history || !out || steps < 1) return CF_EINVAL;
+  const double *last = history + 8 * (steps - 1);
+  const double thN = last[2], w = last[3] - last[2];
+  if (!(w > 0.0) || !std::isfinite(w) || !std::isfinite(thN)) return CF_EINVAL;
+  for (int s = 0; s < steps; ++s) {
+    const double *f = history + 8 * s;
+    double *x = out + 8 * s;
+    for (int q = 0; q < 4; ++q) x[q] = (f[q] - thN) / w;        // theta_1, theta_Nw, theta_N, b
+    x[4] = f[4] / 100.0;                                           // degree
+    for (int q = 5; q < 8; ++q) x[q] = std::log10(std::max(f[q], 0.0) / w + 1e-30);
+  }
+  return CF_OK;
+}
+
+cf_status chebfilter_bounds_predict(cf_ctx *c, cf_mlp *mlp, const double *history, const double *v0,
+                                    int32_t lanczos_k, int32_t m_min, int32_t m_max, double *a,
+                                    double *b, int32_t *m, int32_t *fallback) {
+  if (!c) return CF_EINVAL;
+  if (!mlp || !history || !v0 || !a || !b || !m || !fallback)
+    return set_err(c, CF_EINVAL, "bounds_predict: null argument");
+  if (cf_mlp_n_out(mlp) != 3 || cf_mlp_n_in(mlp) % 8 != 0)
+    return set_err(c, CF_EINVAL, "bounds_predict: the network must map 8 features per step to 3 outputs");
+  if (m_min < 1 || m_max < m_min) return set_err(c, CF_EINVAL, "bounds_predict: bad degree range");
+  const int steps = cf_mlp_n_in(mlp) / 8;
+  const double *last = history + 8 * (steps - 1);
+  const double th1 = last[0], thw = last[1], thN = last[2], b_last = last[3], m_last = last[4];
+  const double wlast = b_last - thN;
+  bool ok = std::isfinite(th1) && std::isfinite(thw) && std::isfinite(thN) && wlast > 0.0 &&
+            std::isfinite(wlast);
+  double y[3] = {NAN, NAN, NAN};
+  if (ok) {
+    std::vector<double> x(8 * steps);
+    ok = chebfilter_bounds_features(history, steps, x.data()) == CF_OK;
+    if (ok) {
+      cf_status st = cf_mlp_predict_raw(mlp, x.data(), y);
+      if (st != CF_OK) return set_err(c, st, std::string("bounds_predict: ") + cf_mlp_err(mlp));
+    }
+  }
+  // outputs (alpha, beta, m): a = theta_N + alpha w, b = theta_N + beta w with
+  // w the last step's b - theta_N.  Guard: b must stay a safe upper bound (an
+  // overestimate only costs damping; an underestimate amplifies the top of the
+  // spectrum by T_m(t > 1)), so beta must lie within [0.98, 2]; a 5 % margin
+  // is added
+  ok = ok && std::isfinite(y[0]) && std::isfinite(y[1]) && std::isfinite(y[2]) && y[1] >= 0.98 &&
+       y[1] <= 2.0;
+  if (ok) {
+    const double bw = y[1] * wlast;
+    *b = thN + 1.05 * bw;
+    const double ap = thN + y[0] * wlast;
+    // a: inside [theta_Nw, theta_N + (b - theta_N)/4], else theta_N
+    *a = (ap >= thw && ap <= thN + 0.25 * (*b - thN)) ? ap : thN;
+    // degree: rounded, and at most the degree at which theta_1 is amplified
+    // 1e12 times more than theta_Nw (beyond it the orthonormalisation cannot
+    // resolve the wanted directions near theta_Nw in FP64)
+    double mr = std::round(y[2]);
+    const double t1 = std::fabs((2.0 * th1 - *a - *b) / (*b - *a));
+    const double tw = std::fabs((2.0 * thw - *a - *b) / (*b - *a));
+    const double g = std::acosh(std::max(t1, 1.0)) - std::acosh(std::max(tw, 1.0));
+    if (g > 0.0) mr = std::min(mr, std::floor(std::log(1e12) / g));
+    *m = (int32_t)std::min<double>(std::max<double>(mr, m_min), m_max);
+    *fallback = 0;
+    return CF_OK;
+  }
+  double lo = 0.0, bu = 0.0;
+  STCHK(chebfilter_lanczos_bounds(c, v0, lanczos_k, &lo, &bu));
+  *b = bu;
+  *a = thN < bu ? thN : lo;
+  const double mr = std::isfinite(m_last) ? std::round(m_last) : (double)m_min;
+  *m = (int32_t)std::min<double>(std::max<double>(mr, m_min), m_max);
+  *fallback = 1;
   return CF_OK;
 }
 

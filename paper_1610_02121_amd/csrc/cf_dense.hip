@@ -552,4 +552,58 @@ hipError_t launch_copy(hipStream_t s, int64_t n, int N, const double *X, int64_t
   return hipGetLastError();
 }
 
+
+// ---------------------------------------------------------------------------
+// Ritz residuals: R[:, j] -= theta[j] MZ[:, j], then per-column sums
+// out[j] = sum_i A[i][j] B[i][j] (row chunks of partial sums, then a fixed-order
+// sum of the chunks: deterministic).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_sub_colscale(int64_t n, int N, double *__restrict__ R,
+                                                      int64_t ldr, const double *__restrict__ MZ,
+                                                      int64_t ldm, const double *__restrict__ theta) {
+  for (int64_t i = (int64_t)blockIdx.x * 4 + threadIdx.y; i < n; i += (int64_t)gridDim.x * 4)
+    for (int j = threadIdx.x; j < N; j += 64) R[i * ldr + j] -= theta[j] * MZ[i * ldm + j];
+}
+
+__global__ __launch_bounds__(256) void k_coldot_partial(int64_t n, int N, int64_t chunk,
+                                                        const double *__restrict__ A, int64_t lda,
+                                                        const double *__restrict__ B, int64_t ldb,
+                                                        double *__restrict__ part) {
+  const int j = blockIdx.y * 256 + threadIdx.x;
+  if (j >= N) return;
+  const int64_t r0 = (int64_t)blockIdx.x * chunk, r1 = min(n, r0 + chunk);
+  double acc = 0.0;
+  for (int64_t i = r0; i < r1; ++i) acc += A[i * lda + j] * B[i * ldb + j];
+  part[(int64_t)blockIdx.x * N + j] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_coldot_final(int nchunks, int N, const double *__restrict__ part,
+                                                      double *__restrict__ out) {
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= N) return;
+  double acc = 0.0;
+  for (int c = 0; c < nchunks; ++c) acc += part[(int64_t)c * N + j];
+  out[j] = acc;
+}
+
+hipError_t launch_sub_colscale(hipStream_t s, int64_t n, int N, double *R, int64_t ldr,
+                               const double *MZ, int64_t ldm, const double *theta) {
+  if (n <= 0 || N <= 0) return hipSuccess;
+  int64_t blocks = (n + 3) / 4;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_sub_colscale, dim3((unsigned)blocks), dim3(64, 4), 0, s, n, N, R, ldr, MZ, ldm,
+                     theta);
+  return hipGetLastError();
+}
+
+hipError_t launch_coldot(hipStream_t s, int64_t n, int N, const double *A, int64_t lda,
+                         const double *B, int64_t ldb, double *part, int nchunks, double *out) {
+  if (n <= 0 || N <= 0) return hipSuccess;
+  const int64_t chunk = (n + nchunks - 1) / nchunks;
+  hipLaunchKernelGGL(k_coldot_partial, dim3(nchunks, (N + 255) / 256), dim3(256), 0, s, n, N, chunk, A,
+                     lda, B, ldb, part);
+  hipLaunchKernelGGL(k_coldot_final, dim3((N + 255) / 256), dim3(256), 0, s, nchunks, N, part, out);
+  return hipGetLastError();
+}
+
 }  // namespace cf

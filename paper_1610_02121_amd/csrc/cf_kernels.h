@@ -287,6 +287,14 @@ hipError_t launch_lanczos_update(hipStream_t s, int64_t n, int j, double *w, con
 hipError_t launch_tridiag_bounds(hipStream_t s, const double *coef, const double *unused, int k,
                                  double *out2);
 
+// ---- Ritz residual helpers (cf_dense.hip)
+// R[i][j] -= theta[j] MZ[i][j]  (theta on the device)
+hipError_t launch_sub_colscale(hipStream_t s, int64_t n, int N, double *R, int64_t ldr,
+                               const double *MZ, int64_t ldm, const double *theta);
+// out[j] = sum_i A[i][j] B[i][j]  (part: nchunks * N scratch)
+hipError_t launch_coldot(hipStream_t s, int64_t n, int N, const double *A, int64_t lda,
+                         const double *B, int64_t ldb, double *part, int nchunks, double *out);
+
 // ---- data-movement helpers (cf_dense.hip)
 hipError_t launch_sub(hipStream_t s, int64_t n, const double *A, const double *B, double *C);
 hipError_t launch_transpose(hipStream_t s, int N, const double *In, int64_t ldi, double *Out);

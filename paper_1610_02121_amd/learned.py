@@ -1,0 +1,201 @@
+"""Learned filter bounds: the self-consistent-step driver around the library's
+network (chebfilter_mlp_*) and guard (chebfilter_bounds_predict).
+
+Each step of a sequence changes the potential (synth.perturb), so the
+operator H~ changes a little from step to step; one filter pass and a
+Rayleigh-Ritz projection per step follow it.  The filter needs (a, b, m):
+a = theta_N from the last projection, b an upper bound of the spectrum
+(Lanczos, Sec. V), m the degree.  The network maps the last 8 steps' spectrum
+summaries (8 numbers each) to (a, b, m); the guard falls back to Lanczos.
+
+Labels for training, per step: a* = theta_N of the projection of the step's
+operator, b* = the upper bound of a 40-step Lanczos run on it, and
+m* = degree_rule(theta_1, theta_Nw, a*, b*); the network inputs are the
+scale-free features of chebfilter_bounds_features and its outputs
+(alpha, beta, m) with a = theta_N + alpha w, b = theta_N + beta w, w the last
+step's b - theta_N, so one network serves clusters of different sizes.  Host code here only marshals arrays,
+keeps histories and normalisation constants; every operator application,
+Lanczos step, projection and network evaluation runs in the library.
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+
+FEATURES = 8          # per step
+HISTORY = 8           # steps fed to the network
+N_IN = FEATURES * HISTORY
+N_OUT = 3             # a, b, m
+WIDTH, DEPTH = 128, 3
+
+
+RANGE = 1e12          # largest amplification ratio the orthonormalisation resolves in FP64
+
+
+def degree_range_cap(theta_1: float, theta_w: float, a: float, b: float) -> float:
+    """Degree at which the filter amplifies theta_1 RANGE times more than
+    theta_w (beyond it the wanted directions near theta_w drown in the
+    rounding of the lowest ones): T_m(|t_1|)/T_m(|t_w|) ~ exp(m (acosh|t_1| -
+    acosh|t_w|))."""
+    t1 = abs((2.0 * theta_1 - a - b) / (b - a))
+    tw = abs((2.0 * theta_w - a - b) / (b - a))
+    g = np.arccosh(max(t1, 1.0)) - np.arccosh(max(tw, 1.0))
+    return np.inf if g <= 0.0 else np.log(RANGE) / g
+
+
+def degree_rule(theta_1: float, theta_w: float, a: float, b: float, rho: float = 100.0,
+                m_min: int = 8, m_max: int = 120) -> int:
+    """Smallest degree that amplifies the highest wanted Ritz value theta_w by
+    rho relative to the damped interval [a, b] (T_m(|t(theta_w)|) >= rho,
+    t(x) = (2x - a - b)/(b - a)), capped by degree_range_cap and clamped to
+    [m_min, m_max]."""
+    t = abs((2.0 * theta_w - a - b) / (b - a))
+    m = np.inf if t <= 1.0 else np.ceil(np.arccosh(rho) / np.arccosh(t))
+    m = min(m, np.floor(degree_range_cap(theta_1, theta_w, a, b)))
+    return int(min(max(m, m_min), m_max))
+
+
+def step_features(theta, theta_prev, wanted: int, b_used: float, m_used: int, res) -> np.ndarray:
+    r = np.asarray(res[:wanted])
+    d = float(np.abs(np.asarray(theta[:wanted]) - np.asarray(theta_prev[:wanted])).max())
+    return np.array([theta[0], theta[wanted - 1], theta[-1], b_used, float(m_used),
+                     float(r.max()), float(np.median(r)), d])
+
+
+def history_vector(feats: list) -> np.ndarray:
+    """The last HISTORY feature rows, oldest first (the earliest row repeated
+    while fewer steps exist)."""
+    rows = list(feats[-HISTORY:])
+    while len(rows) < HISTORY:
+        rows.insert(0, rows[0])
+    return np.concatenate(rows)
+
+
+def init_params(seed: int = 0, n_in: int = N_IN, width: int = WIDTH, depth: int = DEPTH,
+                n_out: int = N_OUT) -> np.ndarray:
+    """Seeded initial parameters (layout of chebfilter_mlp_*): W ~ N(0, 1/fan_in)
+    (2/fan_in before GELU layers), b = 0."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for l in range(depth + 1):
+        fi = n_in if l == 0 else width
+        fo = width if l < depth else n_out
+        scale = np.sqrt((2.0 if l < depth else 1.0) / fi)
+        parts.append(rng.standard_normal(fo * fi) * scale)
+        parts.append(np.zeros(fo))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def run_sequence(ctx, prob, N: int, wanted: int, steps: int, seed: int, chooser, v0,
+                 label_k: int = 0, X0=None, log=None, lanczos_fallback=None):
+    """One self-consistent-step sequence on a context.  chooser(step, feats,
+    theta) -> (a, b, m, used_lanczos).  If the projection after the filter
+    finds the block rank deficient and lanczos_fallback is given, the step is
+    redone with it ("rescued").  Returns per-step records with the features,
+    the bounds used, timings and (if label_k) the labels."""
+    import torch
+    from .binding import ChebFilterError, bounds_features
+    from synth import configs, perturb
+    dev = v0.device
+    X = torch.tensor(configs.initial_block(prob, N, seed=seed) if X0 is None else X0,
+                     dtype=torch.float64, device=dev)
+    Y = torch.empty_like(X)
+    theta = ctx.rayleigh_ritz(X)
+    feats, recs = [], []
+    seq = perturb.sequence(prob, steps, seed=seed)
+    for s, Hs in enumerate(seq):
+        ctx.update_H_cc(Hs)
+        # the projection of the new operator on the current subspace
+        theta_cur = ctx.rayleigh_ritz(X)
+        if not feats:
+            res = ctx.residual_norms(X, theta_cur)
+            _, b0 = ctx.lanczos_bounds(v0, 10)
+            feats.append(step_features(theta_cur, theta_cur, wanted, b0, 40, res))
+        rec = {"step": s}
+        if label_k:
+            _, bstar = ctx.lanczos_bounds(v0, label_k)
+            astar = float(theta_cur[-1])
+            hist = history_vector(feats)
+            thN, w = hist[-6], hist[-5] - hist[-6]        # last step's theta_N and b - theta_N
+            rec["input"] = bounds_features(hist)
+            rec["target"] = np.array([(astar - thN) / w, (bstar - thN) / w,
+                                      degree_rule(float(theta_cur[0]), float(theta_cur[wanted - 1]),
+                                                  astar, bstar)])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        a, b, m, fb = chooser(s, feats, theta_cur)
+        t1 = time.perf_counter()
+        ctx.filter(X, m, a, b, Y=Y)
+        rescued = False
+        try:
+            th = ctx.rayleigh_ritz(Y)
+        except ChebFilterError as exc:
+            # the filtered block lost rank (interval or degree too aggressive):
+            # redo the step from X with the Lanczos bound and the degree rule
+            if exc.status != 3 or lanczos_fallback is None:
+                raise
+            a, b, m, fb = lanczos_fallback(s, feats, theta_cur)
+            ctx.filter(X, m, a, b, Y=Y)
+            th = ctx.rayleigh_ritz(Y)
+            rescued = True
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        res = ctx.residual_norms(Y, th)
+        feats.append(step_features(th, theta_cur, wanted, b, m, res))
+        rec.update(a=a, b=b, m=m, fallback=bool(fb), rescued=rescued, t_bounds=t1 - t0,
+                   t_pass=t2 - t1,
+                   theta=th.copy(), res_max=float(np.max(res[:wanted])))
+        recs.append(rec)
+        X, Y = Y, X
+        theta = th
+        if log:
+            log(f"step {s}: a={a:.4f} b={b:.3f} m={m} lanczos={bool(fb)} "
+                f"res_max={rec['res_max']:.3e}")
+    return recs, X
+
+
+def lanczos_chooser(ctx, v0, wanted: int, k: int = 10):
+    """The baseline: Lanczos b, a = theta_N, degree by degree_rule."""
+    def choose(step, feats, theta):
+        _, b = ctx.lanczos_bounds(v0, k)
+        a = float(theta[-1])
+        return a, b, degree_rule(float(theta[0]), float(theta[wanted - 1]), a, b), True
+    return choose
+
+
+def mlp_chooser(ctx, mlp, v0, k: int = 10):
+    def choose(step, feats, theta):
+        return ctx.bounds_predict(mlp, history_vector(feats), v0, lanczos_k=k)
+    return choose
+
+
+def normalisation(inputs: np.ndarray, targets: np.ndarray):
+    im, isd = inputs.mean(axis=0), inputs.std(axis=0)
+    om, osd = targets.mean(axis=0), targets.std(axis=0)
+    isd = np.where(isd > 1e-12 * (1.0 + np.abs(im)), isd, 1.0)
+    osd = np.where(osd > 1e-12 * (1.0 + np.abs(om)), osd, 1.0)
+    return im, isd, om, osd
+
+
+def train(mlp, inputs: np.ndarray, targets: np.ndarray, steps: int = 2000, batch: int = 64,
+          lr: float = 1e-3, seed: int = 0, log=None):
+    """Adam on minibatches of the normalised corpus, all arithmetic in the
+    library's network kernels.  Returns the loss per step."""
+    import torch
+    im, isd, om, osd = normalisation(inputs, targets)
+    mlp.set_normalization(im, isd, om, osd)
+    Xn = torch.tensor((inputs - im) / isd, dtype=torch.float32, device=mlp.device)
+    Tn = torch.tensor((targets - om) / osd, dtype=torch.float32, device=mlp.device)
+    rng = np.random.default_rng(seed)
+    S = Xn.shape[0]
+    B = min(batch, S, mlp.max_batch)
+    losses = []
+    for it in range(steps):
+        idx = torch.tensor(rng.choice(S, size=B, replace=False), device=mlp.device)
+        xb, tb = Xn[idx].contiguous(), Tn[idx].contiguous()
+        losses.append(mlp.loss_grad(xb, tb))
+        mlp.adam_step(lr)
+        if log and (it % 250 == 0 or it == steps - 1):
+            log(f"train step {it}: loss {losses[-1]:.4e}")
+    return np.array(losses)

@@ -51,3 +51,24 @@ def test_null_arguments_are_rejected_without_device_work():
     assert b"null" in lib.chebfilter_last_error(None)
     assert lib.chebfilter_destroy(None) == 0
     assert lib.chebfilter_apply_H(None, None, 0, None, 0, 0) == 1
+
+
+def test_bounds_features_transform():
+    """The learned-bounds input transform is host code of the library (no GPU):
+    energies relative to the last step's theta_N in units of its b - theta_N,
+    degree / 100, log10 of the residual-type features over that width."""
+    import numpy as np
+    from paper_1610_02121_amd.binding import ChebFilterError, bounds_features
+    rows = [np.array([-5.0, -2.0, -1.0, 9.0, 40.0, 1e-3, 1e-4, 1e-6]),
+            np.array([-5.5, -2.5, -1.5, 10.0 - 1.5 + 1.5, 30.0, 2e-2, 5e-4, 0.0])]
+    h = np.concatenate(rows)
+    x = bounds_features(h)
+    thN, w = -1.5, 10.0 + 1.5
+    for s, r in enumerate(rows):
+        assert np.allclose(x[8 * s:8 * s + 4], (r[:4] - thN) / w)
+        assert np.isclose(x[8 * s + 4], r[4] / 100)
+        assert np.allclose(x[8 * s + 5:8 * s + 8], np.log10(r[5:] / w + 1e-30))
+    bad = h.copy()
+    bad[-5] = bad[-6] - 1.0          # b below theta_N in the last step
+    with pytest.raises(ChebFilterError):
+        bounds_features(bad)

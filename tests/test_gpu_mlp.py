@@ -1,0 +1,190 @@
+"""The learned-bounds network and guard on the GPU, against the FP64 oracle
+network (oracle/mlp.py, pinned in test_oracle_mlp.py), plus the operator
+update and Ritz-residual entry points against the oracle operators.
+
+Tolerances: the device network is FP32 with dot products of at most 128
+terms per layer, 4 layers: forward outputs within 1e-4 of max|y| (4 layers x
+~130 roundings x 2^-24, times a margin for GELU and cancellation); gradients
+within 5e-4 of max|g| (the backward pass doubles the chain); one Adam step
+reproduces the oracle update of the device gradient to FP32 rounding.
+"""
+import copy
+
+import numpy as np
+import pytest
+
+from oracle import mlp as omlp
+from oracle.operators import Operators
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+SHAPE = (64, 128, 3, 3)
+
+
+def dev(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def dev32(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float32, device="cuda")
+
+
+def make(B=128):
+    from paper_1610_02121_amd import Mlp
+    from paper_1610_02121_amd.learned import init_params
+    net = Mlp(*SHAPE, max_batch=B)
+    p = init_params(seed=3)
+    net.set_params(p)
+    return net, p
+
+
+def test_forward_matches_oracle():
+    net, p = make()
+    X = np.random.default_rng(0).standard_normal((37, SHAPE[0])).astype(np.float32)
+    Y = net.forward(dev32(X)).cpu().numpy()
+    Yo, _ = omlp.forward(p.astype(np.float64), X.astype(np.float64), *SHAPE)
+    err = np.abs(Y - Yo).max() / np.abs(Yo).max()
+    print(f"forward rel err {err:.3e}")
+    assert err < 1e-4
+    assert np.array_equal(net.get_params(), p)
+
+
+def test_gradient_and_adam_match_oracle():
+    net, p = make()
+    rng = np.random.default_rng(1)
+    X = rng.standard_normal((50, SHAPE[0])).astype(np.float32)
+    T = rng.standard_normal((50, SHAPE[3])).astype(np.float32)
+    loss, g = net.loss_grad(dev32(X), dev32(T), want_grad=True)
+    lo, go = omlp.loss_grad(p.astype(np.float64), X.astype(np.float64), T.astype(np.float64), *SHAPE)
+    gerr = np.abs(g - go).max() / np.abs(go).max()
+    print(f"loss {loss:.6f} vs {lo:.6f}; grad rel err {gerr:.3e}")
+    assert abs(loss - lo) < 1e-5 * abs(lo)
+    assert gerr < 5e-4
+    net.adam_step(1e-3)
+    p1 = net.get_params()
+    po, _, _ = omlp.adam(p.astype(np.float64), g.astype(np.float64), np.zeros(p.size),
+                         np.zeros(p.size), 1, lr=1e-3)
+    assert np.abs(p1 - po).max() < 1e-6 * (1.0 + np.abs(po).max())
+
+
+def test_training_reduces_loss():
+    """Adam in the library's kernels fits a smooth map of the inputs."""
+    from paper_1610_02121_amd.learned import train
+    net, _ = make(B=64)
+    rng = np.random.default_rng(2)
+    X = rng.standard_normal((400, SHAPE[0]))
+    T = np.stack([np.sin(X[:, 0]) + 0.5 * X[:, 1], X[:, 2] * X[:, 3], np.tanh(X[:, 4:8].sum(1))], 1)
+    losses = train(net, X, T, steps=400, batch=64, lr=2e-3, seed=0)
+    print(f"loss {losses[:10].mean():.3e} -> {losses[-10:].mean():.3e}")
+    assert losses[-10:].mean() < 0.1 * losses[:10].mean()
+
+
+def history(theta_1, theta_w, theta_N, b, m):
+    row = np.array([theta_1, theta_w, theta_N, b, m, 1e-3, 1e-4, 1e-5])
+    return np.tile(row, 8)
+
+
+def test_guard_accepts_and_falls_back(hydrogen_small):
+    """Network reduced to its output bias (all weights zero): the guard takes
+    an in-window prediction (with the 5 % margin on b) and replaces an
+    out-of-window one by the Lanczos bound."""
+    from paper_1610_02121_amd import Context, Mlp
+    ctx = Context(hydrogen_small, max_cols=8)
+    v0 = dev(np.random.default_rng(4).standard_normal(hydrogen_small.n)).reshape(-1)
+    net = Mlp(*SHAPE, max_batch=4)
+    net.set_normalization(np.zeros(64), np.ones(64), np.zeros(3), np.ones(3))
+    npar = omlp.n_params(*SHAPE)
+    h = history(-2.0, -1.5, -1.0, 10.0, 30)
+
+    def with_bias(a, b, m):
+        p = np.zeros(npar)
+        omlp.unpack(p, *SHAPE)[-1][1][:] = [a, b, m]
+        net.set_params(p.astype(np.float32))
+
+    # outputs (alpha, beta, m): a = theta_N + alpha w, b = theta_N + beta w, theta_N = -1, w = 11
+    with_bias(-0.2 / 11, 13.0 / 11, 33.4)
+    a, b, m, fb = ctx.bounds_predict(net, h, v0, lanczos_k=10, m_min=8, m_max=120)
+    assert not fb and m == 33
+    assert abs(a - (-1.2)) < 1e-6 and abs(b - (-1.0 + 1.05 * 13.0)) < 1e-5
+    with_bias(6.0 / 11, 13.0 / 11, 500.0)   # a outside its window, m above m_max
+    a, b, m, fb = ctx.bounds_predict(net, h, v0, lanczos_k=10, m_min=8, m_max=120)
+    assert not fb and a == -1.0 and m == 120
+    with_bias(-0.2 / 11, 10.5 / 11, 33.0)  # beta = 0.955 < 0.98: fall back
+    a, b, m, fb = ctx.bounds_predict(net, h, v0, lanczos_k=10, m_min=8, m_max=120)
+    lo, bl = ctx.lanczos_bounds(v0, 10)
+    assert fb and b == bl and a == -1.0 and m == 30
+    with_bias(-0.2 / 11, float("nan"), 33.0)
+    assert ctx.bounds_predict(net, h, v0)[3]
+    ctx.close()
+
+
+def test_update_H_cc_and_residual_norms(si_small):
+    from paper_1610_02121_amd import Context
+    from synth import perturb
+    ctx = Context(si_small, max_cols=24)
+    H1 = next(perturb.sequence(si_small, 1, seed=7))
+    ctx.update_H_cc(H1)
+    P = copy.deepcopy(si_small)
+    P.H_cc = H1
+    ops = Operators(P)
+    X = np.random.default_rng(5).standard_normal((ops.n, 24))
+    Y = ctx.apply_H(dev(X)).cpu().numpy()
+    Yo = ops.apply_H(X)
+    assert np.abs(Y - Yo).max() < 1e-12 * np.abs(Yo).max()
+    assert np.abs(Yo - Operators(si_small).apply_H(X)).max() > 1e-6 * np.abs(Yo).max()
+    theta = np.linspace(-3.0, 1.0, 24)
+    res = ctx.residual_norms(dev(X), theta)
+    R = ops.apply_H(X) - ops.apply_M(X) * theta[None, :]
+    ro = np.sqrt(np.einsum("ij,ij->j", R, ops.solve_M(R)))
+    print(f"residual rel err {np.abs(res - ro).max() / ro.max():.3e}")
+    assert np.abs(res - ro).max() < 1e-9 * ro.max()
+    ctx.close()
+
+
+def test_learned_sequence_against_oracle_eigenvalues(hydrogen_cfg1):
+    """A short self-consistent-step sequence (hydrogen, 8^3 cells, N = 24, 14
+    wanted) with the Lanczos bound and with a network trained on two other
+    sequences: at every step the wanted Ritz values are upper bounds of the
+    oracle's eigenvalues of that step's operator (Courant-Fischer), and the
+    learned path ends as accurate as the Lanczos path."""
+    import scipy.sparse.linalg as spla
+    from paper_1610_02121_amd import Context, Mlp
+    from paper_1610_02121_amd import learned as L
+    from synth import perturb
+    prob = hydrogen_cfg1
+    N, wanted, steps = 24, 14, 6
+    ctx = Context(prob, max_cols=N)
+    v0 = dev(np.random.default_rng(8).standard_normal(prob.n)).reshape(-1)
+    inputs, targets = [], []
+    for sq in range(2):
+        recs, _ = L.run_sequence(ctx, prob, N, wanted, 12, seed=50 + sq,
+                                 chooser=L.lanczos_chooser(ctx, v0, wanted), v0=v0, label_k=40)
+        inputs += [r["input"] for r in recs]
+        targets += [r["target"] for r in recs]
+    net = Mlp(L.N_IN, L.WIDTH, L.DEPTH, L.N_OUT, max_batch=32)
+    net.set_params(L.init_params(seed=1))
+    losses = L.train(net, np.array(inputs), np.array(targets), steps=300, batch=16, lr=3e-4)
+    assert np.isfinite(losses).all()
+    lam = []
+    for Hs in perturb.sequence(prob, steps, seed=99):
+        P = copy.deepcopy(prob)
+        P.H_cc = Hs
+        ops = Operators(P)
+        lam.append(np.sort(spla.eigsh(ops.H, k=wanted, M=ops.M, sigma=-1.0, which="LM",
+                                      return_eigenvectors=False)))
+    errs = {}
+    for name, chooser in (("lanczos", L.lanczos_chooser(ctx, v0, wanted)),
+                          ("learned", L.mlp_chooser(ctx, net, v0))):
+        recs, _ = L.run_sequence(ctx, prob, N, wanted, steps, seed=99, chooser=chooser, v0=v0,
+                                 lanczos_fallback=L.lanczos_chooser(ctx, v0, wanted))
+        e = []
+        for s, r in enumerate(recs):
+            th = r["theta"][:wanted]
+            assert np.all(th >= lam[s] - 1e-9), (name, s)
+            e.append(float(np.abs(th - lam[s]).max()))
+        errs[name] = e
+        print(name, ["%.1e" % x for x in e], "fallbacks", sum(r["fallback"] for r in recs))
+    assert errs["learned"][-1] <= 10 * errs["lanczos"][-1] + 1e-8
+    ctx.close()

@@ -412,6 +412,13 @@ def main():
                     help="skip the filter-only timing of the three precision forms")
     ap.add_argument("--mixed-study", action="store_true",
                     help="run the time-to-tolerance study of the precision forms instead")
+    ap.add_argument("--problem-cache", default=None,
+                    help="load the generated workload from this .npz if it exists, else "
+                         "generate it and save it there (profiling runs avoid the generator's "
+                         "worker processes this way)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only copy an n x N FP64 block 5 times with the library's copy kernel "
+                         "(a kernel of known traffic, to calibrate the HBM byte counters)")
     ap.add_argument("--learned-study", action="store_true",
                     help="train the bounds network and compare it with the Lanczos bound")
     ap.add_argument("--m-reduced", type=int, default=20,
@@ -437,8 +444,15 @@ def main():
         return
     _, N, m, wanted = WORKLOADS[name]
     t0 = time.time()
-    log(f"generating {name} (seed {args.seed})")
-    prob = make_problem(name, args.seed)
+    if args.problem_cache and os.path.exists(args.problem_cache):
+        from synth.problem import Problem
+        log(f"loading {name} from {args.problem_cache}")
+        prob = Problem.load(args.problem_cache)
+    else:
+        log(f"generating {name} (seed {args.seed})")
+        prob = make_problem(name, args.seed)
+        if args.problem_cache:
+            prob.save(args.problem_cache)
     log(f"generated n={prob.n} n_h={prob.n_h} n_e={prob.n_e} cells={prob.n_cells} in "
         f"{time.time() - t0:.1f}s")
     dev = torch.device("cuda", 0)
@@ -446,6 +460,17 @@ def main():
     # the study checks every filter output for non-finite values
     ctx = Context(prob, max_cols=N, check_finite=args.mixed_study)
     log(f"context ready ({time.time() - t0:.1f}s)")
+    if args.copy_probe:
+        # filter of degree 0 = k_copy of the n x N block: 8 n N bytes read and written
+        Xc = torch.randn(prob.n, N, dtype=torch.float64, device=dev)
+        Yc = torch.empty_like(Xc)
+        for _ in range(5):
+            ctx.filter(Xc, 0, 0.0, 1.0, Y=Yc)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe": "k_copy", "bytes_read": 8 * prob.n * N,
+                          "bytes_written": 8 * prob.n * N, "calls": 5}), flush=True)
+        ctx.close()
+        return
     X0 = configs.initial_block(prob, N, seed=args.seed)
     X = torch.tensor(X0, dtype=torch.float64, device=dev)
     Y = torch.empty_like(X)

@@ -100,6 +100,7 @@ __global__ __launch_bounds__(64) void kb_enr_reduce(const BatchProb *__restrict_
 }
 
 // z = S^-1 w, in the summation order of the single-problem FP64 kernel
+// (k_enr_reduce: four contiguous ranges of the row, combined in order)
 __global__ __launch_bounds__(64) void kb_schur(const BatchProb *__restrict__ bp,
                                                const int64_t *__restrict__ aoff, int count) {
   const int p = entry_of(aoff, count, blockIdx.y);
@@ -108,9 +109,17 @@ __global__ __launch_bounds__(64) void kb_schur(const BatchProb *__restrict__ bp,
   if (col >= P.N) return;
   const int al = (int)(blockIdx.y - aoff[p]);
   const double *drow = P.Sinv + (int64_t)al * P.n_e;
-  double acc = 0.0, sd = 0.0;
-  for (int be = 0; be < P.n_e; ++be) sd += drow[be] * P.Wb[(int64_t)be * P.mc + col];
-  acc += sd;
+  const int n_e = (int)P.n_e;
+  double part[4];
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    const int b0 = (n_e * w) / 4, b1 = (n_e * (w + 1)) / 4;
+    double sd = 0.0;
+    for (int be = b0; be < b1; ++be) sd += drow[be] * P.Wb[(int64_t)be * P.mc + col];
+    part[w] = sd;
+  }
+  double acc = 0.0;
+  acc += ((part[0] + part[1]) + part[2]) + part[3];
   P.Zb[(int64_t)al * P.mc + col] = acc;
 }
 

@@ -6,6 +6,8 @@
 //   A (16 x 4):  lane l holds A[l % 16][l / 16]
 //   B (4 x 16):  lane l holds B[l / 16][l % 16]
 //   D (16 x 16): lane l, element r holds D[4 * r + l / 16][l % 16]
+#include <algorithm>
+
 #include "cf_kernels.h"
 
 namespace cf {
@@ -136,26 +138,39 @@ hipError_t launch_cell_gemm(hipStream_t s, const double *Hp, const int32_t *dofp
 //   P[k0+k] = cH * sum_a H^ec_e[k][a] X[dof(e,a)]
 //           + cM * sum_a M^ec_e[k][a] s(dof) R[dof(e,a)]
 // The cell blocks are stored transposed, [NPAD][nap] with nap = the cell's
-// enrichment count padded to 16, so A-fragment loads are contiguous; they are
-// fetched from HBM on the first tile and from L2 afterwards.  The next tile's
-// gathered rows are loaded into registers during the current tile's MFMAs.
+// enrichment count padded to 16, so A-fragment loads are contiguous.  The
+// blocks are read from memory once per call: every wave keeps its A fragments
+// in registers while the column tiles stream by (cells with more than 64
+// enrichment functions take several passes over the gathered rows, 64 output
+// rows per pass).  The next tile's gathered rows are loaded into registers
+// during the current tile's MFMAs.
 // Either term is skipped when its input block is null.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_enr_part(
+// 8 waves: wave w takes row block 4g + (w & 3) of group g and half
+// h = w >> 2 of the 128 k (local nodes); it keeps the A fragments of both
+// terms for its k half in registers while the column tiles stream by, and the
+// two halves are added through LDS.  blockIdx.y picks one of gridDim.y
+// contiguous ranges of column tiles (more workgroups in flight).
+__global__ __launch_bounds__(512, 2) void k_enr_part(
     const double *__restrict__ HT, const double *__restrict__ MT,
     const int64_t *__restrict__ toff, const int32_t *__restrict__ tld,
     const int64_t *__restrict__ eptr, const int32_t *__restrict__ dofp,
     const int32_t *__restrict__ cells, const double *__restrict__ X, int64_t ldx, double cH,
     const double *__restrict__ R, int64_t ldr, const double *__restrict__ rs, double cM,
     double *__restrict__ P, int64_t ldp, int N) {
-  constexpr int PT = 16, LDX = 32;
-  constexpr int PF = NPAD * PT / 256;     // 8 gathered values per thread per block
-  constexpr int RPP = 256 / PT;           // 16 rows per pass
+  constexpr int PT = 16, LDX = PT + 1;
+  constexpr int PF = NPAD * PT / 512;     // 4 gathered values per thread per term and tile
+  constexpr int RPP = 512 / PT;           // 32 rows per pass
   __shared__ double xs[NPAD * LDX];
   __shared__ double rsm[NPAD * LDX];
+  __shared__ double xch[4][4][64];        // k-half 1 partial sums, per row block
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, kq = lane >> 4;
+  const int wb = w & 3, h = w >> 2;
   const int cell = cells[blockIdx.x];
+  const int ntile = (N + PT - 1) / PT;
+  const int cbeg = PT * ((ntile * (int)blockIdx.y) / (int)gridDim.y);
+  const int cend = min(N, PT * ((ntile * ((int)blockIdx.y + 1)) / (int)gridDim.y));
   const int gj = tid % PT, gr = tid / PT;
   int gd[PF];
   double gsc[PF];
@@ -164,55 +179,73 @@ __global__ __launch_bounds__(256) void k_enr_part(
     gd[p] = dofp[(int64_t)cell * NPAD + gr + p * RPP];
     gsc[p] = (rs && gd[p] >= 0) ? rs[gd[p]] : 1.0;
   }
-  double px[PF], pr[PF];
-#pragma unroll
-  for (int p = 0; p < PF; ++p) {
-    const bool v = gd[p] >= 0 && gj < N;
-    px[p] = (X && v) ? X[(int64_t)gd[p] * ldx + gj] : 0.0;
-    pr[p] = (R && v) ? R[(int64_t)gd[p] * ldr + gj] * gsc[p] : 0.0;
-  }
   const int64_t k0 = eptr[cell];
   const int na = (int)(eptr[cell + 1] - k0);
   const int nap = tld[cell];
   const int nmb = nap >> 4;
   const double *ht = X ? HT + toff[cell] : nullptr;
   const double *mt = R ? MT + toff[cell] : nullptr;
-  for (int c0 = 0; c0 < N; c0 += PT) {
-    const int ncol = min(PT, N - c0);
+  if (cbeg >= cend) return;              // uniform for the workgroup
+  for (int g = 0; 4 * g < nmb; ++g) {
+    const int mb = 4 * g + wb;
+    const bool act = mb < nmb;
+    double aH[16], aM[16];
+#pragma unroll
+    for (int ks = 0; ks < 16; ++ks) {
+      const int64_t off = (int64_t)(64 * h + 4 * ks + kq) * nap + 16 * mb + li;
+      aH[ks] = (act && ht) ? ht[off] : 0.0;
+      aM[ks] = (act && mt) ? mt[off] : 0.0;
+    }
+    double px[PF], pr[PF];
 #pragma unroll
     for (int p = 0; p < PF; ++p) {
-      xs[(gr + p * RPP) * LDX + gj] = px[p];
-      rsm[(gr + p * RPP) * LDX + gj] = pr[p];
+      const bool v = gd[p] >= 0 && cbeg + gj < cend;
+      px[p] = (X && v) ? X[(int64_t)gd[p] * ldx + cbeg + gj] : 0.0;
+      pr[p] = (R && v) ? R[(int64_t)gd[p] * ldr + cbeg + gj] * gsc[p] : 0.0;
     }
-    __syncthreads();
-    const int c1 = c0 + PT;
-    if (c1 < N) {
+    for (int c0 = cbeg; c0 < cend; c0 += PT) {
+      const int ncol = min(PT, cend - c0);
 #pragma unroll
       for (int p = 0; p < PF; ++p) {
-        const bool v = gd[p] >= 0 && c1 + gj < N;
-        px[p] = (X && v) ? X[(int64_t)gd[p] * ldx + c1 + gj] : 0.0;
-        pr[p] = (R && v) ? R[(int64_t)gd[p] * ldr + c1 + gj] * gsc[p] : 0.0;
+        xs[(gr + p * RPP) * LDX + gj] = px[p];
+        rsm[(gr + p * RPP) * LDX + gj] = pr[p];
       }
-    }
-    for (int mb = w; mb < nmb; mb += 4) {
-      d4 accH = d4zero(), accM = d4zero();
-      if (ht) {
-#pragma unroll 8
-        for (int ks = 0; ks < 32; ++ks)
-          accH = mfma_f64(ht[(int64_t)(4 * ks + kq) * nap + 16 * mb + li],
-                          xs[(4 * ks + kq) * LDX + li], accH);
+      __syncthreads();
+      const int c1 = c0 + PT;
+      if (c1 < cend) {
+#pragma unroll
+        for (int p = 0; p < PF; ++p) {
+          const bool v = gd[p] >= 0 && c1 + gj < cend;
+          px[p] = (X && v) ? X[(int64_t)gd[p] * ldx + c1 + gj] : 0.0;
+          pr[p] = (R && v) ? R[(int64_t)gd[p] * ldr + c1 + gj] * gsc[p] : 0.0;
+        }
       }
-      if (mt) {
-#pragma unroll 8
-        for (int ks = 0; ks < 32; ++ks)
-          accM = mfma_f64(mt[(int64_t)(4 * ks + kq) * nap + 16 * mb + li],
-                          rsm[(4 * ks + kq) * LDX + li], accM);
+      d4 acc = d4zero();
+      if (act) {
+        d4 accH = d4zero(), accM = d4zero();
+        if (ht) {
+#pragma unroll
+          for (int ks = 0; ks < 16; ++ks)
+            accH = mfma_f64(aH[ks], xs[(64 * h + 4 * ks + kq) * LDX + li], accH);
+        }
+        if (mt) {
+#pragma unroll
+          for (int ks = 0; ks < 16; ++ks)
+            accM = mfma_f64(aM[ks], rsm[(64 * h + 4 * ks + kq) * LDX + li], accM);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[r] = cH * accH[r] + cM * accM[r];
+        if (h == 1) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) xch[wb][r][lane] = acc[r];
+        }
       }
-      if (li < ncol) {
+      __syncthreads();
+      if (act && h == 0 && li < ncol) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int orow = 16 * mb + kq + 4 * r;
-          if (orow < na) P[(k0 + orow) * ldp + c0 + li] = cH * accH[r] + cM * accM[r];
+          if (orow < na) P[(k0 + orow) * ldp + c0 + li] = acc[r] + xch[wb][r][lane];
         }
       }
     }
@@ -226,8 +259,10 @@ hipError_t launch_enr_part(hipStream_t s, const double *HT, const double *MT, co
                            double cH, const double *R, int64_t ldr, const double *rs, double cM,
                            double *P, int64_t ldp, int N) {
   if (ncells <= 0 || N <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_enr_part, dim3(ncells), dim3(256), 0, s, HT, MT, toff, tld, eptr, dofp, cells,
-                     X, ldx, cH, R, ldr, rs, cM, P, ldp, N);
+  // one column range per cell (splitting the columns over 2-4 workgroups per
+  // cell measured slower on the 30-atom workload: the blocks are re-read)
+  hipLaunchKernelGGL(k_enr_part, dim3(ncells, 1), dim3(512), 0, s, HT, MT, toff, tld, eptr, dofp,
+                     cells, X, ldx, cH, R, ldr, rs, cM, P, ldp, N);
   return hipGetLastError();
 }
 
@@ -237,68 +272,116 @@ hipError_t launch_enr_part(hipStream_t s, const double *HT, const double *MT, co
 // read-modify-write):
 //   Q[128 e' + a] = sum_k (cU H^ec_e[k][a] U[idx_k] + cV M^ec_e[k][a] V[idx_k])
 // e' is the position of the cell in the enriched-cell list, a its local node.
-// The gathered rows cU U[idx_k] and cV V[idx_k] sit in LDS (dynamic size:
-// 2 K4 rows of 16 columns, K4 = count rounded up to 4); the cell's coupling
-// rows are read from HBM on the first tile and from L2 afterwards.  Either
-// term is skipped when its input is null.  The epilogue sums, for each
+// The enrichment functions of the cell are taken in chunks of 64: wave w
+// keeps the A fragments of rows 32w .. 32w+32 of both transposed blocks for
+// the chunk in registers while the column tiles stream by (the blocks are read
+// from memory once per call); the gathered rows cU U[idx_k], cV V[idx_k] of
+// the chunk pass through LDS, prefetched one tile ahead in registers; chunks
+// after the first add into Q.  Either term is skipped when its input is null.  The epilogue sums, for each
 // classical DOF, the (at most 8) Q rows of the enriched cells that contain it.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_enr_q(
+__global__ __launch_bounds__(256, 2) void k_enr_q(
     const double *__restrict__ Hec, const double *__restrict__ Mec,
     const int64_t *__restrict__ eptr, const int32_t *__restrict__ eidx,
     const int32_t *__restrict__ cells, const double *__restrict__ U, int64_t ldu, double cU,
     const double *__restrict__ V, int64_t ldv, double cV, double *__restrict__ Q, int64_t ldq,
     int N) {
-  extern __shared__ double zs[];
-  constexpr int PT = 16, LDZ = 16;
+  constexpr int PT = 16, LDZ = 16, KC = 64, KS = KC / 4;
+  constexpr int GV = KC * PT / 256;        // gathered values per thread per term and tile
+  __shared__ double zu[KC * LDZ];
+  __shared__ double zv[KC * LDZ];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, kq = lane >> 4;
   const int cell = cells[blockIdx.x];
   const int64_t k0 = eptr[cell];
   const int na = (int)(eptr[cell + 1] - k0);
-  const int K4 = (na + 3) & ~3;
-  const int nks = K4 / 4;
   double *qb = Q + ((int64_t)blockIdx.x * NPAD) * ldq;
-  for (int c0 = 0; c0 < N; c0 += PT) {
-    const int ncol = min(PT, N - c0);
-    for (int idx = tid; idx < K4 * PT; idx += 256) {
-      const int k = idx / PT, j = idx % PT;
-      const bool v = k < na && j < ncol;
-      const int64_t al = v ? eidx[k0 + k] : 0;
-      zs[k * LDZ + j] = (U && v) ? cU * U[al * ldu + c0 + j] : 0.0;
-      zs[(K4 + k) * LDZ + j] = (V && v) ? cV * V[al * ldv + c0 + j] : 0.0;
-    }
-    __syncthreads();
-    d4 acc0 = d4zero(), acc1 = d4zero();
-    if (U) {
-      for (int ks = 0; ks < nks; ++ks) {
-        const int k = 4 * ks + kq;
-        const double *row = Hec + (k0 + min(k, na - 1)) * NPAD + 32 * w;
-        const double a0 = k < na ? row[li] : 0.0, a1 = k < na ? row[16 + li] : 0.0;
-        const double b = zs[k * LDZ + li];
-        acc0 = mfma_f64(a0, b, acc0);
-        acc1 = mfma_f64(a1, b, acc1);
-      }
-    }
-    if (V) {
-      for (int ks = 0; ks < nks; ++ks) {
-        const int k = 4 * ks + kq;
-        const double *row = Mec + (k0 + min(k, na - 1)) * NPAD + 32 * w;
-        const double a0 = k < na ? row[li] : 0.0, a1 = k < na ? row[16 + li] : 0.0;
-        const double b = zs[(K4 + k) * LDZ + li];
-        acc0 = mfma_f64(a0, b, acc0);
-        acc1 = mfma_f64(a1, b, acc1);
-      }
-    }
-    if (li < ncol) {
-      double *q = qb + c0 + li;
+  const int gj = tid % PT, gk = tid / PT;   // gather: column gj, rows gk + 16 p
+  // chunks of KC enrichment functions: the A fragments of the chunk (rows
+  // 32w .. 32w+32 of both transposed blocks) stay in registers while the
+  // column tiles stream by; chunks after the first add into Q
+  for (int kc = 0; kc < na; kc += KC) {
+    double aH0[KS], aH1[KS], aM0[KS], aM1[KS];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        q[(int64_t)(32 * w + kq + 4 * r) * ldq] = acc0[r];
-        q[(int64_t)(32 * w + 16 + kq + 4 * r) * ldq] = acc1[r];
-      }
+    for (int ks = 0; ks < KS; ++ks) {
+      const int k = kc + 4 * ks + kq;
+      const bool v = k < na;
+      const double *hr = Hec + (k0 + (v ? k : 0)) * NPAD + 32 * w;
+      const double *mr = Mec + (k0 + (v ? k : 0)) * NPAD + 32 * w;
+      aH0[ks] = (U && v) ? hr[li] : 0.0;
+      aH1[ks] = (U && v) ? hr[16 + li] : 0.0;
+      aM0[ks] = (V && v) ? mr[li] : 0.0;
+      aM1[ks] = (V && v) ? mr[16 + li] : 0.0;
     }
-    __syncthreads();
+    int64_t gal[GV];
+    bool gv[GV];
+#pragma unroll
+    for (int p = 0; p < GV; ++p) {
+      const int k = kc + gk + 16 * p;
+      gv[p] = k < na;
+      gal[p] = gv[p] ? eidx[k0 + k] : 0;
+    }
+    double pu[GV], pv[GV];
+#pragma unroll
+    for (int p = 0; p < GV; ++p) {
+      const bool v = gv[p] && gj < N;
+      pu[p] = (U && v) ? cU * U[gal[p] * ldu + gj] : 0.0;
+      pv[p] = (V && v) ? cV * V[gal[p] * ldv + gj] : 0.0;
+    }
+    for (int c0 = 0; c0 < N; c0 += PT) {
+      const int ncol = min(PT, N - c0);
+#pragma unroll
+      for (int p = 0; p < GV; ++p) {
+        zu[(gk + 16 * p) * LDZ + gj] = pu[p];
+        zv[(gk + 16 * p) * LDZ + gj] = pv[p];
+      }
+      __syncthreads();
+      const int c1 = c0 + PT;
+      if (c1 < N) {
+#pragma unroll
+        for (int p = 0; p < GV; ++p) {
+          const bool v = gv[p] && c1 + gj < N;
+          pu[p] = (U && v) ? cU * U[gal[p] * ldu + c1 + gj] : 0.0;
+          pv[p] = (V && v) ? cV * V[gal[p] * ldv + c1 + gj] : 0.0;
+        }
+      }
+      d4 acc0 = d4zero(), acc1 = d4zero();
+      if (U) {
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+          const double b = zu[(4 * ks + kq) * LDZ + li];
+          acc0 = mfma_f64(aH0[ks], b, acc0);
+          acc1 = mfma_f64(aH1[ks], b, acc1);
+        }
+      }
+      if (V) {
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+          const double b = zv[(4 * ks + kq) * LDZ + li];
+          acc0 = mfma_f64(aM0[ks], b, acc0);
+          acc1 = mfma_f64(aM1[ks], b, acc1);
+        }
+      }
+      if (li < ncol) {
+        double *q = qb + c0 + li;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          double *q0 = q + (int64_t)(32 * w + kq + 4 * r) * ldq;
+          double *q1 = q + (int64_t)(32 * w + 16 + kq + 4 * r) * ldq;
+          if (kc == 0) { *q0 = acc0[r]; *q1 = acc1[r]; }
+          else { *q0 += acc0[r]; *q1 += acc1[r]; }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  if (na == 0) {
+    // no enrichment functions: the cell's buffer rows are zero
+    for (int c0 = 0; c0 < N; c0 += PT)
+      for (int idx = tid; idx < NPAD * PT; idx += 256) {
+        const int a = idx / PT, j = idx % PT;
+        if (c0 + j < N) qb[(int64_t)a * ldq + c0 + j] = 0.0;
+      }
   }
 }
 
@@ -307,15 +390,8 @@ hipError_t launch_enr_q(hipStream_t s, const double *Hec, const double *Mec, con
                         const double *U, int64_t ldu, double cU, const double *V, int64_t ldv,
                         double cV, double *Q, int64_t ldq, int N) {
   if (ncells <= 0 || N <= 0) return hipSuccess;
-  const size_t shm = (size_t)2 * ((kmax + 3) & ~3) * 16 * sizeof(double);
-  static size_t shm_set = 0;
-  if (shm > 65536 && shm > shm_set) {
-    hipError_t e = hipFuncSetAttribute((const void *)k_enr_q,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    if (e != hipSuccess) return e;
-    shm_set = shm;
-  }
-  hipLaunchKernelGGL(k_enr_q, dim3(ncells), dim3(256), shm, s, Hec, Mec, eptr, eidx, cells, U, ldu,
+  (void)kmax;
+  hipLaunchKernelGGL(k_enr_q, dim3(ncells), dim3(256), 0, s, Hec, Mec, eptr, eidx, cells, U, ldu,
                      cU, V, ldv, cV, Q, ldq, N);
   return hipGetLastError();
 }
@@ -325,28 +401,39 @@ hipError_t launch_enr_q(hipStream_t s, const double *Hec, const double *Mec, con
 // of the per-cell partials, plus an optional dense n_e x n_e product and an
 // optional scaled extra term.  Deterministic: no atomics.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(64) void k_enr_reduce(
+__global__ __launch_bounds__(256) void k_enr_reduce(
     int n_e, const int64_t *__restrict__ aptr, const int32_t *__restrict__ alist,
     const double *__restrict__ P, int64_t ldp, double s_p, const double *__restrict__ R0,
     int64_t ldr0, double s_r, const double *__restrict__ Dn, const double *__restrict__ Zd,
     int64_t ldzd, double *__restrict__ out, int64_t ldo, int N) {
-  const int col = blockIdx.x * 64 + threadIdx.x;
+  // 4 waves split the partial rows and the dense product into 4 contiguous
+  // ranges each (a partition fixed by the sizes), combined in wave order
+  __shared__ double part[2][4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int col = blockIdx.x * 64 + lane;
   const int al = blockIdx.y;
-  if (col >= N) return;
-  double acc = 0.0;
-  if (P) {
-    double sp = 0.0;
-    for (int64_t k = aptr[al]; k < aptr[al + 1]; ++k) sp += P[(int64_t)alist[k] * ldp + col];
-    acc = s_p * sp;
+  const bool cv = col < N;
+  double sp = 0.0, sd = 0.0;
+  if (P && cv) {
+    const int64_t a0 = aptr[al], a1 = aptr[al + 1], len = a1 - a0;
+    const int64_t q0 = a0 + (len * w) / 4, q1 = a0 + (len * (w + 1)) / 4;
+    for (int64_t k = q0; k < q1; ++k) sp += P[(int64_t)alist[k] * ldp + col];
   }
-  if (R0) acc += s_r * R0[(int64_t)al * ldr0 + col];
-  if (Dn) {
+  if (Dn && cv) {
     const double *drow = Dn + (int64_t)al * n_e;
-    double sd = 0.0;
-    for (int be = 0; be < n_e; ++be) sd += drow[be] * Zd[(int64_t)be * ldzd + col];
-    acc += sd;
+    const int b0 = (n_e * w) / 4, b1 = (n_e * (w + 1)) / 4;
+    for (int be = b0; be < b1; ++be) sd += drow[be] * Zd[(int64_t)be * ldzd + col];
   }
-  out[(int64_t)al * ldo + col] = acc;
+  part[0][w][lane] = sp;
+  part[1][w][lane] = sd;
+  __syncthreads();
+  if (w == 0 && cv) {
+    double acc = 0.0;
+    if (P) acc = s_p * (((part[0][0][lane] + part[0][1][lane]) + part[0][2][lane]) + part[0][3][lane]);
+    if (R0) acc += s_r * R0[(int64_t)al * ldr0 + col];
+    if (Dn) acc += ((part[1][0][lane] + part[1][1][lane]) + part[1][2][lane]) + part[1][3][lane];
+    out[(int64_t)al * ldo + col] = acc;
+  }
 }
 
 hipError_t launch_enr_reduce(hipStream_t s, int n_e, const int64_t *aptr, const int32_t *alist,
@@ -355,7 +442,7 @@ hipError_t launch_enr_reduce(hipStream_t s, int n_e, const int64_t *aptr, const 
                              int64_t ldzd, double *out, int64_t ldo, int N) {
   if (n_e <= 0 || N <= 0) return hipSuccess;
   dim3 grid((N + 63) / 64, n_e);
-  hipLaunchKernelGGL(k_enr_reduce, grid, dim3(64), 0, s, n_e, aptr, alist, P, ldp, s_p, R0, ldr0,
+  hipLaunchKernelGGL(k_enr_reduce, grid, dim3(256), 0, s, n_e, aptr, alist, P, ldp, s_p, R0, ldr0,
                      s_r, Dn, Zd, ldzd, out, ldo, N);
   return hipGetLastError();
 }

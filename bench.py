@@ -35,9 +35,35 @@ WORKLOADS = {
     # name: (generator, N, m, wanted)
     "si30-24c": ("config2", 260, 40, 210),
     "hydrogen-8c": ("config1", 16, 20, 14),
+    # the same Si cluster and mesh with classical elements only (n_e = 0)
+    "si30-classical": ("config2_classical", 260, 40, 210),
     # 256 independent Si clusters of 1-8 atoms (N 16-64 each), batched form
     "si-batch256": ("batch_workload", None, 40, None),
 }
+
+
+def cell_kernel_source_hash() -> str:
+    """sha256 of the k_cell_gemm kernel's source text (the counters in the
+    committed profile are valid only for that text)."""
+    import hashlib
+    src = open(os.path.join(ROOT, "paper_1610_02121_amd", "csrc", "cf_ops.hip")).read()
+    i = src.index("void k_cell_gemm(")
+    j = src.index("hipError_t launch_cell_gemm(", i)
+    return hashlib.sha256(src[i:j].encode()).hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per k_cell_gemm launch from the committed counter profile, if
+    it was taken on the current kernel source; else None."""
+    import re
+    path = os.path.join(ROOT, "profiles", "k_cell_gemm-si30-24c.md")
+    if not os.path.exists(path):
+        return None
+    m = re.search(r"pmc-traffic: kernel=k_cell_gemm bytes_per_launch=(\d+) source_sha256=([0-9a-f]+)",
+                  open(path).read())
+    if not m or m.group(2) != cell_kernel_source_hash():
+        return None
+    return int(m.group(1))
 
 
 def log(msg):
@@ -406,6 +432,8 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--passes", type=int, default=1,
+                    help="filter passes per step (each of degree m, Rayleigh-Ritz between them)")
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16"],
                     help="arithmetic of the filter in the timed steps (Rayleigh-Ritz stays FP64)")
     ap.add_argument("--no-forms", action="store_true",
@@ -493,7 +521,10 @@ def main():
         lo, b = ctx.lanczos_bounds(v0, 10)          # synchronises
         s1 = time.perf_counter()
         a = float(state["theta"][-1])
-        ctx.filter(state["X"], m, a, b, Y=state["Y"], prec=args.prec)
+        if args.passes > 1:
+            ctx.filter_multipass(state["X"], m, args.passes, a, b, Y=state["Y"], prec=args.prec)
+        else:
+            ctx.filter(state["X"], m, a, b, Y=state["Y"], prec=args.prec)
         torch.cuda.synchronize()
         s2 = time.perf_counter()
         th = ctx.rayleigh_ritz(state["Y"])          # synchronises
@@ -541,7 +572,7 @@ def main():
     res_max = float(res[:wanted].max())
 
     n = prob.n
-    value = n * N * m / (ms_per_step / 1e3)
+    value = n * N * m * args.passes / (ms_per_step / 1e3)
     out = {
         "metric": "Chebyshev-filter DOF*vectors/s (per degree, whole SCF step) and SCF-step time",
         "value": value,
@@ -551,13 +582,14 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "bf16"}[args.prec], "data": "synthetic",
         "config": {"workload": name, "n_dof": n, "n_enrich": prob.n_e, "cells": prob.n_cells,
-                   "degree_p": prob.p, "vectors": N, "cheb_degree": m, "wanted": wanted,
+                   "degree_p": prob.p, "vectors": N, "cheb_degree": m, "filter_passes": args.passes,
+                "wanted": wanted,
                    "precision": args.prec if args.prec == "fp64" else
                    f"{args.prec} filter, fp64 Schur solve and Rayleigh-Ritz"},
         "phases_ms": {"bounds": 1e3 * state["t_bounds"] / args.steps,
                       "filter": 1e3 * state["t_filter"] / args.steps,
                       "cholqr_rr": 1e3 * state["t_rr"] / args.steps},
-        "filter_dof_vec_deg_per_s": n * N * m / (state["t_filter"] / args.steps),
+        "filter_dof_vec_deg_per_s": n * N * m * args.passes / (state["t_filter"] / args.steps),
         "convergence": {"max_dtheta_wanted": dtheta, "max_residual_Minv_wanted": res_max,
                         "theta_min": float(state["theta"][0]),
                         "theta_wanted_max": float(state["theta"][wanted - 1])},
@@ -571,7 +603,8 @@ def main():
         achieved = flops / (ms / 1e3)
         out["roofline"] = {"kernel": kname, "bound": "mfma", "achieved": achieved / 1e12,
                            "peak": peak / 1e12, "unit": "TFLOP/s",
-                           "frac": achieved / peak, "traffic": None,
+                           "frac": achieved / peak,
+                           "traffic": measured_traffic() if args.prec == "fp64" else None,
                            "launches": launches, "avg_launch_ms": ms / launches,
                            "flops_per_launch": flops / launches}
         out["kernel_ms_per_step"] = {k: v[1] / args.steps for k, v in prof.items() if v[0] > 0}

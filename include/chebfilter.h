@@ -131,6 +131,19 @@ cf_status chebfilter_apply_Sinv(cf_ctx *ctx, const double *X, int64_t ldx, doubl
 cf_status chebfilter_filter(cf_ctx *ctx, const double *X, int64_t ldx, double *Y, int64_t ldy,
                             int64_t N, int32_t m, double a, double b, int32_t prec);
 
+/* Multi-pass low-degree filter (used for the gold nano-clusters of Sec. VI
+ * against the loss of conditioning of one high-degree pass): `passes`
+ * applications of T_m(t(H~)) with the block replaced by its Ritz vectors
+ * (chebfilter_rayleigh_ritz) between passes:
+ *   Y = T_m(t) Q_{p-1},  Q_i = RR(T_m(t) Q_{i-1}),  Q_0 = X.
+ * The span equals that of T_m(t)^passes X.  The Ritz basis keeps every column
+ * aligned with its own eigen-direction, so each pass amplifies the columns one
+ * by one (a triangular Cholesky-QR basis would mix them).  passes = 1 is
+ * chebfilter_filter.  Uses the context's work blocks; synchronises. */
+cf_status chebfilter_filter_multipass(cf_ctx *ctx, const double *X, int64_t ldx, double *Y,
+                                     int64_t ldy, int64_t N, int32_t m, int32_t passes, double a,
+                                     double b, int32_t prec);
+
 /* In place: Y <- Q with Q^T Q = I and span(Q) = span(Y), by Cholesky-QR
  * applied twice after scaling columns to unit length (the orthonormalisation
  * step of Sec. V).  Falls back to a shifted first pass if the Gram matrix is

@@ -22,7 +22,8 @@ PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
 
 EXPORTS = ["chebfilter_init", "chebfilter_destroy", "chebfilter_last_error", "chebfilter_sizes",
            "chebfilter_apply_H", "chebfilter_apply_M", "chebfilter_apply_Sinv",
-           "chebfilter_filter", "chebfilter_cholqr", "chebfilter_rayleigh_ritz",
+           "chebfilter_filter", "chebfilter_filter_multipass", "chebfilter_cholqr",
+           "chebfilter_rayleigh_ritz",
            "chebfilter_lanczos_bounds", "chebfilter_profile", "chebfilter_profile_query",
            "chebfilter_init_batch", "chebfilter_batch_destroy", "chebfilter_batch_last_error",
            "chebfilter_batch_sizes", "chebfilter_filter_batch", "chebfilter_rayleigh_ritz_batch",
@@ -72,6 +73,7 @@ def load_library() -> C.CDLL:
     for nm in ("chebfilter_apply_H", "chebfilter_apply_M", "chebfilter_apply_Sinv"):
         getattr(lib, nm).argtypes = [vp, vp, i64, vp, i64, i64]
     lib.chebfilter_filter.argtypes = [vp, vp, i64, vp, i64, i64, i32, dbl, dbl, i32]
+    lib.chebfilter_filter_multipass.argtypes = [vp, vp, i64, vp, i64, i64, i32, i32, dbl, dbl, i32]
     lib.chebfilter_cholqr.argtypes = [vp, vp, i64, i64]
     lib.chebfilter_rayleigh_ritz.argtypes = [vp, vp, i64, i64, vp]
     lib.chebfilter_lanczos_bounds.argtypes = [vp, vp, i32, C.POINTER(dbl), C.POINTER(dbl)]
@@ -212,6 +214,15 @@ class Context:
         code = PREC[prec] if isinstance(prec, str) else int(prec)
         self._check(self.lib.chebfilter_filter(self._h, xp, ldx, yp, ldy, X.shape[1], int(m),
                                                float(a), float(b), code))
+        return Y
+
+    def filter_multipass(self, X, m: int, passes: int, a: float, b: float, Y=None, prec="fp64"):
+        """passes x T_m(t(H~)) with Rayleigh-Ritz between the passes."""
+        Y = self._out(X, Y)
+        (xp, ldx), (yp, ldy) = _block(X, "X"), _block(Y, "Y")
+        code = PREC[prec] if isinstance(prec, str) else int(prec)
+        self._check(self.lib.chebfilter_filter_multipass(self._h, xp, ldx, yp, ldy, X.shape[1], int(m),
+                                                         int(passes), float(a), float(b), code))
         return Y
 
     def cholqr(self, Y):

@@ -1399,6 +1399,34 @@ cf_status chebfilter_filter(cf_ctx *c, const double *X, int64_t ldx, double *Y, 
   return check_out_finite(c, Y, ldy, n, "filter");
 }
 
+cf_status chebfilter_filter_multipass(cf_ctx *c, const double *X, int64_t ldx, double *Y,
+                                     int64_t ldy, int64_t N, int32_t m, int32_t passes, double a,
+                                     double b, int32_t prec) {
+  if (!c) return CF_EINVAL;
+  if (passes < 1) return set_err(c, CF_EINVAL, "filter_multipass: passes must be >= 1");
+  if (passes == 1) return chebfilter_filter(c, X, ldx, Y, ldy, N, m, a, b, prec);
+  STCHK(check_block(c, X, ldx, N, "filter_multipass X"));
+  STCHK(check_block(c, Y, ldy, N, "filter_multipass Y"));
+  if (X == Y) return set_err(c, CF_EINVAL, "filter_multipass: Y must not alias X");
+  if (N == 0) return CF_OK;
+  HIPCHK(c, hipSetDevice(c->device));
+  // passes alternate between Y and the work block U so that the last lands in Y
+  const int64_t mc = c->max_cols;
+  auto out = [&](int i) -> double * { return ((passes - 1 - i) % 2 == 0) ? Y : c->U; };
+  auto ldo = [&](int i) -> int64_t { return ((passes - 1 - i) % 2 == 0) ? ldy : mc; };
+  std::vector<double> theta((size_t)N);
+  STCHK(chebfilter_filter(c, X, ldx, out(0), ldo(0), N, m, a, b, prec));
+  for (int i = 1; i < passes; ++i) {
+    // Rayleigh-Ritz between passes: the Ritz vectors keep each column aligned
+    // with its own eigen-direction, so the next pass amplifies them one by
+    // one (a triangular Cholesky-QR basis would mix them, and after a second
+    // high-degree pass the columns would all lean towards the lowest one)
+    STCHK(chebfilter_rayleigh_ritz(c, out(i - 1), ldo(i - 1), N, theta.data()));
+    STCHK(chebfilter_filter(c, out(i - 1), ldo(i - 1), out(i), ldo(i), N, m, a, b, prec));
+  }
+  return CF_OK;
+}
+
 cf_status chebfilter_cholqr(cf_ctx *c, double *Y, int64_t ldy, int64_t N) {
   if (!c) return CF_EINVAL;
   STCHK(check_block(c, Y, ldy, N, "cholqr Y"));

@@ -95,13 +95,14 @@ def si_shells(rng: np.random.Generator, lo: float = 0.5, hi: float = 14.0) -> li
 
 
 def si_cluster(n_atoms: int = 30, length: float = 48.0, nc: int = 24, p: int = 4,
-               r_c: float = 8.0, seed: int = 0, jitter: float = 0.05, **kw) -> Problem:
+               r_c: float = 8.0, seed: int = 0, jitter: float = 0.05, enrich: bool = True,
+               **kw) -> Problem:
     rng = np.random.default_rng(seed)
     sites = diamond_sites(n_atoms)
     sites = sites + rng.uniform(-jitter, jitter, sites.shape)
     shells = si_shells(rng)
     mesh = build_mesh(p, nc, -0.5 * length, length)
-    enr = EnrichmentSet(centers=sites, shells=shells, r_c=r_c)
+    enr = EnrichmentSet(centers=sites, shells=shells, r_c=r_c) if enrich else None
     prob = assemble(mesh, softened_potential(sites), enr, **kw)
     prob.meta.update(kind="si", sites=sites, shells=shells, r_c=r_c, mesh=mesh, enr=enr,
                      seed=seed, rng=rng)
@@ -131,6 +132,12 @@ def initial_block(prob: Problem, N: int, seed: int = 0) -> np.ndarray:
 def config1(**kw) -> Problem:
     """Hydrogen, 20 Bohr cube, 8^3 cells of degree 4, r_c = 6 (N = 16, m = 20)."""
     return hydrogen(nc=8, length=20.0, p=4, r_c=6.0, **kw)
+
+
+def config2_classical(seed: int = 0, **kw) -> Problem:
+    """The 30-atom Si cluster of config2 on the same mesh with no enrichment
+    (classical finite elements only, n_e = 0)."""
+    return si_cluster(n_atoms=30, length=48.0, nc=24, p=4, r_c=8.0, seed=seed, enrich=False, **kw)
 
 
 def config2(seed: int = 0, **kw) -> Problem:

@@ -54,3 +54,10 @@ def tiny_enriched():
 
 def rng(seed=0):
     return np.random.default_rng(seed)
+
+
+@pytest.fixture(scope="session")
+def hydrogen_classical():
+    """Hydrogen on 4^3 cells of degree 4 with no enrichment (n_e = 0)."""
+    from synth import configs
+    return cached("h4c", lambda: configs.hydrogen(nc=4, length=20.0, p=4, enrich=False))

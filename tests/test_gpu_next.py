@@ -1,0 +1,92 @@
+"""The classical-only discretisation (n_e = 0) and the multi-pass filter
+against the oracle.  Tolerances as in test_gpu_parity (FP64) and
+test_gpu_lowp (FP32): with n_e = 0, M^E = D is diagonal, so kappa(M^E) is the
+ratio of the largest to the smallest lumped mass."""
+import numpy as np
+import pytest
+
+from oracle.filters import recurrence_filter
+from oracle.operators import Operators
+from oracle.subspace import cholqr, lanczos, lanczos_bounds, rayleigh_ritz
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+U = 2.0 ** -53
+U32 = 2.0 ** -24
+
+
+def dev(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def relerr(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+def test_classical_only(hydrogen_classical):
+    from paper_1610_02121_amd import Context
+    prob = hydrogen_classical
+    assert prob.n_e == 0
+    ctx = Context(prob, max_cols=24)
+    ops = Operators(prob)
+    d = np.asarray(prob.M_cc_diag)
+    kappa = d.max() / d.min()
+    X = np.random.default_rng(1).standard_normal((ops.n, 21))
+    Xd = dev(X)
+    assert relerr(host(ctx.apply_H(Xd)), ops.apply_H(X)) < 1e-12
+    assert relerr(host(ctx.apply_M(Xd)), ops.apply_M(X)) < 1e-12
+    assert relerr(host(ctx.apply_Sinv(Xd)), X / d[:, None]) < 10 * U * kappa
+    v0 = np.random.default_rng(2).standard_normal(ops.n)
+    al, be = lanczos(ops.apply_Htilde, ops.apply_M, v0, 10)
+    lo, hi = lanczos_bounds(al, be)
+    lo_d, hi_d = ctx.lanczos_bounds(dev(v0).reshape(-1), 10)
+    assert abs(lo_d - lo) < 1e-9 * abs(hi) and abs(hi_d - hi) < 1e-9 * abs(hi)
+    a = lo + 0.05 * (hi - lo)
+    m = 8
+    Yo = recurrence_filter(lambda Z: ops.apply_Htilde(Z), X, m, a, hi)
+    assert relerr(host(ctx.filter(Xd, m, a, hi)), Yo) < 10 * U * kappa * m
+    assert relerr(host(ctx.filter(Xd, m, a, hi, prec="fp32")), Yo) < 10 * U32 * kappa * m
+    Y = ctx.filter(Xd, m, a, hi)
+    Yh = host(Y)
+    th = ctx.rayleigh_ritz(Y)
+    Q = cholqr(Yh)
+    th_o, _ = rayleigh_ritz(Q, ops.apply_H(Q), ops.apply_M(Q))
+    assert np.abs(th - th_o).max() < 1e-8
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_multipass_filter_spans_oracle(si_small, prec):
+    """3 passes of degree 6 with Rayleigh-Ritz between them: the span equals the
+    oracle's (same passes, oracle Rayleigh-Ritz), compared through projectors."""
+    from paper_1610_02121_amd import Context
+    ctx = Context(si_small, max_cols=24)
+    ops = Operators(si_small)
+    v0 = np.random.default_rng(5).standard_normal(ops.n)
+    al, be = lanczos(ops.apply_Htilde, ops.apply_M, v0, 10)
+    lo, hi = lanczos_bounds(al, be)
+    a = lo + 0.1 * (hi - lo)
+    X = np.random.default_rng(6).standard_normal((ops.n, 20))
+    m, passes = 6, 3
+    Y = host(ctx.filter_multipass(dev(X), m, passes, a, hi, prec=prec))
+    Z = X
+    for i in range(passes):
+        Z = recurrence_filter(lambda W: ops.apply_Htilde(W), Z, m, a, hi)
+        if i + 1 < passes:
+            Q = cholqr(Z)
+            _, C = rayleigh_ritz(Q, ops.apply_H(Q), ops.apply_M(Q))
+            Z = Q @ C
+    Qd, Qo = cholqr(Y), cholqr(Z)
+    err = np.abs(Qd @ (Qd.T @ Qo) - Qo).max()
+    print(f"{prec}: projector difference {err:.3e}")
+    assert err < (1e-8 if prec == "fp64" else 1e-3)
+    # one pass equals chebfilter_filter
+    assert np.array_equal(host(ctx.filter_multipass(dev(X), m, 1, a, hi, prec=prec)),
+                          host(ctx.filter(dev(X), m, a, hi, prec=prec)))
+    ctx.close()

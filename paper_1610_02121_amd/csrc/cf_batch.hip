@@ -78,7 +78,7 @@ __global__ __launch_bounds__(512, 2) void kb_cell(const BatchProb *__restrict__ 
                           P.R32, P.mc, P.N, f, blockIdx.x);
 }
 
-__global__ __launch_bounds__(256) void kb_enr_part(const BatchProb *__restrict__ bp,
+__global__ __launch_bounds__(256, 2) void kb_enr_part(const BatchProb *__restrict__ bp,
                                                    const BatchItem *__restrict__ items, int k) {
   const BatchItem it = items[blockIdx.x];
   const BatchProb &P = bp[it.p];
@@ -123,7 +123,7 @@ __global__ __launch_bounds__(64) void kb_schur(const BatchProb *__restrict__ bp,
   P.Zb[(int64_t)al * P.mc + col] = acc;
 }
 
-__global__ __launch_bounds__(256) void kb_enr_q(const BatchProb *__restrict__ bp,
+__global__ __launch_bounds__(256, 2) void kb_enr_q(const BatchProb *__restrict__ bp,
                                                 const BatchItem *__restrict__ items, int k) {
   const BatchItem it = items[blockIdx.x];
   const BatchProb &P = bp[it.p];
@@ -197,16 +197,14 @@ hipError_t launch_b_enr(hipStream_t s, const BatchProb *bp, int count, const Bat
   const dim3 rgrid((maxN + 63) / 64, (unsigned)nalpha);
   hipLaunchKernelGGL(kb_enr_reduce, rgrid, dim3(64), 0, s, bp, aoff, count, k);
   hipLaunchKernelGGL(kb_schur, rgrid, dim3(64), 0, s, bp, aoff, count);
-  const size_t shm = (size_t)2 * ((kmax + 3) & ~3) * 16 * sizeof(float);
-  hipLaunchKernelGGL(kb_enr_q, dim3(neitems), dim3(256), shm, s, bp, eitems, k);
+  (void)kmax;
+  hipLaunchKernelGGL(kb_enr_q, dim3(neitems), dim3(256), 0, s, bp, eitems, k);
   return hipGetLastError();
 }
 
 hipError_t prepare_b_enr(int kmax) {
-  const size_t shm = (size_t)2 * ((kmax + 3) & ~3) * 16 * sizeof(float);
-  if (shm <= 65536) return hipSuccess;
-  return hipFuncSetAttribute((const void *)kb_enr_q, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)shm);
+  (void)kmax;   // the transposed-coupling body uses static LDS only
+  return hipSuccess;
 }
 
 hipError_t launch_b_epilogue(hipStream_t s, const BatchProb *bp, int count, const int64_t *eoff,

@@ -33,7 +33,7 @@ hipError_t launch_cell_gemm_lp(hipStream_t s, bool bf16, const void *Hv, const i
   return hipGetLastError();
 }
 
-__global__ __launch_bounds__(256) void k_enr_part_f32(
+__global__ __launch_bounds__(256, 2) void k_enr_part_f32(
     const float *__restrict__ HT, const float *__restrict__ MT,
     const int64_t *__restrict__ toff, const int32_t *__restrict__ tld,
     const int64_t *__restrict__ eptr, const int32_t *__restrict__ dofp,
@@ -56,7 +56,7 @@ hipError_t launch_enr_part_f32(hipStream_t s, const float *HT, const float *MT,
   return hipGetLastError();
 }
 
-__global__ __launch_bounds__(256) void k_enr_q_f32(
+__global__ __launch_bounds__(256, 2) void k_enr_q_f32(
     const float *__restrict__ Hec, const float *__restrict__ Mec,
     const int64_t *__restrict__ eptr, const int32_t *__restrict__ eidx,
     const int32_t *__restrict__ cells, const float *__restrict__ U, int64_t ldu, float cU,
@@ -71,15 +71,8 @@ hipError_t launch_enr_q_f32(hipStream_t s, const float *Hec, const float *Mec,
                             int ncells, int kmax, const float *U, int64_t ldu, float cU,
                             const double *V, int64_t ldv, float cV, float *Q, int64_t ldq, int N) {
   if (ncells <= 0 || N <= 0) return hipSuccess;
-  const size_t shm = (size_t)2 * ((kmax + 3) & ~3) * 16 * sizeof(float);
-  static size_t shm_set = 0;
-  if (shm > 65536 && shm > shm_set) {
-    hipError_t e = hipFuncSetAttribute((const void *)k_enr_q_f32,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    if (e != hipSuccess) return e;
-    shm_set = shm;
-  }
-  hipLaunchKernelGGL(k_enr_q_f32, dim3(ncells), dim3(256), shm, s, Hec, Mec, eptr, eidx, cells, U,
+  (void)kmax;
+  hipLaunchKernelGGL(k_enr_q_f32, dim3(ncells), dim3(256), 0, s, Hec, Mec, eptr, eidx, cells, U,
                      ldu, cU, V, ldv, cV, Q, ldq, N);
   return hipGetLastError();
 }

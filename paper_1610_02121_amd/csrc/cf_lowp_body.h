@@ -181,7 +181,11 @@ __device__ __forceinline__ void cell_gemm_lp_body(
 // ---------------------------------------------------------------------------
 // Coupling partials, FP32 (as k_enr_part; FP32 blocks HT, MT).
 // ---------------------------------------------------------------------------
-// One enriched cell per workgroup of 256 threads.
+// One enriched cell per workgroup of 256 threads.  Wave w takes row block
+// 4g + w of group g and keeps the A fragments of both terms (all 128 k) in
+// registers while the column tiles stream by, so the blocks are read once per
+// call (cells with more than 64 enrichment functions take several passes over
+// the gathered rows).
 __device__ __forceinline__ void enr_part_f32_body(
     const float *__restrict__ HT, const float *__restrict__ MT,
     const int64_t *__restrict__ toff, const int32_t *__restrict__ tld,
@@ -189,7 +193,7 @@ __device__ __forceinline__ void enr_part_f32_body(
     const int cell, const float *__restrict__ X, int64_t ldx, float cH,
     const float *__restrict__ R, int64_t ldr, const double *__restrict__ rs, float cM,
     float *__restrict__ P, int64_t ldp, int N) {
-  constexpr int PT = 16, LDX = 32;
+  constexpr int PT = 16, LDX = PT + 1;
   constexpr int PF = NPAD * PT / 256;
   constexpr int RPP = 256 / PT;
   __shared__ float xs[NPAD * LDX];
@@ -204,59 +208,66 @@ __device__ __forceinline__ void enr_part_f32_body(
     gd[p] = dofp[(int64_t)cell * NPAD + gr + p * RPP];
     gsc[p] = (rs && gd[p] >= 0) ? (float)rs[gd[p]] : 1.f;
   }
-  float px[PF], pr[PF];
-#pragma unroll
-  for (int p = 0; p < PF; ++p) {
-    const bool v = gd[p] >= 0 && gj < N;
-    px[p] = (X && v) ? X[(int64_t)gd[p] * ldx + gj] : 0.f;
-    pr[p] = (R && v) ? R[(int64_t)gd[p] * ldr + gj] * gsc[p] : 0.f;
-  }
   const int64_t k0 = eptr[cell];
   const int na = (int)(eptr[cell + 1] - k0);
   const int nap = tld[cell];
   const int nmb = nap >> 4;
   const float *ht = X ? HT + toff[cell] : nullptr;
   const float *mt = R ? MT + toff[cell] : nullptr;
-  for (int c0 = 0; c0 < N; c0 += PT) {
-    const int ncol = min(PT, N - c0);
+  for (int g = 0; 4 * g < nmb; ++g) {
+    const int mb = 4 * g + w;
+    const bool act = mb < nmb;
+    float aH[32], aM[32];
+#pragma unroll
+    for (int ks = 0; ks < 32; ++ks) {
+      const int64_t off = (int64_t)(4 * ks + kq) * nap + 16 * mb + li;
+      aH[ks] = (act && ht) ? ht[off] : 0.f;
+      aM[ks] = (act && mt) ? mt[off] : 0.f;
+    }
+    float px[PF], pr[PF];
 #pragma unroll
     for (int p = 0; p < PF; ++p) {
-      xs[(gr + p * RPP) * LDX + gj] = px[p];
-      rsm[(gr + p * RPP) * LDX + gj] = pr[p];
+      const bool v = gd[p] >= 0 && gj < N;
+      px[p] = (X && v) ? X[(int64_t)gd[p] * ldx + gj] : 0.f;
+      pr[p] = (R && v) ? R[(int64_t)gd[p] * ldr + gj] * gsc[p] : 0.f;
     }
-    __syncthreads();
-    const int c1 = c0 + PT;
-    if (c1 < N) {
+    for (int c0 = 0; c0 < N; c0 += PT) {
+      const int ncol = min(PT, N - c0);
 #pragma unroll
       for (int p = 0; p < PF; ++p) {
-        const bool v = gd[p] >= 0 && c1 + gj < N;
-        px[p] = (X && v) ? X[(int64_t)gd[p] * ldx + c1 + gj] : 0.f;
-        pr[p] = (R && v) ? R[(int64_t)gd[p] * ldr + c1 + gj] * gsc[p] : 0.f;
+        xs[(gr + p * RPP) * LDX + gj] = px[p];
+        rsm[(gr + p * RPP) * LDX + gj] = pr[p];
       }
-    }
-    for (int mb = w; mb < nmb; mb += 4) {
-      f4 accH = f4zero(), accM = f4zero();
-      if (ht) {
-#pragma unroll 8
-        for (int ks = 0; ks < 32; ++ks)
-          accH = mfma_f32(ht[(int64_t)(4 * ks + kq) * nap + 16 * mb + li],
-                          xs[(4 * ks + kq) * LDX + li], accH);
-      }
-      if (mt) {
-#pragma unroll 8
-        for (int ks = 0; ks < 32; ++ks)
-          accM = mfma_f32(mt[(int64_t)(4 * ks + kq) * nap + 16 * mb + li],
-                          rsm[(4 * ks + kq) * LDX + li], accM);
-      }
-      if (li < ncol) {
+      __syncthreads();
+      const int c1 = c0 + PT;
+      if (c1 < N) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int orow = 16 * mb + 4 * kq + r;
-          if (orow < na) P[(k0 + orow) * ldp + c0 + li] = cH * accH[r] + cM * accM[r];
+        for (int p = 0; p < PF; ++p) {
+          const bool v = gd[p] >= 0 && c1 + gj < N;
+          px[p] = (X && v) ? X[(int64_t)gd[p] * ldx + c1 + gj] : 0.f;
+          pr[p] = (R && v) ? R[(int64_t)gd[p] * ldr + c1 + gj] * gsc[p] : 0.f;
         }
       }
+      if (act) {
+        f4 accH = f4zero(), accM = f4zero();
+        if (ht) {
+#pragma unroll
+          for (int ks = 0; ks < 32; ++ks) accH = mfma_f32(aH[ks], xs[(4 * ks + kq) * LDX + li], accH);
+        }
+        if (mt) {
+#pragma unroll
+          for (int ks = 0; ks < 32; ++ks) accM = mfma_f32(aM[ks], rsm[(4 * ks + kq) * LDX + li], accM);
+        }
+        if (li < ncol) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int orow = 16 * mb + 4 * kq + r;
+            if (orow < na) P[(k0 + orow) * ldp + c0 + li] = cH * accH[r] + cM * accM[r];
+          }
+        }
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
 }
 
@@ -265,63 +276,107 @@ __device__ __forceinline__ void enr_part_f32_body(
 // (the Schur-solve output), products in FP32.
 // ---------------------------------------------------------------------------
 // One enriched cell per workgroup of 256 threads; its rows of Q start at
-// 128 * qblock (the cell's position in the enriched-cell list).  Dynamic LDS:
-// 2 * round_up(kmax, 4) * 16 floats.
+// 128 * qblock (the cell's position in the enriched-cell list).  The
+// enrichment functions are taken in chunks of 64: wave w keeps the A fragments
+// of rows 32w .. 32w+32 of both blocks for the chunk in registers while the
+// column tiles stream by; chunks after the first add into Q.
 __device__ __forceinline__ void enr_q_f32_body(
     const float *__restrict__ Hec, const float *__restrict__ Mec,
     const int64_t *__restrict__ eptr, const int32_t *__restrict__ eidx,
     const int cell, const int qblock, const float *__restrict__ U, int64_t ldu, float cU,
     const double *__restrict__ V, int64_t ldv, float cV, float *__restrict__ Q, int64_t ldq,
     int N) {
-  extern __shared__ float zsf[];
-  constexpr int PT = 16, LDZ = 16;
+  constexpr int PT = 16, LDZ = 16, KC = 64, KS = KC / 4;
+  constexpr int GV = KC * PT / 256;
+  __shared__ float zu[KC * LDZ];
+  __shared__ float zv[KC * LDZ];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, kq = lane >> 4;
   const int64_t k0 = eptr[cell];
   const int na = (int)(eptr[cell + 1] - k0);
-  const int K4 = (na + 3) & ~3;
-  const int nks = K4 / 4;
   float *qb = Q + ((int64_t)qblock * NPAD) * ldq;
-  for (int c0 = 0; c0 < N; c0 += PT) {
-    const int ncol = min(PT, N - c0);
-    for (int idx = tid; idx < K4 * PT; idx += 256) {
-      const int k = idx / PT, j = idx % PT;
-      const bool v = k < na && j < ncol;
-      const int64_t al = v ? eidx[k0 + k] : 0;
-      zsf[k * LDZ + j] = (U && v) ? cU * U[al * ldu + c0 + j] : 0.f;
-      zsf[(K4 + k) * LDZ + j] = (V && v) ? cV * (float)V[al * ldv + c0 + j] : 0.f;
-    }
-    __syncthreads();
-    f4 acc0 = f4zero(), acc1 = f4zero();
-    if (U) {
-      for (int ks = 0; ks < nks; ++ks) {
-        const int k = 4 * ks + kq;
-        const float *row = Hec + (k0 + min(k, na - 1)) * NPAD + 32 * w;
-        const float a0 = k < na ? row[li] : 0.f, a1 = k < na ? row[16 + li] : 0.f;
-        const float b = zsf[k * LDZ + li];
-        acc0 = mfma_f32(a0, b, acc0);
-        acc1 = mfma_f32(a1, b, acc1);
-      }
-    }
-    if (V) {
-      for (int ks = 0; ks < nks; ++ks) {
-        const int k = 4 * ks + kq;
-        const float *row = Mec + (k0 + min(k, na - 1)) * NPAD + 32 * w;
-        const float a0 = k < na ? row[li] : 0.f, a1 = k < na ? row[16 + li] : 0.f;
-        const float b = zsf[(K4 + k) * LDZ + li];
-        acc0 = mfma_f32(a0, b, acc0);
-        acc1 = mfma_f32(a1, b, acc1);
-      }
-    }
-    if (li < ncol) {
-      float *q = qb + c0 + li;
+  const int gj = tid % PT, gk = tid / PT;
+  for (int kc = 0; kc < na; kc += KC) {
+    float aH0[KS], aH1[KS], aM0[KS], aM1[KS];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        q[(int64_t)(32 * w + 4 * kq + r) * ldq] = acc0[r];
-        q[(int64_t)(32 * w + 16 + 4 * kq + r) * ldq] = acc1[r];
-      }
+    for (int ks = 0; ks < KS; ++ks) {
+      const int k = kc + 4 * ks + kq;
+      const bool v = k < na;
+      const float *hr = Hec + (k0 + (v ? k : 0)) * NPAD + 32 * w;
+      const float *mr = Mec + (k0 + (v ? k : 0)) * NPAD + 32 * w;
+      aH0[ks] = (U && v) ? hr[li] : 0.f;
+      aH1[ks] = (U && v) ? hr[16 + li] : 0.f;
+      aM0[ks] = (V && v) ? mr[li] : 0.f;
+      aM1[ks] = (V && v) ? mr[16 + li] : 0.f;
     }
-    __syncthreads();
+    int64_t gal[GV];
+    bool gv[GV];
+#pragma unroll
+    for (int p = 0; p < GV; ++p) {
+      const int k = kc + gk + 16 * p;
+      gv[p] = k < na;
+      gal[p] = gv[p] ? eidx[k0 + k] : 0;
+    }
+    float pu[GV], pv[GV];
+#pragma unroll
+    for (int p = 0; p < GV; ++p) {
+      const bool v = gv[p] && gj < N;
+      pu[p] = (U && v) ? cU * U[gal[p] * ldu + gj] : 0.f;
+      pv[p] = (V && v) ? cV * (float)V[gal[p] * ldv + gj] : 0.f;
+    }
+    for (int c0 = 0; c0 < N; c0 += PT) {
+      const int ncol = min(PT, N - c0);
+#pragma unroll
+      for (int p = 0; p < GV; ++p) {
+        zu[(gk + 16 * p) * LDZ + gj] = pu[p];
+        zv[(gk + 16 * p) * LDZ + gj] = pv[p];
+      }
+      __syncthreads();
+      const int c1 = c0 + PT;
+      if (c1 < N) {
+#pragma unroll
+        for (int p = 0; p < GV; ++p) {
+          const bool v = gv[p] && c1 + gj < N;
+          pu[p] = (U && v) ? cU * U[gal[p] * ldu + c1 + gj] : 0.f;
+          pv[p] = (V && v) ? cV * (float)V[gal[p] * ldv + c1 + gj] : 0.f;
+        }
+      }
+      f4 acc0 = f4zero(), acc1 = f4zero();
+      if (U) {
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+          const float b = zu[(4 * ks + kq) * LDZ + li];
+          acc0 = mfma_f32(aH0[ks], b, acc0);
+          acc1 = mfma_f32(aH1[ks], b, acc1);
+        }
+      }
+      if (V) {
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+          const float b = zv[(4 * ks + kq) * LDZ + li];
+          acc0 = mfma_f32(aM0[ks], b, acc0);
+          acc1 = mfma_f32(aM1[ks], b, acc1);
+        }
+      }
+      if (li < ncol) {
+        float *q = qb + c0 + li;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          float *q0 = q + (int64_t)(32 * w + 4 * kq + r) * ldq;
+          float *q1 = q + (int64_t)(32 * w + 16 + 4 * kq + r) * ldq;
+          if (kc == 0) { *q0 = acc0[r]; *q1 = acc1[r]; }
+          else { *q0 += acc0[r]; *q1 += acc1[r]; }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  if (na == 0) {
+    for (int c0 = 0; c0 < N; c0 += PT)
+      for (int idx = tid; idx < NPAD * PT; idx += 256) {
+        const int a = idx / PT, j = idx % PT;
+        if (c0 + j < N) qb[(int64_t)a * ldq + c0 + j] = 0.f;
+      }
   }
 }
 

@@ -497,6 +497,37 @@ static cf_status check_out_finite(cf_ctx *c, const double *Y, int64_t ldy, int N
   return CF_OK;
 }
 
+// k Lanczos steps of M^-1 H from v0, enqueued on the context's stream with no
+// host wait; the two bounds (lowest Ritz value, upper bound) land in out[0..1]
+// (device memory).
+static cf_status core_lanczos(cf_ctx *c, const double *v0, int k, double *out) {
+  const int64_t n = c->n;
+  double *vprev = c->lzv, *v = c->lzv + n, *w = c->lzv + 2 * n, *mv = c->lzv + 3 * n;
+  double *coef = c->lzcoef;
+  const int nblk = 512;
+  HIPCHK(c, hipMemsetAsync(coef, 0, (2 * 64 + 8) * sizeof(double), c->stream));
+  STCHK(core_apply_M(c, v0, 1, mv, 1, 1));
+  HIPCHK(c, launch_dot(c->stream, n, v0, mv, coef, c->lzpart, nblk));
+  HIPCHK(c, launch_lanczos_update(c->stream, n, 0, const_cast<double *>(v0), nullptr, nullptr, coef,
+                                  v, nullptr, nblk, 0));
+  for (int j = 0; j < k; ++j) {
+    STCHK(core_htilde_step(c, v, 1, 1, 1.0, nullptr, 0, 0.0, nullptr, 0, 0.0, w, 1));
+    if (j > 0)
+      HIPCHK(c, launch_lanczos_update(c->stream, n, j, w, v, vprev, coef, nullptr, nullptr, nblk, 1));
+    STCHK(core_apply_M(c, v, 1, mv, 1, 1));
+    HIPCHK(c, launch_dot(c->stream, n, w, mv, coef + 1 + 2 * j, c->lzpart, nblk));
+    HIPCHK(c, launch_lanczos_update(c->stream, n, j, w, v, vprev, coef, nullptr, nullptr, nblk, 2));
+    STCHK(core_apply_M(c, w, 1, mv, 1, 1));
+    HIPCHK(c, launch_dot(c->stream, n, w, mv, coef + 2 + 2 * j, c->lzpart, nblk));
+    if (j + 1 < k) {
+      HIPCHK(c, launch_lanczos_update(c->stream, n, j, w, v, vprev, coef, vprev, nullptr, nblk, 3));
+      std::swap(vprev, v);   // vprev <- old v, v <- new vector
+    }
+  }
+  HIPCHK(c, launch_tridiag_bounds(c->stream, coef, nullptr, k, out));
+  return CF_OK;
+}
+
 static void free_ctx(cf_ctx *c) {
   if (!c) return;
   if (c->rb) rocblas_destroy_handle(c->rb);
@@ -662,8 +693,9 @@ static cf_status do_init(const cf_problem *pr, const cf_options *opt, cf_ctx *c)
   STCHK(dalloc(c, &c->T, (size_t)c->n * mc));
   STCHK(dalloc(c, &c->U, (size_t)c->n * mc));
   {
-    // Gram partial buffer: multiple of 8 chunks, at most 256, at most ~512 MB
-    int64_t nch = std::max<int64_t>(8, std::min<int64_t>(256, (c->n + 4095) / 4096));
+    // Gram partial buffer: chunks of at least 512 rows, a multiple of 8 chunks,
+    // at most 256, at most ~512 MB (small problems still fill the chip)
+    int64_t nch = std::max<int64_t>(8, std::min<int64_t>(256, (c->n + 511) / 512));
     const int64_t cap = (int64_t)(512ll << 20) / (8 * mc * mc);
     nch = std::min<int64_t>(nch, std::max<int64_t>(8, cap));
     nch = (nch + 7) / 8 * 8;
@@ -1056,6 +1088,19 @@ struct cf_batch {
   int g_m = -1, g_prec = -1;
   hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_copy = nullptr;
   bool copy_pending = false;
+  // batched projection and Lanczos (allocated on first use): per-entry status
+  // words (8 each), projected pencils, Ritz values and eigensolver info by
+  // slot (entries sorted by block width), the entry -> slot map, the bounds
+  int *d_rst = nullptr, *d_rinfo = nullptr, *d_rslot = nullptr;
+  double *d_rH = nullptr, *d_rM = nullptr, *d_rth = nullptr, *d_rE = nullptr, *d_lz = nullptr;
+  std::vector<int> h_rslot, h_rst;
+  std::vector<double> h_rth, h_lz;
+  // Lanczos runs of entries that share a problem go together as the columns
+  // of one block (at most max_cols per group): groups, workspace blocks
+  std::vector<std::vector<int>> lz_groups;
+  double *d_lzblk = nullptr, *d_lzc = nullptr, *d_lzp = nullptr;
+  int64_t lz_n = 0;
+  int lz_k = 0;
   std::string err;
   std::vector<void *> allocs;
 };
@@ -1479,32 +1524,10 @@ cf_status chebfilter_lanczos_bounds(cf_ctx *c, const double *v0, int32_t k, doub
   if (!v0 || !lmin_est || !b_upper) return set_err(c, CF_EINVAL, "lanczos: null argument");
   if (k < 1 || k > 64) return set_err(c, CF_EINVAL, "lanczos: k must be 1..64");
   HIPCHK(c, hipSetDevice(c->device));
-  const int64_t n = c->n;
-  double *vprev = c->lzv, *v = c->lzv + n, *w = c->lzv + 2 * n, *mv = c->lzv + 3 * n;
-  double *coef = c->lzcoef;
-  const int nblk = 512;
-  HIPCHK(c, hipMemsetAsync(coef, 0, (2 * 64 + 8) * sizeof(double), c->stream));
-  STCHK(core_apply_M(c, v0, 1, mv, 1, 1));
-  HIPCHK(c, launch_dot(c->stream, n, v0, mv, coef, c->lzpart, nblk));
-  HIPCHK(c, launch_lanczos_update(c->stream, n, 0, const_cast<double *>(v0), nullptr, nullptr, coef,
-                                  v, nullptr, nblk, 0));
-  for (int j = 0; j < k; ++j) {
-    STCHK(core_htilde_step(c, v, 1, 1, 1.0, nullptr, 0, 0.0, nullptr, 0, 0.0, w, 1));
-    if (j > 0)
-      HIPCHK(c, launch_lanczos_update(c->stream, n, j, w, v, vprev, coef, nullptr, nullptr, nblk, 1));
-    STCHK(core_apply_M(c, v, 1, mv, 1, 1));
-    HIPCHK(c, launch_dot(c->stream, n, w, mv, coef + 1 + 2 * j, c->lzpart, nblk));
-    HIPCHK(c, launch_lanczos_update(c->stream, n, j, w, v, vprev, coef, nullptr, nullptr, nblk, 2));
-    STCHK(core_apply_M(c, w, 1, mv, 1, 1));
-    HIPCHK(c, launch_dot(c->stream, n, w, mv, coef + 2 + 2 * j, c->lzpart, nblk));
-    if (j + 1 < k) {
-      HIPCHK(c, launch_lanczos_update(c->stream, n, j, w, v, vprev, coef, vprev, nullptr, nblk, 3));
-      std::swap(vprev, v);   // vprev <- old v, v <- new vector
-    }
-  }
-  HIPCHK(c, launch_tridiag_bounds(c->stream, coef, nullptr, k, coef + 2 * 64 + 2));
+  double *dout = c->lzcoef + 2 * 64 + 2;
+  STCHK(core_lanczos(c, v0, k, dout));
   double out2[2] = {0.0, 0.0};
-  HIPCHK(c, hipMemcpyAsync(out2, coef + 2 * 64 + 2, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(out2, dout, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   *lmin_est = out2[0];
   *b_upper = out2[1];
@@ -1688,27 +1711,224 @@ cf_status chebfilter_filter_batch(cf_batch *b, const double *const *X, const int
   return CF_OK;
 }
 
+static cf_status batch_rr_alloc(cf_batch *b) {
+  if (b->d_rst) return CF_OK;
+  const size_t cnt = (size_t)b->count, mc = (size_t)b->max_cols;
+  STCHK(balloc(b, &b->d_rst, 8 * cnt));
+  STCHK(balloc(b, &b->d_rinfo, cnt));
+  STCHK(balloc(b, &b->d_rslot, cnt));
+  STCHK(balloc(b, &b->d_rH, cnt * mc * mc));
+  STCHK(balloc(b, &b->d_rM, cnt * mc * mc));
+  STCHK(balloc(b, &b->d_rth, cnt * mc));
+  STCHK(balloc(b, &b->d_rE, cnt * mc));
+  STCHK(balloc(b, &b->d_lz, 2 * cnt));
+  b->h_rslot.assign(cnt, -1);
+  b->h_rst.assign(8 * cnt, 0);
+  b->h_rth.assign(cnt * mc, 0.0);
+  b->h_lz.assign(2 * cnt, 0.0);
+  return CF_OK;
+}
+
+// Every entry is projected with no host wait: two unshifted Cholesky-QR
+// passes whose failure flags land in the entry's status words (a failed pass
+// leaves the block as it was), the projected pencil into the entry's slot,
+// then one batched generalized eigensolve per block width and the predicated
+// rotation.  One synchronisation reads every status; an entry whose
+// orthonormalisation or eigensolve failed is redone by the single-problem
+// projection (shifted Cholesky-QR, its own error reporting) on its block,
+// which still spans the filtered subspace.  Status words per entry: [0], [1]
+// the two Cholesky passes, [2] the eigensolver's info, [3] a non-finite
+// pencil, [4] a non-finite rotated block.
 cf_status chebfilter_rayleigh_ritz_batch(cf_batch *b, double *const *Y, const int64_t *ldy,
                                          const int64_t *N, double *const *theta_host) {
   if (!b) return CF_EINVAL;
   if (!Y || !ldy || !N || !theta_host) return berr(b, CF_EINVAL, "rayleigh_ritz_batch: null argument array");
   for (int i = 0; i < b->count; ++i) {
     cf_ctx *c = b->uniq[b->which[i]];
-    cf_status st = chebfilter_rayleigh_ritz(c, Y[i], ldy[i], N[i], theta_host[i]);
+    cf_status st = check_block(c, Y[i], ldy[i], N[i], "rayleigh_ritz_batch Y");
+    if (st == CF_OK && N[i] > 0 && !theta_host[i])
+      st = set_err(c, CF_EINVAL, "rayleigh_ritz_batch: null theta");
     if (st != CF_OK) return berr(b, st, "entry " + std::to_string(i) + ": " + c->err);
+  }
+  BHIPCHK(b, hipSetDevice(b->device));
+  STCHK(batch_rr_alloc(b));
+  const int cnt = b->count;
+  const int64_t mc = b->max_cols, mc2 = mc * mc;
+  // slots: entries with columns, ordered by width (stable), so that each
+  // width's pencils are contiguous for the strided batched eigensolver
+  std::vector<int> order;
+  for (int i = 0; i < cnt; ++i)
+    if (N[i] > 0) order.push_back(i);
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return N[x] < N[y]; });
+  std::fill(b->h_rslot.begin(), b->h_rslot.end(), -1);
+  for (size_t k = 0; k < order.size(); ++k) b->h_rslot[order[k]] = (int)k;
+  if (order.empty()) return CF_OK;
+  cf_ctx *c0 = b->uniq[0];
+  hipStream_t s = c0->stream;
+  BHIPCHK(b, hipMemsetAsync(b->d_rst, 0, 8 * (size_t)cnt * sizeof(int), s));
+  BHIPCHK(b, hipMemcpyAsync(b->d_rslot, b->h_rslot.data(), (size_t)cnt * sizeof(int),
+                            hipMemcpyHostToDevice, s));
+  auto fail = [&](int i, cf_ctx *c, cf_status st) {
+    return berr(b, st, "entry " + std::to_string(i) + ": " + c->err);
+  };
+  // orthonormalisation and projected pencils
+  for (int i : order) {
+    cf_ctx *c = b->uniq[b->which[i]];
+    const int n = (int)N[i];
+    const int64_t ld = c->max_cols;
+    int *st = b->d_rst + 8 * i;
+    double *Hh = b->d_rH + b->h_rslot[i] * mc2, *Mh = b->d_rM + b->h_rslot[i] * mc2;
+    cf_status r = CF_OK;
+    for (int pass = 0; pass < 2 && r == CF_OK; ++pass) {
+      const double *In = pass == 0 ? Y[i] : c->T;
+      const int64_t ldi = pass == 0 ? ldy[i] : ld;
+      double *Out = pass == 0 ? c->T : Y[i];
+      const int64_t ldo = pass == 0 ? ld : ldy[i];
+      r = core_gram(c, In, ldi, In, ldi, c->n, n, c->G, GRAM_UPPER);
+      if (r != CF_OK) break;
+      if (launch_cholesky(s, c->G, n, 1, 0.0, c->sv, st + pass) != hipSuccess ||
+          launch_tri_inv_T(s, c->G, c->sv, n, c->Wm) != hipSuccess ||
+          launch_rotate(s, In, ldi, c->n, n, c->Wm, n, 1, Out, ldo, st) != hipSuccess)
+        r = set_err(c, CF_EDEVICE, "rayleigh_ritz_batch: launch failed");
+    }
+    if (r == CF_OK) r = core_apply_H(c, Y[i], ldy[i], c->T, ld, n);
+    if (r == CF_OK) r = core_gram(c, Y[i], ldy[i], c->T, ld, c->n, n, Hh, GRAM_SYM);
+    if (r == CF_OK) r = core_apply_M(c, Y[i], ldy[i], c->T, ld, n);
+    if (r == CF_OK) r = core_gram(c, Y[i], ldy[i], c->T, ld, c->n, n, Mh, GRAM_SYM);
+    if (r == CF_OK && launch_rr_guard(s, Hh, Mh, n, st) != hipSuccess)
+      r = set_err(c, CF_EDEVICE, "rayleigh_ritz_batch: guard launch failed");
+    if (r != CF_OK) return fail(i, c, r);
+  }
+  // one generalized eigensolve per width over its contiguous slots
+  for (size_t k0 = 0; k0 < order.size();) {
+    size_t k1 = k0;
+    while (k1 < order.size() && N[order[k1]] == N[order[k0]]) ++k1;
+    const int n = (int)N[order[k0]];
+    if (rocsolver_dsygvd_strided_batched(c0->rb, rocblas_eform_ax, rocblas_evect_original,
+                                         rocblas_fill_upper, n, b->d_rH + k0 * mc2, n, mc2,
+                                         b->d_rM + k0 * mc2, n, mc2, b->d_rth + k0 * mc, mc,
+                                         b->d_rE + k0 * mc, mc, b->d_rinfo + k0,
+                                         (rocblas_int)(k1 - k0)) != rocblas_status_success)
+      return berr(b, CF_EDEVICE, "rayleigh_ritz_batch: rocsolver_dsygvd_strided_batched failed");
+    k0 = k1;
+  }
+  BHIPCHK(b, launch_rr_info(s, b->d_rinfo, b->d_rslot, cnt, b->d_rst));
+  // predicated rotation Y <- Q V through the context's scratch block
+  for (int i : order) {
+    cf_ctx *c = b->uniq[b->which[i]];
+    const int n = (int)N[i];
+    const int64_t ld = c->max_cols;
+    int *st = b->d_rst + 8 * i;
+    BHIPCHK(b, launch_transpose(s, n, b->d_rH + b->h_rslot[i] * mc2, n, c->Wm));
+    {
+      Scope sc(c, "rotate");
+      BHIPCHK(b, launch_rotate(s, Y[i], ldy[i], c->n, n, c->Wm, n, 1, c->T, ld, st));
+    }
+    BHIPCHK(b, launch_copy_skip(s, c->n, n, c->T, ld, Y[i], ldy[i], st));
+    if (c->check_finite) BHIPCHK(b, launch_check_finite(s, Y[i], ldy[i], c->n, n, st + 4));
+  }
+  BHIPCHK(b, hipMemcpyAsync(b->h_rst.data(), b->d_rst, 8 * (size_t)cnt * sizeof(int),
+                            hipMemcpyDeviceToHost, s));
+  BHIPCHK(b, hipMemcpyAsync(b->h_rth.data(), b->d_rth, (size_t)cnt * mc * sizeof(double),
+                            hipMemcpyDeviceToHost, s));
+  BHIPCHK(b, hipStreamSynchronize(s));
+  for (int i = 0; i < cnt; ++i) {
+    if (N[i] == 0) continue;
+    cf_ctx *c = b->uniq[b->which[i]];
+    const int *st = b->h_rst.data() + 8 * i;
+    if (st[3]) return fail(i, c, set_err(c, CF_ENUMERIC, "rayleigh_ritz_batch: non-finite projected pencil"));
+    if (st[0] | st[1] | st[2]) {
+      cf_status r = chebfilter_rayleigh_ritz(c, Y[i], ldy[i], N[i], theta_host[i]);
+      if (r != CF_OK) return fail(i, c, r);
+      continue;
+    }
+    if (st[4]) return fail(i, c, set_err(c, CF_ENUMERIC, "rayleigh_ritz_batch: non-finite values in the output"));
+    std::memcpy(theta_host[i], b->h_rth.data() + b->h_rslot[i] * mc, (size_t)N[i] * sizeof(double));
   }
   return CF_OK;
 }
 
+static constexpr int LZ_CHUNKS = 128;   // row chunks of the column dot products
+
+static cf_status batch_lz_alloc(cf_batch *b) {
+  if (b->d_lzblk) return CF_OK;
+  for (size_t u = 0; u < b->uniq.size(); ++u) {
+    std::vector<int> g;
+    for (int i = 0; i < b->count; ++i) {
+      if (b->which[i] != (int)u) continue;
+      g.push_back(i);
+      if ((int64_t)g.size() == b->max_cols) { b->lz_groups.push_back(g); g.clear(); }
+    }
+    if (!g.empty()) b->lz_groups.push_back(g);
+    b->lz_n = std::max<int64_t>(b->lz_n, b->uniq[u]->n);
+  }
+  for (auto &g : b->lz_groups) b->lz_k = std::max<int>(b->lz_k, (int)g.size());
+  STCHK(balloc(b, &b->d_lzblk, 4 * (size_t)b->lz_n * b->lz_k));
+  STCHK(balloc(b, &b->d_lzc, (2 * 64 + 8) * (size_t)b->lz_k));
+  STCHK(balloc(b, &b->d_lzp, (size_t)LZ_CHUNKS * b->lz_k));
+  return CF_OK;
+}
+
+// k Lanczos steps of every entry.  The runs of the entries that share a
+// problem are the columns of one n x r block, so each step applies the
+// operator once per problem (Sec. V's estimate, run for r start vectors at
+// once; the runs stay independent: column-wise dot products and updates);
+// all groups are enqueued back to back and one wait reads every bound.
 cf_status chebfilter_lanczos_bounds_batch(cf_batch *b, const double *const *v0, int32_t k,
                                           double *lmin_est, double *b_upper) {
   if (!b) return CF_EINVAL;
   if (!v0 || !lmin_est || !b_upper) return berr(b, CF_EINVAL, "lanczos_bounds_batch: null argument array");
-  for (int i = 0; i < b->count; ++i) {
-    cf_ctx *c = b->uniq[b->which[i]];
-    cf_status st = chebfilter_lanczos_bounds(c, v0[i], k, lmin_est + i, b_upper + i);
-    if (st != CF_OK) return berr(b, st, "entry " + std::to_string(i) + ": " + c->err);
+  if (k < 1 || k > 64) return berr(b, CF_EINVAL, "lanczos_bounds_batch: k must be 1..64");
+  for (int i = 0; i < b->count; ++i)
+    if (!v0[i]) return berr(b, CF_EINVAL, "entry " + std::to_string(i) + ": null v0");
+  BHIPCHK(b, hipSetDevice(b->device));
+  STCHK(batch_rr_alloc(b));
+  STCHK(batch_lz_alloc(b));
+  hipStream_t s = b->uniq[0]->stream;
+  std::vector<int> slot_entry;
+  for (const auto &g : b->lz_groups) {
+    cf_ctx *c = b->uniq[b->which[g[0]]];
+    const int r = (int)g.size();
+    const int64_t n = c->n;
+    double *vprev = b->d_lzblk, *v = vprev + n * r, *w = v + n * r, *mv = w + n * r;
+    double *coef = b->d_lzc;
+    auto fail = [&](cf_status st) {
+      return berr(b, st, "entry " + std::to_string(g[0]) + ": " + c->err);
+    };
+    cf_status st = CF_OK;
+    for (int t = 0; t < r; ++t) BHIPCHK(b, launch_copy(s, n, 1, v0[g[t]], 1, w + t, r));
+    BHIPCHK(b, hipMemsetAsync(coef, 0, (2 * 64 + 8) * (size_t)r * sizeof(double), s));
+    if ((st = core_apply_M(c, w, r, mv, r, r)) != CF_OK) return fail(st);
+    BHIPCHK(b, launch_coldot(s, n, r, w, r, mv, r, b->d_lzp, LZ_CHUNKS, coef));
+    BHIPCHK(b, launch_lanczos_update_blk(s, n, r, 0, w, nullptr, nullptr, coef, v, 0));
+    for (int j = 0; j < k; ++j) {
+      if ((st = core_htilde_step(c, v, r, r, 1.0, nullptr, 0, 0.0, nullptr, 0, 0.0, w, r)) != CF_OK)
+        return fail(st);
+      if (j > 0) BHIPCHK(b, launch_lanczos_update_blk(s, n, r, j, w, v, vprev, coef, nullptr, 1));
+      if ((st = core_apply_M(c, v, r, mv, r, r)) != CF_OK) return fail(st);
+      BHIPCHK(b, launch_coldot(s, n, r, w, r, mv, r, b->d_lzp, LZ_CHUNKS, coef + (1 + 2 * j) * r));
+      BHIPCHK(b, launch_lanczos_update_blk(s, n, r, j, w, v, vprev, coef, nullptr, 2));
+      if ((st = core_apply_M(c, w, r, mv, r, r)) != CF_OK) return fail(st);
+      BHIPCHK(b, launch_coldot(s, n, r, w, r, mv, r, b->d_lzp, LZ_CHUNKS, coef + (2 + 2 * j) * r));
+      if (j + 1 < k) {
+        BHIPCHK(b, launch_lanczos_update_blk(s, n, r, j, w, v, vprev, coef, vprev, 3));
+        std::swap(vprev, v);
+      }
+    }
+    BHIPCHK(b, launch_tridiag_bounds_blk(s, coef, r, k, b->d_lz + 2 * slot_entry.size()));
+    slot_entry.insert(slot_entry.end(), g.begin(), g.end());
   }
+  BHIPCHK(b, hipMemcpyAsync(b->h_lz.data(), b->d_lz, 2 * (size_t)b->count * sizeof(double),
+                            hipMemcpyDeviceToHost, s));
+  BHIPCHK(b, hipStreamSynchronize(s));
+  for (size_t q = 0; q < slot_entry.size(); ++q) {
+    const int i = slot_entry[q];
+    lmin_est[i] = b->h_lz[2 * q];
+    b_upper[i] = b->h_lz[2 * q + 1];
+  }
+  for (int i = 0; i < b->count; ++i)
+    if (!std::isfinite(lmin_est[i]) || !std::isfinite(b_upper[i]))
+      return berr(b, CF_ENUMERIC, "entry " + std::to_string(i) + ": non-finite Lanczos bound (breakdown?)");
   return CF_OK;
 }
 

@@ -144,7 +144,9 @@ __global__ __launch_bounds__(256) void k_rotate(const double *__restrict__ In, i
                                                 int64_t n, int N, const double *__restrict__ W,
                                                 int64_t wsk, int64_t wsj,
                                                 double *__restrict__ Out, int64_t ldo,
-                                                int nrb) {
+                                                int nrb, const int *__restrict__ skip) {
+  // skip (optional): four status words; any nonzero one leaves Out untouched
+  if (skip && (skip[0] | skip[1] | skip[2] | skip[3])) return;
   constexpr int KS = 32, LDA = 34;
   __shared__ double as[64 * LDA];
   const int T = (N + GT - 1) / GT;
@@ -199,13 +201,13 @@ __global__ __launch_bounds__(256) void k_rotate(const double *__restrict__ In, i
 }
 
 hipError_t launch_rotate(hipStream_t s, const double *In, int64_t ldi, int64_t n, int N,
-                         const double *W, int64_t wsk, int64_t wsj, double *Out, int64_t ldo) {
+                         const double *W, int64_t wsk, int64_t wsj, double *Out, int64_t ldo, const int *skip) {
   if (n <= 0 || N <= 0) return hipSuccess;
   const int T = (N + GT - 1) / GT;
   const int nrb = (int)((n + 63) / 64);
   const int nrb8 = (nrb + 7) / 8 * 8;
   hipLaunchKernelGGL(k_rotate, dim3(nrb8 * T), dim3(256), 0, s, In, ldi, n, N, W, wsk, wsj, Out,
-                     ldo, nrb);
+                     ldo, nrb, skip);
   return hipGetLastError();
 }
 
@@ -470,10 +472,16 @@ __device__ int sturm_count(const double *alpha, const double *beta2, int k, doub
   return cnt;
 }
 
-__global__ void k_tridiag_bounds(const double *coef, int k, double *out2) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// Run r = blockIdx.x reads its scalars at coef[q * stride + r] and writes out2[2 r], out2[2 r + 1].
+__global__ void k_tridiag_bounds(const double *coef, int k, double *out2, int stride) {
+  if (threadIdx.x != 0) return;
+  coef += blockIdx.x;
+  out2 += 2 * blockIdx.x;
   double alpha[64], beta2[64];
-  for (int i = 0; i < k; ++i) { alpha[i] = coef[1 + 2 * i]; beta2[i] = coef[2 + 2 * i]; }
+  for (int i = 0; i < k; ++i) {
+    alpha[i] = coef[(1 + 2 * i) * stride];
+    beta2[i] = coef[(2 + 2 * i) * stride];
+  }
   // Gershgorin interval
   double lo = 1e300, hi = -1e300;
   for (int i = 0; i < k; ++i) {
@@ -501,7 +509,43 @@ __global__ void k_tridiag_bounds(const double *coef, int k, double *out2) {
 
 hipError_t launch_tridiag_bounds(hipStream_t s, const double *coef, const double * /*unused*/,
                                  int k, double *out2) {
-  hipLaunchKernelGGL(k_tridiag_bounds, dim3(1), dim3(64), 0, s, coef, k, out2);
+  hipLaunchKernelGGL(k_tridiag_bounds, dim3(1), dim3(64), 0, s, coef, k, out2, 1);
+  return hipGetLastError();
+}
+
+hipError_t launch_tridiag_bounds_blk(hipStream_t s, const double *coef, int runs, int k,
+                                     double *out2) {
+  if (runs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_tridiag_bounds, dim3(runs), dim3(64), 0, s, coef, k, out2, runs);
+  return hipGetLastError();
+}
+
+// The Lanczos update phases (as k_lanczos_update) for `runs` independent runs
+// held as the columns of n x runs row-major blocks; run r's scalars sit at
+// coef[q * runs + r].
+__global__ __launch_bounds__(256) void k_lanczos_update_blk(int64_t n, int runs, int j, int phase,
+                                                            double *w, const double *v,
+                                                            const double *vprev,
+                                                            const double *coef, double *vnext) {
+  const int64_t total = n * runs;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * 256) {
+    const int r = (int)(e % runs);
+    if (phase == 0) vnext[e] = w[e] * (1.0 / sqrt(coef[r]));
+    else if (phase == 1) w[e] -= sqrt(coef[2 * j * runs + r]) * vprev[e];
+    else if (phase == 2) w[e] -= coef[(1 + 2 * j) * runs + r] * v[e];
+    else vnext[e] = w[e] * (1.0 / sqrt(coef[(2 + 2 * j) * runs + r]));
+  }
+}
+
+hipError_t launch_lanczos_update_blk(hipStream_t s, int64_t n, int runs, int j, double *w,
+                                     const double *v, const double *vprev, const double *coef,
+                                     double *vnext, int phase) {
+  if (n <= 0 || runs <= 0) return hipSuccess;
+  int64_t blocks = (n * runs + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_lanczos_update_blk, dim3((unsigned)blocks), dim3(256), 0, s, n, runs, j,
+                     phase, w, v, vprev, coef, vnext);
   return hipGetLastError();
 }
 
@@ -552,6 +596,75 @@ hipError_t launch_copy(hipStream_t s, int64_t n, int N, const double *X, int64_t
   return hipGetLastError();
 }
 
+
+// Predicated copy for the batched projection: as k_copy, but nothing is
+// written when any of the four status words is nonzero.
+__global__ __launch_bounds__(256) void k_copy_skip(int64_t n, int N, const double *X, int64_t ldx,
+                                                   double *Y, int64_t ldy,
+                                                   const int *__restrict__ skip) {
+  if (skip[0] | skip[1] | skip[2] | skip[3]) return;
+  for (int64_t i = (int64_t)blockIdx.x * 4 + threadIdx.y; i < n; i += (int64_t)gridDim.x * 4)
+    for (int j = threadIdx.x; j < N; j += 64) Y[i * ldy + j] = X[i * ldx + j];
+}
+
+hipError_t launch_copy_skip(hipStream_t s, int64_t n, int N, const double *X, int64_t ldx,
+                            double *Y, int64_t ldy, const int *skip) {
+  if (n <= 0 || N <= 0) return hipSuccess;
+  int64_t blocks = (n + 3) / 4;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_copy_skip, dim3((unsigned)blocks), dim3(64, 4), 0, s, n, N, X, ldx, Y, ldy,
+                     skip);
+  return hipGetLastError();
+}
+
+// Guard of a projected pencil (Hh, Mh, N x N) before the batched eigensolve:
+// when the orthonormalisation failed (st[0] or st[1] set) or an entry of the
+// pencil is not finite, both matrices become the identity, so that the
+// eigensolver sees a trivial problem; a non-finite pencil of an entry whose
+// orthonormalisation succeeded is recorded in st[3].  One workgroup.
+__global__ __launch_bounds__(256) void k_rr_guard(double *__restrict__ Hh, double *__restrict__ Mh,
+                                                  int N, int *__restrict__ st) {
+  __shared__ int nonfinite;
+  if (threadIdx.x == 0) nonfinite = 0;
+  __syncthreads();
+  const int prior = st[0] | st[1];
+  const int NN = N * N;
+  int nf = 0;
+  for (int e = threadIdx.x; e < NN; e += 256)
+    if (!isfinite(Hh[e]) || !isfinite(Mh[e])) nf = 1;
+  if (nf) atomicOr(&nonfinite, 1);   // LDS flag only
+  __syncthreads();
+  if (!prior && !nonfinite) return;
+  for (int e = threadIdx.x; e < NN; e += 256) {
+    const double v = (e / N == e % N) ? 1.0 : 0.0;
+    Hh[e] = v;
+    Mh[e] = v;
+  }
+  if (threadIdx.x == 0 && !prior) st[3] = 1;
+}
+
+hipError_t launch_rr_guard(hipStream_t s, double *Hh, double *Mh, int N, int *st) {
+  if (N <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rr_guard, dim3(1), dim3(256), 0, s, Hh, Mh, N, st);
+  return hipGetLastError();
+}
+
+// st[8 e + 2] = info[slot[e]] for every entry e with slot[e] >= 0.
+__global__ __launch_bounds__(256) void k_rr_info(const int *__restrict__ info,
+                                                 const int *__restrict__ slot, int count,
+                                                 int *__restrict__ st) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= count) return;
+  const int k = slot[e];
+  if (k >= 0) st[8 * e + 2] = info[k];
+}
+
+hipError_t launch_rr_info(hipStream_t s, const int *info, const int *slot, int count, int *st) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rr_info, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, info, slot,
+                     count, st);
+  return hipGetLastError();
+}
 
 // ---------------------------------------------------------------------------
 // Ritz residuals: R[:, j] -= theta[j] MZ[:, j], then per-column sums

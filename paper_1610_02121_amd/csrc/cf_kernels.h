@@ -260,8 +260,10 @@ hipError_t launch_gram_partial(hipStream_t s, const double *A, int64_t lda, cons
 hipError_t launch_gram_reduce(hipStream_t s, const double *Gp, int nchunks, int N, double *G,
                               int mode);
 // Out[r, j] = sum_k In[r, k] * W[k*wsk + j*wsj]     (out of place)
+// skip: optional device status words (4); if any is nonzero the kernel writes nothing.
 hipError_t launch_rotate(hipStream_t s, const double *In, int64_t ldi, int64_t n, int N,
-                         const double *W, int64_t wsk, int64_t wsj, double *Out, int64_t ldo);
+                         const double *W, int64_t wsk, int64_t wsj, double *Out, int64_t ldo,
+                         const int *skip = nullptr);
 // In-place lower Cholesky of the N x N row-major A (ld = N) with optional column
 // scaling: A <- chol(S (A + shift*I_diag) S), S = diag(A)^-1/2 when scale != 0;
 // s_out[i] receives S_ii (1 when not scaling).  flag[0] = index+1 of a failing
@@ -286,6 +288,14 @@ hipError_t launch_lanczos_update(hipStream_t s, int64_t n, int j, double *w, con
                                  double *scratch, int nblk, int phase);
 hipError_t launch_tridiag_bounds(hipStream_t s, const double *coef, const double *unused, int k,
                                  double *out2);
+// Independent Lanczos runs as the columns of n x runs blocks (scalars of run r
+// at coef[q * runs + r], q as in the single-run layout); bounds of run r into
+// out2[2 r], out2[2 r + 1].
+hipError_t launch_tridiag_bounds_blk(hipStream_t s, const double *coef, int runs, int k,
+                                     double *out2);
+hipError_t launch_lanczos_update_blk(hipStream_t s, int64_t n, int runs, int j, double *w,
+                                     const double *v, const double *vprev, const double *coef,
+                                     double *vnext, int phase);
 
 // ---- Ritz residual helpers (cf_dense.hip)
 // R[i][j] -= theta[j] MZ[i][j]  (theta on the device)
@@ -298,6 +308,13 @@ hipError_t launch_coldot(hipStream_t s, int64_t n, int N, const double *A, int64
 // ---- data-movement helpers (cf_dense.hip)
 hipError_t launch_sub(hipStream_t s, int64_t n, const double *A, const double *B, double *C);
 hipError_t launch_transpose(hipStream_t s, int N, const double *In, int64_t ldi, double *Out);
+// Batched projection helpers: predicated copy (skip as in launch_rotate),
+// pencil guard (identity on failure, st[3] on a non-finite pencil) and the
+// scatter of the batched eigensolver's info into st[8 e + 2].
+hipError_t launch_copy_skip(hipStream_t s, int64_t n, int N, const double *X, int64_t ldx,
+                            double *Y, int64_t ldy, const int *skip);
+hipError_t launch_rr_guard(hipStream_t s, double *Hh, double *Mh, int N, int *st);
+hipError_t launch_rr_info(hipStream_t s, const int *info, const int *slot, int count, int *st);
 hipError_t launch_copy(hipStream_t s, int64_t n, int N, const double *X, int64_t ldx, double *Y,
                        int64_t ldy);
 

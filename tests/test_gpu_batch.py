@@ -118,9 +118,21 @@ def test_batch_entry_against_oracle(tiny_enriched, hydrogen_small, si_small):
     assert rel < 10 * U32 * (lmax / lmin) * m
 
 
+def same_subspace_result(Yb, Ys, th_b, th_s):
+    """Ritz values within 1e-12 relative and Ritz vectors equal column by
+    column up to sign (the batched eigensolver may order its rounding
+    differently from the single one)."""
+    assert np.abs(th_b - th_s).max() <= 1e-12 * max(1.0, np.abs(th_s).max())
+    sgn = np.sign(np.einsum("ij,ij->j", Yb, Ys))
+    err = np.abs(Yb * sgn[None, :] - Ys).max() / np.abs(Ys).max()
+    return float(err)
+
+
 def test_batch_fp64_and_rayleigh_ritz(tiny_enriched, hydrogen_small, si_small):
-    """FP64 batch filter, Rayleigh-Ritz and Lanczos of every entry equal the
-    single-problem entry points."""
+    """The FP64 batch filter of every entry equals the single-problem entry
+    point bit for bit; the batched projection (no host waits, one eigensolve
+    per block width) and the grouped Lanczos runs match the single-problem
+    ones to rounding."""
     print("[batch fp64 + rr]", flush=True)
     batch, probs, singles, Ns, ab = state(tiny_enriched, hydrogen_small, si_small)
     m = 5
@@ -134,12 +146,44 @@ def test_batch_fp64_and_rayleigh_ritz(tiny_enriched, hydrogen_small, si_small):
         Ys = singles[id(p)].filter(Xd[i], m, a, b, prec="fp64")
         assert np.array_equal(host(Ycopy[i]), host(Ys)), i
         th_s = singles[id(p)].rayleigh_ritz(Ys)
-        assert np.array_equal(th_b[i], th_s), i
-        assert np.array_equal(host(Yb[i]), host(Ys)), i
+        err = same_subspace_result(host(Yb[i]), host(Ys), th_b[i], th_s)
+        print(f"  entry {i}: N={Ns[i]} vectors rel diff {err:.2e} "
+              f"bitwise={np.array_equal(host(Yb[i]), host(Ys))}", flush=True)
+        assert err < 1e-10, i
+    # Lanczos runs of entries sharing a problem go as the columns of one block
+    # (column-wise dot products in another summation order): the bounds agree
+    # with the single-vector runs to rounding, amplified at most mildly by 10 steps
     lo_b, hi_b = batch.lanczos_bounds(_STATE["v0"], 10)
     for i, p in enumerate(probs):
         lo_s, hi_s = singles[id(p)].lanczos_bounds(_STATE["v0"][i], 10)
-        assert lo_b[i] == lo_s and hi_b[i] == hi_s, i
+        scale = max(abs(lo_s), abs(hi_s))
+        print(f"  lanczos entry {i}: {abs(lo_b[i] - lo_s) / scale:.1e} {abs(hi_b[i] - hi_s) / scale:.1e}")
+        assert abs(lo_b[i] - lo_s) <= 1e-10 * scale and abs(hi_b[i] - hi_s) <= 1e-10 * scale, i
+
+
+def test_batch_rayleigh_ritz_redo_and_failure(tiny_enriched, hydrogen_small, si_small):
+    """An entry whose block is nearly rank deficient (one column a 1e-12
+    perturbation of another) takes the shifted path of the single-problem
+    projection and gives its result; an entry with a zero column fails with
+    CF_ENOTSPD naming the entry and leaves that block as it was."""
+    from paper_1610_02121_amd import ChebFilterError
+    print("[batch rr redo]", flush=True)
+    batch, probs, singles, Ns, ab = state(tiny_enriched, hydrogen_small, si_small)
+    Xs = blocks(probs, Ns, 90)
+    k = 2                                   # si_small, 37 columns
+    Xs[k][:, 5] = Xs[k][:, 4] * (1.0 + 1e-12 * np.random.default_rng(5).standard_normal(probs[k].n))
+    Yb = [dev(x) for x in Xs]
+    th_b = batch.rayleigh_ritz(Yb)
+    for i, p in enumerate(probs):
+        Ys = dev(Xs[i])
+        th_s = singles[id(p)].rayleigh_ritz(Ys)
+        err = same_subspace_result(host(Yb[i]), host(Ys), th_b[i], th_s)
+        assert err < 1e-10, i
+    Xs[4][:, 2] = 0.0                       # tiny_enriched, 7 columns
+    Yb = [dev(x) for x in Xs]
+    with pytest.raises(ChebFilterError, match="CF_ENOTSPD.*entry 4"):
+        batch.rayleigh_ritz(Yb)
+    assert np.array_equal(host(Yb[4]), Xs[4])
 
 
 def test_batch_errors(tiny_enriched, hydrogen_small, si_small):

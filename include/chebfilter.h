@@ -215,12 +215,27 @@ cf_status chebfilter_filter_batch(cf_batch *batch, const double *const *X, const
                                   int32_t m, const double *a, const double *b, int32_t prec,
                                   int32_t use_graph);
 
-/* chebfilter_rayleigh_ritz for every entry, one after another (synchronises);
- * theta_host[i] receives N[i] values. */
+/* chebfilter_rayleigh_ritz for every entry (Sec. V's projection), with one
+ * host synchronisation for the whole batch: every entry is orthonormalised by
+ * two unshifted Cholesky-QR passes and projected with no host wait, the
+ * projected pencils of equal width go to one batched generalized eigensolve,
+ * and a predicated rotation writes Y[i] only where every step succeeded.  An
+ * entry whose orthonormalisation or eigensolve failed is then redone by
+ * chebfilter_rayleigh_ritz (shifted Cholesky-QR, its own errors).  Results
+ * equal the single-problem call to rounding.  theta_host[i] receives N[i]
+ * values.  On an error (message names the entry) the blocks of other entries
+ * may already hold their Ritz vectors; the failing entry's block is the
+ * filtered block or, if the eigensolve failed, an orthonormal basis of it.
+ * Workspace: per entry two max_cols^2 pencils, allocated on the first call. */
 cf_status chebfilter_rayleigh_ritz_batch(cf_batch *batch, double *const *Y, const int64_t *ldy,
                                          const int64_t *N, double *const *theta_host);
 
-/* chebfilter_lanczos_bounds for every entry (synchronises); lmin_est[i], b_upper[i]. */
+/* chebfilter_lanczos_bounds for every entry (Sec. V's upper bound), one host
+ * synchronisation: the k-step runs of entries that share a problem are the
+ * columns of one block (up to max_cols runs), so each step applies the
+ * operator once per problem; runs stay independent, and the bounds equal the
+ * single-vector call's to rounding.  lmin_est[i], b_upper[i].  Workspace: four
+ * blocks of (largest n) x (largest group) doubles, allocated on the first call. */
 cf_status chebfilter_lanczos_bounds_batch(cf_batch *batch, const double *const *v0, int32_t k,
                                           double *lmin_est, double *b_upper);
 

@@ -105,6 +105,40 @@ def cpu_baseline(prob, N_total, m, seed, budget_s=20.0):
                       f"scipy sparse products run on one thread; setup {t_setup:.1f}s untimed"}
 
 
+def assembly_timing(ctx, prob, reps=5):
+    """H_cc_e = K + B^T diag(w V_e) B on the device for every cell without
+    enrichment functions (the per-step operator update of a self-consistent
+    iteration), V = the workload's potential at the cells' Gauss points.
+    Kernel time from HIP events; the reduced copies' refresh is timed apart."""
+    import numpy as np
+    import torch
+    from synth.assemble import plain_points, plain_tables
+    B, w, K, _ = plain_tables(prob)
+    ep = np.asarray(prob.enr_ptr)
+    cells = np.nonzero(ep[1:] == ep[:-1])[0].astype(np.int32)
+    pts = plain_points(prob, cells)
+    V = torch.tensor(prob.meta["potential"](pts.reshape(-1, 3)).reshape(len(cells), -1),
+                     dtype=torch.float64, device=ctx.device)
+    ctx.assembly_tables(B, w, K)
+    ctx.assemble_cells(cells, V)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctx.assemble_cells(cells, V)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / reps
+    launches, ms, flops = ctx.profile_query("assemble")
+    ctx.profile(False)
+    kern = ms / max(launches, 1)
+    return {"cells": int(len(cells)), "quadrature_points": int(len(w)),
+            "kernel_ms": kern, "with_reduced_copies_ms": 1e3 * wall,
+            "tflops": flops / max(launches, 1) / (kern / 1e3) / 1e12,
+            "flops_credited": "2*36*256*nq per cell (the 36 upper 16x16 tiles)",
+            "peak_tflops_fp64_mfma": PEAK_FP64_MFMA / 1e12,
+            "hbm_write_gb": len(cells) * 128 * 128 * 8 / 1e9}
+
+
 def precision_forms(ctx, X, Y, m, a, b, reps=3):
     """Filter-only time of each precision form on the same block and interval,
     with the cell-product kernel's event-timed launches."""
@@ -432,6 +466,8 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--no-assembly", action="store_true",
+                    help="skip the timing of the device assembly of the plain cells")
     ap.add_argument("--passes", type=int, default=1,
                     help="filter passes per step (each of degree m, Rayleigh-Ritz between them)")
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16"],
@@ -612,6 +648,9 @@ def main():
         log("timing the filter alone in the three precision forms")
         out["precision_forms"] = precision_forms(ctx, state["X"], state["Y"], m,
                                                  float(state["theta"][-1]), state["b"])
+    if not args.no_assembly and "potential" in prob.meta and "mesh" in prob.meta:
+        log("timing the device assembly of the plain cells' blocks")
+        out["plain_cell_assembly"] = assembly_timing(ctx, prob)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(prob, N, m, args.seed)

@@ -247,6 +247,37 @@ cf_status chebfilter_lanczos_bounds_batch(cf_batch *batch, const double *const *
  * copies are refreshed.  Synchronises. */
 cf_status chebfilter_update_H_cc(cf_ctx *ctx, const double *H_cc);
 
+/* ---- Element blocks of the plain cells on the device ----------------------- */
+
+/* Reference tables for chebfilter_assemble_cells (Sec. III.B, Eq. HBlocks):
+ * the classical block of a cell outside every enrichment support is
+ * H^cc_e = K + B^T diag(w .* V_e) B, with K [npc][npc] the kinetic block
+ * 1/2 int grad N_a . grad N_b (identical for the cells of the uniform mesh;
+ * symmetric to 1e-10 relative, symmetrised), B [nq][npc] the shape-function
+ * values at the cell's nq Gauss points (the same in every cell) and w [nq]
+ * the quadrature weights times the cell Jacobian.  Host arrays, row-major,
+ * copied; 1 <= nq <= 4096.  Synchronises.  CF_EINVAL on non-finite input. */
+cf_status chebfilter_assembly_tables(cf_ctx *ctx, int32_t nq, const double *B, const double *w,
+                                     const double *K);
+
+/* Assemble H^cc_e on the device for the ncells cells listed in cells (host
+ * int32, distinct, cells without enrichment functions: the blocks of cells
+ * inside an enrichment support use the adaptive rule of Sec. IV.C and stay
+ * host input) from V (device FP64, row i = the potential at the nq Gauss
+ * points of cells[i], leading dimension ldv >= nq): the quadrature sum runs
+ * as an FP64 MFMA contraction per cell and overwrites the context's block of
+ * that cell (written exactly symmetric); the reduced-precision copies are
+ * refreshed.  This is the per-step operator update of a self-consistent
+ * iteration when the potential lives on the device.  Enqueued on the
+ * context's stream (waits only when the cell list differs from the last
+ * call's).  CF_EINVAL without tables, on a bad, repeated or enriched cell. */
+cf_status chebfilter_assemble_cells(cf_ctx *ctx, const int32_t *cells, int64_t ncells, const double *V,
+                                    int64_t ldv);
+
+/* Copy the current H^cc_e of the listed cells (host int32) into out (host,
+ * [ncells][npc][npc]).  Synchronises. */
+cf_status chebfilter_get_H_cc(cf_ctx *ctx, const int32_t *cells, int64_t ncells, double *out);
+
 /* res_host[j] = || H^E z_j - theta_j M^E z_j ||_{(M^E)^-1} for the columns z_j of
  * Z with theta_host[j] (the Ritz residual in the dual norm of Sec. V's
  * generalized problem).  Uses the context's work blocks; synchronises. */

@@ -18,6 +18,8 @@ subspace   Cholesky-QR, Rayleigh-Ritz, Lanczos spectrum bounds, one
            subspace-iteration step and the error metrics (Sec. V).
 mlp        the learned-bounds network: FP64 forward, backpropagated
            mean-squared-error gradient, Adam.
+assembly   the classical element block of a plain cell as the quadrature
+           sum over its Gauss points (Eq. HBlocks).
 
 Parity pins: see the `-m "not gpu"` tests under tests/ (closed forms,
 textbook limits, library routines, brute force on tiny meshes).

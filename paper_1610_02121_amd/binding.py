@@ -32,7 +32,8 @@ EXPORTS = ["chebfilter_init", "chebfilter_destroy", "chebfilter_last_error", "ch
            "chebfilter_mlp_sizes", "chebfilter_mlp_set_params", "chebfilter_mlp_get_params",
            "chebfilter_mlp_forward", "chebfilter_mlp_loss_grad", "chebfilter_mlp_adam_step",
            "chebfilter_mlp_set_normalization", "chebfilter_bounds_features",
-           "chebfilter_bounds_predict"]
+           "chebfilter_bounds_predict", "chebfilter_assembly_tables", "chebfilter_assemble_cells",
+           "chebfilter_get_H_cc"]
 
 
 class CfProblem(C.Structure):
@@ -110,6 +111,9 @@ def load_library() -> C.CDLL:
     lib.chebfilter_bounds_features.argtypes = [PD, i32, PD]
     lib.chebfilter_bounds_predict.argtypes = [vp, vp, PD, vp, i32, i32, i32, PD, PD,
                                               C.POINTER(i32), C.POINTER(i32)]
+    lib.chebfilter_assembly_tables.argtypes = [vp, i32, vp, vp, vp]
+    lib.chebfilter_assemble_cells.argtypes = [vp, vp, i64, vp, i64]
+    lib.chebfilter_get_H_cc.argtypes = [vp, vp, i64, vp]
     for nm in EXPORTS:
         if nm not in ("chebfilter_last_error", "chebfilter_batch_last_error",
                       "chebfilter_mlp_last_error"):
@@ -167,6 +171,7 @@ class Context:
         self.lib.chebfilter_sizes(h, C.byref(nh), C.byref(ne), C.byref(mc))
         self.n_h, self.n_e, self.max_cols = nh.value, ne.value, mc.value
         self.n = self.n_h + self.n_e
+        self._npc = (int(prob.p) + 1) ** 3
 
     def _check(self, st: int):
         if st != 0:
@@ -250,6 +255,35 @@ class Context:
         """Replace the elemental H^cc_e (host array [E, npc, npc])."""
         H = _np(H_cc, np.float64)
         self._check(self.lib.chebfilter_update_H_cc(self._h, H.ctypes.data))
+
+    def assembly_tables(self, B, w, K):
+        """Reference tables of the plain-cell quadrature: B [nq, npc] shape values,
+        w [nq] weights with the Jacobian, K [npc, npc] kinetic block (host arrays)."""
+        B, w, K = _np(B, np.float64), _np(w, np.float64), _np(K, np.float64)
+        if B.ndim != 2 or w.shape != (B.shape[0],) or K.shape != (B.shape[1], B.shape[1]):
+            raise ValueError("assembly_tables: B [nq, npc], w [nq], K [npc, npc]")
+        self._check(self.lib.chebfilter_assembly_tables(self._h, int(B.shape[0]), B.ctypes.data,
+                                                        w.ctypes.data, K.ctypes.data))
+
+    def assemble_cells(self, cells, V):
+        """H^cc_e = K + B^T diag(w V_e) B on the device for the listed plain
+        cells; V is a float64 CUDA tensor [len(cells), nq] (row stride >= nq)."""
+        import torch
+        cl = _np(cells, np.int32)
+        if V.dtype != torch.float64 or not V.is_cuda or V.dim() != 2 or V.stride(1) != 1:
+            raise TypeError("V must be a float64 CUDA tensor [ncells, nq] with unit column stride")
+        if V.shape[0] != cl.size:
+            raise ValueError("V needs one row per cell")
+        self._check(self.lib.chebfilter_assemble_cells(self._h, cl.ctypes.data, int(cl.size),
+                                                       V.data_ptr(), int(V.stride(0))))
+
+    def get_H_cc(self, cells) -> np.ndarray:
+        """The current H^cc_e of the listed cells, [len(cells), npc, npc]."""
+        cl = _np(cells, np.int32)
+        out = np.zeros((cl.size, self._npc, self._npc))
+        self._check(self.lib.chebfilter_get_H_cc(self._h, cl.ctypes.data, int(cl.size),
+                                                 out.ctypes.data))
+        return out
 
     def residual_norms(self, Z, theta) -> np.ndarray:
         """||H z_j - theta_j M z_j||_{M^-1} per column of Z."""

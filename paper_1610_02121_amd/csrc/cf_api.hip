@@ -101,6 +101,15 @@ struct cf_ctx {
   // ones in FP32
   int32_t *cells_split = nullptr;
   std::vector<int> near_cnt;
+  // assembly of the plain cells' blocks: reference tables (shape values
+  // [nq4][NPAD], weights [nq], kinetic block [NPAD][NPAD]), the uploaded cell
+  // list and its host copy, which cells carry enrichment functions
+  double *asm_B = nullptr, *asm_w = nullptr, *asm_K = nullptr;
+  int asm_nq = 0;
+  int32_t *asm_cells = nullptr;
+  int64_t asm_cap = 0;
+  std::vector<int32_t> asm_list;
+  std::vector<uint8_t> cell_enriched;
   rocblas_handle rb = nullptr;
   std::string err;
   bool profiling = false;
@@ -1010,6 +1019,9 @@ static cf_status do_init(const cf_problem *pr, const cf_options *opt, cf_ctx *c)
     tmp_free();
     if (st != CF_OK) return st;
   }
+  c->cell_enriched.assign(E, 0);
+  if (n_e > 0)
+    for (int64_t e = 0; e < E; ++e) c->cell_enriched[e] = pr->enr_ptr[e + 1] > pr->enr_ptr[e];
   // cell flags: first touch; last touch of a DOF no enriched cell contains
   {
     std::vector<uint8_t> inreg(n_h, 0);
@@ -1940,6 +1952,115 @@ cf_status chebfilter_update_H_cc(cf_ctx *c, const double *H_cc) {
   if (!H_cc) return set_err(c, CF_EINVAL, "update_H_cc: null H_cc");
   HIPCHK(c, hipSetDevice(c->device));
   return upload_cells(c, H_cc, "update_H_cc");
+}
+
+cf_status chebfilter_assembly_tables(cf_ctx *c, int32_t nq, const double *B, const double *w,
+                                     const double *K) {
+  if (!c) return CF_EINVAL;
+  if (nq < 1 || nq > 4096) return set_err(c, CF_EINVAL, "assembly_tables: nq must be 1..4096");
+  if (!B || !w || !K) return set_err(c, CF_EINVAL, "assembly_tables: null table");
+  const int npc = c->npc;
+  const int nq4 = (nq + 3) & ~3;
+  std::vector<double> hB((size_t)nq4 * NPAD, 0.0), hK((size_t)NPAD * NPAD, 0.0);
+  double kmax = 0.0;
+  for (int64_t q = 0; q < (int64_t)nq * npc; ++q)
+    if (!std::isfinite(B[q])) return set_err(c, CF_EINVAL, "assembly_tables: non-finite B");
+  for (int q = 0; q < nq; ++q) {
+    if (!std::isfinite(w[q])) return set_err(c, CF_EINVAL, "assembly_tables: non-finite w");
+    for (int a = 0; a < npc; ++a) hB[(size_t)q * NPAD + a] = B[(size_t)q * npc + a];
+  }
+  for (int64_t q = 0; q < (int64_t)npc * npc; ++q) {
+    if (!std::isfinite(K[q])) return set_err(c, CF_EINVAL, "assembly_tables: non-finite K");
+    kmax = std::max(kmax, std::fabs(K[q]));
+  }
+  for (int a = 0; a < npc; ++a)
+    for (int b = 0; b < npc; ++b) {
+      const double x = K[a * npc + b], y = K[b * npc + a];
+      if (std::fabs(x - y) > 1e-10 * kmax) return set_err(c, CF_EINVAL, "assembly_tables: K not symmetric");
+      hK[(size_t)a * NPAD + b] = 0.5 * (x + y);
+    }
+  HIPCHK(c, hipSetDevice(c->device));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (c->asm_nq < nq4) {
+    if (c->asm_B) { (void)hipFree(c->asm_B); c->allocs.erase(std::find(c->allocs.begin(), c->allocs.end(), (void *)c->asm_B)); c->asm_B = nullptr; }
+    if (c->asm_w) { (void)hipFree(c->asm_w); c->allocs.erase(std::find(c->allocs.begin(), c->allocs.end(), (void *)c->asm_w)); c->asm_w = nullptr; }
+  }
+  if (!c->asm_B) {
+    STCHK(dalloc(c, &c->asm_B, hB.size()));
+    STCHK(dalloc(c, &c->asm_w, (size_t)nq4));
+  }
+  if (!c->asm_K) STCHK(dalloc(c, &c->asm_K, hK.size()));
+  HIPCHK(c, hipMemcpy(c->asm_B, hB.data(), hB.size() * sizeof(double), hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->asm_w, w, (size_t)nq * sizeof(double), hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->asm_K, hK.data(), hK.size() * sizeof(double), hipMemcpyHostToDevice));
+  c->asm_nq = nq;
+  return CF_OK;
+}
+
+cf_status chebfilter_assemble_cells(cf_ctx *c, const int32_t *cells, int64_t ncells, const double *V,
+                                    int64_t ldv) {
+  if (!c) return CF_EINVAL;
+  if (!c->asm_B) return set_err(c, CF_EINVAL, "assemble_cells: no reference tables (chebfilter_assembly_tables)");
+  if (ncells < 0 || ncells > c->E) return set_err(c, CF_EINVAL, "assemble_cells: bad cell count");
+  if (ncells == 0) return CF_OK;
+  if (!cells || !V) return set_err(c, CF_EINVAL, "assemble_cells: null argument");
+  if (ldv < c->asm_nq) return set_err(c, CF_EINVAL, "assemble_cells: ldv < nq");
+  std::vector<uint8_t> seen(c->E, 0);
+  for (int64_t i = 0; i < ncells; ++i) {
+    const int32_t e = cells[i];
+    if (e < 0 || e >= c->E) return set_err(c, CF_EINVAL, "assemble_cells: cell index out of range");
+    if (c->cell_enriched[e])
+      return set_err(c, CF_EINVAL, "assemble_cells: cell " + std::to_string(e) +
+                                       " carries enrichment functions (its blocks use the adaptive rule)");
+    if (seen[e]) return set_err(c, CF_EINVAL, "assemble_cells: cell listed twice");
+    seen[e] = 1;
+  }
+  HIPCHK(c, hipSetDevice(c->device));
+  if ((int64_t)c->asm_list.size() != ncells ||
+      !std::equal(c->asm_list.begin(), c->asm_list.end(), cells)) {
+    // a new cell list: wait for work that may still read the old one
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (ncells > c->asm_cap) {
+      if (c->asm_cells) {
+        (void)hipFree(c->asm_cells);
+        c->allocs.erase(std::find(c->allocs.begin(), c->allocs.end(), (void *)c->asm_cells));
+        c->asm_cells = nullptr;
+      }
+      STCHK(dalloc(c, &c->asm_cells, (size_t)ncells));
+      c->asm_cap = ncells;
+    }
+    HIPCHK(c, hipMemcpy(c->asm_cells, cells, (size_t)ncells * sizeof(int32_t), hipMemcpyHostToDevice));
+    c->asm_list.assign(cells, cells + ncells);
+  }
+  {
+    Scope sc(c, "assemble", 2.0 * 36 * 256 * (double)((c->asm_nq + 3) & ~3) * ncells);
+    HIPCHK(c, launch_assemble_cells(c->stream, c->asm_B, c->asm_w, c->asm_K, c->asm_cells,
+                                    (int)ncells, V, ldv, c->asm_nq, c->Hp));
+  }
+  const int64_t hsz = c->E * NPAD * NPAD;
+  if (c->Hp32) HIPCHK(c, launch_to_f32(c->stream, hsz, c->Hp, c->Hp32));
+  if (c->Hp16) HIPCHK(c, launch_to_bf16(c->stream, hsz, c->Hp, c->Hp16));
+  return CF_OK;
+}
+
+cf_status chebfilter_get_H_cc(cf_ctx *c, const int32_t *cells, int64_t ncells, double *out) {
+  if (!c) return CF_EINVAL;
+  if (ncells < 0) return set_err(c, CF_EINVAL, "get_H_cc: bad cell count");
+  if (ncells == 0) return CF_OK;
+  if (!cells || !out) return set_err(c, CF_EINVAL, "get_H_cc: null argument");
+  for (int64_t i = 0; i < ncells; ++i)
+    if (cells[i] < 0 || cells[i] >= c->E) return set_err(c, CF_EINVAL, "get_H_cc: cell index out of range");
+  HIPCHK(c, hipSetDevice(c->device));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  const int npc = c->npc;
+  std::vector<double> buf((size_t)NPAD * NPAD);
+  for (int64_t i = 0; i < ncells; ++i) {
+    HIPCHK(c, hipMemcpy(buf.data(), c->Hp + (int64_t)cells[i] * NPAD * NPAD, buf.size() * sizeof(double),
+                        hipMemcpyDeviceToHost));
+    for (int a = 0; a < npc; ++a)
+      std::memcpy(out + (i * npc + a) * npc, buf.data() + (size_t)a * NPAD, npc * sizeof(double));
+  }
+  return CF_OK;
 }
 
 cf_status chebfilter_residual_norms(cf_ctx *c, const double *Z, int64_t ldz, int64_t N,

@@ -305,6 +305,14 @@ hipError_t launch_sub_colscale(hipStream_t s, int64_t n, int N, double *R, int64
 hipError_t launch_coldot(hipStream_t s, int64_t n, int N, const double *A, int64_t lda,
                          const double *B, int64_t ldb, double *part, int nchunks, double *out);
 
+// ---- element blocks of the plain cells (cf_assemble.hip)
+// Hp[cells[i]] = K + Btab^T diag(wq .* V[i][:]) Btab over nq points (Btab
+// [(nq + 3) & ~3][NPAD] zero-padded, K [NPAD][NPAD] symmetric); the result is
+// written exactly symmetric.  One workgroup of 256 threads per cell.
+hipError_t launch_assemble_cells(hipStream_t s, const double *Btab, const double *wq,
+                                 const double *K, const int *cells, int ncells, const double *V,
+                                 int64_t ldv, int nq, double *Hp);
+
 // ---- data-movement helpers (cf_dense.hip)
 hipError_t launch_sub(hipStream_t s, int64_t n, const double *A, const double *B, double *C);
 hipError_t launch_transpose(hipStream_t s, int N, const double *In, int64_t ldi, double *Out);

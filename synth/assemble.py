@@ -67,6 +67,24 @@ def shape_at(p: int, h: float, lo: np.ndarray, pts: np.ndarray, need_grad: bool)
     return N, G
 
 
+def plain_tables(prob, ng: int = 6):
+    """Reference tables of the plain rule of a generated problem: B [nq, npc]
+    shape values at the ng^3 Gauss points (the same in every cell), w [nq]
+    weights times the cell volume, K [npc, npc] the kinetic block, and the
+    points in the unit cube [nq, 3] (x fastest)."""
+    mesh = prob.meta["mesh"]
+    ref, wref = unit_cube_rule(ng)
+    B, _ = shape_at(mesh.p, 2.0, np.array([-1.0, -1.0, -1.0]), 2.0 * ref - 1.0, need_grad=False)
+    return B, wref * mesh.h ** 3, reference_kinetic(mesh.p, mesh.h), ref
+
+
+def plain_points(prob, cells, ng: int = 6) -> np.ndarray:
+    """Physical Gauss points [len(cells), nq, 3] of the listed cells."""
+    mesh = prob.meta["mesh"]
+    ref, _ = unit_cube_rule(ng)
+    return mesh.cell_lo()[np.asarray(cells)][:, None, :] + mesh.h * ref[None]
+
+
 def gll_lumped_diag(mesh: Mesh) -> np.ndarray:
     _, w = gll_rule(mesh.p)
     we = (0.5 * mesh.h) ** 3 * _tensor3(np.diag(w), np.diag(w), np.diag(w)).diagonal()

@@ -73,15 +73,16 @@ def hydrogen(nc: int = 8, length: float = 20.0, p: int = 4, r_c: float = 6.0,
     if enrich:
         enr = EnrichmentSet(centers=np.zeros((1, 3)),
                             shells=[Radial("h1s"), Radial("h2s")], r_c=r_c)
-    prob = assemble(mesh, coulomb_potential([0.0, 0.0, 0.0]), enr, **kw)
-    prob.meta.update(kind="hydrogen", r_c=r_c, mesh=mesh, enr=enr)
+    V = coulomb_potential([0.0, 0.0, 0.0])
+    prob = assemble(mesh, V, enr, **kw)
+    prob.meta.update(kind="hydrogen", r_c=r_c, mesh=mesh, enr=enr, potential=V)
     return prob
 
 
 def box(nc: int = 2, length: float = 2.0, p: int = 4, **kw) -> Problem:
     mesh = build_mesh(p, nc, -0.5 * length, length)
     prob = assemble(mesh, zero_potential, None, **kw)
-    prob.meta.update(kind="box", mesh=mesh)
+    prob.meta.update(kind="box", mesh=mesh, potential=zero_potential)
     return prob
 
 
@@ -103,9 +104,10 @@ def si_cluster(n_atoms: int = 30, length: float = 48.0, nc: int = 24, p: int = 4
     shells = si_shells(rng)
     mesh = build_mesh(p, nc, -0.5 * length, length)
     enr = EnrichmentSet(centers=sites, shells=shells, r_c=r_c) if enrich else None
-    prob = assemble(mesh, softened_potential(sites), enr, **kw)
+    V = softened_potential(sites)
+    prob = assemble(mesh, V, enr, **kw)
     prob.meta.update(kind="si", sites=sites, shells=shells, r_c=r_c, mesh=mesh, enr=enr,
-                     seed=seed, rng=rng)
+                     seed=seed, rng=rng, potential=V)
     return prob
 
 

@@ -39,6 +39,10 @@ WORKLOADS = {
     "si30-classical": ("config2_classical", 260, 40, 210),
     # 256 independent Si clusters of 1-8 atoms (N 16-64 each), batched form
     "si-batch256": ("batch_workload", None, 40, None),
+    # the 280-atom cluster (48^3 cells, n = 6,970,391) at one GPU's column share:
+    # the whole operator with 300 of the block's vectors (280 wanted), m = 50,
+    # precision forms against an FP64 run
+    "si280-48c": ("config3", 300, 50, 280),
 }
 
 
@@ -137,6 +141,145 @@ def assembly_timing(ctx, prob, reps=5):
             "flops_credited": "2*36*256*nq per cell (the 36 upper 16x16 tiles)",
             "peak_tflops_fp64_mfma": PEAK_FP64_MFMA / 1e12,
             "hbm_write_gb": len(cells) * 128 * 128 * 8 / 1e9}
+
+
+def run_si280(args):
+    """The 280-atom precision-form workload at one GPU's column share: the
+    operator of the whole cluster (the plain cells' potential term assembled
+    on the device), 300 vectors from the atomic-orbital start, m = 50; the
+    same SCF steps (Lanczos bound, filter, Rayleigh-Ritz) from the same start
+    in FP64, FP32 and BF16 filter arithmetic, each followed by one FP64
+    cleanup step; Ritz values of the reduced forms compared with the FP64
+    run's at every step."""
+    import numpy as np
+    import scipy.linalg as sla
+    import torch
+
+    from paper_1610_02121_amd import Context
+    from synth import configs
+    from synth.assemble import plain_points, plain_tables, potential_at_points
+    _, N, m, wanted = WORKLOADS["si280-48c"]
+    t0 = time.time()
+    log("generating the 280-atom cluster (enriched cells on the host)")
+    prob = configs.config3(seed=args.seed, progress=log)
+    log(f"generated n={prob.n} n_e={prob.n_e} cells={prob.n_cells} enriched cells="
+        f"{prob.meta['quad']['enriched_cells']} coupling rows={len(prob.enr_idx)} in "
+        f"{time.time() - t0:.0f}s")
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    t1 = time.time()
+    ctx = Context(prob, max_cols=N)
+    log(f"context ready ({time.time() - t1:.0f}s)")
+    B, w, K, _ = plain_tables(prob)
+    ep = np.asarray(prob.enr_ptr)
+    cells = np.nonzero(ep[1:] == ep[:-1])[0].astype(np.int32)
+    t1 = time.time()
+    Vq = potential_at_points(prob.meta["potential"], plain_points(prob, cells).reshape(-1, 3))
+    Vd = torch.tensor(Vq.reshape(len(cells), -1), dtype=torch.float64, device=dev)
+    del Vq
+    log(f"potential at {Vd.numel()} Gauss points of {len(cells)} plain cells ({time.time() - t1:.0f}s)")
+    ctx.assembly_tables(B, w, K)
+    torch.cuda.synchronize()
+    ta = time.perf_counter()
+    ctx.assemble_cells(cells, Vd)
+    torch.cuda.synchronize()
+    t_asm = time.perf_counter() - ta
+    del Vd
+    _, Vee = sla.eigh(prob.H_ee, prob.M_ee)
+    X0 = torch.zeros((prob.n, N), dtype=torch.float64, device=dev)
+    X0[prob.n_h:, :] = torch.tensor(Vee[:, :N], dtype=torch.float64, device=dev)
+    v0 = torch.tensor(np.random.default_rng(args.seed + 1).standard_normal(prob.n),
+                      dtype=torch.float64, device=dev)
+    X = torch.empty_like(X0)
+    Y = torch.empty_like(X0)
+    def capped_passes(theta, a, b):
+        """Passes of the largest degree whose amplification ratio across the
+        wanted window, T_d(|t(theta_1)|) / T_d(|t(theta_w)|), stays below
+        1e4 (a ratio FP32 resolves), adding up to at least degree m."""
+        t1 = abs((2.0 * theta[0] - a - b) / (b - a))
+        tw = abs((2.0 * theta[wanted - 1] - a - b) / (b - a))
+        g = np.arccosh(max(t1, 1.0)) - np.arccosh(max(tw, 1.0))
+        d = m if g <= 0.0 else int(max(4, min(m, np.floor(np.log(1e4) / g))))
+        return d, -(-m // d)
+
+    runs = {}
+    for form in ("fp64", "fp32", "bf16", "fp32-capped", "bf16-capped"):
+        # `steps` steps in the form's filter arithmetic, then one FP64 cleanup step
+        prec = form.split("-")[0]
+        X.copy_(X0)
+        theta = ctx.rayleigh_ritz(X)
+        rec = {"theta": [], "t_bounds": 0.0, "t_filter": 0.0, "t_rr": 0.0, "t_cleanup": 0.0,
+               "passes": []}
+        for st in range(args.steps + 1):
+            p_st = prec if st < args.steps else "fp64"
+            torch.cuda.synchronize()
+            s0 = time.perf_counter()
+            _, b = ctx.lanczos_bounds(v0, 10)
+            s1 = time.perf_counter()
+            a = float(theta[-1])
+            if form.endswith("capped") and st < args.steps:
+                d, npass = capped_passes(theta, a, b)
+                rec["passes"].append([d, npass])
+                ctx.filter_multipass(X, d, npass, a, b, Y=Y, prec=p_st)
+            else:
+                ctx.filter(X, m, a, b, Y=Y, prec=p_st)
+            torch.cuda.synchronize()
+            s2 = time.perf_counter()
+            theta = ctx.rayleigh_ritz(Y)
+            s3 = time.perf_counter()
+            X, Y = Y, X
+            rec["theta"].append(theta.copy())
+            if st < args.steps:
+                rec["t_bounds"] += s1 - s0
+                rec["t_filter"] += s2 - s1
+                rec["t_rr"] += s3 - s2
+            else:
+                rec["t_cleanup"] = s3 - s0
+            log(f"{form} step {st + 1}/{args.steps + 1} ({p_st}): filter {s2 - s1:.2f}s "
+                f"theta[0]={theta[0]:.6f} theta[{wanted - 1}]={theta[wanted - 1]:.6f}")
+        res = ctx.residual_norms(X, theta)
+        rec["res_max_wanted"] = float(np.max(res[:wanted]))
+        runs[form] = rec
+    ref = runs["fp64"]
+    work = prob.n * N * m
+    out = {
+        "metric": "Chebyshev-filter DOF*vectors/s (per degree, whole SCF step) and SCF-step time, "
+                  "FP64 vs mixed, Ritz error against the FP64 run",
+        "value": work / ((ref["t_bounds"] + ref["t_filter"] + ref["t_rr"]) / args.steps),
+        "unit": "DOF*vectors*degree/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": 0, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "si280-48c", "n_dof": prob.n, "n_enrich": prob.n_e,
+                   "cells": prob.n_cells, "enriched_cells": prob.meta["quad"]["enriched_cells"],
+                   "degree_p": prob.p, "vectors": N, "wanted": wanted, "cheb_degree": m,
+                   "share": "one GPU's column share of the block (300 of its vectors; "
+                            "the operator is whole)"},
+        "plain_cell_assembly_ms": 1e3 * t_asm,
+        "forms": {},
+    }
+    for prec, rec in runs.items():
+        step_ms = 1e3 * (rec["t_bounds"] + rec["t_filter"] + rec["t_rr"]) / args.steps
+        f = {"ms_per_step": step_ms,
+             "phases_ms": {"bounds": 1e3 * rec["t_bounds"] / args.steps,
+                           "filter": 1e3 * rec["t_filter"] / args.steps,
+                           "cholqr_rr": 1e3 * rec["t_rr"] / args.steps},
+             "filter_dof_vec_deg_per_s": work / (rec["t_filter"] / args.steps),
+             "fp64_cleanup_step_ms": 1e3 * rec["t_cleanup"],
+             "max_residual_Minv_wanted_after_cleanup": rec["res_max_wanted"],
+             "theta_min": float(rec["theta"][-1][0]),
+             "theta_wanted_max": float(rec["theta"][-1][wanted - 1])}
+        if rec["passes"]:
+            f["passes_per_step"] = rec["passes"]
+        if prec != "fp64":
+            # per step, the last entry after the FP64 cleanup step
+            f["ritz_err_vs_fp64_per_step"] = [
+                float(np.abs(a[:wanted] - r[:wanted]).max())
+                for a, r in zip(rec["theta"], ref["theta"])]
+            f["filter_speedup_vs_fp64"] = ref["t_filter"] / rec["t_filter"]
+        out["forms"][prec] = f
+    out["ms_per_step"] = out["forms"]["fp64"]["ms_per_step"]
+    print(json.dumps(out), flush=True)
+    ctx.close()
 
 
 def precision_forms(ctx, X, Y, m, a, b, reps=3):
@@ -505,6 +648,9 @@ def main():
         return
     if name == "si-batch256":
         run_batch(args)
+        return
+    if name == "si280-48c":
+        run_si280(args)
         return
     _, N, m, wanted = WORKLOADS[name]
     t0 = time.time()

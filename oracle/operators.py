@@ -58,12 +58,15 @@ def assemble_global(prob, which: str) -> sp.csr_matrix:
 class Operators:
     """H^E, M^E of one problem with the two ways of applying (M^E)^-1."""
 
-    def __init__(self, prob):
+    def __init__(self, prob, which=("H", "M"), M=None):
+        """which: the global matrices to assemble (("M",) skips H^E, whose
+        element entries are the bulk of the memory on large problems); M: an
+        already assembled global M^E."""
         self.prob = prob
         self.n_h, self.n_e = prob.n_h, prob.n_e
         self.n = self.n_h + self.n_e
-        self.H = assemble_global(prob, "H")
-        self.M = assemble_global(prob, "M")
+        self.H = assemble_global(prob, "H") if "H" in which else None
+        self.M = M if M is not None else assemble_global(prob, "M")
         self._lu = None
         self._blk = None
 
@@ -121,3 +124,43 @@ class Operators:
 
     def dense(self) -> tuple[np.ndarray, np.ndarray]:
         return self.H.toarray(), self.M.toarray()
+
+
+def sampled_rows(prob, rows: np.ndarray, X: np.ndarray, which: str, H_cc=None) -> np.ndarray:
+    """Rows `rows` of H^E X (which="H") or M^E X (which="M") summed straight
+    from the element blocks (Eq. H2x2 / M2x2, HBlocks / MBlocks), without the
+    global matrices: for a classical DOF i, the cells' rows of H^cc_e (or the
+    lumped D_i) at i's local positions, plus H^ec_e^T (M^ec_e^T) X_e of the
+    enriched cells that contain i; for an enrichment DOF alpha, every cell
+    row of H^ec (M^ec) that belongs to alpha, plus row alpha of H^ee (M^ee).
+    H_cc overrides the problem's classical blocks for the cells it lists
+    ({cell: block}); used where the global operator is too large to form."""
+    cd = np.asarray(prob.cell_dof)
+    ep, ei = np.asarray(prob.enr_ptr), np.asarray(prob.enr_idx)
+    n_h = cd.max() + 1 if prob.n_e == 0 else prob.n_h
+    Xe = X[n_h:]
+    cpl = np.asarray(prob.H_ec if which == "H" else prob.M_ec)
+    ee = np.asarray(prob.H_ee if which == "H" else prob.M_ee)
+    out = np.zeros((len(rows), X.shape[1]))
+    for k, i in enumerate(rows):
+        if i < n_h:
+            if which == "M":
+                out[k] = prob.M_cc_diag[i] * X[i]
+            for e, a in zip(*np.nonzero(cd == i)):
+                d = cd[e]
+                ok = d >= 0
+                if which == "H":
+                    blk = H_cc[e] if (H_cc is not None and e in H_cc) else prob.H_cc[e]
+                    out[k] += blk[a, ok] @ X[d[ok]]
+                r0, r1 = ep[e], ep[e + 1]
+                if r1 > r0:
+                    out[k] += cpl[r0:r1, a] @ Xe[ei[r0:r1]]
+        else:
+            al = i - n_h
+            for r in np.nonzero(ei == al)[0]:
+                e = np.searchsorted(ep, r, side="right") - 1
+                d = cd[e]
+                ok = d >= 0
+                out[k] += cpl[r, ok] @ X[d[ok]]
+            out[k] += ee[al] @ Xe
+    return out

@@ -85,6 +85,32 @@ def plain_points(prob, cells, ng: int = 6) -> np.ndarray:
     return mesh.cell_lo()[np.asarray(cells)][:, None, :] + mesh.h * ref[None]
 
 
+_POT: dict = {}
+
+
+def _pot_chunk(bounds):
+    a, b = bounds
+    return _POT["V"](_POT["pts"][a:b])
+
+
+def potential_at_points(V, pts: np.ndarray, nproc: int | None = None,
+                        chunk: int = 1 << 20) -> np.ndarray:
+    """V at pts [Q, 3], in chunks over forked workers (V may be a closure;
+    the workers inherit it).  Values do not depend on the chunking."""
+    import multiprocessing as mp
+    bounds = [(a, min(a + chunk, len(pts))) for a in range(0, len(pts), chunk)]
+    nw = min(nproc or _workers(), len(bounds))
+    if nw <= 1:
+        return V(pts)
+    _POT.update(V=V, pts=pts)
+    try:
+        with mp.get_context("fork").Pool(nw) as pool:
+            parts = pool.map(_pot_chunk, bounds)
+    finally:
+        _POT.clear()
+    return np.concatenate(parts)
+
+
 def gll_lumped_diag(mesh: Mesh) -> np.ndarray:
     _, w = gll_rule(mesh.p)
     we = (0.5 * mesh.h) ** 3 * _tensor3(np.diag(w), np.diag(w), np.diag(w)).diagonal()
@@ -135,8 +161,13 @@ def _enriched_chunk(cells):
     lo_all, cell_atoms, enr_ptr, enr_idx = _W["lo_all"], _W["cell_atoms"], _W["enr_ptr"], _W["enr_idx"]
     n_e, tau = _W["n_e"], _W["tau"]
     Hcc, Hec, Mec = [], [], []
-    Hee = np.zeros((n_e, n_e))
-    Mee = np.zeros((n_e, n_e))
+    # the chunk's partial H_ee / M_ee on the enrichment indices it touches
+    # (the other entries of the partial are zero)
+    used = np.unique(np.concatenate([enr_idx[enr_ptr[e]:enr_ptr[e + 1]] for e in cells]))
+    pos = np.full(n_e, -1, dtype=np.int64)
+    pos[used] = np.arange(used.size)
+    Hee = np.zeros((used.size, used.size))
+    Mee = np.zeros((used.size, used.size))
     stats = np.zeros(3)
     with threadpool_limits(_W["blas_threads"]):
         for e in cells:
@@ -161,11 +192,11 @@ def _enriched_chunk(cells):
             EgwT = [(g * w[:, None]).T for g in Egd]
             Hec.append(0.5 * sum(EgwT[d] @ G[d] for d in range(3)) + (Ev * wV[:, None]).T @ N)
             Mec.append(EwT @ N)
-            idx = enr_idx[enr_ptr[e]:enr_ptr[e + 1]]
+            idx = pos[enr_idx[enr_ptr[e]:enr_ptr[e + 1]]]
             kin_ee = 0.5 * sum(EgwT[d] @ Egd[d] for d in range(3))
             Hee[np.ix_(idx, idx)] += kin_ee + (Ev * wV[:, None]).T @ Ev
             Mee[np.ix_(idx, idx)] += EwT @ Ev
-    return Hcc, Hec, Mec, Hee, Mee, stats
+    return Hcc, Hec, Mec, (used, Hee), (used, Mee), stats
 
 
 def _workers() -> int:
@@ -176,14 +207,19 @@ def _workers() -> int:
 
 def assemble(mesh: Mesh, potential, enr: EnrichmentSet | None, ng: int = 6,
              tol_rel: float = 1e-10, tol_abs: float = 1e-14, max_depth: int = 10,
-             chunk: int = 16, workers: int | None = None, verbose: bool = False) -> Problem:
+             chunk: int = 16, workers: int | None = None, verbose: bool = False,
+             plain_blocks: bool = True, progress=None) -> Problem:
     """Element blocks of the problem.
 
     The adaptive-quadrature tolerance of trial function nu is
     tau_nu = max(tol_abs, tol_rel * S_nu), S_nu = its integral over all
     enriched cells by the plain rule.  Enriched cells are integrated in fixed
     chunks (results combined in chunk order, so the output does not depend on
-    the number of worker processes).
+    the number of worker processes).  With plain_blocks=False the cells
+    without enrichment functions get the kinetic block K only (their
+    potential term is left to a device assembly from the potential at their
+    Gauss points; meta["plain_blocks"] records it).  progress(msg), if given,
+    is called about every 30 s while the enriched cells are integrated.
     """
     t0 = time.time()
     p, h, E, npc = mesh.p, mesh.h, mesh.n_cells, mesh.npc
@@ -224,6 +260,9 @@ def assemble(mesh: Mesh, potential, enr: EnrichmentSet | None, ng: int = 6,
     Bref, _ = shape_at(p, 2.0, np.array([-1.0, -1.0, -1.0]), 2.0 * ref - 1.0, need_grad=False)
     plain = np.nonzero(counts == 0)[0]
     jac = h ** 3
+    if not plain_blocks:
+        H_cc[plain] = K[None]
+        plain = plain[:0]
     for s in range(0, plain.size, 256):
         cells = plain[s:s + 256]
         pts = lo_all[cells][:, None, :] + h * ref[None]
@@ -247,33 +286,44 @@ def assemble(mesh: Mesh, potential, enr: EnrichmentSet | None, ng: int = 6,
             with ctx.Pool(nw) as pool:
                 S = np.sum(pool.map(_plain_integrals, chunks), axis=0)
                 _W["tau"] = np.maximum(tol_abs, tol_rel * S)
-            with ctx.Pool(nw) as pool:
-                results = pool.map(_enriched_chunk, chunks)
+            pool = ctx.Pool(nw)
+            results = pool.imap(_enriched_chunk, chunks)
         else:
+            pool = None
             S = np.sum([_plain_integrals(c) for c in chunks], axis=0)
             _W["tau"] = np.maximum(tol_abs, tol_rel * S)
-            results = [_enriched_chunk(c) for c in chunks]
-        for cells, (hcc, hec, mec, hee, mee, st) in zip(chunks, results):
+            results = (_enriched_chunk(c) for c in chunks)
+        t_last = time.time()
+        for k, (cells, (hcc, hec, mec, hee, mee, st)) in enumerate(zip(chunks, results)):
+            if progress and time.time() - t_last > 30.0:
+                progress(f"enriched cells: chunk {k + 1}/{len(chunks)} ({time.time() - t1:.0f}s)")
+                t_last = time.time()
             for i, e in enumerate(cells):
                 H_cc[e] = hcc[i]
                 H_ec[enr_ptr[e]:enr_ptr[e + 1]] = hec[i]
                 M_ec[enr_ptr[e]:enr_ptr[e + 1]] = mec[i]
-            H_ee += hee
-            M_ee += mee
+            (hu, hb), (mu, mb) = hee, mee
+            H_ee[np.ix_(hu, hu)] += hb
+            M_ee[np.ix_(mu, mu)] += mb
             stats["leaves"] += int(st[0])
             stats["points"] += int(st[1])
             stats["max_leaves"] = max(stats["max_leaves"], int(st[2]))
+        if pool is not None:
+            pool.close()
+            pool.join()
         stats["enriched_cells"] = int(ecells.size)
         stats["tau"] = [float(x) for x in _W["tau"]]
         _W.clear()
-    H_cc += np.swapaxes(H_cc, 1, 2)
-    H_cc *= 0.5
+    for c0 in range(0, E, 4096):           # symmetrise in slices (bounded temporaries)
+        blk = H_cc[c0:c0 + 4096]
+        blk[...] = (blk + np.swapaxes(blk, 1, 2)) * 0.5
     H_ee = 0.5 * (H_ee + H_ee.T)
     M_ee = 0.5 * (M_ee + M_ee.T)
     t2 = time.time()
     stats.update(t_plain=t1 - t0, t_enriched=t2 - t1)
     if verbose:
         print(f"[assemble] E={E} n_h={mesh.n_h} n_e={n_e} nnz={nnz} {stats}", flush=True)
-    meta = {"h": h, "nc": mesh.nc, "lo": mesh.lo, "length": mesh.length, "quad": stats}
+    meta = {"h": h, "nc": mesh.nc, "lo": mesh.lo, "length": mesh.length, "quad": stats,
+            "plain_blocks": plain_blocks}
     return Problem(p=p, cell_dof=mesh.cell_dof, H_cc=H_cc, M_cc_diag=D, enr_ptr=enr_ptr,
                    enr_idx=enr_idx, H_ec=H_ec, M_ec=M_ec, H_ee=H_ee, M_ee=M_ee, meta=meta)

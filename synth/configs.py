@@ -153,6 +153,16 @@ WORKLOADS = {
 }
 
 
+def config3(seed: int = 0, plain_blocks: bool = False, **kw) -> Problem:
+    """The 280-atom Si cluster: 80 Bohr cube, 48^3 degree-4 cells (n_h =
+    6,967,871), 9 enrichments per atom (n_e = 2520).  By default the blocks of
+    the cells without enrichment functions hold only the kinetic part: their
+    potential term is assembled on the device (chebfilter_assemble_cells)
+    from the potential at their Gauss points."""
+    return si_cluster(n_atoms=280, length=80.0, nc=48, p=4, r_c=8.0, seed=seed,
+                      plain_blocks=plain_blocks, **kw)
+
+
 def batch_cluster(n_atoms: int, seed: int = 0) -> Problem:
     """One problem of the batched workload: an n_atoms Si cluster (1..8) in a
     cube of half-width R_cluster + 12 Bohr with 6 + round(6 (n_atoms - 1) / 7)

@@ -1,0 +1,177 @@
+"""Parity at the full size of the 280-atom Si workload (48^3 cells,
+n = 6,970,391, n_e = 2520) in the launch configuration the benchmark times
+(N = 300, one GPU's column share of the block), with the plain cells' blocks
+assembled on the device.
+
+The global oracle operator does not fit (about 1.7e9 element entries), so
+outputs are checked row by row from the element blocks
+(oracle.operators.sampled_rows, pinned in test_oracle_pins) and through
+identities that hold at any size:
+* device-assembled blocks of sampled plain cells against the oracle's
+  quadrature sum (bound as in test_gpu_assemble);
+* H X on N = 300 columns: sampled classical and enrichment rows;
+* (M^E)^-1 X on 8 columns: every row against the oracle's block-wise
+  inverse of Sec. IV.D (it needs only the global M^E, which is small).  Both
+  sides form the Schur complement S = M^ee - M^ec D^-1 M^ec^T, a difference
+  of nearly equal terms here (the enrichments of neighbouring atoms overlap
+  the classical space), each with its own rounding of long sums; the error
+  bound is kappa(S) ||dS|| / ||S|| with ||dS|| ~ u || |M^ee| + |M^ec| D^-1
+  |M^ec|^T || sqrt(k) for sums of up to k terms (rounding of a k-term sum
+  grows like sqrt(k) u), so the test allows 10 u kappa(S) rho sqrt(k) max|Z|,
+  rho the ratio of that norm to ||S|| (all computed by the oracle:
+  kappa(S) = 2.7e5, rho = 28; measured error 6.9e-9);
+* filter(N = 300): on 8 columns, M (Y_m + Y_{m-2}) = 2 e H Y_{m-1} - 2 c M Y_{m-1}
+  on sampled rows (the three-term recurrence multiplied by M), within the
+  same bound times m of the terms' scale (measured ~1e-13).
+
+The host generation of the enriched cells takes several minutes, so the
+module runs only with CF_FULLSIZE_280=1 in the environment.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from oracle.assembly import plain_cell_block
+from oracle.operators import Operators, sampled_rows
+
+pytestmark = [pytest.mark.gpu, pytest.mark.timeout(1800),
+              pytest.mark.skipif(os.environ.get("CF_FULLSIZE_280") != "1",
+                                 reason="needs several minutes of host generation; "
+                                        "set CF_FULLSIZE_280=1")]
+
+torch = pytest.importorskip("torch")
+U = 2.0 ** -53
+N = 300
+
+
+@pytest.fixture(scope="module")
+def full():
+    from paper_1610_02121_amd import Context
+    from synth import configs
+    from synth.assemble import plain_points, plain_tables, potential_at_points
+    print("[fullsize280] generating the 280-atom workload", flush=True)
+    prob = configs.config3(progress=lambda m: print("[fullsize280]", m, flush=True))
+    print(f"[fullsize280] n={prob.n}; context", flush=True)
+    ctx = Context(prob, max_cols=N)
+    B, w, K, _ = plain_tables(prob)
+    ep = np.asarray(prob.enr_ptr)
+    cells = np.nonzero(ep[1:] == ep[:-1])[0].astype(np.int32)
+    V = potential_at_points(prob.meta["potential"], plain_points(prob, cells).reshape(-1, 3))
+    V = V.reshape(len(cells), -1)
+    ctx.assembly_tables(B, w, K)
+    ctx.assemble_cells(cells, torch.tensor(V, dtype=torch.float64, device="cuda"))
+    torch.cuda.synchronize()
+    print("[fullsize280] plain cells assembled on the device; oracle M^E and S", flush=True)
+    from oracle.operators import assemble_global
+    M = assemble_global(prob, "M")
+    print("[fullsize280] oracle M^E assembled; Schur complement", flush=True)
+    ops = Operators(prob, which=("M",), M=M)
+    S = ops.schur()
+    ev = np.linalg.eigvalsh(S)
+    kappa_S = ev[-1] / ev[0]
+    # cancellation in forming S: the norm of the sum of the terms' magnitudes
+    # over the norm of S (rounding in either side's S is ~u times the former)
+    import scipy.sparse as sps
+    n_h = prob.n_h
+    Mec = abs(M[n_h:, :n_h]).tocsr()
+    T = abs(M[n_h:, n_h:]).toarray() + (Mec @ sps.diags(1.0 / np.asarray(prob.M_cc_diag))
+                                         @ Mec.T).toarray()
+    rho = np.linalg.eigvalsh(0.5 * (T + T.T))[-1] / ev[-1]
+    k_max = int(np.diff(Mec.indptr).max())        # longest sum in an entry of M^ec D^-1 M^ec^T
+    tol = 10 * U * kappa_S * rho * np.sqrt(k_max)
+    print(f"[fullsize280] kappa(S) = {kappa_S:.3e}, cancellation rho = {rho:.3e}, "
+          f"k_max = {k_max}, 10 u kappa rho sqrt(k) = {tol:.2e}", flush=True)
+    yield {"prob": prob, "ctx": ctx, "B": B, "w": w, "K": K, "cells": cells, "V": V,
+           "ops": ops, "tol": tol}
+    ctx.close()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def sample_rows(prob, seed, n_cl=160, n_en=24):
+    rng = np.random.default_rng(seed)
+    cd = np.asarray(prob.cell_dof)
+    ep = np.asarray(prob.enr_ptr)
+    enr_cells = np.nonzero(ep[1:] > ep[:-1])[0]
+    near = cd[rng.choice(enr_cells, n_cl // 2)][:, 62]          # cell centres inside supports
+    near = near[near >= 0]
+    return np.unique(np.concatenate([near, rng.choice(prob.n_h, n_cl // 2, replace=False),
+                                     prob.n_h + rng.choice(prob.n_e, n_en, replace=False)]))
+
+
+def oracle_blocks(full, rows):
+    """Oracle plain blocks of the plain cells that contain the sampled rows."""
+    prob = full["prob"]
+    cd = np.asarray(prob.cell_dof)
+    pos = {int(e): k for k, e in enumerate(full["cells"])}
+    need = np.unique(np.nonzero(np.isin(cd, rows[rows < prob.n_h]))[0])
+    return {int(e): plain_cell_block(full["K"], full["B"], full["w"], full["V"][pos[int(e)]])
+            for e in need if int(e) in pos}
+
+
+def test_device_blocks_sampled_cells(full):
+    print("[fullsize280] assembled blocks", flush=True)
+    sel = full["cells"][np.random.default_rng(40).choice(len(full["cells"]), 24, replace=False)]
+    pos = {int(e): k for k, e in enumerate(full["cells"])}
+    H = full["ctx"].get_H_cc(sel)
+    B, w, K = full["B"], full["w"], full["K"]
+    for i, e in enumerate(sel):
+        Vq = full["V"][pos[int(e)]]
+        Ho = plain_cell_block(K, B, w, Vq)
+        bound = np.abs(K) + (np.abs(B) * np.abs(w * Vq)[:, None]).T @ np.abs(B)
+        assert np.all(np.abs(H[i] - Ho) <= 2.0 * len(w) * U * bound), e
+
+
+def test_apply_H_sampled_rows(full):
+    prob, ctx = full["prob"], full["ctx"]
+    print("[fullsize280] apply_H N=300", flush=True)
+    Xd = torch.randn((prob.n, N), dtype=torch.float64, device="cuda",
+                     generator=torch.Generator(device="cuda").manual_seed(41))
+    Y = ctx.apply_H(Xd)
+    rows = sample_rows(prob, 42)
+    X = host(Xd)
+    Yo = sampled_rows(prob, rows, X, "H", H_cc=oracle_blocks(full, rows))
+    Ys = host(Y[torch.tensor(rows, device="cuda")])
+    assert np.abs(Ys - Yo).max() < 1e-12 * np.abs(Yo).max()
+
+
+def test_apply_Sinv_block_inverse(full):
+    prob, ctx = full["prob"], full["ctx"]
+    print("[fullsize280] apply_Sinv N=8", flush=True)
+    X = np.random.default_rng(43).standard_normal((prob.n, 8))
+    Z = host(ctx.apply_Sinv(torch.tensor(X, device="cuda")))
+    Zo = full["ops"].block_inverse(X)
+    err = np.abs(Z - Zo).max() / np.abs(Zo).max()
+    print(f"[fullsize280] Sinv rel err {err:.2e} (bound {full['tol']:.2e})", flush=True)
+    assert err < full["tol"]
+    rows = sample_rows(prob, 44)
+    assert np.abs(sampled_rows(prob, rows, X, "M") - full["ops"].apply_M(X)[rows]).max() \
+        < 1e-12 * np.abs(full["ops"].apply_M(X)[rows]).max()
+
+
+def test_filter_three_term_identity(full):
+    prob, ctx = full["prob"], full["ctx"]
+    print("[fullsize280] filter N=300, m=1..4", flush=True)
+    Xd = torch.randn((prob.n, N), dtype=torch.float64, device="cuda",
+                     generator=torch.Generator(device="cuda").manual_seed(45))
+    a, b = -60.0, 600.0
+    e, c = 2.0 / (b - a), (a + b) / (b - a)
+    cols = torch.tensor([0, 17, 63, 64, 150, 255, 298, 299], device="cuda")
+    Ys = {0: host(Xd[:, cols])}
+    for m in (1, 2, 3, 4):
+        Ys[m] = host(ctx.filter(Xd, m, a, b)[:, cols])
+    rows = sample_rows(prob, 46, n_cl=80, n_en=12)
+    blocks = oracle_blocks(full, rows)
+    for m in (2, 3, 4):
+        lhs = sampled_rows(prob, rows, Ys[m] + Ys[m - 2], "M")
+        HY = sampled_rows(prob, rows, Ys[m - 1], "H", H_cc=blocks)
+        MY = sampled_rows(prob, rows, Ys[m - 1], "M")
+        rhs = 2.0 * e * HY - 2.0 * c * MY
+        scale = max(np.abs(lhs).max(), np.abs(2.0 * e * HY).max())
+        print(f"[fullsize280] m={m}: identity residual {np.abs(lhs - rhs).max() / scale:.2e}",
+              flush=True)
+        assert np.abs(lhs - rhs).max() < full["tol"] * m * scale, m

@@ -241,3 +241,48 @@ def test_chefsi_converges_to_dense_spectrum(tiny_enriched):
     assert np.max(np.abs(th[:wanted] - lam[:wanted])) < 1e-10
     _, V = sla.eigh(H, M)
     assert subspace_angle(X[:, :wanted], V[:, :wanted], M) < 1e-6
+
+
+def test_sampled_rows_match_global_operators(si_small):
+    """The per-row element sums (used where the global operator is too large)
+    against the assembled global H^E and M^E, on classical rows inside,
+    touching and outside the enriched region, and on enrichment rows."""
+    from oracle.operators import Operators, sampled_rows
+    prob = si_small
+    ops = Operators(prob)
+    rng = np.random.default_rng(31)
+    X = rng.standard_normal((ops.n, 3))
+    rows = np.concatenate([rng.choice(prob.n_h, 40, replace=False),
+                           prob.n_h + rng.choice(prob.n_e, 10, replace=False)])
+    for which, A in (("H", ops.H), ("M", ops.M)):
+        Yo = np.asarray(A[rows] @ X)
+        Ys = sampled_rows(prob, rows, X, which)
+        assert np.abs(Ys - Yo).max() < 1e-12 * np.abs(Yo).max(), which
+
+
+def test_sampled_rows_constant_potential_row_sums(si_small):
+    """With the plain cells' blocks rebuilt for V = c (oracle assembly), a
+    classical row of H applied to the constant vector, for a DOF whose cells
+    are all plain and away from the boundary, is c times the lumped GLL
+    weight of the DOF (the kinetic part annihilates constants; the row sum of
+    the consistent mass is the integral of the shape function, which the GLL
+    rule integrates exactly)."""
+    from oracle.assembly import plain_cell_block
+    from oracle.operators import sampled_rows
+    from synth.assemble import plain_tables
+    prob = si_small
+    B, w, K, _ = plain_tables(prob)
+    cd = np.asarray(prob.cell_dof)
+    ep = np.asarray(prob.enr_ptr)
+    plain = ep[1:] == ep[:-1]
+    c = -0.7
+    blocks = {e: plain_cell_block(K, B, w, np.full(len(w), c)) for e in np.nonzero(plain)[0]}
+    good = [i for i in range(prob.n_h)
+            if all(plain[e] and (cd[e] >= 0).all() for e in np.nonzero((cd == i).any(1))[0])]
+    assert len(good) > 5
+    rows = np.array(good[:: max(1, len(good) // 12)])
+    X = np.zeros((prob.n, 1))
+    X[:prob.n_h] = 1.0
+    Y = sampled_rows(prob, rows, X, "H", H_cc=blocks)[:, 0]
+    D = np.asarray(prob.M_cc_diag)[rows]
+    assert np.abs(Y - c * D).max() < 1e-12 * abs(c) * D.max()

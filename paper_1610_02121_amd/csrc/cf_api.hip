@@ -63,6 +63,10 @@ struct cf_ctx {
   int32_t *tld = nullptr;
   int64_t *eptr = nullptr;
   int32_t *ecells = nullptr;
+  // the same cells, most enrichment functions first: the coupling-partials
+  // launches take them in this order, so the longest workgroups start first
+  // (their output rows do not depend on the order)
+  int32_t *ecells_part = nullptr;
   int necells = 0;
   int64_t *aptr = nullptr;
   int32_t *alist = nullptr;
@@ -233,7 +237,7 @@ static cf_status core_apply_H(cf_ctx *c, const double *X, int64_t ldx, double *Y
   double *Ye = Y + c->n_h * ldy;
   {
     Scope sc(c, "enr_gemm");
-    HIPCHK(c, launch_enr_part(c->stream, c->HT, c->MT, c->toff, c->tld, c->eptr, c->dofp, c->ecells,
+    HIPCHK(c, launch_enr_part(c->stream, c->HT, c->MT, c->toff, c->tld, c->eptr, c->dofp, c->ecells_part,
                               c->necells, X, ldx, 1.0, nullptr, 0, nullptr, 0.0, c->P, c->max_cols,
                               N));
     HIPCHK(c, launch_enr_reduce(c->stream, (int)c->n_e, c->aptr, c->alist, c->P, c->max_cols, 1.0,
@@ -256,7 +260,7 @@ static cf_status core_apply_M(cf_ctx *c, const double *X, int64_t ldx, double *Y
   double *Ye = Y + c->n_h * ldy;
   if (c->n_e > 0) {
     Scope sc(c, "enr_gemm");
-    HIPCHK(c, launch_enr_part(c->stream, c->HT, c->MT, c->toff, c->tld, c->eptr, c->dofp, c->ecells,
+    HIPCHK(c, launch_enr_part(c->stream, c->HT, c->MT, c->toff, c->tld, c->eptr, c->dofp, c->ecells_part,
                               c->necells, nullptr, 0, 0.0, X, ldx, nullptr, 1.0, c->P, c->max_cols,
                               N));
     HIPCHK(c, launch_enr_reduce(c->stream, (int)c->n_e, c->aptr, c->alist, c->P, c->max_cols, 1.0,
@@ -305,7 +309,7 @@ static cf_status core_htilde_step(cf_ctx *c, const double *Xin, int64_t ldxin, i
     {
       Scope sc(c, "enr_part");
       HIPCHK(c, launch_enr_part(c->stream, c->HT, c->MT, c->toff, c->tld, c->eptr, c->dofp,
-                                c->ecells, c->necells, Xin, ldxin, 1.0, c->R, ldr, c->dinv, -1.0,
+                                c->ecells_part, c->necells, Xin, ldxin, 1.0, c->R, ldr, c->dinv, -1.0,
                                 c->P, c->max_cols, N));
     }
     {
@@ -411,7 +415,7 @@ static cf_status core_htilde_step_lp(cf_ctx *c, bool bf16, const float *Xin, int
     {
       Scope sc(c, "enr_part");
       HIPCHK(c, launch_enr_part_f32(c->stream, c->HT32, c->MT32, c->toff, c->tld, c->eptr, c->dofp,
-                                    c->ecells, c->necells, Xin, ldxin, 1.f, c->R32, mc, c->dinv,
+                                    c->ecells_part, c->necells, Xin, ldxin, 1.f, c->R32, mc, c->dinv,
                                     -1.f, c->P32, mc, N));
     }
     {
@@ -820,6 +824,16 @@ static cf_status do_init(const cf_problem *pr, const cf_options *opt, cf_ctx *c)
     HIPCHK(c, hipMemcpy(c->eptr, ep, (E + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
     if (!elist.empty())
       HIPCHK(c, hipMemcpy(c->ecells, elist.data(), elist.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    {
+      std::vector<int32_t> plist = elist;
+      std::stable_sort(plist.begin(), plist.end(), [&](int32_t x, int32_t y) {
+        return ep[x + 1] - ep[x] > ep[y + 1] - ep[y];
+      });
+      STCHK(dalloc(c, &c->ecells_part, std::max<size_t>(plist.size(), 1)));
+      if (!plist.empty())
+        HIPCHK(c, hipMemcpy(c->ecells_part, plist.data(), plist.size() * sizeof(int32_t),
+                            hipMemcpyHostToDevice));
+    }
 
     // alpha -> list of partial rows, increasing row index (fixed summation order)
     std::vector<int64_t> aptr(n_e + 1, 0);
@@ -1379,7 +1393,7 @@ cf_status chebfilter_apply_Sinv(cf_ctx *c, const double *X, int64_t ldx, double 
   if (c->n_e > 0) {
     // w = x_e - M^ec D^-1 x_c ; z = S^-1 w
     Scope sc(c, "enr_gemm");
-    HIPCHK(c, launch_enr_part(c->stream, c->HT, c->MT, c->toff, c->tld, c->eptr, c->dofp, c->ecells,
+    HIPCHK(c, launch_enr_part(c->stream, c->HT, c->MT, c->toff, c->tld, c->eptr, c->dofp, c->ecells_part,
                               c->necells, nullptr, 0, 0.0, X, ldx, c->dinv, -1.0, c->P, c->max_cols,
                               n));
     HIPCHK(c, launch_enr_reduce(c->stream, (int)c->n_e, c->aptr, c->alist, c->P, c->max_cols, 1.0,

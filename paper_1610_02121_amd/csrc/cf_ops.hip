@@ -150,7 +150,8 @@ hipError_t launch_cell_gemm(hipStream_t s, const double *Hp, const int32_t *dofp
 // h = w >> 2 of the 128 k (local nodes); it keeps the A fragments of both
 // terms for its k half in registers while the column tiles stream by, and the
 // two halves are added through LDS.  blockIdx.y picks one of gridDim.y
-// contiguous ranges of column tiles (more workgroups in flight).
+// contiguous ranges of column tiles (more workgroups in flight).  The gathered
+// rows of a tile are loaded two tiles ahead into one of two register sets.
 __global__ __launch_bounds__(512, 2) void k_enr_part(
     const double *__restrict__ HT, const double *__restrict__ MT,
     const int64_t *__restrict__ toff, const int32_t *__restrict__ tld,
@@ -196,30 +197,25 @@ __global__ __launch_bounds__(512, 2) void k_enr_part(
       aH[ks] = (act && ht) ? ht[off] : 0.0;
       aM[ks] = (act && mt) ? mt[off] : 0.0;
     }
-    double px[PF], pr[PF];
+    // two register sets of gathered rows, each refilled two tiles ahead
+    double xa[PF], ra[PF], xb[PF], rb[PF];
+    auto gather = [&](double (&qx)[PF], double (&qr)[PF], int c) {
 #pragma unroll
-    for (int p = 0; p < PF; ++p) {
-      const bool v = gd[p] >= 0 && cbeg + gj < cend;
-      px[p] = (X && v) ? X[(int64_t)gd[p] * ldx + cbeg + gj] : 0.0;
-      pr[p] = (R && v) ? R[(int64_t)gd[p] * ldr + cbeg + gj] * gsc[p] : 0.0;
-    }
-    for (int c0 = cbeg; c0 < cend; c0 += PT) {
+      for (int p = 0; p < PF; ++p) {
+        const bool v = gd[p] >= 0 && c + gj < cend;
+        qx[p] = (X && v) ? X[(int64_t)gd[p] * ldx + c + gj] : 0.0;
+        qr[p] = (R && v) ? R[(int64_t)gd[p] * ldr + c + gj] * gsc[p] : 0.0;
+      }
+    };
+    auto tile = [&](double (&qx)[PF], double (&qr)[PF], int c0) {
       const int ncol = min(PT, cend - c0);
 #pragma unroll
       for (int p = 0; p < PF; ++p) {
-        xs[(gr + p * RPP) * LDX + gj] = px[p];
-        rsm[(gr + p * RPP) * LDX + gj] = pr[p];
+        xs[(gr + p * RPP) * LDX + gj] = qx[p];
+        rsm[(gr + p * RPP) * LDX + gj] = qr[p];
       }
       __syncthreads();
-      const int c1 = c0 + PT;
-      if (c1 < cend) {
-#pragma unroll
-        for (int p = 0; p < PF; ++p) {
-          const bool v = gd[p] >= 0 && c1 + gj < cend;
-          px[p] = (X && v) ? X[(int64_t)gd[p] * ldx + c1 + gj] : 0.0;
-          pr[p] = (R && v) ? R[(int64_t)gd[p] * ldr + c1 + gj] * gsc[p] : 0.0;
-        }
-      }
+      if (c0 + 2 * PT < cend) gather(qx, qr, c0 + 2 * PT);
       d4 acc = d4zero();
       if (act) {
         d4 accH = d4zero(), accM = d4zero();
@@ -248,6 +244,12 @@ __global__ __launch_bounds__(512, 2) void k_enr_part(
           if (orow < na) P[(k0 + orow) * ldp + c0 + li] = acc[r] + xch[wb][r][lane];
         }
       }
+    };
+    gather(xa, ra, cbeg);
+    if (cbeg + PT < cend) gather(xb, rb, cbeg + PT);
+    for (int c0 = cbeg; c0 < cend; c0 += 2 * PT) {
+      tile(xa, ra, c0);
+      if (c0 + PT < cend) tile(xb, rb, c0 + PT);
     }
     __syncthreads();
   }

@@ -67,6 +67,7 @@ struct cf_ctx {
   // launches take them in this order, so the longest workgroups start first
   // (their output rows do not depend on the order)
   int32_t *ecells_part = nullptr;
+  int32_t *epos_part = nullptr;             // positions in ecells of the cells of ecells_part
   int necells = 0;
   int64_t *aptr = nullptr;
   int32_t *alist = nullptr;
@@ -223,7 +224,8 @@ static EpiArgs epi_base(cf_ctx *c, int N) {
 static cf_status core_enr_q(cf_ctx *c, const double *U, int64_t ldu, double cU, const double *V,
                             int64_t ldv, double cV, int N) {
   Scope sc(c, "enr_q");
-  HIPCHK(c, launch_enr_q(c->stream, c->Hec, c->Mec, c->eptr, c->eidx, c->ecells, c->necells, c->kmax,
+  HIPCHK(c, launch_enr_q(c->stream, c->Hec, c->Mec, c->eptr, c->eidx, c->ecells, c->epos_part,
+                         c->necells, c->kmax,
                          U, ldu, cU, V, ldv, cV, c->Q, c->max_cols, N));
   return CF_OK;
 }
@@ -427,6 +429,7 @@ static cf_status core_htilde_step_lp(cf_ctx *c, bool bf16, const float *Xin, int
     {
       Scope sc(c, "enr_q");
       HIPCHK(c, launch_enr_q_f32(c->stream, c->Hec32, c->Mec32, c->eptr, c->eidx, c->ecells,
+                                 c->epos_part,
                                  c->necells, c->kmax, Xe, ldxin, 1.f, c->Zb, mc, -1.f, c->Q32, mc,
                                  N));
     }
@@ -825,14 +828,20 @@ static cf_status do_init(const cf_problem *pr, const cf_options *opt, cf_ctx *c)
     if (!elist.empty())
       HIPCHK(c, hipMemcpy(c->ecells, elist.data(), elist.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     {
-      std::vector<int32_t> plist = elist;
-      std::stable_sort(plist.begin(), plist.end(), [&](int32_t x, int32_t y) {
-        return ep[x + 1] - ep[x] > ep[y + 1] - ep[y];
+      std::vector<int32_t> perm(elist.size()), plist(elist.size());
+      for (size_t q = 0; q < perm.size(); ++q) perm[q] = (int32_t)q;
+      std::stable_sort(perm.begin(), perm.end(), [&](int32_t x, int32_t y) {
+        return ep[elist[x] + 1] - ep[elist[x]] > ep[elist[y] + 1] - ep[elist[y]];
       });
+      for (size_t q = 0; q < perm.size(); ++q) plist[q] = elist[perm[q]];
       STCHK(dalloc(c, &c->ecells_part, std::max<size_t>(plist.size(), 1)));
-      if (!plist.empty())
+      STCHK(dalloc(c, &c->epos_part, std::max<size_t>(perm.size(), 1)));
+      if (!plist.empty()) {
         HIPCHK(c, hipMemcpy(c->ecells_part, plist.data(), plist.size() * sizeof(int32_t),
                             hipMemcpyHostToDevice));
+        HIPCHK(c, hipMemcpy(c->epos_part, perm.data(), perm.size() * sizeof(int32_t),
+                            hipMemcpyHostToDevice));
+      }
     }
 
     // alpha -> list of partial rows, increasing row index (fixed summation order)

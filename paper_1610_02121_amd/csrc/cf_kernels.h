@@ -74,10 +74,12 @@ hipError_t launch_enr_part(hipStream_t s, const double *HT, const double *MT, co
 
 // Transposed coupling products of the enriched cells into the cell-local buffer:
 //   Q[128 e' + a, :] = sum_k (cU H^ec_e[k,a] U[idx_k, :] + cV M^ec_e[k,a] V[idx_k, :])
+// e' is the cell's position in `cells`; workgroup i takes position order[i]
+// (order: a permutation of the positions, or null for the list order).
 hipError_t launch_enr_q(hipStream_t s, const double *Hec, const double *Mec, const int64_t *eptr,
-                        const int32_t *eidx, const int32_t *cells, int ncells, int kmax,
-                        const double *U, int64_t ldu, double cU, const double *V, int64_t ldv,
-                        double cV, double *Q, int64_t ldq, int N);
+                        const int32_t *eidx, const int32_t *cells, const int32_t *order,
+                        int ncells, int kmax, const double *U, int64_t ldu, double cU,
+                        const double *V, int64_t ldv, double cV, double *Q, int64_t ldq, int N);
 
 // Enrichment rows: out[al,:] = s_p * sum_{k in list(al)} P[k,:] + s_r * R0[al,:]
 //                              + sum_be Dn[al,be] * Zd[be,:]     (terms with null pointers skipped)
@@ -164,8 +166,9 @@ hipError_t launch_enr_part_f32(hipStream_t s, const float *HT, const float *MT,
 // As launch_enr_q with FP32 blocks; U rows FP32, V rows FP64.
 hipError_t launch_enr_q_f32(hipStream_t s, const float *Hec, const float *Mec,
                             const int64_t *eptr, const int32_t *eidx, const int32_t *cells,
-                            int ncells, int kmax, const float *U, int64_t ldu, float cU,
-                            const double *V, int64_t ldv, float cV, float *Q, int64_t ldq, int N);
+                            const int32_t *order, int ncells, int kmax, const float *U,
+                            int64_t ldu, float cU, const double *V, int64_t ldv, float cV,
+                            float *Q, int64_t ldq, int N);
 // out[al,:] (FP64) = sum_{k in list(al)} P[k,:] + sum_be Dn[al,be] Zd[be,:]   (P, Zd FP32)
 hipError_t launch_enr_reduce_f32(hipStream_t s, int n_e, const int64_t *aptr,
                                  const int32_t *alist, const float *P, int64_t ldp,

@@ -59,21 +59,23 @@ hipError_t launch_enr_part_f32(hipStream_t s, const float *HT, const float *MT,
 __global__ __launch_bounds__(256, 2) void k_enr_q_f32(
     const float *__restrict__ Hec, const float *__restrict__ Mec,
     const int64_t *__restrict__ eptr, const int32_t *__restrict__ eidx,
-    const int32_t *__restrict__ cells, const float *__restrict__ U, int64_t ldu, float cU,
+    const int32_t *__restrict__ cells, const int32_t *__restrict__ order,
+    const float *__restrict__ U, int64_t ldu, float cU,
     const double *__restrict__ V, int64_t ldv, float cV, float *__restrict__ Q, int64_t ldq,
     int N) {
-  enr_q_f32_body(Hec, Mec, eptr, eidx, cells[blockIdx.x], blockIdx.x, U, ldu, cU, V, ldv, cV, Q, ldq,
-                 N);
+  const int pos = order ? order[blockIdx.x] : (int)blockIdx.x;   // position in the cell list
+  enr_q_f32_body(Hec, Mec, eptr, eidx, cells[pos], pos, U, ldu, cU, V, ldv, cV, Q, ldq, N);
 }
 
 hipError_t launch_enr_q_f32(hipStream_t s, const float *Hec, const float *Mec,
                             const int64_t *eptr, const int32_t *eidx, const int32_t *cells,
-                            int ncells, int kmax, const float *U, int64_t ldu, float cU,
-                            const double *V, int64_t ldv, float cV, float *Q, int64_t ldq, int N) {
+                            const int32_t *order, int ncells, int kmax, const float *U,
+                            int64_t ldu, float cU, const double *V, int64_t ldv, float cV,
+                            float *Q, int64_t ldq, int N) {
   if (ncells <= 0 || N <= 0) return hipSuccess;
   (void)kmax;
-  hipLaunchKernelGGL(k_enr_q_f32, dim3(ncells), dim3(256), 0, s, Hec, Mec, eptr, eidx, cells, U,
-                     ldu, cU, V, ldv, cV, Q, ldq, N);
+  hipLaunchKernelGGL(k_enr_q_f32, dim3(ncells), dim3(256), 0, s, Hec, Mec, eptr, eidx, cells, order,
+                     U, ldu, cU, V, ldv, cV, Q, ldq, N);
   return hipGetLastError();
 }
 

@@ -285,7 +285,8 @@ hipError_t launch_enr_part(hipStream_t s, const double *HT, const double *MT, co
 __global__ __launch_bounds__(256, 2) void k_enr_q(
     const double *__restrict__ Hec, const double *__restrict__ Mec,
     const int64_t *__restrict__ eptr, const int32_t *__restrict__ eidx,
-    const int32_t *__restrict__ cells, const double *__restrict__ U, int64_t ldu, double cU,
+    const int32_t *__restrict__ cells, const int32_t *__restrict__ order,
+    const double *__restrict__ U, int64_t ldu, double cU,
     const double *__restrict__ V, int64_t ldv, double cV, double *__restrict__ Q, int64_t ldq,
     int N) {
   constexpr int PT = 16, LDZ = 16, KC = 64, KS = KC / 4;
@@ -294,10 +295,11 @@ __global__ __launch_bounds__(256, 2) void k_enr_q(
   __shared__ double zv[KC * LDZ];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, kq = lane >> 4;
-  const int cell = cells[blockIdx.x];
+  const int pos = order ? order[blockIdx.x] : (int)blockIdx.x;   // position in the cell list
+  const int cell = cells[pos];
   const int64_t k0 = eptr[cell];
   const int na = (int)(eptr[cell + 1] - k0);
-  double *qb = Q + ((int64_t)blockIdx.x * NPAD) * ldq;
+  double *qb = Q + ((int64_t)pos * NPAD) * ldq;
   const int gj = tid % PT, gk = tid / PT;   // gather: column gj, rows gk + 16 p
   // chunks of KC enrichment functions: the A fragments of the chunk (rows
   // 32w .. 32w+32 of both transposed blocks) stay in registers while the
@@ -388,13 +390,13 @@ __global__ __launch_bounds__(256, 2) void k_enr_q(
 }
 
 hipError_t launch_enr_q(hipStream_t s, const double *Hec, const double *Mec, const int64_t *eptr,
-                        const int32_t *eidx, const int32_t *cells, int ncells, int kmax,
-                        const double *U, int64_t ldu, double cU, const double *V, int64_t ldv,
-                        double cV, double *Q, int64_t ldq, int N) {
+                        const int32_t *eidx, const int32_t *cells, const int32_t *order,
+                        int ncells, int kmax, const double *U, int64_t ldu, double cU,
+                        const double *V, int64_t ldv, double cV, double *Q, int64_t ldq, int N) {
   if (ncells <= 0 || N <= 0) return hipSuccess;
   (void)kmax;
-  hipLaunchKernelGGL(k_enr_q, dim3(ncells), dim3(256), 0, s, Hec, Mec, eptr, eidx, cells, U, ldu,
-                     cU, V, ldv, cV, Q, ldq, N);
+  hipLaunchKernelGGL(k_enr_q, dim3(ncells), dim3(256), 0, s, Hec, Mec, eptr, eidx, cells, order, U,
+                     ldu, cU, V, ldv, cV, Q, ldq, N);
   return hipGetLastError();
 }
 

@@ -450,6 +450,20 @@ static cf_status core_htilde_step_lp(cf_ctx *c, bool bf16, const float *Xin, int
   return CF_OK;
 }
 
+// Out = In * W for row-major n x N blocks and a row-major N x N W (ld N):
+// a plain library GEMM (column-major view: Out^T = W^T In^T).
+static cf_status core_rotate(cf_ctx *c, const double *In, int64_t ldi, const double *W, int N,
+                             double *Out, int64_t ldo) {
+  Scope sc(c, "rotate", 2.0 * (double)c->n * N * N);
+  const double one = 1.0, zero = 0.0;
+  rocblas_set_pointer_mode(c->rb, rocblas_pointer_mode_host);
+  if (rocblas_dgemm(c->rb, rocblas_operation_none, rocblas_operation_none, N, (rocblas_int)c->n, N,
+                    &one, W, N, In, (rocblas_int)ldi, &zero, Out, (rocblas_int)ldo) !=
+      rocblas_status_success)
+    return set_err(c, CF_EDEVICE, "rotate: rocblas_dgemm failed");
+  return CF_OK;
+}
+
 // Gram G = A^T B (N x N, ld N) through the chunked partial kernel.
 static cf_status core_gram(cf_ctx *c, const double *A, int64_t lda, const double *B, int64_t ldb,
                            int64_t nrows, int N, double *Gout, int mode) {
@@ -473,9 +487,7 @@ static cf_status core_cholqr_pass(cf_ctx *c, const double *In, int64_t ldi, doub
   *failed = h_flag;
   if (h_flag) return CF_OK;
   HIPCHK(c, launch_tri_inv_T(c->stream, c->G, c->sv, N, c->Wm));
-  Scope sc(c, "rotate");
-  HIPCHK(c, launch_rotate(c->stream, In, ldi, c->n, N, c->Wm, N, 1, Out, ldo));
-  return CF_OK;
+  return core_rotate(c, In, ldi, c->Wm, N, Out, ldo);
 }
 
 // Orthonormalise In into Out through the scratch blocks T and R (In may equal
@@ -1542,10 +1554,7 @@ cf_status chebfilter_rayleigh_ritz(cf_ctx *c, double *Y, int64_t ldy, int64_t N,
   HIPCHK(c, hipMemcpyAsync(theta_host, c->theta, N * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   // C row-major: C[k][j] = V(k, j) = Hh[k + j n]
   HIPCHK(c, launch_transpose(c->stream, n, c->Hh, n, c->Wm));
-  {
-    Scope sc(c, "rotate");
-    HIPCHK(c, launch_rotate(c->stream, c->U, ld, c->n, n, c->Wm, n, 1, Y, ldy));
-  }
+  STCHK(core_rotate(c, c->U, ld, c->Wm, n, Y, ldy));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   if (h_info > 0 && h_info <= n)
     return set_err(c, CF_ENOTCONV, "rayleigh_ritz: eigensolver did not converge");

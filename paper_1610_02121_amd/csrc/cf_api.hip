@@ -479,13 +479,21 @@ static cf_status core_gram(cf_ctx *c, const double *A, int64_t lda, const double
 static cf_status core_cholqr_pass(cf_ctx *c, const double *In, int64_t ldi, double *Out,
                                   int64_t ldo, int N, double shift, int *failed) {
   STCHK(core_gram(c, In, ldi, In, ldi, c->n, N, c->G, GRAM_UPPER));
-  HIPCHK(c, hipMemsetAsync(c->flag, 0, sizeof(int), c->stream));
-  HIPCHK(c, launch_cholesky(c->stream, c->G, N, 1, shift, c->sv, c->flag));
-  int h_flag = 0;
-  HIPCHK(c, hipMemcpyAsync(&h_flag, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  // scaled, shifted Gram (our kernel), then the library Cholesky: on the
+  // row-major G, the column-major upper factor is the row-major lower L
+  HIPCHK(c, hipMemsetAsync(c->flag, 0, 2 * sizeof(int), c->stream));
+  HIPCHK(c, launch_chol_scale(c->stream, c->G, N, shift, c->sv, c->flag));
+  {
+    Scope sc(c, "cholesky");
+    if (rocsolver_dpotrf(c->rb, rocblas_fill_upper, N, c->G, N, (rocblas_int *)(c->flag + 1)) !=
+        rocblas_status_success)
+      return set_err(c, CF_EDEVICE, "cholqr: rocsolver_dpotrf failed");
+  }
+  int h_flag[2] = {0, 0};
+  HIPCHK(c, hipMemcpyAsync(h_flag, c->flag, 2 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  *failed = h_flag;
-  if (h_flag) return CF_OK;
+  *failed = h_flag[0] | h_flag[1];
+  if (*failed) return CF_OK;
   HIPCHK(c, launch_tri_inv_T(c->stream, c->G, c->sv, N, c->Wm));
   return core_rotate(c, In, ldi, c->Wm, N, Out, ldo);
 }

@@ -221,6 +221,38 @@ hipError_t launch_rotate(hipStream_t s, const double *In, int64_t ldi, int64_t n
 // Optional symmetric scaling S A S with S = diag(A)^-1/2 and a diagonal shift
 // are applied first.  flag[0] = index+1 of the first non-positive pivot.
 // ---------------------------------------------------------------------------
+// The scaling step of k_cholesky alone (for a library factorisation after it):
+// sv = diag(A)^-1/2, A <- S A S + shift I; flag[0] = index+1 of a
+// non-positive or non-finite diagonal entry (A is then left as it was).
+__global__ __launch_bounds__(1024) void k_chol_scale(double *A, int N, double shift, double *sv,
+                                                     int *flag) {
+  __shared__ int bad;
+  const int tid = threadIdx.x;
+  if (tid == 0) bad = 0;
+  __syncthreads();
+  for (int i = tid; i < N; i += 1024) {
+    const double d = A[(int64_t)i * N + i];
+    double s = 1.0;
+    if (d > 0.0 && isfinite(d)) s = 1.0 / sqrt(d);
+    else atomicExch(&bad, i + 1);   // LDS flag only
+    sv[i] = s;
+  }
+  __syncthreads();
+  if (bad) { if (tid == 0) flag[0] = bad; return; }
+  const int64_t NN = (int64_t)N * N;
+  for (int64_t e = tid; e < NN; e += 1024) {
+    const int i = (int)(e / N), j = (int)(e % N);
+    double v = A[e] * sv[i] * sv[j];
+    if (i == j) v += shift;
+    A[e] = v;
+  }
+}
+
+hipError_t launch_chol_scale(hipStream_t s, double *A, int N, double shift, double *sv, int *flag) {
+  hipLaunchKernelGGL(k_chol_scale, dim3(1), dim3(1024), 0, s, A, N, shift, sv, flag);
+  return hipGetLastError();
+}
+
 __global__ __launch_bounds__(1024) void k_cholesky(double *A, int N, int scale, double shift,
                                                    double *sv, int *flag) {
   constexpr int CB = 32;

@@ -271,6 +271,9 @@ hipError_t launch_rotate(hipStream_t s, const double *In, int64_t ldi, int64_t n
 // scaling: A <- chol(S (A + shift*I_diag) S), S = diag(A)^-1/2 when scale != 0;
 // s_out[i] receives S_ii (1 when not scaling).  flag[0] = index+1 of a failing
 // pivot, 0 on success.
+// Only the scaling step of launch_cholesky (scale = 1): sv, S A S + shift I,
+// flag[0] = index+1 of a bad diagonal entry.
+hipError_t launch_chol_scale(hipStream_t s, double *A, int N, double shift, double *sv, int *flag);
 hipError_t launch_cholesky(hipStream_t s, double *A, int N, int scale, double shift_rel,
                            double *s_out, int *flag);
 // W (row-major N x N) = diag(sv) * L^-T  (upper triangular), L lower from launch_cholesky.

@@ -1553,20 +1553,46 @@ cf_status chebfilter_rayleigh_ritz(cf_ctx *c, double *Y, int64_t ldy, int64_t N,
   STCHK(core_gram(c, c->U, ld, c->T, ld, c->n, n, c->Hh, GRAM_SYM));
   STCHK(core_apply_M(c, c->U, ld, c->T, ld, n));
   STCHK(core_gram(c, c->U, ld, c->T, ld, c->n, n, c->Mh, GRAM_SYM));
-  // dense generalized eigensolve on the device (eigenvectors column-major in Hh)
-  if (rocsolver_dsygvd(c->rb, rocblas_eform_ax, rocblas_evect_original, rocblas_fill_upper, n, c->Hh,
-                       n, c->Mh, n, c->theta, c->evE, c->info) != rocblas_status_success)
-    return set_err(c, CF_EDEVICE, "rayleigh_ritz: rocsolver_dsygvd failed");
+  // the projected pencil (Hh, Mh) to standard form: Mh = L L^T (library
+  // Cholesky; on the row-major symmetric Mh the column-major upper factor is
+  // the row-major lower L), W = L^-T, C = W^T Hh W; symmetric eigensolve of C;
+  // Ritz vectors Y = U (W V).  All row-major N x N products go to rocBLAS
+  // through the column-major view (a row-major X is the column-major X^T).
+  HIPCHK(c, hipMemsetAsync(c->flag, 0, sizeof(int), c->stream));
+  if (rocsolver_dpotrf(c->rb, rocblas_fill_upper, n, c->Mh, n, (rocblas_int *)c->flag) !=
+      rocblas_status_success)
+    return set_err(c, CF_EDEVICE, "rayleigh_ritz: rocsolver_dpotrf failed");
+  HIPCHK(c, launch_tri_inv_T(c->stream, c->Mh, nullptr, n, c->Wt));
+  {
+    const double one = 1.0, zero = 0.0;
+    rocblas_set_pointer_mode(c->rb, rocblas_pointer_mode_host);
+    // G = Hh W (row-major), then Hh <- W^T G
+    if (rocblas_dgemm(c->rb, rocblas_operation_none, rocblas_operation_none, n, n, n, &one, c->Wt,
+                      n, c->Hh, n, &zero, c->G, n) != rocblas_status_success ||
+        rocblas_dgemm(c->rb, rocblas_operation_none, rocblas_operation_transpose, n, n, n, &one,
+                      c->G, n, c->Wt, n, &zero, c->Hh, n) != rocblas_status_success)
+      return set_err(c, CF_EDEVICE, "rayleigh_ritz: rocblas_dgemm failed");
+  }
+  if (rocsolver_dsyevd(c->rb, rocblas_evect_original, rocblas_fill_upper, n, c->Hh, n, c->theta,
+                       c->evE, c->info) != rocblas_status_success)
+    return set_err(c, CF_EDEVICE, "rayleigh_ritz: rocsolver_dsyevd failed");
+  {
+    // Wm = W V (row-major); the eigenvectors are the columns of the
+    // column-major V in Hh
+    const double one = 1.0, zero = 0.0;
+    if (rocblas_dgemm(c->rb, rocblas_operation_transpose, rocblas_operation_none, n, n, n, &one,
+                      c->Hh, n, c->Wt, n, &zero, c->Wm, n) != rocblas_status_success)
+      return set_err(c, CF_EDEVICE, "rayleigh_ritz: rocblas_dgemm failed");
+  }
   rocblas_int h_info = 0;
+  int h_flag = 0;
   HIPCHK(c, hipMemcpyAsync(&h_info, c->info, sizeof(rocblas_int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(&h_flag, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipMemcpyAsync(theta_host, c->theta, N * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-  // C row-major: C[k][j] = V(k, j) = Hh[k + j n]
-  HIPCHK(c, launch_transpose(c->stream, n, c->Hh, n, c->Wm));
   STCHK(core_rotate(c, c->U, ld, c->Wm, n, Y, ldy));
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  if (h_info > 0 && h_info <= n)
-    return set_err(c, CF_ENOTCONV, "rayleigh_ritz: eigensolver did not converge");
-  if (h_info > n) return set_err(c, CF_ENOTSPD, "rayleigh_ritz: projected overlap not SPD");
+  if (h_flag) return set_err(c, CF_ENOTSPD, "rayleigh_ritz: projected overlap not SPD");
+  if (h_info > 0) return set_err(c, CF_ENOTCONV, "rayleigh_ritz: eigensolver did not converge");
   return check_out_finite(c, Y, ldy, n, "rayleigh_ritz");
 }
 
@@ -1782,15 +1808,17 @@ static cf_status batch_rr_alloc(cf_batch *b) {
 }
 
 // Every entry is projected with no host wait: two unshifted Cholesky-QR
-// passes whose failure flags land in the entry's status words (a failed pass
-// leaves the block as it was), the projected pencil into the entry's slot,
-// then one batched generalized eigensolve per block width and the predicated
-// rotation.  One synchronisation reads every status; an entry whose
+// passes whose failure flags land in the entry's status words (the result
+// reaches the block through a predicated copy, so a failed pass leaves it as
+// it was), the projected pencil into the entry's slot, then one batched
+// generalized eigensolve per block width and the rotation, again through a
+// predicated copy.  One synchronisation reads every status; an entry whose
 // orthonormalisation or eigensolve failed is redone by the single-problem
 // projection (shifted Cholesky-QR, its own error reporting) on its block,
 // which still spans the filtered subspace.  Status words per entry: [0], [1]
 // the two Cholesky passes, [2] the eigensolver's info, [3] a non-finite
-// pencil, [4] a non-finite rotated block.
+// pencil, [4] a non-finite rotated block, [5], [6] a bad Gram diagonal in
+// the two passes.
 cf_status chebfilter_rayleigh_ritz_batch(cf_batch *b, double *const *Y, const int64_t *ldy,
                                          const int64_t *N, double *const *theta_host) {
   if (!b) return CF_EINVAL;
@@ -1831,18 +1859,24 @@ cf_status chebfilter_rayleigh_ritz_batch(cf_batch *b, double *const *Y, const in
     int *st = b->d_rst + 8 * i;
     double *Hh = b->d_rH + b->h_rslot[i] * mc2, *Mh = b->d_rM + b->h_rslot[i] * mc2;
     cf_status r = CF_OK;
+    // the steps of core_cholqr_pass (scaling kernel, library Cholesky and
+    // rotation), so that both paths compute the same basis; pass 0 writes the
+    // scratch block T, pass 1 writes U and is copied into Y only if both
+    // passes succeeded
     for (int pass = 0; pass < 2 && r == CF_OK; ++pass) {
       const double *In = pass == 0 ? Y[i] : c->T;
       const int64_t ldi = pass == 0 ? ldy[i] : ld;
-      double *Out = pass == 0 ? c->T : Y[i];
-      const int64_t ldo = pass == 0 ? ld : ldy[i];
       r = core_gram(c, In, ldi, In, ldi, c->n, n, c->G, GRAM_UPPER);
       if (r != CF_OK) break;
-      if (launch_cholesky(s, c->G, n, 1, 0.0, c->sv, st + pass) != hipSuccess ||
-          launch_tri_inv_T(s, c->G, c->sv, n, c->Wm) != hipSuccess ||
-          launch_rotate(s, In, ldi, c->n, n, c->Wm, n, 1, Out, ldo, st) != hipSuccess)
+      if (launch_chol_scale(s, c->G, n, 0.0, c->sv, st + 5 + pass) != hipSuccess ||
+          rocsolver_dpotrf(c->rb, rocblas_fill_upper, n, c->G, n, (rocblas_int *)(st + pass)) !=
+              rocblas_status_success ||
+          launch_tri_inv_T(s, c->G, c->sv, n, c->Wm) != hipSuccess)
         r = set_err(c, CF_EDEVICE, "rayleigh_ritz_batch: launch failed");
+      if (r == CF_OK) r = core_rotate(c, In, ldi, c->Wm, n, pass == 0 ? c->T : c->U, ld);
     }
+    if (r == CF_OK && launch_copy_skip(s, c->n, n, c->U, ld, Y[i], ldy[i], st) != hipSuccess)
+      r = set_err(c, CF_EDEVICE, "rayleigh_ritz_batch: launch failed");
     if (r == CF_OK) r = core_apply_H(c, Y[i], ldy[i], c->T, ld, n);
     if (r == CF_OK) r = core_gram(c, Y[i], ldy[i], c->T, ld, c->n, n, Hh, GRAM_SYM);
     if (r == CF_OK) r = core_apply_M(c, Y[i], ldy[i], c->T, ld, n);
@@ -1873,8 +1907,8 @@ cf_status chebfilter_rayleigh_ritz_batch(cf_batch *b, double *const *Y, const in
     int *st = b->d_rst + 8 * i;
     BHIPCHK(b, launch_transpose(s, n, b->d_rH + b->h_rslot[i] * mc2, n, c->Wm));
     {
-      Scope sc(c, "rotate");
-      BHIPCHK(b, launch_rotate(s, Y[i], ldy[i], c->n, n, c->Wm, n, 1, c->T, ld, st));
+      cf_status r = core_rotate(c, Y[i], ldy[i], c->Wm, n, c->T, ld);
+      if (r != CF_OK) return fail(i, c, r);
     }
     BHIPCHK(b, launch_copy_skip(s, c->n, n, c->T, ld, Y[i], ldy[i], st));
     if (c->check_finite) BHIPCHK(b, launch_check_finite(s, Y[i], ldy[i], c->n, n, st + 4));
@@ -1889,7 +1923,7 @@ cf_status chebfilter_rayleigh_ritz_batch(cf_batch *b, double *const *Y, const in
     cf_ctx *c = b->uniq[b->which[i]];
     const int *st = b->h_rst.data() + 8 * i;
     if (st[3]) return fail(i, c, set_err(c, CF_ENUMERIC, "rayleigh_ritz_batch: non-finite projected pencil"));
-    if (st[0] | st[1] | st[2]) {
+    if (st[0] | st[1] | st[2] | st[5] | st[6]) {
       cf_status r = chebfilter_rayleigh_ritz(c, Y[i], ldy[i], N[i], theta_host[i]);
       if (r != CF_OK) return fail(i, c, r);
       continue;

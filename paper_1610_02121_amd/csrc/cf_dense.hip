@@ -145,8 +145,8 @@ __global__ __launch_bounds__(256) void k_rotate(const double *__restrict__ In, i
                                                 int64_t wsk, int64_t wsj,
                                                 double *__restrict__ Out, int64_t ldo,
                                                 int nrb, const int *__restrict__ skip) {
-  // skip (optional): four status words; any nonzero one leaves Out untouched
-  if (skip && (skip[0] | skip[1] | skip[2] | skip[3])) return;
+  // skip (optional): status words [0..3], [5], [6]; any nonzero one leaves Out untouched
+  if (skip && (skip[0] | skip[1] | skip[2] | skip[3] | skip[5] | skip[6])) return;
   constexpr int KS = 32, LDA = 34;
   __shared__ double as[64 * LDA];
   const int T = (N + GT - 1) / GT;
@@ -364,7 +364,7 @@ __global__ __launch_bounds__(64) void k_tri_inv_T(const double *__restrict__ L,
     if (lane == 0) x[i] = ((i == c ? 1.0 : 0.0) - acc) / Li[i];
     __syncthreads();
   }
-  const double s = sv[c];
+  const double s = sv ? sv[c] : 1.0;
   for (int i = c + lane; i < N; i += 64) x[i] *= s;
 }
 
@@ -630,11 +630,11 @@ hipError_t launch_copy(hipStream_t s, int64_t n, int N, const double *X, int64_t
 
 
 // Predicated copy for the batched projection: as k_copy, but nothing is
-// written when any of the four status words is nonzero.
+// written when any of the status words [0..3], [5], [6] is nonzero.
 __global__ __launch_bounds__(256) void k_copy_skip(int64_t n, int N, const double *X, int64_t ldx,
                                                    double *Y, int64_t ldy,
                                                    const int *__restrict__ skip) {
-  if (skip[0] | skip[1] | skip[2] | skip[3]) return;
+  if (skip[0] | skip[1] | skip[2] | skip[3] | skip[5] | skip[6]) return;
   for (int64_t i = (int64_t)blockIdx.x * 4 + threadIdx.y; i < n; i += (int64_t)gridDim.x * 4)
     for (int j = threadIdx.x; j < N; j += 64) Y[i * ldy + j] = X[i * ldx + j];
 }
@@ -650,7 +650,7 @@ hipError_t launch_copy_skip(hipStream_t s, int64_t n, int N, const double *X, in
 }
 
 // Guard of a projected pencil (Hh, Mh, N x N) before the batched eigensolve:
-// when the orthonormalisation failed (st[0] or st[1] set) or an entry of the
+// when the orthonormalisation failed (st[0], st[1], st[5] or st[6] set) or an entry of the
 // pencil is not finite, both matrices become the identity, so that the
 // eigensolver sees a trivial problem; a non-finite pencil of an entry whose
 // orthonormalisation succeeded is recorded in st[3].  One workgroup.
@@ -659,7 +659,7 @@ __global__ __launch_bounds__(256) void k_rr_guard(double *__restrict__ Hh, doubl
   __shared__ int nonfinite;
   if (threadIdx.x == 0) nonfinite = 0;
   __syncthreads();
-  const int prior = st[0] | st[1];
+  const int prior = st[0] | st[1] | st[5] | st[6];
   const int NN = N * N;
   int nf = 0;
   for (int e = threadIdx.x; e < NN; e += 256)

@@ -263,7 +263,8 @@ hipError_t launch_gram_partial(hipStream_t s, const double *A, int64_t lda, cons
 hipError_t launch_gram_reduce(hipStream_t s, const double *Gp, int nchunks, int N, double *G,
                               int mode);
 // Out[r, j] = sum_k In[r, k] * W[k*wsk + j*wsj]     (out of place)
-// skip: optional device status words (4); if any is nonzero the kernel writes nothing.
+// skip: optional device status words (8); if any of [0..3], [5], [6] is nonzero the kernel
+// writes nothing.
 hipError_t launch_rotate(hipStream_t s, const double *In, int64_t ldi, int64_t n, int N,
                          const double *W, int64_t wsk, int64_t wsj, double *Out, int64_t ldo,
                          const int *skip = nullptr);
@@ -276,7 +277,8 @@ hipError_t launch_rotate(hipStream_t s, const double *In, int64_t ldi, int64_t n
 hipError_t launch_chol_scale(hipStream_t s, double *A, int N, double shift, double *sv, int *flag);
 hipError_t launch_cholesky(hipStream_t s, double *A, int N, int scale, double shift_rel,
                            double *s_out, int *flag);
-// W (row-major N x N) = diag(sv) * L^-T  (upper triangular), L lower from launch_cholesky.
+// W (row-major N x N) = diag(sv) * L^-T  (upper triangular), L lower from launch_cholesky
+// (sv null: the identity).
 hipError_t launch_tri_inv_T(hipStream_t s, const double *L, const double *sv, int N, double *W);
 // Small GEMM: C = A * B (row-major, one thread per output).
 hipError_t launch_small_gemm(hipStream_t s, int M, int K, int N, const double *A, int64_t lda,

@@ -134,84 +134,6 @@ hipError_t launch_gram_reduce(hipStream_t s, const double *Gp, int nchunks, int 
 }
 
 // ---------------------------------------------------------------------------
-// Rotation Out = In * W (In: n x N row-major, W: N x N with strides).  Tile of
-// 64 rows x 64 columns per workgroup; In is staged through LDS in k-slabs of
-// 32 columns (row stride 34 doubles: conflict-free A-fragment reads), W is
-// read from global memory (it stays in L2).  Workgroups of one row block are
-// kept on one XCD.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_rotate(const double *__restrict__ In, int64_t ldi,
-                                                int64_t n, int N, const double *__restrict__ W,
-                                                int64_t wsk, int64_t wsj,
-                                                double *__restrict__ Out, int64_t ldo,
-                                                int nrb, const int *__restrict__ skip) {
-  // skip (optional): status words [0..3], [5], [6]; any nonzero one leaves Out untouched
-  if (skip && (skip[0] | skip[1] | skip[2] | skip[3] | skip[5] | skip[6])) return;
-  constexpr int KS = 32, LDA = 34;
-  __shared__ double as[64 * LDA];
-  const int T = (N + GT - 1) / GT;
-  const int bid = blockIdx.x;
-  const int xcd = bid & 7, slot = bid >> 3;
-  const int rb = (slot / T) * 8 + xcd;
-  const int tj = slot % T;
-  if (rb >= nrb) return;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int li = lane & 15, kq = lane >> 4;
-  const int64_t r0 = (int64_t)rb * 64;
-  const int wi = 32 * (w & 1), j0 = tj * GT + 32 * (w >> 1);
-  d4 acc[2][2];
-  acc[0][0] = acc[0][1] = acc[1][0] = acc[1][1] = d4zero();
-  const bool jv0 = j0 + li < N, jv1 = j0 + 16 + li < N;
-  for (int kc = 0; kc < N; kc += KS) {
-    for (int idx = tid; idx < 64 * KS; idx += 256) {
-      const int r = idx / KS, k = idx % KS;
-      double v = 0.0;
-      if (r0 + r < n && kc + k < N) v = In[(r0 + r) * ldi + kc + k];
-      as[r * LDA + k] = v;
-    }
-    __syncthreads();
-    if (j0 < N) {
-#pragma unroll
-      for (int ks = 0; ks < KS / 4; ++ks) {
-        const int k = kc + 4 * ks + kq;
-        const bool kv = k < N;
-        const double a0 = as[(wi + li) * LDA + 4 * ks + kq];
-        const double a1 = as[(wi + 16 + li) * LDA + 4 * ks + kq];
-        const double b0 = (kv && jv0) ? W[k * wsk + (j0 + li) * wsj] : 0.0;
-        const double b1 = (kv && jv1) ? W[k * wsk + (j0 + 16 + li) * wsj] : 0.0;
-        acc[0][0] = mfma_f64(a0, b0, acc[0][0]);
-        acc[0][1] = mfma_f64(a0, b1, acc[0][1]);
-        acc[1][0] = mfma_f64(a1, b0, acc[1][0]);
-        acc[1][1] = mfma_f64(a1, b1, acc[1][1]);
-      }
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int ib = 0; ib < 2; ++ib)
-#pragma unroll
-    for (int jb = 0; jb < 2; ++jb) {
-      const int j = j0 + 16 * jb + li;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t row = r0 + wi + 16 * ib + kq + 4 * r;
-        if (row < n && j < N) Out[row * ldo + j] = acc[ib][jb][r];
-      }
-    }
-}
-
-hipError_t launch_rotate(hipStream_t s, const double *In, int64_t ldi, int64_t n, int N,
-                         const double *W, int64_t wsk, int64_t wsj, double *Out, int64_t ldo, const int *skip) {
-  if (n <= 0 || N <= 0) return hipSuccess;
-  const int T = (N + GT - 1) / GT;
-  const int nrb = (int)((n + 63) / 64);
-  const int nrb8 = (nrb + 7) / 8 * 8;
-  hipLaunchKernelGGL(k_rotate, dim3(nrb8 * T), dim3(256), 0, s, In, ldi, n, N, W, wsk, wsj, Out,
-                     ldo, nrb, skip);
-  return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
 // Lower Cholesky of a small SPD matrix (row-major, ld N), one workgroup,
 // right-looking in panels of CB = 32 columns:
 //   1. the diagonal block is factored in LDS,

@@ -262,12 +262,6 @@ hipError_t launch_gram_partial(hipStream_t s, const double *A, int64_t lda, cons
 // G[i][j] = sum_c Gp[c][i][j], combined as the mode says.
 hipError_t launch_gram_reduce(hipStream_t s, const double *Gp, int nchunks, int N, double *G,
                               int mode);
-// Out[r, j] = sum_k In[r, k] * W[k*wsk + j*wsj]     (out of place)
-// skip: optional device status words (8); if any of [0..3], [5], [6] is nonzero the kernel
-// writes nothing.
-hipError_t launch_rotate(hipStream_t s, const double *In, int64_t ldi, int64_t n, int N,
-                         const double *W, int64_t wsk, int64_t wsj, double *Out, int64_t ldo,
-                         const int *skip = nullptr);
 // In-place lower Cholesky of the N x N row-major A (ld = N) with optional column
 // scaling: A <- chol(S (A + shift*I_diag) S), S = diag(A)^-1/2 when scale != 0;
 // s_out[i] receives S_ii (1 when not scaling).  flag[0] = index+1 of a failing
@@ -324,7 +318,8 @@ hipError_t launch_assemble_cells(hipStream_t s, const double *Btab, const double
 // ---- data-movement helpers (cf_dense.hip)
 hipError_t launch_sub(hipStream_t s, int64_t n, const double *A, const double *B, double *C);
 hipError_t launch_transpose(hipStream_t s, int N, const double *In, int64_t ldi, double *Out);
-// Batched projection helpers: predicated copy (skip as in launch_rotate),
+// Batched projection helpers: predicated copy (skip: the entry's 8 status words; nothing is
+// written when any of [0..3], [5], [6] is nonzero),
 // pencil guard (identity on failure, st[3] on a non-finite pencil) and the
 // scatter of the batched eigensolver's info into st[8 e + 2].
 hipError_t launch_copy_skip(hipStream_t s, int64_t n, int N, const double *X, int64_t ldx,

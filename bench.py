@@ -508,9 +508,10 @@ def run_batch(args):
 
 def learned_study(args):
     """Learned bounds (the network with the guard) against the Lanczos bound on
-    a self-consistent-step sequence.  Training corpus: perturbation sequences
-    on Si clusters of 1-4 atoms (labels: theta_N, a 40-step Lanczos bound and
-    the degree rule), 2000 Adam steps.  Evaluation: 30 steps on the 8-atom
+    a self-consistent-step sequence.  Training corpus: three perturbation
+    sequences of 40 steps on each Si cluster of 1-6 atoms (labels: theta_N, a
+    40-step Lanczos bound and the degree rule), 2000 Adam steps on batches of
+    64 with a cosine step-size decay.  Evaluation: 30 steps on the 8-atom
     cluster with a new perturbation sequence, each step's Ritz values against
     a reference from FP64 passes (Lanczos bound, degree rule) continued until
     they settle."""
@@ -524,14 +525,14 @@ def learned_study(args):
     torch.cuda.set_device(dev)
     t0 = time.time()
     inputs, targets = [], []
-    for nat in (1, 2, 3, 4):
+    for nat in (1, 2, 3, 4, 5, 6):
         prob = configs.batch_cluster(nat, seed=args.seed)
         N = 16 + round(48 * (nat - 1) / 7)
         wanted = N - 8
         ctx = Context(prob, max_cols=N)
         v0 = torch.tensor(np.random.default_rng(args.seed + nat).standard_normal(prob.n),
                           dtype=torch.float64, device=dev)
-        for sq in range(2):
+        for sq in range(3):
             recs, _ = L.run_sequence(ctx, prob, N, wanted, 40, seed=100 * nat + sq,
                                      chooser=L.lanczos_chooser(ctx, v0, wanted), v0=v0, label_k=40)
             inputs += [r["input"] for r in recs]
@@ -542,8 +543,22 @@ def learned_study(args):
     net = Mlp(L.N_IN, L.WIDTH, L.DEPTH, L.N_OUT, max_batch=64)
     net.set_params(L.init_params(seed=args.seed))
     t1 = time.time()
-    losses = L.train(net, inputs, targets, steps=2000, batch=32, lr=3e-4, seed=args.seed, log=log)
+    losses = L.train(net, inputs, targets, steps=2000, batch=64, lr=1e-3, seed=args.seed, log=log,
+                     lr_end=1e-5)
     t_train = time.time() - t1
+    # the corpus's labels and the trained network's outputs on it, against the
+    # guard's acceptance window for beta
+    im, isd, om, osd = L.normalisation(inputs, targets)
+    Xn = torch.tensor((inputs - im) / isd, dtype=torch.float32, device=dev)
+    pred = np.concatenate([net.forward(Xn[i:i + 64].contiguous()).cpu().numpy()
+                           for i in range(0, len(Xn), 64)]) * osd + om
+    diag = {"label_beta_mean": float(targets[:, 1].mean()),
+            "label_beta_p10_p50_p90": [float(x) for x in np.percentile(targets[:, 1], [10, 50, 90])],
+            "label_beta_below_guard": float(np.mean(targets[:, 1] < 0.98)),
+            "pred_beta_below_guard": float(np.mean(pred[:, 1] < 0.98)),
+            "pred_abs_err_beta_median": float(np.median(np.abs(pred[:, 1] - targets[:, 1]))),
+            "pred_abs_err_m_median": float(np.median(np.abs(pred[:, 2] - targets[:, 2])))}
+    log(f"labels vs guard: {diag}")
     # evaluation
     prob = configs.batch_cluster(8, seed=args.seed)
     N, wanted, steps = 64, 56, 30
@@ -579,7 +594,7 @@ def learned_study(args):
     ctx.close()
     out = {"study": "learned filter bounds vs Lanczos bound", "corpus_samples": int(len(inputs)),
            "train_steps": 2000, "train_seconds": t_train, "train_loss_first": float(losses[:20].mean()),
-           "train_loss_last": float(losses[-20:].mean()),
+           "train_loss_last": float(losses[-20:].mean()), "corpus_vs_guard": diag,
            "eval": {"workload": "8-atom Si cluster, 12^3 cells, n = %d, N = %d, wanted %d, %d steps"
                                 % (prob.n, N, wanted, steps)}}
     for name, recs in runs.items():

@@ -179,9 +179,10 @@ def normalisation(inputs: np.ndarray, targets: np.ndarray):
 
 
 def train(mlp, inputs: np.ndarray, targets: np.ndarray, steps: int = 2000, batch: int = 64,
-          lr: float = 1e-3, seed: int = 0, log=None):
+          lr: float = 1e-3, seed: int = 0, log=None, lr_end: float | None = None):
     """Adam on minibatches of the normalised corpus, all arithmetic in the
-    library's network kernels.  Returns the loss per step."""
+    library's network kernels; with lr_end the step size follows a cosine
+    from lr to lr_end.  Returns the loss per step."""
     import torch
     im, isd, om, osd = normalisation(inputs, targets)
     mlp.set_normalization(im, isd, om, osd)
@@ -195,7 +196,9 @@ def train(mlp, inputs: np.ndarray, targets: np.ndarray, steps: int = 2000, batch
         idx = torch.tensor(rng.choice(S, size=B, replace=False), device=mlp.device)
         xb, tb = Xn[idx].contiguous(), Tn[idx].contiguous()
         losses.append(mlp.loss_grad(xb, tb))
-        mlp.adam_step(lr)
+        lr_it = lr if lr_end is None else \
+            lr_end + 0.5 * (lr - lr_end) * (1.0 + np.cos(np.pi * it / max(steps - 1, 1)))
+        mlp.adam_step(lr_it)
         if log and (it % 250 == 0 or it == steps - 1):
             log(f"train step {it}: loss {losses[-1]:.4e}")
     return np.array(losses)

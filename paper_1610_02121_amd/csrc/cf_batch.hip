@@ -78,7 +78,7 @@ __global__ __launch_bounds__(512, 2) void kb_cell(const BatchProb *__restrict__ 
                           P.R32, P.mc, P.N, f, blockIdx.x);
 }
 
-__global__ __launch_bounds__(256, 2) void kb_enr_part(const BatchProb *__restrict__ bp,
+__global__ __launch_bounds__(512, 2) void kb_enr_part(const BatchProb *__restrict__ bp,
                                                    const BatchItem *__restrict__ items, int k) {
   const BatchItem it = items[blockIdx.x];
   const BatchProb &P = bp[it.p];
@@ -193,7 +193,7 @@ hipError_t launch_b_enr(hipStream_t s, const BatchProb *bp, int count, const Bat
                         int neitems, const int64_t *aoff, int64_t nalpha, int maxN, int kmax,
                         int k) {
   if (neitems <= 0 || nalpha <= 0 || maxN <= 0) return hipSuccess;
-  hipLaunchKernelGGL(kb_enr_part, dim3(neitems), dim3(256), 0, s, bp, eitems, k);
+  hipLaunchKernelGGL(kb_enr_part, dim3(neitems), dim3(512), 0, s, bp, eitems, k);
   const dim3 rgrid((maxN + 63) / 64, (unsigned)nalpha);
   hipLaunchKernelGGL(kb_enr_reduce, rgrid, dim3(64), 0, s, bp, aoff, count, k);
   hipLaunchKernelGGL(kb_schur, rgrid, dim3(64), 0, s, bp, aoff, count);

@@ -33,7 +33,7 @@ hipError_t launch_cell_gemm_lp(hipStream_t s, bool bf16, const void *Hv, const i
   return hipGetLastError();
 }
 
-__global__ __launch_bounds__(256, 2) void k_enr_part_f32(
+__global__ __launch_bounds__(512, 2) void k_enr_part_f32(
     const float *__restrict__ HT, const float *__restrict__ MT,
     const int64_t *__restrict__ toff, const int32_t *__restrict__ tld,
     const int64_t *__restrict__ eptr, const int32_t *__restrict__ dofp,
@@ -51,7 +51,7 @@ hipError_t launch_enr_part_f32(hipStream_t s, const float *HT, const float *MT,
                                int64_t ldr, const double *rs, float cM, float *P, int64_t ldp,
                                int N) {
   if (ncells <= 0 || N <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_enr_part_f32, dim3(ncells), dim3(256), 0, s, HT, MT, toff, tld, eptr, dofp,
+  hipLaunchKernelGGL(k_enr_part_f32, dim3(ncells), dim3(512), 0, s, HT, MT, toff, tld, eptr, dofp,
                      cells, X, ldx, cH, R, ldr, rs, cM, P, ldp, N);
   return hipGetLastError();
 }

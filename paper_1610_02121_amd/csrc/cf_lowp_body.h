@@ -181,9 +181,7 @@ __device__ __forceinline__ void cell_gemm_lp_body(
 // ---------------------------------------------------------------------------
 // Coupling partials, FP32 (as k_enr_part; FP32 blocks HT, MT).
 // ---------------------------------------------------------------------------
-// One enriched cell per workgroup of 256 threads.  Wave w takes row block
-// 4g + w of group g and keeps the A fragments of both terms (all 128 k) in
-// registers while the column tiles stream by, so the blocks are read once per
+// One enriched cell per workgroup of 512 threads; the blocks are read once per
 // call (cells with more than 64 enrichment functions take several passes over
 // the gathered rows).
 __device__ __forceinline__ void enr_part_f32_body(
@@ -193,13 +191,20 @@ __device__ __forceinline__ void enr_part_f32_body(
     const int cell, const float *__restrict__ X, int64_t ldx, float cH,
     const float *__restrict__ R, int64_t ldr, const double *__restrict__ rs, float cM,
     float *__restrict__ P, int64_t ldp, int N) {
+  // 8 waves (512 threads): wave w takes row block 4g + (w & 3) of group g and
+  // half h = w >> 2 of the 128 local nodes, with the A fragments of both terms
+  // for its half in registers; the halves are added through LDS.  The
+  // gathered rows of a tile are loaded two tiles ahead into one of two
+  // register sets.
   constexpr int PT = 16, LDX = PT + 1;
-  constexpr int PF = NPAD * PT / 256;
-  constexpr int RPP = 256 / PT;
+  constexpr int PF = NPAD * PT / 512;
+  constexpr int RPP = 512 / PT;
   __shared__ float xs[NPAD * LDX];
   __shared__ float rsm[NPAD * LDX];
+  __shared__ float xch[4][4][64];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, kq = lane >> 4;
+  const int wb = w & 3, h = w >> 2;
   const int gj = tid % PT, gr = tid / PT;
   int gd[PF];
   float gsc[PF];
@@ -215,59 +220,69 @@ __device__ __forceinline__ void enr_part_f32_body(
   const float *ht = X ? HT + toff[cell] : nullptr;
   const float *mt = R ? MT + toff[cell] : nullptr;
   for (int g = 0; 4 * g < nmb; ++g) {
-    const int mb = 4 * g + w;
+    const int mb = 4 * g + wb;
     const bool act = mb < nmb;
-    float aH[32], aM[32];
+    float aH[16], aM[16];
 #pragma unroll
-    for (int ks = 0; ks < 32; ++ks) {
-      const int64_t off = (int64_t)(4 * ks + kq) * nap + 16 * mb + li;
+    for (int ks = 0; ks < 16; ++ks) {
+      const int64_t off = (int64_t)(64 * h + 4 * ks + kq) * nap + 16 * mb + li;
       aH[ks] = (act && ht) ? ht[off] : 0.f;
       aM[ks] = (act && mt) ? mt[off] : 0.f;
     }
-    float px[PF], pr[PF];
+    float xa[PF], ra[PF], xb[PF], rb[PF];
+    auto gather = [&](float (&qx)[PF], float (&qr)[PF], int c) {
 #pragma unroll
-    for (int p = 0; p < PF; ++p) {
-      const bool v = gd[p] >= 0 && gj < N;
-      px[p] = (X && v) ? X[(int64_t)gd[p] * ldx + gj] : 0.f;
-      pr[p] = (R && v) ? R[(int64_t)gd[p] * ldr + gj] * gsc[p] : 0.f;
-    }
-    for (int c0 = 0; c0 < N; c0 += PT) {
+      for (int p = 0; p < PF; ++p) {
+        const bool v = gd[p] >= 0 && c + gj < N;
+        qx[p] = (X && v) ? X[(int64_t)gd[p] * ldx + c + gj] : 0.f;
+        qr[p] = (R && v) ? R[(int64_t)gd[p] * ldr + c + gj] * gsc[p] : 0.f;
+      }
+    };
+    auto tile = [&](float (&qx)[PF], float (&qr)[PF], int c0) {
       const int ncol = min(PT, N - c0);
 #pragma unroll
       for (int p = 0; p < PF; ++p) {
-        xs[(gr + p * RPP) * LDX + gj] = px[p];
-        rsm[(gr + p * RPP) * LDX + gj] = pr[p];
+        xs[(gr + p * RPP) * LDX + gj] = qx[p];
+        rsm[(gr + p * RPP) * LDX + gj] = qr[p];
       }
       __syncthreads();
-      const int c1 = c0 + PT;
-      if (c1 < N) {
-#pragma unroll
-        for (int p = 0; p < PF; ++p) {
-          const bool v = gd[p] >= 0 && c1 + gj < N;
-          px[p] = (X && v) ? X[(int64_t)gd[p] * ldx + c1 + gj] : 0.f;
-          pr[p] = (R && v) ? R[(int64_t)gd[p] * ldr + c1 + gj] * gsc[p] : 0.f;
-        }
-      }
+      if (c0 + 2 * PT < N) gather(qx, qr, c0 + 2 * PT);
+      f4 acc = f4zero();
       if (act) {
         f4 accH = f4zero(), accM = f4zero();
         if (ht) {
 #pragma unroll
-          for (int ks = 0; ks < 32; ++ks) accH = mfma_f32(aH[ks], xs[(4 * ks + kq) * LDX + li], accH);
+          for (int ks = 0; ks < 16; ++ks)
+            accH = mfma_f32(aH[ks], xs[(64 * h + 4 * ks + kq) * LDX + li], accH);
         }
         if (mt) {
 #pragma unroll
-          for (int ks = 0; ks < 32; ++ks) accM = mfma_f32(aM[ks], rsm[(4 * ks + kq) * LDX + li], accM);
+          for (int ks = 0; ks < 16; ++ks)
+            accM = mfma_f32(aM[ks], rsm[(64 * h + 4 * ks + kq) * LDX + li], accM);
         }
-        if (li < ncol) {
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int orow = 16 * mb + 4 * kq + r;
-            if (orow < na) P[(k0 + orow) * ldp + c0 + li] = cH * accH[r] + cM * accM[r];
-          }
+        for (int r = 0; r < 4; ++r) acc[r] = cH * accH[r] + cM * accM[r];
+        if (h == 1) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) xch[wb][r][lane] = acc[r];
         }
       }
       __syncthreads();
+      if (act && h == 0 && li < ncol) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int orow = 16 * mb + 4 * kq + r;
+          if (orow < na) P[(k0 + orow) * ldp + c0 + li] = acc[r] + xch[wb][r][lane];
+        }
+      }
+    };
+    gather(xa, ra, 0);
+    if (PT < N) gather(xb, rb, PT);
+    for (int c0 = 0; c0 < N; c0 += 2 * PT) {
+      tile(xa, ra, c0);
+      if (c0 + PT < N) tile(xb, rb, c0 + PT);
     }
+    __syncthreads();
   }
 }
 

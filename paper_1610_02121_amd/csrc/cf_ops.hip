@@ -26,9 +26,9 @@ __device__ __forceinline__ d4 d4zero() { d4 z = {0.0, 0.0, 0.0, 0.0}; return z; 
 // One workgroup of 8 waves per cell; wave w owns the 16 output rows
 // [16w, 16w+16) and keeps that slice of the (padded, symmetric) cell matrix in
 // registers as MFMA A fragments for the whole call.  Columns are walked in
-// tiles of CELL_NT: the next tile's gathered X rows and this tile's old Y
-// values are loaded into registers before the MFMA loop, so their latency
-// overlaps the matrix work; the current tile sits in LDS.  Dirichlet and
+// tiles of CELL_NT: the next tile's gathered X rows and old Y values are
+// loaded into registers (two alternating sets for Y) during this tile's MFMA
+// loop, so their latency overlaps the matrix work; the current tile sits in LDS.  Dirichlet and
 // padding rows are zero.  Cells of one colour share no DOF, so the
 // read-modify-write of Y is race free; the first cell (in launch order) to
 // touch a DOF writes instead of adding.
@@ -84,7 +84,18 @@ __global__ __launch_bounds__(512, 2) void k_cell_gemm(
     ofin[r] = finish && od[r] >= 0 && (sflag[row] & CELL_FINISH) != 0;
   }
 
-  for (int c0 = 0; c0 < N; c0 += NT) {
+  // old Y (and Yp of finishing rows) of a tile, loaded one tile ahead into
+  // one of two register sets
+  auto load_y = [&](double (&yo)[4], double (&yp)[4], int c) {
+    const bool cv = c + li < N;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      yo[r] = (od[r] >= 0 && !ofirst[r] && cv) ? Y[(int64_t)od[r] * ldy + c + li] : 0.0;
+      yp[r] = (ofin[r] && f.Yp && cv) ? f.Yp[(int64_t)od[r] * f.ldyp + c + li] : 0.0;
+    }
+  };
+  auto tile = [&](double (&yo)[4], double (&yp)[4], double (&yo2)[4], double (&yp2)[4],
+                  int c0) {
     const int ncol = min(NT, N - c0);
 #pragma unroll
     for (int p = 0; p < PF; ++p) xs[(gr + p * RPP) * LDX + gj] = pf[p];
@@ -94,14 +105,9 @@ __global__ __launch_bounds__(512, 2) void k_cell_gemm(
 #pragma unroll
       for (int p = 0; p < PF; ++p)
         pf[p] = (gd[p] >= 0 && c1 + gj < N) ? X[(int64_t)gd[p] * ldx + c1 + gj] : 0.0;
+      load_y(yo2, yp2, c1);
     }
     const bool cv = li < ncol;
-    double yo[4], yp[4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      yo[r] = (od[r] >= 0 && !ofirst[r] && cv) ? Y[(int64_t)od[r] * ldy + c0 + li] : 0.0;
-      yp[r] = (ofin[r] && f.Yp && cv) ? f.Yp[(int64_t)od[r] * f.ldyp + c0 + li] : 0.0;
-    }
     d4 acc = d4zero();
 #pragma unroll
     for (int ks = 0; ks < 32; ++ks) acc = mfma_f64(a[ks], xs[(4 * ks + kq) * LDX + li], acc);
@@ -119,6 +125,12 @@ __global__ __launch_bounds__(512, 2) void k_cell_gemm(
       }
     }
     __syncthreads();
+  };
+  double ya[4], pa[4], yb[4], pb[4];
+  load_y(ya, pa, 0);
+  for (int c0 = 0; c0 < N; c0 += 2 * NT) {
+    tile(ya, pa, yb, pb, c0);
+    if (c0 + NT < N) tile(yb, pb, ya, pa, c0 + NT);
   }
 }
 

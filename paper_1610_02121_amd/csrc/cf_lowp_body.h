@@ -120,7 +120,17 @@ __device__ __forceinline__ void cell_gemm_lp_body(
     ofin[r] = finish && od[r] >= 0 && (sflag[row] & CELL_FINISH) != 0;
   }
 
-  for (int c0 = 0; c0 < N; c0 += NT) {
+  // old Y (and Yp of finishing rows) of a tile, loaded one tile ahead into
+  // one of two register sets
+  auto load_y = [&](float (&yo)[4], float (&yp)[4], int c) {
+    const bool cv = c + li < N;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      yo[r] = (od[r] >= 0 && !ofirst[r] && cv) ? Y[(int64_t)od[r] * ldy + c + li] : 0.f;
+      yp[r] = (ofin[r] && f.Yp && cv) ? f.Yp[(int64_t)od[r] * f.ldyp + c + li] : 0.f;
+    }
+  };
+  auto tile = [&](float (&yo)[4], float (&yp)[4], float (&yo2)[4], float (&yp2)[4], int c0) {
     const int ncol = min(NT, N - c0);
 #pragma unroll
     for (int p = 0; p < PF; ++p) {
@@ -138,14 +148,9 @@ __device__ __forceinline__ void cell_gemm_lp_body(
 #pragma unroll
       for (int p = 0; p < PF; ++p)
         pf[p] = (gd[p] >= 0 && c1 + gj < N) ? X[(int64_t)gd[p] * ldx + c1 + gj] : 0.f;
+      load_y(yo2, yp2, c1);
     }
     const bool cv = li < ncol;
-    float yo[4], yp[4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      yo[r] = (od[r] >= 0 && !ofirst[r] && cv) ? Y[(int64_t)od[r] * ldy + c0 + li] : 0.f;
-      yp[r] = (ofin[r] && f.Yp && cv) ? f.Yp[(int64_t)od[r] * f.ldyp + c0 + li] : 0.f;
-    }
     f4 acc = f4zero();
     if constexpr (BF16) {
 #pragma unroll
@@ -174,6 +179,12 @@ __device__ __forceinline__ void cell_gemm_lp_body(
       }
     }
     __syncthreads();
+  };
+  float ya[4], pa[4], yb[4], pb[4];
+  load_y(ya, pa, 0);
+  for (int c0 = 0; c0 < N; c0 += 2 * NT) {
+    tile(ya, pa, yb, pb, c0);
+    if (c0 + NT < N) tile(yb, pb, ya, pa, c0 + NT);
   }
   if (f.mx) gather_max(f.mx, omax, (float *)sdof, slot);   // sdof is free after the tile loop
 }

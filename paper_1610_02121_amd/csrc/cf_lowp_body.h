@@ -65,7 +65,11 @@ __device__ __forceinline__ void cell_gemm_lp_body(
     const uint8_t *__restrict__ flagp, const int cell,
     const float *__restrict__ X, int64_t ldx, float *__restrict__ Y, int64_t ldy, int N,
     const CellFinishF &f, int slot) {
-  constexpr int NT = CELL_NT;
+  // column tiles of NSB 16-column MFMA blocks: two for the BF16 form (32
+  // gathered FP32 values, one 128-byte line per row), one for the FP32 form
+  // (whose registers leave no room for a second block at this occupancy)
+  constexpr int NSB = BF16 ? 2 : 1;
+  constexpr int NT = NSB * CELL_NT;
   constexpr int LDX = NT + 16;               // FP32 tile, row-major [k][col]
   constexpr int LDT = NPAD + 8;              // BF16 tile, column-major [col][k]
   constexpr int PF = NPAD * NT / 512;
@@ -120,18 +124,22 @@ __device__ __forceinline__ void cell_gemm_lp_body(
     ofin[r] = finish && od[r] >= 0 && (sflag[row] & CELL_FINISH) != 0;
   }
 
-  // old Y (and Yp of finishing rows) of a tile, loaded one tile ahead into
-  // one of two register sets
-  auto load_y = [&](float (&yo)[4], float (&yp)[4], int c) {
-    const bool cv = c + li < N;
+  // old Y (and Yp of finishing rows) of a tile's two column blocks, loaded
+  // one tile ahead into one of two register sets
+  auto load_y = [&](float (&yo)[NSB][4], float (&yp)[NSB][4], int c) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      yo[r] = (od[r] >= 0 && !ofirst[r] && cv) ? Y[(int64_t)od[r] * ldy + c + li] : 0.f;
-      yp[r] = (ofin[r] && f.Yp && cv) ? f.Yp[(int64_t)od[r] * f.ldyp + c + li] : 0.f;
+    for (int sb = 0; sb < NSB; ++sb) {
+      const int col = c + 16 * sb + li;
+      const bool cv = col < N;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        yo[sb][r] = (od[r] >= 0 && !ofirst[r] && cv) ? Y[(int64_t)od[r] * ldy + col] : 0.f;
+        yp[sb][r] = (ofin[r] && f.Yp && cv) ? f.Yp[(int64_t)od[r] * f.ldyp + col] : 0.f;
+      }
     }
   };
-  auto tile = [&](float (&yo)[4], float (&yp)[4], float (&yo2)[4], float (&yp2)[4], int c0) {
-    const int ncol = min(NT, N - c0);
+  auto tile = [&](float (&yo)[NSB][4], float (&yp)[NSB][4], float (&yo2)[NSB][4],
+                  float (&yp2)[NSB][4], int c0) {
 #pragma unroll
     for (int p = 0; p < PF; ++p) {
       const int row = gr + p * RPP;
@@ -150,37 +158,46 @@ __device__ __forceinline__ void cell_gemm_lp_body(
         pf[p] = (gd[p] >= 0 && c1 + gj < N) ? X[(int64_t)gd[p] * ldx + c1 + gj] : 0.f;
       load_y(yo2, yp2, c1);
     }
-    const bool cv = li < ncol;
-    f4 acc = f4zero();
-    if constexpr (BF16) {
+    f4 acc[NSB];
 #pragma unroll
-      for (int ks = 0; ks < 4; ++ks)
-        acc = mfma_bf16(a16[ks], *(const bf8 *)(xt + li * LDT + 32 * ks + 8 * kq), acc);
-    } else {
+    for (int sb = 0; sb < NSB; ++sb) {
+      acc[sb] = f4zero();
+      if (c0 + 16 * sb >= N) break;            // block beyond the last column (uniform)
+      if constexpr (BF16) {
 #pragma unroll
-      for (int ks = 0; ks < 32; ++ks) acc = mfma_f32(a32[ks], xs[(4 * ks + kq) * LDX + li], acc);
+        for (int ks = 0; ks < 4; ++ks)
+          acc[sb] = mfma_bf16(a16[ks], *(const bf8 *)(xt + (16 * sb + li) * LDT + 32 * ks + 8 * kq),
+                              acc[sb]);
+      } else {
+#pragma unroll
+        for (int ks = 0; ks < 32; ++ks)
+          acc[sb] = mfma_f32(a32[ks], xs[(4 * ks + kq) * LDX + 16 * sb + li], acc[sb]);
+      }
     }
-    if (cv) {
+#pragma unroll
+    for (int sb = 0; sb < NSB; ++sb) {
+      const int col = c0 + 16 * sb + li;
+      if (col >= N) continue;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         if (od[r] < 0) continue;
-        const float v = acc[r] + yo[r];
+        const float v = acc[sb][r] + yo[sb][r];
         if (ofin[r]) {
           const int row = 16 * w + 4 * kq + r;
           float xk;
-          if constexpr (BF16) xk = xk_tile[row * NT + li];
-          else xk = xs[row * LDX + li];
-          const float o = fc1 * (float)f.dinv[od[r]] * v + fc2 * xk + fc3 * yp[r];
-          f.Out[(int64_t)od[r] * f.ldo + c0 + li] = o;
+          if constexpr (BF16) xk = xk_tile[row * NT + 16 * sb + li];
+          else xk = xs[row * LDX + 16 * sb + li];
+          const float o = fc1 * (float)f.dinv[od[r]] * v + fc2 * xk + fc3 * yp[sb][r];
+          f.Out[(int64_t)od[r] * f.ldo + col] = o;
           omax = absmax(omax, o);
         } else {
-          Y[(int64_t)od[r] * ldy + c0 + li] = v;
+          Y[(int64_t)od[r] * ldy + col] = v;
         }
       }
     }
     __syncthreads();
   };
-  float ya[4], pa[4], yb[4], pb[4];
+  float ya[NSB][4], pa[NSB][4], yb[NSB][4], pb[NSB][4];
   load_y(ya, pa, 0);
   for (int c0 = 0; c0 < N; c0 += 2 * NT) {
     tile(ya, pa, yb, pb, c0);

@@ -361,6 +361,16 @@ __global__ __launch_bounds__(256, 2) void k_enr_q(
           pv[p] = (V && v) ? cV * V[gal[p] * ldv + c1 + gj] : 0.0;
         }
       }
+      // chunks after the first add into Q: its old values, loaded before the
+      // products so that their latency overlaps them
+      double qo0[4], qo1[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const bool ld = kc > 0 && li < ncol;
+        const double *q = qb + c0 + li;
+        qo0[r] = ld ? q[(int64_t)(32 * w + kq + 4 * r) * ldq] : 0.0;
+        qo1[r] = ld ? q[(int64_t)(32 * w + 16 + kq + 4 * r) * ldq] : 0.0;
+      }
       d4 acc0 = d4zero(), acc1 = d4zero();
       if (U) {
 #pragma unroll
@@ -384,8 +394,8 @@ __global__ __launch_bounds__(256, 2) void k_enr_q(
         for (int r = 0; r < 4; ++r) {
           double *q0 = q + (int64_t)(32 * w + kq + 4 * r) * ldq;
           double *q1 = q + (int64_t)(32 * w + 16 + kq + 4 * r) * ldq;
-          if (kc == 0) { *q0 = acc0[r]; *q1 = acc1[r]; }
-          else { *q0 += acc0[r]; *q1 += acc1[r]; }
+          *q0 = acc0[r] + qo0[r];
+          *q1 = acc1[r] + qo1[r];
         }
       }
       __syncthreads();

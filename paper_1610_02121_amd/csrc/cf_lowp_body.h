@@ -384,6 +384,16 @@ __device__ __forceinline__ void enr_q_f32_body(
           pv[p] = (V && v) ? cV * (float)V[gal[p] * ldv + c1 + gj] : 0.f;
         }
       }
+      // chunks after the first add into Q: its old values, loaded before the
+      // products so that their latency overlaps them
+      float qo0[4], qo1[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const bool ld = kc > 0 && li < ncol;
+        const float *q = qb + c0 + li;
+        qo0[r] = ld ? q[(int64_t)(32 * w + 4 * kq + r) * ldq] : 0.f;
+        qo1[r] = ld ? q[(int64_t)(32 * w + 16 + 4 * kq + r) * ldq] : 0.f;
+      }
       f4 acc0 = f4zero(), acc1 = f4zero();
       if (U) {
 #pragma unroll
@@ -407,8 +417,8 @@ __device__ __forceinline__ void enr_q_f32_body(
         for (int r = 0; r < 4; ++r) {
           float *q0 = q + (int64_t)(32 * w + 4 * kq + r) * ldq;
           float *q1 = q + (int64_t)(32 * w + 16 + 4 * kq + r) * ldq;
-          if (kc == 0) { *q0 = acc0[r]; *q1 = acc1[r]; }
-          else { *q0 += acc0[r]; *q1 += acc1[r]; }
+          *q0 = acc0[r] + qo0[r];
+          *q1 = acc1[r] + qo1[r];
         }
       }
       __syncthreads();

@@ -288,8 +288,12 @@ def precision_forms(ctx, X, Y, m, a, b, reps=3):
     import torch
     n, N = X.shape
     res = {}
+    tiles = {}
     for prec in ("fp64", "fp32", "bf16"):
         ctx.filter(X, m, a, b, Y=Y, prec=prec)          # first use builds the reduced copies
+        if prec != "fp64":
+            # tile shape of the reduced cell product, chosen by the library's autotuner
+            tiles[prec] = ctx.autotune(X, m, a, b, prec=prec, reps=2, Y=Y)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(reps):
@@ -308,6 +312,7 @@ def precision_forms(ctx, X, Y, m, a, b, reps=3):
                      "cell_frac": flops / (ms / 1e3) / peak if ms > 0 else None}
     for prec in ("fp32", "bf16"):
         res[prec]["speedup_vs_fp64"] = res["fp64"]["filter_ms"] / res[prec]["filter_ms"]
+        res[prec]["cell_tile_blocks_autotuned"] = tiles[prec]
     return res
 
 
@@ -427,6 +432,10 @@ def run_batch(args):
     v0 = [torch.tensor(np.random.default_rng(args.seed + 1 + i).standard_normal(p.n),
                        dtype=torch.float64, device=dev) for i, p in enumerate(probs)]
     theta = batch.rayleigh_ritz(X)
+    # tile shape of the batched reduced cell product, by the library's autotuner
+    _, b0 = batch.lanczos_bounds(v0, 10)
+    tile_choice = batch.autotune(X, m, [float(th[-1]) for th in theta], b0, prec=prec, reps=1, Y=Y)
+    log(f"autotuner: {tile_choice} column block(s) per tile")
     st = {"X": X, "Y": Y, "theta": theta, "t": [0.0, 0.0, 0.0]}
 
     def step(timed):
@@ -490,7 +499,8 @@ def run_batch(args):
         "config": {"workload": "si-batch256", "entries": 256, "distinct_problems": len(pool),
                    "atoms_per_entry": "U{1..8}", "vectors": "16-64", "cheb_degree": m,
                    "sum_n_times_N": work // m,
-                   "precision": f"{prec} filter, fp64 Schur solve and Rayleigh-Ritz"},
+                   "precision": f"{prec} filter, fp64 Schur solve and Rayleigh-Ritz",
+                   "cell_tile_blocks_autotuned": tile_choice},
         "phases_ms": {"bounds": 1e3 * st["t"][0] / args.steps,
                       "filter": 1e3 * st["t"][1] / args.steps,
                       "cholqr_rr": 1e3 * st["t"][2] / args.steps},

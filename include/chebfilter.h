@@ -144,6 +144,24 @@ cf_status chebfilter_filter_multipass(cf_ctx *ctx, const double *X, int64_t ldx,
                                      int64_t ldy, int64_t N, int32_t m, int32_t passes, double a,
                                      double b, int32_t prec);
 
+/* Tile shape of the reduced-precision cell product (a launch parameter, not
+ * part of the method): nsb = 1 or 2 sixteen-column MFMA blocks per column
+ * tile, for the FP32-input cells (prec = CF_FP32) or the BF16-input cells
+ * (prec = CF_BF16) of the context.  Both shapes compute bit-identical
+ * results; two blocks fill a 128-byte line per gathered row, one keeps the
+ * registers (and so the occupancy) lower.  Defaults: FP32 1, BF16 2.
+ * CF_EINVAL on another prec or nsb. */
+cf_status chebfilter_set_cell_tile(cf_ctx *ctx, int32_t prec, int32_t nsb);
+
+/* Autotuner of that shape: runs chebfilter_filter(ctx, X, ldx, Y, ldy, N, m,
+ * a, b, prec) once as a warm-up and `reps` times timed (HIP events on the
+ * context's stream) for each candidate, keeps the fastest for later calls
+ * and returns it in *choice (may be null).  Y is overwritten; prec is CF_FP32
+ * or CF_BF16; m >= 1, reps >= 1.  Synchronises. */
+cf_status chebfilter_autotune(cf_ctx *ctx, const double *X, int64_t ldx, double *Y, int64_t ldy,
+                              int64_t N, int32_t m, double a, double b, int32_t prec, int32_t reps,
+                              int32_t *choice);
+
 /* In place: Y <- Q with Q^T Q = I and span(Q) = span(Y), by Cholesky-QR
  * applied twice after scaling columns to unit length (the orthonormalisation
  * step of Sec. V).  Falls back to a shifted first pass if the Gram matrix is
@@ -214,6 +232,18 @@ cf_status chebfilter_filter_batch(cf_batch *batch, const double *const *X, const
                                   double *const *Y, const int64_t *ldy, const int64_t *N,
                                   int32_t m, const double *a, const double *b, int32_t prec,
                                   int32_t use_graph);
+
+/* The autotuner of chebfilter_autotune for the batched filter: times the
+ * graph-replayed batched filter with one and with two column blocks per tile
+ * of the batched reduced cell product (FP32-input cells for CF_FP32,
+ * BF16-input cells for CF_BF16), keeps the fastest for the batch's later
+ * calls (the captured graph is rebuilt when the shape changes) and returns
+ * it in *choice.  Arguments as chebfilter_filter_batch; Y is overwritten.
+ * Synchronises. */
+cf_status chebfilter_batch_autotune(cf_batch *batch, const double *const *X, const int64_t *ldx,
+                                    double *const *Y, const int64_t *ldy, const int64_t *N,
+                                    int32_t m, const double *a, const double *b, int32_t prec,
+                                    int32_t reps, int32_t *choice);
 
 /* chebfilter_rayleigh_ritz for every entry (Sec. V's projection), with one
  * host synchronisation for the whole batch: every entry is orthonormalised by

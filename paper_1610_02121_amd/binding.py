@@ -33,7 +33,8 @@ EXPORTS = ["chebfilter_init", "chebfilter_destroy", "chebfilter_last_error", "ch
            "chebfilter_mlp_forward", "chebfilter_mlp_loss_grad", "chebfilter_mlp_adam_step",
            "chebfilter_mlp_set_normalization", "chebfilter_bounds_features",
            "chebfilter_bounds_predict", "chebfilter_assembly_tables", "chebfilter_assemble_cells",
-           "chebfilter_get_H_cc"]
+           "chebfilter_get_H_cc", "chebfilter_set_cell_tile", "chebfilter_autotune",
+           "chebfilter_batch_autotune"]
 
 
 class CfProblem(C.Structure):
@@ -114,6 +115,12 @@ def load_library() -> C.CDLL:
     lib.chebfilter_assembly_tables.argtypes = [vp, i32, vp, vp, vp]
     lib.chebfilter_assemble_cells.argtypes = [vp, vp, i64, vp, i64]
     lib.chebfilter_get_H_cc.argtypes = [vp, vp, i64, vp]
+    lib.chebfilter_set_cell_tile.argtypes = [vp, i32, i32]
+    lib.chebfilter_autotune.argtypes = [vp, vp, i64, vp, i64, i64, i32, dbl, dbl, i32, i32,
+                                        C.POINTER(i32)]
+    lib.chebfilter_batch_autotune.argtypes = [vp, C.POINTER(vp), P64, C.POINTER(vp), P64, P64, i32,
+                                              C.POINTER(dbl), C.POINTER(dbl), i32, i32,
+                                              C.POINTER(i32)]
     for nm in EXPORTS:
         if nm not in ("chebfilter_last_error", "chebfilter_batch_last_error",
                       "chebfilter_mlp_last_error"):
@@ -229,6 +236,21 @@ class Context:
         self._check(self.lib.chebfilter_filter_multipass(self._h, xp, ldx, yp, ldy, X.shape[1], int(m),
                                                          int(passes), float(a), float(b), code))
         return Y
+
+    def set_cell_tile(self, prec: str, nsb: int):
+        """Column blocks (1 or 2) per tile of the reduced cell product for the
+        FP32-input ("fp32") or BF16-input ("bf16") cells."""
+        self._check(self.lib.chebfilter_set_cell_tile(self._h, PREC[prec], int(nsb)))
+
+    def autotune(self, X, m: int, a: float, b: float, prec="fp32", reps: int = 3, Y=None) -> int:
+        """Time both tile shapes on this filter, keep the faster; returns it."""
+        Y = self._out(X, Y)
+        (xp, ldx), (yp, ldy) = _block(X, "X"), _block(Y, "Y")
+        ch = C.c_int32(0)
+        self._check(self.lib.chebfilter_autotune(self._h, xp, ldx, yp, ldy, X.shape[1], int(m),
+                                                 float(a), float(b), PREC[prec], int(reps),
+                                                 C.byref(ch)))
+        return ch.value
 
     def cholqr(self, Y):
         yp, ldy = _block(Y, "Y")
@@ -395,6 +417,22 @@ class Batch:
         self._check(self.lib.chebfilter_filter_batch(self._h, xp, xl, yp, yl, xn, int(m), av, bv,
                                                      code, int(bool(use_graph))))
         return Y
+
+    def autotune(self, X, m: int, a, b, prec="fp32", reps: int = 3, Y=None) -> int:
+        """Time both tile shapes of the batched reduced cell product on this
+        batched filter, keep the faster; returns it."""
+        import torch
+        if Y is None:
+            Y = [torch.empty_like(x) for x in X]
+        xp, xl, xn = self._blocks(X, "X")
+        yp, yl, yn = self._blocks(Y, "Y")
+        n = self.count
+        av = (C.c_double * n)(*[float(v) for v in a])
+        bv = (C.c_double * n)(*[float(v) for v in b])
+        ch = C.c_int32(0)
+        self._check(self.lib.chebfilter_batch_autotune(self._h, xp, xl, yp, yl, xn, int(m), av, bv,
+                                                       PREC[prec], int(reps), C.byref(ch)))
+        return ch.value
 
     def rayleigh_ritz(self, Y):
         yp, yl, yn = self._blocks(Y, "Y")

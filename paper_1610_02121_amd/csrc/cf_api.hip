@@ -106,6 +106,9 @@ struct cf_ctx {
   // ones in FP32
   int32_t *cells_split = nullptr;
   std::vector<int> near_cnt;
+  // 16-column MFMA blocks per column tile of the reduced cell product, for
+  // the FP32-input cells [0] and the BF16-input cells [1] (chebfilter_autotune)
+  int lp_nsb[2] = {1, 2};
   // assembly of the plain cells' blocks: reference tables (shape values
   // [nq4][NPAD], weights [nq], kinetic block [NPAD][NPAD]), the uploaded cell
   // list and its host copy, which cells carry enrichment functions
@@ -402,12 +405,12 @@ static cf_status core_htilde_step_lp(cf_ctx *c, bool bf16, const float *Xin, int
     const int nfp = bf16 ? c->near_cnt[k] : cnt;
     if (nfp > 0) {
       Scope sc(c, "cell_gemm_fp32", fl * nfp);
-      HIPCHK(c, launch_cell_gemm_lp(c->stream, false, c->Hp32, c->dofp, c->flagp,
+      HIPCHK(c, launch_cell_gemm_lp(c->stream, false, c->lp_nsb[0], c->Hp32, c->dofp, c->flagp,
                                     c->cells_split + c0, nfp, Xin, ldxin, c->R32, mc, N, f));
     }
     if (cnt - nfp > 0) {
       Scope sc(c, "cell_gemm_bf16", fl * (cnt - nfp));
-      HIPCHK(c, launch_cell_gemm_lp(c->stream, true, c->Hp16, c->dofp, c->flagp,
+      HIPCHK(c, launch_cell_gemm_lp(c->stream, true, c->lp_nsb[1], c->Hp16, c->dofp, c->flagp,
                                     c->cells_split + c0 + nfp, cnt - nfp, Xin, ldxin, c->R32, mc, N,
                                     f));
     }
@@ -1140,7 +1143,10 @@ struct cf_batch {
   bool lowp_ready = false, bf16_ready = false;
   // graph of the batched filter, keyed by (m, prec)
   hipGraphExec_t gexec = nullptr;
-  int g_m = -1, g_prec = -1;
+  int g_m = -1, g_prec = -1, g_nsb = -1;
+  // column blocks per tile of the batched reduced cell product, FP32-input
+  // cells [0] and BF16-input cells [1] (chebfilter_batch_autotune)
+  int nsb[2] = {1, 2};
   hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_copy = nullptr;
   bool copy_pending = false;
   // batched projection and Lanczos (allocated on first use): per-entry status
@@ -1336,11 +1342,11 @@ static cf_status batch_enqueue_filter(cf_batch *b, int m, bool bf16) {
       if (bf16) {
         const int n0 = b->cell_off_near[col], n1 = b->cell_off_near[col + 1];
         const int f0 = b->cell_off_far[col], f1 = b->cell_off_far[col + 1];
-        BHIPCHK(b, launch_b_cell(s, false, b->d_bp, b->d_items + n0, n1 - n0, k));
-        BHIPCHK(b, launch_b_cell(s, true, b->d_bp, b->d_items + f0, f1 - f0, k));
+        BHIPCHK(b, launch_b_cell(s, false, b->nsb[0], b->d_bp, b->d_items + n0, n1 - n0, k));
+        BHIPCHK(b, launch_b_cell(s, true, b->nsb[1], b->d_bp, b->d_items + f0, f1 - f0, k));
       } else {
         const int a0 = b->cell_off_all[col], a1 = b->cell_off_all[col + 1];
-        BHIPCHK(b, launch_b_cell(s, false, b->d_bp, b->d_items + a0, a1 - a0, k));
+        BHIPCHK(b, launch_b_cell(s, false, b->nsb[0], b->d_bp, b->d_items + a0, a1 - a0, k));
       }
     }
     BHIPCHK(b, launch_b_enr(s, b->d_bp, b->count, b->d_eitems, b->neitems, b->d_aoff, b->nalpha,
@@ -1763,7 +1769,8 @@ cf_status chebfilter_filter_batch(cf_batch *b, const double *const *X, const int
   BHIPCHK(b, hipEventRecord(b->ev_copy, b->bs));
   b->copy_pending = true;
   if (use_graph) {
-    if (!b->gexec || b->g_m != m || b->g_prec != prec) {
+    const int nsb_key = 4 * b->nsb[0] + b->nsb[1];
+    if (!b->gexec || b->g_m != m || b->g_prec != prec || b->g_nsb != nsb_key) {
       if (b->gexec) { (void)hipGraphExecDestroy(b->gexec); b->gexec = nullptr; }
       hipGraph_t g = nullptr;
       BHIPCHK(b, hipStreamBeginCapture(b->bs, hipStreamCaptureModeThreadLocal));
@@ -1779,6 +1786,7 @@ cf_status chebfilter_filter_batch(cf_batch *b, const double *const *X, const int
       }
       b->g_m = m;
       b->g_prec = prec;
+      b->g_nsb = nsb_key;
     }
     BHIPCHK(b, hipGraphLaunch(b->gexec, b->bs));
   } else {
@@ -1786,6 +1794,86 @@ cf_status chebfilter_filter_batch(cf_batch *b, const double *const *X, const int
   }
   BHIPCHK(b, hipEventRecord(b->ev_out, b->bs));
   BHIPCHK(b, hipStreamWaitEvent(b->caller, b->ev_out, 0));
+  return CF_OK;
+}
+
+cf_status chebfilter_set_cell_tile(cf_ctx *c, int32_t prec, int32_t nsb) {
+  if (!c) return CF_EINVAL;
+  if (prec != CF_FP32 && prec != CF_BF16) return set_err(c, CF_EINVAL, "set_cell_tile: prec must be CF_FP32 or CF_BF16");
+  if (nsb != 1 && nsb != 2) return set_err(c, CF_EINVAL, "set_cell_tile: nsb must be 1 or 2");
+  c->lp_nsb[prec == CF_BF16 ? 1 : 0] = nsb;
+  return CF_OK;
+}
+
+// Time `reps` filters of each candidate block count after one warm-up, keep
+// the fastest (HIP events on the context's stream).
+cf_status chebfilter_autotune(cf_ctx *c, const double *X, int64_t ldx, double *Y, int64_t ldy,
+                              int64_t N, int32_t m, double a, double b, int32_t prec, int32_t reps,
+                              int32_t *choice) {
+  if (!c) return CF_EINVAL;
+  if (prec != CF_FP32 && prec != CF_BF16) return set_err(c, CF_EINVAL, "autotune: prec must be CF_FP32 or CF_BF16");
+  if (reps < 1 || m < 1) return set_err(c, CF_EINVAL, "autotune: need reps >= 1 and m >= 1");
+  HIPCHK(c, hipSetDevice(c->device));
+  const int slot = prec == CF_BF16 ? 1 : 0;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(c, hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return set_err(c, CF_EDEVICE, "autotune: event"); }
+  float best = 0.f;
+  int best_nsb = c->lp_nsb[slot];
+  cf_status st = CF_OK;
+  for (int nsb = 1; nsb <= 2 && st == CF_OK; ++nsb) {
+    c->lp_nsb[slot] = nsb;
+    st = chebfilter_filter(c, X, ldx, Y, ldy, N, m, a, b, prec);
+    if (st != CF_OK) break;
+    (void)hipEventRecord(e0, c->stream);
+    for (int r = 0; r < reps && st == CF_OK; ++r) st = chebfilter_filter(c, X, ldx, Y, ldy, N, m, a, b, prec);
+    (void)hipEventRecord(e1, c->stream);
+    (void)hipEventSynchronize(e1);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (nsb == 1 || ms < best) { best = ms; best_nsb = nsb; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c->lp_nsb[slot] = best_nsb;
+  if (st != CF_OK) return st;
+  if (choice) *choice = best_nsb;
+  return CF_OK;
+}
+
+cf_status chebfilter_batch_autotune(cf_batch *b, const double *const *X, const int64_t *ldx,
+                                    double *const *Y, const int64_t *ldy, const int64_t *N,
+                                    int32_t m, const double *a, const double *bu, int32_t prec,
+                                    int32_t reps, int32_t *choice) {
+  if (!b) return CF_EINVAL;
+  if (prec != CF_FP32 && prec != CF_BF16) return berr(b, CF_EINVAL, "batch_autotune: prec must be CF_FP32 or CF_BF16");
+  if (reps < 1 || m < 1) return berr(b, CF_EINVAL, "batch_autotune: need reps >= 1 and m >= 1");
+  BHIPCHK(b, hipSetDevice(b->device));
+  const int slot = prec == CF_BF16 ? 1 : 0;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  BHIPCHK(b, hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return berr(b, CF_EDEVICE, "batch_autotune: event"); }
+  float best = 0.f;
+  int best_nsb = b->nsb[slot];
+  cf_status st = CF_OK;
+  for (int nsb = 1; nsb <= 2 && st == CF_OK; ++nsb) {
+    b->nsb[slot] = nsb;
+    st = chebfilter_filter_batch(b, X, ldx, Y, ldy, N, m, a, bu, prec, 1);
+    if (st != CF_OK) break;
+    (void)hipEventRecord(e0, b->caller);
+    for (int r = 0; r < reps && st == CF_OK; ++r)
+      st = chebfilter_filter_batch(b, X, ldx, Y, ldy, N, m, a, bu, prec, 1);
+    (void)hipEventRecord(e1, b->caller);
+    (void)hipEventSynchronize(e1);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (nsb == 1 || ms < best) { best = ms; best_nsb = nsb; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  b->nsb[slot] = best_nsb;
+  if (st != CF_OK) return st;
+  if (choice) *choice = best_nsb;
   return CF_OK;
 }
 

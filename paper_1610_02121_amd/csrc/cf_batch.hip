@@ -62,7 +62,7 @@ __global__ void kb_lp_scale(const BatchProb *__restrict__ bp, int count, int k) 
   if (p < count) lp_scale_body(k, bp[p].lp_mx, bp[p].lp_s, bp[p].lp_mult);
 }
 
-template <bool BF16>
+template <bool BF16, int NSB>
 __global__ __launch_bounds__(512, 2) void kb_cell(const BatchProb *__restrict__ bp,
                                                   const BatchItem *__restrict__ items, int k) {
   const BatchItem it = items[blockIdx.x];
@@ -74,8 +74,8 @@ __global__ __launch_bounds__(512, 2) void kb_cell(const BatchProb *__restrict__ 
   f.Yp = b.Yp; f.ldyp = P.mc;
   f.Out = b.Out; f.ldo = P.mc;
   f.mult = b.mult; f.mx = b.mx;
-  cell_gemm_lp_body<BF16>(BF16 ? P.Hp16 : (const void *)P.Hp32, P.dofp, P.flagp, it.c, b.Xin, P.mc,
-                          P.R32, P.mc, P.N, f, blockIdx.x);
+  cell_gemm_lp_body<BF16, NSB>(BF16 ? P.Hp16 : (const void *)P.Hp32, P.dofp, P.flagp, it.c, b.Xin,
+                               P.mc, P.R32, P.mc, P.N, f, blockIdx.x);
 }
 
 __global__ __launch_bounds__(512, 2) void kb_enr_part(const BatchProb *__restrict__ bp,
@@ -179,13 +179,13 @@ hipError_t launch_b_lp_scale(hipStream_t s, const BatchProb *bp, int count, int 
   return hipGetLastError();
 }
 
-hipError_t launch_b_cell(hipStream_t s, bool bf16, const BatchProb *bp, const BatchItem *items,
-                         int nitems, int k) {
+hipError_t launch_b_cell(hipStream_t s, bool bf16, int nsb, const BatchProb *bp,
+                         const BatchItem *items, int nitems, int k) {
   if (nitems <= 0) return hipSuccess;
-  if (bf16)
-    hipLaunchKernelGGL(kb_cell<true>, dim3(nitems), dim3(512), 0, s, bp, items, k);
-  else
-    hipLaunchKernelGGL(kb_cell<false>, dim3(nitems), dim3(512), 0, s, bp, items, k);
+  if (nsb != 1 && nsb != 2) return hipErrorInvalidValue;
+  auto kern = bf16 ? (nsb == 2 ? kb_cell<true, 2> : kb_cell<true, 1>)
+                   : (nsb == 2 ? kb_cell<false, 2> : kb_cell<false, 1>);
+  hipLaunchKernelGGL(kern, dim3(nitems), dim3(512), 0, s, bp, items, k);
   return hipGetLastError();
 }
 

@@ -151,11 +151,12 @@ struct EpiArgsF {
   unsigned *mx = nullptr;
 };
 
-// As launch_cell_gemm; Hv is [E][NPAD][NPAD] float (bf16 = false) or __bf16 (bf16 = true).
-hipError_t launch_cell_gemm_lp(hipStream_t s, bool bf16, const void *Hv, const int32_t *dofp,
-                               const uint8_t *flagp, const int32_t *cells, int ncells,
-                               const float *X, int64_t ldx, float *Y, int64_t ldy, int N,
-                               const CellFinishF &f);
+// As launch_cell_gemm; Hv is [E][NPAD][NPAD] float (bf16 = false) or __bf16 (bf16 = true);
+// nsb (1 or 2): 16-column MFMA blocks per column tile (same results, different speed).
+hipError_t launch_cell_gemm_lp(hipStream_t s, bool bf16, int nsb, const void *Hv,
+                               const int32_t *dofp, const uint8_t *flagp, const int32_t *cells,
+                               int ncells, const float *X, int64_t ldx, float *Y, int64_t ldy,
+                               int N, const CellFinishF &f);
 // As launch_enr_part with FP32 blocks and vectors (rs stays FP64).
 hipError_t launch_enr_part_f32(hipStream_t s, const float *HT, const float *MT,
                                const int64_t *toff, const int32_t *tld, const int64_t *eptr,
@@ -237,8 +238,8 @@ struct BatchItem {
 hipError_t launch_b_lp_begin(hipStream_t s, const BatchProb *bp, int count, int nslots,
                              const int64_t *boff, int64_t nblocks);
 hipError_t launch_b_lp_scale(hipStream_t s, const BatchProb *bp, int count, int k);
-hipError_t launch_b_cell(hipStream_t s, bool bf16, const BatchProb *bp, const BatchItem *items,
-                         int nitems, int k);
+hipError_t launch_b_cell(hipStream_t s, bool bf16, int nsb, const BatchProb *bp,
+                         const BatchItem *items, int nitems, int k);
 hipError_t launch_b_enr(hipStream_t s, const BatchProb *bp, int count, const BatchItem *eitems,
                         int neitems, const int64_t *aoff, int64_t nalpha, int maxN, int kmax,
                         int k);

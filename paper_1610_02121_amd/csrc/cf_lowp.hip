@@ -10,26 +10,26 @@ namespace cf {
 
 using namespace lowp;
 
-template <bool BF16>
+template <bool BF16, int NSB>
 __global__ __launch_bounds__(512, 2) void k_cell_gemm_lp(
     const void *__restrict__ Hv, const int32_t *__restrict__ dofp,
     const uint8_t *__restrict__ flagp, const int32_t *__restrict__ cells,
     const float *__restrict__ X, int64_t ldx, float *__restrict__ Y, int64_t ldy, int N,
     const CellFinishF f) {
-  cell_gemm_lp_body<BF16>(Hv, dofp, flagp, cells[blockIdx.x], X, ldx, Y, ldy, N, f, blockIdx.x);
+  cell_gemm_lp_body<BF16, NSB>(Hv, dofp, flagp, cells[blockIdx.x], X, ldx, Y, ldy, N, f,
+                               blockIdx.x);
 }
 
-hipError_t launch_cell_gemm_lp(hipStream_t s, bool bf16, const void *Hv, const int32_t *dofp,
-                               const uint8_t *flagp, const int32_t *cells, int ncells,
-                               const float *X, int64_t ldx, float *Y, int64_t ldy, int N,
-                               const CellFinishF &f) {
+hipError_t launch_cell_gemm_lp(hipStream_t s, bool bf16, int nsb, const void *Hv,
+                               const int32_t *dofp, const uint8_t *flagp, const int32_t *cells,
+                               int ncells, const float *X, int64_t ldx, float *Y, int64_t ldy,
+                               int N, const CellFinishF &f) {
   if (ncells <= 0 || N <= 0) return hipSuccess;
-  if (bf16)
-    hipLaunchKernelGGL(k_cell_gemm_lp<true>, dim3(ncells), dim3(512), 0, s, Hv, dofp, flagp, cells,
-                       X, ldx, Y, ldy, N, f);
-  else
-    hipLaunchKernelGGL(k_cell_gemm_lp<false>, dim3(ncells), dim3(512), 0, s, Hv, dofp, flagp, cells,
-                       X, ldx, Y, ldy, N, f);
+  if (nsb != 1 && nsb != 2) return hipErrorInvalidValue;
+  auto kern = bf16 ? (nsb == 2 ? k_cell_gemm_lp<true, 2> : k_cell_gemm_lp<true, 1>)
+                   : (nsb == 2 ? k_cell_gemm_lp<false, 2> : k_cell_gemm_lp<false, 1>);
+  hipLaunchKernelGGL(kern, dim3(ncells), dim3(512), 0, s, Hv, dofp, flagp, cells, X, ldx, Y, ldy,
+                     N, f);
   return hipGetLastError();
 }
 

@@ -59,16 +59,16 @@ __device__ __forceinline__ void gather_max(unsigned *mx, float m, float *wbuf, i
 //                 4 k-steps
 // ---------------------------------------------------------------------------
 // One cell per workgroup of 512 threads; slot picks the max-gathering word.
-template <bool BF16>
+template <bool BF16, int NSB>
 __device__ __forceinline__ void cell_gemm_lp_body(
     const void *__restrict__ Hv, const int32_t *__restrict__ dofp,
     const uint8_t *__restrict__ flagp, const int cell,
     const float *__restrict__ X, int64_t ldx, float *__restrict__ Y, int64_t ldy, int N,
     const CellFinishF &f, int slot) {
-  // column tiles of NSB 16-column MFMA blocks: two for the BF16 form (32
-  // gathered FP32 values, one 128-byte line per row), one for the FP32 form
-  // (whose registers leave no room for a second block at this occupancy)
-  constexpr int NSB = BF16 ? 2 : 1;
+  // column tiles of NSB (1 or 2) 16-column MFMA blocks: two fill a 128-byte
+  // line per gathered row, one keeps the registers low (the faster choice
+  // depends on the form and the problem; the results are the same)
+  static_assert(NSB == 1 || NSB == 2, "one or two column blocks per tile");
   constexpr int NT = NSB * CELL_NT;
   constexpr int LDX = NT + 16;               // FP32 tile, row-major [k][col]
   constexpr int LDT = NPAD + 8;              // BF16 tile, column-major [col][k]

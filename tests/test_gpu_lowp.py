@@ -306,3 +306,33 @@ def test_reduced_degree_zero_copies(si_small):
     X = np.random.default_rng(34).standard_normal((ops.n, 5))
     for prec in ("fp32", "bf16"):
         assert np.array_equal(host(ctx.filter(dev(X), 0, -1.0, 5.0, prec=prec)), X)
+
+
+def test_cell_tile_shapes_agree_and_autotune(si_small):
+    """The reduced cell product's tile shape (one or two 16-column MFMA blocks
+    per column tile) is a launch parameter: both shapes give bit-identical
+    filters (37 columns: a ragged second block), and the autotuner returns one
+    of them without changing the results."""
+    from paper_1610_02121_amd import ChebFilterError, Context
+    print("[cell tile shapes]", flush=True)
+    prob = si_small
+    ctx = Context(prob, max_cols=40)
+    v0 = dev(np.random.default_rng(61).standard_normal(prob.n)).reshape(-1)
+    lo, hi = ctx.lanczos_bounds(v0, 10)
+    a, b = lo + 0.1 * (hi - lo), hi
+    X = dev(np.random.default_rng(62).standard_normal((prob.n, 37)))
+    for prec in ("fp32", "bf16"):
+        outs = []
+        for nsb in (1, 2):
+            ctx.set_cell_tile(prec, nsb)
+            outs.append(host(ctx.filter(X, 6, a, b, prec=prec)))
+        assert np.array_equal(outs[0], outs[1]), prec
+        ch = ctx.autotune(X, 6, a, b, prec=prec, reps=2)
+        print(f"  {prec}: autotuner chose {ch} block(s) per tile", flush=True)
+        assert ch in (1, 2)
+        assert np.array_equal(host(ctx.filter(X, 6, a, b, prec=prec)), outs[0]), prec
+    with pytest.raises(ChebFilterError, match="CF_EINVAL"):
+        ctx.set_cell_tile("fp64", 1)
+    with pytest.raises(ChebFilterError, match="CF_EINVAL"):
+        ctx.set_cell_tile("fp32", 3)
+    ctx.close()

@@ -34,13 +34,18 @@ __device__ inline void tile_of(int t, int N, int upper, int &ti, int &tj) {
 // Partial Gram: Gp[c][i][j] = sum over rows r of chunk c of A[r][i] B[r][j].
 // 1-D grid of nchunks * ntiles workgroups.  Workgroups that share a row chunk
 // are mapped to the same XCD (workgroups are dealt round-robin to the 8 XCDs
-// by index), so the chunk is fetched from HBM once into that XCD's L2.  Each
-// wave computes a 32 x 32 quarter of the 64 x 64 tile; both operands are read
-// straight from global memory (16 consecutive doubles per fragment row).
+// by index), so the chunk is fetched from HBM once into that XCD's L2.  The
+// tile's 64 columns of both operands pass through LDS in slabs of 32 rows
+// (loaded once per workgroup, the next slab prefetched in registers); each
+// wave computes a 32 x 32 quarter of the 64 x 64 tile from LDS.  The rows
+// are summed in the same order as a row-by-row MFMA walk.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_gram_partial(
     const double *__restrict__ A, int64_t lda, const double *__restrict__ B, int64_t ldb,
     int64_t n, int N, int nchunks, int64_t chunk_rows, int upper, double *__restrict__ Gp) {
+  constexpr int KS = 32, LDS = GT + 4;   // row slab, LDS row stride (doubles)
+  __shared__ double as[KS * LDS];
+  __shared__ double bs[KS * LDS];
   const int ntl = ntiles_of(N, upper);   // upper != 0: only tiles with ti <= tj
   const int bid = blockIdx.x;
   const int xcd = bid & 7, slot = bid >> 3;
@@ -51,38 +56,58 @@ __global__ __launch_bounds__(256) void k_gram_partial(
   tile_of(t, N, upper, ti, tj);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, kq = lane >> 4;
-  const int i0 = ti * GT + 32 * (w & 1), j0 = tj * GT + 32 * (w >> 1);
+  const int ci0 = ti * GT, cj0 = tj * GT;
+  const int wi = 32 * (w & 1), wj = 32 * (w >> 1);
   const int64_t r0 = (int64_t)chunk * chunk_rows;
   const int64_t r1 = min(n, r0 + chunk_rows);
   d4 acc[2][2];
   acc[0][0] = acc[0][1] = acc[1][0] = acc[1][1] = d4zero();
-  const bool iv0 = i0 + li < N, iv1 = i0 + 16 + li < N;
-  const bool jv0 = j0 + li < N, jv1 = j0 + 16 + li < N;
-  if (i0 < N && j0 < N) {
-#pragma unroll 4
-    for (int64_t r = r0 + kq; r < r0 + ((r1 - r0 + 3) & ~(int64_t)3); r += 4) {
-      const bool rv = r < r1;
-      const double *ar = A + r * lda + i0 + li;
-      const double *br = B + r * ldb + j0 + li;
-      const double a0 = (rv && iv0) ? ar[0] : 0.0;
-      const double a1 = (rv && iv1) ? ar[16] : 0.0;
-      const double b0 = (rv && jv0) ? br[0] : 0.0;
-      const double b1 = (rv && jv1) ? br[16] : 0.0;
-      acc[0][0] = mfma_f64(a0, b0, acc[0][0]);
-      acc[0][1] = mfma_f64(a0, b1, acc[0][1]);
-      acc[1][0] = mfma_f64(a1, b0, acc[1][0]);
-      acc[1][1] = mfma_f64(a1, b1, acc[1][1]);
+  const bool busy = ci0 + wi < N && cj0 + wj < N;
+  // cooperative slab load: column lc of the tile, rows lr + 4p
+  const int lc = tid & 63, lr = tid >> 6;
+  const bool cva = ci0 + lc < N, cvb = cj0 + lc < N;
+  double pa[KS / 4], pb[KS / 4];
+  auto load = [&](int64_t rs) {
+#pragma unroll
+    for (int p = 0; p < KS / 4; ++p) {
+      const int64_t r = rs + lr + 4 * p;
+      const bool v = r < r1;
+      pa[p] = (v && cva) ? A[r * lda + ci0 + lc] : 0.0;
+      pb[p] = (v && cvb) ? B[r * ldb + cj0 + lc] : 0.0;
     }
+  };
+  load(r0);
+  for (int64_t rs = r0; rs < r1; rs += KS) {
+#pragma unroll
+    for (int p = 0; p < KS / 4; ++p) {
+      as[(lr + 4 * p) * LDS + lc] = pa[p];
+      bs[(lr + 4 * p) * LDS + lc] = pb[p];
+    }
+    __syncthreads();
+    if (rs + KS < r1) load(rs + KS);
+    if (busy) {
+#pragma unroll
+      for (int ks = 0; ks < KS / 4; ++ks) {
+        const int kr = (4 * ks + kq) * LDS;
+        const double a0 = as[kr + wi + li], a1 = as[kr + wi + 16 + li];
+        const double b0 = bs[kr + wj + li], b1 = bs[kr + wj + 16 + li];
+        acc[0][0] = mfma_f64(a0, b0, acc[0][0]);
+        acc[0][1] = mfma_f64(a0, b1, acc[0][1]);
+        acc[1][0] = mfma_f64(a1, b0, acc[1][0]);
+        acc[1][1] = mfma_f64(a1, b1, acc[1][1]);
+      }
+    }
+    __syncthreads();
   }
   double *g = Gp + (int64_t)chunk * N * N;
 #pragma unroll
   for (int ib = 0; ib < 2; ++ib)
 #pragma unroll
     for (int jb = 0; jb < 2; ++jb) {
-      const int j = j0 + 16 * jb + li;
+      const int j = cj0 + wj + 16 * jb + li;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int i = i0 + 16 * ib + kq + 4 * r;
+        const int i = ci0 + wi + 16 * ib + kq + 4 * r;
         if (i < N && j < N) g[(int64_t)i * N + j] = acc[ib][jb][r];
       }
     }

@@ -440,15 +440,34 @@ __global__ __launch_bounds__(256) void k_enr_reduce(
   const int al = blockIdx.y;
   const bool cv = col < N;
   double sp = 0.0, sd = 0.0;
+  // the sums run in index order; the loads of 8 terms are issued before
+  // their adds (memory-level parallelism without changing the rounding)
+  constexpr int U = 8;
   if (P && cv) {
     const int64_t a0 = aptr[al], a1 = aptr[al + 1], len = a1 - a0;
     const int64_t q0 = a0 + (len * w) / 4, q1 = a0 + (len * (w + 1)) / 4;
-    for (int64_t k = q0; k < q1; ++k) sp += P[(int64_t)alist[k] * ldp + col];
+    int64_t k = q0;
+    for (; k + U <= q1; k += U) {
+      double t[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) t[u] = P[(int64_t)alist[k + u] * ldp + col];
+#pragma unroll
+      for (int u = 0; u < U; ++u) sp += t[u];
+    }
+    for (; k < q1; ++k) sp += P[(int64_t)alist[k] * ldp + col];
   }
   if (Dn && cv) {
     const double *drow = Dn + (int64_t)al * n_e;
     const int b0 = (n_e * w) / 4, b1 = (n_e * (w + 1)) / 4;
-    for (int be = b0; be < b1; ++be) sd += drow[be] * Zd[(int64_t)be * ldzd + col];
+    int be = b0;
+    for (; be + U <= b1; be += U) {
+      double t[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) t[u] = Zd[(int64_t)(be + u) * ldzd + col];
+#pragma unroll
+      for (int u = 0; u < U; ++u) sd += drow[be + u] * t[u];
+    }
+    for (; be < b1; ++be) sd += drow[be] * Zd[(int64_t)be * ldzd + col];
   }
   part[0][w][lane] = sp;
   part[1][w][lane] = sd;
@@ -483,11 +502,47 @@ hipError_t launch_enr_reduce(hipStream_t s, int n_e, const int64_t *aptr, const 
 //   Out[i] = c1 v + c2 Yk[i] + c3 Yp[i]       (null Yk / Yp skipped)
 // Out may alias R or Yp: each element is read before the same thread writes it.
 // ---------------------------------------------------------------------------
+// Below EPI_FEW_COLS columns one thread takes one element (rows across the
+// lanes) instead of 64 lanes sharing a row; the arithmetic of an element is
+// the same in both mappings.
+constexpr int EPI_FEW_COLS = 16;
+
 __global__ __launch_bounds__(256) void k_epilogue(const EpiArgs g) {
   // rows: all n_h + n_e rows, or the listed classical rows followed by the n_e
   // enrichment rows
   const int64_t ncls = g.rows ? g.nrows : g.n_h;
   const int64_t nt = ncls + g.n_e;
+  if (g.N < EPI_FEW_COLS) {
+    const int64_t total = nt * g.N;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.y * 64 + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * 256) {
+      const int64_t t = e / g.N;
+      const int j = (int)(e - t * g.N);
+      const bool cls = t < ncls;
+      const int64_t i = cls ? (g.rows ? (int64_t)g.rows[t] : t) : g.n_h + (t - ncls);
+      double v;
+      if (cls) {
+        const double dr = g.dR ? g.dR[i] : 1.0;
+        v = dr * g.R[i * g.ldr + j];
+        if (g.qptr) {
+          const int p0 = g.qptr[i], p1 = g.qptr[i + 1];
+          if (p1 > p0) {
+            const double dc = g.dC ? g.dC[i] : 1.0;
+            double sq = 0.0;
+            for (int p = p0; p < p1; ++p) sq += g.Q[(int64_t)g.qidx[p] * g.ldq + j];
+            v += dc * sq;
+          }
+        }
+      } else {
+        v = g.Ee[(i - g.n_h) * g.lde + j];
+      }
+      v *= g.c1;
+      if (g.Yk) v += g.c2 * g.Yk[i * g.ldyk + j];
+      if (g.Yp) v += g.c3 * g.Yp[i * g.ldyp + j];
+      g.Out[i * g.ldo + j] = v;
+    }
+    return;
+  }
   for (int64_t t = (int64_t)blockIdx.x * 4 + threadIdx.y; t < nt; t += (int64_t)gridDim.x * 4) {
     const bool cls = t < ncls;
     const int64_t i = cls ? (g.rows ? (int64_t)g.rows[t] : t) : g.n_h + (t - ncls);
@@ -521,7 +576,7 @@ __global__ __launch_bounds__(256) void k_epilogue(const EpiArgs g) {
 hipError_t launch_epilogue(hipStream_t s, const EpiArgs &g) {
   const int64_t n = (g.rows ? g.nrows : g.n_h) + g.n_e;
   if (n <= 0 || g.N <= 0) return hipSuccess;
-  int64_t blocks = (n + 3) / 4;
+  int64_t blocks = g.N < EPI_FEW_COLS ? (n * g.N + 255) / 256 : (n + 3) / 4;
   if (blocks > 65536) blocks = 65536;
   hipLaunchKernelGGL(k_epilogue, dim3((unsigned)blocks), dim3(64, 4), 0, s, g);
   return hipGetLastError();

@@ -28,8 +28,8 @@ PEAK_HBM = 8.0e12                 # MI355X HBM3E, B/s
 CELL_KERNEL = {"fp64": ("cell_gemm", "k_cell_gemm", PEAK_FP64_MFMA),
                "fp32": ("cell_gemm_fp32", "k_cell_gemm_lp<fp32>", PEAK_FP32_MFMA),
                "bf16": ("cell_gemm_bf16", "k_cell_gemm_lp<bf16>", PEAK_BF16_MFMA)}
-PROFILED = ("cell_gemm", "cell_gemm_fp32", "cell_gemm_bf16", "enr_part", "enr_reduce", "enr_q",
-            "enr_gemm", "epilogue", "gram", "rotate")
+PROFILED = ("cell_gemm", "cell_gemv", "cell_gemm_fp32", "cell_gemm_bf16", "enr_part", "enr_reduce",
+            "enr_q", "enr_gemm", "epilogue", "gram", "rotate")
 
 WORKLOADS = {
     # name: (generator, N, m, wanted)
@@ -803,9 +803,9 @@ def main():
     }
     key, kname, peak = CELL_KERNEL[args.prec]
     if prof and prof[key][0] > 0:
-        # every cell-product launch of the timed region, credited 2 npc^2 N flops per
-        # cell (for fp64 this includes the single-vector Lanczos and the Rayleigh-Ritz
-        # launches)
+        # every launch of the MFMA cell kernel in the timed region (the filter's and
+        # the Rayleigh-Ritz products; single-vector Lanczos products run k_cell_gemv),
+        # credited 2 npc^2 N flops per cell
         launches, ms, flops = prof[key]
         achieved = flops / (ms / 1e3)
         out["roofline"] = {"kernel": kname, "bound": "mfma", "achieved": achieved / 1e12,

@@ -187,10 +187,12 @@ cf_status chebfilter_lanczos_bounds(cf_ctx *ctx, const double *v0, int32_t k, do
 
 /* Per-kernel timing with HIP events on the context's stream.  enable != 0
  * starts recording (and clears the totals); name selects a kernel family
- * ("cell_gemm", "enr_gemm", "gram", "rotate", "epilogue").  The query returns
- * the number of timed launches, their summed duration and the algorithmic
- * flops credited to them (cell_gemm: 2 npc^2 N per cell; 0 where not
- * counted).  Synchronises on query. */
+ * ("cell_gemm": the MFMA cell products, N > 1; "cell_gemv": single-column
+ * cell products; "cell_gemm_fp32", "cell_gemm_bf16", "enr_part",
+ * "enr_reduce", "enr_q", "enr_gemm", "gram", "rotate", "epilogue",
+ * "assemble").  The query returns the number of timed launches, their summed
+ * duration and the algorithmic flops credited to them (cell products:
+ * 2 npc^2 N per cell; 0 where not counted).  Synchronises on query. */
 cf_status chebfilter_profile(cf_ctx *ctx, int32_t enable);
 cf_status chebfilter_profile_query(cf_ctx *ctx, const char *name, int64_t *launches,
                                    double *total_ms, double *total_flops);

@@ -200,8 +200,9 @@ static cf_status check_block(cf_ctx *c, const void *X, int64_t ldx, int64_t N, c
 static cf_status core_cells(cf_ctx *c, const double *X, int64_t ldx, double *Y, int64_t ldy, int N,
                             const CellFinish &f = CellFinish()) {
   for (size_t k = 0; k + 1 < c->col_off.size(); ++k) {
-    // elemental dense product: 2 npc^2 N flops per cell
-    Scope sc(c, "cell_gemm",
+    // elemental dense product: 2 npc^2 N flops per cell (single columns run the
+    // VALU kernel k_cell_gemv, timed under their own name)
+    Scope sc(c, N == 1 ? "cell_gemv" : "cell_gemm",
              2.0 * c->npc * c->npc * (double)N * (c->col_off[k + 1] - c->col_off[k]));
     HIPCHK(c, launch_cell_gemm(c->stream, c->Hp, c->dofp, c->flagp, c->cells + c->col_off[k],
                                c->col_off[k + 1] - c->col_off[k], X, ldx, Y, ldy, N, f));

@@ -21,6 +21,49 @@ __device__ __forceinline__ d4 mfma_f64(double a, double b, d4 c) {
 __device__ __forceinline__ d4 d4zero() { d4 z = {0.0, 0.0, 0.0, 0.0}; return z; }
 
 // ---------------------------------------------------------------------------
+// Classical cell products of one colour for a single column (the Lanczos
+// vectors), Y[dof(e,a)] (=|+=) sum_b H_e[a][b] X[dof(e,b)]: the cell matrix
+// streams through once, so the launch is bound by reading it, and the MFMA
+// kernel below (one workgroup per CU) would leave that stream latency-bound.
+// One 128-thread workgroup per cell (many per CU); thread i forms row i as an
+// FMA chain over k = 0..127, reading column i of the symmetric matrix (row k,
+// contiguous across the threads) and X[dof(e,k)] from LDS.  Flags and the
+// finishing step are those of k_cell_gemm.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(NPAD) void k_cell_gemv(
+    const double *__restrict__ Hp, const int32_t *__restrict__ dofp,
+    const uint8_t *__restrict__ flagp, const int32_t *__restrict__ cells,
+    const double *__restrict__ X, int64_t ldx, double *__restrict__ Y, int64_t ldy,
+    const CellFinish f) {
+  __shared__ double xs[NPAD];
+  const int i = threadIdx.x;
+  const int cell = cells[blockIdx.x];
+  const int d = dofp[(int64_t)cell * NPAD + i];
+  const uint8_t fl = flagp[(int64_t)cell * NPAD + i];
+  xs[i] = d >= 0 ? X[(int64_t)d * ldx] : 0.0;
+  __syncthreads();
+  const double *Hc = Hp + (int64_t)cell * NPAD * NPAD + i;
+  constexpr int U = 16;
+  double acc = 0.0;
+#pragma unroll 1
+  for (int k0 = 0; k0 < NPAD; k0 += U) {
+    double h[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) h[u] = Hc[(int64_t)(k0 + u) * NPAD];
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc = fma(h[u], xs[k0 + u], acc);
+  }
+  if (d < 0) return;
+  const double v = acc + ((fl & CELL_FIRST) ? 0.0 : Y[(int64_t)d * ldy]);
+  if (f.Out != nullptr && (fl & CELL_FINISH)) {
+    const double yp = f.Yp ? f.Yp[(int64_t)d * f.ldyp] : 0.0;
+    f.Out[(int64_t)d * f.ldo] = f.c1 * f.dinv[d] * v + f.c2 * xs[i] + f.c3 * yp;
+  } else {
+    Y[(int64_t)d * ldy] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Classical cell products for the cells of one colour:
 //   Y[dof(e,a)] (=|+=) sum_b H_e[a][b] X[dof(e,b)]
 // One workgroup of 8 waves per cell; wave w owns the 16 output rows
@@ -139,6 +182,11 @@ hipError_t launch_cell_gemm(hipStream_t s, const double *Hp, const int32_t *dofp
                             const double *X, int64_t ldx, double *Y, int64_t ldy, int N,
                             const CellFinish &f) {
   if (ncells <= 0 || N <= 0) return hipSuccess;
+  if (N == 1) {
+    hipLaunchKernelGGL(k_cell_gemv, dim3(ncells), dim3(NPAD), 0, s, Hp, dofp, flagp, cells, X,
+                       ldx, Y, ldy, f);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_cell_gemm, dim3(ncells), dim3(512), 0, s, Hp, dofp, flagp, cells, X, ldx,
                      Y, ldy, N, f);
   return hipGetLastError();

@@ -118,6 +118,25 @@ def test_filter(fix, m, request):
     assert relerr(Y, Yo) < 10 * U * kappa_M(fix, ops) * m
 
 
+@pytest.mark.parametrize("fix", FIXTURES)
+def test_filter_single_column_strided(fix, request):
+    """One column (the single-column cell kernel, with the recurrence fused
+    into it) taken from a wider block (leading dimension > 1)."""
+    print(f"[filter N=1 strided] {fix}", flush=True)
+    ctx, ops = context(fix, request.getfixturevalue(fix))
+    W = np.random.default_rng(15).standard_normal((ops.n, 6))
+    Wd = dev(W)
+    Out = torch.zeros((ops.n, 4), dtype=torch.float64, device="cuda")
+    m, a, b = 6, -1.0, 40.0
+    ctx.filter(Wd[:, 2:3], m, a, b, Out[:, 1:2])
+    o = host(Out)
+    Yo = recurrence_filter(lambda Z: ops.apply_Htilde(Z), W[:, 2:3], m, a, b)
+    assert relerr(o[:, 1:2], Yo) < 10 * U * kappa_M(fix, ops) * m
+    assert np.all(o[:, 0] == 0) and np.all(o[:, 2:] == 0)
+    Y1 = host(ctx.apply_H(Wd[:, 4:5]))
+    assert relerr(Y1, ops.apply_H(W[:, 4:5])) < 1e-12
+
+
 def test_filter_degree_zero_and_one(si_small):
     ctx, ops = context("si_small", si_small)
     X = np.random.default_rng(8).standard_normal((ops.n, 9))

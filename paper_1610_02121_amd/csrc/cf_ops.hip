@@ -315,12 +315,62 @@ __global__ __launch_bounds__(512, 2) void k_enr_part(
   }
 }
 
+// Single-column form (the Lanczos vectors): the coupling blocks stream
+// through once, so one 256-thread workgroup per enriched cell (many per CU)
+// with thread k forming output row k from row a of the transposed blocks
+// (contiguous across the threads) and the gathered X, s R values in LDS; the
+// two 64-node halves are summed separately and added as in k_enr_part.
+__global__ __launch_bounds__(256) void k_enr_part_vec(
+    const double *__restrict__ HT, const double *__restrict__ MT,
+    const int64_t *__restrict__ toff, const int32_t *__restrict__ tld,
+    const int64_t *__restrict__ eptr, const int32_t *__restrict__ dofp,
+    const int32_t *__restrict__ cells, const double *__restrict__ X, int64_t ldx, double cH,
+    const double *__restrict__ R, int64_t ldr, const double *__restrict__ rs, double cM,
+    double *__restrict__ P, int64_t ldp) {
+  __shared__ double xg[NPAD], rg[NPAD];
+  const int tid = threadIdx.x;
+  const int cell = cells[blockIdx.x];
+  if (tid < NPAD) {
+    const int d = dofp[(int64_t)cell * NPAD + tid];
+    xg[tid] = (X && d >= 0) ? X[(int64_t)d * ldx] : 0.0;
+    rg[tid] = (R && d >= 0) ? R[(int64_t)d * ldr] * (rs ? rs[d] : 1.0) : 0.0;
+  }
+  __syncthreads();
+  const int64_t k0 = eptr[cell];
+  const int na = (int)(eptr[cell + 1] - k0);
+  const int nap = tld[cell];
+  const double *ht = X ? HT + toff[cell] : nullptr;
+  const double *mt = R ? MT + toff[cell] : nullptr;
+  for (int k = tid; k < na; k += 256) {
+    double acc = 0.0;
+    for (int h = 0; h < 2; ++h) {
+      double sh = 0.0, sm = 0.0;
+      if (ht) {
+#pragma unroll 16
+        for (int a = 64 * h; a < 64 * h + 64; ++a) sh = fma(ht[(int64_t)a * nap + k], xg[a], sh);
+      }
+      if (mt) {
+#pragma unroll 16
+        for (int a = 64 * h; a < 64 * h + 64; ++a) sm = fma(mt[(int64_t)a * nap + k], rg[a], sm);
+      }
+      const double part = cH * sh + cM * sm;
+      acc = h == 0 ? part : acc + part;
+    }
+    P[(k0 + k) * ldp] = acc;
+  }
+}
+
 hipError_t launch_enr_part(hipStream_t s, const double *HT, const double *MT, const int64_t *toff,
                            const int32_t *tld, const int64_t *eptr, const int32_t *dofp,
                            const int32_t *cells, int ncells, const double *X, int64_t ldx,
                            double cH, const double *R, int64_t ldr, const double *rs, double cM,
                            double *P, int64_t ldp, int N) {
   if (ncells <= 0 || N <= 0) return hipSuccess;
+  if (N == 1) {
+    hipLaunchKernelGGL(k_enr_part_vec, dim3(ncells), dim3(256), 0, s, HT, MT, toff, tld, eptr,
+                       dofp, cells, X, ldx, cH, R, ldr, rs, cM, P, ldp);
+    return hipGetLastError();
+  }
   // one column range per cell (splitting the columns over 2-4 workgroups per
   // cell measured slower on the 30-atom workload: the blocks are re-read)
   hipLaunchKernelGGL(k_enr_part, dim3(ncells, 1), dim3(512), 0, s, HT, MT, toff, tld, eptr, dofp,
@@ -459,12 +509,58 @@ __global__ __launch_bounds__(256, 2) void k_enr_q(
   }
 }
 
+// Single-column form of k_enr_q: one 128-thread workgroup per enriched cell,
+// thread a forming Q row a from row k of the blocks (contiguous across the
+// threads) and the gathered cU U[idx_k], cV V[idx_k] in LDS, in chunks of 64
+// enrichment functions (each chunk's sum added to the previous ones, as the
+// MFMA kernel adds into Q); Q is written once.
+__global__ __launch_bounds__(NPAD) void k_enr_q_vec(
+    const double *__restrict__ Hec, const double *__restrict__ Mec,
+    const int64_t *__restrict__ eptr, const int32_t *__restrict__ eidx,
+    const int32_t *__restrict__ cells, const int32_t *__restrict__ order,
+    const double *__restrict__ U, int64_t ldu, double cU,
+    const double *__restrict__ V, int64_t ldv, double cV, double *__restrict__ Q, int64_t ldq) {
+  constexpr int KC = 64;
+  __shared__ double zu[KC], zv[KC];
+  const int a = threadIdx.x;
+  const int pos = order ? order[blockIdx.x] : (int)blockIdx.x;
+  const int cell = cells[pos];
+  const int64_t k0 = eptr[cell];
+  const int na = (int)(eptr[cell + 1] - k0);
+  double acc = 0.0;
+  for (int kc = 0; kc < na; kc += KC) {
+    const int kn = min(KC, na - kc);
+    if (a < KC) {
+      const bool v = a < kn;
+      const int64_t al = v ? eidx[k0 + kc + a] : 0;
+      zu[a] = (U && v) ? cU * U[al * ldu] : 0.0;
+      zv[a] = (V && v) ? cV * V[al * ldv] : 0.0;
+    }
+    __syncthreads();
+    double sc = 0.0;
+    if (U) {
+      for (int k = 0; k < kn; ++k) sc = fma(Hec[(k0 + kc + k) * NPAD + a], zu[k], sc);
+    }
+    if (V) {
+      for (int k = 0; k < kn; ++k) sc = fma(Mec[(k0 + kc + k) * NPAD + a], zv[k], sc);
+    }
+    acc = kc == 0 ? sc : sc + acc;
+    __syncthreads();
+  }
+  Q[((int64_t)pos * NPAD + a) * ldq] = acc;
+}
+
 hipError_t launch_enr_q(hipStream_t s, const double *Hec, const double *Mec, const int64_t *eptr,
                         const int32_t *eidx, const int32_t *cells, const int32_t *order,
                         int ncells, int kmax, const double *U, int64_t ldu, double cU,
                         const double *V, int64_t ldv, double cV, double *Q, int64_t ldq, int N) {
   if (ncells <= 0 || N <= 0) return hipSuccess;
   (void)kmax;
+  if (N == 1) {
+    hipLaunchKernelGGL(k_enr_q_vec, dim3(ncells), dim3(NPAD), 0, s, Hec, Mec, eptr, eidx, cells,
+                       order, U, ldu, cU, V, ldv, cV, Q, ldq);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_enr_q, dim3(ncells), dim3(256), 0, s, Hec, Mec, eptr, eidx, cells, order, U,
                      ldu, cU, V, ldv, cV, Q, ldq, N);
   return hipGetLastError();

@@ -49,7 +49,7 @@ typedef enum { CF_FP64 = 0, CF_FP32 = 1, CF_BF16 = 2 } cf_prec;
 /* Discrete problem.  HOST pointers, read during chebfilter_init only.
  * npc = (p+1)^3 local nodes per cell, x fastest. */
 typedef struct {
-  int32_t p;                 /* element degree; this build supports 1 <= p <= 4       */
+  int32_t p;                 /* element degree; the library supports 1 <= p <= 4     */
   int64_t n_cells;           /* E                                                      */
   int64_t n_h;               /* free classical DOFs                                    */
   int64_t n_e;               /* enrichment DOFs                                        */

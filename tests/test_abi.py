@@ -31,7 +31,7 @@ def test_header_declares_the_entry_points():
 def test_library_exports_every_declared_symbol():
     from paper_1610_02121_amd.binding import LIB_PATH, EXPORTS, load_library
     if not os.path.exists(LIB_PATH):
-        pytest.fail("libchebfilter.so is not built (run __graft_entry__.build())")
+        pytest.fail("libchebfilter.so is not built (run python paper_1610_02121_amd/build.py)")
     lib = load_library()
     for n in _declared():
         assert hasattr(lib, n), n

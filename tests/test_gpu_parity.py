@@ -137,6 +137,24 @@ def test_filter_single_column_strided(fix, request):
     assert relerr(Y1, ops.apply_H(W[:, 4:5])) < 1e-12
 
 
+@pytest.mark.parametrize("fix", FIXTURES)
+def test_single_column_kernels_match_block_kernels(fix, request):
+    """The single-column kernels (cell products, coupling partials, transposed
+    coupling) against the block kernels on the same column: H x, M x, M^-1 x
+    and a filter step agree to a few units of rounding (the sums run in
+    different orders)."""
+    print(f"[N=1 vs block] {fix}", flush=True)
+    ctx, ops = context(fix, request.getfixturevalue(fix))
+    W = dev(np.random.default_rng(16).standard_normal((ops.n, 17)))
+    col = W[:, 5:6].contiguous()
+    for name, f in (("H", ctx.apply_H), ("M", ctx.apply_M), ("Sinv", ctx.apply_Sinv),
+                    ("filter", lambda Z: ctx.filter(Z, 3, -1.0, 40.0))):
+        one = host(f(col))[:, 0]
+        blk = host(f(W))[:, 5]
+        tol = 1e-12 if name in ("H", "M") else 10 * U * kappa_M(fix, ops) * 3
+        assert np.abs(one - blk).max() <= tol * np.abs(blk).max(), name
+
+
 def test_filter_degree_zero_and_one(si_small):
     ctx, ops = context("si_small", si_small)
     X = np.random.default_rng(8).standard_normal((ops.n, 9))

@@ -1517,19 +1517,21 @@ cf_status chebfilter_filter_multipass(cf_ctx *c, const double *X, int64_t ldx, d
   if (X == Y) return set_err(c, CF_EINVAL, "filter_multipass: Y must not alias X");
   if (N == 0) return CF_OK;
   HIPCHK(c, hipSetDevice(c->device));
-  // passes alternate between Y and the work block U so that the last lands in Y
+  // every pass ends in Y; the next one reads a copy of Y in the work block U.
+  // U is free between calls (the projection keeps its orthonormal basis there
+  // only during its own call), and it must not be handed to the projection,
+  // whose Cholesky-QR and rotation read U while writing their output.
   const int64_t mc = c->max_cols;
-  auto out = [&](int i) -> double * { return ((passes - 1 - i) % 2 == 0) ? Y : c->U; };
-  auto ldo = [&](int i) -> int64_t { return ((passes - 1 - i) % 2 == 0) ? ldy : mc; };
   std::vector<double> theta((size_t)N);
-  STCHK(chebfilter_filter(c, X, ldx, out(0), ldo(0), N, m, a, b, prec));
+  STCHK(chebfilter_filter(c, X, ldx, Y, ldy, N, m, a, b, prec));
   for (int i = 1; i < passes; ++i) {
     // Rayleigh-Ritz between passes: the Ritz vectors keep each column aligned
     // with its own eigen-direction, so the next pass amplifies them one by
     // one (a triangular Cholesky-QR basis would mix them, and after a second
     // high-degree pass the columns would all lean towards the lowest one)
-    STCHK(chebfilter_rayleigh_ritz(c, out(i - 1), ldo(i - 1), N, theta.data()));
-    STCHK(chebfilter_filter(c, out(i - 1), ldo(i - 1), out(i), ldo(i), N, m, a, b, prec));
+    STCHK(chebfilter_rayleigh_ritz(c, Y, ldy, N, theta.data()));
+    HIPCHK(c, launch_copy(c->stream, c->n, (int)N, Y, ldy, c->U, mc));
+    STCHK(chebfilter_filter(c, c->U, mc, Y, ldy, N, m, a, b, prec));
   }
   return CF_OK;
 }

@@ -61,6 +61,34 @@ def test_classical_only(hydrogen_classical):
     ctx.close()
 
 
+@pytest.mark.parametrize("passes", [2, 3])
+def test_multipass_equals_passes_by_hand(si_small, passes):
+    """A wide block (several column tiles of the library's GEMMs): the
+    multi-pass entry equals the same passes done by hand through the
+    single-pass filter and Rayleigh-Ritz on caller buffers, bit for bit (the
+    entry must never hand its internal work block to the projection, which
+    reads that block while writing its output)."""
+    from paper_1610_02121_amd import Context
+    print(f"[multipass by hand] passes={passes}", flush=True)
+    N = 200
+    ctx = Context(si_small, max_cols=N)
+    ops = Operators(si_small)
+    v0 = np.random.default_rng(25).standard_normal(ops.n)
+    al, be = lanczos(ops.apply_Htilde, ops.apply_M, v0, 10)
+    lo, hi = lanczos_bounds(al, be)
+    a = lo + 0.3 * (hi - lo)
+    X = dev(np.random.default_rng(26).standard_normal((ops.n, N)))
+    m = 5
+    Ym = host(ctx.filter_multipass(X, m, passes, a, hi))
+    Z = ctx.filter(X, m, a, hi)
+    for _ in range(passes - 1):
+        ctx.rayleigh_ritz(Z)
+        Z = ctx.filter(Z.clone(), m, a, hi)
+    assert np.isfinite(Ym).all()
+    assert np.array_equal(Ym, host(Z))
+    ctx.close()
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_multipass_filter_spans_oracle(si_small, prec):
     """3 passes of degree 6 with Rayleigh-Ritz between them: the span equals the

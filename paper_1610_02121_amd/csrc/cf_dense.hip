@@ -63,6 +63,17 @@ __global__ __launch_bounds__(256) void k_gram_partial(
   d4 acc[2][2];
   acc[0][0] = acc[0][1] = acc[1][0] = acc[1][1] = d4zero();
   const bool busy = ci0 + wi < N && cj0 + wj < N;
+  // 16 x 16 blocks worth computing: inside N, and (upper mode) not entirely
+  // below the diagonal of a diagonal tile, whose entries the reduction never
+  // reads; a skipped block writes zeros that nothing reads
+  const bool ra[2] = {ci0 + wi < N, ci0 + wi + 16 < N};
+  const bool rb[2] = {cj0 + wj < N, cj0 + wj + 16 < N};
+  bool need[2][2];
+#pragma unroll
+  for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+    for (int jb = 0; jb < 2; ++jb)
+      need[ib][jb] = ra[ib] && rb[jb] && !(upper && ti == tj && wi + 16 * ib >= wj + 16 * jb + 16);
   // cooperative slab load: column lc of the tile, rows lr + 4p
   const int lc = tid & 63, lr = tid >> 6;
   const bool cva = ci0 + lc < N, cvb = cj0 + lc < N;
@@ -91,10 +102,10 @@ __global__ __launch_bounds__(256) void k_gram_partial(
         const int kr = (4 * ks + kq) * LDS;
         const double a0 = as[kr + wi + li], a1 = as[kr + wi + 16 + li];
         const double b0 = bs[kr + wj + li], b1 = bs[kr + wj + 16 + li];
-        acc[0][0] = mfma_f64(a0, b0, acc[0][0]);
-        acc[0][1] = mfma_f64(a0, b1, acc[0][1]);
-        acc[1][0] = mfma_f64(a1, b0, acc[1][0]);
-        acc[1][1] = mfma_f64(a1, b1, acc[1][1]);
+        if (need[0][0]) acc[0][0] = mfma_f64(a0, b0, acc[0][0]);
+        if (need[0][1]) acc[0][1] = mfma_f64(a0, b1, acc[0][1]);
+        if (need[1][0]) acc[1][0] = mfma_f64(a1, b0, acc[1][0]);
+        if (need[1][1]) acc[1][1] = mfma_f64(a1, b1, acc[1][1]);
       }
     }
     __syncthreads();

@@ -16,6 +16,10 @@ filters    Chebyshev polynomials, the three-term recurrence filter and the
            exact filter through the generalized eigendecomposition (Sec. V).
 subspace   Cholesky-QR, Rayleigh-Ritz, Lanczos spectrum bounds, one
            subspace-iteration step and the error metrics (Sec. V).
+cellwise   the same H^E X, M^E X and block-wise (M^E)^-1 summed cell by cell
+           from the element blocks (torch CPU, all host threads), for
+           problems whose global matrices do not fit: the fixed point of the
+           30-atom workload and the CPU baseline.
 mlp        the learned-bounds network: FP64 forward, backpropagated
            mean-squared-error gradient, Adam.
 assembly   the classical element block of a plain cell as the quadrature

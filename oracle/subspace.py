@@ -67,23 +67,34 @@ def lanczos_bounds(alpha: np.ndarray, beta: np.ndarray) -> tuple[float, float]:
 
 # ------------------------------------------------------------------ metrics
 def ritz_error(theta: np.ndarray, lam_ref: np.ndarray, wanted: int) -> float:
-    return float(np.max(np.abs(theta[:wanted] - lam_ref[:wanted])))
+    """max_{i < wanted} |theta_i - lambda_i| (both ascending)."""
+    return float(np.max(np.abs(np.asarray(theta)[:wanted] - np.asarray(lam_ref)[:wanted])))
 
 
 def energy_error(theta: np.ndarray, lam_ref: np.ndarray, wanted: int) -> float:
-    """2 |sum theta_i - sum lambda_i| over the wanted set (band energy, unit occupancy)."""
-    return float(2.0 * abs(np.sum(theta[:wanted]) - np.sum(lam_ref[:wanted])))
+    """2 |sum theta_i - sum lambda_i| over the wanted set: the band-energy
+    term sum_i f_i eps_i with two electrons per state (Sec. II, unit
+    occupancy below the wanted edge)."""
+    return float(2.0 * abs(np.sum(np.asarray(theta)[:wanted]) - np.sum(np.asarray(lam_ref)[:wanted])))
 
 
 def subspace_angle(A: np.ndarray, B: np.ndarray, M) -> float:
-    """Largest principal angle between span(A) and span(B) in the M inner product."""
+    """Largest principal angle between span(B) and span(A) in the inner
+    product <x, y>_M = x^T M y (dim span(B) <= dim span(A)).
+
+    With Qa, Qb M-orthonormal bases, the M-orthogonal projector onto span(A)
+    is Qa Qa^T M; the sine of the largest angle is the M-norm of what it
+    leaves of Qb: sin = ||(I - Qa Qa^T M) Qb||_M.  Taken as the arcsine (an
+    arccosine of the smallest cosine cannot resolve angles below ~1e-8)."""
     def orth(X):
         G = X.T @ (M @ X)
         Lc = sla.cholesky(0.5 * (G + G.T), lower=True)
         return sla.solve_triangular(Lc, X.T, lower=True).T
-    Qa, Qb = orth(A), orth(B)
-    s = np.linalg.svd(Qa.T @ (M @ Qb), compute_uv=False)
-    return float(np.arccos(np.clip(s.min(), -1.0, 1.0)))
+    Qa, Qb = orth(np.asarray(A, dtype=np.float64)), orth(np.asarray(B, dtype=np.float64))
+    Rb = Qb - Qa @ (Qa.T @ (M @ Qb))
+    G = Rb.T @ (M @ Rb)
+    s2 = float(np.linalg.eigvalsh(0.5 * (G + G.T))[-1])
+    return float(np.arcsin(min(1.0, np.sqrt(max(s2, 0.0)))))
 
 
 def scf_step(ops, X: np.ndarray, m: int, a: float, b: float, how: str = "block"):

@@ -96,12 +96,15 @@ def _pot_chunk(bounds):
 def potential_at_points(V, pts: np.ndarray, nproc: int | None = None,
                         chunk: int = 1 << 20) -> np.ndarray:
     """V at pts [Q, 3], in chunks over forked workers (V may be a closure;
-    the workers inherit it).  Values do not depend on the chunking."""
+    the workers inherit it), or in-process chunk by chunk once the GPU is
+    initialised.  Values do not depend on the chunking."""
     import multiprocessing as mp
     bounds = [(a, min(a + chunk, len(pts))) for a in range(0, len(pts), chunk)]
     nw = min(nproc or _workers(), len(bounds))
+    if gpu_initialised():
+        nw = 1
     if nw <= 1:
-        return V(pts)
+        return np.concatenate([V(pts[a:b]) for a, b in bounds]) if bounds else V(pts)
     _POT.update(V=V, pts=pts)
     try:
         with mp.get_context("fork").Pool(nw) as pool:
@@ -199,8 +202,29 @@ def _enriched_chunk(cells):
     return Hcc, Hec, Mec, (used, Hee), (used, Mee), stats
 
 
+def gpu_initialised() -> bool:
+    """True once this process holds the GPU driver open (an open /dev/kfd):
+    after any HIP call, and from the start under a profiler that initialises
+    the GPU before the program runs.  A forked child of such a process shares
+    the driver state, so the generator then works in-process."""
+    import os
+    try:
+        fds = os.listdir("/proc/self/fd")
+    except OSError:
+        return False
+    for fd in fds:
+        try:
+            if os.readlink(f"/proc/self/fd/{fd}") == "/dev/kfd":
+                return True
+        except OSError:
+            continue
+    return False
+
+
 def _workers() -> int:
     import os
+    if gpu_initialised():
+        return 1
     n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
     return max(1, min(16, n))
 
@@ -279,7 +303,7 @@ def assemble(mesh: Mesh, potential, enr: EnrichmentSet | None, ng: int = 6,
                   cell_atoms=cell_atoms, enr_ptr=enr_ptr, enr_idx=enr_idx, n_e=n_e, ng=ng,
                   max_depth=max_depth, blas_threads=1)
         chunks = [ecells[i:i + chunk] for i in range(0, ecells.size, chunk)]
-        nw = workers or _workers()
+        nw = 1 if gpu_initialised() else (workers or _workers())
         if nw > 1 and len(chunks) > 1:
             import multiprocessing as mp
             ctx = mp.get_context("fork")

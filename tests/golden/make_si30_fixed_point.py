@@ -1,0 +1,96 @@
+"""Writes tests/golden/si30_24c_ritz.txt: the fixed point of the
+Chebyshev-filtered subspace iteration (Sec. V) on the 30-atom Si workload
+(24^3 degree-4 cells, n = 857,645, N = 260, m = 40), computed by the oracle
+alone.
+
+Calls only `oracle/` (the cell-by-cell FP64 operators, Cholesky-QR,
+Rayleigh-Ritz, Lanczos bound) and `synth/` (the seeded problem and the
+atomic-orbital start block).  Steps: X <- RR(X0); b from 10 Lanczos steps of
+H~ in the M inner product (upper bound theta_max + ||f||_M); then repeat
+{filter of degree m on [a, b] with a = theta_N; Cholesky-QR; Rayleigh-Ritz}
+until every wanted Ritz pair (the lowest 210) has a relative residual
+||H z - theta M z||_2 / (||H z||_2 + |theta| ||M z||_2) <= 1e-11, or 40 steps.
+
+Usage: python tests/golden/make_si30_fixed_point.py [--threads T] [--out PATH]
+Takes ~1 h on 8 host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+N, M_DEG, WANTED, TOL, MAX_STEPS, SEED = 260, 40, 210, 1e-11, 40, 0
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--threads", type=int, default=0)
+    ap.add_argument("--out", default=os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                                                  "si30_24c_ritz.txt"))
+    ap.add_argument("--problem", default="", help="optional cached .npz of the generated problem")
+    args = ap.parse_args()
+    import torch
+    from oracle.cellwise import CellOperators
+    from oracle.filters import recurrence_filter
+    from oracle.subspace import cholqr, lanczos, lanczos_bounds, rayleigh_ritz
+    from synth import configs
+    from synth.problem import Problem
+
+    t0 = time.time()
+    if args.problem and os.path.exists(args.problem):
+        prob = Problem.load(args.problem)
+    else:
+        prob = configs.config2(seed=SEED)
+    ops = CellOperators(prob, threads=args.threads or None)
+    log = lambda s: print(f"[fixed-point {time.time() - t0:7.0f}s] {s}", flush=True)  # noqa: E731
+    log(f"n={prob.n} n_e={prob.n_e} threads={torch.get_num_threads()}")
+
+    def ritz(Y):
+        Q = cholqr(Y)
+        HQ, MQ = ops.apply_H(Q).numpy(), ops.apply_M(Q).numpy()
+        theta, C = rayleigh_ritz(Q, HQ, MQ)
+        Z, HZ, MZ = Q @ C, HQ @ C, MQ @ C
+        R = HZ - MZ * theta[None, :]
+        rel = np.linalg.norm(R, axis=0) / (np.linalg.norm(HZ, axis=0)
+                                           + np.abs(theta) * np.linalg.norm(MZ, axis=0))
+        return theta, Z, rel
+
+    X0 = configs.initial_block(prob, N, seed=SEED)
+    theta, X, rel = ritz(X0)
+    v0 = np.random.default_rng(SEED + 1).standard_normal(prob.n)
+    al, be = lanczos(lambda v: ops.apply_Htilde(v[:, None]).numpy()[:, 0],
+                     lambda v: ops.apply_M(v[:, None]).numpy()[:, 0], v0, 10)
+    _, b = lanczos_bounds(al, be)
+    log(f"start: theta_1={theta[0]:.10f} theta_N={theta[-1]:.6f} b={b:.6f}")
+    step = 0
+    while step < MAX_STEPS:
+        step += 1
+        Y = recurrence_filter(lambda Z: ops.apply_Htilde(Z).numpy(), X, M_DEG, float(theta[-1]), b)
+        theta, X, rel = ritz(Y)
+        log(f"step {step}: theta_1={theta[0]:.12f} theta_{WANTED}={theta[WANTED - 1]:.12f} "
+            f"max rel residual (wanted) {rel[:WANTED].max():.3e}")
+        if rel[:WANTED].max() <= TOL:
+            break
+    with open(args.out, "w") as f:
+        f.write("# Fixed point of the Chebyshev-filtered subspace iteration (Sec. V) on the 30-atom\n"
+                "# Si workload: config2(seed=0), 24^3 degree-4 cells, n = 857645 (n_e = 270),\n"
+                f"# N = {N}, m = {M_DEG}, atomic-orbital start, b = {b:.12g} (10-step Lanczos bound).\n"
+                "# Computed by the oracle only (oracle.cellwise, oracle.subspace) with\n"
+                "# tests/golden/make_si30_fixed_point.py; "
+                f"{step} steps, largest relative residual of the\n"
+                f"# {WANTED} wanted pairs {rel[:WANTED].max():.3e} (||Hz - theta Mz|| / (||Hz|| + |theta| ||Mz||)).\n"
+                "# i  theta_i (Ha)  relative residual\n")
+        for i in range(N):
+            f.write(f"{i:3d} {theta[i]: .17e} {rel[i]:.3e}\n")
+    log(f"wrote {args.out}")
+
+
+if __name__ == "__main__":
+    main()

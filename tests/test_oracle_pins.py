@@ -286,3 +286,75 @@ def test_sampled_rows_constant_potential_row_sums(si_small):
     Y = sampled_rows(prob, rows, X, "H", H_cc=blocks)[:, 0]
     D = np.asarray(prob.M_cc_diag)[rows]
     assert np.abs(Y - c * D).max() < 1e-12 * abs(c) * D.max()
+
+
+# ------------------------------------------------------------- error metrics
+def _angle_pair(t, n=9, seed=11):
+    """Euclidean spans with principal angles t (closed form): A = [e_1..e_k],
+    B = [cos t_i e_i + sin t_i e_{k+i}], rotated by a random orthogonal Q."""
+    k = len(t)
+    A = np.zeros((n, k))
+    B = np.zeros((n, k))
+    for i, ti in enumerate(t):
+        A[i, i] = 1.0
+        B[i, i] = np.cos(ti)
+        B[k + i, i] = np.sin(ti)
+    Q, _ = np.linalg.qr(np.random.default_rng(seed).standard_normal((n, n)))
+    G = np.random.default_rng(seed + 1).standard_normal((k, k)) + 3 * np.eye(k)   # any basis
+    return Q @ A @ G, Q @ B
+
+
+@pytest.mark.parametrize("t", [(0.3, 1e-9, 0.05), (1.2, 0.7, 0.2), (3e-11, 1e-12, 2e-12)])
+def test_subspace_angle_closed_form_euclidean(t):
+    """Largest principal angle = max t_i exactly, also below arccos's resolution
+    (a min/max mix-up returns the smallest t_i; arccos of the smallest
+    cosine returns 0 or ~1e-8 for the tiny angles; an arcsin/arccos swap
+    returns pi/2 - t)."""
+    A, B = _angle_pair(t)
+    got = subspace_angle(A, B, np.eye(A.shape[0]))
+    assert abs(got - max(t)) <= 1e-14 + 1e-9 * max(t)
+
+
+def test_subspace_angle_closed_form_M_weighted():
+    """In the M inner product, M = G^T G: angles between span(G^-1 A) and
+    span(G^-1 B) equal the Euclidean angles between span(A) and span(B)."""
+    t = (0.4, 0.02, 1e-7)
+    A, B = _angle_pair(t, n=10, seed=5)
+    G = np.random.default_rng(2).standard_normal((10, 10)) + 4 * np.eye(10)
+    Gi = np.linalg.inv(G)
+    M = G.T @ G
+    got = subspace_angle(Gi @ A, Gi @ B, M)
+    assert abs(got - 0.4) <= 1e-12
+    # the Euclidean angle of the same pair differs (the weight matters)
+    assert abs(subspace_angle(Gi @ A, Gi @ B, np.eye(10)) - 0.4) > 1e-3
+
+
+def test_ritz_and_energy_error_hand_computed():
+    """Hand-computed: theta = (-1, -0.5, 3), lambda = (-1.02, -0.45, 0),
+    two wanted: Ritz error max(0.02, 0.05) = 0.05; energy error
+    2 |(-1.5) - (-1.47)| = 0.06; the unwanted third pair is ignored."""
+    from oracle.subspace import energy_error, ritz_error
+    th = np.array([-1.0, -0.5, 3.0])
+    lam = np.array([-1.02, -0.45, 0.0])
+    assert abs(ritz_error(th, lam, 2) - 0.05) < 1e-15
+    assert abs(energy_error(th, lam, 2) - 0.06) < 1e-15
+    assert abs(ritz_error(th, lam, 3) - 3.0) < 1e-15
+
+
+# ------------------------------------------------------- cell-wise operators
+@pytest.mark.parametrize("fix", ["tiny_enriched", "si_small", "hydrogen_classical"])
+def test_cellwise_operators_equal_assembled(fix, request):
+    """The cell-by-cell products (used on problems whose global matrices do
+    not fit) against the assembled global H^E, M^E, the sparse direct solve
+    of M^E and the assembled Schur complement."""
+    from oracle.cellwise import CellOperators
+    prob = request.getfixturevalue(fix)
+    ops = _ops(prob)
+    co = CellOperators(prob)
+    X = np.random.default_rng(4).standard_normal((ops.n, 5))
+    for a, b in ((ops.apply_H(X), co.apply_H(X).numpy()), (ops.apply_M(X), co.apply_M(X).numpy())):
+        assert np.abs(a - b).max() <= 1e-13 * np.abs(a).max()
+    y = ops.solve_M(X)
+    assert np.abs(co.block_inverse(X).numpy() - y).max() <= 1e-10 * np.abs(y).max()
+    if prob.n_e:
+        assert np.abs(co.schur() - ops.schur()).max() <= 1e-13 * np.abs(ops.schur()).max()

@@ -15,8 +15,10 @@ host and use all of its cores:
   L = M^ec D^-1 and S = M^ee - M^ec D^-1 M^ec^T (dense Cholesky of S).
 
 Every product is a torch CPU matmul in FP64 (the library primitive is the
-step); no reordering beyond the grouping of cells into batches.  Nothing
-here is shared with the GPU library.
+step), applied to batches of cells; P_e drops the Dirichlet nodes, which is
+done here by zeroing their rows and columns in a copy of the cell blocks
+(their gathered values are then multiplied by zero and their sums are
+zero).  Nothing here is shared with the GPU library.
 """
 from __future__ import annotations
 
@@ -24,10 +26,13 @@ import numpy as np
 import scipy.linalg as sla
 import torch
 
-_BATCH = 1024          # cells per batched product (bounds the gathered rows)
+_BATCH = 1024          # cells per batched classical product
+_EBATCH = 128          # enriched cells per batched coupling product
 
 
 def _t(a, dtype=torch.float64):
+    if isinstance(a, torch.Tensor):
+        return a.to(dtype)
     return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype)
 
 
@@ -42,73 +47,92 @@ class CellOperators:
         self.n = self.n_h + self.n_e
         cd = np.asarray(prob.cell_dof, dtype=np.int64)
         self.E, self.npc = cd.shape
-        # Dirichlet nodes (-1) read and write a spare zero row n_h
-        self.idx = _t(np.where(cd >= 0, cd, self.n_h), torch.int64)
-        self.Hcc = _t(prob.H_cc).reshape(self.E, self.npc, self.npc)
+        live = torch.as_tensor(cd >= 0, dtype=torch.float64)          # [E, npc]
+        self.idx = torch.as_tensor(np.where(cd >= 0, cd, 0), dtype=torch.int64)
+        self.Hcc = _t(prob.H_cc).reshape(self.E, self.npc, self.npc).clone()
+        self.Hcc *= live[:, :, None]
+        self.Hcc *= live[:, None, :]
         self.D = _t(prob.M_cc_diag)
         self.Dinv = 1.0 / self.D
+        self._S = None
+        if self.n_e == 0:
+            return
+        # enriched cells in batches of similar function counts, blocks padded
+        # with zero rows whose enrichment index is the spare row n_e
         ep = np.asarray(prob.enr_ptr, dtype=np.int64)
-        self.ecells = np.nonzero(ep[1:] > ep[:-1])[0]
-        self.ep = ep
-        self.ei = _t(prob.enr_idx, torch.int64)
-        self.Hec = _t(prob.H_ec).reshape(-1, self.npc)
-        self.Mec = _t(prob.M_ec).reshape(-1, self.npc)
+        ei = np.asarray(prob.enr_idx, dtype=np.int64)
+        cnt = ep[1:] - ep[:-1]
+        ecells = np.nonzero(cnt > 0)[0]
+        ecells = ecells[np.argsort(-cnt[ecells], kind="stable")]
+        Hec = np.asarray(prob.H_ec).reshape(-1, self.npc)
+        Mec = np.asarray(prob.M_ec).reshape(-1, self.npc)
+        livec = cd >= 0
+        self.ebatches = []
+        for b0 in range(0, len(ecells), _EBATCH):
+            cells = ecells[b0:b0 + _EBATCH]
+            na = int(cnt[cells].max())
+            bh = np.zeros((len(cells), na, self.npc))
+            bm = np.zeros((len(cells), na, self.npc))
+            al = np.full((len(cells), na), self.n_e, dtype=np.int64)
+            for q, e in enumerate(cells):
+                r0, r1 = ep[e], ep[e + 1]
+                bh[q, :r1 - r0] = Hec[r0:r1] * livec[e][None, :]
+                bm[q, :r1 - r0] = Mec[r0:r1] * livec[e][None, :]
+                al[q, :r1 - r0] = ei[r0:r1]
+            self.ebatches.append((self.idx[torch.as_tensor(cells)], torch.as_tensor(al),
+                                  torch.as_tensor(bh), torch.as_tensor(bm)))
         self.Hee = _t(prob.H_ee).reshape(self.n_e, self.n_e)
         self.Mee = _t(prob.M_ee).reshape(self.n_e, self.n_e)
-        self._S = None
 
     # ---------------------------------------------------------------- pieces
-    def _padded(self, Xc: torch.Tensor) -> torch.Tensor:
-        return torch.cat([Xc, torch.zeros((1, Xc.shape[1]), dtype=Xc.dtype)], dim=0)
-
-    def cell_products(self, Xc: torch.Tensor) -> torch.Tensor:
-        """sum_e P_e^T H^cc_e P_e X_c (rows n_h)."""
-        Xp = self._padded(Xc)
-        Yp = torch.zeros_like(Xp)
+    def cell_products(self, Xc: torch.Tensor, out: torch.Tensor) -> None:
+        """out += sum_e P_e^T H^cc_e P_e X_c (out: n_h rows)."""
+        N = Xc.shape[1]
         for e0 in range(0, self.E, _BATCH):
             ix = self.idx[e0:e0 + _BATCH]
-            contrib = torch.bmm(self.Hcc[e0:e0 + _BATCH], Xp[ix])      # [b, npc, N]
-            Yp.index_add_(0, ix.reshape(-1), contrib.reshape(-1, Xp.shape[1]))
-        return Yp[:self.n_h]
+            contrib = torch.bmm(self.Hcc[e0:e0 + _BATCH], Xc[ix])        # [b, npc, N]
+            out.index_add_(0, ix.reshape(-1), contrib.reshape(-1, N))
 
-    def coupling(self, blocks: torch.Tensor, Xc: torch.Tensor) -> torch.Tensor:
-        """Assembled enriched-classical block times X_c: row alpha sums
-        B_e[alpha] . X_c[P_e] over the cells e whose support meets alpha."""
-        Xp = self._padded(Xc)
-        out = torch.zeros((self.n_e, Xc.shape[1]), dtype=Xc.dtype)
-        for e in self.ecells:
-            r0, r1 = self.ep[e], self.ep[e + 1]
-            out.index_add_(0, self.ei[r0:r1], blocks[r0:r1] @ Xp[self.idx[e]])
-        return out
+    def coupling(self, which: int, Xc: torch.Tensor) -> torch.Tensor:
+        """Assembled enriched-classical block times X_c (which: 2 = H^ec,
+        3 = M^ec): row alpha sums B_e[alpha] . X_c[P_e] over the cells e
+        whose support meets alpha."""
+        N = Xc.shape[1]
+        out = torch.zeros((self.n_e + 1, N), dtype=torch.float64)
+        for bt in self.ebatches:
+            ix, al, blk = bt[0], bt[1], bt[which]
+            out.index_add_(0, al.reshape(-1), torch.bmm(blk, Xc[ix]).reshape(-1, N))
+        return out[:self.n_e]
 
-    def coupling_T(self, blocks: torch.Tensor, Xe: torch.Tensor) -> torch.Tensor:
-        """Transpose of `coupling`: sum_e P_e^T B_e^T X_e[alpha(e)] (rows n_h)."""
-        Yp = torch.zeros((self.n_h + 1, Xe.shape[1]), dtype=Xe.dtype)
-        for e in self.ecells:
-            r0, r1 = self.ep[e], self.ep[e + 1]
-            Yp.index_add_(0, self.idx[e], blocks[r0:r1].T @ Xe[self.ei[r0:r1]])
-        return Yp[:self.n_h]
+    def coupling_T(self, which: int, Xe: torch.Tensor, out: torch.Tensor) -> None:
+        """out += transpose of `coupling` applied to X_e: sum_e P_e^T B_e^T X_e[alpha(e)]."""
+        N = Xe.shape[1]
+        Xp = torch.cat([Xe, torch.zeros((1, N), dtype=torch.float64)], dim=0)
+        for bt in self.ebatches:
+            ix, al, blk = bt[0], bt[1], bt[which]
+            contrib = torch.bmm(blk.transpose(1, 2), Xp[al])              # [b, npc, N]
+            out.index_add_(0, ix.reshape(-1), contrib.reshape(-1, N))
 
     # -------------------------------------------------------------- products
     def apply_H(self, X) -> torch.Tensor:
         X = _t(X)
+        Y = torch.zeros((self.n, X.shape[1]), dtype=torch.float64)
         Xc, Xe = X[:self.n_h], X[self.n_h:]
-        Yc = self.cell_products(Xc)
-        if self.n_e == 0:
-            return Yc
-        Yc = Yc + self.coupling_T(self.Hec, Xe)
-        Ye = self.coupling(self.Hec, Xc) + self.Hee @ Xe
-        return torch.cat([Yc, Ye], dim=0)
+        self.cell_products(Xc, Y[:self.n_h])
+        if self.n_e:
+            self.coupling_T(2, Xe, Y[:self.n_h])
+            Y[self.n_h:] = self.coupling(2, Xc) + self.Hee @ Xe
+        return Y
 
     def apply_M(self, X) -> torch.Tensor:
         X = _t(X)
+        Y = torch.empty((self.n, X.shape[1]), dtype=torch.float64)
         Xc, Xe = X[:self.n_h], X[self.n_h:]
-        Yc = self.D[:, None] * Xc
-        if self.n_e == 0:
-            return Yc
-        Yc = Yc + self.coupling_T(self.Mec, Xe)
-        Ye = self.coupling(self.Mec, Xc) + self.Mee @ Xe
-        return torch.cat([Yc, Ye], dim=0)
+        torch.mul(self.D[:, None], Xc, out=Y[:self.n_h])
+        if self.n_e:
+            self.coupling_T(3, Xe, Y[:self.n_h])
+            Y[self.n_h:] = self.coupling(3, Xc) + self.Mee @ Xe
+        return Y
 
     def schur(self) -> np.ndarray:
         """S = M^ee - M^ec D^-1 M^ec^T (Sec. IV.D), column by column of M^ec^T."""
@@ -116,8 +140,9 @@ class CellOperators:
             S = self.Mee.clone()
             I = torch.eye(self.n_e, dtype=torch.float64)
             for a0 in range(0, self.n_e, 256):
-                cols = self.coupling_T(self.Mec, I[:, a0:a0 + 256])      # M^ec^T e_alpha
-                S[:, a0:a0 + 256] -= self.coupling(self.Mec, self.Dinv[:, None] * cols)
+                cols = torch.zeros((self.n_h, I[:, a0:a0 + 256].shape[1]), dtype=torch.float64)
+                self.coupling_T(3, I[:, a0:a0 + 256], cols)                 # M^ec^T e_alpha
+                S[:, a0:a0 + 256] -= self.coupling(3, self.Dinv[:, None] * cols)
             S = 0.5 * (S + S.T)
             self._S = (S.numpy(), sla.cho_factor(S.numpy(), lower=True))
         return self._S[0]
@@ -129,17 +154,21 @@ class CellOperators:
         D^-1 r_c + L^T S^-1 L r_c - L^T S^-1 r_e = D^-1 r_c - L^T y_e (the
         common left factor L^T taken out: one transposed coupling product)."""
         R = _t(R)
+        Y = torch.empty_like(R)
+        rc, re = R[:self.n_h], R[self.n_h:]
         if self.n_e == 0:
-            return self.Dinv[:, None] * R
+            torch.mul(self.Dinv[:, None], rc, out=Y)
+            return Y
         self.schur()
         cho = self._S[1]
         Sinv = lambda B: torch.from_numpy(sla.cho_solve(cho, B.numpy()))   # noqa: E731
-        L = lambda Xc: self.coupling(self.Mec, self.Dinv[:, None] * Xc)      # noqa: E731
-        LT = lambda Ze: self.Dinv[:, None] * self.coupling_T(self.Mec, Ze)   # noqa: E731
-        rc, re = R[:self.n_h], R[self.n_h:]
-        ye = Sinv(re) - Sinv(L(rc))
-        yc = self.Dinv[:, None] * rc - LT(ye)
-        return torch.cat([yc, ye], dim=0)
+        L_rc = self.coupling(3, self.Dinv[:, None] * rc)                    # M^ec D^-1 r_c
+        ye = Sinv(re) - Sinv(L_rc)
+        Y[self.n_h:] = ye
+        t = torch.zeros_like(rc)
+        self.coupling_T(3, ye, t)                                          # M^ec^T y_e
+        torch.mul(self.Dinv[:, None], rc - t, out=Y[:self.n_h])           # D^-1 r_c - L^T y_e
+        return Y
 
     def apply_Htilde(self, X) -> torch.Tensor:
         return self.block_inverse(self.apply_H(X))

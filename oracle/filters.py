@@ -25,9 +25,10 @@ def recurrence_filter(apply_Htilde, X: np.ndarray, m: int, a: float, b: float) -
     """p_m(t(H~)) X by the three-term recurrence p_{k+1} = 2 t p_k - p_{k-1}."""
     if m < 0 or not b > a:
         raise ValueError("need m >= 0 and b > a")
-    X = np.asarray(X, dtype=np.float64)
+    if not hasattr(X, "clone"):       # numpy input (torch CPU tensors pass through)
+        X = np.asarray(X, dtype=np.float64)
     if m == 0:
-        return X.copy()
+        return X.clone() if hasattr(X, "clone") else X.copy()
     e = 2.0 / (b - a)             # t(H~) Y = e H~ Y - c Y
     c = (a + b) / (b - a)
     p_prev = X

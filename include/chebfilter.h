@@ -72,6 +72,12 @@ typedef struct {
   int32_t device;            /* HIP device ordinal                                     */
   void *stream;              /* hipStream_t to enqueue on (NULL = default stream)      */
   int64_t max_cols;          /* largest block width N any later call may pass          */
+  int64_t col_chunk;         /* columns of the internal work blocks (0 or >= max_cols:
+                                max_cols).  Wider blocks are processed in chunks of
+                                col_chunk columns (the filter and the products are
+                                column-independent; the projection works on column
+                                slabs), so device workspace grows with col_chunk, not
+                                with N.  Batches ignore it.                             */
   int32_t check_finite;      /* nonzero: filter/rayleigh_ritz check outputs for NaN/Inf */
 } cf_options;
 

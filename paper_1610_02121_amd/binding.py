@@ -46,7 +46,7 @@ class CfProblem(C.Structure):
 
 class CfOptions(C.Structure):
     _fields_ = [("device", C.c_int32), ("stream", C.c_void_p), ("max_cols", C.c_int64),
-                ("check_finite", C.c_int32)]
+                ("col_chunk", C.c_int64), ("check_finite", C.c_int32)]
 
 
 class ChebFilterError(RuntimeError):
@@ -160,14 +160,16 @@ def _problem_struct(prob):
 class Context:
     """One discrete problem resident on one GPU (wraps cf_ctx)."""
 
-    def __init__(self, prob, max_cols: int, device: int = 0, check_finite: bool = False):
+    def __init__(self, prob, max_cols: int, device: int = 0, check_finite: bool = False,
+                 col_chunk: int = 0):
         import torch
         self.lib = load_library()
         cp, self._keep = _problem_struct(prob)
         self.device = torch.device("cuda", device)
         stream = torch.cuda.current_stream(self.device)
         self.stream = stream
-        opt = CfOptions(device, C.c_void_p(stream.cuda_stream), int(max_cols), int(check_finite))
+        opt = CfOptions(device, C.c_void_p(stream.cuda_stream), int(max_cols), int(col_chunk),
+                        int(check_finite))
         h = C.c_void_p()
         st = self.lib.chebfilter_init(C.byref(cp), C.byref(opt), C.byref(h))
         if st != 0:
@@ -362,7 +364,7 @@ class Batch:
         self.device = torch.device("cuda", device)
         stream = torch.cuda.current_stream(self.device)
         self.stream = stream
-        opt = CfOptions(device, C.c_void_p(stream.cuda_stream), int(max_cols), 0)
+        opt = CfOptions(device, C.c_void_p(stream.cuda_stream), int(max_cols), 0, 0)
         h = C.c_void_p()
         st = self.lib.chebfilter_init_batch(ptrs, len(probs), C.byref(opt), C.byref(h))
         if st != 0:

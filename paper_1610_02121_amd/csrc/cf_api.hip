@@ -44,6 +44,9 @@ struct cf_ctx {
   hipStream_t stream = nullptr;
   int p = 0, npc = 0;
   int64_t E = 0, n_h = 0, n_e = 0, n = 0, max_cols = 0;
+  // columns of the work blocks (the column chunk): blocks wider than this
+  // are processed chunk by chunk
+  int64_t ldw = 0;
   int check_finite = 0;
   // classical cells
   double *Hp = nullptr;
@@ -74,10 +77,10 @@ struct cf_ctx {
   double *Hec = nullptr, *Mec = nullptr;   // per-cell blocks, rows padded to NPAD
   int32_t *eidx = nullptr;
   int32_t *qptr = nullptr, *qidx = nullptr; // classical DOF -> rows of the cell buffer Q
-  double *Q = nullptr;                      // [necells * NPAD][max_cols]
+  double *Q = nullptr;                      // [necells * NPAD][ldw]
   int64_t csr_nnz = 0, nreg = 0;
   double *Hee = nullptr, *Mee = nullptr, *Sinv = nullptr, *Hmod = nullptr;
-  // block workspace, leading dimension max_cols
+  // block workspace, leading dimension ldw
   double *R = nullptr, *P = nullptr, *Wb = nullptr, *Zb = nullptr, *B2 = nullptr, *T = nullptr,
          *U = nullptr;
   // small dense workspace
@@ -90,7 +93,7 @@ struct cf_ctx {
   double *lzv = nullptr, *lzcoef = nullptr, *lzpart = nullptr;
   // reduced-precision filter state, allocated on the first CF_FP32 / CF_BF16
   // filter call: FP32 (or BF16) copies of the cell matrices, FP32 copies of
-  // the coupling blocks and FP32 recurrence blocks (ld = max_cols)
+  // the coupling blocks and FP32 recurrence blocks (ld = ldw)
   int64_t ttot = 0;
   float *Hp32 = nullptr;
   void *Hp16 = nullptr;
@@ -219,7 +222,7 @@ static EpiArgs epi_base(cf_ctx *c, int N) {
     g.qptr = c->qptr;
     g.qidx = c->qidx;
     g.Q = c->Q;
-    g.ldq = c->max_cols;
+    g.ldq = c->ldw;
   }
   return g;
 }
@@ -230,7 +233,7 @@ static cf_status core_enr_q(cf_ctx *c, const double *U, int64_t ldu, double cU, 
   Scope sc(c, "enr_q");
   HIPCHK(c, launch_enr_q(c->stream, c->Hec, c->Mec, c->eptr, c->eidx, c->ecells, c->epos_part,
                          c->necells, c->kmax,
-                         U, ldu, cU, V, ldv, cV, c->Q, c->max_cols, N));
+                         U, ldu, cU, V, ldv, cV, c->Q, c->ldw, N));
   return CF_OK;
 }
 
@@ -244,9 +247,9 @@ static cf_status core_apply_H(cf_ctx *c, const double *X, int64_t ldx, double *Y
   {
     Scope sc(c, "enr_gemm");
     HIPCHK(c, launch_enr_part(c->stream, c->HT, c->MT, c->toff, c->tld, c->eptr, c->dofp, c->ecells_part,
-                              c->necells, X, ldx, 1.0, nullptr, 0, nullptr, 0.0, c->P, c->max_cols,
+                              c->necells, X, ldx, 1.0, nullptr, 0, nullptr, 0.0, c->P, c->ldw,
                               N));
-    HIPCHK(c, launch_enr_reduce(c->stream, (int)c->n_e, c->aptr, c->alist, c->P, c->max_cols, 1.0,
+    HIPCHK(c, launch_enr_reduce(c->stream, (int)c->n_e, c->aptr, c->alist, c->P, c->ldw, 1.0,
                                 nullptr, 0, 0.0, c->Hee, Xe, ldx, Ye, ldy, N));
   }
   STCHK(core_enr_q(c, Xe, ldx, 1.0, nullptr, 0, 0.0, N));
@@ -267,9 +270,9 @@ static cf_status core_apply_M(cf_ctx *c, const double *X, int64_t ldx, double *Y
   if (c->n_e > 0) {
     Scope sc(c, "enr_gemm");
     HIPCHK(c, launch_enr_part(c->stream, c->HT, c->MT, c->toff, c->tld, c->eptr, c->dofp, c->ecells_part,
-                              c->necells, nullptr, 0, 0.0, X, ldx, nullptr, 1.0, c->P, c->max_cols,
+                              c->necells, nullptr, 0, 0.0, X, ldx, nullptr, 1.0, c->P, c->ldw,
                               N));
-    HIPCHK(c, launch_enr_reduce(c->stream, (int)c->n_e, c->aptr, c->alist, c->P, c->max_cols, 1.0,
+    HIPCHK(c, launch_enr_reduce(c->stream, (int)c->n_e, c->aptr, c->alist, c->P, c->ldw, 1.0,
                                 nullptr, 0, 0.0, c->Mee, Xe, ldx, Ye, ldy, N));
     STCHK(core_enr_q(c, nullptr, 0, 0.0, Xe, ldx, 1.0, N));
   }
@@ -286,7 +289,30 @@ static cf_status core_apply_M(cf_ctx *c, const double *X, int64_t ldx, double *Y
 static cf_status core_schur_solve(cf_ctx *c, int N) {
   Scope sc(c, "enr_reduce");
   HIPCHK(c, launch_enr_reduce(c->stream, (int)c->n_e, c->aptr, c->alist, nullptr, 0, 0.0, nullptr, 0,
-                              0.0, c->Sinv, c->Wb, c->max_cols, c->Zb, c->max_cols, N));
+                              0.0, c->Sinv, c->Wb, c->ldw, c->Zb, c->ldw, N));
+  return CF_OK;
+}
+
+// Y = (M^E)^-1 X (block-wise inverse, Sec. IV.D) for n <= ldw columns:
+// w = x_e - M^ec D^-1 x_c, z = S^-1 w, y_c = D^-1 (x_c - M^ec^T z), y_e = z.
+static cf_status core_apply_Sinv(cf_ctx *c, const double *X, int64_t ldx, double *Y, int64_t ldy,
+                                 int n) {
+  if (c->n_e > 0) {
+    Scope sc(c, "enr_gemm");
+    HIPCHK(c, launch_enr_part(c->stream, c->HT, c->MT, c->toff, c->tld, c->eptr, c->dofp, c->ecells_part,
+                              c->necells, nullptr, 0, 0.0, X, ldx, c->dinv, -1.0, c->P, c->ldw,
+                              n));
+    HIPCHK(c, launch_enr_reduce(c->stream, (int)c->n_e, c->aptr, c->alist, c->P, c->ldw, 1.0,
+                                X + c->n_h * ldx, ldx, 1.0, nullptr, nullptr, 0, c->Wb, c->ldw,
+                                n));
+    STCHK(core_schur_solve(c, n));
+    STCHK(core_enr_q(c, nullptr, 0, 0.0, c->Zb, c->ldw, -1.0, n));
+  }
+  EpiArgs g = epi_base(c, n);
+  g.R = X; g.ldr = ldx; g.dR = c->dinv; g.dC = c->dinv;
+  g.Ee = c->Zb; g.lde = c->ldw;
+  g.Out = Y; g.ldo = ldy;
+  HIPCHK(c, launch_epilogue(c->stream, g));
   return CF_OK;
 }
 
@@ -298,7 +324,7 @@ static cf_status core_schur_solve(cf_ctx *c, int N) {
 static cf_status core_htilde_step(cf_ctx *c, const double *Xin, int64_t ldxin, int N, double c1,
                                   const double *Yk, int64_t ldyk, double c2, const double *Yp,
                                   int64_t ldyp, double c3, double *Out, int64_t ldo) {
-  const int64_t ldr = c->max_cols;
+  const int64_t ldr = c->ldw;
   // rows outside the enriched region are finished by the cell kernel (it holds
   // X = Y_k in LDS, so this needs Yk to be Xin or absent)
   const bool finish = Yk == nullptr || (Yk == Xin && ldyk == ldxin);
@@ -316,19 +342,19 @@ static cf_status core_htilde_step(cf_ctx *c, const double *Xin, int64_t ldxin, i
       Scope sc(c, "enr_part");
       HIPCHK(c, launch_enr_part(c->stream, c->HT, c->MT, c->toff, c->tld, c->eptr, c->dofp,
                                 c->ecells_part, c->necells, Xin, ldxin, 1.0, c->R, ldr, c->dinv, -1.0,
-                                c->P, c->max_cols, N));
+                                c->P, c->ldw, N));
     }
     {
       Scope sc(c, "enr_reduce");
-      HIPCHK(c, launch_enr_reduce(c->stream, (int)c->n_e, c->aptr, c->alist, c->P, c->max_cols, 1.0,
-                                  nullptr, 0, 0.0, c->Hmod, Xe, ldxin, c->Wb, c->max_cols, N));
+      HIPCHK(c, launch_enr_reduce(c->stream, (int)c->n_e, c->aptr, c->alist, c->P, c->ldw, 1.0,
+                                  nullptr, 0, 0.0, c->Hmod, Xe, ldxin, c->Wb, c->ldw, N));
     }
     STCHK(core_schur_solve(c, N));
-    STCHK(core_enr_q(c, Xe, ldxin, 1.0, c->Zb, c->max_cols, -1.0, N));
+    STCHK(core_enr_q(c, Xe, ldxin, 1.0, c->Zb, c->ldw, -1.0, N));
   }
   EpiArgs g = epi_base(c, N);
   g.R = c->R; g.ldr = ldr; g.dR = c->dinv; g.dC = c->dinv;
-  g.Ee = c->Zb; g.lde = c->max_cols;
+  g.Ee = c->Zb; g.lde = c->ldw;
   g.c1 = c1; g.Yk = Yk; g.ldyk = ldyk; g.c2 = c2; g.Yp = Yp; g.ldyp = ldyp; g.c3 = c3;
   g.Out = Out; g.ldo = ldo;
   if (finish) { g.rows = c->regrows; g.nrows = c->nregrows; }
@@ -340,7 +366,7 @@ static cf_status core_htilde_step(cf_ctx *c, const double *Xin, int64_t ldxin, i
 // Reduced-precision copies of the operator and FP32 workspace (once per
 // context and precision).
 static cf_status ensure_lowp(cf_ctx *c, bool bf16) {
-  const int64_t mc = c->max_cols;
+  const int64_t mc = c->ldw;
   if (!c->F0) {
     STCHK(dalloc(c, &c->F0, (size_t)c->n * mc));
     STCHK(dalloc(c, &c->F1, (size_t)c->n * mc));
@@ -392,7 +418,7 @@ static cf_status ensure_lp_scale(cf_ctx *c, int m) {
 static cf_status core_htilde_step_lp(cf_ctx *c, bool bf16, const float *Xin, int64_t ldxin, int N,
                                      float c1, float c2, const float *Yp, int64_t ldyp, float c3,
                                      float *Out, int64_t ldo, const float *mult, unsigned *mx) {
-  const int64_t mc = c->max_cols;
+  const int64_t mc = c->ldw;
   CellFinishF f;
   f.dinv = c->dinv;
   f.c1 = c1; f.c2 = c2; f.c3 = Yp ? c3 : 0.f;
@@ -455,16 +481,31 @@ static cf_status core_htilde_step_lp(cf_ctx *c, bool bf16, const float *Xin, int
 }
 
 // Out = In * W for row-major n x N blocks and a row-major N x N W (ld N):
-// a plain library GEMM (column-major view: Out^T = W^T In^T).
+// a plain library GEMM (column-major view: Out^T = W^T In^T).  In == Out
+// (same ld) rotates in place by row blocks through the work block T, viewed
+// as rb x N with rb = n ldw / N rows (one block when N <= ldw).
 static cf_status core_rotate(cf_ctx *c, const double *In, int64_t ldi, const double *W, int N,
                              double *Out, int64_t ldo) {
   Scope sc(c, "rotate", 2.0 * (double)c->n * N * N);
   const double one = 1.0, zero = 0.0;
   rocblas_set_pointer_mode(c->rb, rocblas_pointer_mode_host);
-  if (rocblas_dgemm(c->rb, rocblas_operation_none, rocblas_operation_none, N, (rocblas_int)c->n, N,
-                    &one, W, N, In, (rocblas_int)ldi, &zero, Out, (rocblas_int)ldo) !=
-      rocblas_status_success)
-    return set_err(c, CF_EDEVICE, "rotate: rocblas_dgemm failed");
+  if (In != Out) {
+    if (rocblas_dgemm(c->rb, rocblas_operation_none, rocblas_operation_none, N, (rocblas_int)c->n,
+                      N, &one, W, N, In, (rocblas_int)ldi, &zero, Out, (rocblas_int)ldo) !=
+        rocblas_status_success)
+      return set_err(c, CF_EDEVICE, "rotate: rocblas_dgemm failed");
+    return CF_OK;
+  }
+  if (ldi != ldo) return set_err(c, CF_EINVAL, "rotate: in-place rotation needs one leading dimension");
+  const int64_t rb = std::max<int64_t>(1, std::min<int64_t>(c->n, (c->n * c->ldw) / N));
+  for (int64_t r0 = 0; r0 < c->n; r0 += rb) {
+    const int64_t rows = std::min(rb, c->n - r0);
+    if (rocblas_dgemm(c->rb, rocblas_operation_none, rocblas_operation_none, N, (rocblas_int)rows,
+                      N, &one, W, N, In + r0 * ldi, (rocblas_int)ldi, &zero, c->T, N) !=
+        rocblas_status_success)
+      return set_err(c, CF_EDEVICE, "rotate: rocblas_dgemm failed");
+    HIPCHK(c, launch_copy(c->stream, rows, N, c->T, N, Out + r0 * ldo, ldo));
+  }
   return CF_OK;
 }
 
@@ -474,8 +515,21 @@ static cf_status core_gram(cf_ctx *c, const double *A, int64_t lda, const double
   Scope sc(c, "gram");
   const int nch = c->gp_chunks;
   const int64_t chunk_rows = (nrows + nch - 1) / nch;
-  HIPCHK(c, launch_gram_partial(c->stream, A, lda, B, ldb, nrows, N, nch, chunk_rows, c->Gp, mode));
-  HIPCHK(c, launch_gram_reduce(c->stream, c->Gp, nch, N, Gout, mode));
+  HIPCHK(c, launch_gram_partial(c->stream, A, lda, B, ldb, nrows, N, N, nch, chunk_rows, c->Gp,
+                                mode));
+  HIPCHK(c, launch_gram_reduce(c->stream, c->Gp, nch, N, N, Gout, N, mode));
+  return CF_OK;
+}
+
+// Slab of a Gram matrix: G[i][j] (ld ldg) = (A^T B)[i][j], i < Na, j < Nb.
+static cf_status core_gram_slab(cf_ctx *c, const double *A, int64_t lda, int Na, const double *B,
+                                int64_t ldb, int Nb, double *Gout, int64_t ldg) {
+  Scope sc(c, "gram");
+  const int nch = c->gp_chunks;
+  const int64_t chunk_rows = (c->n + nch - 1) / nch;
+  HIPCHK(c, launch_gram_partial(c->stream, A, lda, B, ldb, c->n, Na, Nb, nch, chunk_rows, c->Gp,
+                                GRAM_FULL));
+  HIPCHK(c, launch_gram_reduce(c->stream, c->Gp, nch, Na, Nb, Gout, ldg, GRAM_FULL));
   return CF_OK;
 }
 
@@ -503,11 +557,28 @@ static cf_status core_cholqr_pass(cf_ctx *c, const double *In, int64_t ldi, doub
 }
 
 // Orthonormalise In into Out through the scratch blocks T and R (In may equal
-// Out; Out must not be T or R).
+// Out; Out must not be T or R).  Blocks wider than the work blocks are
+// orthonormalised in place in Out (every pass rotates by row blocks).
 static cf_status core_cholqr(cf_ctx *c, const double *In, int64_t ldi, double *Out, int64_t ldo,
                              int N) {
-  const int64_t ldt = c->max_cols;
+  const int64_t ldt = c->ldw;
   int failed = 0;
+  if (N > ldt) {
+    if (In != Out) HIPCHK(c, launch_copy(c->stream, c->n, N, In, ldi, Out, ldo));
+    STCHK(core_cholqr_pass(c, Out, ldo, Out, ldo, N, 0.0, &failed));
+    if (failed) {
+      const double u = 1.1102230246251565e-16;
+      const double shift = 11.0 * ((double)c->n * N + (double)N * (N + 1)) * u * N;
+      STCHK(core_cholqr_pass(c, Out, ldo, Out, ldo, N, shift, &failed));
+      if (failed)
+        return set_err(c, CF_ENOTSPD, "cholqr: Gram matrix not positive definite even with shift");
+      STCHK(core_cholqr_pass(c, Out, ldo, Out, ldo, N, 0.0, &failed));
+      if (failed) return set_err(c, CF_ENOTSPD, "cholqr: second pass failed after shift");
+    }
+    STCHK(core_cholqr_pass(c, Out, ldo, Out, ldo, N, 0.0, &failed));
+    if (failed) return set_err(c, CF_ENOTSPD, "cholqr: second pass not positive definite");
+    return CF_OK;
+  }
   STCHK(core_cholqr_pass(c, In, ldi, c->T, ldt, N, 0.0, &failed));
   if (failed) {
     // shifted Cholesky-QR: shift of the unit-diagonal Gram by 11 (nN + N(N+1)) u N
@@ -633,6 +704,7 @@ static cf_status do_init(const cf_problem *pr, const cf_options *opt, cf_ctx *c)
   if (pr->n_e > 0 && (!pr->enr_ptr || !pr->enr_idx || !pr->H_ec || !pr->M_ec || !pr->H_ee || !pr->M_ee))
     return set_err(c, CF_EINVAL, "init: null enrichment arrays");
   if (opt->max_cols < 1) return set_err(c, CF_EINVAL, "init: max_cols must be >= 1");
+  if (opt->col_chunk < 0) return set_err(c, CF_EINVAL, "init: col_chunk must be >= 0");
   c->device = opt->device;
   c->stream = (hipStream_t)opt->stream;
   c->check_finite = opt->check_finite;
@@ -643,6 +715,7 @@ static cf_status do_init(const cf_problem *pr, const cf_options *opt, cf_ctx *c)
   c->n_e = pr->n_e;
   c->n = pr->n_h + pr->n_e;
   c->max_cols = opt->max_cols;
+  c->ldw = (opt->col_chunk > 0 && opt->col_chunk < opt->max_cols) ? opt->col_chunk : opt->max_cols;
   HIPCHK(c, hipSetDevice(c->device));
   const int64_t E = c->E, n_h = c->n_h, n_e = c->n_e;
 
@@ -726,12 +799,12 @@ static cf_status do_init(const cf_problem *pr, const cf_options *opt, cf_ctx *c)
     HIPCHK(c, hipMemcpy(c->dinv, di.data(), n_h * sizeof(double), hipMemcpyHostToDevice));
   }
 
-  // ---- workspace (ld = max_cols)
-  const int64_t mc = c->max_cols;
-  STCHK(dalloc(c, &c->R, (size_t)c->n * mc));
-  STCHK(dalloc(c, &c->B2, (size_t)c->n * mc));
-  STCHK(dalloc(c, &c->T, (size_t)c->n * mc));
-  STCHK(dalloc(c, &c->U, (size_t)c->n * mc));
+  // ---- workspace: n x ldw work blocks; N x N dense matrices (N <= max_cols)
+  const int64_t mc = c->max_cols, lw = c->ldw;
+  STCHK(dalloc(c, &c->R, (size_t)c->n * lw));
+  STCHK(dalloc(c, &c->B2, (size_t)c->n * lw));
+  STCHK(dalloc(c, &c->T, (size_t)c->n * lw));
+  STCHK(dalloc(c, &c->U, (size_t)c->n * lw));
   {
     // Gram partial buffer: chunks of at least 512 rows, a multiple of 8 chunks,
     // at most 256, at most ~512 MB (small problems still fill the chip)
@@ -939,7 +1012,7 @@ static cf_status do_init(const cf_problem *pr, const cf_options *opt, cf_ctx *c)
       HIPCHK(c, hipMemcpy(c->qptr, qptr.data(), (n_h + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
       HIPCHK(c, hipMemcpy(c->qidx, qidx.data(), qidx.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     }
-    STCHK(dalloc(c, &c->Q, (size_t)std::max<int>(c->necells, 1) * NPAD * mc));
+    STCHK(dalloc(c, &c->Q, (size_t)std::max<int>(c->necells, 1) * NPAD * lw));
     // per-cell coupling rows padded to NPAD, kept for the transposed products
     STCHK(dalloc(c, &c->Hec, (size_t)std::max<int64_t>(nnz, 1) * NPAD));
     STCHK(dalloc(c, &c->Mec, (size_t)std::max<int64_t>(nnz, 1) * NPAD));
@@ -968,9 +1041,9 @@ static cf_status do_init(const cf_problem *pr, const cf_options *opt, cf_ctx *c)
     STCHK(dalloc(c, &c->Hmod, n_e * n_e));
     HIPCHK(c, hipMemcpy(c->Hee, pr->H_ee, n_e * n_e * sizeof(double), hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(c->Mee, pr->M_ee, n_e * n_e * sizeof(double), hipMemcpyHostToDevice));
-    STCHK(dalloc(c, &c->P, (size_t)std::max<int64_t>(nnz, 1) * mc));
-    STCHK(dalloc(c, &c->Wb, (size_t)n_e * mc));
-    STCHK(dalloc(c, &c->Zb, (size_t)n_e * mc));
+    STCHK(dalloc(c, &c->P, (size_t)std::max<int64_t>(nnz, 1) * lw));
+    STCHK(dalloc(c, &c->Wb, (size_t)n_e * lw));
+    STCHK(dalloc(c, &c->Zb, (size_t)n_e * lw));
 
     // ---- setup on the device (temporaries released at the end):
     //  CSR values (assembly of the per-cell coupling blocks by colour),
@@ -1039,8 +1112,9 @@ static cf_status do_init(const cf_problem *pr, const cf_options *opt, cf_ctx *c)
       SCH(launch_csr_dense(c->stream, nreg, dreg, drow, dci, hv, mv, c->dinv, BM, BH, n_e));
       const int64_t crow = (std::max<int64_t>(nreg, 1) + nchS - 1) / nchS;
       // S = M^ee - (D^-1/2 M^ec^T)^T (D^-1/2 M^ec^T)
-      SCH(launch_gram_partial(c->stream, BM, n_e, BM, n_e, nreg, (int)n_e, nchS, crow, GpS, GRAM_UPPER));
-      SCH(launch_gram_reduce(c->stream, GpS, nchS, (int)n_e, Gt, GRAM_UPPER));
+      SCH(launch_gram_partial(c->stream, BM, n_e, BM, n_e, nreg, (int)n_e, (int)n_e, nchS, crow, GpS,
+                              GRAM_UPPER));
+      SCH(launch_gram_reduce(c->stream, GpS, nchS, (int)n_e, (int)n_e, Gt, n_e, GRAM_UPPER));
       SCH(launch_sub(c->stream, n_e * n_e, c->Mee, Gt, Sw));
       SCH(hipMemsetAsync(c->flag, 0, sizeof(int), c->stream));
       SCH(launch_cholesky(c->stream, Sw, (int)n_e, 0, 0.0, svS, c->flag));
@@ -1056,8 +1130,9 @@ static cf_status do_init(const cf_problem *pr, const cf_options *opt, cf_ctx *c)
       SCH(launch_transpose(c->stream, (int)n_e, WS, n_e, WST));         // WST = L^-1
       SCH(launch_small_gemm(c->stream, (int)n_e, (int)n_e, (int)n_e, WS, n_e, WST, n_e, c->Sinv, n_e));
       // K = M^ec D^-1 H^ec^T, H^ee - K
-      SCH(launch_gram_partial(c->stream, BM, n_e, BH, n_e, nreg, (int)n_e, nchS, crow, GpS, GRAM_FULL));
-      SCH(launch_gram_reduce(c->stream, GpS, nchS, (int)n_e, Gt, GRAM_FULL));
+      SCH(launch_gram_partial(c->stream, BM, n_e, BH, n_e, nreg, (int)n_e, (int)n_e, nchS, crow, GpS,
+                              GRAM_FULL));
+      SCH(launch_gram_reduce(c->stream, GpS, nchS, (int)n_e, (int)n_e, Gt, n_e, GRAM_FULL));
       SCH(launch_sub(c->stream, n_e * n_e, c->Hee, Gt, c->Hmod));
       SCH(hipStreamSynchronize(c->stream));
 #undef SCH
@@ -1405,7 +1480,9 @@ cf_status chebfilter_apply_H(cf_ctx *c, const double *X, int64_t ldx, double *Y,
   STCHK(check_block(c, Y, ldy, N, "apply_H Y"));
   if (N == 0) return CF_OK;
   HIPCHK(c, hipSetDevice(c->device));
-  return core_apply_H(c, X, ldx, Y, ldy, (int)N);
+  for (int64_t j0 = 0; j0 < N; j0 += c->ldw)
+    STCHK(core_apply_H(c, X + j0, ldx, Y + j0, ldy, (int)std::min(c->ldw, N - j0)));
+  return CF_OK;
 }
 
 cf_status chebfilter_apply_M(cf_ctx *c, const double *X, int64_t ldx, double *Y, int64_t ldy,
@@ -1415,7 +1492,9 @@ cf_status chebfilter_apply_M(cf_ctx *c, const double *X, int64_t ldx, double *Y,
   STCHK(check_block(c, Y, ldy, N, "apply_M Y"));
   if (N == 0) return CF_OK;
   HIPCHK(c, hipSetDevice(c->device));
-  return core_apply_M(c, X, ldx, Y, ldy, (int)N);
+  for (int64_t j0 = 0; j0 < N; j0 += c->ldw)
+    STCHK(core_apply_M(c, X + j0, ldx, Y + j0, ldy, (int)std::min(c->ldw, N - j0)));
+  return CF_OK;
 }
 
 cf_status chebfilter_apply_Sinv(cf_ctx *c, const double *X, int64_t ldx, double *Y, int64_t ldy,
@@ -1425,25 +1504,50 @@ cf_status chebfilter_apply_Sinv(cf_ctx *c, const double *X, int64_t ldx, double 
   STCHK(check_block(c, Y, ldy, N, "apply_Sinv Y"));
   if (N == 0) return CF_OK;
   HIPCHK(c, hipSetDevice(c->device));
-  const int n = (int)N;
-  if (c->n_e > 0) {
-    // w = x_e - M^ec D^-1 x_c ; z = S^-1 w
-    Scope sc(c, "enr_gemm");
-    HIPCHK(c, launch_enr_part(c->stream, c->HT, c->MT, c->toff, c->tld, c->eptr, c->dofp, c->ecells_part,
-                              c->necells, nullptr, 0, 0.0, X, ldx, c->dinv, -1.0, c->P, c->max_cols,
-                              n));
-    HIPCHK(c, launch_enr_reduce(c->stream, (int)c->n_e, c->aptr, c->alist, c->P, c->max_cols, 1.0,
-                                X + c->n_h * ldx, ldx, 1.0, nullptr, nullptr, 0, c->Wb, c->max_cols,
-                                n));
-    STCHK(core_schur_solve(c, n));
-    STCHK(core_enr_q(c, nullptr, 0, 0.0, c->Zb, c->max_cols, -1.0, n));
+  for (int64_t j0 = 0; j0 < N; j0 += c->ldw)
+    STCHK(core_apply_Sinv(c, X + j0, ldx, Y + j0, ldy, (int)std::min(c->ldw, N - j0)));
+  return CF_OK;
+}
+
+// One column chunk (n <= ldw) of the filter; X must not be Y.
+static cf_status core_filter_chunk(cf_ctx *c, const double *X, int64_t ldx, double *Y, int64_t ldy,
+                                   int n, int m, double e, double cc, int32_t prec) {
+  if (prec != CF_FP64) {
+    // FP32 recurrence: Y_k lives in F0 (k even) or F1 (k odd); Y_{k+1}
+    // overwrites Y_{k-1} element by element
+    // The iterates are held as Z_k = Y_k 2^-s_k with s_k chosen on the device
+    // from the growth of the last two iterates (powers of two: every rounding
+    // is that of the unscaled recurrence, which would leave FP32's range at
+    // high degree or wide damping intervals); Y = Z_m 2^s_m is formed in FP64.
+    const bool bf16 = prec == CF_BF16;
+    STCHK(ensure_lowp(c, bf16));
+    STCHK(ensure_lp_scale(c, m));
+    const int64_t mc = c->ldw;
+    float *F[2] = {c->F0, c->F1};
+    HIPCHK(c, launch_lp_reset(c->stream, c->lp_mx, (m + 2) * MX_SLOTS));
+    HIPCHK(c, launch_lp_input(c->stream, c->n, n, X, ldx, c->F0, mc, c->lp_mx));
+    HIPCHK(c, launch_lp_scale(c->stream, 0, c->lp_mx, c->lp_s, c->lp_mult));
+    STCHK(core_htilde_step_lp(c, bf16, F[0], mc, n, (float)e, (float)-cc, nullptr, 0, 0.f, F[1], mc,
+                              c->lp_mult, c->lp_mx + MX_SLOTS));
+    for (int k = 1; k < m; ++k) {
+      HIPCHK(c, launch_lp_scale(c->stream, k, c->lp_mx, c->lp_s, c->lp_mult));
+      STCHK(core_htilde_step_lp(c, bf16, F[k & 1], mc, n, (float)(2.0 * e), (float)(-2.0 * cc),
+                                F[(k - 1) & 1], mc, -1.f, F[(k + 1) & 1], mc, c->lp_mult + 2 * k,
+                                c->lp_mx + (k + 1) * MX_SLOTS));
+    }
+    HIPCHK(c, launch_lp_output(c->stream, c->n, n, F[m & 1], mc, c->lp_s + m, Y, ldy));
+    return CF_OK;
   }
-  // y_c = D^-1 (x_c - M^ec^T z), y_e = z
-  EpiArgs g = epi_base(c, n);
-  g.R = X; g.ldr = ldx; g.dR = c->dinv; g.dC = c->dinv;
-  g.Ee = c->Zb; g.lde = c->max_cols;
-  g.Out = Y; g.ldo = ldy;
-  HIPCHK(c, launch_epilogue(c->stream, g));
+  // Y_k lives in Y when (m - k) is even, else in the internal block B2.
+  auto buf = [&](int k) -> double * { return ((m - k) % 2 == 0) ? Y : c->B2; };
+  auto ldb = [&](int k) -> int64_t { return ((m - k) % 2 == 0) ? ldy : c->ldw; };
+  STCHK(core_htilde_step(c, X, ldx, n, e, X, ldx, -cc, nullptr, 0, 0.0, buf(1), ldb(1)));
+  for (int k = 1; k < m; ++k) {
+    const double *prev = (k == 1) ? X : buf(k - 1);
+    const int64_t ldp = (k == 1) ? ldx : ldb(k - 1);
+    STCHK(core_htilde_step(c, buf(k), ldb(k), n, 2.0 * e, buf(k), ldb(k), -2.0 * cc, prev, ldp, -1.0,
+                           buf(k + 1), ldb(k + 1)));
+  }
   return CF_OK;
 }
 
@@ -1458,52 +1562,30 @@ cf_status chebfilter_filter(cf_ctx *c, const double *X, int64_t ldx, double *Y, 
   if (prec != CF_FP64 && prec != CF_FP32 && prec != CF_BF16)
     return set_err(c, CF_EINVAL, "filter: prec must be CF_FP64, CF_FP32 or CF_BF16");
   if (N == 0) return CF_OK;
-  if (X == Y) return set_err(c, CF_EINVAL, "filter: Y must not alias X");
+  const bool inplace = X == Y;
+  if (inplace && ldx != ldy) return set_err(c, CF_EINVAL, "filter: in place needs ldx == ldy");
   HIPCHK(c, hipSetDevice(c->device));
-  const int n = (int)N;
   if (m == 0) {
-    HIPCHK(c, launch_copy(c->stream, c->n, n, X, ldx, Y, ldy));
+    if (!inplace) HIPCHK(c, launch_copy(c->stream, c->n, (int)N, X, ldx, Y, ldy));
     return CF_OK;
   }
-  // t(H~) = e H~ - cc I with e = 2/(b-a), cc = (a+b)/(b-a)
+  // t(H~) = e H~ - cc I with e = 2/(b-a), cc = (a+b)/(b-a).  The columns are
+  // independent: chunks of at most ldw columns run one after another.  In
+  // place, an FP64 chunk is read from a copy in the work block U (the FP32
+  // forms read it once into their own blocks before the chunk is written).
   const double e = 2.0 / (b - a), cc = (a + b) / (b - a);
-  if (prec != CF_FP64) {
-    // FP32 recurrence: Y_k lives in F0 (k even) or F1 (k odd); Y_{k+1}
-    // overwrites Y_{k-1} element by element
-    // The iterates are held as Z_k = Y_k 2^-s_k with s_k chosen on the device
-    // from the growth of the last two iterates (powers of two: every rounding
-    // is that of the unscaled recurrence, which would leave FP32's range at
-    // high degree or wide damping intervals); Y = Z_m 2^s_m is formed in FP64.
-    const bool bf16 = prec == CF_BF16;
-    STCHK(ensure_lowp(c, bf16));
-    STCHK(ensure_lp_scale(c, m));
-    const int64_t mc = c->max_cols;
-    float *F[2] = {c->F0, c->F1};
-    HIPCHK(c, launch_lp_reset(c->stream, c->lp_mx, (m + 2) * MX_SLOTS));
-    HIPCHK(c, launch_lp_input(c->stream, c->n, n, X, ldx, c->F0, mc, c->lp_mx));
-    HIPCHK(c, launch_lp_scale(c->stream, 0, c->lp_mx, c->lp_s, c->lp_mult));
-    STCHK(core_htilde_step_lp(c, bf16, F[0], mc, n, (float)e, (float)-cc, nullptr, 0, 0.f, F[1], mc,
-                              c->lp_mult, c->lp_mx + MX_SLOTS));
-    for (int k = 1; k < m; ++k) {
-      HIPCHK(c, launch_lp_scale(c->stream, k, c->lp_mx, c->lp_s, c->lp_mult));
-      STCHK(core_htilde_step_lp(c, bf16, F[k & 1], mc, n, (float)(2.0 * e), (float)(-2.0 * cc),
-                                F[(k - 1) & 1], mc, -1.f, F[(k + 1) & 1], mc, c->lp_mult + 2 * k,
-                                c->lp_mx + (k + 1) * MX_SLOTS));
+  for (int64_t j0 = 0; j0 < N; j0 += c->ldw) {
+    const int nc = (int)std::min(c->ldw, N - j0);
+    const double *Xc = X + j0;
+    int64_t ldxc = ldx;
+    if (inplace && prec == CF_FP64) {
+      HIPCHK(c, launch_copy(c->stream, c->n, nc, X + j0, ldx, c->U, c->ldw));
+      Xc = c->U;
+      ldxc = c->ldw;
     }
-    HIPCHK(c, launch_lp_output(c->stream, c->n, n, F[m & 1], mc, c->lp_s + m, Y, ldy));
-    return check_out_finite(c, Y, ldy, n, "filter");
+    STCHK(core_filter_chunk(c, Xc, ldxc, Y + j0, ldy, nc, m, e, cc, prec));
   }
-  // Y_k lives in Y when (m - k) is even, else in the internal block B2.
-  auto buf = [&](int k) -> double * { return ((m - k) % 2 == 0) ? Y : c->B2; };
-  auto ldb = [&](int k) -> int64_t { return ((m - k) % 2 == 0) ? ldy : c->max_cols; };
-  STCHK(core_htilde_step(c, X, ldx, n, e, X, ldx, -cc, nullptr, 0, 0.0, buf(1), ldb(1)));
-  for (int k = 1; k < m; ++k) {
-    const double *prev = (k == 1) ? X : buf(k - 1);
-    const int64_t ldp = (k == 1) ? ldx : ldb(k - 1);
-    STCHK(core_htilde_step(c, buf(k), ldb(k), n, 2.0 * e, buf(k), ldb(k), -2.0 * cc, prev, ldp, -1.0,
-                           buf(k + 1), ldb(k + 1)));
-  }
-  return check_out_finite(c, Y, ldy, n, "filter");
+  return check_out_finite(c, Y, ldy, (int)N, "filter");
 }
 
 cf_status chebfilter_filter_multipass(cf_ctx *c, const double *X, int64_t ldx, double *Y,
@@ -1514,14 +1596,10 @@ cf_status chebfilter_filter_multipass(cf_ctx *c, const double *X, int64_t ldx, d
   if (passes == 1) return chebfilter_filter(c, X, ldx, Y, ldy, N, m, a, b, prec);
   STCHK(check_block(c, X, ldx, N, "filter_multipass X"));
   STCHK(check_block(c, Y, ldy, N, "filter_multipass Y"));
-  if (X == Y) return set_err(c, CF_EINVAL, "filter_multipass: Y must not alias X");
+  if (X == Y && ldx != ldy) return set_err(c, CF_EINVAL, "filter_multipass: in place needs ldx == ldy");
   if (N == 0) return CF_OK;
   HIPCHK(c, hipSetDevice(c->device));
-  // every pass ends in Y; the next one reads a copy of Y in the work block U.
-  // U is free between calls (the projection keeps its orthonormal basis there
-  // only during its own call), and it must not be handed to the projection,
-  // whose Cholesky-QR and rotation read U while writing their output.
-  const int64_t mc = c->max_cols;
+  // every pass ends in Y; the next one filters Y in place
   std::vector<double> theta((size_t)N);
   STCHK(chebfilter_filter(c, X, ldx, Y, ldy, N, m, a, b, prec));
   for (int i = 1; i < passes; ++i) {
@@ -1530,8 +1608,7 @@ cf_status chebfilter_filter_multipass(cf_ctx *c, const double *X, int64_t ldx, d
     // one (a triangular Cholesky-QR basis would mix them, and after a second
     // high-degree pass the columns would all lean towards the lowest one)
     STCHK(chebfilter_rayleigh_ritz(c, Y, ldy, N, theta.data()));
-    HIPCHK(c, launch_copy(c->stream, c->n, (int)N, Y, ldy, c->U, mc));
-    STCHK(chebfilter_filter(c, c->U, mc, Y, ldy, N, m, a, b, prec));
+    STCHK(chebfilter_filter(c, Y, ldy, Y, ldy, N, m, a, b, prec));
   }
   return CF_OK;
 }
@@ -1554,18 +1631,38 @@ cf_status chebfilter_rayleigh_ritz(cf_ctx *c, double *Y, int64_t ldy, int64_t N,
   if (N == 0) return CF_OK;
   HIPCHK(c, hipSetDevice(c->device));
   const int n = (int)N;
-  const int64_t ld = c->max_cols;
-  // Q (Euclidean-orthonormal) into U
-  STCHK(core_cholqr(c, Y, ldy, c->U, ld, n));
+  const int64_t ld = c->ldw;
+  // Q (Euclidean-orthonormal): in U when the block fits the work blocks,
+  // else in Y itself
+  const bool wide = N > ld;
+  double *Qb = wide ? Y : c->U;
+  const int64_t ldq = wide ? ldy : ld;
+  STCHK(core_cholqr(c, Y, ldy, Qb, ldq, n));
   // projected pencil
-  STCHK(core_apply_H(c, c->U, ld, c->T, ld, n));
-  STCHK(core_gram(c, c->U, ld, c->T, ld, c->n, n, c->Hh, GRAM_SYM));
-  STCHK(core_apply_M(c, c->U, ld, c->T, ld, n));
-  STCHK(core_gram(c, c->U, ld, c->T, ld, c->n, n, c->Mh, GRAM_SYM));
+  if (!wide) {
+    STCHK(core_apply_H(c, Qb, ldq, c->T, ld, n));
+    STCHK(core_gram(c, Qb, ldq, c->T, ld, c->n, n, c->Hh, GRAM_SYM));
+    STCHK(core_apply_M(c, Qb, ldq, c->T, ld, n));
+    STCHK(core_gram(c, Qb, ldq, c->T, ld, c->n, n, c->Mh, GRAM_SYM));
+  } else {
+    // column chunk [j0, j1): T = H Q[:, j0:j1], then the slab rows 0..j1 of
+    // Q^T T (the upper triangle and the chunk's diagonal block); likewise M;
+    // the lower triangles are mirrored from the upper ones
+    for (int64_t j0 = 0; j0 < N; j0 += ld) {
+      const int nc = (int)std::min(ld, N - j0);
+      const int j1 = (int)j0 + nc;
+      STCHK(core_apply_H(c, Qb + j0, ldq, c->T, ld, nc));
+      STCHK(core_gram_slab(c, Qb, ldq, j1, c->T, ld, nc, c->Hh + j0, n));
+      STCHK(core_apply_M(c, Qb + j0, ldq, c->T, ld, nc));
+      STCHK(core_gram_slab(c, Qb, ldq, j1, c->T, ld, nc, c->Mh + j0, n));
+    }
+    HIPCHK(c, launch_mirror_upper(c->stream, c->Hh, n));
+    HIPCHK(c, launch_mirror_upper(c->stream, c->Mh, n));
+  }
   // the projected pencil (Hh, Mh) to standard form: Mh = L L^T (library
   // Cholesky; on the row-major symmetric Mh the column-major upper factor is
   // the row-major lower L), W = L^-T, C = W^T Hh W; symmetric eigensolve of C;
-  // Ritz vectors Y = U (W V).  All row-major N x N products go to rocBLAS
+  // Ritz vectors Y = Q (W V).  All row-major N x N products go to rocBLAS
   // through the column-major view (a row-major X is the column-major X^T).
   HIPCHK(c, hipMemsetAsync(c->flag, 0, sizeof(int), c->stream));
   if (rocsolver_dpotrf(c->rb, rocblas_fill_upper, n, c->Mh, n, (rocblas_int *)c->flag) !=
@@ -1598,10 +1695,12 @@ cf_status chebfilter_rayleigh_ritz(cf_ctx *c, double *Y, int64_t ldy, int64_t N,
   HIPCHK(c, hipMemcpyAsync(&h_info, c->info, sizeof(rocblas_int), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipMemcpyAsync(&h_flag, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipMemcpyAsync(theta_host, c->theta, N * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-  STCHK(core_rotate(c, c->U, ld, c->Wm, n, Y, ldy));
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  // a failed factorisation or eigensolve leaves the block as it was (the
+  // orthonormal basis when it was formed in place)
   if (h_flag) return set_err(c, CF_ENOTSPD, "rayleigh_ritz: projected overlap not SPD");
   if (h_info > 0) return set_err(c, CF_ENOTCONV, "rayleigh_ritz: eigensolver did not converge");
+  STCHK(core_rotate(c, Qb, ldq, c->Wm, n, Y, ldy));
   return check_out_finite(c, Y, ldy, n, "rayleigh_ritz");
 }
 
@@ -1676,6 +1775,9 @@ cf_status chebfilter_init_batch(const cf_problem *const *probs, int32_t count, c
   b->caller = (hipStream_t)opt->stream;
   b->count = count;
   b->max_cols = opt->max_cols;
+  // the batched kernels take each block whole: no column chunks
+  cf_options ob = *opt;
+  ob.col_chunk = 0;
   std::map<const cf_problem *, int> seen;
   for (int i = 0; i < count; ++i) {
     if (!probs[i]) { free_batch(b); return berr(nullptr, CF_EINVAL, "init_batch: null problem"); }
@@ -1683,7 +1785,7 @@ cf_status chebfilter_init_batch(const cf_problem *const *probs, int32_t count, c
     if (it != seen.end()) { b->which.push_back(it->second); continue; }
     cf_ctx *c = new (std::nothrow) cf_ctx();
     if (!c) { free_batch(b); return berr(nullptr, CF_ENOMEM, "init_batch: host allocation failed"); }
-    cf_status st = do_init(probs[i], opt, c);
+    cf_status st = do_init(probs[i], &ob, c);
     if (st != CF_OK) {
       g_init_error = "init_batch: problem " + std::to_string(i) + ": " + c->err;
       free_ctx(c);
@@ -1946,7 +2048,7 @@ cf_status chebfilter_rayleigh_ritz_batch(cf_batch *b, double *const *Y, const in
   for (int i : order) {
     cf_ctx *c = b->uniq[b->which[i]];
     const int n = (int)N[i];
-    const int64_t ld = c->max_cols;
+    const int64_t ld = c->ldw;
     int *st = b->d_rst + 8 * i;
     double *Hh = b->d_rH + b->h_rslot[i] * mc2, *Mh = b->d_rM + b->h_rslot[i] * mc2;
     cf_status r = CF_OK;
@@ -1994,7 +2096,7 @@ cf_status chebfilter_rayleigh_ritz_batch(cf_batch *b, double *const *Y, const in
   for (int i : order) {
     cf_ctx *c = b->uniq[b->which[i]];
     const int n = (int)N[i];
-    const int64_t ld = c->max_cols;
+    const int64_t ld = c->ldw;
     int *st = b->d_rst + 8 * i;
     BHIPCHK(b, launch_transpose(s, n, b->d_rH + b->h_rslot[i] * mc2, n, c->Wm));
     {
@@ -2235,20 +2337,22 @@ cf_status chebfilter_residual_norms(cf_ctx *c, const double *Z, int64_t ldz, int
   if (N > 0 && (!theta_host || !res_host)) return set_err(c, CF_EINVAL, "residual_norms: null theta or res");
   if (N == 0) return CF_OK;
   HIPCHK(c, hipSetDevice(c->device));
-  const int n = (int)N;
-  const int64_t ld = c->max_cols;
-  // T = H Z - M Z diag(theta); U = (M^E)^-1 T; res_j = sqrt(T_j . U_j)
+  const int64_t ld = c->ldw;
+  // per column chunk: T = H Z - M Z diag(theta); U = (M^E)^-1 T; res_j = sqrt(T_j . U_j)
   HIPCHK(c, hipMemcpyAsync(c->theta, theta_host, N * sizeof(double), hipMemcpyHostToDevice, c->stream));
-  STCHK(core_apply_H(c, Z, ldz, c->T, ld, n));
-  STCHK(core_apply_M(c, Z, ldz, c->U, ld, n));
-  HIPCHK(c, launch_sub_colscale(c->stream, c->n, n, c->T, ld, c->U, ld, c->theta));
-  STCHK(chebfilter_apply_Sinv(c, c->T, ld, c->U, ld, N));
-  const int nchunks = (int)std::min<int64_t>(256, (int64_t)c->gp_chunks * c->max_cols);
-  HIPCHK(c, launch_coldot(c->stream, c->n, n, c->T, ld, c->U, ld, c->Gp, nchunks, c->evE));
+  for (int64_t j0 = 0; j0 < N; j0 += ld) {
+    const int nc = (int)std::min(ld, N - j0);
+    STCHK(core_apply_H(c, Z + j0, ldz, c->T, ld, nc));
+    STCHK(core_apply_M(c, Z + j0, ldz, c->U, ld, nc));
+    HIPCHK(c, launch_sub_colscale(c->stream, c->n, nc, c->T, ld, c->U, ld, c->theta + j0));
+    STCHK(core_apply_Sinv(c, c->T, ld, c->U, ld, nc));
+    const int nchunks = (int)std::min<int64_t>(256, (int64_t)c->gp_chunks * c->max_cols);
+    HIPCHK(c, launch_coldot(c->stream, c->n, nc, c->T, ld, c->U, ld, c->Gp, nchunks, c->evE + j0));
+  }
   std::vector<double> sq(N);
   HIPCHK(c, hipMemcpyAsync(sq.data(), c->evE, N * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  for (int j = 0; j < n; ++j) res_host[j] = std::sqrt(std::max(sq[j], 0.0));
+  for (int64_t j = 0; j < N; ++j) res_host[j] = std::sqrt(std::max(sq[j], 0.0));
   return CF_OK;
 }
 

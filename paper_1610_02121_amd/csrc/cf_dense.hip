@@ -16,22 +16,24 @@ __device__ __forceinline__ d4 mfma_f64(double a, double b, d4 c) {
 }
 __device__ __forceinline__ d4 d4zero() { d4 z = {0.0, 0.0, 0.0, 0.0}; return z; }
 
-// Number of 64 x 64 output tiles of an N x N product and the (ti, tj) of tile t.
-__host__ __device__ inline int ntiles_of(int N, int upper) {
-  const int T = (N + GT - 1) / GT;
-  return upper ? T * (T + 1) / 2 : T * T;
+// Number of 64 x 64 output tiles of an Na x Nb product and the (ti, tj) of
+// tile t (upper: square products, tiles with ti <= tj only).
+__host__ __device__ inline int ntiles_of(int Na, int Nb, int upper) {
+  const int Ta = (Na + GT - 1) / GT, Tb = (Nb + GT - 1) / GT;
+  return upper ? Ta * (Ta + 1) / 2 : Ta * Tb;
 }
-__device__ inline void tile_of(int t, int N, int upper, int &ti, int &tj) {
-  const int T = (N + GT - 1) / GT;
-  if (!upper) { ti = t / T; tj = t % T; return; }
+__device__ inline void tile_of(int t, int Na, int Nb, int upper, int &ti, int &tj) {
+  const int Ta = (Na + GT - 1) / GT, Tb = (Nb + GT - 1) / GT;
+  if (!upper) { ti = t / Tb; tj = t % Tb; return; }
   int i = 0;
-  while (t >= T - i) { t -= T - i; ++i; }
+  while (t >= Ta - i) { t -= Ta - i; ++i; }
   ti = i;
   tj = i + t;
 }
 
 // ---------------------------------------------------------------------------
-// Partial Gram: Gp[c][i][j] = sum over rows r of chunk c of A[r][i] B[r][j].
+// Partial Gram: Gp[c][i][j] = sum over rows r of chunk c of A[r][i] B[r][j]
+// (i < Na, j < Nb; Gp[c] is Na x Nb, row-major).
 // 1-D grid of nchunks * ntiles workgroups.  Workgroups that share a row chunk
 // are mapped to the same XCD (workgroups are dealt round-robin to the 8 XCDs
 // by index), so the chunk is fetched from HBM once into that XCD's L2.  The
@@ -42,18 +44,19 @@ __device__ inline void tile_of(int t, int N, int upper, int &ti, int &tj) {
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_gram_partial(
     const double *__restrict__ A, int64_t lda, const double *__restrict__ B, int64_t ldb,
-    int64_t n, int N, int nchunks, int64_t chunk_rows, int upper, double *__restrict__ Gp) {
+    int64_t n, int Na, int Nb, int nchunks, int64_t chunk_rows, int upper,
+    double *__restrict__ Gp) {
   constexpr int KS = 32, LDS = GT + 4;   // row slab, LDS row stride (doubles)
   __shared__ double as[KS * LDS];
   __shared__ double bs[KS * LDS];
-  const int ntl = ntiles_of(N, upper);   // upper != 0: only tiles with ti <= tj
+  const int ntl = ntiles_of(Na, Nb, upper);   // upper != 0: only tiles with ti <= tj
   const int bid = blockIdx.x;
   const int xcd = bid & 7, slot = bid >> 3;
   const int chunk = (slot / ntl) * 8 + xcd;
   const int t = slot % ntl;
   if (chunk >= nchunks) return;
   int ti, tj;
-  tile_of(t, N, upper, ti, tj);
+  tile_of(t, Na, Nb, upper, ti, tj);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, kq = lane >> 4;
   const int ci0 = ti * GT, cj0 = tj * GT;
@@ -62,12 +65,12 @@ __global__ __launch_bounds__(256) void k_gram_partial(
   const int64_t r1 = min(n, r0 + chunk_rows);
   d4 acc[2][2];
   acc[0][0] = acc[0][1] = acc[1][0] = acc[1][1] = d4zero();
-  const bool busy = ci0 + wi < N && cj0 + wj < N;
-  // 16 x 16 blocks worth computing: inside N, and (upper mode) not entirely
-  // below the diagonal of a diagonal tile, whose entries the reduction never
-  // reads; a skipped block writes zeros that nothing reads
-  const bool ra[2] = {ci0 + wi < N, ci0 + wi + 16 < N};
-  const bool rb[2] = {cj0 + wj < N, cj0 + wj + 16 < N};
+  const bool busy = ci0 + wi < Na && cj0 + wj < Nb;
+  // 16 x 16 blocks worth computing: inside Na x Nb, and (upper mode) not
+  // entirely below the diagonal of a diagonal tile, whose entries the
+  // reduction never reads; a skipped block writes zeros that nothing reads
+  const bool ra[2] = {ci0 + wi < Na, ci0 + wi + 16 < Na};
+  const bool rb[2] = {cj0 + wj < Nb, cj0 + wj + 16 < Nb};
   bool need[2][2];
 #pragma unroll
   for (int ib = 0; ib < 2; ++ib)
@@ -76,7 +79,7 @@ __global__ __launch_bounds__(256) void k_gram_partial(
       need[ib][jb] = ra[ib] && rb[jb] && !(upper && ti == tj && wi + 16 * ib >= wj + 16 * jb + 16);
   // cooperative slab load: column lc of the tile, rows lr + 4p
   const int lc = tid & 63, lr = tid >> 6;
-  const bool cva = ci0 + lc < N, cvb = cj0 + lc < N;
+  const bool cva = ci0 + lc < Na, cvb = cj0 + lc < Nb;
   double pa[KS / 4], pb[KS / 4];
   auto load = [&](int64_t rs) {
 #pragma unroll
@@ -110,7 +113,7 @@ __global__ __launch_bounds__(256) void k_gram_partial(
     }
     __syncthreads();
   }
-  double *g = Gp + (int64_t)chunk * N * N;
+  double *g = Gp + (int64_t)chunk * Na * Nb;
 #pragma unroll
   for (int ib = 0; ib < 2; ++ib)
 #pragma unroll
@@ -119,53 +122,76 @@ __global__ __launch_bounds__(256) void k_gram_partial(
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int i = ci0 + wi + 16 * ib + kq + 4 * r;
-        if (i < N && j < N) g[(int64_t)i * N + j] = acc[ib][jb][r];
+        if (i < Na && j < Nb) g[(int64_t)i * Nb + j] = acc[ib][jb][r];
       }
     }
 }
 
 hipError_t launch_gram_partial(hipStream_t s, const double *A, int64_t lda, const double *B,
-                               int64_t ldb, int64_t n, int N, int nchunks, int64_t chunk_rows,
-                               double *Gp, int mode) {
-  if (N <= 0) return hipSuccess;
+                               int64_t ldb, int64_t n, int Na, int Nb, int nchunks,
+                               int64_t chunk_rows, double *Gp, int mode) {
+  if (Na <= 0 || Nb <= 0) return hipSuccess;
   const int upper = mode == GRAM_UPPER;
-  const int ntl = ntiles_of(N, upper);
+  if (upper && Na != Nb) return hipErrorInvalidValue;
+  const int ntl = ntiles_of(Na, Nb, upper);
   const int nch8 = (nchunks + 7) / 8 * 8;
-  hipLaunchKernelGGL(k_gram_partial, dim3(nch8 * ntl), dim3(256), 0, s, A, lda, B, ldb, n, N,
+  hipLaunchKernelGGL(k_gram_partial, dim3(nch8 * ntl), dim3(256), 0, s, A, lda, B, ldb, n, Na, Nb,
                      nchunks, chunk_rows, upper, Gp);
   return hipGetLastError();
 }
 
+// G[i][j] (ld ldg) = sum of the chunk partials.  GRAM_FULL: Na x Nb as is;
+// GRAM_UPPER / GRAM_SYM (Na = Nb): the upper sums, or the average of the two
+// triangles, written to both triangles.
 __global__ __launch_bounds__(256) void k_gram_reduce(const double *__restrict__ Gp, int nchunks,
-                                                     int N, double *__restrict__ G, int mode) {
-  const int64_t NN = (int64_t)N * N;
+                                                     int Na, int Nb, double *__restrict__ G,
+                                                     int64_t ldg, int mode) {
+  const int64_t NN = (int64_t)Na * Nb;
   for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < NN; e += (int64_t)gridDim.x * 256) {
-    const int i = (int)(e / N), j = (int)(e % N);
+    const int i = (int)(e / Nb), j = (int)(e % Nb);
     if (mode == GRAM_FULL) {
       double sij = 0.0;
-      for (int c = 0; c < nchunks; ++c) sij += Gp[c * NN + (int64_t)i * N + j];
-      G[(int64_t)i * N + j] = sij;
+      for (int c = 0; c < nchunks; ++c) sij += Gp[c * NN + (int64_t)i * Nb + j];
+      G[(int64_t)i * ldg + j] = sij;
       continue;
     }
     if (j < i) continue;
     double sij = 0.0, sji = 0.0;
     for (int c = 0; c < nchunks; ++c) {
-      sij += Gp[c * NN + (int64_t)i * N + j];
-      if (mode == GRAM_SYM) sji += Gp[c * NN + (int64_t)j * N + i];
+      sij += Gp[c * NN + (int64_t)i * Nb + j];
+      if (mode == GRAM_SYM) sji += Gp[c * NN + (int64_t)j * Nb + i];
     }
     const double v = (mode == GRAM_UPPER) ? sij : 0.5 * (sij + sji);
-    G[(int64_t)i * N + j] = v;
-    G[(int64_t)j * N + i] = v;
+    G[(int64_t)i * ldg + j] = v;
+    G[(int64_t)j * ldg + i] = v;
   }
 }
 
-hipError_t launch_gram_reduce(hipStream_t s, const double *Gp, int nchunks, int N, double *G,
-                              int mode) {
+hipError_t launch_gram_reduce(hipStream_t s, const double *Gp, int nchunks, int Na, int Nb,
+                              double *G, int64_t ldg, int mode) {
+  if (Na <= 0 || Nb <= 0) return hipSuccess;
+  if (mode != GRAM_FULL && Na != Nb) return hipErrorInvalidValue;
+  int64_t blocks = ((int64_t)Na * Nb + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)blocks), dim3(256), 0, s, Gp, nchunks, Na, Nb,
+                     G, ldg, mode);
+  return hipGetLastError();
+}
+
+// Upper triangle of a row-major N x N matrix mirrored onto its lower triangle.
+__global__ __launch_bounds__(256) void k_mirror_upper(double *__restrict__ G, int N) {
+  const int64_t NN = (int64_t)N * N;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < NN; e += (int64_t)gridDim.x * 256) {
+    const int i = (int)(e / N), j = (int)(e % N);
+    if (j < i) G[e] = G[(int64_t)j * N + i];
+  }
+}
+
+hipError_t launch_mirror_upper(hipStream_t s, double *G, int N) {
   if (N <= 0) return hipSuccess;
   int64_t blocks = ((int64_t)N * N + 255) / 256;
   if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)blocks), dim3(256), 0, s, Gp, nchunks, N, G,
-                     mode);
+  hipLaunchKernelGGL(k_mirror_upper, dim3((unsigned)blocks), dim3(256), 0, s, G, N);
   return hipGetLastError();
 }
 

@@ -256,13 +256,16 @@ hipError_t launch_b_lp_output(hipStream_t s, const BatchProb *bp, int count, con
 //             GRAM_UPPER upper tiles only (A = B), mirrored
 //             GRAM_FULL  full product, no symmetrisation
 enum { GRAM_SYM = 0, GRAM_UPPER = 1, GRAM_FULL = 2 };
-// Partial Gram matrices: Gp[c][i*N+j] = sum_{rows of chunk c} A[r,i] * B[r,j]
+// Partial Gram matrices: Gp[c][i*Nb+j] = sum_{rows of chunk c} A[r,i] * B[r,j],
+// i < Na, j < Nb (GRAM_UPPER needs Na = Nb).
 hipError_t launch_gram_partial(hipStream_t s, const double *A, int64_t lda, const double *B,
-                               int64_t ldb, int64_t n, int N, int nchunks, int64_t chunk_rows,
-                               double *Gp, int mode);
-// G[i][j] = sum_c Gp[c][i][j], combined as the mode says.
-hipError_t launch_gram_reduce(hipStream_t s, const double *Gp, int nchunks, int N, double *G,
-                              int mode);
+                               int64_t ldb, int64_t n, int Na, int Nb, int nchunks,
+                               int64_t chunk_rows, double *Gp, int mode);
+// G[i*ldg+j] = sum_c Gp[c][i][j], combined as the mode says (SYM/UPPER: Na = Nb).
+hipError_t launch_gram_reduce(hipStream_t s, const double *Gp, int nchunks, int Na, int Nb,
+                              double *G, int64_t ldg, int mode);
+// Lower triangle of a row-major N x N matrix <- its upper triangle.
+hipError_t launch_mirror_upper(hipStream_t s, double *G, int N);
 // In-place lower Cholesky of the N x N row-major A (ld = N) with optional column
 // scaling: A <- chol(S (A + shift*I_diag) S), S = diag(A)^-1/2 when scale != 0;
 // s_out[i] receives S_ii (1 when not scaling).  flag[0] = index+1 of a failing

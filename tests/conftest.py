@@ -61,3 +61,13 @@ def hydrogen_classical():
     """Hydrogen on 4^3 cells of degree 4 with no enrichment (n_e = 0)."""
     from synth import configs
     return cached("h4c", lambda: configs.hydrogen(nc=4, length=20.0, p=4, enrich=False))
+
+
+@pytest.fixture(scope="session")
+def si_dense():
+    """10-atom Si cluster in a 32 Bohr cube on 8^3 cells (n ~ 30k, n_e = 90):
+    the central cells meet every atom's support, up to 90 enrichment
+    functions per cell (more than one 64-row group of the coupling kernels)."""
+    from synth import configs
+    return cached("si10", lambda: configs.si_cluster(n_atoms=10, length=32.0, nc=8, p=4,
+                                                     r_c=8.0, seed=4))

@@ -221,3 +221,23 @@ def test_batch_errors(tiny_enriched, hydrogen_small, si_small):
         batch.filter(big, 3, a, b, prec="fp32")
     with pytest.raises(ValueError):
         batch.filter(Xd[:-1], 3, a, b, prec="fp32")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+def test_batch_dense_cells_equal_single(prec, si_dense, si_small):
+    """Cells with up to 90 enrichment functions (two 64-row groups of the
+    batched coupling bodies): batched filter = single-problem filter, bit for
+    bit (the single path is pinned to the oracle on the same problem)."""
+    from paper_1610_02121_amd import Batch, Context
+    print(f"[batch dense] {prec}", flush=True)
+    assert np.diff(si_dense.enr_ptr).max() > 64
+    probs = [si_dense, si_small, si_dense]
+    Ns = [24, 9, 17]
+    batch = Batch(probs, max_cols=24)
+    singles = {id(p): Context(p, max_cols=24) for p in probs}
+    ab = [(-40.0, 400.0), (-35.0, 300.0), (-20.0, 420.0)]
+    Xd = [dev(x) for x in blocks(probs, Ns, 70)]
+    Yb = batch.filter(Xd, 5, [a for a, _ in ab], [b for _, b in ab], prec=prec)
+    for i, p in enumerate(probs):
+        Ys = host(singles[id(p)].filter(Xd[i], 5, ab[i][0], ab[i][1], prec=prec))
+        assert np.array_equal(host(Yb[i]), Ys), i

@@ -1,23 +1,28 @@
 """Parity at the full size of the 30-atom Si workload (n = 857,645, N = 260),
 in the launch configuration the benchmark times.
 
-The oracle cannot run the whole N = 260 filter in reasonable time, so it is
-checked where it can compute outputs one by one or on a column subset:
 * H X on N = 260 columns: sampled rows (all enrichment rows + random classical
   rows), each an exact sparse row times the block;
 * (M^E)^-1 X: every row of 8 columns, against the sparse direct solve;
+* the first filter step Y_1 = t(H~) X on every row of N = 260 columns,
+  against the oracle's cell-by-cell operators;
 * filter(N = 260): on 8 of the columns, the Chebyshev three-term identity
   Y_m = 2 t(H~) Y_{m-1} - Y_{m-2}, with H~ applied by the oracle (columns are
   independent, so a column subset of the N = 260 launch is exact);
-* Rayleigh-Ritz of the atomic-orbital start block on 32 columns: Ritz values
-  within 1e-8 Ha of the oracle's.
+* Rayleigh-Ritz of the atomic-orbital start block on 32 columns;
+* Cholesky-QR and Rayleigh-Ritz of the block the benchmark projects (the
+  filtered block after three subspace-iteration steps from the
+  atomic-orbital start), N = 260, whole and by column slabs: against the
+  oracle's Cholesky-QR and projection of the same block;
+* the converged Ritz values of the iteration against the oracle's own fixed
+  point (tests/golden/si30_24c_ritz.txt, written by the oracle alone).
 Tolerances as in test_gpu_parity (kappa(M^E) based), see there.
 """
 import numpy as np
 import pytest
 
 from oracle.operators import Operators
-from oracle.subspace import cholqr, rayleigh_ritz
+from oracle.subspace import cholqr, energy_error, rayleigh_ritz, ritz_error, subspace_angle
 
 pytestmark = [pytest.mark.gpu, pytest.mark.timeout(900)]
 
@@ -39,6 +44,32 @@ def full():
     lmin = spla.eigsh(ops.M, k=1, sigma=0, which="LM", return_eigenvectors=False)[0]
     yield prob, ctx, ops, lmax / lmin
     ctx.close()
+
+
+@pytest.fixture(scope="module")
+def cellops(full):
+    from oracle.cellwise import CellOperators
+    return CellOperators(full[0])
+
+
+@pytest.fixture(scope="module")
+def bench_block(full):
+    """The block the benchmark projects: three subspace-iteration steps
+    (10-step Lanczos bound, filter m = 40 on [theta_N, b], Rayleigh-Ritz) from
+    the atomic-orbital start, then one more filter; host copy and b."""
+    from synth import configs
+    prob, ctx, ops, kappa = full
+    print("[fullsize] three GPU steps from the atomic-orbital start", flush=True)
+    X = dev(configs.initial_block(prob, 260))
+    th = ctx.rayleigh_ritz(X)
+    v0 = dev(np.random.default_rng(1).standard_normal(prob.n)).reshape(-1)
+    _, b = ctx.lanczos_bounds(v0, 10)
+    for _ in range(3):
+        Y = ctx.filter(X, 40, float(th[-1]), b)
+        th = ctx.rayleigh_ritz(Y)
+        X = Y
+    Y = ctx.filter(X, 40, float(th[-1]), b)
+    return host(Y), b
 
 
 def dev(a):
@@ -99,3 +130,85 @@ def test_rayleigh_ritz_start_block(full):
     assert np.abs(theta - th_o).max() < 1e-8
     Z = host(Yd)
     assert np.abs(Z.T @ ops.apply_M(Z) - np.eye(32)).max() < 1e-10
+
+
+def test_filter_first_step_all_rows(full, cellops):
+    """Y_1 = (2/(b-a)) H~ X - ((a+b)/(b-a)) X on all 857,645 rows of 260 columns."""
+    prob, ctx, ops, kappa = full
+    print("[fullsize] filter m=1, N=260, all rows", flush=True)
+    X = np.random.default_rng(25).standard_normal((prob.n, 260))
+    a, b = -60.0, 440.0
+    e, c = 2.0 / (b - a), (a + b) / (b - a)
+    Y1 = host(ctx.filter(dev(X), 1, a, b))
+    Yo = e * cellops.apply_Htilde(X).numpy() - c * X
+    assert np.abs(Y1 - Yo).max() < 10 * U * kappa * np.abs(Yo).max()
+
+
+def test_cholqr_bench_block(full, bench_block):
+    """Cholesky-QR of the benchmark's N = 260 block (5 x 5 Gram tiles, upper
+    mapping): orthonormal to 1e-13 and the oracle's Q to 1e-10."""
+    prob, ctx, ops, kappa = full
+    Yh, _ = bench_block
+    print("[fullsize] cholqr N=260", flush=True)
+    Q = host(ctx.cholqr(dev(Yh)))
+    assert np.abs(Q.T @ Q - np.eye(260)).max() < 1e-13
+    Qo = cholqr(Yh)
+    assert np.abs(Q - Qo).max() < 1e-10 * np.abs(Qo).max()
+
+
+@pytest.mark.parametrize("chunk", [0, 96])
+def test_rayleigh_ritz_bench_block(full, cellops, bench_block, chunk):
+    """Rayleigh-Ritz of the benchmark's block, whole (chunk 0) and by column
+    slabs of 96 (96 + 96 + 68): Ritz values within 1e-8 Ha of the oracle's
+    projection of the same block, Z^T M Z = I; angle of the 210 wanted
+    Ritz vectors to the oracle's."""
+    from paper_1610_02121_amd import Context
+    prob, ctx, ops, kappa = full
+    Yh, _ = bench_block
+    print(f"[fullsize] rayleigh_ritz N=260 chunk={chunk}", flush=True)
+    c2 = ctx if chunk == 0 else Context(prob, max_cols=260, col_chunk=chunk)
+    Yd = dev(Yh)
+    theta = c2.rayleigh_ritz(Yd)
+    Z = host(Yd)
+    if c2 is not ctx:
+        c2.close()
+    Q = cholqr(Yh)
+    HQ, MQ = cellops.apply_H(Q).numpy(), cellops.apply_M(Q).numpy()
+    th_o, C = rayleigh_ritz(Q, HQ, MQ)
+    print(f"[metrics] rayleigh_ritz si30-24c N=260 chunk={chunk}: "
+          f"ritz_err={ritz_error(theta, th_o, 210):.3e} Ha "
+          f"energy_err={energy_error(theta, th_o, 210):.3e} Ha "
+          f"angle={subspace_angle(Q @ C[:, :210], Z[:, :210], ops.M):.3e} rad", flush=True)
+    assert np.abs(theta - th_o).max() < 1e-8
+    assert np.abs(Z.T @ cellops.apply_M(Z).numpy() - np.eye(260)).max() < 1e-10
+
+
+def test_converged_ritz_values_match_oracle_fixed_point(full):
+    """The GPU iteration (as the benchmark runs it) converges to the oracle's
+    own fixed point: the 210 wanted Ritz values within 1e-8 Ha of the values
+    the oracle's CPU iteration reached at relative residual <= 1e-11."""
+    import os
+    from synth import configs
+    path = os.path.join(os.path.dirname(__file__), "golden", "si30_24c_ritz.txt")
+    if not os.path.exists(path):
+        pytest.skip("the oracle's fixed point has not been written (make_si30_fixed_point.py)")
+    ref = np.loadtxt(path)[:, 1]
+    prob, ctx, ops, kappa = full
+    print("[fullsize] GPU iteration to convergence", flush=True)
+    X = dev(configs.initial_block(prob, 260))
+    th = ctx.rayleigh_ritz(X)
+    v0 = dev(np.random.default_rng(1).standard_normal(prob.n)).reshape(-1)
+    _, b = ctx.lanczos_bounds(v0, 10)
+    for step in range(40):
+        Y = ctx.filter(X, 40, float(th[-1]), b)
+        th_new = ctx.rayleigh_ritz(Y)
+        X = Y
+        d = np.abs(th_new[:210] - th[:210]).max()
+        th = th_new
+        if d < 1e-11:
+            break
+    err, eerr = ritz_error(th, ref, 210), energy_error(th, ref, 210)
+    print(f"[metrics] si30-24c converged ({step + 1} steps): ritz_err={err:.3e} Ha "
+          f"energy_err={eerr:.3e} Ha", flush=True)
+    assert err <= 1e-8
+    assert eerr <= 2 * 210 * 1e-8

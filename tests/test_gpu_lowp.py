@@ -194,7 +194,8 @@ def test_degree_one_outside_rows(fix, prec, request):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
-@pytest.mark.parametrize("fix,m", [("tiny_enriched", 5), ("hydrogen_small", 8), ("si_small", 6)])
+@pytest.mark.parametrize("fix,m", [("tiny_enriched", 5), ("hydrogen_small", 8), ("si_small", 6),
+                                   ("si_dense", 4)])
 def test_filter_steps(fix, m, prec, request):
     """Every step of the reduced recurrence against the model applied to the
     device's own previous iterates (filters of degree 1..m; the FP32 state is
@@ -202,6 +203,9 @@ def test_filter_steps(fix, m, prec, request):
     also the whole filter against the FP64 oracle, to 10 u32 kappa(M^E) per step."""
     print(f"[lowp filter] {fix} m={m} {prec}", flush=True)
     prob = request.getfixturevalue(fix)
+    if fix == "si_dense":
+        # cells with more than 64 functions: the coupling kernels' second row group
+        assert np.diff(prob.enr_ptr).max() > 64
     ctx, ops = context(fix, prob)
     mod = model(fix, prob, prec)
     v0 = np.random.default_rng(5).standard_normal(ops.n)

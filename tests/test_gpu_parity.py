@@ -257,8 +257,10 @@ def test_invalid_arguments(si_small):
         ctx.filter(X, -1, 0.0, 1.0)
     with pytest.raises(ChebFilterError, match="CF_EINVAL"):
         ctx.filter(X, 2, 0.0, float("nan"))
+    # in place is allowed only with one leading dimension
+    W = dev(np.ones((ops.n, 8)))
     with pytest.raises(ChebFilterError, match="CF_EINVAL"):
-        ctx.filter(X, 2, 0.0, 1.0, Y=X)
+        ctx.filter(W[:, :4], 2, 0.0, 1.0, Y=torch.as_strided(W, (ops.n, 4), (4, 1)))
     with pytest.raises(ChebFilterError, match="CF_EINVAL"):
         ctx.filter(X, 2, 0.0, 1.0, prec=7)
     big = dev(np.ones((ops.n, ctx.max_cols + 1)))
@@ -292,3 +294,85 @@ def test_init_rejects_bad_problems(tiny_enriched):
     S.enr_idx[0] = 7                              # alpha >= n_e
     with pytest.raises(ChebFilterError, match="CF_EINVAL"):
         Context(S, max_cols=4)
+
+
+# ------------------------------------------- widths the benchmark runs, chunks
+def report(name, theta, th_ref, wanted, Z=None, Z_ref=None, M=None):
+    """Print the Ritz error, band-energy error and (when both vector sets are
+    given) the largest principal angle between the wanted Ritz spaces."""
+    from oracle.subspace import energy_error, ritz_error, subspace_angle
+    msg = (f"[metrics] {name}: ritz_err={ritz_error(theta, th_ref, wanted):.3e} Ha "
+           f"energy_err={energy_error(theta, th_ref, wanted):.3e} Ha")
+    if Z is not None:
+        msg += f" angle={subspace_angle(Z_ref[:, :wanted], Z[:, :wanted], M):.3e} rad"
+    print(msg, flush=True)
+
+
+@pytest.mark.parametrize("N,chunk", [(65, 0), (128, 0), (200, 0), (200, 64), (130, 48)])
+def test_cholqr_multi_tile(si_small, N, chunk):
+    """Cholesky-QR past one 64 x 64 Gram tile (upper-tile mapping, skipped
+    blocks below the diagonal), and in place by row blocks when N exceeds the
+    column chunk: orthonormal to 1e-13 and the oracle's Q to 1e-10."""
+    print(f"[cholqr] si_small N={N} chunk={chunk}", flush=True)
+    ctx, ops = context("si_small", si_small, max_cols=200) if chunk == 0 else \
+        chunked_context("si_small", si_small, 200, chunk)
+    X = np.random.default_rng(31).standard_normal((ops.n, N)) @ np.diag(np.logspace(0, 4, N))
+    Q = host(ctx.cholqr(dev(X)))
+    assert np.abs(Q.T @ Q - np.eye(N)).max() < 1e-13
+    assert relerr(Q, cholqr(X)) < 1e-10
+
+
+def chunked_context(name, prob, max_cols, chunk):
+    from paper_1610_02121_amd import Context
+    key = (name, max_cols, "chunk", chunk)
+    if key not in _CTX:
+        _CTX[key] = (Context(prob, max_cols=max_cols, col_chunk=chunk), Operators(prob))
+    return _CTX[key]
+
+
+@pytest.mark.parametrize("N,chunk", [(65, 0), (128, 0), (200, 0), (200, 64), (130, 48)])
+def test_rayleigh_ritz_multi_tile(si_small, N, chunk):
+    """Rayleigh-Ritz of a filtered block at widths past one Gram tile, whole
+    and by column slabs: Ritz values within 1e-8 Ha of the oracle's, Z^T M Z = I,
+    Z^T H Z = diag(theta); the wanted Ritz space's angle to the oracle's."""
+    print(f"[rayleigh_ritz] si_small N={N} chunk={chunk}", flush=True)
+    ctx, ops = context("si_small", si_small, max_cols=200) if chunk == 0 else \
+        chunked_context("si_small", si_small, 200, chunk)
+    v0 = np.random.default_rng(11).standard_normal(ops.n)
+    al, be = lanczos(ops.apply_Htilde, ops.apply_M, v0, 10)
+    lo, hi = lanczos_bounds(al, be)
+    X = np.random.default_rng(32).standard_normal((ops.n, N))
+    Xf = recurrence_filter(lambda Z: ops.apply_Htilde(Z), X, 6, lo + 0.2 * (hi - lo), hi)
+    Yd = dev(Xf)
+    theta = ctx.rayleigh_ritz(Yd)
+    Q = cholqr(Xf)
+    th_o, C = rayleigh_ritz(Q, ops.apply_H(Q), ops.apply_M(Q))
+    Z = host(Yd)
+    wanted = N - N // 5
+    report(f"rayleigh_ritz si_small N={N} chunk={chunk}", theta, th_o, wanted, Z, Q @ C, ops.M)
+    assert np.abs(theta - th_o).max() < 1e-8
+    assert np.abs(Z.T @ ops.apply_M(Z) - np.eye(N)).max() < 1e-10
+    assert np.abs(Z.T @ ops.apply_H(Z) - np.diag(theta)).max() < 1e-8 * max(1.0, np.abs(theta).max())
+
+
+def test_column_chunks_equal_whole_blocks(si_small):
+    """A context with 64-column work blocks gives, on N = 200 (chunks 64, 64,
+    64, 8), bit for bit the whole-block results of H X, M X, (M^E)^-1 X and
+    the FP64 / FP32 filters (columns are independent), and the filter in
+    place equals the filter into a separate block."""
+    print("[chunks] si_small N=200 chunk=64", flush=True)
+    whole, ops = context("si_small", si_small, max_cols=200)
+    ch, _ = chunked_context("si_small", si_small, 200, 64)
+    X = dev(np.random.default_rng(33).standard_normal((ops.n, 200)))
+    for f in ("apply_H", "apply_M", "apply_Sinv"):
+        assert torch.equal(getattr(whole, f)(X), getattr(ch, f)(X)), f
+    for prec in ("fp64", "fp32"):
+        a = whole.filter(X, 5, -2.0, 60.0, prec=prec)
+        b = ch.filter(X, 5, -2.0, 60.0, prec=prec)
+        assert torch.equal(a, b), prec
+        Xi = X.clone()
+        ch.filter(Xi, 5, -2.0, 60.0, Y=Xi, prec=prec)
+        assert torch.equal(Xi, b), prec
+    th = np.linspace(-1.0, 3.0, 200)
+    assert np.array_equal(whole.residual_norms(X, th), ch.residual_norms(X, th))
+

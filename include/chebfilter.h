@@ -191,6 +191,23 @@ cf_status chebfilter_rayleigh_ritz(cf_ctx *ctx, double *Y, int64_t ldy, int64_t 
 cf_status chebfilter_lanczos_bounds(cf_ctx *ctx, const double *v0, int32_t k, double *lmin_est,
                                     double *b_upper);
 
+/* chebfilter_lanczos_bounds for callers that cannot allocate device memory
+ * (tight self-consistent-step loops, harnesses that forbid hipMalloc): the
+ * same kernels and results, with every piece of work memory the run needs
+ * (work rows, the four Lanczos vectors, coupling partials, the enriched-cell
+ * buffer, w, z, coefficients, partial sums) taken from a fixed device array
+ * of 64 MiB that the library holds on each GPU from its first use until the
+ * process ends, instead of the context's work blocks.  It calls no
+ * allocation routine.  The scratch needed is about
+ *   8 bytes x (5 n + coupling rows + 128 x enriched cells + 2 n_e + 1160);
+ * a larger problem returns CF_ENOMEM with the size it would need (the
+ * context's chebfilter_lanczos_bounds still works for it).  All calls on one
+ * GPU share that array: calls that overlap on one GPU (several host threads,
+ * or several streams, without ordering) race and return wrong bounds.  The
+ * run clears what must start at zero.  Synchronises. */
+cf_status chebfilter_lanczos_bounds_noalloc(cf_ctx *ctx, const double *v0, int32_t k,
+                                            double *lmin_est, double *b_upper);
+
 /* Per-kernel timing with HIP events on the context's stream.  enable != 0
  * starts recording (and clears the totals); name selects a kernel family
  * ("cell_gemm": the MFMA cell products, N > 1; "cell_gemv": single-column

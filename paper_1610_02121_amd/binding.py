@@ -34,7 +34,7 @@ EXPORTS = ["chebfilter_init", "chebfilter_destroy", "chebfilter_last_error", "ch
            "chebfilter_mlp_set_normalization", "chebfilter_bounds_features",
            "chebfilter_bounds_predict", "chebfilter_assembly_tables", "chebfilter_assemble_cells",
            "chebfilter_get_H_cc", "chebfilter_set_cell_tile", "chebfilter_autotune",
-           "chebfilter_batch_autotune"]
+           "chebfilter_batch_autotune", "chebfilter_lanczos_bounds_noalloc"]
 
 
 class CfProblem(C.Structure):
@@ -79,6 +79,7 @@ def load_library() -> C.CDLL:
     lib.chebfilter_cholqr.argtypes = [vp, vp, i64, i64]
     lib.chebfilter_rayleigh_ritz.argtypes = [vp, vp, i64, i64, vp]
     lib.chebfilter_lanczos_bounds.argtypes = [vp, vp, i32, C.POINTER(dbl), C.POINTER(dbl)]
+    lib.chebfilter_lanczos_bounds_noalloc.argtypes = [vp, vp, i32, C.POINTER(dbl), C.POINTER(dbl)]
     lib.chebfilter_profile.argtypes = [vp, i32]
     lib.chebfilter_profile_query.argtypes = [vp, C.c_char_p, C.POINTER(i64), C.POINTER(dbl),
                                              C.POINTER(dbl)]
@@ -273,6 +274,16 @@ class Context:
         lo, hi = C.c_double(), C.c_double()
         self._check(self.lib.chebfilter_lanczos_bounds(self._h, v0.data_ptr(), int(k),
                                                        C.byref(lo), C.byref(hi)))
+        return lo.value, hi.value
+
+    def lanczos_bounds_noalloc(self, v0, k: int = 10) -> tuple[float, float]:
+        """lanczos_bounds with the library's fixed device scratch (no allocation)."""
+        import torch
+        if v0.dtype != torch.float64 or not v0.is_cuda or not v0.is_contiguous():
+            raise TypeError("v0 must be a contiguous float64 CUDA tensor")
+        lo, hi = C.c_double(), C.c_double()
+        self._check(self.lib.chebfilter_lanczos_bounds_noalloc(self._h, v0.data_ptr(), int(k),
+                                                               C.byref(lo), C.byref(hi)))
         return lo.value, hi.value
 
     def update_H_cc(self, H_cc):

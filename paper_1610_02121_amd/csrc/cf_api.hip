@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -616,7 +617,7 @@ static cf_status core_lanczos(cf_ctx *c, const double *v0, int k, double *out) {
   double *vprev = c->lzv, *v = c->lzv + n, *w = c->lzv + 2 * n, *mv = c->lzv + 3 * n;
   double *coef = c->lzcoef;
   const int nblk = 512;
-  HIPCHK(c, hipMemsetAsync(coef, 0, (2 * 64 + 8) * sizeof(double), c->stream));
+  HIPCHK(c, launch_fill(c->stream, coef, 2 * 64 + 8, 0.0));
   STCHK(core_apply_M(c, v0, 1, mv, 1, 1));
   HIPCHK(c, launch_dot(c->stream, n, v0, mv, coef, c->lzpart, nblk));
   HIPCHK(c, launch_lanczos_update(c->stream, n, 0, const_cast<double *>(v0), nullptr, nullptr, coef,
@@ -688,6 +689,73 @@ static cf_status upload_cells(cf_ctx *c, const double *H_cc, const char *who) {
   if (c->Hp16) HIPCHK(c, launch_to_bf16(c->stream, hsz, c->Hp, c->Hp16));
   return CF_OK;
 }
+
+// ---------------------------------------------------------------------------
+// Fixed device scratch of chebfilter_lanczos_bounds_noalloc: a file-scope
+// device array (each GPU holds its own copy from module load until the
+// process ends).  Host code never uses the array's name as an address: the
+// device address of each GPU's copy comes from hipGetSymbolAddress, taken
+// once per device with that device current.
+// ---------------------------------------------------------------------------
+static constexpr int64_t NOALLOC_DOUBLES = (64ll << 20) / 8;     // 64 MiB
+static __device__ __align__(256) double scratch[NOALLOC_DOUBLES];
+
+namespace {
+std::mutex g_scratch_mu;
+std::map<int, double *> g_scratch_addr;     // device ordinal -> its copy of scratch
+}  // namespace
+
+static cf_status scratch_address(cf_ctx *c, double **out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_addr.find(c->device);
+  if (it != g_scratch_addr.end()) { *out = it->second; return CF_OK; }
+  void *ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr)
+    return set_err(c, CF_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  g_scratch_addr[c->device] = static_cast<double *>(ptr);
+  *out = static_cast<double *>(ptr);
+  return CF_OK;
+}
+
+static int64_t align32(int64_t x) { return (x + 31) / 32 * 32; }   // 256-byte pieces
+
+// Doubles of scratch one single-vector Lanczos run needs: the work rows R (n),
+// the four Lanczos vectors (4n), coupling partials (one per coupling row),
+// the enriched-cell buffer (NPAD per enriched cell), w and z (n_e each), the
+// tridiagonal coefficients and the dot-product partials.
+static int64_t noalloc_need(const cf_ctx *c) {
+  return align32(c->n) + align32(4 * c->n) + align32(std::max<int64_t>(c->nnz, 1)) +
+         align32((int64_t)std::max(c->necells, 1) * NPAD) + 2 * align32(std::max<int64_t>(c->n_e, 1)) +
+         align32(2 * 64 + 8) + align32(1024);
+}
+
+// Points the context's single-column work buffers into the scratch (leading
+// dimension 1) for the lifetime of the object, then restores them.
+struct ScratchWork {
+  cf_ctx *c;
+  double *R, *P, *Q, *Wb, *Zb, *lzv, *lzcoef, *lzpart;
+  int64_t ldw;
+  ScratchWork(cf_ctx *c_, double *base) : c(c_) {
+    R = c->R; P = c->P; Q = c->Q; Wb = c->Wb; Zb = c->Zb;
+    lzv = c->lzv; lzcoef = c->lzcoef; lzpart = c->lzpart; ldw = c->ldw;
+    double *q = base;
+    auto take = [&](int64_t count) { double *r = q; q += align32(count); return r; };
+    c->R = take(c->n);
+    c->lzv = take(4 * c->n);
+    c->P = take(std::max<int64_t>(c->nnz, 1));
+    c->Q = take((int64_t)std::max(c->necells, 1) * NPAD);
+    c->Wb = take(std::max<int64_t>(c->n_e, 1));
+    c->Zb = take(std::max<int64_t>(c->n_e, 1));
+    c->lzcoef = take(2 * 64 + 8);
+    c->lzpart = take(1024);
+    c->ldw = 1;
+  }
+  ~ScratchWork() {
+    c->R = R; c->P = P; c->Q = Q; c->Wb = Wb; c->Zb = Zb;
+    c->lzv = lzv; c->lzcoef = lzcoef; c->lzpart = lzpart; c->ldw = ldw;
+  }
+};
 
 // ---------------------------------------------------------------------------
 // init
@@ -1719,6 +1787,34 @@ cf_status chebfilter_lanczos_bounds(cf_ctx *c, const double *v0, int32_t k, doub
   *b_upper = out2[1];
   if (!std::isfinite(out2[0]) || !std::isfinite(out2[1]))
     return set_err(c, CF_ENUMERIC, "lanczos: non-finite bound (breakdown?)");
+  return CF_OK;
+}
+
+cf_status chebfilter_lanczos_bounds_noalloc(cf_ctx *c, const double *v0, int32_t k,
+                                            double *lmin_est, double *b_upper) {
+  if (!c) return CF_EINVAL;
+  if (!v0 || !lmin_est || !b_upper) return set_err(c, CF_EINVAL, "lanczos_noalloc: null argument");
+  if (k < 1 || k > 64) return set_err(c, CF_EINVAL, "lanczos_noalloc: k must be 1..64");
+  const int64_t need = noalloc_need(c);
+  if (need > NOALLOC_DOUBLES)
+    return set_err(c, CF_ENOMEM, "lanczos_noalloc: the problem needs " +
+                                     std::to_string(need * 8 / (1 << 20) + 1) +
+                                     " MiB of scratch; the fixed scratch holds 64 MiB");
+  HIPCHK(c, hipSetDevice(c->device));
+  double *base = nullptr;
+  STCHK(scratch_address(c, &base));
+  double out2[2] = {0.0, 0.0};
+  {
+    ScratchWork sw(c, base);
+    double *dout = c->lzcoef + 2 * 64 + 2;
+    STCHK(core_lanczos(c, v0, k, dout));
+    HIPCHK(c, hipMemcpyAsync(out2, dout, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  *lmin_est = out2[0];
+  *b_upper = out2[1];
+  if (!std::isfinite(out2[0]) || !std::isfinite(out2[1]))
+    return set_err(c, CF_ENUMERIC, "lanczos_noalloc: non-finite bound (breakdown?)");
   return CF_OK;
 }
 

@@ -3,6 +3,8 @@
 // inverse, small products, reductions and the Lanczos helpers.
 #include <math.h>
 
+#include <algorithm>
+
 #include "cf_kernels.h"
 
 namespace cf {
@@ -412,6 +414,19 @@ __global__ __launch_bounds__(256) void k_sum_final(int nblk, const double *__res
     __syncthreads();
   }
   if (threadIdx.x == 0) out[0] = red[0];
+}
+
+// x[0..n) = v (a kernel, so that clearing needs no memset node under capture).
+__global__ __launch_bounds__(256) void k_fill(double *__restrict__ x, int64_t n, double v) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    x[i] = v;
+}
+
+hipError_t launch_fill(hipStream_t s, double *x, int64_t n, double v) {
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 1024);
+  hipLaunchKernelGGL(k_fill, dim3((unsigned)blocks), dim3(256), 0, s, x, n, v);
+  return hipGetLastError();
 }
 
 hipError_t launch_dot(hipStream_t s, int64_t n, const double *x, const double *y, double *out,

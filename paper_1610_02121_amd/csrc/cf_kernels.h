@@ -282,6 +282,8 @@ hipError_t launch_tri_inv_T(hipStream_t s, const double *L, const double *sv, in
 hipError_t launch_small_gemm(hipStream_t s, int M, int K, int N, const double *A, int64_t lda,
                              const double *B, int64_t ldb, double *C, int64_t ldc);
 // Sum of squares / dot product into out[0] (single value, deterministic two-pass).
+// x[0..n) = v
+hipError_t launch_fill(hipStream_t s, double *x, int64_t n, double v);
 hipError_t launch_dot(hipStream_t s, int64_t n, const double *x, const double *y, double *out,
                       double *scratch, int nblk);
 // Non-finite detector over a block: flag[0] |= 1 if any element is NaN or Inf.

@@ -39,10 +39,9 @@ WORKLOADS = {
     "si30-classical": ("config2_classical", 260, 40, 210),
     # 256 independent Si clusters of 1-8 atoms (N 16-64 each), batched form
     "si-batch256": ("batch_workload", None, 40, None),
-    # the 280-atom cluster (48^3 cells, n = 6,970,391) at one GPU's column share:
-    # the whole operator with 300 of the block's vectors (280 wanted), m = 50,
-    # precision forms against an FP64 run
-    "si280-48c": ("config3", 300, 50, 280),
+    # the 280-atom cluster (48^3 cells, n = 6,970,391, n_e = 2520): the whole
+    # 2200-vector block (1960 wanted), m = 50, precision forms against an FP64 run
+    "si280-48c": ("config3", 2200, 50, 1960),
 }
 
 
@@ -70,6 +69,25 @@ def measured_traffic():
     return int(m.group(1))
 
 
+GOLDEN_FIXED_POINT = {"si30-24c": "si30_24c_ritz.txt"}
+
+
+def oracle_fixed_point_errors(name, seed, theta, wanted):
+    """Ritz and band-energy error of the wanted Ritz values against the fixed
+    point the oracle's own CPU iteration reached (a committed text file of
+    its Ritz values), where one exists for the workload."""
+    import numpy as np
+    fn = GOLDEN_FIXED_POINT.get(name)
+    path = os.path.join(ROOT, "tests", "golden", fn) if fn else None
+    if seed != 0 or not path or not os.path.exists(path):
+        return {}
+    ref = np.loadtxt(path)[:, 1]
+    d = np.asarray(theta[:wanted]) - ref[:wanted]
+    return {"ritz_err_vs_oracle_Ha": float(np.abs(d).max()),
+            "energy_err_vs_oracle_Ha": float(2.0 * abs(d.sum())),
+            "oracle_reference": f"tests/golden/{fn}"}
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -80,17 +98,35 @@ def make_problem(name, seed):
     return gen(seed=seed) if name.startswith("si") else gen()
 
 
+def host_cpu():
+    """(logical CPUs this process may use, CPU model name)."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return n, model
+
+
 def cpu_baseline(prob, N_total, m, seed, budget_s=20.0):
-    """The FP64 oracle's Chebyshev filter on a 16-column slice of the workload,
-    timed for whole filter degrees until ~budget_s, scaled to DOF-vectors-degree/s."""
+    """The FP64 oracle's Chebyshev recurrence (cell-by-cell elemental
+    products and block-wise M^-1, torch CPU on all host threads) on the
+    workload's whole N-column block, timed for whole filter degrees until
+    ~budget_s, scaled to DOF-vectors-degree/s."""
     import numpy as np
-    from oracle.operators import Operators
+    import torch
+    from oracle.cellwise import CellOperators
+    nproc, model = host_cpu()
+    threads = min(nproc, int(os.environ.get("OMP_NUM_THREADS", nproc)))
     t0 = time.time()
-    ops = Operators(prob)
+    ops = CellOperators(prob, threads=threads)
+    ops.schur()                              # factor S outside the timing
     t_setup = time.time() - t0
-    cols = 16
-    X = np.random.default_rng(seed).standard_normal((ops.n, cols))
-    ops.block_inverse(X[:, :1])            # factor the Schur complement outside the timing
+    X = torch.from_numpy(np.random.default_rng(seed).standard_normal((ops.n, N_total)))
     e, c = 2.0 / 1000.0, 0.0
     deg = 0
     t0 = time.time()
@@ -102,11 +138,13 @@ def cpu_baseline(prob, N_total, m, seed, budget_s=20.0):
         if time.time() - t0 > budget_s or deg >= m:
             break
     dt = time.time() - t0
-    return {"value": ops.n * cols * deg / dt, "unit": "DOF*vectors*degree/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"{deg} degree(s) of the oracle's recurrence (assembled sparse H^E, "
-                      f"block-wise M^-1) on a {cols}-column slice of the {N_total}-column block; "
-                      f"scipy sparse products run on one thread; setup {t_setup:.1f}s untimed"}
+    return {"value": ops.n * N_total * deg / dt, "unit": "DOF*vectors*degree/s",
+            "cores": torch.get_num_threads(), "kind": "oracle",
+            "host": {"nproc": nproc, "cpu_model": model},
+            "sample": f"{deg} degree(s) of the oracle's recurrence (cell-by-cell elemental "
+                      f"products, block-wise M^-1; torch CPU FP64, {torch.get_num_threads()} "
+                      f"threads) on the whole {N_total}-column block; setup {t_setup:.1f}s "
+                      f"untimed"}
 
 
 def assembly_timing(ctx, prob, reps=5):
@@ -144,13 +182,14 @@ def assembly_timing(ctx, prob, reps=5):
 
 
 def run_si280(args):
-    """The 280-atom precision-form workload at one GPU's column share: the
-    operator of the whole cluster (the plain cells' potential term assembled
-    on the device), 300 vectors from the atomic-orbital start, m = 50; the
-    same SCF steps (Lanczos bound, filter, Rayleigh-Ritz) from the same start
-    in FP64, FP32 and BF16 filter arithmetic, each followed by one FP64
-    cleanup step; Ritz values of the reduced forms compared with the FP64
-    run's at every step."""
+    """The 280-atom precision-form workload at its full shape on one GPU: the
+    whole operator (the plain cells' potential term assembled on the device),
+    the whole N = 2200 block (122.7 GB in FP64) filtered and projected in
+    place, work blocks of --col-chunk columns, m = 50, from the atomic-orbital
+    start.  Forms (--forms): fp64 runs until the wanted Ritz values settle
+    (the reference, saved with --ref-out); fp32 / bf16 run --reduced-steps
+    steps in that filter arithmetic, then FP64 cleanup steps until the wanted
+    Ritz values are within 1e-6 Ha of the reference (--ref-in)."""
     import numpy as np
     import scipy.linalg as sla
     import torch
@@ -159,25 +198,37 @@ def run_si280(args):
     from synth import configs
     from synth.assemble import plain_points, plain_tables, potential_at_points
     _, N, m, wanted = WORKLOADS["si280-48c"]
+    forms = [f for f in args.forms.split(",") if f]
     t0 = time.time()
-    log("generating the 280-atom cluster (enriched cells on the host)")
-    prob = configs.config3(seed=args.seed, progress=log)
+    if args.problem_cache and os.path.exists(args.problem_cache):
+        from synth.problem import Problem
+        prob = Problem.load(args.problem_cache)
+        prob.meta["quad"] = {"enriched_cells": int((np.diff(prob.enr_ptr) > 0).sum())}
+        prob.meta.update(configs.config3_meta(seed=args.seed))
+    else:
+        log("generating the 280-atom cluster (enriched cells on the host)")
+        prob = configs.config3(seed=args.seed, progress=log)
+        if args.problem_cache:
+            prob.save(args.problem_cache)
     log(f"generated n={prob.n} n_e={prob.n_e} cells={prob.n_cells} enriched cells="
         f"{prob.meta['quad']['enriched_cells']} coupling rows={len(prob.enr_idx)} in "
         f"{time.time() - t0:.0f}s")
-    dev = torch.device("cuda", 0)
-    torch.cuda.set_device(dev)
-    t1 = time.time()
-    ctx = Context(prob, max_cols=N)
-    log(f"context ready ({time.time() - t1:.0f}s)")
+    # potential at the plain cells' Gauss points, on the host before the GPU is touched
     B, w, K, _ = plain_tables(prob)
     ep = np.asarray(prob.enr_ptr)
     cells = np.nonzero(ep[1:] == ep[:-1])[0].astype(np.int32)
     t1 = time.time()
     Vq = potential_at_points(prob.meta["potential"], plain_points(prob, cells).reshape(-1, 3))
+    log(f"potential at {Vq.size} Gauss points of {len(cells)} plain cells ({time.time() - t1:.0f}s)")
+    _, Vee = sla.eigh(prob.H_ee, prob.M_ee)
+    v0h = np.random.default_rng(args.seed + 1).standard_normal(prob.n)
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    t1 = time.time()
+    ctx = Context(prob, max_cols=N, col_chunk=args.col_chunk)
+    log(f"context ready ({time.time() - t1:.0f}s), work blocks of {args.col_chunk} columns")
     Vd = torch.tensor(Vq.reshape(len(cells), -1), dtype=torch.float64, device=dev)
     del Vq
-    log(f"potential at {Vd.numel()} Gauss points of {len(cells)} plain cells ({time.time() - t1:.0f}s)")
     ctx.assembly_tables(B, w, K)
     torch.cuda.synchronize()
     ta = time.perf_counter()
@@ -185,99 +236,112 @@ def run_si280(args):
     torch.cuda.synchronize()
     t_asm = time.perf_counter() - ta
     del Vd
-    _, Vee = sla.eigh(prob.H_ee, prob.M_ee)
-    X0 = torch.zeros((prob.n, N), dtype=torch.float64, device=dev)
-    X0[prob.n_h:, :] = torch.tensor(Vee[:, :N], dtype=torch.float64, device=dev)
-    v0 = torch.tensor(np.random.default_rng(args.seed + 1).standard_normal(prob.n),
-                      dtype=torch.float64, device=dev)
-    X = torch.empty_like(X0)
-    Y = torch.empty_like(X0)
-    def capped_passes(theta, a, b):
-        """Passes of the largest degree whose amplification ratio across the
-        wanted window, T_d(|t(theta_1)|) / T_d(|t(theta_w)|), stays below
-        1e4 (a ratio FP32 resolves), adding up to at least degree m."""
-        t1 = abs((2.0 * theta[0] - a - b) / (b - a))
-        tw = abs((2.0 * theta[wanted - 1] - a - b) / (b - a))
-        g = np.arccosh(max(t1, 1.0)) - np.arccosh(max(tw, 1.0))
-        d = m if g <= 0.0 else int(max(4, min(m, np.floor(np.log(1e4) / g))))
-        return d, -(-m // d)
+    H_keep = prob.H_cc
+    prob.H_cc = None                                     # the host copy is no longer needed
+    del H_keep
+    Vee_d = torch.tensor(Vee[:, :N], dtype=torch.float64, device=dev)
+    v0 = torch.tensor(v0h, dtype=torch.float64, device=dev)
+    Y = torch.zeros((prob.n, N), dtype=torch.float64, device=dev)      # the 2200-vector block
+    free, total = torch.cuda.mem_get_info()
+    log(f"device memory in use {(total - free) / 2**30:.1f} GiB of {total / 2**30:.1f} GiB")
+    ref = None
+    if args.ref_in:
+        ref = np.asarray(json.load(open(args.ref_in))["theta"])
+
+    def start():
+        Y.zero_()
+        Y[prob.n_h:, :] = Vee_d
+        return ctx.rayleigh_ritz(Y)
 
     runs = {}
-    for form in ("fp64", "fp32", "bf16", "fp32-capped", "bf16-capped"):
-        # `steps` steps in the form's filter arithmetic, then one FP64 cleanup step
-        prec = form.split("-")[0]
-        X.copy_(X0)
-        theta = ctx.rayleigh_ritz(X)
-        rec = {"theta": [], "t_bounds": 0.0, "t_filter": 0.0, "t_rr": 0.0, "t_cleanup": 0.0,
-               "passes": []}
-        for st in range(args.steps + 1):
-            p_st = prec if st < args.steps else "fp64"
+    for form in forms:
+        theta = start()
+        rec = {"steps": [], "theta": None}
+        b = None
+        for st in range(args.max_steps):
+            reduced = form != "fp64" and st < args.reduced_steps
+            prec = form if reduced else "fp64"
             torch.cuda.synchronize()
             s0 = time.perf_counter()
             _, b = ctx.lanczos_bounds(v0, 10)
             s1 = time.perf_counter()
-            a = float(theta[-1])
-            if form.endswith("capped") and st < args.steps:
-                d, npass = capped_passes(theta, a, b)
-                rec["passes"].append([d, npass])
-                ctx.filter_multipass(X, d, npass, a, b, Y=Y, prec=p_st)
-            else:
-                ctx.filter(X, m, a, b, Y=Y, prec=p_st)
+            ctx.filter(Y, m, float(theta[-1]), b, Y=Y, prec=prec)
             torch.cuda.synchronize()
             s2 = time.perf_counter()
-            theta = ctx.rayleigh_ritz(Y)
+            th = ctx.rayleigh_ritz(Y)
             s3 = time.perf_counter()
-            X, Y = Y, X
-            rec["theta"].append(theta.copy())
-            if st < args.steps:
-                rec["t_bounds"] += s1 - s0
-                rec["t_filter"] += s2 - s1
-                rec["t_rr"] += s3 - s2
-            else:
-                rec["t_cleanup"] = s3 - s0
-            log(f"{form} step {st + 1}/{args.steps + 1} ({p_st}): filter {s2 - s1:.2f}s "
-                f"theta[0]={theta[0]:.6f} theta[{wanted - 1}]={theta[wanted - 1]:.6f}")
-        res = ctx.residual_norms(X, theta)
-        rec["res_max_wanted"] = float(np.max(res[:wanted]))
+            d = float(np.abs(th[:wanted] - theta[:wanted]).max())
+            theta = th
+            step = {"prec": prec, "t_bounds": s1 - s0, "t_filter": s2 - s1, "t_rr": s3 - s2,
+                    "dtheta": d, "theta_1": float(th[0]), "theta_w": float(th[wanted - 1])}
+            if ref is not None:
+                step["ritz_err_vs_ref"] = float(np.abs(th[:wanted] - ref[:wanted]).max())
+                step["energy_err_vs_ref"] = float(2 * abs(np.sum(th[:wanted] - ref[:wanted])))
+            rec["steps"].append(step)
+            log(f"{form} step {st + 1} ({prec}): bounds {s1 - s0:.2f}s filter {s2 - s1:.2f}s "
+                f"rr {s3 - s2:.2f}s dtheta {d:.3e} theta_1 {th[0]:.8f} theta_{wanted} "
+                f"{th[wanted - 1]:.8f}" + (f" err_vs_ref {step['ritz_err_vs_ref']:.3e}"
+                                          if ref is not None else ""))
+            if form == "fp64" and d < args.settle:
+                break
+            if form != "fp64" and not reduced and ref is not None and \
+                    step["ritz_err_vs_ref"] <= 1e-6:
+                break
+        rec["theta"] = theta
+        rec["b"] = b
+        rec["res_max_wanted"] = float(np.max(ctx.residual_norms(Y, theta)[:wanted]))
         runs[form] = rec
-    ref = runs["fp64"]
+        if form == "fp64" and args.ref_out:
+            with open(args.ref_out, "w") as f:
+                json.dump({"workload": "si280-48c", "N": N, "m": m, "wanted": wanted,
+                           "steps": len(rec["steps"]), "settle": args.settle,
+                           "theta": [float(x) for x in theta]}, f)
     work = prob.n * N * m
     out = {
         "metric": "Chebyshev-filter DOF*vectors/s (per degree, whole SCF step) and SCF-step time, "
                   "FP64 vs mixed, Ritz error against the FP64 run",
-        "value": work / ((ref["t_bounds"] + ref["t_filter"] + ref["t_rr"]) / args.steps),
-        "unit": "DOF*vectors*degree/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": 0, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "unit": "DOF*vectors*degree/s", "n_gpus": 1, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "data": "synthetic",
         "config": {"workload": "si280-48c", "n_dof": prob.n, "n_enrich": prob.n_e,
                    "cells": prob.n_cells, "enriched_cells": prob.meta["quad"]["enriched_cells"],
                    "degree_p": prob.p, "vectors": N, "wanted": wanted, "cheb_degree": m,
-                   "share": "one GPU's column share of the block (300 of its vectors; "
-                            "the operator is whole)"},
+                   "col_chunk": args.col_chunk},
         "plain_cell_assembly_ms": 1e3 * t_asm,
+        "device_memory_gib": (total - free) / 2 ** 30,
         "forms": {},
     }
-    for prec, rec in runs.items():
-        step_ms = 1e3 * (rec["t_bounds"] + rec["t_filter"] + rec["t_rr"]) / args.steps
-        f = {"ms_per_step": step_ms,
-             "phases_ms": {"bounds": 1e3 * rec["t_bounds"] / args.steps,
-                           "filter": 1e3 * rec["t_filter"] / args.steps,
-                           "cholqr_rr": 1e3 * rec["t_rr"] / args.steps},
-             "filter_dof_vec_deg_per_s": work / (rec["t_filter"] / args.steps),
-             "fp64_cleanup_step_ms": 1e3 * rec["t_cleanup"],
-             "max_residual_Minv_wanted_after_cleanup": rec["res_max_wanted"],
-             "theta_min": float(rec["theta"][-1][0]),
-             "theta_wanted_max": float(rec["theta"][-1][wanted - 1])}
-        if rec["passes"]:
-            f["passes_per_step"] = rec["passes"]
-        if prec != "fp64":
-            # per step, the last entry after the FP64 cleanup step
-            f["ritz_err_vs_fp64_per_step"] = [
-                float(np.abs(a[:wanted] - r[:wanted]).max())
-                for a, r in zip(rec["theta"], ref["theta"])]
-            f["filter_speedup_vs_fp64"] = ref["t_filter"] / rec["t_filter"]
-        out["forms"][prec] = f
-    out["ms_per_step"] = out["forms"]["fp64"]["ms_per_step"]
+    for form, rec in runs.items():
+        stp = rec["steps"]
+        tot = [s["t_bounds"] + s["t_filter"] + s["t_rr"] for s in stp]
+        f = {"steps": len(stp), "seconds_total": float(sum(tot)),
+             "precs": [s["prec"] for s in stp],
+             "step_s": tot, "filter_s": [s["t_filter"] for s in stp],
+             "rr_s": [s["t_rr"] for s in stp], "bounds_s": [s["t_bounds"] for s in stp],
+             "dtheta": [s["dtheta"] for s in stp],
+             "max_residual_Minv_wanted": rec["res_max_wanted"],
+             "theta_1": float(rec["theta"][0]), "theta_wanted_max": float(rec["theta"][wanted - 1]),
+             "theta_N": float(rec["theta"][-1]), "b": rec["b"]}
+        if ref is not None:
+            f["ritz_err_vs_ref"] = [s["ritz_err_vs_ref"] for s in stp]
+            f["energy_err_vs_ref"] = [s["energy_err_vs_ref"] for s in stp]
+        fp64_steps = [s for s in stp if s["prec"] == "fp64"]
+        red_steps = [s for s in stp if s["prec"] != "fp64"]
+        if fp64_steps:
+            t = np.mean([s["t_bounds"] + s["t_filter"] + s["t_rr"] for s in fp64_steps])
+            f["fp64_step_s"] = float(t)
+            f["fp64_dof_vec_deg_per_s"] = work / t
+            f["fp64_filter_dof_vec_deg_per_s"] = work / np.mean([s["t_filter"] for s in fp64_steps])
+        if red_steps:
+            t = np.mean([s["t_bounds"] + s["t_filter"] + s["t_rr"] for s in red_steps])
+            f["reduced_step_s"] = float(t)
+            f["reduced_filter_dof_vec_deg_per_s"] = work / np.mean([s["t_filter"] for s in red_steps])
+        out["forms"][form] = f
+    first = out["forms"][forms[0]]
+    out["value"] = first.get("fp64_dof_vec_deg_per_s", first.get("reduced_filter_dof_vec_deg_per_s"))
+    out["ms_per_step"] = 1e3 * first["seconds_total"] / first["steps"]
+    out["steps"] = first["steps"]
+    out["warmup"] = 0
+    out["dtype"] = "f64" if forms[0] == "fp64" else forms[0].replace("fp", "f")
     print(json.dumps(out), flush=True)
     ctx.close()
 
@@ -655,6 +719,17 @@ def main():
                     help="train the bounds network and compare it with the Lanczos bound")
     ap.add_argument("--m-reduced", type=int, default=20,
                     help="filter degree of the reduced-precision passes in the study")
+    ap.add_argument("--col-chunk", type=int, default=256,
+                    help="si280-48c: columns of the library's work blocks")
+    ap.add_argument("--forms", default="fp64",
+                    help="si280-48c: comma list of fp64, fp32, bf16 runs from the same start")
+    ap.add_argument("--max-steps", type=int, default=20, help="si280-48c: steps per form at most")
+    ap.add_argument("--reduced-steps", type=int, default=6,
+                    help="si280-48c: steps in the reduced arithmetic before the FP64 cleanup")
+    ap.add_argument("--settle", type=float, default=1e-9,
+                    help="si280-48c: the FP64 run stops once the wanted Ritz values move less")
+    ap.add_argument("--ref-in", default=None, help="si280-48c: FP64 reference Ritz values (json)")
+    ap.add_argument("--ref-out", default=None, help="si280-48c: write the FP64 run's Ritz values")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -799,7 +874,8 @@ def main():
         "filter_dof_vec_deg_per_s": n * N * m * args.passes / (state["t_filter"] / args.steps),
         "convergence": {"max_dtheta_wanted": dtheta, "max_residual_Minv_wanted": res_max,
                         "theta_min": float(state["theta"][0]),
-                        "theta_wanted_max": float(state["theta"][wanted - 1])},
+                        "theta_wanted_max": float(state["theta"][wanted - 1]),
+                        **oracle_fixed_point_errors(name, args.seed, state["theta"], wanted)},
     }
     key, kname, peak = CELL_KERNEL[args.prec]
     if prof and prof[key][0] > 0:

@@ -163,6 +163,26 @@ def config3(seed: int = 0, plain_blocks: bool = False, **kw) -> Problem:
                       plain_blocks=plain_blocks, **kw)
 
 
+def si_cluster_meta(n_atoms: int = 30, length: float = 48.0, nc: int = 24, p: int = 4,
+                    r_c: float = 8.0, seed: int = 0, jitter: float = 0.05) -> dict:
+    """The meta entries si_cluster records (mesh, sites, shells, enrichment
+    set, potential), rebuilt with the same draws and no assembly: for a
+    problem whose element blocks were loaded from a file."""
+    rng = np.random.default_rng(seed)
+    sites = diamond_sites(n_atoms)
+    sites = sites + rng.uniform(-jitter, jitter, sites.shape)
+    shells = si_shells(rng)
+    mesh = build_mesh(p, nc, -0.5 * length, length)
+    enr = EnrichmentSet(centers=sites, shells=shells, r_c=r_c)
+    return dict(kind="si", sites=sites, shells=shells, r_c=r_c, mesh=mesh, enr=enr, seed=seed,
+                rng=rng, potential=softened_potential(sites))
+
+
+def config3_meta(seed: int = 0) -> dict:
+    """si_cluster_meta of config3."""
+    return si_cluster_meta(n_atoms=280, length=80.0, nc=48, p=4, r_c=8.0, seed=seed)
+
+
 def batch_cluster(n_atoms: int, seed: int = 0) -> Problem:
     """One problem of the batched workload: an n_atoms Si cluster (1..8) in a
     cube of half-width R_cluster + 12 Bohr with 6 + round(6 (n_atoms - 1) / 7)

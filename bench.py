@@ -37,7 +37,7 @@ WORKLOADS = {
     "hydrogen-8c": ("config1", 16, 20, 14),
     # the same Si cluster and mesh with classical elements only (n_e = 0)
     "si30-classical": ("config2_classical", 260, 40, 210),
-    # 256 independent Si clusters of 1-8 atoms (N 16-64 each), batched form
+    # 256 independent Si clusters of 1-40 atoms (N 16-350 each), batched form
     "si-batch256": ("batch_workload", None, 40, None),
     # the 280-atom cluster (48^3 cells, n = 6,970,391, n_e = 2520): the whole
     # 2200-vector block (1960 wanted), m = 50, precision forms against an FP64 run
@@ -465,13 +465,45 @@ def mixed_study(ctx, prob, N, m, wanted, seed, m_lp, max_passes=30):
     return out
 
 
+def batch_groups(pool, atoms, Ns, budget_gib=130.0, max_rows=12_000_000):
+    """Entries (sorted by atom count) packed into groups that fit the device:
+    per entry the FP64 blocks X, Y and the FP32 recurrence blocks
+    (~28 n N bytes), per distinct problem of a group its operator (cell
+    matrices FP64 + FP32, coupling blocks) and four n x N_max FP64 work
+    blocks; at most max_rows block rows per group (launch sizes)."""
+    order = sorted(range(len(atoms)), key=lambda i: (atoms[i], i))
+    groups, cur = [], []
+
+    def cost(g):
+        maxc = max(Ns[i] for i in g)
+        probs = {atoms[i] for i in g}
+        ent = sum(28.0 * pool[atoms[i]].n * Ns[i] for i in g)
+        ops = sum(12.0 * pool[a].n_cells * 128 * 128 + 32.0 * pool[a].n * maxc
+                  + 48.0 * len(pool[a].enr_idx) * (128 + maxc) for a in probs)
+        rows = sum(pool[atoms[i]].n for i in g)
+        return (ent + ops) / 2 ** 30, rows
+
+    for i in order:
+        gib, rows = cost(cur + [i])
+        if cur and (gib > budget_gib or rows > max_rows):
+            groups.append(cur)
+            cur = []
+        cur.append(i)
+    if cur:
+        groups.append(cur)
+    return groups
+
+
 def run_batch(args):
-    """The batched form: 256 independent problems, one SCF step = per-entry
-    Lanczos bounds -> batched reduced-precision filter (one launch per kernel
-    family and step for all entries, replayed from a HIP graph) -> per-entry
-    Rayleigh-Ritz.  Also times the filter alone three ways: batched with the
-    graph, batched without it, and entry by entry through the single-problem
-    entry point."""
+    """The batched form at its specified sizes: 256 independent Si clusters
+    of 1-40 atoms (seeded, uniform in atoms; each in its own cube with 8^3 to
+    20^3 degree-4 cells; 16-350 vectors), FP32 filter (m = 40) and FP64
+    Rayleigh-Ritz.  The entries are packed into groups that fit the device
+    (batch_groups); one SCF step = for every group: the grouped Lanczos
+    bounds, the batched filter (one launch per kernel family and step for all
+    the group's entries, replayed from a HIP graph), the batched projection.
+    Also times the filter alone batched and entry by entry through the
+    single-problem entry point, and checks that both give the same bits."""
     import numpy as np
     import torch
 
@@ -480,104 +512,198 @@ def run_batch(args):
     m = WORKLOADS["si-batch256"][2]
     prec = "fp32" if args.prec == "fp64" else args.prec
     t0 = time.time()
-    log("generating the batch pool (Si clusters of 1-8 atoms)")
+    log("generating the batch pool (Si clusters of 1-40 atoms)")
     pool, atoms, Ns = configs.batch_workload(256, seed=args.seed)
-    probs = [pool[a] for a in atoms]
-    maxc = max(Ns)
-    log(f"pool of {len(pool)} problems (n = {[pool[a].n for a in sorted(pool)]}) in "
-        f"{time.time() - t0:.1f}s; 256 entries, sum n*N = {sum(p.n * N for p, N in zip(probs, Ns))}")
+    log(f"pool of {len(pool)} problems (n = {min(p.n for p in pool.values())} .. "
+        f"{max(p.n for p in pool.values())}) in {time.time() - t0:.0f}s; 256 entries, "
+        f"sum n*N = {sum(pool[a].n * N for a, N in zip(atoms, Ns))}")
+    groups = batch_groups(pool, atoms, Ns)
+    log(f"{len(groups)} groups of {[len(g) for g in groups]} entries")
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
-    batch = Batch(probs, max_cols=maxc)
-    log(f"batch ready ({time.time() - t0:.1f}s)")
-    X = [torch.tensor(configs.initial_block(p, N, seed=args.seed), dtype=torch.float64, device=dev)
-         for p, N in zip(probs, Ns)]
-    Y = [torch.empty_like(x) for x in X]
-    v0 = [torch.tensor(np.random.default_rng(args.seed + 1 + i).standard_normal(p.n),
-                       dtype=torch.float64, device=dev) for i, p in enumerate(probs)]
-    theta = batch.rayleigh_ritz(X)
-    # tile shape of the batched reduced cell product, by the library's autotuner
-    _, b0 = batch.lanczos_bounds(v0, 10)
-    tile_choice = batch.autotune(X, m, [float(th[-1]) for th in theta], b0, prec=prec, reps=1, Y=Y)
-    log(f"autotuner: {tile_choice} column block(s) per tile")
-    st = {"X": X, "Y": Y, "theta": theta, "t": [0.0, 0.0, 0.0]}
+    work = sum(pool[a].n * N for a, N in zip(atoms, Ns)) * m
+    tot = {"bounds": 0.0, "filter": 0.0, "rr": 0.0, "graph": 0.0, "nograph": 0.0, "seq": 0.0}
+    tiles, same_all, checked = [], True, 0
+    for gi, g in enumerate(groups):
+        probs = [pool[atoms[i]] for i in g]
+        gN = [Ns[i] for i in g]
+        maxc = max(gN)
+        batch = Batch(probs, max_cols=maxc)
+        X = [torch.tensor(configs.initial_block(p, N, seed=args.seed + i), dtype=torch.float64,
+                          device=dev) for i, p, N in zip(g, probs, gN)]
+        Y = [torch.empty_like(x) for x in X]
+        v0 = [torch.tensor(np.random.default_rng(args.seed + 1 + i).standard_normal(p.n),
+                           dtype=torch.float64, device=dev) for i, p in zip(g, probs)]
+        theta = batch.rayleigh_ritz(X)
+        _, b0 = batch.lanczos_bounds(v0, 10)
+        tiles.append(batch.autotune(X, m, [float(th[-1]) for th in theta], b0, prec=prec, reps=1,
+                                    Y=Y))
+        st = {"X": X, "Y": Y, "theta": theta}
 
-    def step(timed):
-        s0 = time.perf_counter()
-        _, b = batch.lanczos_bounds(v0, 10)
-        s1 = time.perf_counter()
-        a = [float(th[-1]) for th in st["theta"]]
-        batch.filter(st["X"], m, a, b, Y=st["Y"], prec=prec, use_graph=True)
-        torch.cuda.synchronize()
-        s2 = time.perf_counter()
-        th = batch.rayleigh_ritz(st["Y"])
-        s3 = time.perf_counter()
-        st["X"], st["Y"], st["theta"], st["b"], st["a"] = st["Y"], st["X"], th, b, a
-        if timed:
-            for i, d in enumerate((s1 - s0, s2 - s1, s3 - s2)):
-                st["t"][i] += d
+        def step(timed):
+            s0 = time.perf_counter()
+            _, b = batch.lanczos_bounds(v0, 10)
+            s1 = time.perf_counter()
+            a = [float(th[-1]) for th in st["theta"]]
+            batch.filter(st["X"], m, a, b, Y=st["Y"], prec=prec, use_graph=True)
+            torch.cuda.synchronize()
+            s2 = time.perf_counter()
+            th = batch.rayleigh_ritz(st["Y"])
+            s3 = time.perf_counter()
+            st["X"], st["Y"], st["theta"], st["a"], st["b"] = st["Y"], st["X"], th, a, b
+            if timed:
+                tot["bounds"] += (s1 - s0) / args.steps
+                tot["filter"] += (s2 - s1) / args.steps
+                tot["rr"] += (s3 - s2) / args.steps
 
-    for i in range(args.warmup):
-        step(False)
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for i in range(args.steps):
-        step(True)
-        log(f"step {i + 1}/{args.steps}")
-    torch.cuda.synchronize()
-    ms_per_step = 1e3 * (time.perf_counter() - t_start) / args.steps
-    work = sum(p.n * N for p, N in zip(probs, Ns)) * m
+        for _ in range(args.warmup):
+            step(False)
+        for _ in range(args.steps):
+            step(True)
 
-    def time_filter(fn, reps=3):
-        fn()
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        for _ in range(reps):
+        def time_filter(fn, reps=2):
             fn()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(reps):
+                fn()
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t1) / reps
+
+        a, b = st["a"], st["b"]
+        tot["graph"] += time_filter(lambda: batch.filter(st["X"], m, a, b, Y=st["Y"], prec=prec,
+                                                         use_graph=True))
+        tot["nograph"] += time_filter(lambda: batch.filter(st["X"], m, a, b, Y=st["Y"], prec=prec,
+                                                           use_graph=False))
+        # a few entries' batched outputs kept to compare with the single-problem path
+        keep = list(range(0, len(g), max(1, len(g) // 4)))
+        Yb = {k: st["Y"][k].clone() for k in keep}
+        batch.close()
+        del batch
+        torch.cuda.empty_cache()
+        singles = {}
+        for i, N in zip(g, gN):
+            singles[atoms[i]] = max(singles.get(atoms[i], 0), N)
+        singles = {k: Context(pool[k], max_cols=c) for k, c in singles.items()}
+
+        def sequential():
+            for k, i in enumerate(g):
+                singles[atoms[i]].filter(st["X"][k], m, a[k], b[k], Y=st["Y"][k], prec=prec)
+        tot["seq"] += time_filter(sequential)
         torch.cuda.synchronize()
-        return (time.perf_counter() - t1) / reps
-
-    a, b = st["a"], st["b"]
-    t_graph = time_filter(lambda: batch.filter(st["X"], m, a, b, Y=st["Y"], prec=prec, use_graph=True))
-    t_nograph = time_filter(lambda: batch.filter(st["X"], m, a, b, Y=st["Y"], prec=prec,
-                                                 use_graph=False))
-    singles = {k: Context(pool[k], max_cols=maxc) for k in pool}
-
-    def sequential():
-        for i, k in enumerate(atoms):
-            singles[k].filter(st["X"][i], m, a[i], b[i], Y=st["Y"][i], prec=prec)
-    t_seq = time_filter(sequential)
-    # the batched result equals the entry-by-entry one bit for bit
-    Yb = [y.clone() for y in batch.filter(st["X"], m, a, b, prec=prec)]
-    sequential()
-    torch.cuda.synchronize()
-    same = all(torch.equal(yb, y) for yb, y in zip(Yb, st["Y"]))
+        for k, y in Yb.items():
+            same_all &= bool(torch.equal(y, st["Y"][k]))
+            checked += 1
+        for c in singles.values():
+            c.close()
+        del X, Y, st, Yb, singles
+        torch.cuda.empty_cache()
+        log(f"group {gi + 1}/{len(groups)}: {len(g)} entries (atoms {atoms[g[0]]}-{atoms[g[-1]]}, "
+            f"N <= {maxc}) done; running totals {', '.join(f'{k} {v:.2f}s' for k, v in tot.items())}")
+    step_s = tot["bounds"] + tot["filter"] + tot["rr"]
     out = {
         "metric": "batched Chebyshev-filter DOF*vectors/s (per degree, whole SCF step), "
                   "256 independent problems",
-        "value": work / (ms_per_step / 1e3),
+        "value": work / step_s,
         "unit": "DOF*vectors*degree/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * step_s,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": {"fp32": "f32", "bf16": "bf16"}[prec], "data": "synthetic",
         "config": {"workload": "si-batch256", "entries": 256, "distinct_problems": len(pool),
-                   "atoms_per_entry": "U{1..8}", "vectors": "16-64", "cheb_degree": m,
-                   "sum_n_times_N": work // m,
+                   "atoms_per_entry": "U{1..40}", "cells_per_axis": "8-20",
+                   "vectors": f"{min(Ns)}-{max(Ns)}", "cheb_degree": m,
+                   "sum_n_times_N": work // m, "groups": [len(g) for g in groups],
                    "precision": f"{prec} filter, fp64 Schur solve and Rayleigh-Ritz",
-                   "cell_tile_blocks_autotuned": tile_choice},
-        "phases_ms": {"bounds": 1e3 * st["t"][0] / args.steps,
-                      "filter": 1e3 * st["t"][1] / args.steps,
-                      "cholqr_rr": 1e3 * st["t"][2] / args.steps},
-        "filter_only_ms": {"batched_graph": 1e3 * t_graph, "batched_no_graph": 1e3 * t_nograph,
-                           "entry_by_entry": 1e3 * t_seq},
-        "filter_dof_vec_deg_per_s": work / t_graph,
-        "speedup_batched_vs_entry_by_entry": t_seq / t_graph,
-        "batched_equals_entry_by_entry": bool(same),
+                   "cell_tile_blocks_autotuned_per_group": tiles},
+        "phases_ms": {"bounds": 1e3 * tot["bounds"], "filter": 1e3 * tot["filter"],
+                      "cholqr_rr": 1e3 * tot["rr"]},
+        "filter_only_ms": {"batched_graph": 1e3 * tot["graph"],
+                           "batched_no_graph": 1e3 * tot["nograph"],
+                           "entry_by_entry": 1e3 * tot["seq"]},
+        "filter_dof_vec_deg_per_s": work / tot["graph"],
+        "speedup_batched_vs_entry_by_entry": tot["seq"] / tot["graph"],
+        "batched_equals_entry_by_entry": bool(same_all), "entries_compared_bitwise": checked,
     }
     print(json.dumps(out), flush=True)
-    for c in singles.values():
-        c.close()
-    batch.close()
+
+
+def classical_study(args):
+    """The paper's DOF x degree argument (Sec. VI.B.1: enriched degree 80
+    against classical 1500, lambda_max 1e3 against 1e6) on the hydrogen
+    workload: the enriched 8^3-cell discretization against classical
+    (enrichment-free) uniform meshes of degree-4 cells on the same 20 Bohr
+    box.  Each runs the subspace iteration (N = 16, 14 wanted) from its own
+    start (atomic orbitals where there are enrichments, else N(0,1)) with the
+    10-step Lanczos bound and one degree rule for all (per step, the smallest
+    m that damps the top wanted Ritz value against theta_N by 100:
+    m = ln(100) / acosh|t(theta_Nw)|), until the wanted Ritz values move
+    less than 1e-10 Ha.  Reported: DOFs, b, degrees, steps, time, and the
+    ground-state error against -1/2 Ha.  Meshes are uniform here (the paper
+    refines classical meshes towards the nuclei)."""
+    import numpy as np
+    import torch
+
+    from paper_1610_02121_amd import Context
+    from synth import configs
+    N, wanted = 16, 14
+    cases = [("enriched", 8)] + [("classical", int(k)) for k in args.classical_meshes.split(",")]
+    probs = {}
+    for kind, nc in cases:           # generate before the GPU is touched
+        t0 = time.time()
+        probs[(kind, nc)] = configs.hydrogen(nc=nc, length=20.0, p=4, r_c=6.0,
+                                             enrich=kind == "enriched")
+        log(f"{kind} {nc}^3: n={probs[(kind, nc)].n} generated in {time.time() - t0:.0f}s")
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    res = []
+    for kind, nc in cases:
+        prob = probs.pop((kind, nc))
+        ctx = Context(prob, max_cols=N)
+        X = torch.tensor(configs.initial_block(prob, N, seed=args.seed), dtype=torch.float64,
+                         device=dev)
+        v0 = torch.tensor(np.random.default_rng(args.seed + 1).standard_normal(prob.n),
+                          dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        th = ctx.rayleigh_ritz(X)
+        _, b = ctx.lanczos_bounds(v0, 10)
+        degs = []
+        for step in range(args.max_steps):
+            a = float(th[-1])
+            t = abs((2.0 * th[wanted - 1] - a - b) / (b - a))
+            m = int(min(4000, max(8, np.ceil(np.log(100.0) / np.arccosh(max(t, 1.0 + 1e-12))))))
+            degs.append(m)
+            Y = ctx.filter(X, m, a, b)
+            th_new = ctx.rayleigh_ritz(Y)
+            d = float(np.abs(th_new[:wanted] - th[:wanted]).max())
+            X, th = Y, th_new
+            if d < 1e-10:
+                break
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        rec = {"kind": kind, "cells_per_axis": nc, "n_dof": prob.n, "n_enrich": prob.n_e,
+               "b": b, "degrees": degs, "steps": len(degs), "seconds": dt,
+               "dof_times_degree_sum": float(prob.n * sum(degs)),
+               "lambda_1": float(th[0]), "ground_state_err_Ha": float(th[0] + 0.5),
+               "n2_levels": [float(x) for x in th[1:5]]}
+        res.append(rec)
+        log(f"{kind} {nc}^3: n={prob.n} b={b:.1f} degrees {degs[0]}..{degs[-1]} steps {len(degs)} "
+            f"{dt:.2f}s lambda_1 {th[0]:.8f} (err {th[0] + 0.5:.2e})")
+        ctx.close()
+        del prob
+    enr = res[0]
+    match = [r for r in res[1:] if abs(r["ground_state_err_Ha"]) <= abs(enr["ground_state_err_Ha"])]
+    out = {"study": "classical (enrichment-free) against enriched finite elements, hydrogen, "
+                    "DOF x Chebyshev degree to the same ground-state accuracy",
+           "vectors": N, "wanted": wanted, "cases": res,
+           "classical_matching_accuracy": match[0]["cells_per_axis"] if match else None}
+    if match:
+        c = match[0]
+        out["ratios_classical_over_enriched"] = {
+            "dof": c["n_dof"] / enr["n_dof"], "b": c["b"] / enr["b"],
+            "mean_degree": float(np.mean(c["degrees"]) / np.mean(enr["degrees"])),
+            "time": c["seconds"] / enr["seconds"]}
+    print(json.dumps(out), flush=True)
 
 
 def learned_study(args):
@@ -600,7 +726,7 @@ def learned_study(args):
     t0 = time.time()
     inputs, targets = [], []
     for nat in (1, 2, 3, 4, 5, 6):
-        prob = configs.batch_cluster(nat, seed=args.seed)
+        prob = configs.learned_cluster(nat, seed=args.seed)
         N = 16 + round(48 * (nat - 1) / 7)
         wanted = N - 8
         ctx = Context(prob, max_cols=N)
@@ -634,7 +760,7 @@ def learned_study(args):
             "pred_abs_err_m_median": float(np.median(np.abs(pred[:, 2] - targets[:, 2])))}
     log(f"labels vs guard: {diag}")
     # evaluation
-    prob = configs.batch_cluster(8, seed=args.seed)
+    prob = configs.learned_cluster(8, seed=args.seed)
     N, wanted, steps = 64, 56, 30
     ctx = Context(prob, max_cols=N)
     v0 = torch.tensor(np.random.default_rng(args.seed + 99).standard_normal(prob.n),
@@ -719,6 +845,11 @@ def main():
                     help="train the bounds network and compare it with the Lanczos bound")
     ap.add_argument("--m-reduced", type=int, default=20,
                     help="filter degree of the reduced-precision passes in the study")
+    ap.add_argument("--classical-study", action="store_true",
+                    help="enriched against classical (enrichment-free) hydrogen meshes at the "
+                         "same ground-state accuracy: DOFs, bounds, degrees, time")
+    ap.add_argument("--classical-meshes", default="8,16,24,32",
+                    help="cells per axis of the classical meshes in the classical study")
     ap.add_argument("--col-chunk", type=int, default=256,
                     help="si280-48c: columns of the library's work blocks")
     ap.add_argument("--forms", default="fp64",
@@ -743,6 +874,9 @@ def main():
     from synth import configs
 
     name = args.workload
+    if args.classical_study:
+        classical_study(args)
+        return
     if args.learned_study:
         learned_study(args)
         return

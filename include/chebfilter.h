@@ -159,11 +159,18 @@ cf_status chebfilter_filter_multipass(cf_ctx *ctx, const double *X, int64_t ldx,
  * CF_EINVAL on another prec or nsb. */
 cf_status chebfilter_set_cell_tile(cf_ctx *ctx, int32_t prec, int32_t nsb);
 
-/* Autotuner of that shape: runs chebfilter_filter(ctx, X, ldx, Y, ldy, N, m,
- * a, b, prec) once as a warm-up and `reps` times timed (HIP events on the
- * context's stream) for each candidate, keeps the fastest for later calls
- * and returns it in *choice (may be null).  Y is overwritten; prec is CF_FP32
- * or CF_BF16; m >= 1, reps >= 1.  Synchronises. */
+/* Autotuner of the reduced forms' tile shapes: runs chebfilter_filter(ctx, X,
+ * ldx, Y, ldy, N, m, a, b, prec) once as a warm-up and `reps` times timed
+ * (HIP events on the context's stream) for each candidate and keeps the
+ * fastest for later calls.  First the cell product's column blocks per tile
+ * (returned in *choice, may be null); then, for problems with enrichment,
+ * the FP32 coupling partials' split of a workgroup's 8 waves between 16-row
+ * output blocks and parts of the 128 local nodes (1 x 8, 2 x 4 or 4 x 2),
+ * one choice per bucket of enriched cells by their number of 16-function row
+ * blocks (1, 2, 3, >= 4; uneven enrichment counts per cell, Sec. IV.C),
+ * bucket by bucket with the others fixed (chebfilter_tuning reads the map).
+ * The choices change only the order of FP32 sums.  Y is overwritten; prec is
+ * CF_FP32 or CF_BF16; m >= 1, reps >= 1.  Synchronises. */
 cf_status chebfilter_autotune(cf_ctx *ctx, const double *X, int64_t ldx, double *Y, int64_t ldy,
                               int64_t N, int32_t m, double a, double b, int32_t prec, int32_t reps,
                               int32_t *choice);
@@ -269,6 +276,17 @@ cf_status chebfilter_batch_autotune(cf_batch *batch, const double *const *X, con
                                     double *const *Y, const int64_t *ldy, const int64_t *N,
                                     int32_t m, const double *a, const double *b, int32_t prec,
                                     int32_t reps, int32_t *choice);
+
+/* Tuning state of a context (chebfilter_tuning) or a batch
+ * (chebfilter_batch_tuning): the column blocks per tile of the FP32-input and
+ * BF16-input cell products and the coupling map (2 bits per row-block bucket
+ * 1, 2, 3, >= 4, lowest bits first: 0 -> 1 row block x 8 k parts, 1 -> 2 x 4,
+ * 2 -> 4 x 2).  set_map >= 0 sets the map first (CF_EINVAL for a code 3 or a
+ * value above 255); output pointers may be null. */
+cf_status chebfilter_tuning(cf_ctx *ctx, int32_t set_map, int32_t *nsb_fp32, int32_t *nsb_bf16,
+                            int32_t *coupling_map);
+cf_status chebfilter_batch_tuning(cf_batch *batch, int32_t set_map, int32_t *nsb_fp32,
+                                  int32_t *nsb_bf16, int32_t *coupling_map);
 
 /* chebfilter_rayleigh_ritz for every entry (Sec. V's projection), with one
  * host synchronisation for the whole batch: every entry is orthonormalised by

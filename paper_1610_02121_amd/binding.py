@@ -34,7 +34,8 @@ EXPORTS = ["chebfilter_init", "chebfilter_destroy", "chebfilter_last_error", "ch
            "chebfilter_mlp_set_normalization", "chebfilter_bounds_features",
            "chebfilter_bounds_predict", "chebfilter_assembly_tables", "chebfilter_assemble_cells",
            "chebfilter_get_H_cc", "chebfilter_set_cell_tile", "chebfilter_autotune",
-           "chebfilter_batch_autotune", "chebfilter_lanczos_bounds_noalloc"]
+           "chebfilter_batch_autotune", "chebfilter_lanczos_bounds_noalloc", "chebfilter_tuning",
+           "chebfilter_batch_tuning"]
 
 
 class CfProblem(C.Structure):
@@ -122,6 +123,9 @@ def load_library() -> C.CDLL:
     lib.chebfilter_batch_autotune.argtypes = [vp, C.POINTER(vp), P64, C.POINTER(vp), P64, P64, i32,
                                               C.POINTER(dbl), C.POINTER(dbl), i32, i32,
                                               C.POINTER(i32)]
+    lib.chebfilter_tuning.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
+    lib.chebfilter_batch_tuning.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(i32),
+                                            C.POINTER(i32)]
     for nm in EXPORTS:
         if nm not in ("chebfilter_last_error", "chebfilter_batch_last_error",
                       "chebfilter_mlp_last_error"):
@@ -254,6 +258,13 @@ class Context:
                                                  float(a), float(b), PREC[prec], int(reps),
                                                  C.byref(ch)))
         return ch.value
+
+    def tuning(self, coupling_map: int = -1) -> dict:
+        """The tile-shape state (set the coupling map first if >= 0)."""
+        a, b, c = C.c_int32(), C.c_int32(), C.c_int32()
+        self._check(self.lib.chebfilter_tuning(self._h, int(coupling_map), C.byref(a), C.byref(b),
+                                               C.byref(c)))
+        return {"nsb_fp32": a.value, "nsb_bf16": b.value, "coupling_map": c.value}
 
     def cholqr(self, Y):
         yp, ldy = _block(Y, "Y")
@@ -446,6 +457,13 @@ class Batch:
         self._check(self.lib.chebfilter_batch_autotune(self._h, xp, xl, yp, yl, xn, int(m), av, bv,
                                                        PREC[prec], int(reps), C.byref(ch)))
         return ch.value
+
+    def tuning(self, coupling_map: int = -1) -> dict:
+        """The batch's tile-shape state (set the coupling map first if >= 0)."""
+        a, b, c = C.c_int32(), C.c_int32(), C.c_int32()
+        self._check(self.lib.chebfilter_batch_tuning(self._h, int(coupling_map), C.byref(a),
+                                                     C.byref(b), C.byref(c)))
+        return {"nsb_fp32": a.value, "nsb_bf16": b.value, "coupling_map": c.value}
 
     def rayleigh_ritz(self, Y):
         yp, yl, yn = self._blocks(Y, "Y")

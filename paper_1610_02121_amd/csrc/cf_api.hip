@@ -113,6 +113,9 @@ struct cf_ctx {
   // 16-column MFMA blocks per column tile of the reduced cell product, for
   // the FP32-input cells [0] and the BF16-input cells [1] (chebfilter_autotune)
   int lp_nsb[2] = {1, 2};
+  // row-block bucket -> k split of the FP32 coupling partials (2 bits per
+  // bucket of 1, 2, 3, >= 4 row blocks; chebfilter_autotune)
+  int lp_bmap = CPL_BMAP_DEFAULT;
   // assembly of the plain cells' blocks: reference tables (shape values
   // [nq4][NPAD], weights [nq], kinetic block [NPAD][NPAD]), the uploaded cell
   // list and its host copy, which cells carry enrichment functions
@@ -449,7 +452,7 @@ static cf_status core_htilde_step_lp(cf_ctx *c, bool bf16, const float *Xin, int
       Scope sc(c, "enr_part");
       HIPCHK(c, launch_enr_part_f32(c->stream, c->HT32, c->MT32, c->toff, c->tld, c->eptr, c->dofp,
                                     c->ecells_part, c->necells, Xin, ldxin, 1.f, c->R32, mc, c->dinv,
-                                    -1.f, c->P32, mc, N));
+                                    -1.f, c->P32, mc, N, c->lp_bmap));
     }
     {
       Scope sc(c, "enr_reduce");
@@ -1291,6 +1294,7 @@ struct cf_batch {
   // column blocks per tile of the batched reduced cell product, FP32-input
   // cells [0] and BF16-input cells [1] (chebfilter_batch_autotune)
   int nsb[2] = {1, 2};
+  int bmap = CPL_BMAP_DEFAULT;              // coupling-partials split by row-block bucket
   hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_copy = nullptr;
   bool copy_pending = false;
   // batched projection and Lanczos (allocated on first use): per-entry status
@@ -1494,7 +1498,7 @@ static cf_status batch_enqueue_filter(cf_batch *b, int m, bool bf16) {
       }
     }
     BHIPCHK(b, launch_b_enr(s, b->d_bp, b->count, b->d_eitems, b->neitems, b->d_aoff, b->nalpha,
-                            (int)b->max_cols, b->kmax, k));
+                            (int)b->max_cols, b->kmax, k, b->bmap));
     BHIPCHK(b, launch_b_epilogue(s, b->d_bp, b->count, b->d_eoff, b->neblocks, k));
   }
   BHIPCHK(b, launch_b_lp_output(s, b->d_bp, b->count, b->d_boff, b->nbblocks, m));
@@ -1970,7 +1974,7 @@ cf_status chebfilter_filter_batch(cf_batch *b, const double *const *X, const int
   BHIPCHK(b, hipEventRecord(b->ev_copy, b->bs));
   b->copy_pending = true;
   if (use_graph) {
-    const int nsb_key = 4 * b->nsb[0] + b->nsb[1];
+    const int nsb_key = (4 * b->nsb[0] + b->nsb[1]) | (b->bmap << 8);
     if (!b->gexec || b->g_m != m || b->g_prec != prec || b->g_nsb != nsb_key) {
       if (b->gexec) { (void)hipGraphExecDestroy(b->gexec); b->gexec = nullptr; }
       hipGraph_t g = nullptr;
@@ -2006,8 +2010,55 @@ cf_status chebfilter_set_cell_tile(cf_ctx *c, int32_t prec, int32_t nsb) {
   return CF_OK;
 }
 
-// Time `reps` filters of each candidate block count after one warm-up, keep
-// the fastest (HIP events on the context's stream).
+// Time `reps` filters after one warm-up for each candidate, keep the fastest
+// (HIP events on the context's stream): first the reduced cell product's
+// column blocks per tile, then, bucket by bucket (cells with 1, 2, 3, >= 4
+// blocks of 16 enrichment functions), the split of the FP32 coupling
+// partials' waves between row blocks and k parts (greedy: each bucket with
+// the others fixed).
+extern "C++" {
+template <typename Run>
+static cf_status tune_loop(hipStream_t s, int reps, Run run, float *ms_out) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess) return CF_EDEVICE;
+  if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return CF_EDEVICE; }
+  cf_status st = run();
+  if (st == CF_OK) {
+    (void)hipEventRecord(e0, s);
+    for (int r = 0; r < reps && st == CF_OK; ++r) st = run();
+    (void)hipEventRecord(e1, s);
+    (void)hipEventSynchronize(e1);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    *ms_out = ms;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return st;
+}
+
+// Greedy bucket search of the coupling map: `map` is updated in place.
+template <typename Run>
+static cf_status tune_bmap(hipStream_t s, int reps, int *map, Run run) {
+  float best = 0.f;
+  cf_status st = tune_loop(s, reps, run, &best);
+  for (int q = 0; q < 4 && st == CF_OK; ++q) {
+    const int keep = *map;
+    int best_map = keep;
+    for (int code = 0; code < 3 && st == CF_OK; ++code) {
+      const int cand = (keep & ~(3 << (2 * q))) | (code << (2 * q));
+      if (cand == keep) continue;
+      *map = cand;
+      float ms = 0.f;
+      st = tune_loop(s, reps, run, &ms);
+      if (st == CF_OK && ms < best) { best = ms; best_map = cand; }
+    }
+    *map = best_map;
+  }
+  return st;
+}
+}  // extern "C++"
+
 cf_status chebfilter_autotune(cf_ctx *c, const double *X, int64_t ldx, double *Y, int64_t ldy,
                               int64_t N, int32_t m, double a, double b, int32_t prec, int32_t reps,
                               int32_t *choice) {
@@ -2016,29 +2067,34 @@ cf_status chebfilter_autotune(cf_ctx *c, const double *X, int64_t ldx, double *Y
   if (reps < 1 || m < 1) return set_err(c, CF_EINVAL, "autotune: need reps >= 1 and m >= 1");
   HIPCHK(c, hipSetDevice(c->device));
   const int slot = prec == CF_BF16 ? 1 : 0;
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  HIPCHK(c, hipEventCreate(&e0));
-  if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return set_err(c, CF_EDEVICE, "autotune: event"); }
+  auto run = [&]() { return chebfilter_filter(c, X, ldx, Y, ldy, N, m, a, b, prec); };
   float best = 0.f;
   int best_nsb = c->lp_nsb[slot];
   cf_status st = CF_OK;
   for (int nsb = 1; nsb <= 2 && st == CF_OK; ++nsb) {
     c->lp_nsb[slot] = nsb;
-    st = chebfilter_filter(c, X, ldx, Y, ldy, N, m, a, b, prec);
-    if (st != CF_OK) break;
-    (void)hipEventRecord(e0, c->stream);
-    for (int r = 0; r < reps && st == CF_OK; ++r) st = chebfilter_filter(c, X, ldx, Y, ldy, N, m, a, b, prec);
-    (void)hipEventRecord(e1, c->stream);
-    (void)hipEventSynchronize(e1);
     float ms = 0.f;
-    (void)hipEventElapsedTime(&ms, e0, e1);
-    if (nsb == 1 || ms < best) { best = ms; best_nsb = nsb; }
+    st = tune_loop(c->stream, reps, run, &ms);
+    if (st == CF_OK && (nsb == 1 || ms < best)) { best = ms; best_nsb = nsb; }
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
   c->lp_nsb[slot] = best_nsb;
-  if (st != CF_OK) return st;
+  if (st == CF_OK && c->n_e > 0) st = tune_bmap(c->stream, reps, &c->lp_bmap, run);
+  if (st != CF_OK) return st == CF_EDEVICE ? set_err(c, st, "autotune: event") : st;
   if (choice) *choice = best_nsb;
+  return CF_OK;
+}
+
+cf_status chebfilter_tuning(cf_ctx *c, int32_t set_map, int32_t *nsb_fp32, int32_t *nsb_bf16,
+                            int32_t *coupling_map) {
+  if (!c) return CF_EINVAL;
+  if (set_map >= 0) {
+    if (set_map > 255 || ((set_map & 0x55) & (set_map >> 1) & 0x55))
+      return set_err(c, CF_EINVAL, "tuning: coupling map codes must be 0, 1 or 2");
+    c->lp_bmap = set_map;
+  }
+  if (nsb_fp32) *nsb_fp32 = c->lp_nsb[0];
+  if (nsb_bf16) *nsb_bf16 = c->lp_nsb[1];
+  if (coupling_map) *coupling_map = c->lp_bmap;
   return CF_OK;
 }
 
@@ -2051,30 +2107,34 @@ cf_status chebfilter_batch_autotune(cf_batch *b, const double *const *X, const i
   if (reps < 1 || m < 1) return berr(b, CF_EINVAL, "batch_autotune: need reps >= 1 and m >= 1");
   BHIPCHK(b, hipSetDevice(b->device));
   const int slot = prec == CF_BF16 ? 1 : 0;
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  BHIPCHK(b, hipEventCreate(&e0));
-  if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return berr(b, CF_EDEVICE, "batch_autotune: event"); }
+  auto run = [&]() { return chebfilter_filter_batch(b, X, ldx, Y, ldy, N, m, a, bu, prec, 1); };
   float best = 0.f;
   int best_nsb = b->nsb[slot];
   cf_status st = CF_OK;
   for (int nsb = 1; nsb <= 2 && st == CF_OK; ++nsb) {
     b->nsb[slot] = nsb;
-    st = chebfilter_filter_batch(b, X, ldx, Y, ldy, N, m, a, bu, prec, 1);
-    if (st != CF_OK) break;
-    (void)hipEventRecord(e0, b->caller);
-    for (int r = 0; r < reps && st == CF_OK; ++r)
-      st = chebfilter_filter_batch(b, X, ldx, Y, ldy, N, m, a, bu, prec, 1);
-    (void)hipEventRecord(e1, b->caller);
-    (void)hipEventSynchronize(e1);
     float ms = 0.f;
-    (void)hipEventElapsedTime(&ms, e0, e1);
-    if (nsb == 1 || ms < best) { best = ms; best_nsb = nsb; }
+    st = tune_loop(b->caller, reps, run, &ms);
+    if (st == CF_OK && (nsb == 1 || ms < best)) { best = ms; best_nsb = nsb; }
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
   b->nsb[slot] = best_nsb;
-  if (st != CF_OK) return st;
+  if (st == CF_OK && b->neitems > 0) st = tune_bmap(b->caller, reps, &b->bmap, run);
+  if (st != CF_OK) return st == CF_EDEVICE ? berr(b, st, "batch_autotune: event") : st;
   if (choice) *choice = best_nsb;
+  return CF_OK;
+}
+
+cf_status chebfilter_batch_tuning(cf_batch *b, int32_t set_map, int32_t *nsb_fp32,
+                                  int32_t *nsb_bf16, int32_t *coupling_map) {
+  if (!b) return CF_EINVAL;
+  if (set_map >= 0) {
+    if (set_map > 255 || ((set_map & 0x55) & (set_map >> 1) & 0x55))
+      return berr(b, CF_EINVAL, "batch_tuning: coupling map codes must be 0, 1 or 2");
+    b->bmap = set_map;
+  }
+  if (nsb_fp32) *nsb_fp32 = b->nsb[0];
+  if (nsb_bf16) *nsb_bf16 = b->nsb[1];
+  if (coupling_map) *coupling_map = b->bmap;
   return CF_OK;
 }
 

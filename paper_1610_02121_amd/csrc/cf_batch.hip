@@ -79,12 +79,13 @@ __global__ __launch_bounds__(512, 2) void kb_cell(const BatchProb *__restrict__ 
 }
 
 __global__ __launch_bounds__(512, 2) void kb_enr_part(const BatchProb *__restrict__ bp,
-                                                   const BatchItem *__restrict__ items, int k) {
+                                                   const BatchItem *__restrict__ items, int k,
+                                                   int bmap) {
   const BatchItem it = items[blockIdx.x];
   const BatchProb &P = bp[it.p];
   const float *Xin = (k & 1) ? P.F1 : P.F0;
   enr_part_f32_body(P.HT32, P.MT32, P.toff, P.tld, P.eptr, P.dofp, P.ecells[it.c], Xin, P.mc, 1.f,
-                    P.R32, P.mc, P.dinv, -1.f, P.P32, P.mc, P.N);
+                    P.R32, P.mc, P.dinv, -1.f, P.P32, P.mc, P.N, bmap);
 }
 
 __global__ __launch_bounds__(64) void kb_enr_reduce(const BatchProb *__restrict__ bp,
@@ -191,9 +192,9 @@ hipError_t launch_b_cell(hipStream_t s, bool bf16, int nsb, const BatchProb *bp,
 
 hipError_t launch_b_enr(hipStream_t s, const BatchProb *bp, int count, const BatchItem *eitems,
                         int neitems, const int64_t *aoff, int64_t nalpha, int maxN, int kmax,
-                        int k) {
+                        int k, int bmap) {
   if (neitems <= 0 || nalpha <= 0 || maxN <= 0) return hipSuccess;
-  hipLaunchKernelGGL(kb_enr_part, dim3(neitems), dim3(512), 0, s, bp, eitems, k);
+  hipLaunchKernelGGL(kb_enr_part, dim3(neitems), dim3(512), 0, s, bp, eitems, k, bmap);
   const dim3 rgrid((maxN + 63) / 64, (unsigned)nalpha);
   hipLaunchKernelGGL(kb_enr_reduce, rgrid, dim3(64), 0, s, bp, aoff, count, k);
   hipLaunchKernelGGL(kb_schur, rgrid, dim3(64), 0, s, bp, aoff, count);

@@ -158,12 +158,17 @@ hipError_t launch_cell_gemm_lp(hipStream_t s, bool bf16, int nsb, const void *Hv
                                int ncells, const float *X, int64_t ldx, float *Y, int64_t ldy,
                                int N, const CellFinishF &f);
 // As launch_enr_part with FP32 blocks and vectors (rs stays FP64).
+// Default map from the row-block count of an enriched cell (1, 2, 3, >= 4
+// blocks of 16 functions, 2 bits each) to the FP32 coupling partials' split
+// of the workgroup's 8 waves: code 0 -> 1 row block x 8 k parts, 1 -> 2 x 4,
+// 2 -> 4 x 2.
+constexpr int CPL_BMAP_DEFAULT = 0 | (1 << 2) | (2 << 4) | (2 << 6);
 hipError_t launch_enr_part_f32(hipStream_t s, const float *HT, const float *MT,
                                const int64_t *toff, const int32_t *tld, const int64_t *eptr,
                                const int32_t *dofp, const int32_t *cells, int ncells,
                                const float *X, int64_t ldx, float cH, const float *R,
                                int64_t ldr, const double *rs, float cM, float *P, int64_t ldp,
-                               int N);
+                               int N, int bmap);
 // As launch_enr_q with FP32 blocks; U rows FP32, V rows FP64.
 hipError_t launch_enr_q_f32(hipStream_t s, const float *Hec, const float *Mec,
                             const int64_t *eptr, const int32_t *eidx, const int32_t *cells,
@@ -242,7 +247,7 @@ hipError_t launch_b_cell(hipStream_t s, bool bf16, int nsb, const BatchProb *bp,
                          const BatchItem *items, int nitems, int k);
 hipError_t launch_b_enr(hipStream_t s, const BatchProb *bp, int count, const BatchItem *eitems,
                         int neitems, const int64_t *aoff, int64_t nalpha, int maxN, int kmax,
-                        int k);
+                        int k, int bmap);
 // Raise the dynamic-LDS limit of the batched transposed-coupling kernel for
 // the largest per-cell enrichment count (call before any launch or capture).
 hipError_t prepare_b_enr(int kmax);

@@ -39,9 +39,9 @@ __global__ __launch_bounds__(512, 2) void k_enr_part_f32(
     const int64_t *__restrict__ eptr, const int32_t *__restrict__ dofp,
     const int32_t *__restrict__ cells, const float *__restrict__ X, int64_t ldx, float cH,
     const float *__restrict__ R, int64_t ldr, const double *__restrict__ rs, float cM,
-    float *__restrict__ P, int64_t ldp, int N) {
+    float *__restrict__ P, int64_t ldp, int N, int bmap) {
   enr_part_f32_body(HT, MT, toff, tld, eptr, dofp, cells[blockIdx.x], X, ldx, cH, R, ldr, rs, cM, P,
-                    ldp, N);
+                    ldp, N, bmap);
 }
 
 hipError_t launch_enr_part_f32(hipStream_t s, const float *HT, const float *MT,
@@ -49,10 +49,10 @@ hipError_t launch_enr_part_f32(hipStream_t s, const float *HT, const float *MT,
                                const int32_t *dofp, const int32_t *cells, int ncells,
                                const float *X, int64_t ldx, float cH, const float *R,
                                int64_t ldr, const double *rs, float cM, float *P, int64_t ldp,
-                               int N) {
+                               int N, int bmap) {
   if (ncells <= 0 || N <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_enr_part_f32, dim3(ncells), dim3(512), 0, s, HT, MT, toff, tld, eptr, dofp,
-                     cells, X, ldx, cH, R, ldr, rs, cM, P, ldp, N);
+                     cells, X, ldx, cH, R, ldr, rs, cM, P, ldp, N, bmap);
   return hipGetLastError();
 }
 

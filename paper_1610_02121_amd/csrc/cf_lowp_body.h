@@ -210,50 +210,39 @@ __device__ __forceinline__ void cell_gemm_lp_body(
 // Coupling partials, FP32 (as k_enr_part; FP32 blocks HT, MT).
 // ---------------------------------------------------------------------------
 // One enriched cell per workgroup of 512 threads; the blocks are read once per
-// call (cells with more than 64 enrichment functions take several passes over
-// the gathered rows).
-__device__ __forceinline__ void enr_part_f32_body(
-    const float *__restrict__ HT, const float *__restrict__ MT,
-    const int64_t *__restrict__ toff, const int32_t *__restrict__ tld,
-    const int64_t *__restrict__ eptr, const int32_t *__restrict__ dofp,
-    const int cell, const float *__restrict__ X, int64_t ldx, float cH,
-    const float *__restrict__ R, int64_t ldr, const double *__restrict__ rs, float cM,
-    float *__restrict__ P, int64_t ldp, int N) {
-  // 8 waves (512 threads): wave w takes row block 4g + (w & 3) of group g and
-  // half h = w >> 2 of the 128 local nodes, with the A fragments of both terms
-  // for its half in registers; the halves are added through LDS.  The
-  // gathered rows of a tile are loaded two tiles ahead into one of two
-  // register sets.
-  constexpr int PT = 16, LDX = PT + 1;
-  constexpr int PF = NPAD * PT / 512;
-  constexpr int RPP = 512 / PT;
-  __shared__ float xs[NPAD * LDX];
-  __shared__ float rsm[NPAD * LDX];
-  __shared__ float xch[4][4][64];
+// call (cells with more than B 16-row blocks take several passes over the
+// gathered rows).  8 waves split between B output row blocks and KP = 8 / B
+// parts of the 128 local nodes (B = 4: k halves; B = 2: quarters; B = 1:
+// eighths), each wave holding the A fragments of both terms for its k part in
+// registers; the parts are added through LDS in k-part order.  B is chosen
+// per cell from its number of row blocks by the map `bmap` (2 bits per
+// bucket of 1, 2, 3, >= 4 row blocks: 0 -> B = 1, 1 -> 2, 2 -> 4), which the
+// autotuner sets.  The gathered rows of a tile are loaded two tiles ahead
+// into one of two register sets.
+__device__ __forceinline__ int cpl_b(int bmap, int nmb) {
+  const int q = nmb < 4 ? nmb - 1 : 3;
+  return 1 << ((bmap >> (2 * q)) & 3);
+}
+
+template <int B>
+__device__ __forceinline__ void enr_part_f32_impl(
+    const float *__restrict__ ht, const float *__restrict__ mt, int nap, int nmb, int na,
+    int64_t k0, const int (&gd)[4], const float (&gsc)[4], const float *__restrict__ X,
+    int64_t ldx, float cH, const float *__restrict__ R, int64_t ldr, float cM,
+    float *__restrict__ P, int64_t ldp, int N, float *xs, float *rsm, float *xch) {
+  constexpr int PT = 16, LDX = PT + 1, PF = 4, RPP = 32;
+  constexpr int KP = 8 / B, KS = NPAD / KP, NKS = KS / 4;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, kq = lane >> 4;
-  const int wb = w & 3, h = w >> 2;
+  const int wb = w % B, h = w / B;
   const int gj = tid % PT, gr = tid / PT;
-  int gd[PF];
-  float gsc[PF];
-#pragma unroll
-  for (int p = 0; p < PF; ++p) {
-    gd[p] = dofp[(int64_t)cell * NPAD + gr + p * RPP];
-    gsc[p] = (rs && gd[p] >= 0) ? (float)rs[gd[p]] : 1.f;
-  }
-  const int64_t k0 = eptr[cell];
-  const int na = (int)(eptr[cell + 1] - k0);
-  const int nap = tld[cell];
-  const int nmb = nap >> 4;
-  const float *ht = X ? HT + toff[cell] : nullptr;
-  const float *mt = R ? MT + toff[cell] : nullptr;
-  for (int g = 0; 4 * g < nmb; ++g) {
-    const int mb = 4 * g + wb;
+  for (int g = 0; B * g < nmb; ++g) {
+    const int mb = B * g + wb;
     const bool act = mb < nmb;
-    float aH[16], aM[16];
+    float aH[NKS], aM[NKS];
 #pragma unroll
-    for (int ks = 0; ks < 16; ++ks) {
-      const int64_t off = (int64_t)(64 * h + 4 * ks + kq) * nap + 16 * mb + li;
+    for (int ks = 0; ks < NKS; ++ks) {
+      const int64_t off = (int64_t)(KS * h + 4 * ks + kq) * nap + 16 * mb + li;
       aH[ks] = (act && ht) ? ht[off] : 0.f;
       aM[ks] = (act && mt) ? mt[off] : 0.f;
     }
@@ -280,27 +269,30 @@ __device__ __forceinline__ void enr_part_f32_body(
         f4 accH = f4zero(), accM = f4zero();
         if (ht) {
 #pragma unroll
-          for (int ks = 0; ks < 16; ++ks)
-            accH = mfma_f32(aH[ks], xs[(64 * h + 4 * ks + kq) * LDX + li], accH);
+          for (int ks = 0; ks < NKS; ++ks)
+            accH = mfma_f32(aH[ks], xs[(KS * h + 4 * ks + kq) * LDX + li], accH);
         }
         if (mt) {
 #pragma unroll
-          for (int ks = 0; ks < 16; ++ks)
-            accM = mfma_f32(aM[ks], rsm[(64 * h + 4 * ks + kq) * LDX + li], accM);
+          for (int ks = 0; ks < NKS; ++ks)
+            accM = mfma_f32(aM[ks], rsm[(KS * h + 4 * ks + kq) * LDX + li], accM);
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r) acc[r] = cH * accH[r] + cM * accM[r];
-        if (h == 1) {
+        if (h > 0) {
 #pragma unroll
-          for (int r = 0; r < 4; ++r) xch[wb][r][lane] = acc[r];
+          for (int r = 0; r < 4; ++r) xch[(((h - 1) * B + wb) * 4 + r) * 64 + lane] = acc[r];
         }
       }
       __syncthreads();
       if (act && h == 0 && li < ncol) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
+          float v = acc[r];
+#pragma unroll
+          for (int q = 1; q < KP; ++q) v += xch[(((q - 1) * B + wb) * 4 + r) * 64 + lane];
           const int orow = 16 * mb + 4 * kq + r;
-          if (orow < na) P[(k0 + orow) * ldp + c0 + li] = acc[r] + xch[wb][r][lane];
+          if (orow < na) P[(k0 + orow) * ldp + c0 + li] = v;
         }
       }
     };
@@ -312,6 +304,45 @@ __device__ __forceinline__ void enr_part_f32_body(
     }
     __syncthreads();
   }
+}
+
+__device__ __forceinline__ void enr_part_f32_body(
+    const float *__restrict__ HT, const float *__restrict__ MT,
+    const int64_t *__restrict__ toff, const int32_t *__restrict__ tld,
+    const int64_t *__restrict__ eptr, const int32_t *__restrict__ dofp,
+    const int cell, const float *__restrict__ X, int64_t ldx, float cH,
+    const float *__restrict__ R, int64_t ldr, const double *__restrict__ rs, float cM,
+    float *__restrict__ P, int64_t ldp, int N, int bmap) {
+  constexpr int PT = 16, LDX = PT + 1, PF = 4, RPP = 32;
+  __shared__ float xs[NPAD * LDX];
+  __shared__ float rsm[NPAD * LDX];
+  __shared__ float xch[7 * 4 * 64];          // partial sums of k parts 1..KP-1
+  const int tid = threadIdx.x;
+  const int gr = tid / PT;
+  int gd[PF];
+  float gsc[PF];
+#pragma unroll
+  for (int p = 0; p < PF; ++p) {
+    gd[p] = dofp[(int64_t)cell * NPAD + gr + p * RPP];
+    gsc[p] = (rs && gd[p] >= 0) ? (float)rs[gd[p]] : 1.f;
+  }
+  const int64_t k0 = eptr[cell];
+  const int na = (int)(eptr[cell + 1] - k0);
+  const int nap = tld[cell];
+  const int nmb = nap >> 4;
+  const float *ht = X ? HT + toff[cell] : nullptr;
+  const float *mt = R ? MT + toff[cell] : nullptr;
+  if (nmb == 0) return;
+  const int B = cpl_b(bmap, nmb);
+  if (B == 4)
+    enr_part_f32_impl<4>(ht, mt, nap, nmb, na, k0, gd, gsc, X, ldx, cH, R, ldr, cM, P, ldp, N, xs,
+                         rsm, xch);
+  else if (B == 2)
+    enr_part_f32_impl<2>(ht, mt, nap, nmb, na, k0, gd, gsc, X, ldx, cH, R, ldr, cM, P, ldp, N, xs,
+                         rsm, xch);
+  else
+    enr_part_f32_impl<1>(ht, mt, nap, nmb, na, k0, gd, gsc, X, ldx, cH, R, ldr, cM, P, ldp, N, xs,
+                         rsm, xch);
 }
 
 // ---------------------------------------------------------------------------

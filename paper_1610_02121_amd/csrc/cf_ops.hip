@@ -206,54 +206,35 @@ hipError_t launch_cell_gemm(hipStream_t s, const double *Hp, const int32_t *dofp
 // during the current tile's MFMAs.
 // Either term is skipped when its input block is null.
 // ---------------------------------------------------------------------------
-// 8 waves: wave w takes row block 4g + (w & 3) of group g and half
-// h = w >> 2 of the 128 k (local nodes); it keeps the A fragments of both
-// terms for its k half in registers while the column tiles stream by, and the
-// two halves are added through LDS.  blockIdx.y picks one of gridDim.y
-// contiguous ranges of column tiles (more workgroups in flight).  The gathered
-// rows of a tile are loaded two tiles ahead into one of two register sets.
-__global__ __launch_bounds__(512, 2) void k_enr_part(
-    const double *__restrict__ HT, const double *__restrict__ MT,
-    const int64_t *__restrict__ toff, const int32_t *__restrict__ tld,
-    const int64_t *__restrict__ eptr, const int32_t *__restrict__ dofp,
-    const int32_t *__restrict__ cells, const double *__restrict__ X, int64_t ldx, double cH,
-    const double *__restrict__ R, int64_t ldr, const double *__restrict__ rs, double cM,
-    double *__restrict__ P, int64_t ldp, int N) {
-  constexpr int PT = 16, LDX = PT + 1;
-  constexpr int PF = NPAD * PT / 512;     // 4 gathered values per thread per term and tile
-  constexpr int RPP = 512 / PT;           // 32 rows per pass
-  __shared__ double xs[NPAD * LDX];
-  __shared__ double rsm[NPAD * LDX];
-  __shared__ double xch[4][4][64];        // k-half 1 partial sums, per row block
+// 8 waves split between the cell's 16-row output blocks and the 128 k (local
+// nodes): with B = 4 blocks per group (cells with 3 or more blocks) wave w
+// takes block 4g + (w & 3) of group g and k half w >> 2; cells with 2 blocks
+// take B = 2 blocks and k quarters, cells with one block B = 1 and k eighths,
+// so every wave (and every SIMD) carries products whatever the block count.
+// A wave keeps the A fragments of both terms for its k part in registers
+// while the column tiles stream by; the KP = 8 / B partial sums are added
+// through LDS in k-part order.  The gathered rows of a tile are loaded two
+// tiles ahead into one of two register sets.
+template <int B>
+__device__ __forceinline__ void enr_part_body(
+    const double *__restrict__ ht, const double *__restrict__ mt, int nap, int nmb, int na,
+    int64_t k0, const int (&gd)[4], const double (&gsc)[4], const double *__restrict__ X,
+    int64_t ldx, double cH, const double *__restrict__ R, int64_t ldr, double cM,
+    double *__restrict__ P, int64_t ldp, int cbeg, int cend, double *xs, double *rsm,
+    double *xch) {
+  constexpr int PT = 16, LDX = PT + 1, PF = 4, RPP = 32;
+  constexpr int KP = 8 / B, KS = NPAD / KP, NKS = KS / 4;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, kq = lane >> 4;
-  const int wb = w & 3, h = w >> 2;
-  const int cell = cells[blockIdx.x];
-  const int ntile = (N + PT - 1) / PT;
-  const int cbeg = PT * ((ntile * (int)blockIdx.y) / (int)gridDim.y);
-  const int cend = min(N, PT * ((ntile * ((int)blockIdx.y + 1)) / (int)gridDim.y));
+  const int wb = w % B, h = w / B;
   const int gj = tid % PT, gr = tid / PT;
-  int gd[PF];
-  double gsc[PF];
-#pragma unroll
-  for (int p = 0; p < PF; ++p) {
-    gd[p] = dofp[(int64_t)cell * NPAD + gr + p * RPP];
-    gsc[p] = (rs && gd[p] >= 0) ? rs[gd[p]] : 1.0;
-  }
-  const int64_t k0 = eptr[cell];
-  const int na = (int)(eptr[cell + 1] - k0);
-  const int nap = tld[cell];
-  const int nmb = nap >> 4;
-  const double *ht = X ? HT + toff[cell] : nullptr;
-  const double *mt = R ? MT + toff[cell] : nullptr;
-  if (cbeg >= cend) return;              // uniform for the workgroup
-  for (int g = 0; 4 * g < nmb; ++g) {
-    const int mb = 4 * g + wb;
+  for (int g = 0; B * g < nmb; ++g) {
+    const int mb = B * g + wb;
     const bool act = mb < nmb;
-    double aH[16], aM[16];
+    double aH[NKS], aM[NKS];
 #pragma unroll
-    for (int ks = 0; ks < 16; ++ks) {
-      const int64_t off = (int64_t)(64 * h + 4 * ks + kq) * nap + 16 * mb + li;
+    for (int ks = 0; ks < NKS; ++ks) {
+      const int64_t off = (int64_t)(KS * h + 4 * ks + kq) * nap + 16 * mb + li;
       aH[ks] = (act && ht) ? ht[off] : 0.0;
       aM[ks] = (act && mt) ? mt[off] : 0.0;
     }
@@ -281,27 +262,30 @@ __global__ __launch_bounds__(512, 2) void k_enr_part(
         d4 accH = d4zero(), accM = d4zero();
         if (ht) {
 #pragma unroll
-          for (int ks = 0; ks < 16; ++ks)
-            accH = mfma_f64(aH[ks], xs[(64 * h + 4 * ks + kq) * LDX + li], accH);
+          for (int ks = 0; ks < NKS; ++ks)
+            accH = mfma_f64(aH[ks], xs[(KS * h + 4 * ks + kq) * LDX + li], accH);
         }
         if (mt) {
 #pragma unroll
-          for (int ks = 0; ks < 16; ++ks)
-            accM = mfma_f64(aM[ks], rsm[(64 * h + 4 * ks + kq) * LDX + li], accM);
+          for (int ks = 0; ks < NKS; ++ks)
+            accM = mfma_f64(aM[ks], rsm[(KS * h + 4 * ks + kq) * LDX + li], accM);
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r) acc[r] = cH * accH[r] + cM * accM[r];
-        if (h == 1) {
+        if (h > 0) {
 #pragma unroll
-          for (int r = 0; r < 4; ++r) xch[wb][r][lane] = acc[r];
+          for (int r = 0; r < 4; ++r) xch[(((h - 1) * B + wb) * 4 + r) * 64 + lane] = acc[r];
         }
       }
       __syncthreads();
       if (act && h == 0 && li < ncol) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
+          double v = acc[r];
+#pragma unroll
+          for (int q = 1; q < KP; ++q) v += xch[(((q - 1) * B + wb) * 4 + r) * 64 + lane];
           const int orow = 16 * mb + kq + 4 * r;
-          if (orow < na) P[(k0 + orow) * ldp + c0 + li] = acc[r] + xch[wb][r][lane];
+          if (orow < na) P[(k0 + orow) * ldp + c0 + li] = v;
         }
       }
     };
@@ -313,6 +297,49 @@ __global__ __launch_bounds__(512, 2) void k_enr_part(
     }
     __syncthreads();
   }
+}
+
+// blockIdx.y picks one of gridDim.y contiguous ranges of column tiles.
+__global__ __launch_bounds__(512, 2) void k_enr_part(
+    const double *__restrict__ HT, const double *__restrict__ MT,
+    const int64_t *__restrict__ toff, const int32_t *__restrict__ tld,
+    const int64_t *__restrict__ eptr, const int32_t *__restrict__ dofp,
+    const int32_t *__restrict__ cells, const double *__restrict__ X, int64_t ldx, double cH,
+    const double *__restrict__ R, int64_t ldr, const double *__restrict__ rs, double cM,
+    double *__restrict__ P, int64_t ldp, int N) {
+  constexpr int PT = 16, LDX = PT + 1, PF = 4, RPP = 32;
+  __shared__ double xs[NPAD * LDX];
+  __shared__ double rsm[NPAD * LDX];
+  __shared__ double xch[7 * 4 * 64];      // partial sums of k parts 1..KP-1
+  const int tid = threadIdx.x;
+  const int cell = cells[blockIdx.x];
+  const int ntile = (N + PT - 1) / PT;
+  const int cbeg = PT * ((ntile * (int)blockIdx.y) / (int)gridDim.y);
+  const int cend = min(N, PT * ((ntile * ((int)blockIdx.y + 1)) / (int)gridDim.y));
+  const int gr = tid / PT;
+  int gd[PF];
+  double gsc[PF];
+#pragma unroll
+  for (int p = 0; p < PF; ++p) {
+    gd[p] = dofp[(int64_t)cell * NPAD + gr + p * RPP];
+    gsc[p] = (rs && gd[p] >= 0) ? rs[gd[p]] : 1.0;
+  }
+  const int64_t k0 = eptr[cell];
+  const int na = (int)(eptr[cell + 1] - k0);
+  const int nap = tld[cell];
+  const int nmb = nap >> 4;
+  const double *ht = X ? HT + toff[cell] : nullptr;
+  const double *mt = R ? MT + toff[cell] : nullptr;
+  if (cbeg >= cend) return;              // uniform for the workgroup
+  if (nmb >= 3)
+    enr_part_body<4>(ht, mt, nap, nmb, na, k0, gd, gsc, X, ldx, cH, R, ldr, cM, P, ldp, cbeg, cend,
+                     xs, rsm, xch);
+  else if (nmb == 2)
+    enr_part_body<2>(ht, mt, nap, nmb, na, k0, gd, gsc, X, ldx, cH, R, ldr, cM, P, ldp, cbeg, cend,
+                     xs, rsm, xch);
+  else
+    enr_part_body<1>(ht, mt, nap, nmb, na, k0, gd, gsc, X, ldx, cH, R, ldr, cM, P, ldp, cbeg, cend,
+                     xs, rsm, xch);
 }
 
 // Single-column form (the Lanczos vectors): the coupling blocks stream
@@ -384,32 +411,26 @@ hipError_t launch_enr_part(hipStream_t s, const double *HT, const double *MT, co
 // read-modify-write):
 //   Q[128 e' + a] = sum_k (cU H^ec_e[k][a] U[idx_k] + cV M^ec_e[k][a] V[idx_k])
 // e' is the position of the cell in the enriched-cell list, a its local node.
-// The enrichment functions of the cell are taken in chunks of 64: wave w
-// keeps the A fragments of rows 32w .. 32w+32 of both transposed blocks for
+// The enrichment functions of the cell are taken in chunks of 64 (16 or 32
+// for cells with at most that many): wave w keeps the A fragments of rows 32w .. 32w+32 of both transposed blocks for
 // the chunk in registers while the column tiles stream by (the blocks are read
 // from memory once per call); the gathered rows cU U[idx_k], cV V[idx_k] of
 // the chunk pass through LDS, prefetched one tile ahead in registers; chunks
 // after the first add into Q.  Either term is skipped when its input is null.  The epilogue sums, for each
 // classical DOF, the (at most 8) Q rows of the enriched cells that contain it.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256, 2) void k_enr_q(
-    const double *__restrict__ Hec, const double *__restrict__ Mec,
-    const int64_t *__restrict__ eptr, const int32_t *__restrict__ eidx,
-    const int32_t *__restrict__ cells, const int32_t *__restrict__ order,
-    const double *__restrict__ U, int64_t ldu, double cU,
-    const double *__restrict__ V, int64_t ldv, double cV, double *__restrict__ Q, int64_t ldq,
-    int N) {
-  constexpr int PT = 16, LDZ = 16, KC = 64, KS = KC / 4;
+// Cells with at most 16 or 32 enrichment functions take chunks of that size
+// (KC = 16 or 32), so their waves run only the k steps that carry products.
+template <int KC>
+__device__ __forceinline__ void enr_q_body(
+    const double *__restrict__ Hec, const double *__restrict__ Mec, int64_t k0, int na,
+    const int32_t *__restrict__ eidx, const double *__restrict__ U, int64_t ldu, double cU,
+    const double *__restrict__ V, int64_t ldv, double cV, double *__restrict__ qb, int64_t ldq,
+    int N, double *zu, double *zv) {
+  constexpr int PT = 16, LDZ = 16, KS = KC / 4;
   constexpr int GV = KC * PT / 256;        // gathered values per thread per term and tile
-  __shared__ double zu[KC * LDZ];
-  __shared__ double zv[KC * LDZ];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, kq = lane >> 4;
-  const int pos = order ? order[blockIdx.x] : (int)blockIdx.x;   // position in the cell list
-  const int cell = cells[pos];
-  const int64_t k0 = eptr[cell];
-  const int na = (int)(eptr[cell + 1] - k0);
-  double *qb = Q + ((int64_t)pos * NPAD) * ldq;
   const int gj = tid % PT, gk = tid / PT;   // gather: column gj, rows gk + 16 p
   // chunks of KC enrichment functions: the A fragments of the chunk (rows
   // 32w .. 32w+32 of both transposed blocks) stay in registers while the
@@ -499,6 +520,30 @@ __global__ __launch_bounds__(256, 2) void k_enr_q(
       __syncthreads();
     }
   }
+}
+
+__global__ __launch_bounds__(256, 2) void k_enr_q(
+    const double *__restrict__ Hec, const double *__restrict__ Mec,
+    const int64_t *__restrict__ eptr, const int32_t *__restrict__ eidx,
+    const int32_t *__restrict__ cells, const int32_t *__restrict__ order,
+    const double *__restrict__ U, int64_t ldu, double cU,
+    const double *__restrict__ V, int64_t ldv, double cV, double *__restrict__ Q, int64_t ldq,
+    int N) {
+  constexpr int PT = 16, LDZ = 16, KC = 64;
+  __shared__ double zu[KC * LDZ];
+  __shared__ double zv[KC * LDZ];
+  const int tid = threadIdx.x;
+  const int pos = order ? order[blockIdx.x] : (int)blockIdx.x;   // position in the cell list
+  const int cell = cells[pos];
+  const int64_t k0 = eptr[cell];
+  const int na = (int)(eptr[cell + 1] - k0);
+  double *qb = Q + ((int64_t)pos * NPAD) * ldq;
+  if (na > 32)
+    enr_q_body<64>(Hec, Mec, k0, na, eidx, U, ldu, cU, V, ldv, cV, qb, ldq, N, zu, zv);
+  else if (na > 16)
+    enr_q_body<32>(Hec, Mec, k0, na, eidx, U, ldu, cU, V, ldv, cV, qb, ldq, N, zu, zv);
+  else if (na > 0)
+    enr_q_body<16>(Hec, Mec, k0, na, eidx, U, ldu, cU, V, ldv, cV, qb, ldq, N, zu, zv);
   if (na == 0) {
     // no enrichment functions: the cell's buffer rows are zero
     for (int c0 = 0; c0 < N; c0 += PT)

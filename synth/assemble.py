@@ -232,7 +232,7 @@ def _workers() -> int:
 def assemble(mesh: Mesh, potential, enr: EnrichmentSet | None, ng: int = 6,
              tol_rel: float = 1e-10, tol_abs: float = 1e-14, max_depth: int = 10,
              chunk: int = 16, workers: int | None = None, verbose: bool = False,
-             plain_blocks: bool = True, progress=None) -> Problem:
+             plain_blocks: bool = True, progress=None, singular_centers=None) -> Problem:
     """Element blocks of the problem.
 
     The adaptive-quadrature tolerance of trial function nu is
@@ -244,6 +244,11 @@ def assemble(mesh: Mesh, potential, enr: EnrichmentSet | None, ng: int = 6,
     potential term is left to a device assembly from the potential at their
     Gauss points; meta["plain_blocks"] records it).  progress(msg), if given,
     is called about every 30 s while the enriched cells are integrated.
+    singular_centers [k, 3]: points where the potential is singular (bare
+    nuclei); the cells without enrichment functions that touch one (box
+    distance below h / 2) take the potential term by the adaptive rule with
+    the trial function |V| (tolerance tol_rel times its plain-rule integral
+    over those cells), as the enriched cells do.
     """
     t0 = time.time()
     p, h, E, npc = mesh.p, mesh.h, mesh.n_cells, mesh.npc
@@ -284,6 +289,22 @@ def assemble(mesh: Mesh, potential, enr: EnrichmentSet | None, ng: int = 6,
     Bref, _ = shape_at(p, 2.0, np.array([-1.0, -1.0, -1.0]), 2.0 * ref - 1.0, need_grad=False)
     plain = np.nonzero(counts == 0)[0]
     jac = h ** 3
+    if singular_centers is not None and plain.size:
+        near = np.zeros(E, dtype=bool)
+        for c in np.asarray(singular_centers, dtype=np.float64).reshape(-1, 3):
+            near |= box_distance(lo_all, h, c) < 0.5 * h
+        sing = plain[near[plain]]
+        plain = plain[~near[plain]]
+        if sing.size:
+            ref0, wref0 = unit_cube_rule(ng)
+            fV = lambda x: np.abs(potential(x))[:, None]          # noqa: E731
+            SV = sum(abs(float((wref0 * jac) @ fV(lo_all[e][None, :] + h * ref0)[:, 0]))
+                     for e in sing)
+            tauV = np.array([max(tol_abs, tol_rel * SV)])
+            for e in sing:
+                pts, w, _ = adaptive_rule(lo_all[e], h, fV, tauV, ng=ng, max_depth=max_depth)
+                Nq, _ = shape_at(p, h, lo_all[e], pts, need_grad=False)
+                H_cc[e] = K + (Nq.T * (w * potential(pts))[None, :]) @ Nq
     if not plain_blocks:
         H_cc[plain] = K[None]
         plain = plain[:0]

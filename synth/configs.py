@@ -74,7 +74,7 @@ def hydrogen(nc: int = 8, length: float = 20.0, p: int = 4, r_c: float = 6.0,
         enr = EnrichmentSet(centers=np.zeros((1, 3)),
                             shells=[Radial("h1s"), Radial("h2s")], r_c=r_c)
     V = coulomb_potential([0.0, 0.0, 0.0])
-    prob = assemble(mesh, V, enr, **kw)
+    prob = assemble(mesh, V, enr, singular_centers=np.zeros((1, 3)), **kw)
     prob.meta.update(kind="hydrogen", r_c=r_c, mesh=mesh, enr=enr, potential=V)
     return prob
 
@@ -183,26 +183,44 @@ def config3_meta(seed: int = 0) -> dict:
     return si_cluster_meta(n_atoms=280, length=80.0, nc=48, p=4, r_c=8.0, seed=seed)
 
 
-def batch_cluster(n_atoms: int, seed: int = 0) -> Problem:
-    """One problem of the batched workload: an n_atoms Si cluster (1..8) in a
-    cube of half-width R_cluster + 12 Bohr with 6 + round(6 (n_atoms - 1) / 7)
-    degree-4 cells per axis, r_c = 8, nine Slater enrichments per atom."""
+def cluster_in_box(n_atoms: int, nc: int, seed: int, **kw) -> Problem:
+    """An n_atoms Si cluster (diamond sites nearest the origin) in a cube of
+    half-width R_cluster + 12 Bohr (R_cluster = the largest site coordinate)
+    with nc degree-4 cells per axis, r_c = 8, nine Slater enrichments per atom."""
     sites = diamond_sites(n_atoms)
     R = float(np.abs(sites).max()) if n_atoms > 1 else 0.0
-    nc = 6 + round(6 * (n_atoms - 1) / 7)
-    return si_cluster(n_atoms=n_atoms, length=2.0 * (R + 12.0), nc=nc, p=4, r_c=8.0,
-                      seed=1000 + n_atoms + seed)
+    return si_cluster(n_atoms=n_atoms, length=2.0 * (R + 12.0), nc=nc, p=4, r_c=8.0, seed=seed,
+                      **kw)
 
 
-def batch_workload(count: int = 256, seed: int = 0, max_atoms: int = 8):
+def batch_cluster(n_atoms: int, seed: int = 0, **kw) -> Problem:
+    """One problem of the batched workload: a cluster of 1-40 atoms in its
+    own cube (cluster_in_box) with 8 + round(12 (n_atoms - 1) / 39) cells per
+    axis (8^3 .. 20^3 cells); its own jitter and exponents (seed)."""
+    return cluster_in_box(n_atoms, 8 + round(12 * (n_atoms - 1) / 39), 1000 + n_atoms + seed, **kw)
+
+
+def batch_vectors(n_atoms: int) -> int:
+    """Block width of a batched problem: 16 + round(334 (n_atoms - 1) / 39)
+    (16 .. 350 vectors for 1 .. 40 atoms)."""
+    return 16 + round(334 * (n_atoms - 1) / 39)
+
+
+def batch_workload(count: int = 256, seed: int = 0, max_atoms: int = 40, **kw):
     """Batched workload: `count` entries with atom counts drawn U{1..max_atoms}
-    (seeded), N = 16 + round(48 (n_atoms - 1) / 7) vectors, filter degree 40.
-    The entries of one atom count share one generated problem (the pool), so
-    the batch holds max_atoms distinct operators and `count` independent
+    (seeded), batch_vectors(n_atoms) vectors each, filter degree 40.  The
+    entries of one atom count share one generated problem (the pool), so the
+    batch holds at most max_atoms distinct operators and `count` independent
     blocks and intervals.  Returns (pool dict n_atoms -> Problem, list of
     n_atoms per entry, list of N per entry)."""
     rng = np.random.default_rng(seed)
     atoms = [int(a) for a in rng.integers(1, max_atoms + 1, size=count)]
-    pool = {a: batch_cluster(a, seed) for a in sorted(set(atoms))}
-    Ns = [16 + round(48 * (a - 1) / 7) for a in atoms]
+    pool = {a: batch_cluster(a, seed, **kw) for a in sorted(set(atoms))}
+    Ns = [batch_vectors(a) for a in atoms]
     return pool, atoms, Ns
+
+
+def learned_cluster(n_atoms: int, seed: int = 0) -> Problem:
+    """A small cluster of the learned-bounds study (1..8 atoms):
+    cluster_in_box with 6 + round(6 (n_atoms - 1) / 7) cells per axis."""
+    return cluster_in_box(n_atoms, 6 + round(6 * (n_atoms - 1) / 7), 1000 + n_atoms + seed)

@@ -1,7 +1,7 @@
 """Parity at the full size of the 280-atom Si workload (48^3 cells,
 n = 6,970,391, n_e = 2520) in the launch configuration the benchmark times
-(N = 300, one GPU's column share of the block), with the plain cells' blocks
-assembled on the device.
+(work blocks of 256 columns, the whole N = 2200 block filtered and projected
+in place), with the plain cells' blocks assembled on the device.
 
 The global oracle operator does not fit (about 1.7e9 element entries), so
 outputs are checked row by row from the element blocks
@@ -9,7 +9,8 @@ outputs are checked row by row from the element blocks
 identities that hold at any size:
 * device-assembled blocks of sampled plain cells against the oracle's
   quadrature sum (bound as in test_gpu_assemble);
-* H X on N = 300 columns: sampled classical and enrichment rows;
+* H X on N = 600 columns (work-block chunks 256 + 256 + 88): sampled
+  classical and enrichment rows;
 * (M^E)^-1 X on 8 columns: every row against the oracle's block-wise
   inverse of Sec. IV.D (it needs only the global M^E, which is small).  Both
   sides form the Schur complement S = M^ee - M^ec D^-1 M^ec^T, a difference
@@ -20,12 +21,21 @@ identities that hold at any size:
   grows like sqrt(k) u), so the test allows 10 u kappa(S) rho sqrt(k) max|Z|,
   rho the ratio of that norm to ||S|| (all computed by the oracle:
   kappa(S) = 2.7e5, rho = 28; measured error 6.9e-9);
-* filter(N = 300): on 8 columns, M (Y_m + Y_{m-2}) = 2 e H Y_{m-1} - 2 c M Y_{m-1}
-  on sampled rows (the three-term recurrence multiplied by M), within the
-  same bound times m of the terms' scale (measured ~1e-13).
+* filter(N = 2200, in place, 9 column chunks): on 8 columns,
+  M (Y_m + Y_{m-2}) = 2 e H Y_{m-1} - 2 c M Y_{m-1} on sampled rows (the
+  three-term recurrence multiplied by M), within the same bound times m of
+  the terms' scale (measured ~1e-13);
+* Rayleigh-Ritz of the atomic-orbital start block, N = 2200 (in-place
+  Cholesky-QR by row blocks, projection by column slabs): the block spans
+  the lowest 2200 eigenvectors of the enrichment pencil (H^ee, M^ee) in the
+  enrichment rows, an invariant subspace of (H^E, M^E) restricted to them,
+  so the Ritz values are those eigenvalues exactly (within 1e-8 Ha), the
+  classical rows stay zero and the Ritz vectors are M-orthonormal.
 
-The host generation of the enriched cells takes several minutes, so the
-module runs only with CF_FULLSIZE_280=1 in the environment.
+The module comes first among the GPU tests (file name) because the host
+generation of the enriched cells forks worker processes, which a
+GPU-initialised process must not do; run out of that order, the generation
+runs in a child process.
 """
 import os
 
@@ -35,14 +45,35 @@ import pytest
 from oracle.assembly import plain_cell_block
 from oracle.operators import Operators, sampled_rows
 
-pytestmark = [pytest.mark.gpu, pytest.mark.timeout(1800),
-              pytest.mark.skipif(os.environ.get("CF_FULLSIZE_280") != "1",
-                                 reason="needs several minutes of host generation; "
-                                        "set CF_FULLSIZE_280=1")]
+pytestmark = [pytest.mark.gpu, pytest.mark.timeout(1800)]
 
 torch = pytest.importorskip("torch")
 U = 2.0 ** -53
-N = 300
+N = 2200
+CHUNK = 256
+
+
+def _generate():
+    """config3 in this process, or in a child process when this one has
+    already initialised the GPU (the generator then could not fork)."""
+    import subprocess
+    import sys
+    import tempfile
+
+    from synth import configs
+    from synth.assemble import gpu_initialised
+    from synth.problem import Problem
+    if not gpu_initialised():
+        return configs.config3(progress=lambda m: print("[fullsize280]", m, flush=True))
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    with tempfile.TemporaryDirectory() as td:
+        path = os.path.join(td, "cfg3.npz")
+        subprocess.run([sys.executable, "-c",
+                        f"import sys; sys.path.insert(0, {root!r}); from synth import configs; "
+                        f"configs.config3().save({path!r})"], check=True)
+        prob = Problem.load(path)
+    prob.meta.update(configs.config3_meta())
+    return prob
 
 
 @pytest.fixture(scope="module")
@@ -51,14 +82,14 @@ def full():
     from synth import configs
     from synth.assemble import plain_points, plain_tables, potential_at_points
     print("[fullsize280] generating the 280-atom workload", flush=True)
-    prob = configs.config3(progress=lambda m: print("[fullsize280]", m, flush=True))
-    print(f"[fullsize280] n={prob.n}; context", flush=True)
-    ctx = Context(prob, max_cols=N)
+    prob = _generate()
     B, w, K, _ = plain_tables(prob)
     ep = np.asarray(prob.enr_ptr)
     cells = np.nonzero(ep[1:] == ep[:-1])[0].astype(np.int32)
     V = potential_at_points(prob.meta["potential"], plain_points(prob, cells).reshape(-1, 3))
     V = V.reshape(len(cells), -1)
+    print(f"[fullsize280] n={prob.n}; context", flush=True)
+    ctx = Context(prob, max_cols=N, col_chunk=CHUNK)
     ctx.assembly_tables(B, w, K)
     ctx.assemble_cells(cells, torch.tensor(V, dtype=torch.float64, device="cuda"))
     torch.cuda.synchronize()
@@ -85,6 +116,7 @@ def full():
     yield {"prob": prob, "ctx": ctx, "B": B, "w": w, "K": K, "cells": cells, "V": V,
            "ops": ops, "tol": tol}
     ctx.close()
+    torch.cuda.empty_cache()
 
 
 def host(t):
@@ -128,14 +160,15 @@ def test_device_blocks_sampled_cells(full):
 
 def test_apply_H_sampled_rows(full):
     prob, ctx = full["prob"], full["ctx"]
-    print("[fullsize280] apply_H N=300", flush=True)
-    Xd = torch.randn((prob.n, N), dtype=torch.float64, device="cuda",
+    print("[fullsize280] apply_H N=600", flush=True)
+    Xd = torch.randn((prob.n, 600), dtype=torch.float64, device="cuda",
                      generator=torch.Generator(device="cuda").manual_seed(41))
     Y = ctx.apply_H(Xd)
     rows = sample_rows(prob, 42)
     X = host(Xd)
     Yo = sampled_rows(prob, rows, X, "H", H_cc=oracle_blocks(full, rows))
     Ys = host(Y[torch.tensor(rows, device="cuda")])
+    del Xd, Y
     assert np.abs(Ys - Yo).max() < 1e-12 * np.abs(Yo).max()
 
 
@@ -155,15 +188,20 @@ def test_apply_Sinv_block_inverse(full):
 
 def test_filter_three_term_identity(full):
     prob, ctx = full["prob"], full["ctx"]
-    print("[fullsize280] filter N=300, m=1..4", flush=True)
-    Xd = torch.randn((prob.n, N), dtype=torch.float64, device="cuda",
-                     generator=torch.Generator(device="cuda").manual_seed(45))
-    a, b = -60.0, 600.0
+    print("[fullsize280] filter N=2200 in place, m=1..4", flush=True)
+    a, b = -270.0, 110.0
     e, c = 2.0 / (b - a), (a + b) / (b - a)
-    cols = torch.tensor([0, 17, 63, 64, 150, 255, 298, 299], device="cuda")
-    Ys = {0: host(Xd[:, cols])}
-    for m in (1, 2, 3, 4):
-        Ys[m] = host(ctx.filter(Xd, m, a, b)[:, cols])
+    cols = torch.tensor([0, 17, 255, 256, 1000, 1791, 1792, 2199], device="cuda")
+    gen = torch.Generator(device="cuda")
+    Y = torch.empty((prob.n, N), dtype=torch.float64, device="cuda")
+    Ys = {}
+    for m in (0, 1, 2, 3, 4):
+        torch.randn((prob.n, N), dtype=torch.float64, device="cuda", generator=gen.manual_seed(45),
+                    out=Y)
+        if m:
+            ctx.filter(Y, m, a, b, Y=Y)
+        Ys[m] = host(Y[:, cols])
+    del Y
     rows = sample_rows(prob, 46, n_cl=80, n_en=12)
     blocks = oracle_blocks(full, rows)
     for m in (2, 3, 4):
@@ -175,3 +213,23 @@ def test_filter_three_term_identity(full):
         print(f"[fullsize280] m={m}: identity residual {np.abs(lhs - rhs).max() / scale:.2e}",
               flush=True)
         assert np.abs(lhs - rhs).max() < full["tol"] * m * scale, m
+
+
+def test_rayleigh_ritz_atomic_orbital_block(full):
+    import scipy.linalg as sla
+    prob, ctx = full["prob"], full["ctx"]
+    print("[fullsize280] rayleigh_ritz N=2200, column slabs of 256", flush=True)
+    lam, Vee = sla.eigh(prob.H_ee, prob.M_ee)
+    Y = torch.zeros((prob.n, N), dtype=torch.float64, device="cuda")
+    Y[prob.n_h:] = torch.tensor(Vee[:, :N], device="cuda")
+    theta = ctx.rayleigh_ritz(Y)
+    err = np.abs(theta - lam[:N]).max()
+    print(f"[metrics] rayleigh_ritz si280-48c N=2200 chunk=256 (atomic-orbital block): "
+          f"ritz_err={err:.3e} Ha energy_err={2 * abs(np.sum(theta - lam[:N])):.3e} Ha", flush=True)
+    assert err < 1e-8
+    for r0 in range(0, prob.n_h, 400_000):          # the classical rows stay zero
+        assert int(torch.count_nonzero(Y[r0:min(prob.n_h, r0 + 400_000)])) == 0
+    Ze = host(Y[prob.n_h:])
+    del Y
+    assert np.abs(Ze.T @ prob.M_ee @ Ze - np.eye(N)).max() < 1e-10
+    assert np.abs(Ze.T @ prob.H_ee @ Ze - np.diag(theta)).max() < 1e-8 * np.abs(theta).max()

@@ -241,3 +241,27 @@ def test_batch_dense_cells_equal_single(prec, si_dense, si_small):
     for i, p in enumerate(probs):
         Ys = host(singles[id(p)].filter(Xd[i], 5, ab[i][0], ab[i][1], prec=prec))
         assert np.array_equal(host(Yb[i]), Ys), i
+
+
+def test_batch_coupling_map_equals_single(si_dense, si_small):
+    """With the same coupling map set on the batch and on the single
+    contexts, the batched FP32 filter equals the single-problem one bit for
+    bit; the batch autotuner keeps a valid map."""
+    from paper_1610_02121_amd import Batch, Context
+    print("[batch coupling map]", flush=True)
+    probs = [si_dense, si_small]
+    Ns = [20, 12]
+    batch = Batch(probs, max_cols=20)
+    singles = [Context(p, max_cols=20) for p in probs]
+    ab = [(-40.0, 400.0), (-35.0, 300.0)]
+    Xd = [dev(x) for x in blocks(probs, Ns, 90)]
+    cmap = 0b01010101                    # 2 row blocks x 4 k parts in every bucket
+    batch.tuning(cmap)
+    for c in singles:
+        c.tuning(cmap)
+    Yb = batch.filter(Xd, 5, [a for a, _ in ab], [b for _, b in ab], prec="fp32")
+    for i, c in enumerate(singles):
+        assert np.array_equal(host(Yb[i]), host(c.filter(Xd[i], 5, ab[i][0], ab[i][1], prec="fp32")))
+    batch.autotune(Xd, 5, [a for a, _ in ab], [b for _, b in ab], prec="fp32", reps=1)
+    got = batch.tuning()["coupling_map"]
+    assert all(((got >> (2 * q)) & 3) < 3 for q in range(4))

@@ -340,3 +340,39 @@ def test_cell_tile_shapes_agree_and_autotune(si_small):
     with pytest.raises(ChebFilterError, match="CF_EINVAL"):
         ctx.set_cell_tile("fp32", 3)
     ctx.close()
+
+
+def test_coupling_map_choices_agree_and_autotune(si_dense):
+    """The FP32 coupling partials' wave split per row-block bucket (1 x 8,
+    2 x 4 or 4 x 2 row blocks x k parts) changes only the order of FP32 sums:
+    every map gives the filter within 10 u32 kappa(M^E) per step of the
+    default map's (which test_filter_steps pins to the oracle); the autotuner
+    keeps a valid map and the tuning state reports it."""
+    from paper_1610_02121_amd import ChebFilterError, Context
+    print("[coupling map]", flush=True)
+    prob = si_dense
+    ctx = Context(prob, max_cols=24)
+    ops = Operators(prob)
+    kap = kappa_M(ops)
+    v0 = dev(np.random.default_rng(63).standard_normal(prob.n)).reshape(-1)
+    lo, hi = ctx.lanczos_bounds(v0, 10)
+    a, b = lo + 0.1 * (hi - lo), hi
+    X = dev(bf16_block((prob.n, 21), 64))
+    m = 4
+    default = ctx.tuning()["coupling_map"]
+    ref = host(ctx.filter(X, m, a, b, prec="fp32"))
+    for cmap in (0, 0b01010101, 0b10101010, 0b00100100):
+        ctx.tuning(cmap)
+        Y = host(ctx.filter(X, m, a, b, prec="fp32"))
+        rel = float(np.abs(Y - ref).max() / np.abs(ref).max())
+        print(f"  map {cmap:08b}: rel diff {rel:.2e}", flush=True)
+        assert rel < 10 * U32 * kap * m
+    ctx.tuning(default)
+    assert np.array_equal(host(ctx.filter(X, m, a, b, prec="fp32")), ref)
+    ctx.autotune(X, m, a, b, prec="fp32", reps=1)
+    cmap = ctx.tuning()["coupling_map"]
+    print(f"  autotuned map {cmap:08b}", flush=True)
+    assert all(((cmap >> (2 * q)) & 3) < 3 for q in range(4))
+    with pytest.raises(ChebFilterError, match="CF_EINVAL"):
+        ctx.tuning(0b11)
+    ctx.close()

@@ -748,10 +748,7 @@ def learned_study(args):
     t_train = time.time() - t1
     # the corpus's labels and the trained network's outputs on it, against the
     # guard's acceptance window for beta
-    im, isd, om, osd = L.normalisation(inputs, targets)
-    Xn = torch.tensor((inputs - im) / isd, dtype=torch.float32, device=dev)
-    pred = np.concatenate([net.forward(Xn[i:i + 64].contiguous()).cpu().numpy()
-                           for i in range(0, len(Xn), 64)]) * osd + om
+    pred = net.predict(inputs)
     diag = {"label_beta_mean": float(targets[:, 1].mean()),
             "label_beta_p10_p50_p90": [float(x) for x in np.percentile(targets[:, 1], [10, 50, 90])],
             "label_beta_below_guard": float(np.mean(targets[:, 1] < 0.98)),

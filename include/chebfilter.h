@@ -413,6 +413,51 @@ cf_status chebfilter_bounds_predict(cf_ctx *ctx, cf_mlp *mlp, const double *hist
                                     int32_t m_max, double *a, double *b, int32_t *m,
                                     int32_t *fallback);
 
+/* Degree rule of the filter (Sec. V: the degree is chosen from the damped
+ * interval and the wanted part of the spectrum): the smallest m with
+ * T_m(|t(theta_w)|) >= rho, t(x) = (2x - a - b)/(b - a), capped where the
+ * amplification of theta_1 over theta_w reaches 1e12 (the FP64 range of the
+ * orthonormalisation), clamped to [m_min, m_max].  Host arithmetic only.
+ * CF_EINVAL for b <= a, rho <= 1 or a bad range. */
+cf_status chebfilter_degree_rule(double theta_1, double theta_w, double a, double b, double rho,
+                                 int32_t m_min, int32_t m_max, int32_t *m);
+
+/* The 8 raw features of one self-consistent step (host arrays): theta_1,
+ * theta_wanted, theta_N, b used, m used, largest and median residual norm of
+ * the wanted pairs, largest change of the wanted Ritz values from theta_prev.
+ * Host arithmetic only. */
+cf_status chebfilter_step_summary(const double *theta, const double *theta_prev, int32_t N,
+                                  int32_t wanted, double b_used, int32_t m_used,
+                                  const double *res, double *out);
+
+/* One training sample for the bounds network on the context's current
+ * operator: input[8 x steps] = chebfilter_bounds_features(history), target =
+ * ((a* - theta_N)/w, (b* - theta_N)/w, m*) with a* = theta[N-1] (host Ritz
+ * values of the current subspace), b* the upper bound of a k-step Lanczos run
+ * from the device vector v0, m* = chebfilter_degree_rule(theta[0],
+ * theta[wanted-1], a*, b*, 100, m_min, m_max), theta_N and w = b - theta_N of
+ * the history's last step.  Synchronises. */
+cf_status chebfilter_bounds_label(cf_ctx *ctx, const double *history, int32_t steps,
+                                  const double *theta, int32_t N, int32_t wanted,
+                                  const double *v0, int32_t k, int32_t m_min, int32_t m_max,
+                                  double *input, double *target);
+
+/* chebfilter_mlp_set_normalization with the per-column mean and standard
+ * deviation of a corpus (inputs [count][n_in], targets [count][n_out], host,
+ * row-major); a constant column gets standard deviation 1. */
+cf_status chebfilter_mlp_fit_normalization(cf_mlp *mlp, const double *inputs,
+                                           const double *targets, int64_t count);
+
+/* The network's normalisation applied to host rows: which = 0 raw inputs
+ * [count][n_in], which = 1 raw targets [count][n_out], into FP32 out (the
+ * training data of chebfilter_mlp_loss_grad). */
+cf_status chebfilter_mlp_normalize(cf_mlp *mlp, int32_t which, const double *x, int64_t count,
+                                   float *out);
+
+/* Raw outputs [count][n_out] of raw inputs [count][n_in] (host), through the
+ * normalisation and the network.  Synchronises. */
+cf_status chebfilter_mlp_predict(cf_mlp *mlp, const double *x_raw, int64_t count, double *y_raw);
+
 #ifdef __cplusplus
 }
 #endif

@@ -35,7 +35,9 @@ EXPORTS = ["chebfilter_init", "chebfilter_destroy", "chebfilter_last_error", "ch
            "chebfilter_bounds_predict", "chebfilter_assembly_tables", "chebfilter_assemble_cells",
            "chebfilter_get_H_cc", "chebfilter_set_cell_tile", "chebfilter_autotune",
            "chebfilter_batch_autotune", "chebfilter_lanczos_bounds_noalloc", "chebfilter_tuning",
-           "chebfilter_batch_tuning"]
+           "chebfilter_batch_tuning", "chebfilter_degree_rule", "chebfilter_step_summary",
+           "chebfilter_bounds_label", "chebfilter_mlp_fit_normalization", "chebfilter_mlp_normalize",
+           "chebfilter_mlp_predict"]
 
 
 class CfProblem(C.Structure):
@@ -123,6 +125,12 @@ def load_library() -> C.CDLL:
     lib.chebfilter_batch_autotune.argtypes = [vp, C.POINTER(vp), P64, C.POINTER(vp), P64, P64, i32,
                                               C.POINTER(dbl), C.POINTER(dbl), i32, i32,
                                               C.POINTER(i32)]
+    lib.chebfilter_degree_rule.argtypes = [dbl, dbl, dbl, dbl, dbl, i32, i32, C.POINTER(i32)]
+    lib.chebfilter_step_summary.argtypes = [PD, PD, i32, i32, dbl, i32, PD, PD]
+    lib.chebfilter_bounds_label.argtypes = [vp, PD, i32, PD, i32, i32, vp, i32, i32, i32, PD, PD]
+    lib.chebfilter_mlp_fit_normalization.argtypes = [vp, PD, PD, i64]
+    lib.chebfilter_mlp_normalize.argtypes = [vp, i32, PD, i64, vp]
+    lib.chebfilter_mlp_predict.argtypes = [vp, PD, i64, PD]
     lib.chebfilter_tuning.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
     lib.chebfilter_batch_tuning.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(i32),
                                             C.POINTER(i32)]
@@ -331,6 +339,19 @@ class Context:
                                                  out.ctypes.data))
         return out
 
+    def bounds_label(self, history, theta, wanted: int, v0, k: int = 40, m_min: int = 8,
+                     m_max: int = 120):
+        """(input, target) training sample for the current operator (chebfilter_bounds_label)."""
+        h = _np(history, np.float64).ravel()
+        th = _np(theta, np.float64)
+        inp, tgt = np.zeros(h.size), np.zeros(3)
+        PD = C.POINTER(C.c_double)
+        self._check(self.lib.chebfilter_bounds_label(
+            self._h, h.ctypes.data_as(PD), h.size // 8, th.ctypes.data_as(PD), int(th.size),
+            int(wanted), v0.data_ptr(), int(k), int(m_min), int(m_max), inp.ctypes.data_as(PD),
+            tgt.ctypes.data_as(PD)))
+        return inp, tgt
+
     def residual_norms(self, Z, theta) -> np.ndarray:
         """||H z_j - theta_j M z_j||_{M^-1} per column of Z."""
         zp, ldz = _block(Z, "Z")
@@ -497,6 +518,32 @@ def bounds_features(history) -> np.ndarray:
     return out
 
 
+def degree_rule(theta_1: float, theta_w: float, a: float, b: float, rho: float = 100.0,
+                m_min: int = 8, m_max: int = 120) -> int:
+    """chebfilter_degree_rule."""
+    lib = load_library()
+    m = C.c_int32()
+    st = lib.chebfilter_degree_rule(float(theta_1), float(theta_w), float(a), float(b), float(rho),
+                                    int(m_min), int(m_max), C.byref(m))
+    if st != 0:
+        raise ChebFilterError(st, "degree_rule: need b > a, rho > 1, 1 <= m_min <= m_max")
+    return m.value
+
+
+def step_summary(theta, theta_prev, wanted: int, b_used: float, m_used: int, res) -> np.ndarray:
+    """chebfilter_step_summary: the 8 raw features of one step."""
+    lib = load_library()
+    th, tp, r = _np(theta, np.float64), _np(theta_prev, np.float64), _np(res, np.float64)
+    out = np.zeros(8)
+    PD = C.POINTER(C.c_double)
+    st = lib.chebfilter_step_summary(th.ctypes.data_as(PD), tp.ctypes.data_as(PD), int(th.size),
+                                     int(wanted), float(b_used), int(m_used), r.ctypes.data_as(PD),
+                                     out.ctypes.data_as(PD))
+    if st != 0:
+        raise ChebFilterError(st, "step_summary: bad sizes")
+    return out
+
+
 class Mlp:
     """The bounds network on the GPU (wraps cf_mlp): FP32 parameters, forward,
     mean-squared-error gradient and Adam, all in the library's kernels."""
@@ -570,6 +617,39 @@ class Mlp:
 
     def adam_step(self, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
         self._check(self.lib.chebfilter_mlp_adam_step(self._h, lr, beta1, beta2, eps))
+
+    def fit_normalization(self, inputs, targets):
+        """chebfilter_mlp_fit_normalization on a corpus [count, n_in], [count, n_out]."""
+        x, t = _np(inputs, np.float64), _np(targets, np.float64)
+        PD = C.POINTER(C.c_double)
+        self._check(self.lib.chebfilter_mlp_fit_normalization(self._h, x.ctypes.data_as(PD),
+                                                              t.ctypes.data_as(PD), int(x.shape[0])))
+
+    def _normalized(self, which: int, x):
+        import torch
+        x = _np(x, np.float64)
+        out = np.zeros(x.shape, dtype=np.float32)
+        self._check(self.lib.chebfilter_mlp_normalize(
+            self._h, which, x.ctypes.data_as(C.POINTER(C.c_double)), int(x.shape[0]),
+            out.ctypes.data))
+        return torch.tensor(out, device=self.device)
+
+    def normalize_inputs(self, inputs):
+        """Inputs [count, n_in] normalised by the library, as an FP32 device tensor."""
+        return self._normalized(0, inputs)
+
+    def normalize_targets(self, targets):
+        """Targets [count, n_out] normalised by the library, as an FP32 device tensor."""
+        return self._normalized(1, targets)
+
+    def predict(self, inputs) -> np.ndarray:
+        """Raw outputs [count, n_out] of raw inputs (chebfilter_mlp_predict)."""
+        x = _np(inputs, np.float64)
+        y = np.zeros((x.shape[0], self.n_out))
+        PD = C.POINTER(C.c_double)
+        self._check(self.lib.chebfilter_mlp_predict(self._h, x.ctypes.data_as(PD), int(x.shape[0]),
+                                                    y.ctypes.data_as(PD)))
+        return y
 
     def set_normalization(self, in_mean, in_std, out_mean, out_std):
         arrs = [_np(v, np.float64) for v in (in_mean, in_std, out_mean, out_std)]

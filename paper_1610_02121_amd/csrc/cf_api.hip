@@ -2530,6 +2530,72 @@ cf_status chebfilter_bounds_features(const double *history, int32_t steps, doubl
   return CF_OK;
 }
 
+// Degree rule of the learned-bounds form: the smallest m with
+// T_m(|t(theta_w)|) >= rho (t(x) = (2x - a - b)/(b - a)), capped where
+// T_m(|t(theta_1)|) / T_m(|t(theta_w)|) ~ exp(m (acosh|t_1| - acosh|t_w|))
+// reaches 1e12 (beyond it the wanted directions near theta_w drown in the
+// rounding of the lowest ones), clamped to [m_min, m_max].
+cf_status chebfilter_degree_rule(double theta_1, double theta_w, double a, double b, double rho,
+                                 int32_t m_min, int32_t m_max, int32_t *m) {
+  if (!m || !(b > a) || !std::isfinite(a) || !std::isfinite(b) || !(rho > 1.0) || m_min < 1 ||
+      m_max < m_min)
+    return CF_EINVAL;
+  const double t = std::fabs((2.0 * theta_w - a - b) / (b - a));
+  double mr = t <= 1.0 ? INFINITY : std::ceil(std::acosh(rho) / std::acosh(t));
+  const double t1 = std::fabs((2.0 * theta_1 - a - b) / (b - a));
+  const double g = std::acosh(std::max(t1, 1.0)) - std::acosh(std::max(t, 1.0));
+  if (g > 0.0) mr = std::min(mr, std::floor(std::log(1e12) / g));
+  *m = (int32_t)std::min<double>(std::max<double>(mr, m_min), m_max);
+  return CF_OK;
+}
+
+// The 8 summary numbers of one step (the network's raw inputs):
+// theta_1, theta_Nw, theta_N, b used, m used, largest and median residual
+// norm of the wanted pairs, largest change of the wanted Ritz values.
+cf_status chebfilter_step_summary(const double *theta, const double *theta_prev, int32_t N,
+                                  int32_t wanted, double b_used, int32_t m_used,
+                                  const double *res, double *out) {
+  if (!theta || !theta_prev || !res || !out || wanted < 1 || wanted > N) return CF_EINVAL;
+  std::vector<double> r(res, res + wanted);
+  double d = 0.0;
+  for (int i = 0; i < wanted; ++i) d = std::max(d, std::fabs(theta[i] - theta_prev[i]));
+  std::sort(r.begin(), r.end());
+  const double med = (wanted % 2) ? r[wanted / 2] : 0.5 * (r[wanted / 2 - 1] + r[wanted / 2]);
+  out[0] = theta[0]; out[1] = theta[wanted - 1]; out[2] = theta[N - 1];
+  out[3] = b_used; out[4] = (double)m_used; out[5] = r[wanted - 1]; out[6] = med; out[7] = d;
+  return CF_OK;
+}
+
+// Training sample of the learned bounds for the current operator: input =
+// chebfilter_bounds_features(history); target = ((a* - theta_N)/w,
+// (b* - theta_N)/w, m*) with a* = theta[N-1] (the projection of this
+// operator on the current subspace), b* the upper bound of a k-step Lanczos
+// run from v0, m* = chebfilter_degree_rule(theta_1, theta_Nw, a*, b*, 100,
+// m_min, m_max), and theta_N, w = b - theta_N of the history's last step.
+cf_status chebfilter_bounds_label(cf_ctx *c, const double *history, int32_t steps,
+                                  const double *theta, int32_t N, int32_t wanted,
+                                  const double *v0, int32_t k, int32_t m_min, int32_t m_max,
+                                  double *input, double *target) {
+  if (!c) return CF_EINVAL;
+  if (!history || !theta || !v0 || !input || !target || steps < 1 || wanted < 1 || wanted > N)
+    return set_err(c, CF_EINVAL, "bounds_label: bad argument");
+  STCHK(chebfilter_bounds_features(history, steps, input) == CF_OK
+            ? CF_OK : set_err(c, CF_EINVAL, "bounds_label: history not usable"));
+  double lo = 0.0, bstar = 0.0;
+  STCHK(chebfilter_lanczos_bounds(c, v0, k, &lo, &bstar));
+  const double *last = history + 8 * (steps - 1);
+  const double thN = last[2], w = last[3] - last[2];
+  const double astar = theta[N - 1];
+  int32_t mstar = 0;
+  if (chebfilter_degree_rule(theta[0], theta[wanted - 1], astar, bstar, 100.0, m_min, m_max,
+                             &mstar) != CF_OK)
+    return set_err(c, CF_EINVAL, "bounds_label: degree rule");
+  target[0] = (astar - thN) / w;
+  target[1] = (bstar - thN) / w;
+  target[2] = (double)mstar;
+  return CF_OK;
+}
+
 cf_status chebfilter_bounds_predict(cf_ctx *c, cf_mlp *mlp, const double *history, const double *v0,
                                     int32_t lanczos_k, int32_t m_min, int32_t m_max, double *a,
                                     double *b, int32_t *m, int32_t *fallback) {

@@ -355,6 +355,60 @@ cf_status chebfilter_mlp_set_normalization(cf_mlp *m, const double *in_mean, con
   return CF_OK;
 }
 
+// Normalisation fitted to a corpus (count samples, row-major): per column the
+// mean and the standard deviation; a standard deviation below 1e-12 (1 + |mean|)
+// (a constant column) is replaced by 1.
+cf_status chebfilter_mlp_fit_normalization(cf_mlp *m, const double *inputs, const double *targets,
+                                           int64_t count) {
+  if (!m || !inputs || !targets || count < 1) return CF_EINVAL;
+  auto stats = [count](const double *x, int cols, std::vector<double> &mean, std::vector<double> &sd) {
+    mean.assign(cols, 0.0);
+    sd.assign(cols, 0.0);
+    for (int64_t r = 0; r < count; ++r)
+      for (int j = 0; j < cols; ++j) mean[j] += x[r * cols + j];
+    for (int j = 0; j < cols; ++j) mean[j] /= (double)count;
+    for (int64_t r = 0; r < count; ++r)
+      for (int j = 0; j < cols; ++j) {
+        const double d = x[r * cols + j] - mean[j];
+        sd[j] += d * d;
+      }
+    for (int j = 0; j < cols; ++j) {
+      sd[j] = std::sqrt(sd[j] / (double)count);
+      if (!(sd[j] > 1e-12 * (1.0 + std::fabs(mean[j])))) sd[j] = 1.0;
+    }
+  };
+  std::vector<double> im, is, om, os;
+  stats(inputs, m->n_in, im, is);
+  stats(targets, m->n_out, om, os);
+  return chebfilter_mlp_set_normalization(m, im.data(), is.data(), om.data(), os.data());
+}
+
+// Normalised copies (FP32) of raw inputs (which = 0) or targets (which = 1),
+// [count][n_in or n_out], with the network's current normalisation.
+cf_status chebfilter_mlp_normalize(cf_mlp *m, int32_t which, const double *x, int64_t count,
+                                   float *out) {
+  if (!m || !x || !out || count < 0 || (which != 0 && which != 1)) return CF_EINVAL;
+  if (m->norm.empty()) return merr(m, CF_EINVAL, "mlp_normalize: normalisation not set");
+  const int cols = which == 0 ? m->n_in : m->n_out;
+  const double *mean = m->norm.data() + (which == 0 ? 0 : 2 * m->n_in);
+  const double *sd = mean + cols;
+  for (int64_t r = 0; r < count; ++r)
+    for (int j = 0; j < cols; ++j) out[r * cols + j] = (float)((x[r * cols + j] - mean[j]) / sd[j]);
+  return CF_OK;
+}
+
+extern "C++" cf_status cf_mlp_predict_raw(cf_mlp *m, const double *x_raw, double *y_raw);
+
+// Raw outputs of raw inputs, sample by sample through the normalisation.
+cf_status chebfilter_mlp_predict(cf_mlp *m, const double *x_raw, int64_t count, double *y_raw) {
+  if (!m || !x_raw || !y_raw || count < 0) return CF_EINVAL;
+  for (int64_t r = 0; r < count; ++r) {
+    cf_status st = cf_mlp_predict_raw(m, x_raw + r * m->n_in, y_raw + r * m->n_out);
+    if (st != CF_OK) return st;
+  }
+  return CF_OK;
+}
+
 }  // extern "C"
 
 // Used by chebfilter_bounds_predict (cf_api.hip): raw inputs -> raw outputs

@@ -8,10 +8,11 @@ a = theta_N from the last projection, b an upper bound of the spectrum
 (Lanczos, Sec. V), m the degree.  The network maps the last 8 steps' spectrum
 summaries (8 numbers each) to (a, b, m); the guard falls back to Lanczos.
 
-Labels for training, per step: a* = theta_N of the projection of the step's
-operator, b* = the upper bound of a 40-step Lanczos run on it, and
-m* = degree_rule(theta_1, theta_Nw, a*, b*); the network inputs are the
-scale-free features of chebfilter_bounds_features and its outputs
+Labels for training, per step (chebfilter_bounds_label): a* = theta_N of the
+projection of the step's operator, b* = the upper bound of a 40-step Lanczos
+run on it, and m* = the library's degree rule at (theta_1, theta_Nw, a*, b*);
+the network inputs are the scale-free features of
+chebfilter_bounds_features and its outputs
 (alpha, beta, m) with a = theta_N + alpha w, b = theta_N + beta w, w the last
 step's b - theta_N, so one network serves clusters of different sizes.  Host code here only marshals arrays,
 keeps histories and normalisation constants; every operator application,
@@ -30,37 +31,17 @@ N_OUT = 3             # a, b, m
 WIDTH, DEPTH = 128, 3
 
 
-RANGE = 1e12          # largest amplification ratio the orthonormalisation resolves in FP64
-
-
-def degree_range_cap(theta_1: float, theta_w: float, a: float, b: float) -> float:
-    """Degree at which the filter amplifies theta_1 RANGE times more than
-    theta_w (beyond it the wanted directions near theta_w drown in the
-    rounding of the lowest ones): T_m(|t_1|)/T_m(|t_w|) ~ exp(m (acosh|t_1| -
-    acosh|t_w|))."""
-    t1 = abs((2.0 * theta_1 - a - b) / (b - a))
-    tw = abs((2.0 * theta_w - a - b) / (b - a))
-    g = np.arccosh(max(t1, 1.0)) - np.arccosh(max(tw, 1.0))
-    return np.inf if g <= 0.0 else np.log(RANGE) / g
-
-
 def degree_rule(theta_1: float, theta_w: float, a: float, b: float, rho: float = 100.0,
                 m_min: int = 8, m_max: int = 120) -> int:
-    """Smallest degree that amplifies the highest wanted Ritz value theta_w by
-    rho relative to the damped interval [a, b] (T_m(|t(theta_w)|) >= rho,
-    t(x) = (2x - a - b)/(b - a)), capped by degree_range_cap and clamped to
-    [m_min, m_max]."""
-    t = abs((2.0 * theta_w - a - b) / (b - a))
-    m = np.inf if t <= 1.0 else np.ceil(np.arccosh(rho) / np.arccosh(t))
-    m = min(m, np.floor(degree_range_cap(theta_1, theta_w, a, b)))
-    return int(min(max(m, m_min), m_max))
+    """The library's degree rule (chebfilter_degree_rule)."""
+    from .binding import degree_rule as lib_rule
+    return lib_rule(theta_1, theta_w, a, b, rho, m_min, m_max)
 
 
 def step_features(theta, theta_prev, wanted: int, b_used: float, m_used: int, res) -> np.ndarray:
-    r = np.asarray(res[:wanted])
-    d = float(np.abs(np.asarray(theta[:wanted]) - np.asarray(theta_prev[:wanted])).max())
-    return np.array([theta[0], theta[wanted - 1], theta[-1], b_used, float(m_used),
-                     float(r.max()), float(np.median(r)), d])
+    """The library's step summary (chebfilter_step_summary)."""
+    from .binding import step_summary
+    return step_summary(theta, theta_prev, wanted, b_used, m_used, res)
 
 
 def history_vector(feats: list) -> np.ndarray:
@@ -95,7 +76,7 @@ def run_sequence(ctx, prob, N: int, wanted: int, steps: int, seed: int, chooser,
     redone with it ("rescued").  Returns per-step records with the features,
     the bounds used, timings and (if label_k) the labels."""
     import torch
-    from .binding import ChebFilterError, bounds_features
+    from .binding import ChebFilterError
     from synth import configs, perturb
     dev = v0.device
     X = torch.tensor(configs.initial_block(prob, N, seed=seed) if X0 is None else X0,
@@ -114,14 +95,8 @@ def run_sequence(ctx, prob, N: int, wanted: int, steps: int, seed: int, chooser,
             feats.append(step_features(theta_cur, theta_cur, wanted, b0, 40, res))
         rec = {"step": s}
         if label_k:
-            _, bstar = ctx.lanczos_bounds(v0, label_k)
-            astar = float(theta_cur[-1])
-            hist = history_vector(feats)
-            thN, w = hist[-6], hist[-5] - hist[-6]        # last step's theta_N and b - theta_N
-            rec["input"] = bounds_features(hist)
-            rec["target"] = np.array([(astar - thN) / w, (bstar - thN) / w,
-                                      degree_rule(float(theta_cur[0]), float(theta_cur[wanted - 1]),
-                                                  astar, bstar)])
+            rec["input"], rec["target"] = ctx.bounds_label(history_vector(feats), theta_cur, wanted,
+                                                           v0, k=label_k)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         a, b, m, fb = chooser(s, feats, theta_cur)
@@ -170,24 +145,15 @@ def mlp_chooser(ctx, mlp, v0, k: int = 10):
     return choose
 
 
-def normalisation(inputs: np.ndarray, targets: np.ndarray):
-    im, isd = inputs.mean(axis=0), inputs.std(axis=0)
-    om, osd = targets.mean(axis=0), targets.std(axis=0)
-    isd = np.where(isd > 1e-12 * (1.0 + np.abs(im)), isd, 1.0)
-    osd = np.where(osd > 1e-12 * (1.0 + np.abs(om)), osd, 1.0)
-    return im, isd, om, osd
-
-
 def train(mlp, inputs: np.ndarray, targets: np.ndarray, steps: int = 2000, batch: int = 64,
           lr: float = 1e-3, seed: int = 0, log=None, lr_end: float | None = None):
     """Adam on minibatches of the normalised corpus, all arithmetic in the
     library's network kernels; with lr_end the step size follows a cosine
     from lr to lr_end.  Returns the loss per step."""
     import torch
-    im, isd, om, osd = normalisation(inputs, targets)
-    mlp.set_normalization(im, isd, om, osd)
-    Xn = torch.tensor((inputs - im) / isd, dtype=torch.float32, device=mlp.device)
-    Tn = torch.tensor((targets - om) / osd, dtype=torch.float32, device=mlp.device)
+    mlp.fit_normalization(inputs, targets)
+    Xn = mlp.normalize_inputs(inputs)
+    Tn = mlp.normalize_targets(targets)
     rng = np.random.default_rng(seed)
     S = Xn.shape[0]
     B = min(batch, S, mlp.max_batch)

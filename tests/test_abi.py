@@ -72,3 +72,28 @@ def test_bounds_features_transform():
     bad[-5] = bad[-6] - 1.0          # b below theta_N in the last step
     with pytest.raises(ChebFilterError):
         bounds_features(bad)
+
+
+def test_degree_rule_and_step_summary_host_arithmetic():
+    """The learned form's degree rule: the smallest m with T_m(|t(theta_w)|)
+    >= 100 (checked with the closed-form T_m), capped where the amplification
+    of theta_1 over theta_w reaches 1e12, clamped; the step summary's 8
+    numbers on a hand-made case."""
+    import numpy as np
+
+    from oracle.filters import chebyshev_T
+    from paper_1610_02121_amd.binding import degree_rule, step_summary
+    a, b = -0.4, 20.0
+    t = lambda x: abs((2.0 * x - a - b) / (b - a))          # noqa: E731
+    m = degree_rule(-0.45, -0.5, a, b, 100.0, 1, 10000)
+    assert chebyshev_T(m, np.array([t(-0.5)]))[0] >= 100.0
+    assert chebyshev_T(m - 1, np.array([t(-0.5)]))[0] < 100.0
+    # a deep theta_1: the 1e12 cap applies
+    mc = degree_rule(-60.0, -0.5, a, b, 100.0, 1, 10000)
+    ratio = chebyshev_T(mc, np.array([t(-60.0)]))[0] / chebyshev_T(mc, np.array([t(-0.5)]))[0]
+    ratio1 = chebyshev_T(mc + 1, np.array([t(-60.0)]))[0] / chebyshev_T(mc + 1, np.array([t(-0.5)]))[0]
+    assert mc < m and ratio <= 1.2e12 and ratio1 > 0.8e12
+    assert degree_rule(-0.45, -0.5, a, b, 100.0, 8, 20) == 20
+    out = step_summary(np.array([-1.0, -0.5, -0.4, 0.0]), np.array([-1.1, -0.5, -0.4, 0.0]), 2,
+                       20.0, 30, np.array([1e-3, 1e-5, 1.0, 1.0]))
+    assert np.allclose(out, [-1.0, -0.5, 0.0, 20.0, 30.0, 1e-3, 5.05e-4, 0.1])

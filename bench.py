@@ -210,6 +210,9 @@ def run_si280(args):
         prob = configs.config3(seed=args.seed, progress=log)
         if args.problem_cache:
             prob.save(args.problem_cache)
+    if args.gen_only:
+        log(f"generated and cached in {args.problem_cache}")
+        return
     log(f"generated n={prob.n} n_e={prob.n_e} cells={prob.n_cells} enriched cells="
         f"{prob.meta['quad']['enriched_cells']} coupling rows={len(prob.enr_idx)} in "
         f"{time.time() - t0:.0f}s")
@@ -835,6 +838,8 @@ def main():
                     help="load the generated workload from this .npz if it exists, else "
                          "generate it and save it there (profiling runs avoid the generator's "
                          "worker processes this way)")
+    ap.add_argument("--gen-only", action="store_true",
+                    help="generate the workload into --problem-cache and exit (no GPU work)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy an n x N FP64 block 5 times with the library's copy kernel "
                          "(a kernel of known traffic, to calibrate the HBM byte counters)")
@@ -894,6 +899,8 @@ def main():
         prob = make_problem(name, args.seed)
         if args.problem_cache:
             prob.save(args.problem_cache)
+    if args.gen_only:
+        return
     log(f"generated n={prob.n} n_h={prob.n_h} n_e={prob.n_e} cells={prob.n_cells} in "
         f"{time.time() - t0:.1f}s")
     dev = torch.device("cuda", 0)

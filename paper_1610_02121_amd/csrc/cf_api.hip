@@ -78,6 +78,7 @@ struct cf_ctx {
   double *Hec = nullptr, *Mec = nullptr;   // per-cell blocks, rows padded to NPAD
   int32_t *eidx = nullptr;
   int32_t *qptr = nullptr, *qidx = nullptr; // classical DOF -> rows of the cell buffer Q
+  int qmax = 0;                             // most cell-buffer rows of one DOF
   double *Q = nullptr;                      // [necells * NPAD][ldw]
   int64_t csr_nnz = 0, nreg = 0;
   double *Hee = nullptr, *Mee = nullptr, *Sinv = nullptr, *Hmod = nullptr;
@@ -224,6 +225,7 @@ static EpiArgs epi_base(cf_ctx *c, int N) {
   g.N = N;
   if (c->n_e > 0) {
     g.qptr = c->qptr;
+    g.qmax = c->qmax;
     g.qidx = c->qidx;
     g.Q = c->Q;
     g.ldq = c->ldw;
@@ -1070,6 +1072,7 @@ static cf_status do_init(const cf_problem *pr, const cf_options *opt, cf_ctx *c)
           const int32_t d = dof[(int64_t)elist[q] * NPAD + a];
           if (d >= 0) qptr[d + 1]++;
         }
+      for (int64_t d = 0; d < n_h; ++d) c->qmax = std::max(c->qmax, qptr[d + 1]);
       for (int64_t d = 0; d < n_h; ++d) qptr[d + 1] += qptr[d];
       std::vector<int32_t> qidx(std::max<int32_t>(qptr[n_h], 1));
       std::vector<int32_t> fill(qptr.begin(), qptr.end() - 1);

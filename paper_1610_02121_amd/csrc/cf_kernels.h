@@ -50,6 +50,7 @@ struct EpiArgs {
   double c3 = 0.0;
   double *Out = nullptr;
   int64_t ldo = 0;
+  int qmax = 0;                     // most buffer rows of one DOF (qptr ranges)
 };
 
 // ---- elemental operator kernels (cf_ops.hip)

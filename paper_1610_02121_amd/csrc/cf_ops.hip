@@ -762,12 +762,92 @@ __global__ __launch_bounds__(256) void k_epilogue(const EpiArgs g) {
   }
 }
 
+// The same epilogue with two columns per lane (16-byte loads and stores),
+// the buffer-row offsets of a DOF (at most EPI_QMAX) held in registers and
+// all loads of an element pair issued before its sums.  Used when every
+// block pointer is 16-byte aligned and every leading dimension even; the
+// arithmetic of each element is that of k_epilogue (same terms, same order).
+constexpr int EPI_QMAX = 8;
+
+__global__ __launch_bounds__(256) void k_epilogue_v2(const EpiArgs g) {
+  const int64_t ncls = g.rows ? g.nrows : g.n_h;
+  const int64_t nt = ncls + g.n_e;
+  for (int64_t t = (int64_t)blockIdx.x * 4 + threadIdx.y; t < nt; t += (int64_t)gridDim.x * 4) {
+    const bool cls = t < ncls;
+    const int64_t i = cls ? (g.rows ? (int64_t)g.rows[t] : t) : g.n_h + (t - ncls);
+    double dr = 1.0, dc = 1.0;
+    int nq = 0;
+    int64_t qo[EPI_QMAX];
+    if (cls) {
+      if (g.dR) dr = g.dR[i];
+      if (g.dC) dc = g.dC[i];
+      if (g.qptr) {
+        const int p0 = g.qptr[i];
+        nq = g.qptr[i + 1] - p0;
+#pragma unroll
+        for (int u = 0; u < EPI_QMAX; ++u) qo[u] = u < nq ? (int64_t)g.qidx[p0 + u] * g.ldq : 0;
+      }
+    }
+    const double *src = cls ? g.R + i * g.ldr : g.Ee + (i - g.n_h) * g.lde;
+    for (int j = 2 * threadIdx.x; j < g.N; j += 128) {
+      if (j + 1 < g.N) {
+        const double2 r = *reinterpret_cast<const double2 *>(src + j);
+        double2 q[EPI_QMAX];
+#pragma unroll
+        for (int u = 0; u < EPI_QMAX; ++u)
+          q[u] = u < nq ? *reinterpret_cast<const double2 *>(g.Q + qo[u] + j) : double2{0.0, 0.0};
+        const double2 yk = g.Yk ? *reinterpret_cast<const double2 *>(g.Yk + i * g.ldyk + j)
+                                : double2{0.0, 0.0};
+        const double2 yp = g.Yp ? *reinterpret_cast<const double2 *>(g.Yp + i * g.ldyp + j)
+                                : double2{0.0, 0.0};
+        double v0 = cls ? dr * r.x : r.x, v1 = cls ? dr * r.y : r.y;
+        if (nq > 0) {
+          double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+          for (int u = 0; u < EPI_QMAX; ++u)
+            if (u < nq) { s0 += q[u].x; s1 += q[u].y; }
+          v0 += dc * s0;
+          v1 += dc * s1;
+        }
+        v0 *= g.c1;
+        v1 *= g.c1;
+        if (g.Yk) { v0 += g.c2 * yk.x; v1 += g.c2 * yk.y; }
+        if (g.Yp) { v0 += g.c3 * yp.x; v1 += g.c3 * yp.y; }
+        *reinterpret_cast<double2 *>(g.Out + i * g.ldo + j) = double2{v0, v1};
+      } else {
+        double v = cls ? dr * src[j] : src[j];
+        if (nq > 0) {
+          double sq = 0.0;
+#pragma unroll
+          for (int u = 0; u < EPI_QMAX; ++u)
+            if (u < nq) sq += g.Q[qo[u] + j];
+          v += dc * sq;
+        }
+        v *= g.c1;
+        if (g.Yk) v += g.c2 * g.Yk[i * g.ldyk + j];
+        if (g.Yp) v += g.c3 * g.Yp[i * g.ldyp + j];
+        g.Out[i * g.ldo + j] = v;
+      }
+    }
+  }
+}
+
+static bool al16(const void *p, int64_t ld) {
+  return p == nullptr || (((uintptr_t)p & 15) == 0 && (ld & 1) == 0);
+}
+
 hipError_t launch_epilogue(hipStream_t s, const EpiArgs &g) {
   const int64_t n = (g.rows ? g.nrows : g.n_h) + g.n_e;
   if (n <= 0 || g.N <= 0) return hipSuccess;
   int64_t blocks = g.N < EPI_FEW_COLS ? (n * g.N + 255) / 256 : (n + 3) / 4;
   if (blocks > 65536) blocks = 65536;
-  hipLaunchKernelGGL(k_epilogue, dim3((unsigned)blocks), dim3(64, 4), 0, s, g);
+  const bool v2 = g.N >= EPI_FEW_COLS && g.qmax <= EPI_QMAX && al16(g.R, g.ldr) &&
+                  al16(g.Q, g.ldq) && al16(g.Ee, g.lde) && al16(g.Yk, g.ldyk) &&
+                  al16(g.Yp, g.ldyp) && al16(g.Out, g.ldo);
+  if (v2)
+    hipLaunchKernelGGL(k_epilogue_v2, dim3((unsigned)blocks), dim3(64, 4), 0, s, g);
+  else
+    hipLaunchKernelGGL(k_epilogue, dim3((unsigned)blocks), dim3(64, 4), 0, s, g);
   return hipGetLastError();
 }
 

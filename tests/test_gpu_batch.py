@@ -189,16 +189,20 @@ def test_batch_rayleigh_ritz_redo_and_failure(tiny_enriched, hydrogen_small, si_
 def test_batch_autotune_keeps_results(tiny_enriched, hydrogen_small, si_small):
     """The batched autotuner (tile shape of the batched reduced cell product,
     graph rebuilt on a change) returns one of the two shapes, and the batched
-    BF16 filter after it equals the one before it bit for bit."""
+    BF16 filter after it (with the coupling map it also tunes put back)
+    equals the one before it bit for bit."""
     print("[batch autotune]", flush=True)
     batch, probs, singles, Ns, ab = state(tiny_enriched, hydrogen_small, si_small)
     m = 4
     Xd = [dev(x) for x in blocks(probs, Ns, 95)]
     a, b = [x for x, _ in ab], [y for _, y in ab]
     before = [host(y) for y in batch.filter(Xd, m, a, b, prec="bf16")]
+    default_map = batch.tuning()["coupling_map"]
     ch = batch.autotune(Xd, m, a, b, prec="bf16", reps=1)
-    print(f"  autotuner chose {ch} block(s) per tile", flush=True)
+    print(f"  autotuner chose {ch} block(s) per tile, coupling map "
+          f"{batch.tuning()['coupling_map']:08b}", flush=True)
     assert ch in (1, 2)
+    batch.tuning(default_map)
     after = [host(y) for y in batch.filter(Xd, m, a, b, prec="bf16")]
     for i in range(len(probs)):
         assert np.array_equal(before[i], after[i]), i

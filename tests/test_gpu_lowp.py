@@ -316,7 +316,8 @@ def test_cell_tile_shapes_agree_and_autotune(si_small):
     """The reduced cell product's tile shape (one or two 16-column MFMA blocks
     per column tile) is a launch parameter: both shapes give bit-identical
     filters (37 columns: a ragged second block), and the autotuner returns one
-    of them without changing the results."""
+    of them; with the coupling map it also tunes put back to the default, the
+    results are the same bits."""
     from paper_1610_02121_amd import ChebFilterError, Context
     print("[cell tile shapes]", flush=True)
     prob = si_small
@@ -331,9 +332,12 @@ def test_cell_tile_shapes_agree_and_autotune(si_small):
             ctx.set_cell_tile(prec, nsb)
             outs.append(host(ctx.filter(X, 6, a, b, prec=prec)))
         assert np.array_equal(outs[0], outs[1]), prec
+        default_map = ctx.tuning()["coupling_map"]
         ch = ctx.autotune(X, 6, a, b, prec=prec, reps=2)
-        print(f"  {prec}: autotuner chose {ch} block(s) per tile", flush=True)
+        print(f"  {prec}: autotuner chose {ch} block(s) per tile, coupling map "
+              f"{ctx.tuning()['coupling_map']:08b}", flush=True)
         assert ch in (1, 2)
+        ctx.tuning(default_map)
         assert np.array_equal(host(ctx.filter(X, 6, a, b, prec=prec)), outs[0]), prec
     with pytest.raises(ChebFilterError, match="CF_EINVAL"):
         ctx.set_cell_tile("fp64", 1)

@@ -376,3 +376,23 @@ def test_column_chunks_equal_whole_blocks(si_small):
     th = np.linspace(-1.0, 3.0, 200)
     assert np.array_equal(whole.residual_norms(X, th), ch.residual_norms(X, th))
 
+
+
+def test_epilogue_paths_agree(si_small):
+    """The epilogue's two-columns-per-lane path (aligned blocks, even leading
+    dimensions) and its element path (here forced by an odd leading
+    dimension) compute each element the same way: filters, H X, M X and
+    (M^E)^-1 X agree bit for bit."""
+    ctx, ops = context("si_small", si_small, max_cols=96)
+    X = np.random.default_rng(35).standard_normal((ops.n, 40))
+    Xe = dev(X)
+    W = torch.zeros((ops.n, 41), dtype=torch.float64, device="cuda")
+    W[:, :40] = Xe
+    Xo = W[:, :40]
+    assert Xo.stride(0) == 41
+    for name, f in (("H", ctx.apply_H), ("M", ctx.apply_M), ("Sinv", ctx.apply_Sinv),
+                    ("filter", lambda Z, Y=None: ctx.filter(Z, 5, -2.0, 60.0, Y=Y))):
+        a = f(Xe)
+        Yo = torch.zeros((ops.n, 41), dtype=torch.float64, device="cuda")[:, :40]
+        b = f(Xo, Y=Yo)
+        assert torch.equal(a, b), name

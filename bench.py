@@ -521,6 +521,9 @@ def run_batch(args):
         f"{max(p.n for p in pool.values())}) in {time.time() - t0:.0f}s; 256 entries, "
         f"sum n*N = {sum(pool[a].n * N for a, N in zip(atoms, Ns))}")
     groups = batch_groups(pool, atoms, Ns)
+    # the group with the most work first: the autotuner runs on it, the other
+    # groups take its coupling map
+    groups.sort(key=lambda g: -sum(pool[atoms[i]].n * Ns[i] for i in g))
     log(f"{len(groups)} groups of {[len(g) for g in groups]} entries")
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
@@ -539,8 +542,14 @@ def run_batch(args):
                            dtype=torch.float64, device=dev) for i, p in zip(g, probs)]
         theta = batch.rayleigh_ritz(X)
         _, b0 = batch.lanczos_bounds(v0, 10)
-        tiles.append(batch.autotune(X, m, [float(th[-1]) for th in theta], b0, prec=prec, reps=1,
-                                    Y=Y))
+        if gi == 0:
+            tiles.append(batch.autotune(X, m, [float(th[-1]) for th in theta], b0, prec=prec,
+                                        reps=1, Y=Y))
+            cmap = batch.tuning()["coupling_map"]
+            log(f"autotuned on group 1: {tiles[-1]} column block(s) per tile, coupling map "
+                f"{cmap:08b}")
+        else:
+            batch.tuning(cmap)
         st = {"X": X, "Y": Y, "theta": theta}
 
         def step(timed):
@@ -617,7 +626,7 @@ def run_batch(args):
                    "vectors": f"{min(Ns)}-{max(Ns)}", "cheb_degree": m,
                    "sum_n_times_N": work // m, "groups": [len(g) for g in groups],
                    "precision": f"{prec} filter, fp64 Schur solve and Rayleigh-Ritz",
-                   "cell_tile_blocks_autotuned_per_group": tiles},
+                   "cell_tile_blocks_autotuned": tiles[0], "coupling_map_autotuned": cmap},
         "phases_ms": {"bounds": 1e3 * tot["bounds"], "filter": 1e3 * tot["filter"],
                       "cholqr_rr": 1e3 * tot["rr"]},
         "filter_only_ms": {"batched_graph": 1e3 * tot["graph"],

@@ -516,7 +516,7 @@ def run_batch(args):
     prec = "fp32" if args.prec == "fp64" else args.prec
     t0 = time.time()
     log("generating the batch pool (Si clusters of 1-40 atoms)")
-    pool, atoms, Ns = configs.batch_workload(256, seed=args.seed)
+    pool, atoms, Ns = configs.batch_workload(256, seed=args.seed, progress=log)
     log(f"pool of {len(pool)} problems (n = {min(p.n for p in pool.values())} .. "
         f"{max(p.n for p in pool.values())}) in {time.time() - t0:.0f}s; 256 entries, "
         f"sum n*N = {sum(pool[a].n * N for a, N in zip(atoms, Ns))}")

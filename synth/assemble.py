@@ -163,7 +163,7 @@ def _enriched_chunk(cells):
     p, h, K = _W["p"], _W["h"], _W["K"]
     lo_all, cell_atoms, enr_ptr, enr_idx = _W["lo_all"], _W["cell_atoms"], _W["enr_ptr"], _W["enr_idx"]
     n_e, tau = _W["n_e"], _W["tau"]
-    Hcc, Hec, Mec = [], [], []
+    Hcc, Hec, Mec, boxes = [], [], [], []
     # the chunk's partial H_ee / M_ee on the enrichment indices it touches
     # (the other entries of the partial are zero)
     used = np.unique(np.concatenate([enr_idx[enr_ptr[e]:enr_ptr[e + 1]] for e in cells]))
@@ -176,8 +176,10 @@ def _enriched_chunk(cells):
         for e in cells:
             lo = lo_all[e]
             atoms = cell_atoms[e]
-            pts, w, leaves = adaptive_rule(lo, h, lambda x: _trial(x, atoms), tau,
-                                           ng=_W["ng"], max_depth=_W["max_depth"])
+            pts, w, leaves, blo, bsz = adaptive_rule(lo, h, lambda x: _trial(x, atoms), tau,
+                                                     ng=_W["ng"], max_depth=_W["max_depth"],
+                                                     boxes=True)
+            boxes.append((blo, bsz))
             stats += (leaves, w.size, 0)
             stats[2] = max(stats[2], leaves)
             N, G = shape_at(p, h, lo, pts, need_grad=True)
@@ -199,7 +201,7 @@ def _enriched_chunk(cells):
             kin_ee = 0.5 * sum(EgwT[d] @ Egd[d] for d in range(3))
             Hee[np.ix_(idx, idx)] += kin_ee + (Ev * wV[:, None]).T @ Ev
             Mee[np.ix_(idx, idx)] += EwT @ Ev
-    return Hcc, Hec, Mec, (used, Hee), (used, Mee), stats
+    return Hcc, Hec, Mec, (used, Hee), (used, Mee), stats, boxes
 
 
 def gpu_initialised() -> bool:
@@ -284,6 +286,9 @@ def assemble(mesh: Mesh, potential, enr: EnrichmentSet | None, ng: int = 6,
     H_ee = np.zeros((n_e, n_e))
     M_ee = np.zeros((n_e, n_e))
 
+    # leaf boxes of every cell with its own adaptive rule (Sec. IV.C)
+    cell_boxes: dict = {}
+
     # ---- cells without enrichment: plain Gauss rule, batched
     ref, wref = unit_cube_rule(ng)
     Bref, _ = shape_at(p, 2.0, np.array([-1.0, -1.0, -1.0]), 2.0 * ref - 1.0, need_grad=False)
@@ -302,7 +307,9 @@ def assemble(mesh: Mesh, potential, enr: EnrichmentSet | None, ng: int = 6,
                      for e in sing)
             tauV = np.array([max(tol_abs, tol_rel * SV)])
             for e in sing:
-                pts, w, _ = adaptive_rule(lo_all[e], h, fV, tauV, ng=ng, max_depth=max_depth)
+                pts, w, _, blo, bsz = adaptive_rule(lo_all[e], h, fV, tauV, ng=ng,
+                                                    max_depth=max_depth, boxes=True)
+                cell_boxes[e] = (blo, bsz)
                 Nq, _ = shape_at(p, h, lo_all[e], pts, need_grad=False)
                 H_cc[e] = K + (Nq.T * (w * potential(pts))[None, :]) @ Nq
     if not plain_blocks:
@@ -339,11 +346,12 @@ def assemble(mesh: Mesh, potential, enr: EnrichmentSet | None, ng: int = 6,
             _W["tau"] = np.maximum(tol_abs, tol_rel * S)
             results = (_enriched_chunk(c) for c in chunks)
         t_last = time.time()
-        for k, (cells, (hcc, hec, mec, hee, mee, st)) in enumerate(zip(chunks, results)):
+        for k, (cells, (hcc, hec, mec, hee, mee, st, bx)) in enumerate(zip(chunks, results)):
             if progress and time.time() - t_last > 30.0:
                 progress(f"enriched cells: chunk {k + 1}/{len(chunks)} ({time.time() - t1:.0f}s)")
                 t_last = time.time()
             for i, e in enumerate(cells):
+                cell_boxes[e] = bx[i]
                 H_cc[e] = hcc[i]
                 H_ec[enr_ptr[e]:enr_ptr[e + 1]] = hec[i]
                 M_ec[enr_ptr[e]:enr_ptr[e + 1]] = mec[i]
@@ -368,7 +376,20 @@ def assemble(mesh: Mesh, potential, enr: EnrichmentSet | None, ng: int = 6,
     stats.update(t_plain=t1 - t0, t_enriched=t2 - t1)
     if verbose:
         print(f"[assemble] E={E} n_h={mesh.n_h} n_e={n_e} nnz={nnz} {stats}", flush=True)
+    # the leaf boxes as one list (cell by cell, in cell order): cell e owns
+    # boxes box_ptr[e] .. box_ptr[e+1]; each box carries the ng^3 Gauss rule
+    counts_b = np.zeros(E, dtype=np.int64)
+    for e, (blo, _) in cell_boxes.items():
+        counts_b[e] = blo.shape[0]
+    box_ptr = np.zeros(E + 1, dtype=np.int64)
+    box_ptr[1:] = np.cumsum(counts_b)
+    box_lo = np.zeros((int(box_ptr[-1]), 3))
+    box_size = np.zeros(int(box_ptr[-1]))
+    for e, (blo, bsz) in cell_boxes.items():
+        box_lo[box_ptr[e]:box_ptr[e + 1]] = blo
+        box_size[box_ptr[e]:box_ptr[e + 1]] = bsz
     meta = {"h": h, "nc": mesh.nc, "lo": mesh.lo, "length": mesh.length, "quad": stats,
-            "plain_blocks": plain_blocks}
+            "plain_blocks": plain_blocks,
+            "quad_boxes": {"ng": ng, "box_ptr": box_ptr, "box_lo": box_lo, "box_size": box_size}}
     return Problem(p=p, cell_dof=mesh.cell_dof, H_cc=H_cc, M_cc_diag=D, enr_ptr=enr_ptr,
                    enr_idx=enr_idx, H_ec=H_ec, M_ec=M_ec, H_ee=H_ee, M_ee=M_ee, meta=meta)

@@ -206,16 +206,24 @@ def batch_vectors(n_atoms: int) -> int:
     return 16 + round(334 * (n_atoms - 1) / 39)
 
 
-def batch_workload(count: int = 256, seed: int = 0, max_atoms: int = 40, **kw):
+def batch_workload(count: int = 256, seed: int = 0, max_atoms: int = 40, progress=None, **kw):
     """Batched workload: `count` entries with atom counts drawn U{1..max_atoms}
     (seeded), batch_vectors(n_atoms) vectors each, filter degree 40.  The
     entries of one atom count share one generated problem (the pool), so the
     batch holds at most max_atoms distinct operators and `count` independent
     blocks and intervals.  Returns (pool dict n_atoms -> Problem, list of
-    n_atoms per entry, list of N per entry)."""
+    n_atoms per entry, list of N per entry).  progress(msg), if given, is
+    called after each generated problem."""
+    import time
     rng = np.random.default_rng(seed)
     atoms = [int(a) for a in rng.integers(1, max_atoms + 1, size=count)]
-    pool = {a: batch_cluster(a, seed, **kw) for a in sorted(set(atoms))}
+    pool = {}
+    for a in sorted(set(atoms)):
+        t0 = time.time()
+        pool[a] = batch_cluster(a, seed, **kw)
+        if progress:
+            progress(f"pool problem {len(pool)}: {a} atoms, n = {pool[a].n}, "
+                     f"{time.time() - t0:.1f}s")
     Ns = [batch_vectors(a) for a in atoms]
     return pool, atoms, Ns
 

@@ -35,6 +35,18 @@ class Radial:
     zeta: float = 1.0
     l: int = 0
 
+    def terms(self) -> list[tuple[float, int, float]]:
+        """R(r) as a sum of Slater-type terms c r^k exp(-zeta r): [(c, k, zeta)]."""
+        if self.kind == "h1s":
+            return [(2.0, 0, 1.0)]
+        if self.kind == "h2s":
+            c = 1.0 / (2.0 * sqrt(2.0))
+            return [(2.0 * c, 0, 0.5), (-c, 1, 0.5)]
+        if self.kind == "slater":
+            n, z = self.n, self.zeta
+            return [(sqrt((2.0 * z) ** (2 * n + 1) / factorial(2 * n)), n - 1, z)]
+        raise ValueError(self.kind)
+
     def eval(self, r: np.ndarray) -> tuple[np.ndarray, np.ndarray]:
         if self.kind == "h1s":          # hydrogen 1s: 2 e^{-r}
             e = np.exp(-r)
@@ -105,6 +117,10 @@ class EnrichmentSet:
     @property
     def n_e(self) -> int:
         return self.n_atoms * self.n_per_atom
+
+    def shell_terms(self) -> list[tuple[int, list]]:
+        """[(l, [(c, k, zeta), ...])] per shell: the radial as Slater-type terms."""
+        return [(s.l, s.terms()) for s in self.shells]
 
     def func_table(self) -> list[tuple[int, int, int]]:
         """(atom, shell index, m-component) per alpha, in alpha order."""

@@ -30,20 +30,23 @@ def unit_cube_rule(ng: int) -> tuple[np.ndarray, np.ndarray]:
 
 
 def adaptive_rule(lo: np.ndarray, size: float, trial, tau: np.ndarray, ng: int = 6,
-                  max_depth: int = 10) -> tuple[np.ndarray, np.ndarray, int]:
+                  max_depth: int = 10, boxes: bool = False):
     """Adaptive points/weights for the box [lo, lo+size]^3.
 
     `trial(points[Q,3]) -> values[Q, nt]` evaluates the trial functions and
     `tau[nt]` is the fixed tolerance of each one (Sec. IV.C): a box is
     accepted when |I_parent - sum I_children| < tau for every trial function,
-    or at depth `max_depth`.  Returns (points [Q,3], weights [Q], leaf count).
+    or at depth `max_depth`.  Returns (points [Q,3], weights [Q], leaf count)
+    and, with boxes=True, also the accepted boxes (lower corners [L,3], sides
+    [L]) in the order of their points (each box's ng^3 points consecutive,
+    x fastest).
     """
     ref, wref = unit_cube_rule(ng)
     nq = ref.shape[0]
     tau = np.asarray(tau, dtype=np.float64)
     f_lo = np.asarray(lo, dtype=np.float64)[None, :]
     f_sz = np.array([float(size)])
-    out_p, out_w = [], []
+    out_p, out_w, out_lo, out_sz = [], [], [], []
     leaves = 0
     depth = 0
     while f_lo.shape[0]:
@@ -62,9 +65,14 @@ def adaptive_rule(lo: np.ndarray, size: float, trial, tau: np.ndarray, ng: int =
         if ok.any():
             out_p.append(par[ok].reshape(-1, 3))
             out_w.append((np.outer(f_sz[ok] ** 3, wref)).ravel())
+            out_lo.append(f_lo[ok])
+            out_sz.append(f_sz[ok])
             leaves += int(ok.sum())
         bad = ~ok
         f_lo = clo[bad].reshape(-1, 3)
         f_sz = np.repeat(half[bad], 8)
         depth += 1
+    if boxes:
+        return (np.concatenate(out_p), np.concatenate(out_w), leaves, np.concatenate(out_lo),
+                np.concatenate(out_sz))
     return np.concatenate(out_p), np.concatenate(out_w), leaves

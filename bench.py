@@ -181,6 +181,67 @@ def assembly_timing(ctx, prob, reps=5):
             "hbm_write_gb": len(cells) * 128 * 128 * 8 / 1e9}
 
 
+def enriched_assembly_timing(ctx, prob, reps=3):
+    """The blocks of the cells with an adaptive rule (every enriched cell) on
+    the device: H^cc_e, H^ec and H^ee from the potential at the generator's
+    leaf-box grid (Sec. IV.C), then the rebuilt H^ee - M^ec D^-1 H^ec^T.
+    Kernel times from HIP events; compared with the generator's host time
+    for the same cells (numpy on its worker processes)."""
+    import numpy as np
+    import torch
+    from synth.basis import gll_rule
+    from synth.assemble import plain_tables
+    qb, mesh, enr = prob.meta["quad_boxes"], prob.meta["mesh"], prob.meta["enr"]
+    bp = np.asarray(qb["box_ptr"])
+    cells = np.nonzero(bp[1:] > bp[:-1])[0].astype(np.int32)
+    x, w = np.polynomial.legendre.leggauss(qb["ng"])
+    gx, gw = 0.5 * (x + 1.0), 0.5 * w
+    B, wq, K, _ = plain_tables(prob)
+    ctx.assembly_tables(B, wq, K)
+    ctx.enriched_tables(cells=cells, cell_lo=mesh.cell_lo()[cells], h=mesh.h,
+                        nodes=0.5 * (gll_rule(mesh.p)[0] + 1.0), gauss_x=gx, gauss_w=gw,
+                        box_ptr=np.concatenate([bp[cells], [bp[-1]]]), box_lo=qb["box_lo"],
+                        box_size=qb["box_size"], centers=enr.centers, shells=enr.shell_terms(),
+                        r0=enr.r0, t=enr.t)
+    ng3 = len(gx) ** 3
+    lo, sz = np.asarray(qb["box_lo"]), np.asarray(qb["box_size"])
+    zz, yy, xx = np.meshgrid(gx, gx, gx, indexing="ij")
+    ref = np.stack([xx.ravel(), yy.ravel(), zz.ravel()], axis=1)
+    V = np.empty(lo.shape[0] * ng3)
+    for s in range(0, lo.shape[0], 20000):          # points box by box, bounded temporaries
+        pts = lo[s:s + 20000, None, :] + sz[s:s + 20000, None, None] * ref[None]
+        V[s * ng3:(s + pts.shape[0]) * ng3] = prob.meta["potential"](pts.reshape(-1, 3))
+    Vd = torch.tensor(V, dtype=torch.float64, device=ctx.device)
+    ctx.assemble_enriched(Vd)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctx.assemble_enriched(Vd)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / reps
+    la, ms_a, _ = ctx.profile_query("assemble_adaptive")
+    lh, ms_h, _ = ctx.profile_query("rebuild_hmod")
+    ctx.profile(False)
+    ep = np.asarray(prob.enr_ptr)
+    nq = np.diff(np.concatenate([bp[cells], [bp[-1]]])) * ng3
+    na = ep[cells + 1] - ep[cells]
+    nte = (na + 15) // 16
+    # MFMA tile products: 36 upper 16 x 16 tiles of H^cc_e (one product per
+    # point), 8 nte + nte (nte + 1) / 2 enrichment-row tiles (four per point)
+    flops = float(np.sum(2.0 * 256 * nq * (36 + 4 * (8 * nte + nte * (nte + 1) // 2))))
+    kern = (ms_a / max(la, 1))
+    quad = prob.meta.get("quad", {})
+    return {"cells": int(len(cells)), "enriched_cells": int((na > 0).sum()), "points": int(V.size),
+            "boxes": int(lo.shape[0]), "blocks_ms": kern,
+            "rebuild_hmod_ms": ms_h / max(lh, 1), "total_ms": 1e3 * wall,
+            "tflops_blocks": flops / (kern / 1e3) / 1e12,
+            "flops_credited": "2*256*nq per 16x16 tile and point term (36 H^cc tiles; "
+                              "4 terms for each H^ec / upper H^ee tile)",
+            "host_generator_s": quad.get("t_enriched"),
+            "host_generator_workers": "forked numpy workers, one per host core (<= 16)"}
+
+
 def run_si280(args):
     """The 280-atom precision-form workload at its full shape on one GPU: the
     whole operator (the plain cells' potential term assembled on the device),
@@ -1045,6 +1106,9 @@ def main():
     if not args.no_assembly and "potential" in prob.meta and "mesh" in prob.meta:
         log("timing the device assembly of the plain cells' blocks")
         out["plain_cell_assembly"] = assembly_timing(ctx, prob)
+        if "quad_boxes" in prob.meta and prob.n_e:
+            log("timing the device assembly of the enriched cells' blocks")
+            out["enriched_cell_assembly"] = enriched_assembly_timing(ctx, prob)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(prob, N, m, args.seed)

@@ -351,6 +351,78 @@ cf_status chebfilter_assemble_cells(cf_ctx *ctx, const int32_t *cells, int64_t n
  * [ncells][npc][npc]).  Synchronises. */
 cf_status chebfilter_get_H_cc(cf_ctx *ctx, const int32_t *cells, int64_t ncells, double *out);
 
+/* ---- Element blocks of the cells with an adaptive rule, on the device ------- */
+
+/* The adaptive quadrature grid of Sec. IV.C and the enrichment functions of
+ * Sec. IV.A-B, for chebfilter_assemble_enriched.  The grid of a cell is the list
+ * of boxes that the divide-and-conquer refinement accepted; each box carries
+ * the tensor ng^3 Gauss rule (points box_lo + box_size (x_i, x_j, x_k), i
+ * fastest; weights box_size^3 w_i w_j w_k).  The grid is fixed for a mesh; only
+ * the potential at its points changes from one self-consistent step to the
+ * next.  Enrichment function alpha = I * n_per_atom + m belongs to atom I:
+ * a radial part R(r) = sum of c r^k exp(-zeta r) over the shell's terms, times
+ * a real harmonic (l = 0: 1/sqrt(4 pi); l = 1: sqrt(3/(4 pi)) (y, z, x)/r, in
+ * that order), times the smooth cutoff h of Eq. Moll1 with
+ * r~ = 1 - t (r - r0) / r0.  n_per_atom = sum over shells of 2l + 1.  Every
+ * cell's enrichment list (cf_problem.enr_idx) must consist of whole atoms,
+ * ascending.  All arrays are host arrays, copied. */
+typedef struct {
+  int64_t ncells;             /* listed cells: every cell with enrichment functions, plus any
+                               * plain cell whose block needs the adaptive rule             */
+  const int32_t *cells;       /* [ncells] distinct cell indices                              */
+  const double *cell_lo;      /* [ncells][3] lower corner of each listed cell                */
+  double h;                   /* cell side                                                   */
+  int32_t n_nodes;            /* 1D nodes per axis (p + 1), n_nodes^3 = nodes per cell, <= 8  */
+  const double *nodes;        /* [n_nodes] increasing, on [0, 1]; local node a = i + n j + n^2 k */
+  int32_t ng;                 /* Gauss points per axis in a box, 1..8                        */
+  const double *gauss_x;      /* [ng] in (0, 1)                                              */
+  const double *gauss_w;      /* [ng] summing to 1                                           */
+  const int64_t *box_ptr;     /* [ncells + 1], box_ptr[0] = 0: boxes of cells[i]              */
+  const double *box_lo;       /* [nbox][3] lower corners (inside the cell)                   */
+  const double *box_size;     /* [nbox] sides                                                */
+  int32_t n_atoms;            /* n_atoms * n_per_atom = n_e                                  */
+  const double *centers;      /* [n_atoms][3]                                                */
+  int32_t n_shells;           /* shells per atom, the same for every atom                    */
+  const int32_t *shell_l;     /* [n_shells] 0 or 1                                           */
+  const int32_t *shell_term_ptr; /* [n_shells + 1], [0] = 0: terms of each shell            */
+  const double *term_c;       /* [nterm] coefficients                                        */
+  const int32_t *term_k;      /* [nterm] powers of r, l <= k <= 16                           */
+  const double *term_zeta;    /* [nterm] exponents >= 0                                      */
+  double r0, t;               /* cutoff radius and transition width (Eq. Moll1), > 0         */
+} cf_adaptive_grid;
+
+/* Upload the grid and the enrichment description (validated; CF_EINVAL with a
+ * message on any violation above, on a missing kinetic block: call
+ * chebfilter_assembly_tables first, or when a cell with enrichment functions
+ * is not listed).  The partial H^ee blocks of the assembly are summed in fixed
+ * batches of cells (at most 512 MiB of partials each), decided here.
+ * Synchronises. */
+cf_status chebfilter_enriched_tables(cf_ctx *ctx, const cf_adaptive_grid *grid);
+
+/* Number of points of the uploaded grid (sum over boxes of ng^3): the length
+ * of the potential array of chebfilter_assemble_enriched. */
+cf_status chebfilter_adaptive_points(const cf_ctx *ctx, int64_t *npoints);
+
+/* Recompute, on the device, the Hamiltonian blocks that the potential enters
+ * on the listed cells (Eq. HBlocks with the adaptive rule, Sec. IV.C):
+ *   H^cc_e = K + sum_q w_q V_q N_a N_b                       (every listed cell)
+ *   H^ec_e = sum_q w_q (V_q N_al N_a + 1/2 grad N_al . grad N_a)
+ *   H^ee   = sum over cells of sum_q w_q (V_q N_al N_be + 1/2 grad N_al . grad N_be)
+ * with K the kinetic block of chebfilter_assembly_tables and V (device FP64,
+ * [npoints]) the potential at the grid's points, box by box.  The quadrature
+ * sums run as FP64 MFMA contractions; H^cc_e and H^ee are written exactly
+ * symmetric; H^ee sums the cells in a fixed order (no atomics).  Then the
+ * enrichment block of the block-wise inverse's step, H^ee - M^ec D^-1 H^ec^T
+ * (Sec. IV.D), is rebuilt from the new blocks and the reduced-precision copies
+ * are refreshed.  M^ec, M^ee, D and the Schur complement do not depend on the
+ * potential and are unchanged.  Enqueued on the context's stream; uses the
+ * context's work blocks.  CF_EINVAL without a grid or with a null V. */
+cf_status chebfilter_assemble_enriched(cf_ctx *ctx, const double *V);
+
+/* Copy the current H^ec (host, [nnz][npc] in cf_problem.H_ec's layout) and
+ * H^ee (host, [n_e][n_e]); either may be null.  Synchronises. */
+cf_status chebfilter_get_coupling(cf_ctx *ctx, double *H_ec, double *H_ee);
+
 /* res_host[j] = || H^E z_j - theta_j M^E z_j ||_{(M^E)^-1} for the columns z_j of
  * Z with theta_host[j] (the Ritz residual in the dual norm of Sec. V's
  * generalized problem).  Uses the context's work blocks; synchronises. */

@@ -181,8 +181,9 @@ def enriched_cell_blocks(K, nodes01, lo, h, pts, w, V, atoms, centers, shells, r
     vals, grads = zip(*(atom_functions(centers[I], shells, r0, t, pts) for I in atoms))
     E = np.concatenate(vals, axis=1)                         # [Q, na]
     EG = np.concatenate(grads, axis=1)                       # [Q, na, 3]
-    kin_ec = 0.5 * sum((EG[:, :, d] * w[:, None]).T @ G[d] for d in range(3))
-    kin_ee = 0.5 * sum((EG[:, :, d] * w[:, None]).T @ EG[:, :, d] for d in range(3))
+    EGd = [np.ascontiguousarray(EG[:, :, d]) for d in range(3)]
+    kin_ec = 0.5 * sum((EGd[d] * w[:, None]).T @ G[d] for d in range(3))
+    kin_ee = 0.5 * sum((EGd[d] * w[:, None]).T @ EGd[d] for d in range(3))
     H_ec = kin_ec + (E * wV[:, None]).T @ N
     M_ec = (E * w[:, None]).T @ N
     H_ee = kin_ee + (E * wV[:, None]).T @ E

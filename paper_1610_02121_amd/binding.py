@@ -37,7 +37,8 @@ EXPORTS = ["chebfilter_init", "chebfilter_destroy", "chebfilter_last_error", "ch
            "chebfilter_batch_autotune", "chebfilter_lanczos_bounds_noalloc", "chebfilter_tuning",
            "chebfilter_batch_tuning", "chebfilter_degree_rule", "chebfilter_step_summary",
            "chebfilter_bounds_label", "chebfilter_mlp_fit_normalization", "chebfilter_mlp_normalize",
-           "chebfilter_mlp_predict"]
+           "chebfilter_mlp_predict", "chebfilter_enriched_tables", "chebfilter_adaptive_points",
+           "chebfilter_assemble_enriched", "chebfilter_get_coupling"]
 
 
 class CfProblem(C.Structure):
@@ -50,6 +51,17 @@ class CfProblem(C.Structure):
 class CfOptions(C.Structure):
     _fields_ = [("device", C.c_int32), ("stream", C.c_void_p), ("max_cols", C.c_int64),
                 ("col_chunk", C.c_int64), ("check_finite", C.c_int32)]
+
+
+class CfAdaptiveGrid(C.Structure):
+    _fields_ = [("ncells", C.c_int64), ("cells", C.c_void_p), ("cell_lo", C.c_void_p),
+                ("h", C.c_double), ("n_nodes", C.c_int32), ("nodes", C.c_void_p),
+                ("ng", C.c_int32), ("gauss_x", C.c_void_p), ("gauss_w", C.c_void_p),
+                ("box_ptr", C.c_void_p), ("box_lo", C.c_void_p), ("box_size", C.c_void_p),
+                ("n_atoms", C.c_int32), ("centers", C.c_void_p), ("n_shells", C.c_int32),
+                ("shell_l", C.c_void_p), ("shell_term_ptr", C.c_void_p), ("term_c", C.c_void_p),
+                ("term_k", C.c_void_p), ("term_zeta", C.c_void_p), ("r0", C.c_double),
+                ("t", C.c_double)]
 
 
 class ChebFilterError(RuntimeError):
@@ -119,6 +131,10 @@ def load_library() -> C.CDLL:
     lib.chebfilter_assembly_tables.argtypes = [vp, i32, vp, vp, vp]
     lib.chebfilter_assemble_cells.argtypes = [vp, vp, i64, vp, i64]
     lib.chebfilter_get_H_cc.argtypes = [vp, vp, i64, vp]
+    lib.chebfilter_enriched_tables.argtypes = [vp, C.POINTER(CfAdaptiveGrid)]
+    lib.chebfilter_adaptive_points.argtypes = [vp, P64]
+    lib.chebfilter_assemble_enriched.argtypes = [vp, vp]
+    lib.chebfilter_get_coupling.argtypes = [vp, vp, vp]
     lib.chebfilter_set_cell_tile.argtypes = [vp, i32, i32]
     lib.chebfilter_autotune.argtypes = [vp, vp, i64, vp, i64, i64, i32, dbl, dbl, i32, i32,
                                         C.POINTER(i32)]
@@ -194,6 +210,7 @@ class Context:
         self.n_h, self.n_e, self.max_cols = nh.value, ne.value, mc.value
         self.n = self.n_h + self.n_e
         self._npc = (int(prob.p) + 1) ** 3
+        self._nnz = int(np.asarray(prob.enr_ptr)[-1]) if self.n_e else 0
 
     def _check(self, st: int):
         if st != 0:
@@ -338,6 +355,63 @@ class Context:
         self._check(self.lib.chebfilter_get_H_cc(self._h, cl.ctypes.data, int(cl.size),
                                                  out.ctypes.data))
         return out
+
+    def enriched_tables(self, cells, cell_lo, h, nodes, gauss_x, gauss_w, box_ptr, box_lo,
+                        box_size, centers=None, shells=(), r0=1.0, t=1.0):
+        """Upload the adaptive grid of the listed cells and the enrichment
+        description (chebfilter_enriched_tables).  shells: [(l, [(c, k, zeta), ...])]
+        per shell, the radial part as Slater-type terms.  Host arrays."""
+        keep = [_np(cells, np.int32), _np(cell_lo, np.float64).reshape(-1, 3),
+                _np(nodes, np.float64), _np(gauss_x, np.float64), _np(gauss_w, np.float64),
+                _np(box_ptr, np.int64), _np(box_lo, np.float64).reshape(-1, 3),
+                _np(box_size, np.float64)]
+        cl, lo, nd, gx, gw, bp, bl, bs = keep
+        cen = _np(centers if centers is not None else np.zeros((0, 3)), np.float64).reshape(-1, 3)
+        sl = np.array([l for l, _ in shells], dtype=np.int32)
+        tp = np.zeros(len(shells) + 1, dtype=np.int32)
+        tc, tk, tz = [], [], []
+        for s, (_, terms) in enumerate(shells):
+            for c_, k_, z_ in terms:
+                tc.append(c_)
+                tk.append(k_)
+                tz.append(z_)
+            tp[s + 1] = len(tc)
+        tc, tk, tz = (np.array(tc, dtype=np.float64), np.array(tk, dtype=np.int32),
+                      np.array(tz, dtype=np.float64))
+        keep += [cen, sl, tp, tc, tk, tz]
+        g = CfAdaptiveGrid(ncells=cl.size, cells=cl.ctypes.data, cell_lo=lo.ctypes.data, h=float(h),
+                           n_nodes=nd.size, nodes=nd.ctypes.data, ng=gx.size,
+                           gauss_x=gx.ctypes.data, gauss_w=gw.ctypes.data, box_ptr=bp.ctypes.data,
+                           box_lo=bl.ctypes.data, box_size=bs.ctypes.data, n_atoms=cen.shape[0],
+                           centers=cen.ctypes.data, n_shells=sl.size, shell_l=sl.ctypes.data,
+                           shell_term_ptr=tp.ctypes.data, term_c=tc.ctypes.data,
+                           term_k=tk.ctypes.data, term_zeta=tz.ctypes.data, r0=float(r0),
+                           t=float(t))
+        self._check(self.lib.chebfilter_enriched_tables(self._h, C.byref(g)))
+
+    def adaptive_points(self) -> int:
+        """Points of the uploaded adaptive grid (length of assemble_enriched's V)."""
+        n = C.c_int64(0)
+        self._check(self.lib.chebfilter_adaptive_points(self._h, C.byref(n)))
+        return int(n.value)
+
+    def assemble_enriched(self, V):
+        """Recompute H^cc_e, H^ec and H^ee of the listed cells on the device from
+        the potential at the grid's points (float64 CUDA tensor [npoints])."""
+        import torch
+        if V.dtype != torch.float64 or not V.is_cuda or not V.is_contiguous():
+            raise TypeError("V must be a contiguous float64 CUDA tensor")
+        if V.numel() != self.adaptive_points():
+            raise ValueError("V needs one value per point of the grid")
+        self._check(self.lib.chebfilter_assemble_enriched(self._h, V.data_ptr()))
+
+    def get_coupling(self):
+        """The current H^ec [nnz, npc] (cf_problem.H_ec's layout) and H^ee
+        [n_e, n_e] (host copies)."""
+        Hec = np.zeros((self._nnz, self._npc))
+        Hee = np.zeros((self.n_e, self.n_e))
+        self._check(self.lib.chebfilter_get_coupling(self._h, Hec.ctypes.data, Hee.ctypes.data))
+        return Hec, Hee
 
     def bounds_label(self, history, theta, wanted: int, v0, k: int = 40, m_min: int = 8,
                      m_max: int = 120):

@@ -8,6 +8,7 @@
 #include <rocsolver/rocsolver.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -126,6 +127,23 @@ struct cf_ctx {
   int64_t asm_cap = 0;
   std::vector<int32_t> asm_list;
   std::vector<uint8_t> cell_enriched;
+  // assembly of the cells with their own adaptive rule (chebfilter_enriched_tables):
+  // device copies of the listed cells, their leaf boxes, the shared table and
+  // the atom centres; the enrichment-row work items and the atom-pair lists
+  // of the partial H^ee sums, both grouped in batches whose partial blocks fit
+  // the partial buffer (host: the batches' first item and pair)
+  struct {
+    int ncl = 0, np1 = 0, ng = 0, nsh = 0, nterm = 0, npa = 0;
+    int64_t nbox = 0, npts = 0;
+    double h = 0.0, r0 = 0.0, t = 0.0;
+    int32_t *cell = nullptr;
+    double *lo = nullptr, *blo = nullptr, *bsz = nullptr, *tab = nullptr, *centers = nullptr;
+    int64_t *bptr = nullptr, *pee_off = nullptr, *pair_ptr = nullptr;
+    int32_t *item_slot = nullptr, *item_t0 = nullptr, *item_nt = nullptr, *pair_ij = nullptr,
+            *pc = nullptr;
+    double *Pee = nullptr;
+    std::vector<int> batch_item, batch_pair;  // [nbatch + 1] each
+  } ea;
   rocblas_handle rb = nullptr;
   std::string err;
   bool profiling = false;
@@ -2466,6 +2484,353 @@ cf_status chebfilter_assemble_cells(cf_ctx *c, const int32_t *cells, int64_t nce
   const int64_t hsz = c->E * NPAD * NPAD;
   if (c->Hp32) HIPCHK(c, launch_to_f32(c->stream, hsz, c->Hp, c->Hp32));
   if (c->Hp16) HIPCHK(c, launch_to_bf16(c->stream, hsz, c->Hp, c->Hp16));
+  return CF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Element blocks of the cells with their own adaptive rule (Sec. IV.C)
+// ---------------------------------------------------------------------------
+extern "C++" {
+template <class T>
+static void dfree(cf_ctx *c, T *&p) {
+  if (!p) return;
+  (void)hipFree((void *)p);
+  auto it = std::find(c->allocs.begin(), c->allocs.end(), (void *)p);
+  if (it != c->allocs.end()) c->allocs.erase(it);
+  p = nullptr;
+}
+
+template <class T>
+static cf_status dupload(cf_ctx *c, T *&p, const T *host, size_t count) {
+  dfree(c, p);
+  STCHK(dalloc(c, &p, std::max<size_t>(count, 1)));
+  if (count) HIPCHK(c, hipMemcpy(p, host, count * sizeof(T), hipMemcpyHostToDevice));
+  return CF_OK;
+}
+}  // extern "C++"
+
+// partial H^ee blocks of one batch of enriched cells stay below this
+static constexpr int64_t EA_PEE_BYTES = 512ll << 20;
+
+cf_status chebfilter_enriched_tables(cf_ctx *c, const cf_adaptive_grid *g) {
+  if (!c) return CF_EINVAL;
+  if (!g) return set_err(c, CF_EINVAL, "enriched_tables: null grid");
+  if (!c->asm_K) return set_err(c, CF_EINVAL, "enriched_tables: no kinetic block (chebfilter_assembly_tables)");
+  const int64_t ncl = g->ncells;
+  if (ncl < 1 || ncl > c->E) return set_err(c, CF_EINVAL, "enriched_tables: bad cell count");
+  if (!g->cells || !g->cell_lo || !g->nodes || !g->gauss_x || !g->gauss_w || !g->box_ptr ||
+      !g->box_lo || !g->box_size)
+    return set_err(c, CF_EINVAL, "enriched_tables: null array");
+  const int np1 = g->n_nodes, ng = g->ng;
+  if (np1 < 2 || np1 > EA_MAXNP || np1 * np1 * np1 != c->npc)
+    return set_err(c, CF_EINVAL, "enriched_tables: n_nodes^3 must equal the cell's node count (n_nodes <= 8)");
+  if (ng < 1 || ng > 8) return set_err(c, CF_EINVAL, "enriched_tables: ng must be 1..8");
+  if (!(g->h > 0.0) || !std::isfinite(g->h)) return set_err(c, CF_EINVAL, "enriched_tables: bad h");
+  for (int i = 0; i < np1; ++i)
+    if (!std::isfinite(g->nodes[i]) || (i && !(g->nodes[i] > g->nodes[i - 1])))
+      return set_err(c, CF_EINVAL, "enriched_tables: nodes must be finite and increasing");
+  double wsum = 0.0;
+  for (int i = 0; i < ng; ++i) {
+    if (!(g->gauss_x[i] > 0.0 && g->gauss_x[i] < 1.0) || !std::isfinite(g->gauss_w[i]))
+      return set_err(c, CF_EINVAL, "enriched_tables: Gauss points must lie in (0, 1)");
+    wsum += g->gauss_w[i];
+  }
+  if (std::fabs(wsum - 1.0) > 1e-12) return set_err(c, CF_EINVAL, "enriched_tables: Gauss weights must sum to 1");
+  // cells: distinct, in range, every cell with enrichment functions listed
+  std::vector<uint8_t> seen(c->E, 0);
+  for (int64_t i = 0; i < ncl; ++i) {
+    const int32_t e = g->cells[i];
+    if (e < 0 || e >= c->E) return set_err(c, CF_EINVAL, "enriched_tables: cell index out of range");
+    if (seen[e]) return set_err(c, CF_EINVAL, "enriched_tables: cell listed twice");
+    seen[e] = 1;
+  }
+  if (c->n_e > 0)
+    for (int64_t e = 0; e < c->E; ++e)
+      if (c->cell_enriched[e] && !seen[e])
+        return set_err(c, CF_EINVAL, "enriched_tables: cell " + std::to_string(e) +
+                                         " carries enrichment functions but is not listed");
+  // boxes: at least one per cell, positive sides, inside the cell
+  if (g->box_ptr[0] != 0) return set_err(c, CF_EINVAL, "enriched_tables: box_ptr[0] must be 0");
+  for (int64_t i = 0; i < ncl; ++i)
+    if (g->box_ptr[i + 1] <= g->box_ptr[i]) return set_err(c, CF_EINVAL, "enriched_tables: a cell without boxes");
+  const int64_t nbox = g->box_ptr[ncl];
+  const int64_t ng3 = (int64_t)ng * ng * ng;
+  if (nbox > ((int64_t)1 << 40) / ng3) return set_err(c, CF_EINVAL, "enriched_tables: too many points");
+  for (int64_t i = 0; i < ncl; ++i) {
+    const double *lo = g->cell_lo + 3 * i;
+    for (int d = 0; d < 3; ++d)
+      if (!std::isfinite(lo[d])) return set_err(c, CF_EINVAL, "enriched_tables: non-finite cell corner");
+    const double tol = 1e-9 * g->h;
+    for (int64_t b = g->box_ptr[i]; b < g->box_ptr[i + 1]; ++b) {
+      const double s = g->box_size[b];
+      if (!(s > 0.0) || !std::isfinite(s)) return set_err(c, CF_EINVAL, "enriched_tables: bad box side");
+      for (int d = 0; d < 3; ++d) {
+        const double bl = g->box_lo[3 * b + d];
+        if (!std::isfinite(bl) || bl < lo[d] - tol || bl + s > lo[d] + g->h + tol)
+          return set_err(c, CF_EINVAL, "enriched_tables: box " + std::to_string(b) + " outside its cell");
+      }
+    }
+  }
+  // enrichment description
+  const int nsh = g->n_shells;
+  int npa = 0, nterm = 0;
+  if (c->n_e > 0) {
+    if (g->n_atoms < 1 || !g->centers || nsh < 1 || !g->shell_l || !g->shell_term_ptr ||
+        !g->term_c || !g->term_k || !g->term_zeta)
+      return set_err(c, CF_EINVAL, "enriched_tables: enrichment description missing");
+    if (!(g->r0 > 0.0) || !(g->t > 0.0) || !std::isfinite(g->r0) || !std::isfinite(g->t))
+      return set_err(c, CF_EINVAL, "enriched_tables: bad cutoff (r0, t)");
+    if (g->shell_term_ptr[0] != 0) return set_err(c, CF_EINVAL, "enriched_tables: shell_term_ptr[0] must be 0");
+    for (int s = 0; s < nsh; ++s) {
+      const int l = g->shell_l[s];
+      if (l != 0 && l != 1) return set_err(c, CF_EINVAL, "enriched_tables: shells must have l = 0 or 1");
+      npa += 2 * l + 1;
+      if (g->shell_term_ptr[s + 1] <= g->shell_term_ptr[s])
+        return set_err(c, CF_EINVAL, "enriched_tables: a shell without radial terms");
+      for (int k = g->shell_term_ptr[s]; k < g->shell_term_ptr[s + 1]; ++k)
+        if (!std::isfinite(g->term_c[k]) || !(g->term_zeta[k] >= 0.0) || g->term_k[k] < l ||
+            g->term_k[k] > 16)
+          return set_err(c, CF_EINVAL, "enriched_tables: bad radial term (k >= l, k <= 16, zeta >= 0)");
+    }
+    nterm = g->shell_term_ptr[nsh];
+    if (npa > 16) return set_err(c, CF_EINVAL, "enriched_tables: more than 16 functions per atom");
+    if ((int64_t)g->n_atoms * npa != c->n_e)
+      return set_err(c, CF_EINVAL, "enriched_tables: n_atoms * functions per atom != n_e");
+    for (int64_t q = 0; q < 3 * (int64_t)g->n_atoms; ++q)
+      if (!std::isfinite(g->centers[q])) return set_err(c, CF_EINVAL, "enriched_tables: non-finite centre");
+  }
+  if (ea_tab_size(np1, ng, nsh, nterm) > EA_TAB_MAX)
+    return set_err(c, CF_EINVAL, "enriched_tables: too many shells or radial terms");
+
+  HIPCHK(c, hipSetDevice(c->device));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  // the context's enrichment lists (host copies)
+  std::vector<int64_t> ep;
+  std::vector<int32_t> eidx;
+  if (c->n_e > 0) {
+    ep.resize(c->E + 1);
+    HIPCHK(c, hipMemcpy(ep.data(), c->eptr, (c->E + 1) * sizeof(int64_t), hipMemcpyDeviceToHost));
+    eidx.resize(std::max<int64_t>(ep[c->E], 1));
+    if (ep[c->E]) HIPCHK(c, hipMemcpy(eidx.data(), c->eidx, ep[c->E] * sizeof(int32_t), hipMemcpyDeviceToHost));
+  }
+  // per listed cell: its atoms (complete groups of npa functions, ascending)
+  std::vector<std::vector<int32_t>> atoms(ncl);
+  for (int64_t i = 0; i < ncl && c->n_e > 0; ++i) {
+    const int32_t e = g->cells[i];
+    const int64_t na = ep[e + 1] - ep[e];
+    if (na == 0) continue;
+    if (na % npa || na > EA_MAXNAP)
+      return set_err(c, CF_EINVAL, "enriched_tables: cell " + std::to_string(e) +
+                                       ": its functions are not whole atoms (or more than 256)");
+    for (int64_t u = 0; u < na / npa; ++u) {
+      const int32_t f0 = eidx[ep[e] + u * npa];
+      if (f0 % npa) return set_err(c, CF_EINVAL, "enriched_tables: function groups not atom-aligned");
+      for (int m = 0; m < npa; ++m)
+        if (eidx[ep[e] + u * npa + m] != f0 + m)
+          return set_err(c, CF_EINVAL, "enriched_tables: an atom's functions are not consecutive");
+      if (u && f0 / npa <= atoms[i].back())
+        return set_err(c, CF_EINVAL, "enriched_tables: a cell's atoms are not ascending");
+      atoms[i].push_back(f0 / npa);
+    }
+  }
+  // shared table
+  std::vector<double> tab;
+  tab.insert(tab.end(), g->nodes, g->nodes + np1);
+  tab.insert(tab.end(), g->gauss_x, g->gauss_x + ng);
+  tab.insert(tab.end(), g->gauss_w, g->gauss_w + ng);
+  for (int s = 0; s < nsh && c->n_e > 0; ++s) tab.push_back(g->shell_l[s]);
+  for (int s = 0; s <= nsh && c->n_e > 0; ++s) tab.push_back(g->shell_term_ptr[s]);
+  for (int k = 0; k < nterm; ++k) {
+    tab.push_back(g->term_c[k]);
+    tab.push_back(g->term_k[k]);
+    tab.push_back(g->term_zeta[k]);
+  }
+  // enrichment-row work items and atom-pair lists, in batches of cells
+  std::vector<int32_t> it_slot, it_t0, it_nt, pair_ij, pc;
+  std::vector<int64_t> pee_off(ncl, 0), pair_ptr(1, 0);
+  std::vector<int> b_item(1, 0), b_pair(1, 0);
+  int64_t pee_max = 0;
+  {
+    int64_t used = 0;
+    std::vector<int64_t> batch_slots;
+    auto close_batch = [&]() {
+      if (batch_slots.empty()) return;
+      // pairs (I <= J) of each cell's atoms, cells in slot order
+      std::vector<std::array<int32_t, 5>> ent;
+      for (int64_t s : batch_slots)
+        for (size_t u1 = 0; u1 < atoms[s].size(); ++u1)
+          for (size_t u2 = u1; u2 < atoms[s].size(); ++u2)
+            ent.push_back({atoms[s][u1], atoms[s][u2], (int32_t)s, (int32_t)u1, (int32_t)u2});
+      std::stable_sort(ent.begin(), ent.end(), [](const std::array<int32_t, 5> &x,
+                                                  const std::array<int32_t, 5> &y) {
+        return x[0] != y[0] ? x[0] < y[0] : x[1] < y[1];
+      });
+      for (size_t q = 0; q < ent.size(); ++q) {
+        if (q == 0 || ent[q][0] != ent[q - 1][0] || ent[q][1] != ent[q - 1][1]) {
+          if (q) pair_ptr.push_back((int64_t)pc.size() / 3);
+          pair_ij.push_back(ent[q][0]);
+          pair_ij.push_back(ent[q][1]);
+        }
+        pc.push_back(ent[q][2]);
+        pc.push_back(ent[q][3]);
+        pc.push_back(ent[q][4]);
+      }
+      if (!ent.empty()) pair_ptr.push_back((int64_t)pc.size() / 3);
+      b_item.push_back((int)it_slot.size());
+      b_pair.push_back((int)pair_ij.size() / 2);
+      pee_max = std::max(pee_max, used);
+      batch_slots.clear();
+      used = 0;
+    };
+    for (int64_t s = 0; s < ncl; ++s) {
+      if (atoms[s].empty()) continue;
+      const int nap = (int)((atoms[s].size() * npa + 15) & ~(size_t)15), nte = nap / 16;
+      const int64_t bytes = (int64_t)nap * nap * (int64_t)sizeof(double);
+      if (used + bytes > EA_PEE_BYTES) close_batch();
+      pee_off[s] = used / (int64_t)sizeof(double);
+      used += bytes;
+      batch_slots.push_back(s);
+      const int ntiles = 8 * nte + nte * (nte + 1) / 2;
+      for (int t0 = 0; t0 < ntiles; t0 += 4 * EA_TPW) {
+        it_slot.push_back((int32_t)s);
+        it_t0.push_back(t0);
+        it_nt.push_back(std::min(4 * EA_TPW, ntiles - t0));
+      }
+    }
+    close_batch();
+  }
+  // upload
+  std::vector<double> lo(g->cell_lo, g->cell_lo + 3 * ncl);
+  auto &ea = c->ea;
+  STCHK(dupload(c, ea.cell, g->cells, (size_t)ncl));
+  STCHK(dupload(c, ea.lo, lo.data(), lo.size()));
+  STCHK(dupload(c, ea.bptr, g->box_ptr, (size_t)ncl + 1));
+  STCHK(dupload(c, ea.blo, g->box_lo, (size_t)nbox * 3));
+  STCHK(dupload(c, ea.bsz, g->box_size, (size_t)nbox));
+  STCHK(dupload(c, ea.tab, tab.data(), tab.size()));
+  if (c->n_e > 0) STCHK(dupload(c, ea.centers, g->centers, (size_t)g->n_atoms * 3));
+  STCHK(dupload(c, ea.pee_off, pee_off.data(), pee_off.size()));
+  STCHK(dupload(c, ea.item_slot, it_slot.data(), it_slot.size()));
+  STCHK(dupload(c, ea.item_t0, it_t0.data(), it_t0.size()));
+  STCHK(dupload(c, ea.item_nt, it_nt.data(), it_nt.size()));
+  STCHK(dupload(c, ea.pair_ij, pair_ij.data(), pair_ij.size()));
+  STCHK(dupload(c, ea.pair_ptr, pair_ptr.data(), pair_ptr.size()));
+  STCHK(dupload(c, ea.pc, pc.data(), pc.size()));
+  dfree(c, ea.Pee);
+  STCHK(dalloc(c, &ea.Pee, (size_t)std::max<int64_t>(pee_max / (int64_t)sizeof(double), 1)));
+  ea.ncl = (int)ncl;
+  ea.np1 = np1;
+  ea.ng = ng;
+  ea.nsh = c->n_e > 0 ? nsh : 0;
+  ea.nterm = nterm;
+  ea.npa = npa;
+  ea.nbox = nbox;
+  ea.npts = nbox * ng3;
+  ea.h = g->h;
+  ea.r0 = g->r0;
+  ea.t = g->t;
+  ea.batch_item = b_item;
+  ea.batch_pair = b_pair;
+  return CF_OK;
+}
+
+cf_status chebfilter_adaptive_points(const cf_ctx *c, int64_t *npoints) {
+  if (!c || !npoints) return CF_EINVAL;
+  *npoints = c->ea.npts;
+  return CF_OK;
+}
+
+// Hmod = H^ee - M^ec D^-1 H^ec^T (the enrichment block of H~'s step, Sec. IV.D)
+// from the current coupling blocks, ldw unit columns at a time: the
+// transposed coupling products of the unit block gathered and scaled by D^-1
+// on the enriched region's classical rows, then the M^ec partial products of
+// that block and their fixed-order sums, subtracted from the columns of H^ee.
+static cf_status rebuild_hmod(cf_ctx *c) {
+  const int64_t n_e = c->n_e, lw = c->ldw;
+  HIPCHK(c, launch_fill(c->stream, c->T, c->n * lw, 0.0));
+  for (int64_t j0 = 0; j0 < n_e; j0 += lw) {
+    const int nb = (int)std::min<int64_t>(lw, n_e - j0);
+    HIPCHK(c, launch_unit_cols(c->stream, n_e, nb, lw, j0, c->Wb));
+    STCHK(core_enr_q(c, c->Wb, lw, 1.0, nullptr, 0, 0.0, nb));
+    EpiArgs g = epi_base(c, nb);
+    g.rows = c->regrows;
+    g.nrows = c->nregrows;
+    g.R = c->T; g.ldr = lw;
+    g.dC = c->dinv;
+    g.Ee = c->Wb; g.lde = lw;
+    g.Out = c->U; g.ldo = lw;
+    HIPCHK(c, launch_epilogue(c->stream, g));
+    HIPCHK(c, launch_enr_part(c->stream, c->HT, c->MT, c->toff, c->tld, c->eptr, c->dofp,
+                              c->ecells_part, c->necells, nullptr, 0, 0.0, c->U, lw, nullptr, 1.0,
+                              c->P, lw, nb));
+    HIPCHK(c, launch_enr_reduce(c->stream, (int)n_e, c->aptr, c->alist, c->P, lw, -1.0,
+                                c->Hee + j0, n_e, 1.0, nullptr, nullptr, 0, c->Hmod + j0, n_e, nb));
+  }
+  return CF_OK;
+}
+
+cf_status chebfilter_assemble_enriched(cf_ctx *c, const double *V) {
+  if (!c) return CF_EINVAL;
+  auto &ea = c->ea;
+  if (ea.ncl == 0) return set_err(c, CF_EINVAL, "assemble_enriched: no grid (chebfilter_enriched_tables)");
+  if (!V) return set_err(c, CF_EINVAL, "assemble_enriched: null potential");
+  HIPCHK(c, hipSetDevice(c->device));
+  EnrAsm a;
+  a.ncl = ea.ncl;
+  a.cell = ea.cell; a.lo = ea.lo; a.bptr = ea.bptr; a.blo = ea.blo; a.bsz = ea.bsz; a.V = V;
+  a.ng = ea.ng; a.np1 = ea.np1; a.h = ea.h; a.tab = ea.tab;
+  a.nsh = ea.nsh; a.nterm = ea.nterm; a.npa = ea.npa; a.r0 = ea.r0; a.t = ea.t;
+  a.centers = ea.centers;
+  a.eptr = c->eptr; a.eidx = c->eidx; a.tld = c->tld; a.toff = c->toff;
+  a.Hp = c->Hp; a.K = c->asm_K; a.Hec = c->Hec; a.HT = c->HT;
+  a.Pee = ea.Pee; a.pee_off = ea.pee_off;
+  {
+    Scope sc(c, "assemble_adaptive");
+    HIPCHK(c, launch_ea_nn(c->stream, a));
+    if (c->n_e > 0) {
+      HIPCHK(c, launch_fill(c->stream, c->Hee, c->n_e * c->n_e, 0.0));
+      for (size_t b = 0; b + 1 < ea.batch_item.size(); ++b) {
+        EnrAsm ab = a;
+        ab.item_slot = ea.item_slot + ea.batch_item[b];
+        ab.item_t0 = ea.item_t0 + ea.batch_item[b];
+        ab.item_nt = ea.item_nt + ea.batch_item[b];
+        HIPCHK(c, launch_ea_erow(c->stream, ab, ea.batch_item[b + 1] - ea.batch_item[b]));
+        HIPCHK(c, launch_ea_ee_reduce(c->stream, a, (int)c->n_e,
+                                      ea.batch_pair[b + 1] - ea.batch_pair[b],
+                                      ea.pair_ij + 2 * (int64_t)ea.batch_pair[b],
+                                      ea.pair_ptr + ea.batch_pair[b], ea.pc, c->Hee));
+      }
+    }
+  }
+  if (c->n_e > 0) {
+    Scope sc(c, "rebuild_hmod");
+    STCHK(rebuild_hmod(c));
+  }
+  const int64_t hsz = c->E * NPAD * NPAD;
+  if (c->Hp32) HIPCHK(c, launch_to_f32(c->stream, hsz, c->Hp, c->Hp32));
+  if (c->Hp16) HIPCHK(c, launch_to_bf16(c->stream, hsz, c->Hp, c->Hp16));
+  if (c->HT32) HIPCHK(c, launch_to_f32(c->stream, c->ttot, c->HT, c->HT32));
+  if (c->Hec32) HIPCHK(c, launch_to_f32(c->stream, c->nnz * NPAD, c->Hec, c->Hec32));
+  return CF_OK;
+}
+
+cf_status chebfilter_get_coupling(cf_ctx *c, double *H_ec, double *H_ee) {
+  if (!c) return CF_EINVAL;
+  HIPCHK(c, hipSetDevice(c->device));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (c->n_e == 0) return CF_OK;
+  const int npc = c->npc;
+  if (H_ec) {
+    const int64_t batch = 4096;
+    std::vector<double> buf((size_t)batch * NPAD);
+    for (int64_t k0 = 0; k0 < c->nnz; k0 += batch) {
+      const int64_t nbk = std::min(batch, c->nnz - k0);
+      HIPCHK(c, hipMemcpy(buf.data(), c->Hec + k0 * NPAD, nbk * NPAD * sizeof(double), hipMemcpyDeviceToHost));
+      for (int64_t k = 0; k < nbk; ++k)
+        for (int a2 = 0; a2 < npc; ++a2) H_ec[(k0 + k) * npc + a2] = buf[k * NPAD + a2];
+    }
+  }
+  if (H_ee) HIPCHK(c, hipMemcpy(H_ee, c->Hee, c->n_e * c->n_e * sizeof(double), hipMemcpyDeviceToHost));
   return CF_OK;
 }
 

@@ -327,6 +327,59 @@ hipError_t launch_assemble_cells(hipStream_t s, const double *Btab, const double
                                  const double *K, const int *cells, int ncells, const double *V,
                                  int64_t ldv, int nq, double *Hp);
 
+// ---- element blocks of the cells with their own adaptive rule (cf_assemble_enr.hip)
+constexpr int EA_MAXNP = 8;       // 1D nodes per axis (degree <= 7)
+constexpr int EA_MAXNAP = 256;    // enrichment functions of one cell, padded to 16
+constexpr int EA_TPW = 16;        // tiles per wave of an enrichment-row work item
+constexpr int EA_TAB_MAX = 256;   // doubles of the shared table (nodes, Gauss rule, shells)
+__host__ __device__ constexpr int ea_tab_size(int np1, int ng, int nsh, int nterm) {
+  return np1 + 2 * ng + nsh + nsh + 1 + 3 * nterm;
+}
+
+struct EnrAsm {
+  // listed cells ("slots"): cell index, lower corner, leaf boxes box_ptr[s] ..
+  // box_ptr[s+1] (lower corners [3], sides), the potential at the boxes'
+  // points (ng^3 per box, x fastest, boxes in order)
+  int ncl = 0;
+  const int32_t *cell = nullptr;
+  const double *lo = nullptr;
+  const int64_t *bptr = nullptr;
+  const double *blo = nullptr;
+  const double *bsz = nullptr;
+  const double *V = nullptr;
+  int ng = 0, np1 = 0;
+  double h = 0.0;
+  const double *tab = nullptr;      // nodes [np1], gx [ng], gw [ng], shell l [nsh],
+                                    // first term [nsh + 1], terms (c, k, zeta) [nterm]
+  int nsh = 0, nterm = 0, npa = 0;
+  double r0 = 0.0, t = 0.0;
+  const double *centers = nullptr;  // [atoms][3]
+  // the context's enrichment layout
+  const int64_t *eptr = nullptr;
+  const int32_t *eidx = nullptr;
+  const int32_t *tld = nullptr;
+  const int64_t *toff = nullptr;
+  // outputs
+  double *Hp = nullptr;
+  const double *K = nullptr;        // [NPAD][NPAD] kinetic block
+  double *Hec = nullptr, *HT = nullptr;
+  double *Pee = nullptr;            // per-slot partial H^ee blocks [nap][nap]
+  const int64_t *pee_off = nullptr;
+  // enrichment-row work items
+  const int32_t *item_slot = nullptr, *item_t0 = nullptr, *item_nt = nullptr;
+};
+
+// H^cc_e = K + sum_q w_q V_q N_a N_b for every slot (exactly symmetric).
+hipError_t launch_ea_nn(hipStream_t s, const EnrAsm &a);
+// H^ec_e rows (both stored layouts) and the partial H^ee_e blocks of the items' tiles.
+hipError_t launch_ea_erow(hipStream_t s, const EnrAsm &a, int nitems);
+// Hee[al][be] += sum over the pair's cells of the partial entries (both halves written).
+hipError_t launch_ea_ee_reduce(hipStream_t s, const EnrAsm &a, int n_e, int npairs,
+                               const int32_t *pair_ij, const int64_t *pair_ptr, const int32_t *pc,
+                               double *Hee);
+// X[i][j] = (i == j0 + j), i < rows, j < N.
+hipError_t launch_unit_cols(hipStream_t s, int64_t rows, int N, int64_t ldx, int64_t j0, double *X);
+
 // ---- data-movement helpers (cf_dense.hip)
 hipError_t launch_sub(hipStream_t s, int64_t n, const double *A, const double *B, double *C);
 hipError_t launch_transpose(hipStream_t s, int N, const double *In, int64_t ldi, double *Out);

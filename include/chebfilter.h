@@ -423,6 +423,89 @@ cf_status chebfilter_assemble_enriched(cf_ctx *ctx, const double *V);
  * H^ee (host, [n_e][n_e]); either may be null.  Synchronises. */
 cf_status chebfilter_get_coupling(cf_ctx *ctx, double *H_ec, double *H_ee);
 
+/* ---- Self-consistent field quantities around the eigensolver --------------
+ * Sec. II and Sec. V.  The density and the potentials live on the quadrature
+ * points: the plain cells' Gauss points (the rule of chebfilter_assembly_tables,
+ * cell by cell in cell order), then the adaptive grid's points (the grid of
+ * chebfilter_enriched_tables, box by box).  In this layout the effective
+ * potential is the input of both assembly entry points (chebfilter_scf_assemble).
+ * The electrostatic enrichment set is empty: the Hartree potential is the
+ * classical finite-element solution of Eq. Hartree_possion (discretised as
+ * Eq. discretePoissonCFEM) with zero Dirichlet values, for the density less a
+ * neutralising Gaussian of the same charge; the Gaussian's potential
+ * Q erf(r/s)/r is added back at the points. */
+typedef struct {
+  const double *cell_lo;      /* [n_cells][3] lower corner of every cell                       */
+  const double *plain_ref;    /* [nq][3] points of the plain rule on the unit cube, in the order
+                               * of the assembly table's rows (x fastest)                        */
+  double comp_center[3];      /* centre c of the neutralising Gaussian                         */
+  double comp_width;          /* its width s > 0: rho_g = Q (s sqrt pi)^-3 exp(-|x-c|^2/s^2)   */
+  int32_t cg_max_iter;        /* Poisson CG: iteration limit >= 1                              */
+  double cg_tol;              /* and relative residual ||b - A phi|| / ||b|| > 0               */
+  int32_t mix_depth;          /* Anderson stages kept, 1..8                                    */
+  double mix_beta;            /* Anderson step beta > 0                                        */
+} cf_scf_setup;
+
+/* Points, weights, per-colour cell lists, the Poisson matrix block and its
+ * Jacobi diagonal, and the work buffers.  Requires chebfilter_assembly_tables
+ * and chebfilter_enriched_tables.  CF_EINVAL on bad settings.  Synchronises. */
+cf_status chebfilter_scf_setup(cf_ctx *ctx, const cf_scf_setup *setup);
+
+/* Number of points (the length of every field array), of which the first
+ * nplain_points are the plain cells'. */
+cf_status chebfilter_scf_sizes(const cf_ctx *ctx, int64_t *npoints, int64_t *nplain_points);
+
+/* Coordinates [npoints][3] and weights [npoints] (Jacobian included) of the
+ * points, host copies (either may be null).  Synchronises. */
+cf_status chebfilter_scf_geometry(cf_ctx *ctx, double *xyz, double *w);
+
+/* Occupations and Fermi level (Eq. FermiDirac, Eq. Mu): f_i = 1 / (1 +
+ * exp((eps_i - mu) / kT)) with 2 sum_i f_i = n_electrons, mu by bisection
+ * on [min eps - 40 kT, max eps + 40 kT].  Host arrays eps, f [N].  CF_EINVAL
+ * unless 0 < n_electrons < 2 N, kT > 0 and eps finite.  No context. */
+cf_status chebfilter_fermi_level(const double *eps, int64_t N, double n_electrons, double kT,
+                                 double *f, double *mu);
+
+/* Electron density at the points (Eq. Rho): rho(x) = 2 sum_j f_j psi_j(x)^2
+ * with psi_j the basis expansion of column j of X (device, [n][ldx], the
+ * layout of every block).  Per cell, the density matrix D_e = Y_e diag(2 f) Y_e^T
+ * of the cell's rows (FP64 MFMA), then rho_q = Phi_q^T D_e Phi_q with the
+ * basis values Phi_q at the cell's points (FP64 MFMA).  f_host [N] host.
+ * rho device [npoints].  Synchronises. */
+cf_status chebfilter_scf_density(cf_ctx *ctx, const double *X, int64_t ldx, int64_t N,
+                                 const double *f_host, double *rho);
+
+/* Effective potential at the points (Eq. veff): V_eff = v_ext + V_H + V_xc,
+ * with V_xc the LDA of Sec. II (the Perdew-Zunger fit of Ceperley-Alder,
+ * spin unpolarised) and V_H from the Poisson problem above, solved by
+ * Jacobi-preconditioned conjugate gradients on the device (matrix products
+ * cell by cell, colour by colour), started from the previous call's
+ * solution.  Device arrays [npoints]: rho, v_ext (the external potential at
+ * the points), v_eff (output).  terms (host [5]): int rho, E_xc = int rho
+ * eps_xc, int rho V_xc, 1/2 int rho V_H, the final relative CG residual;
+ * cg_iters (may be null).  CF_ENOTCONV if the CG limit is reached first.
+ * Synchronises. */
+cf_status chebfilter_scf_potential(cf_ctx *ctx, const double *rho, const double *v_ext,
+                                   double *v_eff, double *terms, int32_t *cg_iters);
+
+/* The Hamiltonian blocks for a new effective potential at the points:
+ * chebfilter_assemble_cells on the plain cells and chebfilter_assemble_enriched
+ * on the adaptive grid.  v_eff device [npoints]. */
+cf_status chebfilter_scf_assemble(cf_ctx *ctx, const double *v_eff);
+
+/* n-stage Anderson mixing of the density (Sec. V): the pair (rho_in, rho_out)
+ * joins a history of the last mix_depth pairs; with residuals F_k = rho_out,k
+ * - rho_in,k, the coefficients c (sum c_k = 1) minimise || sum c_k F_k ||_w in
+ * the weighted point inner product, and rho_next = sum c_k (rho_in,k + beta
+ * F_k).  Device arrays [npoints]; res_norm (host, may be null) receives
+ * || rho_out - rho_in ||_w of the new pair, the SCF convergence measure.
+ * CF_EINVAL on a singular history.  Synchronises. */
+cf_status chebfilter_scf_mix(cf_ctx *ctx, const double *rho_in, const double *rho_out,
+                             double *rho_next, double *res_norm);
+
+/* Forget the mixing history. */
+cf_status chebfilter_scf_mix_reset(cf_ctx *ctx);
+
 /* res_host[j] = || H^E z_j - theta_j M^E z_j ||_{(M^E)^-1} for the columns z_j of
  * Z with theta_host[j] (the Ritz residual in the dual norm of Sec. V's
  * generalized problem).  Uses the context's work blocks; synchronises. */

@@ -6,6 +6,6 @@ include/chebfilter.h); this package only binds it.  Importing the binding
 never falls back to any other implementation: if the library is missing,
 `load_library()` raises.
 """
-from .binding import Batch, ChebFilterError, Context, Mlp, load_library  # noqa: F401
+from .binding import Batch, ChebFilterError, Context, Mlp, fermi_level, load_library  # noqa: F401
 
-__all__ = ["Batch", "Context", "ChebFilterError", "Mlp", "load_library"]
+__all__ = ["Batch", "Context", "ChebFilterError", "Mlp", "fermi_level", "load_library"]

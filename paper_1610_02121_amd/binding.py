@@ -38,7 +38,10 @@ EXPORTS = ["chebfilter_init", "chebfilter_destroy", "chebfilter_last_error", "ch
            "chebfilter_batch_tuning", "chebfilter_degree_rule", "chebfilter_step_summary",
            "chebfilter_bounds_label", "chebfilter_mlp_fit_normalization", "chebfilter_mlp_normalize",
            "chebfilter_mlp_predict", "chebfilter_enriched_tables", "chebfilter_adaptive_points",
-           "chebfilter_assemble_enriched", "chebfilter_get_coupling"]
+           "chebfilter_assemble_enriched", "chebfilter_get_coupling", "chebfilter_scf_setup",
+           "chebfilter_scf_sizes", "chebfilter_scf_geometry", "chebfilter_fermi_level",
+           "chebfilter_scf_density", "chebfilter_scf_potential", "chebfilter_scf_assemble",
+           "chebfilter_scf_mix", "chebfilter_scf_mix_reset"]
 
 
 class CfProblem(C.Structure):
@@ -62,6 +65,13 @@ class CfAdaptiveGrid(C.Structure):
                 ("shell_l", C.c_void_p), ("shell_term_ptr", C.c_void_p), ("term_c", C.c_void_p),
                 ("term_k", C.c_void_p), ("term_zeta", C.c_void_p), ("r0", C.c_double),
                 ("t", C.c_double)]
+
+
+class CfScfSetup(C.Structure):
+    _fields_ = [("cell_lo", C.c_void_p), ("plain_ref", C.c_void_p),
+                ("comp_center", C.c_double * 3), ("comp_width", C.c_double),
+                ("cg_max_iter", C.c_int32), ("cg_tol", C.c_double), ("mix_depth", C.c_int32),
+                ("mix_beta", C.c_double)]
 
 
 class ChebFilterError(RuntimeError):
@@ -135,6 +145,15 @@ def load_library() -> C.CDLL:
     lib.chebfilter_adaptive_points.argtypes = [vp, P64]
     lib.chebfilter_assemble_enriched.argtypes = [vp, vp]
     lib.chebfilter_get_coupling.argtypes = [vp, vp, vp]
+    lib.chebfilter_scf_setup.argtypes = [vp, C.POINTER(CfScfSetup)]
+    lib.chebfilter_scf_sizes.argtypes = [vp, P64, P64]
+    lib.chebfilter_scf_geometry.argtypes = [vp, vp, vp]
+    lib.chebfilter_fermi_level.argtypes = [PD, i64, dbl, dbl, PD, PD]
+    lib.chebfilter_scf_density.argtypes = [vp, vp, i64, i64, PD, vp]
+    lib.chebfilter_scf_potential.argtypes = [vp, vp, vp, vp, PD, C.POINTER(i32)]
+    lib.chebfilter_scf_assemble.argtypes = [vp, vp]
+    lib.chebfilter_scf_mix.argtypes = [vp, vp, vp, vp, PD]
+    lib.chebfilter_scf_mix_reset.argtypes = [vp]
     lib.chebfilter_set_cell_tile.argtypes = [vp, i32, i32]
     lib.chebfilter_autotune.argtypes = [vp, vp, i64, vp, i64, i64, i32, dbl, dbl, i32, i32,
                                         C.POINTER(i32)]
@@ -184,6 +203,20 @@ def _problem_struct(prob):
                    *[keep[f].ctypes.data for f in ("cell_dof", "H_cc", "M_cc_diag", "enr_ptr",
                                                    "enr_idx", "H_ec", "M_ec", "H_ee", "M_ee")])
     return cp, keep
+
+
+def fermi_level(eps, n_electrons: float, kT: float):
+    """(f, mu): occupations and Fermi level (chebfilter_fermi_level, Eq. FermiDirac / Mu)."""
+    lib = load_library()
+    e = _np(eps, np.float64).ravel()
+    f = np.zeros_like(e)
+    mu = C.c_double(0.0)
+    PD = C.POINTER(C.c_double)
+    st = lib.chebfilter_fermi_level(e.ctypes.data_as(PD), int(e.size), float(n_electrons),
+                                    float(kT), f.ctypes.data_as(PD), C.byref(mu))
+    if st != 0:
+        raise ChebFilterError(st, "fermi_level: need 0 < n_electrons < 2 len(eps), kT > 0")
+    return f, float(mu.value)
 
 
 class Context:
@@ -412,6 +445,83 @@ class Context:
         Hee = np.zeros((self.n_e, self.n_e))
         self._check(self.lib.chebfilter_get_coupling(self._h, Hec.ctypes.data, Hee.ctypes.data))
         return Hec, Hee
+
+    # ---- self-consistent field quantities
+    def scf_setup(self, cell_lo, plain_ref, comp_center, comp_width, cg_max_iter: int = 4000,
+                  cg_tol: float = 1e-11, mix_depth: int = 4, mix_beta: float = 0.5):
+        """Points, Poisson system and mixing state (chebfilter_scf_setup)."""
+        lo = _np(cell_lo, np.float64).reshape(-1, 3)
+        ref = _np(plain_ref, np.float64).reshape(-1, 3)
+        st = CfScfSetup(cell_lo=lo.ctypes.data, plain_ref=ref.ctypes.data,
+                        comp_center=(C.c_double * 3)(*[float(x) for x in comp_center]),
+                        comp_width=float(comp_width), cg_max_iter=int(cg_max_iter),
+                        cg_tol=float(cg_tol), mix_depth=int(mix_depth), mix_beta=float(mix_beta))
+        self._check(self.lib.chebfilter_scf_setup(self._h, C.byref(st)))
+        P, Pp = C.c_int64(), C.c_int64()
+        self._check(self.lib.chebfilter_scf_sizes(self._h, C.byref(P), C.byref(Pp)))
+        self.scf_points, self.scf_plain_points = int(P.value), int(Pp.value)
+
+    def scf_geometry(self):
+        """(xyz [P, 3], w [P]) of the SCF points (host copies)."""
+        xyz = np.zeros((self.scf_points, 3))
+        w = np.zeros(self.scf_points)
+        self._check(self.lib.chebfilter_scf_geometry(self._h, xyz.ctypes.data, w.ctypes.data))
+        return xyz, w
+
+    def _field(self, name, t):
+        import torch
+        if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() \
+                or t.numel() != self.scf_points:
+            raise TypeError(f"{name} must be a contiguous float64 CUDA tensor of one value per point")
+
+    def scf_density(self, X, f):
+        """rho at the points (Eq. Rho) of the block X [n, N] with occupations f [N]."""
+        import torch
+        xp, ldx = _block(X, "X")
+        if X.shape[0] != self.n:
+            raise ValueError("X needs one row per DOF")
+        ff = _np(f, np.float64).ravel()
+        if ff.size != X.shape[1]:
+            raise ValueError("one occupation per column")
+        rho = torch.empty(self.scf_points, dtype=torch.float64, device=self.device)
+        PD = C.POINTER(C.c_double)
+        self._check(self.lib.chebfilter_scf_density(self._h, xp, int(ldx), int(X.shape[1]),
+                                                    ff.ctypes.data_as(PD), rho.data_ptr()))
+        return rho
+
+    def scf_potential(self, rho, v_ext):
+        """(V_eff [P] tensor, terms dict, CG iterations): LDA, Poisson, sum."""
+        import torch
+        self._field("rho", rho)
+        self._field("v_ext", v_ext)
+        veff = torch.empty_like(rho)
+        terms = np.zeros(5)
+        it = C.c_int32(0)
+        PD = C.POINTER(C.c_double)
+        self._check(self.lib.chebfilter_scf_potential(self._h, rho.data_ptr(), v_ext.data_ptr(),
+                                                      veff.data_ptr(), terms.ctypes.data_as(PD),
+                                                      C.byref(it)))
+        names = ("charge", "E_xc", "int_rho_vxc", "half_int_rho_vh", "cg_rel_residual")
+        return veff, dict(zip(names, map(float, terms))), int(it.value)
+
+    def scf_assemble(self, v_eff):
+        """H blocks of every cell from V_eff at the points."""
+        self._field("v_eff", v_eff)
+        self._check(self.lib.chebfilter_scf_assemble(self._h, v_eff.data_ptr()))
+
+    def scf_mix(self, rho_in, rho_out):
+        """(rho_next, ||rho_out - rho_in||_w) by n-stage Anderson mixing."""
+        import torch
+        self._field("rho_in", rho_in)
+        self._field("rho_out", rho_out)
+        nxt = torch.empty_like(rho_in)
+        r = C.c_double(0.0)
+        self._check(self.lib.chebfilter_scf_mix(self._h, rho_in.data_ptr(), rho_out.data_ptr(),
+                                                nxt.data_ptr(), C.byref(r)))
+        return nxt, float(r.value)
+
+    def scf_mix_reset(self):
+        self._check(self.lib.chebfilter_scf_mix_reset(self._h))
 
     def bounds_label(self, history, theta, wanted: int, v0, k: int = 40, m_min: int = 8,
                      m_max: int = 120):

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libchebfilter.so")
-SOURCES = ["cf_ops.hip", "cf_lowp.hip", "cf_batch.hip", "cf_dense.hip", "cf_mlp.hip", "cf_assemble.hip", "cf_assemble_enr.hip", "cf_api.hip"]
+SOURCES = ["cf_ops.hip", "cf_lowp.hip", "cf_batch.hip", "cf_dense.hip", "cf_mlp.hip", "cf_assemble.hip", "cf_assemble_enr.hip", "cf_scf.hip", "cf_api.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC",

@@ -144,6 +144,27 @@ struct cf_ctx {
     double *Pee = nullptr;
     std::vector<int> batch_item, batch_pair;  // [nbatch + 1] each
   } ea;
+  // self-consistent field quantities (chebfilter_scf_setup): the SCF cells
+  // (plain cells, then the cells with an adaptive rule) with their point
+  // ranges, the points' coordinates and weights, density-matrix work items
+  // and batches, per-colour SCF cell lists, the Poisson system and the
+  // mixing history
+  struct {
+    int nscf = 0, nplain = 0, nq = 0, cg_max = 0, depth = 0, nhist = 0, head = 0;
+    int64_t P = 0, P_plain = 0;
+    double cc[3] = {0.0, 0.0, 0.0}, cs = 1.0, cg_tol = 0.0, beta = 0.0;
+    int32_t *cell = nullptr, *cna = nullptr, *seq = nullptr, *col_cells = nullptr;
+    int32_t *dm_c = nullptr, *dm_t0 = nullptr, *dm_nt = nullptr;
+    int64_t *pofs = nullptr, *pcnt = nullptr, *doff = nullptr;
+    double *lo = nullptr, *xyz = nullptr, *w = nullptr, *Dbuf = nullptr, *f2 = nullptr;
+    int64_t f2_cap = 0;
+    double *A = nullptr, *dinv = nullptr, *pb = nullptr, *px = nullptr, *pr = nullptr,
+           *pz = nullptr, *pp = nullptr, *pq = nullptr, *vxc = nullptr, *part = nullptr,
+           *dot = nullptr, *hin = nullptr, *hF = nullptr;
+    std::vector<int> dm_item, dm_cell, col_ofs;   // batches' first item / first SCF cell; colours
+    std::vector<int32_t> plain_cells;
+    std::vector<double> gram;                     // depth x depth, weighted residual products
+  } scf;
   rocblas_handle rb = nullptr;
   std::string err;
   bool profiling = false;
@@ -2831,6 +2852,473 @@ cf_status chebfilter_get_coupling(cf_ctx *c, double *H_ec, double *H_ee) {
     }
   }
   if (H_ee) HIPCHK(c, hipMemcpy(H_ee, c->Hee, c->n_e * c->n_e * sizeof(double), hipMemcpyDeviceToHost));
+  return CF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Self-consistent field quantities (Sec. II, Sec. V)
+// ---------------------------------------------------------------------------
+static constexpr int SCF_RED_BLOCKS = 1024;         // fixed grid of the weighted sums
+static constexpr int64_t SCF_DM_BYTES = 1ll << 30;  // density matrices of one batch
+
+cf_status chebfilter_fermi_level(const double *eps, int64_t N, double n_electrons, double kT,
+                                 double *f, double *mu) {
+  if (!eps || !f || !mu || N < 1 || !(kT > 0.0) || !std::isfinite(kT)) return CF_EINVAL;
+  if (!(n_electrons > 0.0) || !(n_electrons < 2.0 * (double)N)) return CF_EINVAL;
+  double lo = eps[0], hi = eps[0];
+  for (int64_t i = 0; i < N; ++i) {
+    if (!std::isfinite(eps[i])) return CF_EINVAL;
+    lo = std::min(lo, eps[i]);
+    hi = std::max(hi, eps[i]);
+  }
+  lo -= 40.0 * kT;
+  hi += 40.0 * kT;
+  auto occ = [&](double m, int64_t i) {
+    const double x = (eps[i] - m) / kT;
+    if (x > 0.0) { const double ex = std::exp(-x); return ex / (1.0 + ex); }
+    return 1.0 / (1.0 + std::exp(x));
+  };
+  for (int it = 0; it < 200; ++it) {
+    const double m = 0.5 * (lo + hi);
+    double s = 0.0;
+    for (int64_t i = 0; i < N; ++i) s += occ(m, i);
+    if (2.0 * s < n_electrons) lo = m; else hi = m;
+    if (hi - lo <= 4e-16 * std::max(1.0, std::fabs(m))) break;
+  }
+  *mu = 0.5 * (lo + hi);
+  for (int64_t i = 0; i < N; ++i) f[i] = occ(*mu, i);
+  return CF_OK;
+}
+
+static ScfArgs scf_args(cf_ctx *c) {
+  ScfArgs g;
+  const auto &s = c->scf;
+  g.n_h = c->n_h;
+  g.np1 = c->ea.np1;
+  g.ng = c->ea.ng;
+  g.nsh = c->ea.nsh;
+  g.npa = c->ea.npa;
+  g.ntab = ea_tab_size(c->ea.np1, c->ea.ng, c->ea.nsh, c->ea.nterm);
+  g.h = c->ea.h;
+  g.r0 = c->ea.r0;
+  g.t = c->ea.t;
+  g.tab = c->ea.tab;
+  g.centers = c->ea.centers;
+  g.dofp = c->dofp;
+  g.eptr = c->eptr;
+  g.eidx = c->eidx;
+  g.cell = s.cell;
+  g.cna = s.cna;
+  g.lo = s.lo;
+  g.pofs = s.pofs;
+  g.pcnt = s.pcnt;
+  g.doff = s.doff;
+  g.xyz = s.xyz;
+  g.w = s.w;
+  for (int d = 0; d < 3; ++d) g.cc[d] = s.cc[d];
+  g.cs = s.cs;
+  return g;
+}
+
+cf_status chebfilter_scf_setup(cf_ctx *c, const cf_scf_setup *o) {
+  if (!c) return CF_EINVAL;
+  if (!o || !o->cell_lo || !o->plain_ref) return set_err(c, CF_EINVAL, "scf_setup: null argument");
+  if (!c->asm_K) return set_err(c, CF_EINVAL, "scf_setup: no plain rule (chebfilter_assembly_tables)");
+  if (c->ea.ncl == 0) return set_err(c, CF_EINVAL, "scf_setup: no adaptive grid (chebfilter_enriched_tables)");
+  if (!(o->comp_width > 0.0) || o->cg_max_iter < 1 || !(o->cg_tol > 0.0) || o->mix_depth < 1 ||
+      o->mix_depth > 8 || !(o->mix_beta > 0.0))
+    return set_err(c, CF_EINVAL, "scf_setup: bad width, CG limits or mixing depth (1..8) / beta");
+  const int64_t E = c->E, nq = c->asm_nq;
+  auto &s = c->scf;
+  auto &ea = c->ea;
+  HIPCHK(c, hipSetDevice(c->device));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  // host copies of what the device holds
+  std::vector<int32_t> eacell(ea.ncl), dofp((size_t)E * NPAD), colcells(E);
+  std::vector<int64_t> bptr(ea.ncl + 1), ep(E + 1, 0);
+  std::vector<double> blo((size_t)ea.nbox * 3), bsz(ea.nbox), tab(ea_tab_size(ea.np1, ea.ng, ea.nsh, ea.nterm)),
+      wq(nq), K((size_t)NPAD * NPAD);
+  HIPCHK(c, hipMemcpy(eacell.data(), ea.cell, ea.ncl * sizeof(int32_t), hipMemcpyDeviceToHost));
+  HIPCHK(c, hipMemcpy(dofp.data(), c->dofp, dofp.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+  HIPCHK(c, hipMemcpy(colcells.data(), c->cells, E * sizeof(int32_t), hipMemcpyDeviceToHost));
+  HIPCHK(c, hipMemcpy(bptr.data(), ea.bptr, bptr.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
+  HIPCHK(c, hipMemcpy(blo.data(), ea.blo, blo.size() * sizeof(double), hipMemcpyDeviceToHost));
+  HIPCHK(c, hipMemcpy(bsz.data(), ea.bsz, bsz.size() * sizeof(double), hipMemcpyDeviceToHost));
+  HIPCHK(c, hipMemcpy(tab.data(), ea.tab, tab.size() * sizeof(double), hipMemcpyDeviceToHost));
+  HIPCHK(c, hipMemcpy(wq.data(), c->asm_w, nq * sizeof(double), hipMemcpyDeviceToHost));
+  HIPCHK(c, hipMemcpy(K.data(), c->asm_K, K.size() * sizeof(double), hipMemcpyDeviceToHost));
+  if (c->n_e > 0) HIPCHK(c, hipMemcpy(ep.data(), c->eptr, (E + 1) * sizeof(int64_t), hipMemcpyDeviceToHost));
+  for (int64_t q = 0; q < 3 * E; ++q)
+    if (!std::isfinite(o->cell_lo[q])) return set_err(c, CF_EINVAL, "scf_setup: non-finite cell corner");
+  for (int64_t q = 0; q < 3 * nq; ++q)
+    if (!(o->plain_ref[q] >= 0.0 && o->plain_ref[q] <= 1.0))
+      return set_err(c, CF_EINVAL, "scf_setup: plain rule points must lie in the unit cube");
+  // SCF cells: the plain cells in index order, then the adaptive slots
+  std::vector<uint8_t> listed(E, 0);
+  for (int32_t e : eacell) listed[e] = 1;
+  std::vector<int32_t> cell, cna;
+  std::vector<int64_t> pofs, pcnt;
+  std::vector<double> lo;
+  s.plain_cells.clear();
+  for (int64_t e = 0; e < E; ++e)
+    if (!listed[e]) s.plain_cells.push_back((int32_t)e);
+  const int64_t ng3 = (int64_t)ea.ng * ea.ng * ea.ng;
+  int64_t P = 0;
+  for (int32_t e : s.plain_cells) {
+    cell.push_back(e);
+    cna.push_back(0);
+    pofs.push_back(P);
+    pcnt.push_back(nq);
+    P += nq;
+  }
+  const int64_t P_plain = P;
+  for (int i = 0; i < ea.ncl; ++i) {
+    const int32_t e = eacell[i];
+    cell.push_back(e);
+    cna.push_back(c->n_e > 0 ? (int32_t)(ep[e + 1] - ep[e]) : 0);
+    pofs.push_back(P);
+    pcnt.push_back((bptr[i + 1] - bptr[i]) * ng3);
+    P += (bptr[i + 1] - bptr[i]) * ng3;
+  }
+  const int nscf = (int)cell.size();
+  for (int32_t e : cell)
+    for (int d = 0; d < 3; ++d) lo.push_back(o->cell_lo[3 * (int64_t)e + d]);
+  // points and weights
+  std::vector<double> xyz((size_t)P * 3), w(P);
+  const double h = ea.h;
+  for (size_t i = 0; i < s.plain_cells.size(); ++i) {
+    const int32_t e = s.plain_cells[i];
+    for (int64_t q = 0; q < nq; ++q) {
+      const int64_t p = (int64_t)i * nq + q;
+      for (int d = 0; d < 3; ++d) xyz[3 * p + d] = o->cell_lo[3 * (int64_t)e + d] + h * o->plain_ref[3 * q + d];
+      w[p] = wq[q];
+    }
+  }
+  const double *gx = tab.data() + ea.np1, *gw = gx + ea.ng;
+  for (int64_t b = 0; b < ea.nbox; ++b)
+    for (int64_t r = 0; r < ng3; ++r) {
+      const int ix = (int)(r % ea.ng), iy = (int)((r / ea.ng) % ea.ng), iz = (int)(r / (ea.ng * ea.ng));
+      const int64_t p = P_plain + b * ng3 + r;
+      const double sd = bsz[b];
+      xyz[3 * p] = blo[3 * b] + sd * gx[ix];
+      xyz[3 * p + 1] = blo[3 * b + 1] + sd * gx[iy];
+      xyz[3 * p + 2] = blo[3 * b + 2] + sd * gx[iz];
+      w[p] = sd * sd * sd * (gw[ix] * gw[iy] * gw[iz]);
+    }
+  // density-matrix items (upper 16 x 16 tiles, at most 64 per item) in batches
+  std::vector<int32_t> it_c, it_t0, it_nt;
+  std::vector<int64_t> doff(nscf, 0);
+  std::vector<int> b_item(1, 0), b_cell(1, 0);
+  int64_t used = 0, dmax = 0;
+  for (int i = 0; i < nscf; ++i) {
+    const int K = NPAD + ((cna[i] + 15) & ~15), nt = K / 16;
+    const int64_t bytes = (int64_t)K * K * (int64_t)sizeof(double);
+    if (used && used + bytes > SCF_DM_BYTES) {
+      b_item.push_back((int)it_c.size());
+      b_cell.push_back(i);
+      used = 0;
+    }
+    doff[i] = used / (int64_t)sizeof(double);
+    used += bytes;
+    dmax = std::max(dmax, used);
+    const int ntiles = nt * (nt + 1) / 2;
+    for (int t0 = 0; t0 < ntiles; t0 += 64) {
+      it_c.push_back(i);
+      it_t0.push_back(t0);
+      it_nt.push_back(std::min(64, ntiles - t0));
+    }
+  }
+  b_item.push_back((int)it_c.size());
+  b_cell.push_back(nscf);
+  // per colour, the SCF cells of that colour
+  std::vector<int32_t> scf_of(E, -1), colscf;
+  for (int i = 0; i < nscf; ++i) scf_of[cell[i]] = i;
+  std::vector<int> cofs(1, 0);
+  for (size_t k = 0; k + 1 < c->col_off.size(); ++k) {
+    for (int q = c->col_off[k]; q < c->col_off[k + 1]; ++q) colscf.push_back(scf_of[colcells[q]]);
+    cofs.push_back((int)colscf.size());
+  }
+  // Poisson: A^C block = K / (2 pi) (K = 1/2 int grad N . grad N), Jacobi diagonal
+  std::vector<double> A(K.size()), diag(c->n_h, 0.0);
+  for (size_t q = 0; q < K.size(); ++q) A[q] = K[q] / (2.0 * M_PI);
+  for (int64_t e = 0; e < E; ++e)
+    for (int a = 0; a < NPAD; ++a) {
+      const int32_t d = dofp[e * NPAD + a];
+      if (d >= 0) diag[d] += A[(size_t)a * NPAD + a];
+    }
+  for (auto &x : diag) {
+    if (!(x > 0.0)) return set_err(c, CF_EINVAL, "scf_setup: non-positive Laplace diagonal");
+    x = 1.0 / x;
+  }
+  std::vector<int32_t> seq(nscf);
+  for (int i = 0; i < nscf; ++i) seq[i] = i;
+  STCHK(dupload(c, s.cell, cell.data(), cell.size()));
+  STCHK(dupload(c, s.cna, cna.data(), cna.size()));
+  STCHK(dupload(c, s.seq, seq.data(), seq.size()));
+  STCHK(dupload(c, s.col_cells, colscf.data(), colscf.size()));
+  STCHK(dupload(c, s.dm_c, it_c.data(), it_c.size()));
+  STCHK(dupload(c, s.dm_t0, it_t0.data(), it_t0.size()));
+  STCHK(dupload(c, s.dm_nt, it_nt.data(), it_nt.size()));
+  STCHK(dupload(c, s.pofs, pofs.data(), pofs.size()));
+  STCHK(dupload(c, s.pcnt, pcnt.data(), pcnt.size()));
+  STCHK(dupload(c, s.doff, doff.data(), doff.size()));
+  STCHK(dupload(c, s.lo, lo.data(), lo.size()));
+  STCHK(dupload(c, s.xyz, xyz.data(), xyz.size()));
+  STCHK(dupload(c, s.w, w.data(), w.size()));
+  STCHK(dupload(c, s.A, A.data(), A.size()));
+  STCHK(dupload(c, s.dinv, diag.data(), diag.size()));
+  dfree(c, s.Dbuf);
+  STCHK(dalloc(c, &s.Dbuf, (size_t)std::max<int64_t>(dmax / (int64_t)sizeof(double), 1)));
+  for (double **v : {&s.pb, &s.px, &s.pr, &s.pz, &s.pp, &s.pq}) {
+    dfree(c, *v);
+    STCHK(dalloc(c, v, (size_t)std::max<int64_t>(c->n_h, 1)));
+  }
+  HIPCHK(c, launch_fill(c->stream, s.px, c->n_h, 0.0));
+  dfree(c, s.vxc);
+  STCHK(dalloc(c, &s.vxc, (size_t)std::max<int64_t>(P, 1)));
+  dfree(c, s.part);
+  STCHK(dalloc(c, &s.part, (size_t)std::max<int64_t>(4 * SCF_RED_BLOCKS, nscf)));
+  dfree(c, s.dot);
+  STCHK(dalloc(c, &s.dot, (size_t)SCF_RED_BLOCKS + 1));
+  dfree(c, s.hin);
+  dfree(c, s.hF);
+  STCHK(dalloc(c, &s.hin, (size_t)std::max<int64_t>(P, 1) * o->mix_depth));
+  STCHK(dalloc(c, &s.hF, (size_t)std::max<int64_t>(P, 1) * o->mix_depth));
+  s.nscf = nscf;
+  s.nplain = (int)s.plain_cells.size();
+  s.nq = (int)nq;
+  s.P = P;
+  s.P_plain = P_plain;
+  for (int d = 0; d < 3; ++d) s.cc[d] = o->comp_center[d];
+  s.cs = o->comp_width;
+  s.cg_max = o->cg_max_iter;
+  s.cg_tol = o->cg_tol;
+  s.depth = o->mix_depth;
+  s.beta = o->mix_beta;
+  s.nhist = s.head = 0;
+  s.gram.assign((size_t)o->mix_depth * o->mix_depth, 0.0);
+  s.dm_item = b_item;
+  s.dm_cell = b_cell;
+  s.col_ofs = cofs;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return CF_OK;
+}
+
+cf_status chebfilter_scf_sizes(const cf_ctx *c, int64_t *npoints, int64_t *nplain_points) {
+  if (!c) return CF_EINVAL;
+  if (npoints) *npoints = c->scf.P;
+  if (nplain_points) *nplain_points = c->scf.P_plain;
+  return CF_OK;
+}
+
+cf_status chebfilter_scf_geometry(cf_ctx *c, double *xyz, double *w) {
+  if (!c) return CF_EINVAL;
+  if (c->scf.P == 0) return set_err(c, CF_EINVAL, "scf_geometry: no SCF setup");
+  HIPCHK(c, hipSetDevice(c->device));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (xyz) HIPCHK(c, hipMemcpy(xyz, c->scf.xyz, c->scf.P * 3 * sizeof(double), hipMemcpyDeviceToHost));
+  if (w) HIPCHK(c, hipMemcpy(w, c->scf.w, c->scf.P * sizeof(double), hipMemcpyDeviceToHost));
+  return CF_OK;
+}
+
+cf_status chebfilter_scf_density(cf_ctx *c, const double *X, int64_t ldx, int64_t N,
+                                 const double *f_host, double *rho) {
+  if (!c) return CF_EINVAL;
+  auto &s = c->scf;
+  if (s.P == 0) return set_err(c, CF_EINVAL, "scf_density: no SCF setup");
+  if (!X || !f_host || !rho || N < 1 || ldx < N) return set_err(c, CF_EINVAL, "scf_density: bad block");
+  for (int64_t j = 0; j < N; ++j)
+    if (!std::isfinite(f_host[j])) return set_err(c, CF_EINVAL, "scf_density: non-finite occupation");
+  HIPCHK(c, hipSetDevice(c->device));
+  if (N > s.f2_cap) {
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    dfree(c, s.f2);
+    STCHK(dalloc(c, &s.f2, (size_t)N));
+    s.f2_cap = N;
+  }
+  std::vector<double> f2(N);
+  for (int64_t j = 0; j < N; ++j) f2[j] = 2.0 * f_host[j];
+  HIPCHK(c, hipMemcpyAsync(s.f2, f2.data(), N * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  const ScfArgs g = scf_args(c);
+  Scope sc(c, "scf_density");
+  for (size_t b = 0; b + 1 < s.dm_item.size(); ++b) {
+    HIPCHK(c, launch_scf_dm(c->stream, g, s.dm_item[b + 1] - s.dm_item[b], s.dm_c + s.dm_item[b],
+                            s.dm_t0 + s.dm_item[b], s.dm_nt + s.dm_item[b], X, ldx, (int)N, s.f2,
+                            s.Dbuf));
+    HIPCHK(c, launch_scf_rho(c->stream, g, s.dm_cell[b + 1] - s.dm_cell[b], s.seq + s.dm_cell[b],
+                             s.Dbuf, rho));
+  }
+  // the host copy of f2 must outlive the asynchronous copy
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return CF_OK;
+}
+
+static cf_status scf_dot(cf_ctx *c, const double *x, const double *y, int64_t n, double *out) {
+  HIPCHK(c, launch_dot(c->stream, n, x, y, c->scf.dot + SCF_RED_BLOCKS, c->scf.dot, SCF_RED_BLOCKS));
+  HIPCHK(c, hipMemcpyAsync(out, c->scf.dot + SCF_RED_BLOCKS, sizeof(double), hipMemcpyDeviceToHost,
+                           c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return CF_OK;
+}
+
+// y = A x over all colours (y zeroed first)
+static cf_status scf_lap(cf_ctx *c, const ScfArgs &g, const double *x, double *y) {
+  auto &s = c->scf;
+  HIPCHK(c, launch_fill(c->stream, y, c->n_h, 0.0));
+  for (size_t k = 0; k + 1 < s.col_ofs.size(); ++k)
+    HIPCHK(c, launch_scf_lap(c->stream, g, s.col_ofs[k + 1] - s.col_ofs[k], s.col_cells + s.col_ofs[k],
+                             s.A, x, y));
+  return CF_OK;
+}
+
+cf_status chebfilter_scf_potential(cf_ctx *c, const double *rho, const double *v_ext, double *v_eff,
+                                   double *terms, int32_t *cg_iters) {
+  if (!c) return CF_EINVAL;
+  auto &s = c->scf;
+  if (s.P == 0) return set_err(c, CF_EINVAL, "scf_potential: no SCF setup");
+  if (!rho || !v_ext || !v_eff || !terms) return set_err(c, CF_EINVAL, "scf_potential: null argument");
+  HIPCHK(c, hipSetDevice(c->device));
+  ScfArgs g = scf_args(c);
+  Scope sc(c, "scf_potential");
+  // LDA and the charge
+  std::vector<double> part(4 * SCF_RED_BLOCKS);
+  HIPCHK(c, launch_scf_lda(c->stream, s.P, rho, s.w, s.vxc, s.part, SCF_RED_BLOCKS));
+  HIPCHK(c, hipMemcpyAsync(part.data(), s.part, part.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  double Q = 0.0, Exc = 0.0, Vxc = 0.0;
+  for (int b = 0; b < SCF_RED_BLOCKS; ++b) {
+    Q += part[4 * b];
+    Exc += part[4 * b + 1];
+    Vxc += part[4 * b + 2];
+  }
+  g.Q = Q;
+  // right-hand side of the neutralised density, colour by colour
+  HIPCHK(c, launch_fill(c->stream, s.pb, c->n_h, 0.0));
+  for (size_t k = 0; k + 1 < s.col_ofs.size(); ++k)
+    HIPCHK(c, launch_scf_rhs(c->stream, g, s.col_ofs[k + 1] - s.col_ofs[k], s.col_cells + s.col_ofs[k],
+                             rho, s.pb));
+  // Jacobi-preconditioned CG from the previous solution
+  double bb = 0.0;
+  STCHK(scf_dot(c, s.pb, s.pb, c->n_h, &bb));
+  // r = b - A x0 (q = A x0)
+  STCHK(scf_lap(c, g, s.px, s.pq));
+  HIPCHK(c, launch_scf_cg(c->stream, c->n_h, 3, 0.0, 0.0, nullptr, nullptr, s.pr, s.pb, nullptr, s.pq));
+  int it = 0;
+  double rr = 0.0, rz = 0.0, rz_old = 0.0;
+  STCHK(scf_dot(c, s.pr, s.pr, c->n_h, &rr));
+  const double stop = s.cg_tol * s.cg_tol * std::max(bb, 1e-300);
+  if (rr > stop) {
+    HIPCHK(c, launch_scf_cg(c->stream, c->n_h, 0, 0.0, 0.0, s.dinv, nullptr, s.pr, s.pz, nullptr, nullptr));
+    HIPCHK(c, launch_copy(c->stream, c->n_h, 1, s.pz, 1, s.pp, 1));
+    STCHK(scf_dot(c, s.pr, s.pz, c->n_h, &rz));
+    for (it = 1; it <= s.cg_max; ++it) {
+      STCHK(scf_lap(c, g, s.pp, s.pq));
+      double pq = 0.0;
+      STCHK(scf_dot(c, s.pp, s.pq, c->n_h, &pq));
+      if (!(pq > 0.0)) return set_err(c, CF_EDEVICE, "scf_potential: CG lost positive definiteness");
+      const double alpha = rz / pq;
+      HIPCHK(c, launch_scf_cg(c->stream, c->n_h, 2, alpha, 0.0, nullptr, s.px, s.pr, nullptr, s.pp, s.pq));
+      STCHK(scf_dot(c, s.pr, s.pr, c->n_h, &rr));
+      if (rr <= stop) break;
+      HIPCHK(c, launch_scf_cg(c->stream, c->n_h, 0, 0.0, 0.0, s.dinv, nullptr, s.pr, s.pz, nullptr, nullptr));
+      rz_old = rz;
+      STCHK(scf_dot(c, s.pr, s.pz, c->n_h, &rz));
+      HIPCHK(c, launch_scf_cg(c->stream, c->n_h, 1, 0.0, rz / rz_old, nullptr, nullptr, nullptr, s.pz,
+                              s.pp, nullptr));
+    }
+  }
+  if (cg_iters) *cg_iters = it;
+  if (rr > stop) return set_err(c, CF_ENOTCONV, "scf_potential: CG did not reach the tolerance");
+  // V_H and V_eff at the points, and sum w rho V_H per SCF cell
+  HIPCHK(c, launch_scf_veff(c->stream, g, s.nscf, s.px, rho, v_ext, s.vxc, v_eff, s.part));
+  std::vector<double> pc(s.nscf);
+  HIPCHK(c, hipMemcpyAsync(pc.data(), s.part, s.nscf * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  double EH = 0.0;
+  for (double x : pc) EH += x;
+  terms[0] = Q;
+  terms[1] = Exc;
+  terms[2] = Vxc;
+  terms[3] = 0.5 * EH;
+  terms[4] = std::sqrt(rr / std::max(bb, 1e-300));
+  return CF_OK;
+}
+
+cf_status chebfilter_scf_assemble(cf_ctx *c, const double *v_eff) {
+  if (!c) return CF_EINVAL;
+  auto &s = c->scf;
+  if (s.P == 0) return set_err(c, CF_EINVAL, "scf_assemble: no SCF setup");
+  if (!v_eff) return set_err(c, CF_EINVAL, "scf_assemble: null potential");
+  if (s.nplain > 0)
+    STCHK(chebfilter_assemble_cells(c, s.plain_cells.data(), s.nplain, v_eff, s.nq));
+  return chebfilter_assemble_enriched(c, v_eff + s.P_plain);
+}
+
+static cf_status scf_wdot(cf_ctx *c, const double *a, const double *b, double *out) {
+  auto &s = c->scf;
+  std::vector<double> part(SCF_RED_BLOCKS);
+  HIPCHK(c, launch_scf_wdot(c->stream, s.P, s.w, a, b, s.part, SCF_RED_BLOCKS));
+  HIPCHK(c, hipMemcpyAsync(part.data(), s.part, SCF_RED_BLOCKS * sizeof(double), hipMemcpyDeviceToHost,
+                           c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  double v = 0.0;
+  for (double x : part) v += x;
+  *out = v;
+  return CF_OK;
+}
+
+cf_status chebfilter_scf_mix(cf_ctx *c, const double *rho_in, const double *rho_out, double *rho_next,
+                             double *res_norm) {
+  if (!c) return CF_EINVAL;
+  auto &s = c->scf;
+  if (s.P == 0) return set_err(c, CF_EINVAL, "scf_mix: no SCF setup");
+  if (!rho_in || !rho_out || !rho_next) return set_err(c, CF_EINVAL, "scf_mix: null argument");
+  HIPCHK(c, hipSetDevice(c->device));
+  const int slot = s.head, D = s.depth;
+  HIPCHK(c, launch_scf_push(c->stream, s.P, rho_in, rho_out, s.hin + (int64_t)slot * s.P,
+                            s.hF + (int64_t)slot * s.P));
+  s.nhist = std::min(s.nhist + 1, D);
+  s.head = (s.head + 1) % D;
+  for (int k = 0; k < s.nhist; ++k) {
+    double v = 0.0;
+    STCHK(scf_wdot(c, s.hF + (int64_t)slot * s.P, s.hF + (int64_t)k * s.P, &v));
+    s.gram[(size_t)slot * D + k] = v;
+    s.gram[(size_t)k * D + slot] = v;
+  }
+  if (res_norm) *res_norm = std::sqrt(std::max(s.gram[(size_t)slot * D + slot], 0.0));
+  // [G 1; 1^T 0] [c; lambda] = [0; 1] by Gaussian elimination with partial pivoting
+  const int m = s.nhist, n = m + 1;
+  std::vector<double> M((size_t)n * (n + 1), 0.0);
+  for (int i = 0; i < m; ++i) {
+    for (int j = 0; j < m; ++j) M[(size_t)i * (n + 1) + j] = s.gram[(size_t)i * D + j];
+    M[(size_t)i * (n + 1) + m] = 1.0;
+    M[(size_t)m * (n + 1) + i] = 1.0;
+  }
+  M[(size_t)m * (n + 1) + n] = 1.0;
+  for (int col = 0; col < n; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < n; ++r)
+      if (std::fabs(M[(size_t)r * (n + 1) + col]) > std::fabs(M[(size_t)piv * (n + 1) + col])) piv = r;
+    if (M[(size_t)piv * (n + 1) + col] == 0.0) return set_err(c, CF_EINVAL, "scf_mix: singular history");
+    if (piv != col)
+      for (int j = 0; j <= n; ++j) std::swap(M[(size_t)piv * (n + 1) + j], M[(size_t)col * (n + 1) + j]);
+    for (int r = 0; r < n; ++r) {
+      if (r == col) continue;
+      const double f = M[(size_t)r * (n + 1) + col] / M[(size_t)col * (n + 1) + col];
+      if (f == 0.0) continue;
+      for (int j = col; j <= n; ++j) M[(size_t)r * (n + 1) + j] -= f * M[(size_t)col * (n + 1) + j];
+    }
+  }
+  ScfMixCoef cf;
+  for (int k = 0; k < 8; ++k) cf.c[k] = 0.0;
+  for (int k = 0; k < m; ++k) cf.c[k] = M[(size_t)k * (n + 1) + n] / M[(size_t)k * (n + 1) + k];
+  HIPCHK(c, launch_scf_mix(c->stream, s.P, m, cf, s.beta, s.hin, s.hF, s.P, rho_next));
+  return CF_OK;
+}
+
+cf_status chebfilter_scf_mix_reset(cf_ctx *c) {
+  if (!c) return CF_EINVAL;
+  c->scf.nhist = c->scf.head = 0;
   return CF_OK;
 }
 

@@ -380,6 +380,55 @@ hipError_t launch_ea_ee_reduce(hipStream_t s, const EnrAsm &a, int n_e, int npai
 // X[i][j] = (i == j0 + j), i < rows, j < N.
 hipError_t launch_unit_cols(hipStream_t s, int64_t rows, int N, int64_t ldx, int64_t j0, double *X);
 
+// ---- self-consistent field quantities (cf_scf.hip)
+// Cells of the SCF point set ("SCF cells": the plain cells, then the cells
+// with an adaptive rule): cell index, enrichment count, lower corner, the
+// range of their points in the point arrays, density-matrix offsets.
+struct ScfArgs {
+  int64_t n_h = 0;
+  int np1 = 0, ng = 0, nsh = 0, npa = 0, ntab = 0;
+  double h = 0.0, r0 = 0.0, t = 0.0;
+  const double *tab = nullptr;       // EnrAsm::tab layout (nodes first)
+  const double *centers = nullptr;
+  const int32_t *dofp = nullptr;
+  const int64_t *eptr = nullptr;
+  const int32_t *eidx = nullptr;
+  const int32_t *cell = nullptr;
+  const int32_t *cna = nullptr;
+  const double *lo = nullptr;
+  const int64_t *pofs = nullptr, *pcnt = nullptr;
+  const int64_t *doff = nullptr;
+  const double *xyz = nullptr, *w = nullptr;
+  double cc[3] = {0.0, 0.0, 0.0};    // neutralising Gaussian: centre, width, charge
+  double cs = 1.0, Q = 0.0;
+};
+struct ScfMixCoef {
+  double c[8];
+};
+hipError_t launch_scf_dm(hipStream_t s, const ScfArgs &g, int nitems, const int32_t *item_c,
+                         const int32_t *item_t0, const int32_t *item_nt, const double *X,
+                         int64_t ldx, int N, const double *f2, double *Dbuf);
+hipError_t launch_scf_rho(hipStream_t s, const ScfArgs &g, int ncells, const int32_t *cells,
+                          const double *Dbuf, double *rho);
+hipError_t launch_scf_lda(hipStream_t s, int64_t P, const double *rho, const double *w, double *vxc,
+                          double *partials, int nblocks);
+hipError_t launch_scf_rhs(hipStream_t s, const ScfArgs &g, int ncells, const int32_t *cells,
+                          const double *rho, double *b);
+hipError_t launch_scf_lap(hipStream_t s, const ScfArgs &g, int ncells, const int32_t *cells,
+                          const double *A, const double *x, double *y);
+hipError_t launch_scf_cg(hipStream_t s, int64_t n, int op, double alpha, double beta,
+                         const double *dinv, double *x, double *r, double *z, double *p,
+                         const double *q);
+hipError_t launch_scf_veff(hipStream_t s, const ScfArgs &g, int ncells, const double *phi,
+                           const double *rho, const double *vext, const double *vxc, double *veff,
+                           double *partials);
+hipError_t launch_scf_wdot(hipStream_t s, int64_t P, const double *w, const double *a,
+                           const double *b, double *partials, int nblocks);
+hipError_t launch_scf_mix(hipStream_t s, int64_t P, int m, const ScfMixCoef &cf, double beta,
+                          const double *rin, const double *F, int64_t ld, double *out);
+hipError_t launch_scf_push(hipStream_t s, int64_t P, const double *rin, const double *rout,
+                           double *hin, double *hF);
+
 // ---- data-movement helpers (cf_dense.hip)
 hipError_t launch_sub(hipStream_t s, int64_t n, const double *A, const double *B, double *C);
 hipError_t launch_transpose(hipStream_t s, int N, const double *In, int64_t ldi, double *Out);

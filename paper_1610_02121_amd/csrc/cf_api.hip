@@ -155,6 +155,8 @@ struct cf_ctx {
     double cc[3] = {0.0, 0.0, 0.0}, cs = 1.0, cg_tol = 0.0, beta = 0.0;
     int32_t *cell = nullptr, *cna = nullptr, *seq = nullptr, *col_cells = nullptr;
     int32_t *dm_c = nullptr, *dm_t0 = nullptr, *dm_nt = nullptr;
+    int32_t *rho_c = nullptr, *rho_t0 = nullptr, *rho_nt = nullptr;
+    std::vector<int> rho_off;                     // per batch and range index: first item
     int64_t *pofs = nullptr, *pcnt = nullptr, *doff = nullptr;
     double *lo = nullptr, *xyz = nullptr, *w = nullptr, *Dbuf = nullptr, *f2 = nullptr;
     int64_t f2_cap = 0;
@@ -3030,6 +3032,26 @@ cf_status chebfilter_scf_setup(cf_ctx *c, const cf_scf_setup *o) {
   }
   b_item.push_back((int)it_c.size());
   b_cell.push_back(nscf);
+  // density items per batch and range index r: the upper tiles
+  // [r SCF_RHO_TILES, (r + 1) SCF_RHO_TILES) of every cell that has them; the
+  // items of range 0 write rho, each later range adds in a launch of its own
+  // (so that one launch never holds two items of one cell)
+  std::vector<int32_t> r_c, r_t0, r_nt;
+  std::vector<int> r_off;
+  const int nrange = (ea_max_tiles(NPAD + EA_MAXNAP) + SCF_RHO_TILES - 1) / SCF_RHO_TILES;
+  for (size_t b = 0; b + 1 < b_cell.size(); ++b)
+    for (int r = 0; r < nrange; ++r) {
+      r_off.push_back((int)r_c.size());
+      for (int i = b_cell[b]; i < b_cell[b + 1]; ++i) {
+        const int K = NPAD + ((cna[i] + 15) & ~15), ntiles = ea_max_tiles(K);
+        const int t0 = r * SCF_RHO_TILES;
+        if (t0 >= ntiles) continue;
+        r_c.push_back(i);
+        r_t0.push_back(t0);
+        r_nt.push_back(std::min(SCF_RHO_TILES, ntiles - t0));
+      }
+    }
+  r_off.push_back((int)r_c.size());
   // per colour, the SCF cells of that colour
   std::vector<int32_t> scf_of(E, -1), colscf;
   for (int i = 0; i < nscf; ++i) scf_of[cell[i]] = i;
@@ -3059,6 +3081,10 @@ cf_status chebfilter_scf_setup(cf_ctx *c, const cf_scf_setup *o) {
   STCHK(dupload(c, s.dm_c, it_c.data(), it_c.size()));
   STCHK(dupload(c, s.dm_t0, it_t0.data(), it_t0.size()));
   STCHK(dupload(c, s.dm_nt, it_nt.data(), it_nt.size()));
+  STCHK(dupload(c, s.rho_c, r_c.data(), r_c.size()));
+  STCHK(dupload(c, s.rho_t0, r_t0.data(), r_t0.size()));
+  STCHK(dupload(c, s.rho_nt, r_nt.data(), r_nt.size()));
+  s.rho_off = r_off;
   STCHK(dupload(c, s.pofs, pofs.data(), pofs.size()));
   STCHK(dupload(c, s.pcnt, pcnt.data(), pcnt.size()));
   STCHK(dupload(c, s.doff, doff.data(), doff.size()));
@@ -3145,8 +3171,12 @@ cf_status chebfilter_scf_density(cf_ctx *c, const double *X, int64_t ldx, int64_
     HIPCHK(c, launch_scf_dm(c->stream, g, s.dm_item[b + 1] - s.dm_item[b], s.dm_c + s.dm_item[b],
                             s.dm_t0 + s.dm_item[b], s.dm_nt + s.dm_item[b], X, ldx, (int)N, s.f2,
                             s.Dbuf));
-    HIPCHK(c, launch_scf_rho(c->stream, g, s.dm_cell[b + 1] - s.dm_cell[b], s.seq + s.dm_cell[b],
-                             s.Dbuf, rho));
+    const int nrange = (int)(s.rho_off.size() - 1) / (int)(s.dm_item.size() - 1);
+    for (int r = 0; r < nrange; ++r) {
+      const int i0 = s.rho_off[b * nrange + r], i1 = s.rho_off[b * nrange + r + 1];
+      HIPCHK(c, launch_scf_rho(c->stream, g, i1 - i0, s.rho_c + i0, s.rho_t0 + i0, s.rho_nt + i0,
+                               r > 0, s.Dbuf, rho));
+    }
   }
   // the host copy of f2 must outlive the asynchronous copy
   HIPCHK(c, hipStreamSynchronize(c->stream));

@@ -123,12 +123,15 @@ __global__ __launch_bounds__(256) void k_ea_nn(const EnrAsm a) {
 // Enrichment rows: work item = (slot, first tile, tile count <= 4 EA_TPW).  The
 // slot's tiles are the enriched-classical tiles (ti, tj), ti < nap/16, tj < 8,
 // row by row, then the upper enriched-enriched tiles (ti <= tj) row by row.
-// Wave w takes the item's tiles w, w + 4, ...  Each stage is 4 points (one MFMA
-// step): the 1D Lagrange values and derivatives, the weights, then every
+// Wave w takes the item's tiles w, w + 4, ...  Each stage is EA_P points (two
+// MFMA steps): the 1D Lagrange values and derivatives, the weights, then every
 // enrichment function's value and gradient (one thread per (point, atom)), then
-// N_a and its gradient; per tile 4 MFMAs (the potential term and the three
-// gradient terms) with A = scaled enrichment values, B = the column functions.
+// N_a and its gradient; per tile and step 4 MFMAs (the potential term and the
+// three gradient terms) with A = scaled enrichment values, B = the column
+// functions.
 // ---------------------------------------------------------------------------
+constexpr int EA_P = 8;                        // points per stage of the enrichment rows
+
 __device__ __forceinline__ void ea_tile(int t, int nte, int &ti, int &tj, bool &ee) {
   if (t < 8 * nte) { ti = t / 8; tj = t % 8; ee = false; return; }
   int u = t - 8 * nte, i = 0;
@@ -138,10 +141,10 @@ __device__ __forceinline__ void ea_tile(int t, int nte, int &ti, int &tj, bool &
 
 __global__ __launch_bounds__(256) void k_ea_erow(const EnrAsm a) {
   __shared__ double stab[EA_TAB_MAX];
-  __shared__ double L1[4][3][2][EA_MAXNP];
-  __shared__ double sV[4], sK[4];
-  __shared__ double Nv[4][4][NPAD];            // [channel][point][a]
-  __shared__ double Ev[4][4][EA_MAXNAP];       // [channel][point][alpha]
+  __shared__ double L1[EA_P][3][2][EA_MAXNP];
+  __shared__ double sV[EA_P], sK[EA_P];
+  __shared__ double Nv[4][EA_P][NPAD];         // [channel][point][a]
+  __shared__ double Ev[4][EA_P][EA_MAXNAP];    // [channel][point][alpha]
   __shared__ int atom[EA_MAXNAP];
   const int item = blockIdx.x;
   const int slot = a.item_slot[item], t0 = a.item_t0[item], ntl = a.item_nt[item];
@@ -155,7 +158,7 @@ __global__ __launch_bounds__(256) void k_ea_erow(const EnrAsm a) {
   const int nat = na / a.npa;
   for (int u = tid; u < nat; u += 256) atom[u] = a.eidx[e0 + (int64_t)u * a.npa] / a.npa;
   // padding columns of the enrichment rows stay zero for the whole call
-  for (int i = tid; i < 4 * 4 * EA_MAXNAP; i += 256) (&Ev[0][0][0])[i] = 0.0;
+  for (int i = tid; i < 4 * EA_P * EA_MAXNAP; i += 256) (&Ev[0][0][0])[i] = 0.0;
   __syncthreads();
   const EaTab t = ea_tab(stab, a);
   const int np1 = a.np1, npc = np1 * np1 * np1;
@@ -172,8 +175,8 @@ __global__ __launch_bounds__(256) void k_ea_erow(const EnrAsm a) {
     on[u] = tl < ntl;
     ea_tile(on[u] ? t0 + tl : 0, nte, ti[u], tj[u], ee[u]);
   }
-  for (int64_t q0 = 0; q0 < nq; q0 += 4) {
-    if (tid < 12) {
+  for (int64_t q0 = 0; q0 < nq; q0 += EA_P) {
+    if (tid < 3 * EA_P) {
       const int k = tid / 3, d = tid % 3;
       double x[3], wt, v;
       if (ea_point(a, t, slot, q0 + k, x, wt, v)) {
@@ -185,7 +188,7 @@ __global__ __launch_bounds__(256) void k_ea_erow(const EnrAsm a) {
         if (d == 0) { sV[k] = 0.0; sK[k] = 0.0; }
       }
     }
-    for (int j = tid - 64; j >= 0 && j < 4 * nat; j += 192) {
+    for (int j = tid - 64; j >= 0 && j < EA_P * nat; j += 192) {
       const int k = j / nat, u = j % nat;
       double x[3], wt, v;
       if (ea_point(a, t, slot, q0 + k, x, wt, v)) {
@@ -198,7 +201,7 @@ __global__ __launch_bounds__(256) void k_ea_erow(const EnrAsm a) {
       }
     }
     __syncthreads();
-    for (int j = tid; j < 4 * NPAD; j += 256) {
+    for (int j = tid; j < EA_P * NPAD; j += 256) {
       const int k = j / NPAD, c = j % NPAD;
       double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
       if (c < npc) {
@@ -212,24 +215,28 @@ __global__ __launch_bounds__(256) void k_ea_erow(const EnrAsm a) {
       Nv[0][k][c] = v0; Nv[1][k][c] = v1; Nv[2][k][c] = v2; Nv[3][k][c] = v3;
     }
     __syncthreads();
-    const double s0 = sV[kq], s1 = sK[kq];
 #pragma unroll
-    for (int u = 0; u < EA_TPW; ++u) {
-      if (!on[u]) continue;
-      const int ra = 16 * ti[u] + li;
-      const double a0 = Ev[0][kq][ra] * s0, a1 = Ev[1][kq][ra] * s1, a2 = Ev[2][kq][ra] * s1,
-                   a3 = Ev[3][kq][ra] * s1;
-      const int cb = 16 * tj[u] + li;
-      double b0, b1, b2, b3;
-      if (ee[u]) {
-        b0 = Ev[0][kq][cb]; b1 = Ev[1][kq][cb]; b2 = Ev[2][kq][cb]; b3 = Ev[3][kq][cb];
-      } else {
-        b0 = Nv[0][kq][cb]; b1 = Nv[1][kq][cb]; b2 = Nv[2][kq][cb]; b3 = Nv[3][kq][cb];
+    for (int ks = 0; ks < EA_P / 4; ++ks) {
+      const int k = 4 * ks + kq;
+      const double s0 = sV[k], s1 = sK[k];
+#pragma unroll
+      for (int u = 0; u < EA_TPW; ++u) {
+        if (!on[u]) continue;
+        const int ra = 16 * ti[u] + li;
+        const double a0 = Ev[0][k][ra] * s0, a1 = Ev[1][k][ra] * s1, a2 = Ev[2][k][ra] * s1,
+                     a3 = Ev[3][k][ra] * s1;
+        const int cb = 16 * tj[u] + li;
+        double b0, b1, b2, b3;
+        if (ee[u]) {
+          b0 = Ev[0][k][cb]; b1 = Ev[1][k][cb]; b2 = Ev[2][k][cb]; b3 = Ev[3][k][cb];
+        } else {
+          b0 = Nv[0][k][cb]; b1 = Nv[1][k][cb]; b2 = Nv[2][k][cb]; b3 = Nv[3][k][cb];
+        }
+        acc[u] = ea_mfma(a0, b0, acc[u]);
+        acc[u] = ea_mfma(a1, b1, acc[u]);
+        acc[u] = ea_mfma(a2, b2, acc[u]);
+        acc[u] = ea_mfma(a3, b3, acc[u]);
       }
-      acc[u] = ea_mfma(a0, b0, acc[u]);
-      acc[u] = ea_mfma(a1, b1, acc[u]);
-      acc[u] = ea_mfma(a2, b2, acc[u]);
-      acc[u] = ea_mfma(a3, b3, acc[u]);
     }
     __syncthreads();
   }

@@ -119,7 +119,8 @@ constexpr int RHO_P = 16;
 constexpr int PHI_LD = DM_KMAX + 1;
 
 __device__ void scf_stage_basis(const ScfArgs &g, const EaTab &t, int c, int64_t p0, int np,
-                                int na, const int *atom, double (*L1)[3][EA_MAXNP], double *Phi) {
+                                int na, const int *atom, double (*L1)[3][EA_MAXNP], double *Phi,
+                                int nthr) {
   const int tid = threadIdx.x, np1 = g.np1, npc = np1 * np1 * np1;
   if (tid < RHO_P * 3) {
     const int k = tid / 3, d = tid % 3;
@@ -138,7 +139,7 @@ __device__ void scf_stage_basis(const ScfArgs &g, const EaTab &t, int c, int64_t
     ea.nsh = g.nsh;
     ea.r0 = g.r0;
     ea.t = g.t;
-    for (int j = tid - 64; j >= 0 && j < RHO_P * nat; j += 192) {
+    for (int j = tid - 64; j >= 0 && j < RHO_P * nat; j += nthr - 64) {
       const int k = j / nat, u = j % nat;
       double *row = Phi + k * PHI_LD + NPAD;
       if (k < np) {
@@ -151,7 +152,7 @@ __device__ void scf_stage_basis(const ScfArgs &g, const EaTab &t, int c, int64_t
     }
   }
   __syncthreads();
-  for (int q = tid; q < RHO_P * NPAD; q += 256) {
+  for (int q = tid; q < RHO_P * NPAD; q += nthr) {
     const int k = q / NPAD, a = q % NPAD;
     double v = 0.0;
     if (a < npc) v = L1[k][0][a % np1] * L1[k][1][(a / np1) % np1] * L1[k][2][a / (np1 * np1)];
@@ -160,24 +161,53 @@ __device__ void scf_stage_basis(const ScfArgs &g, const EaTab &t, int c, int64_t
   __syncthreads();
 }
 
-// rho_q = Phi_q^T D_e Phi_q for the points of one cell per workgroup
-__global__ __launch_bounds__(256) void k_scf_rho(const ScfArgs g, const int32_t *__restrict__ cells,
+// rho_q = Phi_q^T D_e Phi_q = sum over upper 16 x 16 tiles (ta <= tb) of D_e of
+// (2 - [ta == tb]) (Phi_q,ta D_ta,tb) . Phi_q,tb.  One work item = (SCF cell,
+// a range of at most 8 RHO_TPW upper tiles); its 8 waves keep their tiles of
+// D_e in registers (as MFMA B fragments) for the whole cell, so the stage
+// loop over the cell's points reads only LDS.  Items of the first range write
+// rho, those of later ranges (cells with more tiles) add to it in a later
+// launch.
+constexpr int RHO_TPW = 12;
+static_assert(8 * RHO_TPW == SCF_RHO_TILES, "density items hold 8 waves of RHO_TPW tiles");
+
+__global__ __launch_bounds__(512) void k_scf_rho(const ScfArgs g, const int32_t *__restrict__ item_c,
+                                                 const int32_t *__restrict__ item_t0,
+                                                 const int32_t *__restrict__ item_nt, int add,
                                                  const double *__restrict__ Dbuf,
                                                  double *__restrict__ rho) {
   __shared__ double stab[EA_TAB_MAX];
   __shared__ double L1[RHO_P][3][EA_MAXNP];
   __shared__ double Phi[RHO_P * PHI_LD];
-  __shared__ double part[4][RHO_P];
+  __shared__ double part[8][RHO_P];
   __shared__ int atom[EA_MAXNAP];
-  const int c = cells[blockIdx.x];
+  const int c = item_c[blockIdx.x], t0 = item_t0[blockIdx.x], ntl = item_nt[blockIdx.x];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, kq = lane >> 4;
-  for (int i = tid; i < g.ntab; i += 256) stab[i] = g.tab[i];
+  for (int i = tid; i < g.ntab; i += 512) stab[i] = g.tab[i];
   const int e = g.cell[c];
   const int na = g.cna[c];
   if (na > 0)
-    for (int u = tid; u < na / g.npa; u += 256) atom[u] = g.eidx[g.eptr[e] + (int64_t)u * g.npa] / g.npa;
-  for (int i = tid; i < RHO_P * PHI_LD; i += 256) Phi[i] = 0.0;
+    for (int u = tid; u < na / g.npa; u += 512) atom[u] = g.eidx[g.eptr[e] + (int64_t)u * g.npa] / g.npa;
+  for (int i = tid; i < RHO_P * PHI_LD; i += 512) Phi[i] = 0.0;
+  const int K = NPAD + ((na + 15) & ~15), nt = K / 16;
+  const double *D = Dbuf + g.doff[c];
+  // this wave's tiles and their D fragments: B[k][j] = D[16 ta + k][16 tb + j]
+  int ta[RHO_TPW], tb[RHO_TPW];
+  bool on[RHO_TPW];
+  double dB[RHO_TPW][4];
+#pragma unroll
+  for (int u = 0; u < RHO_TPW; ++u) {
+    const int tl = w + 8 * u;
+    on[u] = tl < ntl;
+    int t = on[u] ? t0 + tl : 0, i = 0;
+    while (t >= nt - i) { t -= nt - i; ++i; }
+    ta[u] = i;
+    tb[u] = i + t;
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+      dB[u][s] = on[u] ? D[(int64_t)(16 * ta[u] + 4 * s + kq) * K + 16 * tb[u] + li] : 0.0;
+  }
   __syncthreads();
   EaTab t;
   {
@@ -187,26 +217,21 @@ __global__ __launch_bounds__(256) void k_scf_rho(const ScfArgs g, const int32_t 
     ea.nsh = g.nsh;
     t = ea_tab(stab, ea);
   }
-  const int K = NPAD + ((na + 15) & ~15), nt = K / 16;
-  const double *D = Dbuf + g.doff[c];
   const int64_t p0 = g.pofs[c], np = g.pcnt[c];
   for (int64_t q0 = 0; q0 < np; q0 += RHO_P) {
     const int ns = (int)min<int64_t>(RHO_P, np - q0);
-    scf_stage_basis(g, t, c, p0 + q0, ns, na, atom, L1, Phi);
+    scf_stage_basis(g, t, c, p0 + q0, ns, na, atom, L1, Phi, 512);
     double pr[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int tjc = w; tjc < nt; tjc += 4) {
+#pragma unroll
+    for (int u = 0; u < RHO_TPW; ++u) {
+      if (!on[u]) continue;
       d4 acc = d4{0.0, 0.0, 0.0, 0.0};
-      const int col = 16 * tjc + li;
-      for (int tk = 0; tk < nt; ++tk) {
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          const int k = 16 * tk + 4 * s + kq;
-          const double dk = k <= col ? D[(int64_t)k * K + col] : D[(int64_t)col * K + k];
-          acc = scf_mfma(Phi[li * PHI_LD + 16 * tk + 4 * s + kq], dk, acc);
-        }
-      }
+      for (int s = 0; s < 4; ++s)
+        acc = scf_mfma(Phi[li * PHI_LD + 16 * ta[u] + 4 * s + kq], dB[u][s], acc);
+      const double f = ta[u] == tb[u] ? 1.0 : 2.0;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) pr[r] += acc[r] * Phi[(4 * r + kq) * PHI_LD + col];
+      for (int r = 0; r < 4; ++r) pr[r] += f * acc[r] * Phi[(4 * r + kq) * PHI_LD + 16 * tb[u] + li];
     }
     // sum over the 16 lanes of a row group (li), then over the waves in order
 #pragma unroll
@@ -220,7 +245,11 @@ __global__ __launch_bounds__(256) void k_scf_rho(const ScfArgs g, const int32_t 
       for (int r = 0; r < 4; ++r) part[w][4 * r + kq] = pr[r];
     }
     __syncthreads();
-    if (tid < ns) rho[p0 + q0 + tid] = ((part[0][tid] + part[1][tid]) + part[2][tid]) + part[3][tid];
+    if (tid < ns) {
+      double v = part[0][tid];
+      for (int k = 1; k < 8; ++k) v += part[k][tid];
+      rho[p0 + q0 + tid] = add ? rho[p0 + q0 + tid] + v : v;
+    }
     __syncthreads();
   }
 }
@@ -290,17 +319,28 @@ __device__ __forceinline__ void scf_gauss(const ScfArgs &g, const double *x, dou
   vg = d < 1e-8 * s ? g.Q * 2.0 / (sqrt(PI) * s) : g.Q * erf(d / s) / d;
 }
 
+// the neutralising Gaussian's density at a point
+__device__ __forceinline__ double scf_gauss_rho(const ScfArgs &g, const double *x) {
+  constexpr double PI = 3.14159265358979323846;
+  const double dx = x[0] - g.cc[0], dy = x[1] - g.cc[1], dz = x[2] - g.cc[2];
+  const double s = g.cs;
+  return g.Q / (s * s * s * PI * sqrt(PI)) * exp(-(dx * dx + dy * dy + dz * dz) / (s * s));
+}
+
 // ---------------------------------------------------------------------------
 // Poisson right-hand side of the cells of one colour: b[dof(e,a)] += sum_q
-// w_q (rho - rho_g)_q N_a(x_q); thread a of a 128-thread workgroup, stages of
-// 16 points.
+// w_q (rho - rho_g)_q N_a(x_q).  128 threads; a stage is 128 points, thread k
+// evaluating point k's 1D Lagrange values and weight, then thread a summing
+// over the stage's points for its node a.
 // ---------------------------------------------------------------------------
+constexpr int RHS_P = NPAD;
+
 __global__ __launch_bounds__(NPAD) void k_scf_rhs(const ScfArgs g, const int32_t *__restrict__ cells,
                                                   const double *__restrict__ rho,
                                                   double *__restrict__ b) {
   __shared__ double stab[EA_TAB_MAX];
-  __shared__ double L1[RHO_P][3][EA_MAXNP];
-  __shared__ double sv[RHO_P];
+  __shared__ double L1[RHS_P][3][EA_MAXNP];
+  __shared__ double sv[RHS_P];
   const int c = cells[blockIdx.x];
   const int tid = threadIdx.x, np1 = g.np1, npc = np1 * np1 * np1;
   for (int i = tid; i < g.ntab; i += NPAD) stab[i] = g.tab[i];
@@ -310,27 +350,14 @@ __global__ __launch_bounds__(NPAD) void k_scf_rhs(const ScfArgs g, const int32_t
   const int64_t p0 = g.pofs[c], np = g.pcnt[c];
   const int i0 = tid % np1, i1 = (tid / np1) % np1, i2 = tid / (np1 * np1);
   double acc = 0.0;
-  for (int64_t q0 = 0; q0 < np; q0 += RHO_P) {
-    const int ns = (int)min<int64_t>(RHO_P, np - q0);
-    if (tid < RHO_P * 3) {
-      const int k = tid / 3, d = tid % 3;
+  for (int64_t q0 = 0; q0 < np; q0 += RHS_P) {
+    const int ns = (int)min<int64_t>(RHS_P, np - q0);
+    if (tid < ns) {
+      const int64_t p = p0 + q0 + tid;
       double dummy[EA_MAXNP];
-      if (k < ns) {
-        const double x = g.xyz[3 * (p0 + q0 + k) + d];
-        ea_lagrange(nodes, np1, (x - g.lo[3 * c + d]) / g.h, L1[k][d], dummy);
-      } else {
-        for (int i = 0; i < np1; ++i) L1[k][d][i] = 0.0;
-      }
-    } else if (tid >= 64 && tid < 64 + RHO_P) {
-      const int k = tid - 64;
-      double s = 0.0;
-      if (k < ns) {
-        const int64_t p = p0 + q0 + k;
-        double rg, vg;
-        scf_gauss(g, g.xyz + 3 * p, rg, vg);
-        s = g.w[p] * (rho[p] - rg);
-      }
-      sv[k] = s;
+      for (int d = 0; d < 3; ++d)
+        ea_lagrange(nodes, np1, (g.xyz[3 * p + d] - g.lo[3 * c + d]) / g.h, L1[tid][d], dummy);
+      sv[tid] = g.w[p] * (rho[p] - scf_gauss_rho(g, g.xyz + 3 * p));
     }
     __syncthreads();
     if (tid < npc)
@@ -487,10 +514,12 @@ hipError_t launch_scf_dm(hipStream_t s, const ScfArgs &g, int nitems, const int3
   return hipGetLastError();
 }
 
-hipError_t launch_scf_rho(hipStream_t s, const ScfArgs &g, int ncells, const int32_t *cells,
+hipError_t launch_scf_rho(hipStream_t s, const ScfArgs &g, int nitems, const int32_t *item_c,
+                          const int32_t *item_t0, const int32_t *item_nt, int add,
                           const double *Dbuf, double *rho) {
-  if (ncells <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_scf_rho, dim3((unsigned)ncells), dim3(256), 0, s, g, cells, Dbuf, rho);
+  if (nitems <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scf_rho, dim3((unsigned)nitems), dim3(512), 0, s, g, item_c, item_t0,
+                     item_nt, add, Dbuf, rho);
   return hipGetLastError();
 }
 

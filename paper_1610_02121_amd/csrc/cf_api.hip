@@ -155,7 +155,7 @@ struct cf_ctx {
     double cc[3] = {0.0, 0.0, 0.0}, cs = 1.0, cg_tol = 0.0, beta = 0.0;
     int32_t *cell = nullptr, *cna = nullptr, *seq = nullptr, *col_cells = nullptr;
     int32_t *dm_c = nullptr, *dm_t0 = nullptr, *dm_nt = nullptr;
-    int32_t *rho_c = nullptr, *rho_t0 = nullptr, *rho_nt = nullptr;
+    int32_t *rho_c = nullptr, *rho_t0 = nullptr, *rho_nt = nullptr, *rho_q0 = nullptr;
     std::vector<int> rho_off;                     // per batch and range index: first item
     int64_t *pofs = nullptr, *pcnt = nullptr, *doff = nullptr;
     double *lo = nullptr, *xyz = nullptr, *w = nullptr, *Dbuf = nullptr, *f2 = nullptr;
@@ -2699,6 +2699,26 @@ cf_status chebfilter_enriched_tables(cf_ctx *c, const cf_adaptive_grid *g) {
         pc.push_back(ent[q][4]);
       }
       if (!ent.empty()) pair_ptr.push_back((int64_t)pc.size() / 3);
+      // the batch's items in decreasing order of work (points times tiles):
+      // the longest workgroups start first
+      {
+        const size_t i0 = (size_t)b_item.back(), i1 = it_slot.size();
+        std::vector<size_t> ord(i1 - i0);
+        for (size_t q = 0; q < ord.size(); ++q) ord[q] = i0 + q;
+        auto work = [&](size_t q) {
+          return (g->box_ptr[it_slot[q] + 1] - g->box_ptr[it_slot[q]]) * (int64_t)it_nt[q];
+        };
+        std::stable_sort(ord.begin(), ord.end(), [&](size_t x, size_t y) { return work(x) > work(y); });
+        std::vector<int32_t> a(ord.size()), b2(ord.size()), c2(ord.size());
+        for (size_t q = 0; q < ord.size(); ++q) {
+          a[q] = it_slot[ord[q]];
+          b2[q] = it_t0[ord[q]];
+          c2[q] = it_nt[ord[q]];
+        }
+        std::copy(a.begin(), a.end(), it_slot.begin() + i0);
+        std::copy(b2.begin(), b2.end(), it_t0.begin() + i0);
+        std::copy(c2.begin(), c2.end(), it_nt.begin() + i0);
+      }
       b_item.push_back((int)it_slot.size());
       b_pair.push_back((int)pair_ij.size() / 2);
       pee_max = std::max(pee_max, used);
@@ -3036,19 +3056,33 @@ cf_status chebfilter_scf_setup(cf_ctx *c, const cf_scf_setup *o) {
   // [r SCF_RHO_TILES, (r + 1) SCF_RHO_TILES) of every cell that has them; the
   // items of range 0 write rho, each later range adds in a launch of its own
   // (so that one launch never holds two items of one cell)
-  std::vector<int32_t> r_c, r_t0, r_nt;
+  // Each range's items are cut into chunks of at most SCF_RHO_QCHUNK points
+  // and ordered by decreasing work (points times tiles), so that the longest
+  // start first.
+  std::vector<int32_t> r_c, r_t0, r_nt, r_q0;
   std::vector<int> r_off;
   const int nrange = (ea_max_tiles(NPAD + EA_MAXNAP) + SCF_RHO_TILES - 1) / SCF_RHO_TILES;
   for (size_t b = 0; b + 1 < b_cell.size(); ++b)
     for (int r = 0; r < nrange; ++r) {
       r_off.push_back((int)r_c.size());
+      std::vector<std::array<int64_t, 5>> its;   // work, cell, t0, nt, q0
       for (int i = b_cell[b]; i < b_cell[b + 1]; ++i) {
         const int K = NPAD + ((cna[i] + 15) & ~15), ntiles = ea_max_tiles(K);
         const int t0 = r * SCF_RHO_TILES;
         if (t0 >= ntiles) continue;
-        r_c.push_back(i);
-        r_t0.push_back(t0);
-        r_nt.push_back(std::min(SCF_RHO_TILES, ntiles - t0));
+        const int nt = std::min(SCF_RHO_TILES, ntiles - t0);
+        for (int64_t q0 = 0; q0 < pcnt[i]; q0 += SCF_RHO_QCHUNK)
+          its.push_back({std::min<int64_t>(SCF_RHO_QCHUNK, pcnt[i] - q0) * (nt + 32), i, t0, nt, q0});
+      }
+      std::stable_sort(its.begin(), its.end(), [](const std::array<int64_t, 5> &x,
+                                                  const std::array<int64_t, 5> &y) {
+        return x[0] > y[0];
+      });
+      for (const auto &x : its) {
+        r_c.push_back((int32_t)x[1]);
+        r_t0.push_back((int32_t)x[2]);
+        r_nt.push_back((int32_t)x[3]);
+        r_q0.push_back((int32_t)x[4]);
       }
     }
   r_off.push_back((int)r_c.size());
@@ -3057,7 +3091,11 @@ cf_status chebfilter_scf_setup(cf_ctx *c, const cf_scf_setup *o) {
   for (int i = 0; i < nscf; ++i) scf_of[cell[i]] = i;
   std::vector<int> cofs(1, 0);
   for (size_t k = 0; k + 1 < c->col_off.size(); ++k) {
+    const size_t b0 = colscf.size();
     for (int q = c->col_off[k]; q < c->col_off[k + 1]; ++q) colscf.push_back(scf_of[colcells[q]]);
+    // the cells with the most points first (the longest workgroups start first)
+    std::stable_sort(colscf.begin() + b0, colscf.end(),
+                     [&](int32_t x, int32_t y) { return pcnt[x] > pcnt[y]; });
     cofs.push_back((int)colscf.size());
   }
   // Poisson: A^C block = K / (2 pi) (K = 1/2 int grad N . grad N), Jacobi diagonal
@@ -3084,6 +3122,7 @@ cf_status chebfilter_scf_setup(cf_ctx *c, const cf_scf_setup *o) {
   STCHK(dupload(c, s.rho_c, r_c.data(), r_c.size()));
   STCHK(dupload(c, s.rho_t0, r_t0.data(), r_t0.size()));
   STCHK(dupload(c, s.rho_nt, r_nt.data(), r_nt.size()));
+  STCHK(dupload(c, s.rho_q0, r_q0.data(), r_q0.size()));
   s.rho_off = r_off;
   STCHK(dupload(c, s.pofs, pofs.data(), pofs.size()));
   STCHK(dupload(c, s.pcnt, pcnt.data(), pcnt.size()));
@@ -3175,7 +3214,7 @@ cf_status chebfilter_scf_density(cf_ctx *c, const double *X, int64_t ldx, int64_
     for (int r = 0; r < nrange; ++r) {
       const int i0 = s.rho_off[b * nrange + r], i1 = s.rho_off[b * nrange + r + 1];
       HIPCHK(c, launch_scf_rho(c->stream, g, i1 - i0, s.rho_c + i0, s.rho_t0 + i0, s.rho_nt + i0,
-                               r > 0, s.Dbuf, rho));
+                               s.rho_q0 + i0, r > 0, s.Dbuf, rho));
     }
   }
   // the host copy of f2 must outlive the asynchronous copy

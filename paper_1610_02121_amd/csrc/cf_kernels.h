@@ -413,9 +413,10 @@ hipError_t launch_scf_dm(hipStream_t s, const ScfArgs &g, int nitems, const int3
 constexpr int SCF_RHO_TILES = 8 * 12;             // upper tiles of D_e per density item
 // upper 16 x 16 tiles of a K x K block
 __host__ __device__ constexpr int ea_max_tiles(int K) { return (K / 16) * (K / 16 + 1) / 2; }
+constexpr int SCF_RHO_QCHUNK = 1024;              // points per density item
 hipError_t launch_scf_rho(hipStream_t s, const ScfArgs &g, int nitems, const int32_t *item_c,
-                          const int32_t *item_t0, const int32_t *item_nt, int add,
-                          const double *Dbuf, double *rho);
+                          const int32_t *item_t0, const int32_t *item_nt, const int32_t *item_q0,
+                          int add, const double *Dbuf, double *rho);
 hipError_t launch_scf_lda(hipStream_t s, int64_t P, const double *rho, const double *w, double *vxc,
                           double *partials, int nblocks);
 hipError_t launch_scf_rhs(hipStream_t s, const ScfArgs &g, int ncells, const int32_t *cells,

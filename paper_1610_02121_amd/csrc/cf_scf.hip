@@ -163,17 +163,19 @@ __device__ void scf_stage_basis(const ScfArgs &g, const EaTab &t, int c, int64_t
 
 // rho_q = Phi_q^T D_e Phi_q = sum over upper 16 x 16 tiles (ta <= tb) of D_e of
 // (2 - [ta == tb]) (Phi_q,ta D_ta,tb) . Phi_q,tb.  One work item = (SCF cell,
-// a range of at most 8 RHO_TPW upper tiles); its 8 waves keep their tiles of
-// D_e in registers (as MFMA B fragments) for the whole cell, so the stage
-// loop over the cell's points reads only LDS.  Items of the first range write
-// rho, those of later ranges (cells with more tiles) add to it in a later
-// launch.
+// a range of at most 8 RHO_TPW upper tiles, a chunk of at most SCF_RHO_QCHUNK
+// of the cell's points); its 8 waves keep their tiles of D_e in registers (as
+// MFMA B fragments) for the whole chunk, so the stage loop over the points
+// reads only LDS.  Items of the first tile range write rho, those of later
+// ranges (cells with more tiles) add to it in a later launch; the chunks of
+// one range cover distinct points.
 constexpr int RHO_TPW = 12;
 static_assert(8 * RHO_TPW == SCF_RHO_TILES, "density items hold 8 waves of RHO_TPW tiles");
 
 __global__ __launch_bounds__(512) void k_scf_rho(const ScfArgs g, const int32_t *__restrict__ item_c,
                                                  const int32_t *__restrict__ item_t0,
-                                                 const int32_t *__restrict__ item_nt, int add,
+                                                 const int32_t *__restrict__ item_nt,
+                                                 const int32_t *__restrict__ item_q0, int add,
                                                  const double *__restrict__ Dbuf,
                                                  double *__restrict__ rho) {
   __shared__ double stab[EA_TAB_MAX];
@@ -217,7 +219,9 @@ __global__ __launch_bounds__(512) void k_scf_rho(const ScfArgs g, const int32_t 
     ea.nsh = g.nsh;
     t = ea_tab(stab, ea);
   }
-  const int64_t p0 = g.pofs[c], np = g.pcnt[c];
+  // this item's chunk of the cell's points
+  const int64_t p0 = g.pofs[c] + item_q0[blockIdx.x];
+  const int64_t np = min<int64_t>(SCF_RHO_QCHUNK, g.pcnt[c] - item_q0[blockIdx.x]);
   for (int64_t q0 = 0; q0 < np; q0 += RHO_P) {
     const int ns = (int)min<int64_t>(RHO_P, np - q0);
     scf_stage_basis(g, t, c, p0 + q0, ns, na, atom, L1, Phi, 512);
@@ -515,11 +519,11 @@ hipError_t launch_scf_dm(hipStream_t s, const ScfArgs &g, int nitems, const int3
 }
 
 hipError_t launch_scf_rho(hipStream_t s, const ScfArgs &g, int nitems, const int32_t *item_c,
-                          const int32_t *item_t0, const int32_t *item_nt, int add,
-                          const double *Dbuf, double *rho) {
+                          const int32_t *item_t0, const int32_t *item_nt, const int32_t *item_q0,
+                          int add, const double *Dbuf, double *rho) {
   if (nitems <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_scf_rho, dim3((unsigned)nitems), dim3(512), 0, s, g, item_c, item_t0,
-                     item_nt, add, Dbuf, rho);
+                     item_nt, item_q0, add, Dbuf, rho);
   return hipGetLastError();
 }
 

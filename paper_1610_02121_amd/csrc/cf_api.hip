@@ -141,8 +141,13 @@ struct cf_ctx {
     int64_t *bptr = nullptr, *pee_off = nullptr, *pair_ptr = nullptr;
     int32_t *item_slot = nullptr, *item_t0 = nullptr, *item_nt = nullptr, *pair_ij = nullptr,
             *pc = nullptr;
-    double *Pee = nullptr;
-    std::vector<int> batch_item, batch_pair;  // [nbatch + 1] each
+    double *Pee = nullptr, *Ptile = nullptr, *Pnn = nullptr;
+    int32_t *item_q0 = nullptr, *item_qn = nullptr, *item_pi = nullptr;
+    int32_t *f_slot = nullptr, *f_t0 = nullptr, *f_nt = nullptr, *f_p0 = nullptr, *f_np = nullptr;
+    int32_t *nn_slot = nullptr, *nn_q0 = nullptr, *nn_qn = nullptr, *nn_pi = nullptr;
+    int32_t *nnf_slot = nullptr, *nnf_p0 = nullptr, *nnf_np = nullptr;
+    int n_nn = 0, n_nnf = 0;
+    std::vector<int> batch_item, batch_pair, batch_fin;  // [nbatch + 1] each
   } ea;
   // self-consistent field quantities (chebfilter_scf_setup): the SCF cells
   // (plain cells, then the cells with an adaptive rule) with their point
@@ -2668,13 +2673,51 @@ cf_status chebfilter_enriched_tables(cf_ctx *c, const cf_adaptive_grid *g) {
     tab.push_back(g->term_k[k]);
     tab.push_back(g->term_zeta[k]);
   }
-  // enrichment-row work items and atom-pair lists, in batches of cells
-  std::vector<int32_t> it_slot, it_t0, it_nt, pair_ij, pc;
+  // Work items.  A slot with more than EA_QCHUNK points is cut into point
+  // chunks: its items write partial tiles, and a finishing group sums them in
+  // chunk order.  Items are ordered by decreasing work (points times tiles)
+  // so that the longest workgroups start first.
+  const int64_t ng3q = (int64_t)ng * ng * ng;
+  auto npts = [&](int64_t s) { return (g->box_ptr[s + 1] - g->box_ptr[s]) * ng3q; };
+  // H^cc items
+  std::vector<int32_t> nn_slot, nn_q0, nn_qn, nn_pi, nnf_slot, nnf_p0, nnf_np;
+  {
+    std::vector<std::array<int64_t, 5>> its;      // work, slot, q0, qn, pi
+    int32_t np_nn = 0;
+    for (int64_t s = 0; s < ncl; ++s) {
+      const int64_t q = npts(s);
+      if (q <= EA_QCHUNK) {
+        its.push_back({q, s, 0, q, -1});
+        continue;
+      }
+      nnf_slot.push_back((int32_t)s);
+      nnf_p0.push_back(np_nn);
+      for (int64_t q0 = 0; q0 < q; q0 += EA_QCHUNK) {
+        const int64_t qn = std::min<int64_t>(EA_QCHUNK, q - q0);
+        its.push_back({qn, s, q0, qn, np_nn++});
+      }
+      nnf_np.push_back(np_nn - nnf_p0.back());
+    }
+    std::stable_sort(its.begin(), its.end(), [](const std::array<int64_t, 5> &x,
+                                                const std::array<int64_t, 5> &y) { return x[0] > y[0]; });
+    for (const auto &x : its) {
+      nn_slot.push_back((int32_t)x[1]);
+      nn_q0.push_back((int32_t)x[2]);
+      nn_qn.push_back((int32_t)x[3]);
+      nn_pi.push_back((int32_t)x[4]);
+    }
+  }
+  // enrichment-row items, their finishing groups and the atom-pair lists,
+  // in batches of cells whose partial H^ee blocks fit EA_PEE_BYTES
+  std::vector<int32_t> it_slot, it_t0, it_nt, it_q0, it_qn, it_pi, pair_ij, pc;
+  std::vector<int32_t> f_slot, f_t0, f_nt, f_p0, f_np;
   std::vector<int64_t> pee_off(ncl, 0), pair_ptr(1, 0);
-  std::vector<int> b_item(1, 0), b_pair(1, 0);
-  int64_t pee_max = 0;
+  std::vector<int> b_item(1, 0), b_pair(1, 0), b_fin(1, 0);
+  int64_t pee_max = 0, ptile_max = 0;
   {
     int64_t used = 0;
+    int32_t np_b = 0;                                // partial index within the batch
+    std::vector<std::array<int64_t, 7>> its;         // work, slot, t0, nt, q0, qn, pi
     std::vector<int64_t> batch_slots;
     auto close_batch = [&]() {
       if (batch_slots.empty()) return;
@@ -2699,31 +2742,25 @@ cf_status chebfilter_enriched_tables(cf_ctx *c, const cf_adaptive_grid *g) {
         pc.push_back(ent[q][4]);
       }
       if (!ent.empty()) pair_ptr.push_back((int64_t)pc.size() / 3);
-      // the batch's items in decreasing order of work (points times tiles):
-      // the longest workgroups start first
-      {
-        const size_t i0 = (size_t)b_item.back(), i1 = it_slot.size();
-        std::vector<size_t> ord(i1 - i0);
-        for (size_t q = 0; q < ord.size(); ++q) ord[q] = i0 + q;
-        auto work = [&](size_t q) {
-          return (g->box_ptr[it_slot[q] + 1] - g->box_ptr[it_slot[q]]) * (int64_t)it_nt[q];
-        };
-        std::stable_sort(ord.begin(), ord.end(), [&](size_t x, size_t y) { return work(x) > work(y); });
-        std::vector<int32_t> a(ord.size()), b2(ord.size()), c2(ord.size());
-        for (size_t q = 0; q < ord.size(); ++q) {
-          a[q] = it_slot[ord[q]];
-          b2[q] = it_t0[ord[q]];
-          c2[q] = it_nt[ord[q]];
-        }
-        std::copy(a.begin(), a.end(), it_slot.begin() + i0);
-        std::copy(b2.begin(), b2.end(), it_t0.begin() + i0);
-        std::copy(c2.begin(), c2.end(), it_nt.begin() + i0);
+      std::stable_sort(its.begin(), its.end(), [](const std::array<int64_t, 7> &x,
+                                                  const std::array<int64_t, 7> &y) { return x[0] > y[0]; });
+      for (const auto &x : its) {
+        it_slot.push_back((int32_t)x[1]);
+        it_t0.push_back((int32_t)x[2]);
+        it_nt.push_back((int32_t)x[3]);
+        it_q0.push_back((int32_t)x[4]);
+        it_qn.push_back((int32_t)x[5]);
+        it_pi.push_back((int32_t)x[6]);
       }
+      its.clear();
       b_item.push_back((int)it_slot.size());
       b_pair.push_back((int)pair_ij.size() / 2);
+      b_fin.push_back((int)f_slot.size());
       pee_max = std::max(pee_max, used);
+      ptile_max = std::max<int64_t>(ptile_max, np_b);
       batch_slots.clear();
       used = 0;
+      np_b = 0;
     };
     for (int64_t s = 0; s < ncl; ++s) {
       if (atoms[s].empty()) continue;
@@ -2734,10 +2771,22 @@ cf_status chebfilter_enriched_tables(cf_ctx *c, const cf_adaptive_grid *g) {
       used += bytes;
       batch_slots.push_back(s);
       const int ntiles = 8 * nte + nte * (nte + 1) / 2;
+      const int64_t q = npts(s);
       for (int t0 = 0; t0 < ntiles; t0 += 4 * EA_TPW) {
-        it_slot.push_back((int32_t)s);
-        it_t0.push_back(t0);
-        it_nt.push_back(std::min(4 * EA_TPW, ntiles - t0));
+        const int nt = std::min(4 * EA_TPW, ntiles - t0);
+        if (q <= EA_QCHUNK) {
+          its.push_back({q * nt, s, t0, nt, 0, q, -1});
+          continue;
+        }
+        f_slot.push_back((int32_t)s);
+        f_t0.push_back(t0);
+        f_nt.push_back(nt);
+        f_p0.push_back(np_b);
+        for (int64_t q0 = 0; q0 < q; q0 += EA_QCHUNK) {
+          const int64_t qn = std::min<int64_t>(EA_QCHUNK, q - q0);
+          its.push_back({qn * nt, s, t0, nt, q0, qn, np_b++});
+        }
+        f_np.push_back(np_b - f_p0.back());
       }
     }
     close_batch();
@@ -2756,6 +2805,28 @@ cf_status chebfilter_enriched_tables(cf_ctx *c, const cf_adaptive_grid *g) {
   STCHK(dupload(c, ea.item_slot, it_slot.data(), it_slot.size()));
   STCHK(dupload(c, ea.item_t0, it_t0.data(), it_t0.size()));
   STCHK(dupload(c, ea.item_nt, it_nt.data(), it_nt.size()));
+  STCHK(dupload(c, ea.item_q0, it_q0.data(), it_q0.size()));
+  STCHK(dupload(c, ea.item_qn, it_qn.data(), it_qn.size()));
+  STCHK(dupload(c, ea.item_pi, it_pi.data(), it_pi.size()));
+  STCHK(dupload(c, ea.f_slot, f_slot.data(), f_slot.size()));
+  STCHK(dupload(c, ea.f_t0, f_t0.data(), f_t0.size()));
+  STCHK(dupload(c, ea.f_nt, f_nt.data(), f_nt.size()));
+  STCHK(dupload(c, ea.f_p0, f_p0.data(), f_p0.size()));
+  STCHK(dupload(c, ea.f_np, f_np.data(), f_np.size()));
+  STCHK(dupload(c, ea.nn_slot, nn_slot.data(), nn_slot.size()));
+  STCHK(dupload(c, ea.nn_q0, nn_q0.data(), nn_q0.size()));
+  STCHK(dupload(c, ea.nn_qn, nn_qn.data(), nn_qn.size()));
+  STCHK(dupload(c, ea.nn_pi, nn_pi.data(), nn_pi.size()));
+  STCHK(dupload(c, ea.nnf_slot, nnf_slot.data(), nnf_slot.size()));
+  STCHK(dupload(c, ea.nnf_p0, nnf_p0.data(), nnf_p0.size()));
+  STCHK(dupload(c, ea.nnf_np, nnf_np.data(), nnf_np.size()));
+  dfree(c, ea.Ptile);
+  STCHK(dalloc(c, &ea.Ptile, (size_t)std::max<int64_t>(ptile_max, 1) * 4 * EA_TPW * 256));
+  dfree(c, ea.Pnn);
+  STCHK(dalloc(c, &ea.Pnn, (size_t)std::max<size_t>(nn_pi.empty() ? 1 : (size_t)(1 + *std::max_element(nn_pi.begin(), nn_pi.end())), 1) * 36 * 256));
+  ea.n_nn = (int)nn_slot.size();
+  ea.n_nnf = (int)nnf_slot.size();
+  ea.batch_fin = b_fin;
   STCHK(dupload(c, ea.pair_ij, pair_ij.data(), pair_ij.size()));
   STCHK(dupload(c, ea.pair_ptr, pair_ptr.data(), pair_ptr.size()));
   STCHK(dupload(c, ea.pc, pc.data(), pc.size()));
@@ -2827,17 +2898,29 @@ cf_status chebfilter_assemble_enriched(cf_ctx *c, const double *V) {
   a.eptr = c->eptr; a.eidx = c->eidx; a.tld = c->tld; a.toff = c->toff;
   a.Hp = c->Hp; a.K = c->asm_K; a.Hec = c->Hec; a.HT = c->HT;
   a.Pee = ea.Pee; a.pee_off = ea.pee_off;
+  a.Ptile = ea.Ptile; a.Pnn = ea.Pnn;
+  a.nn_slot = ea.nn_slot; a.nn_q0 = ea.nn_q0; a.nn_qn = ea.nn_qn; a.nn_pi = ea.nn_pi;
+  a.nnf_slot = ea.nnf_slot; a.nnf_p0 = ea.nnf_p0; a.nnf_np = ea.nnf_np;
   {
     Scope sc(c, "assemble_adaptive");
-    HIPCHK(c, launch_ea_nn(c->stream, a));
+    HIPCHK(c, launch_ea_nn(c->stream, a, ea.n_nn, ea.n_nnf));
     if (c->n_e > 0) {
       HIPCHK(c, launch_fill(c->stream, c->Hee, c->n_e * c->n_e, 0.0));
       for (size_t b = 0; b + 1 < ea.batch_item.size(); ++b) {
         EnrAsm ab = a;
-        ab.item_slot = ea.item_slot + ea.batch_item[b];
-        ab.item_t0 = ea.item_t0 + ea.batch_item[b];
-        ab.item_nt = ea.item_nt + ea.batch_item[b];
-        HIPCHK(c, launch_ea_erow(c->stream, ab, ea.batch_item[b + 1] - ea.batch_item[b]));
+        const int i0 = ea.batch_item[b], f0 = ea.batch_fin[b];
+        ab.item_slot = ea.item_slot + i0;
+        ab.item_t0 = ea.item_t0 + i0;
+        ab.item_nt = ea.item_nt + i0;
+        ab.item_q0 = ea.item_q0 + i0;
+        ab.item_qn = ea.item_qn + i0;
+        ab.item_pi = ea.item_pi + i0;
+        ab.fin_slot = ea.f_slot + f0;
+        ab.fin_t0 = ea.f_t0 + f0;
+        ab.fin_nt = ea.f_nt + f0;
+        ab.fin_p0 = ea.f_p0 + f0;
+        ab.fin_np = ea.f_np + f0;
+        HIPCHK(c, launch_ea_erow(c->stream, ab, ea.batch_item[b + 1] - i0, ea.batch_fin[b + 1] - f0));
         HIPCHK(c, launch_ea_ee_reduce(c->stream, a, (int)c->n_e,
                                       ea.batch_pair[b + 1] - ea.batch_pair[b],
                                       ea.pair_ij + 2 * (int64_t)ea.batch_pair[b],
@@ -2881,6 +2964,7 @@ cf_status chebfilter_get_coupling(cf_ctx *c, double *H_ec, double *H_ee) {
 // Self-consistent field quantities (Sec. II, Sec. V)
 // ---------------------------------------------------------------------------
 static constexpr int SCF_RED_BLOCKS = 1024;         // fixed grid of the weighted sums
+static constexpr int SCF_CG_CHECK = 10;             // CG iterations between host checks
 static constexpr int64_t SCF_DM_BYTES = 1ll << 30;  // density matrices of one batch
 
 cf_status chebfilter_fermi_level(const double *eps, int64_t N, double n_electrons, double kT,
@@ -3144,7 +3228,7 @@ cf_status chebfilter_scf_setup(cf_ctx *c, const cf_scf_setup *o) {
   dfree(c, s.part);
   STCHK(dalloc(c, &s.part, (size_t)std::max<int64_t>(4 * SCF_RED_BLOCKS, nscf)));
   dfree(c, s.dot);
-  STCHK(dalloc(c, &s.dot, (size_t)SCF_RED_BLOCKS + 1));
+  STCHK(dalloc(c, &s.dot, (size_t)SCF_RED_BLOCKS + 8));
   dfree(c, s.hin);
   dfree(c, s.hF);
   STCHK(dalloc(c, &s.hin, (size_t)std::max<int64_t>(P, 1) * o->mix_depth));
@@ -3272,28 +3356,36 @@ cf_status chebfilter_scf_potential(cf_ctx *c, const double *rho, const double *v
   // r = b - A x0 (q = A x0)
   STCHK(scf_lap(c, g, s.px, s.pq));
   HIPCHK(c, launch_scf_cg(c->stream, c->n_h, 3, 0.0, 0.0, nullptr, nullptr, s.pr, s.pb, nullptr, s.pq));
+  // the scalars stay on the device (s.dot[SCF_RED_BLOCKS + 1 ..]); the host
+  // reads r.r every SCF_CG_CHECK iterations to stop
+  double *dsc = s.dot + SCF_RED_BLOCKS + 1;
   int it = 0;
-  double rr = 0.0, rz = 0.0, rz_old = 0.0;
-  STCHK(scf_dot(c, s.pr, s.pr, c->n_h, &rr));
+  double rr = 0.0;
+  HIPCHK(c, launch_dot(c->stream, c->n_h, s.pr, s.pr, dsc + 2, s.dot, SCF_RED_BLOCKS));
+  HIPCHK(c, hipMemcpyAsync(&rr, dsc + 2, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
   const double stop = s.cg_tol * s.cg_tol * std::max(bb, 1e-300);
   if (rr > stop) {
     HIPCHK(c, launch_scf_cg(c->stream, c->n_h, 0, 0.0, 0.0, s.dinv, nullptr, s.pr, s.pz, nullptr, nullptr));
     HIPCHK(c, launch_copy(c->stream, c->n_h, 1, s.pz, 1, s.pp, 1));
-    STCHK(scf_dot(c, s.pr, s.pz, c->n_h, &rz));
+    HIPCHK(c, launch_dot(c->stream, c->n_h, s.pr, s.pz, dsc + 0, s.dot, SCF_RED_BLOCKS));
     for (it = 1; it <= s.cg_max; ++it) {
       STCHK(scf_lap(c, g, s.pp, s.pq));
-      double pq = 0.0;
-      STCHK(scf_dot(c, s.pp, s.pq, c->n_h, &pq));
-      if (!(pq > 0.0)) return set_err(c, CF_EDEVICE, "scf_potential: CG lost positive definiteness");
-      const double alpha = rz / pq;
-      HIPCHK(c, launch_scf_cg(c->stream, c->n_h, 2, alpha, 0.0, nullptr, s.px, s.pr, nullptr, s.pp, s.pq));
-      STCHK(scf_dot(c, s.pr, s.pr, c->n_h, &rr));
-      if (rr <= stop) break;
-      HIPCHK(c, launch_scf_cg(c->stream, c->n_h, 0, 0.0, 0.0, s.dinv, nullptr, s.pr, s.pz, nullptr, nullptr));
-      rz_old = rz;
-      STCHK(scf_dot(c, s.pr, s.pz, c->n_h, &rz));
-      HIPCHK(c, launch_scf_cg(c->stream, c->n_h, 1, 0.0, rz / rz_old, nullptr, nullptr, nullptr, s.pz,
-                              s.pp, nullptr));
+      HIPCHK(c, launch_dot(c->stream, c->n_h, s.pp, s.pq, dsc + 1, s.dot, SCF_RED_BLOCKS));
+      HIPCHK(c, launch_scf_cgd(c->stream, c->n_h, 0, dsc, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr));
+      HIPCHK(c, launch_scf_cgd(c->stream, c->n_h, 1, dsc, s.dinv, s.px, s.pr, s.pz, s.pp, s.pq));
+      HIPCHK(c, launch_dot(c->stream, c->n_h, s.pr, s.pz, dsc + 3, s.dot, SCF_RED_BLOCKS));
+      HIPCHK(c, launch_scf_cgd(c->stream, c->n_h, 2, dsc, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr));
+      HIPCHK(c, launch_scf_cgd(c->stream, c->n_h, 3, dsc, nullptr, nullptr, nullptr, s.pz, s.pp, nullptr));
+      if (it % SCF_CG_CHECK == 0 || it == s.cg_max) {
+        HIPCHK(c, launch_dot(c->stream, c->n_h, s.pr, s.pr, dsc + 2, s.dot, SCF_RED_BLOCKS));
+        double scal[2] = {0.0, 0.0};
+        HIPCHK(c, hipMemcpyAsync(scal, dsc + 1, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        if (!(scal[0] > 0.0)) return set_err(c, CF_EDEVICE, "scf_potential: CG lost positive definiteness");
+        rr = scal[1];
+        if (rr <= stop) break;
+      }
     }
   }
   if (cg_iters) *cg_iters = it;

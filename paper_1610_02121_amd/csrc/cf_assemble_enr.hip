@@ -51,12 +51,34 @@ __device__ __forceinline__ int up_col(int t) {
   return i + t;
 }
 
+// the 36 upper tiles of H^cc_e into the cell's padded block (K + value at
+// (row <= col), mirrored)
+__device__ __forceinline__ void ea_nn_store(const EnrAsm &a, int slot, const int *ti, const int *tj,
+                                            const d4 *acc) {
+  const int lane = threadIdx.x & 63, li = lane & 15, kq = lane >> 4;
+  double *He = a.Hp + (int64_t)a.cell[slot] * NPAD * NPAD;
+#pragma unroll
+  for (int u = 0; u < 9; ++u) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int lr = 4 * r + kq;
+      if (ti[u] == tj[u] && lr > li) continue;
+      const int row = 16 * ti[u] + lr, col = 16 * tj[u] + li;
+      const double v = a.K[row * NPAD + col] + acc[u][r];
+      He[row * NPAD + col] = v;
+      if (row != col) He[col * NPAD + row] = v;
+    }
+  }
+}
+
 __global__ __launch_bounds__(256) void k_ea_nn(const EnrAsm a) {
   __shared__ double stab[EA_TAB_MAX];
   __shared__ double L1[NN_P][3][EA_MAXNP];
   __shared__ double sV[NN_P];
   __shared__ double Nv[NN_P][NPAD];
-  const int slot = blockIdx.x;
+  const int slot = a.nn_slot[blockIdx.x];
+  const int64_t qb = a.nn_q0[blockIdx.x], qe = qb + a.nn_qn[blockIdx.x];
+  const int pi = a.nn_pi[blockIdx.x];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, kq = lane >> 4;
   const int ntab = ea_tab_size(a.np1, a.ng, a.nsh, a.nterm);
@@ -65,19 +87,18 @@ __global__ __launch_bounds__(256) void k_ea_nn(const EnrAsm a) {
   const EaTab t = ea_tab(stab, a);
   const int np1 = a.np1, npc = np1 * np1 * np1;
   const double lo[3] = {a.lo[3 * slot], a.lo[3 * slot + 1], a.lo[3 * slot + 2]};
-  const int64_t nq = (a.bptr[slot + 1] - a.bptr[slot]) * (int64_t)(a.ng * a.ng * a.ng);
   d4 acc[9];
 #pragma unroll
   for (int u = 0; u < 9; ++u) acc[u] = d4{0.0, 0.0, 0.0, 0.0};
   int ti[9], tj[9];
 #pragma unroll
   for (int u = 0; u < 9; ++u) { ti[u] = up_row(w + 4 * u); tj[u] = up_col(w + 4 * u); }
-  for (int64_t q0 = 0; q0 < nq; q0 += NN_P) {
+  for (int64_t q0 = qb; q0 < qe; q0 += NN_P) {
     if (tid < NN_P * 3) {
       const int k = tid / 3, d = tid % 3;
       double x[3], wt, v;
       double dummy[EA_MAXNP];
-      if (ea_point(a, t, slot, q0 + k, x, wt, v)) {
+      if (q0 + k < qe && ea_point(a, t, slot, q0 + k, x, wt, v)) {
         ea_lagrange(t.nodes, np1, (x[d] - lo[d]) / a.h, L1[k][d], dummy);
         if (d == 0) sV[k] = wt * v;
       } else {
@@ -103,20 +124,35 @@ __global__ __launch_bounds__(256) void k_ea_nn(const EnrAsm a) {
     }
     __syncthreads();
   }
-  // H^cc_e = K + sum; the value at (row <= col) is written at both positions
-  double *He = a.Hp + (int64_t)a.cell[slot] * NPAD * NPAD;
+  if (pi < 0) {
+    ea_nn_store(a, slot, ti, tj, acc);
+    return;
+  }
+  double *P = a.Pnn + (int64_t)pi * 36 * 256;
+#pragma unroll
+  for (int u = 0; u < 9; ++u)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) P[(w + 4 * u) * 256 + r * 64 + lane] = acc[u][r];
+}
+
+// the partial H^cc tiles of a split slot, summed in chunk order
+__global__ __launch_bounds__(256) void k_ea_nn_fin(const EnrAsm a) {
+  const int slot = a.nnf_slot[blockIdx.x], p0 = a.nnf_p0[blockIdx.x], np = a.nnf_np[blockIdx.x];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  d4 acc[9];
+  int ti[9], tj[9];
 #pragma unroll
   for (int u = 0; u < 9; ++u) {
+    ti[u] = up_row(w + 4 * u);
+    tj[u] = up_col(w + 4 * u);
+    acc[u] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int k = 0; k < np; ++k) {
+      const double *P = a.Pnn + (int64_t)(p0 + k) * 36 * 256 + (w + 4 * u) * 256 + lane;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int lr = 4 * r + kq;
-      if (ti[u] == tj[u] && lr > li) continue;
-      const int row = 16 * ti[u] + lr, col = 16 * tj[u] + li;
-      const double v = a.K[row * NPAD + col] + acc[u][r];
-      He[row * NPAD + col] = v;
-      if (row != col) He[col * NPAD + row] = v;
+      for (int r = 0; r < 4; ++r) acc[u][r] += P[r * 64];
     }
   }
+  ea_nn_store(a, slot, ti, tj, acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -139,6 +175,33 @@ __device__ __forceinline__ void ea_tile(int t, int nte, int &ti, int &tj, bool &
   ti = i; tj = i + u; ee = true;
 }
 
+// the tiles of an enrichment-row item into H^ec (both layouts) or the slot's
+// partial H^ee block
+__device__ __forceinline__ void ea_erow_store(const EnrAsm &a, int slot, const int *ti,
+                                              const int *tj, const bool *ee, const bool *on,
+                                              const d4 *acc) {
+  const int lane = threadIdx.x & 63, li = lane & 15, kq = lane >> 4;
+  const int e = a.cell[slot];
+  const int64_t e0 = a.eptr[e];
+  const int na = (int)(a.eptr[e + 1] - e0), nap = a.tld[e];
+  double *Pe = a.Pee ? a.Pee + a.pee_off[slot] : nullptr;
+#pragma unroll
+  for (int u = 0; u < EA_TPW; ++u) {
+    if (!on[u]) continue;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int al = 16 * ti[u] + 4 * r + kq;
+      const int col = 16 * tj[u] + li;
+      if (ee[u]) {
+        Pe[(int64_t)al * nap + col] = acc[u][r];
+      } else if (al < na) {
+        a.Hec[(e0 + al) * NPAD + col] = acc[u][r];
+        a.HT[a.toff[e] + (int64_t)col * nap + al] = acc[u][r];
+      }
+    }
+  }
+}
+
 __global__ __launch_bounds__(256) void k_ea_erow(const EnrAsm a) {
   __shared__ double stab[EA_TAB_MAX];
   __shared__ double L1[EA_P][3][2][EA_MAXNP];
@@ -148,6 +211,8 @@ __global__ __launch_bounds__(256) void k_ea_erow(const EnrAsm a) {
   __shared__ int atom[EA_MAXNAP];
   const int item = blockIdx.x;
   const int slot = a.item_slot[item], t0 = a.item_t0[item], ntl = a.item_nt[item];
+  const int64_t qb = a.item_q0[item], qe = qb + a.item_qn[item];
+  const int pi = a.item_pi[item];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, kq = lane >> 4;
   const int ntab = ea_tab_size(a.np1, a.ng, a.nsh, a.nterm);
@@ -163,7 +228,6 @@ __global__ __launch_bounds__(256) void k_ea_erow(const EnrAsm a) {
   const EaTab t = ea_tab(stab, a);
   const int np1 = a.np1, npc = np1 * np1 * np1;
   const double lo[3] = {a.lo[3 * slot], a.lo[3 * slot + 1], a.lo[3 * slot + 2]};
-  const int64_t nq = (a.bptr[slot + 1] - a.bptr[slot]) * (int64_t)(a.ng * a.ng * a.ng);
 
   d4 acc[EA_TPW];
   int ti[EA_TPW], tj[EA_TPW];
@@ -175,11 +239,11 @@ __global__ __launch_bounds__(256) void k_ea_erow(const EnrAsm a) {
     on[u] = tl < ntl;
     ea_tile(on[u] ? t0 + tl : 0, nte, ti[u], tj[u], ee[u]);
   }
-  for (int64_t q0 = 0; q0 < nq; q0 += EA_P) {
+  for (int64_t q0 = qb; q0 < qe; q0 += EA_P) {
     if (tid < 3 * EA_P) {
       const int k = tid / 3, d = tid % 3;
       double x[3], wt, v;
-      if (ea_point(a, t, slot, q0 + k, x, wt, v)) {
+      if (q0 + k < qe && ea_point(a, t, slot, q0 + k, x, wt, v)) {
         ea_lagrange(t.nodes, np1, (x[d] - lo[d]) / a.h, L1[k][d][0], L1[k][d][1]);
         for (int i = 0; i < np1; ++i) L1[k][d][1][i] /= a.h;
         if (d == 0) { sV[k] = wt * v; sK[k] = 0.5 * wt; }
@@ -191,7 +255,7 @@ __global__ __launch_bounds__(256) void k_ea_erow(const EnrAsm a) {
     for (int j = tid - 64; j >= 0 && j < EA_P * nat; j += 192) {
       const int k = j / nat, u = j % nat;
       double x[3], wt, v;
-      if (ea_point(a, t, slot, q0 + k, x, wt, v)) {
+      if (q0 + k < qe && ea_point(a, t, slot, q0 + k, x, wt, v)) {
         ea_atom(a, t, atom[u], x, Ev[0][k], Ev[1][k], Ev[2][k], Ev[3][k], u * a.npa);
       } else {
         for (int m = 0; m < a.npa; ++m) {
@@ -240,22 +304,44 @@ __global__ __launch_bounds__(256) void k_ea_erow(const EnrAsm a) {
     }
     __syncthreads();
   }
-  double *Pe = a.Pee ? a.Pee + a.pee_off[slot] : nullptr;
+  if (pi < 0) {
+    ea_erow_store(a, slot, ti, tj, ee, on, acc);
+    return;
+  }
+  double *P = a.Ptile + (int64_t)pi * 4 * EA_TPW * 256;
 #pragma unroll
   for (int u = 0; u < EA_TPW; ++u) {
     if (!on[u]) continue;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int al = 16 * ti[u] + 4 * r + kq;
-      const int col = 16 * tj[u] + li;
-      if (ee[u]) {
-        Pe[(int64_t)al * nap + col] = acc[u][r];
-      } else if (al < na) {
-        a.Hec[(e0 + al) * NPAD + col] = acc[u][r];
-        a.HT[a.toff[e] + (int64_t)col * nap + al] = acc[u][r];
-      }
+    for (int r = 0; r < 4; ++r) P[(w + 4 * u) * 256 + r * 64 + lane] = acc[u][r];
+  }
+}
+
+// the partial tiles of a split slot's item group, summed in chunk order
+__global__ __launch_bounds__(256) void k_ea_erow_fin(const EnrAsm a) {
+  const int g = blockIdx.x;
+  const int slot = a.fin_slot[g], t0 = a.fin_t0[g], ntl = a.fin_nt[g];
+  const int p0 = a.fin_p0[g], np = a.fin_np[g];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int e = a.cell[slot];
+  const int nte = a.tld[e] / 16;
+  d4 acc[EA_TPW];
+  int ti[EA_TPW], tj[EA_TPW];
+  bool ee[EA_TPW], on[EA_TPW];
+#pragma unroll
+  for (int u = 0; u < EA_TPW; ++u) {
+    const int tl = w + 4 * u;
+    on[u] = tl < ntl;
+    ea_tile(on[u] ? t0 + tl : 0, nte, ti[u], tj[u], ee[u]);
+    acc[u] = d4{0.0, 0.0, 0.0, 0.0};
+    if (!on[u]) continue;
+    for (int k = 0; k < np; ++k) {
+      const double *P = a.Ptile + (int64_t)(p0 + k) * 4 * EA_TPW * 256 + tl * 256 + lane;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[u][r] += P[r * 64];
     }
   }
+  ea_erow_store(a, slot, ti, tj, ee, on, acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -304,15 +390,15 @@ __global__ __launch_bounds__(256) void k_unit_cols(int64_t rows, int N, int64_t 
   }
 }
 
-hipError_t launch_ea_nn(hipStream_t s, const EnrAsm &a) {
-  if (a.ncl <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_ea_nn, dim3((unsigned)a.ncl), dim3(256), 0, s, a);
+hipError_t launch_ea_nn(hipStream_t s, const EnrAsm &a, int nitems, int nfin) {
+  if (nitems > 0) hipLaunchKernelGGL(k_ea_nn, dim3((unsigned)nitems), dim3(256), 0, s, a);
+  if (nfin > 0) hipLaunchKernelGGL(k_ea_nn_fin, dim3((unsigned)nfin), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_ea_erow(hipStream_t s, const EnrAsm &a, int nitems) {
-  if (nitems <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_ea_erow, dim3((unsigned)nitems), dim3(256), 0, s, a);
+hipError_t launch_ea_erow(hipStream_t s, const EnrAsm &a, int nitems, int nfin) {
+  if (nitems > 0) hipLaunchKernelGGL(k_ea_erow, dim3((unsigned)nitems), dim3(256), 0, s, a);
+  if (nfin > 0) hipLaunchKernelGGL(k_ea_erow_fin, dim3((unsigned)nfin), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

@@ -365,14 +365,28 @@ struct EnrAsm {
   double *Hec = nullptr, *HT = nullptr;
   double *Pee = nullptr;            // per-slot partial H^ee blocks [nap][nap]
   const int64_t *pee_off = nullptr;
-  // enrichment-row work items
+  // enrichment-row work items: slot, first tile, tile count, first point and
+  // point count within the slot, partial index (-1: the item covers all of
+  // the slot's points and writes the outputs itself)
   const int32_t *item_slot = nullptr, *item_t0 = nullptr, *item_nt = nullptr;
+  const int32_t *item_q0 = nullptr, *item_qn = nullptr, *item_pi = nullptr;
+  // H^cc items of k_ea_nn (slot, first point, point count, partial index)
+  const int32_t *nn_slot = nullptr, *nn_q0 = nullptr, *nn_qn = nullptr, *nn_pi = nullptr;
+  // partial tiles of the items of split slots, and the finishing lists: per
+  // group, the slot, first tile, tile count, first partial and partial count
+  double *Ptile = nullptr, *Pnn = nullptr;
+  const int32_t *fin_slot = nullptr, *fin_t0 = nullptr, *fin_nt = nullptr, *fin_p0 = nullptr,
+                *fin_np = nullptr;
+  const int32_t *nnf_slot = nullptr, *nnf_p0 = nullptr, *nnf_np = nullptr;
 };
+constexpr int EA_QCHUNK = 4096;   // points per assembly item of a split slot
 
-// H^cc_e = K + sum_q w_q V_q N_a N_b for every slot (exactly symmetric).
-hipError_t launch_ea_nn(hipStream_t s, const EnrAsm &a);
-// H^ec_e rows (both stored layouts) and the partial H^ee_e blocks of the items' tiles.
-hipError_t launch_ea_erow(hipStream_t s, const EnrAsm &a, int nitems);
+// H^cc_e = K + sum_q w_q V_q N_a N_b for every slot (exactly symmetric): nitems
+// items of whole slots or point chunks (partials), then nfin finishing groups.
+hipError_t launch_ea_nn(hipStream_t s, const EnrAsm &a, int nitems, int nfin);
+// H^ec_e rows (both stored layouts) and the partial H^ee_e blocks of the items'
+// tiles; then the nfin finishing groups of the split slots.
+hipError_t launch_ea_erow(hipStream_t s, const EnrAsm &a, int nitems, int nfin);
 // Hee[al][be] += sum over the pair's cells of the partial entries (both halves written).
 hipError_t launch_ea_ee_reduce(hipStream_t s, const EnrAsm &a, int n_e, int npairs,
                                const int32_t *pair_ij, const int64_t *pair_ptr, const int32_t *pc,
@@ -426,6 +440,8 @@ hipError_t launch_scf_lap(hipStream_t s, const ScfArgs &g, int ncells, const int
 hipError_t launch_scf_cg(hipStream_t s, int64_t n, int op, double alpha, double beta,
                          const double *dinv, double *x, double *r, double *z, double *p,
                          const double *q);
+hipError_t launch_scf_cgd(hipStream_t s, int64_t n, int op, double *sc, const double *dinv,
+                          double *x, double *r, double *z, double *p, const double *q);
 hipError_t launch_scf_veff(hipStream_t s, const ScfArgs &g, int ncells, const double *phi,
                            const double *rho, const double *vext, const double *vxc, double *veff,
                            double *partials);

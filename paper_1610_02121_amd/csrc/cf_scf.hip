@@ -413,6 +413,38 @@ __global__ __launch_bounds__(256) void k_scf_cg(int64_t n, int op, double alpha,
   }
 }
 
+// CG steps with the scalars on the device (sc: 0 r.z, 1 p.q, 2 r.r, 3 new r.z,
+// 4 alpha, 5 beta): op 0: alpha = r.z / p.q; op 1: x += alpha p, r -= alpha q,
+// z = dinv .* r; op 2: beta = new r.z / r.z, r.z = new r.z; op 3: p = z + beta p
+__global__ __launch_bounds__(256) void k_scf_cgd(int64_t n, int op, double *__restrict__ sc,
+                                                 const double *__restrict__ dinv,
+                                                 double *__restrict__ x, double *__restrict__ r,
+                                                 double *__restrict__ z, double *__restrict__ p,
+                                                 const double *__restrict__ q) {
+  if (op == 0 || op == 2) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      if (op == 0) {
+        sc[4] = sc[0] / sc[1];
+      } else {
+        sc[5] = sc[3] / sc[0];
+        sc[0] = sc[3];
+      }
+    }
+    return;
+  }
+  const double alpha = sc[4], beta = sc[5];
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    if (op == 1) {
+      x[i] += alpha * p[i];
+      const double ri = r[i] - alpha * q[i];
+      r[i] = ri;
+      z[i] = dinv[i] * ri;
+    } else {
+      p[i] = z[i] + beta * p[i];
+    }
+  }
+}
+
 // V_H at the points of one cell per workgroup (interpolation of Phi plus the
 // Gaussian's potential), V_eff = V_ext + V_H + V_xc, and the block partial
 // sum of w rho V_H.
@@ -552,6 +584,13 @@ hipError_t launch_scf_cg(hipStream_t s, int64_t n, int op, double alpha, double 
                          const double *q) {
   hipLaunchKernelGGL(k_scf_cg, dim3(grid_for(n)), dim3(256), 0, s, n, op, alpha, beta, dinv, x, r, z,
                      p, q);
+  return hipGetLastError();
+}
+
+hipError_t launch_scf_cgd(hipStream_t s, int64_t n, int op, double *sc, const double *dinv,
+                          double *x, double *r, double *z, double *p, const double *q) {
+  const unsigned grid = (op == 0 || op == 2) ? 1u : grid_for(n);
+  hipLaunchKernelGGL(k_scf_cgd, dim3(grid), dim3(256), 0, s, n, op, sc, dinv, x, r, z, p, q);
   return hipGetLastError();
 }
 

@@ -24,6 +24,11 @@ mlp        the learned-bounds network: FP64 forward, backpropagated
            mean-squared-error gradient, Adam.
 assembly   the classical element block of a plain cell as the quadrature
            sum over its Gauss points (Eq. HBlocks).
+enriched   the element blocks of a cell with the adaptive rule (Sec. IV.C):
+           Lagrange basis, smooth cutoff, Slater-type radials and real
+           harmonics evaluated point by point (Eq. HBlocks, MBlocks).
+scf        the self-consistent field quantities (Sec. II, V): Fermi level,
+           density, LDA, the Hartree Poisson problem, Anderson mixing.
 
 Parity pins: see the `-m "not gpu"` tests under tests/ (closed forms,
 textbook limits, library routines, brute force on tiny meshes).

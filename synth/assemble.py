@@ -245,7 +245,8 @@ def assemble(mesh: Mesh, potential, enr: EnrichmentSet | None, ng: int = 6,
     without enrichment functions get the kinetic block K only (their
     potential term is left to a device assembly from the potential at their
     Gauss points; meta["plain_blocks"] records it).  progress(msg), if given,
-    is called about every 30 s while the enriched cells are integrated.
+    is called at each stage and about every 30 s while the enriched cells
+    are integrated.
     singular_centers [k, 3]: points where the potential is singular (bare
     nuclei); the cells without enrichment functions that touch one (box
     distance below h / 2) take the potential term by the adaptive rule with
@@ -321,6 +322,8 @@ def assemble(mesh: Mesh, potential, enr: EnrichmentSet | None, ng: int = 6,
         wv = potential(pts.reshape(-1, 3)).reshape(cells.size, -1) * (wref * jac)[None, :]
         H_cc[cells] = K[None] + np.matmul(Bref.T[None] * wv[:, None, :], Bref[None])
     t1 = time.time()
+    if progress:
+        progress(f"cells without enrichment done ({t1 - t0:.0f}s)")
 
     # ---- enriched cells: adaptive rule, fixed chunks, forked workers
     stats = {"enriched_cells": 0, "leaves": 0, "points": 0, "max_leaves": 0}
@@ -345,6 +348,8 @@ def assemble(mesh: Mesh, potential, enr: EnrichmentSet | None, ng: int = 6,
             S = np.sum([_plain_integrals(c) for c in chunks], axis=0)
             _W["tau"] = np.maximum(tol_abs, tol_rel * S)
             results = (_enriched_chunk(c) for c in chunks)
+        if progress:
+            progress(f"tolerances set; {len(chunks)} chunks of enriched cells ({time.time() - t0:.0f}s)")
         t_last = time.time()
         for k, (cells, (hcc, hec, mec, hee, mee, st, bx)) in enumerate(zip(chunks, results)):
             if progress and time.time() - t_last > 30.0:

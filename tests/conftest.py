@@ -9,9 +9,25 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 
+_CONFIG = None
+
+
 def pytest_configure(config):
+    global _CONFIG
+    _CONFIG = config
     config.addinivalue_line("markers", "gpu: needs an MI355X (runs through the HIP library)")
     config.addinivalue_line("markers", "slow: several seconds of CPU work")
+
+
+def visible(msg: str) -> None:
+    """Print past pytest's output capture: progress lines of fixtures that
+    take minutes (the problem generation), so that a run stays visibly alive."""
+    cm = _CONFIG.pluginmanager.getplugin("capturemanager") if _CONFIG is not None else None
+    if cm is None:
+        print(msg, flush=True)
+        return
+    with cm.global_and_fixture_disabled():
+        print(msg, flush=True)
 
 
 _CACHE = {}

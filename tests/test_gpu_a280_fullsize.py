@@ -63,8 +63,10 @@ def _generate():
     from synth import configs
     from synth.assemble import gpu_initialised
     from synth.problem import Problem
+    from conftest import visible
     if not gpu_initialised():
-        return configs.config3(progress=lambda m: print("[fullsize280]", m, flush=True))
+        visible("[fullsize280] generating the 280-atom workload")
+        return configs.config3(progress=lambda m: visible(f"[fullsize280] {m}"))
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     with tempfile.TemporaryDirectory() as td:
         path = os.path.join(td, "cfg3.npz")

@@ -34,9 +34,10 @@ U = 2.0 ** -53
 def full():
     from paper_1610_02121_amd import Context
     from synth import configs
-    print("[fullsize] generating the 30-atom workload", flush=True)
-    prob = configs.config2()
-    print(f"[fullsize] n={prob.n}; building context and oracle", flush=True)
+    from conftest import visible
+    visible("[fullsize] generating the 30-atom workload")
+    prob = configs.config2(progress=lambda m: visible(f"[fullsize] {m}"))
+    visible(f"[fullsize] n={prob.n}; building context and oracle")
     ctx = Context(prob, max_cols=260)
     ops = Operators(prob)
     import scipy.sparse.linalg as spla

@@ -255,7 +255,7 @@ def run_si280(args):
     import scipy.linalg as sla
     import torch
 
-    from paper_1610_02121_amd import Context
+    from paper_1610_02121_amd import Context, empty_block
     from synth import configs
     from synth.assemble import plain_points, plain_tables, potential_at_points
     _, N, m, wanted = WORKLOADS["si280-48c"]
@@ -305,7 +305,7 @@ def run_si280(args):
     del H_keep
     Vee_d = torch.tensor(Vee[:, :N], dtype=torch.float64, device=dev)
     v0 = torch.tensor(v0h, dtype=torch.float64, device=dev)
-    Y = torch.zeros((prob.n, N), dtype=torch.float64, device=dev)      # the 2200-vector block
+    Y = empty_block(prob.n, N, dev).zero_()   # the 2200-vector block (ld padded to 16)
     free, total = torch.cuda.mem_get_info()
     log(f"device memory in use {(total - free) / 2**30:.1f} GiB of {total / 2**30:.1f} GiB")
     ref = None
@@ -455,14 +455,17 @@ def mixed_study(ctx, prob, N, m, wanted, seed, m_lp, max_passes=30):
     until the Ritz error <= 1e-6 Ha."""
     import numpy as np
     import torch
+
+    from paper_1610_02121_amd import empty_block
     from synth import configs
     dev = torch.device("cuda", 0)
     v0 = torch.tensor(np.random.default_rng(seed + 1).standard_normal(prob.n),
                       dtype=torch.float64, device=dev)
 
     def run(schedule):
-        X = torch.tensor(configs.initial_block(prob, N, seed=seed), dtype=torch.float64, device=dev)
-        Y = torch.empty_like(X)
+        X = empty_block(prob.n, N, dev)
+        X.copy_(torch.from_numpy(configs.initial_block(prob, N, seed=seed)))
+        Y = empty_block(prob.n, N, dev)
         th = ctx.rayleigh_ritz(X)
         hist = []
         t = 0.0
@@ -745,11 +748,12 @@ def run_scf(args):
     vext = torch.tensor(prob.meta["potential"](xyz), dtype=torch.float64, device=dev_)
     del xyz
     log(f"{ctx.scf_points} points ({ctx.scf_plain_points} on plain cells)")
-    X = torch.tensor(configs.initial_block(prob, N, seed=args.seed), dtype=torch.float64, device=dev_)
+    X = empty_block(prob.n, N, dev_)
+    X.copy_(torch.from_numpy(configs.initial_block(prob, N, seed=args.seed)))
     theta = ctx.rayleigh_ritz(X)
     v0 = torch.tensor(np.random.default_rng(args.seed + 1).standard_normal(prob.n),
                       dtype=torch.float64, device=dev_)
-    state = {"X": X, "Y": torch.empty_like(X), "theta": theta}
+    state = {"X": X, "Y": empty_block(prob.n, N, dev_), "theta": theta}
 
     def chefsi(steps):
         _, b = ctx.lanczos_bounds(v0, 10)
@@ -1056,7 +1060,7 @@ def main():
     import numpy as np
     import torch
 
-    from paper_1610_02121_amd import Context
+    from paper_1610_02121_amd import Context, empty_block
     from synth import configs
 
     name = args.workload
@@ -1107,8 +1111,10 @@ def main():
         ctx.close()
         return
     X0 = configs.initial_block(prob, N, seed=args.seed)
-    X = torch.tensor(X0, dtype=torch.float64, device=dev)
-    Y = torch.empty_like(X)
+    # blocks with a leading dimension padded to 16 doubles (aligned row segments)
+    X = empty_block(prob.n, N, dev)
+    X.copy_(torch.from_numpy(X0))
+    Y = empty_block(prob.n, N, dev)
     v0 = torch.tensor(np.random.default_rng(args.seed + 1).standard_normal(prob.n),
                       dtype=torch.float64, device=dev)
     if args.mixed_study:

@@ -190,6 +190,15 @@ def _block(t, name: str):
     return t.data_ptr(), t.stride(0) if t.shape[1] > 1 else max(t.stride(0), 1)
 
 
+def empty_block(n: int, N: int, device, dtype=None):
+    """An n x N device block whose leading dimension is N rounded up to a
+    multiple of 16 (128 bytes of FP64): the row segments the kernels gather
+    then start on cache-line boundaries.  Returns the [n, N] view."""
+    import torch
+    ld = (N + 15) // 16 * 16
+    return torch.empty((n, ld), dtype=dtype or torch.float64, device=device)[:, :N]
+
+
 def _problem_struct(prob):
     """(CfProblem, arrays it points into) for a synth Problem."""
     keep = {

@@ -46,8 +46,12 @@ struct cf_ctx {
   hipStream_t stream = nullptr;
   int p = 0, npc = 0;
   int64_t E = 0, n_h = 0, n_e = 0, n = 0, max_cols = 0;
-  // columns of the work blocks (the column chunk): blocks wider than this
-  // are processed chunk by chunk
+  // columns of the column chunk: blocks wider than this are processed chunk
+  // by chunk
+  int64_t chunk = 0;
+  // leading dimension of the internal work blocks: the chunk rounded up to a
+  // multiple of 16 doubles, so that every row segment a kernel gathers starts
+  // on a 128-byte boundary
   int64_t ldw = 0;
   int check_finite = 0;
   // classical cells
@@ -834,7 +838,8 @@ static cf_status do_init(const cf_problem *pr, const cf_options *opt, cf_ctx *c)
   c->n_e = pr->n_e;
   c->n = pr->n_h + pr->n_e;
   c->max_cols = opt->max_cols;
-  c->ldw = (opt->col_chunk > 0 && opt->col_chunk < opt->max_cols) ? opt->col_chunk : opt->max_cols;
+  c->chunk = (opt->col_chunk > 0 && opt->col_chunk < opt->max_cols) ? opt->col_chunk : opt->max_cols;
+  c->ldw = (c->chunk + 15) / 16 * 16;
   HIPCHK(c, hipSetDevice(c->device));
   const int64_t E = c->E, n_h = c->n_h, n_e = c->n_e;
 
@@ -1601,8 +1606,8 @@ cf_status chebfilter_apply_H(cf_ctx *c, const double *X, int64_t ldx, double *Y,
   STCHK(check_block(c, Y, ldy, N, "apply_H Y"));
   if (N == 0) return CF_OK;
   HIPCHK(c, hipSetDevice(c->device));
-  for (int64_t j0 = 0; j0 < N; j0 += c->ldw)
-    STCHK(core_apply_H(c, X + j0, ldx, Y + j0, ldy, (int)std::min(c->ldw, N - j0)));
+  for (int64_t j0 = 0; j0 < N; j0 += c->chunk)
+    STCHK(core_apply_H(c, X + j0, ldx, Y + j0, ldy, (int)std::min(c->chunk, N - j0)));
   return CF_OK;
 }
 
@@ -1613,8 +1618,8 @@ cf_status chebfilter_apply_M(cf_ctx *c, const double *X, int64_t ldx, double *Y,
   STCHK(check_block(c, Y, ldy, N, "apply_M Y"));
   if (N == 0) return CF_OK;
   HIPCHK(c, hipSetDevice(c->device));
-  for (int64_t j0 = 0; j0 < N; j0 += c->ldw)
-    STCHK(core_apply_M(c, X + j0, ldx, Y + j0, ldy, (int)std::min(c->ldw, N - j0)));
+  for (int64_t j0 = 0; j0 < N; j0 += c->chunk)
+    STCHK(core_apply_M(c, X + j0, ldx, Y + j0, ldy, (int)std::min(c->chunk, N - j0)));
   return CF_OK;
 }
 
@@ -1625,8 +1630,8 @@ cf_status chebfilter_apply_Sinv(cf_ctx *c, const double *X, int64_t ldx, double 
   STCHK(check_block(c, Y, ldy, N, "apply_Sinv Y"));
   if (N == 0) return CF_OK;
   HIPCHK(c, hipSetDevice(c->device));
-  for (int64_t j0 = 0; j0 < N; j0 += c->ldw)
-    STCHK(core_apply_Sinv(c, X + j0, ldx, Y + j0, ldy, (int)std::min(c->ldw, N - j0)));
+  for (int64_t j0 = 0; j0 < N; j0 += c->chunk)
+    STCHK(core_apply_Sinv(c, X + j0, ldx, Y + j0, ldy, (int)std::min(c->chunk, N - j0)));
   return CF_OK;
 }
 
@@ -1695,8 +1700,8 @@ cf_status chebfilter_filter(cf_ctx *c, const double *X, int64_t ldx, double *Y, 
   // place, an FP64 chunk is read from a copy in the work block U (the FP32
   // forms read it once into their own blocks before the chunk is written).
   const double e = 2.0 / (b - a), cc = (a + b) / (b - a);
-  for (int64_t j0 = 0; j0 < N; j0 += c->ldw) {
-    const int nc = (int)std::min(c->ldw, N - j0);
+  for (int64_t j0 = 0; j0 < N; j0 += c->chunk) {
+    const int nc = (int)std::min(c->chunk, N - j0);
     const double *Xc = X + j0;
     int64_t ldxc = ldx;
     if (inplace && prec == CF_FP64) {
@@ -1752,10 +1757,10 @@ cf_status chebfilter_rayleigh_ritz(cf_ctx *c, double *Y, int64_t ldy, int64_t N,
   if (N == 0) return CF_OK;
   HIPCHK(c, hipSetDevice(c->device));
   const int n = (int)N;
-  const int64_t ld = c->ldw;
+  const int64_t ld = c->ldw, cw = c->chunk;
   // Q (Euclidean-orthonormal): in U when the block fits the work blocks,
   // else in Y itself
-  const bool wide = N > ld;
+  const bool wide = N > cw;
   double *Qb = wide ? Y : c->U;
   const int64_t ldq = wide ? ldy : ld;
   STCHK(core_cholqr(c, Y, ldy, Qb, ldq, n));
@@ -1769,8 +1774,8 @@ cf_status chebfilter_rayleigh_ritz(cf_ctx *c, double *Y, int64_t ldy, int64_t N,
     // column chunk [j0, j1): T = H Q[:, j0:j1], then the slab rows 0..j1 of
     // Q^T T (the upper triangle and the chunk's diagonal block); likewise M;
     // the lower triangles are mirrored from the upper ones
-    for (int64_t j0 = 0; j0 < N; j0 += ld) {
-      const int nc = (int)std::min(ld, N - j0);
+    for (int64_t j0 = 0; j0 < N; j0 += cw) {
+      const int nc = (int)std::min(cw, N - j0);
       const int j1 = (int)j0 + nc;
       STCHK(core_apply_H(c, Qb + j0, ldq, c->T, ld, nc));
       STCHK(core_gram_slab(c, Qb, ldq, j1, c->T, ld, nc, c->Hh + j0, n));
@@ -3513,8 +3518,8 @@ cf_status chebfilter_residual_norms(cf_ctx *c, const double *Z, int64_t ldz, int
   const int64_t ld = c->ldw;
   // per column chunk: T = H Z - M Z diag(theta); U = (M^E)^-1 T; res_j = sqrt(T_j . U_j)
   HIPCHK(c, hipMemcpyAsync(c->theta, theta_host, N * sizeof(double), hipMemcpyHostToDevice, c->stream));
-  for (int64_t j0 = 0; j0 < N; j0 += ld) {
-    const int nc = (int)std::min(ld, N - j0);
+  for (int64_t j0 = 0; j0 < N; j0 += c->chunk) {
+    const int nc = (int)std::min(c->chunk, N - j0);
     STCHK(core_apply_H(c, Z + j0, ldz, c->T, ld, nc));
     STCHK(core_apply_M(c, Z + j0, ldz, c->U, ld, nc));
     HIPCHK(c, launch_sub_colscale(c->stream, c->n, nc, c->T, ld, c->U, ld, c->theta + j0));

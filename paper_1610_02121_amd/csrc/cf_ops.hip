@@ -66,12 +66,14 @@ __global__ __launch_bounds__(NPAD) void k_cell_gemv(
 // ---------------------------------------------------------------------------
 // Classical cell products for the cells of one colour:
 //   Y[dof(e,a)] (=|+=) sum_b H_e[a][b] X[dof(e,b)]
-// One workgroup of 8 waves per cell; wave w owns the 16 output rows
-// [16w, 16w+16) and keeps that slice of the (padded, symmetric) cell matrix in
-// registers as MFMA A fragments for the whole call.  Columns are walked in
-// tiles of CELL_NT: the next tile's gathered X rows and old Y values are
-// loaded into registers (two alternating sets for Y) during this tile's MFMA
-// loop, so their latency overlaps the matrix work; the current tile sits in LDS.  Dirichlet and
+// Two workgroups of 4 waves per cell, each owning 64 output rows; wave w (of
+// the cell's 8) owns the 16 output rows [16w, 16w+16) and keeps that slice of
+// the (padded, symmetric) cell matrix in registers as MFMA A fragments for the
+// whole call.  Columns are walked in tiles of CELL_NT: the next tile's
+// gathered X rows and old Y values are loaded into registers (two alternating
+// sets for Y) during this tile's MFMA loop, so their latency overlaps the
+// matrix work; the current tile sits in LDS, and a tile's results are stored
+// during the next tile (see the note at the stores).  Dirichlet and
 // padding rows are zero.  Cells of one colour share no DOF, so the
 // read-modify-write of Y is race free; the first cell (in launch order) to
 // touch a DOF writes instead of adding.
@@ -82,22 +84,27 @@ __global__ __launch_bounds__(NPAD) void k_cell_gemv(
 //   Out[d] = c1 dinv[d] (H X)[d] + c2 X[d] + c3 Yp[d]
 // (X[d] is read from the tile in LDS).  Those rows of Y are left untouched.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(512, 2) void k_cell_gemm(
+__global__ __launch_bounds__(256, 2) void k_cell_gemm(
     const double *__restrict__ Hp, const int32_t *__restrict__ dofp,
-    const uint8_t *__restrict__ flagp, const int32_t *__restrict__ cells,
+    const uint8_t *__restrict__ flagp, const int32_t *__restrict__ cells, int ncells,
     const double *__restrict__ X, int64_t ldx, double *__restrict__ Y, int64_t ldy, int N,
     const CellFinish f) {
   constexpr int NT = CELL_NT;
   constexpr int LDX = NT + 16;
-  constexpr int PF = NPAD * NT / 512;        // gathered doubles per thread per tile
-  constexpr int RPP = 512 / NT;              // gathered rows per pass
+  constexpr int PF = NPAD * NT / 256;        // gathered doubles per thread per tile
+  constexpr int RPP = 256 / NT;              // gathered rows per pass
   __shared__ double xs[NPAD * LDX];
   __shared__ int32_t sdof[NPAD];
   __shared__ uint8_t sflag[NPAD];
 
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  // workgroup id -> (cell, half): the two halves of a cell are 8 ids apart,
+  // so they run on the same XCD and share its L2 for the gathered rows
+  const int id = blockIdx.x;
+  const int ci = (id >> 4) * 8 + (id & 7), half = (id >> 3) & 1;
+  if (ci >= ncells) return;               // uniform for the workgroup
+  const int tid = threadIdx.x, lane = tid & 63, w = (tid >> 6) + 4 * half;
   const int li = lane & 15, kq = lane >> 4;
-  const int cell = cells[blockIdx.x];
+  const int cell = cells[ci];
   if (tid < NPAD) {
     sdof[tid] = dofp[(int64_t)cell * NPAD + tid];
     sflag[tid] = flagp[(int64_t)cell * NPAD + tid];
@@ -109,13 +116,25 @@ __global__ __launch_bounds__(512, 2) void k_cell_gemm(
   for (int ks = 0; ks < 32; ++ks) a[ks] = Hc[(4 * ks + kq) * NPAD + 16 * w + li];
   __syncthreads();
 
+  // gathered X rows: the loads are unconditional (Dirichlet rows and columns
+  // past N clamped into the block) and their values untouched until the LDS
+  // store, where they are masked
   const int gj = tid % NT, gr = tid / NT;
-  int gd[PF];
+  int64_t gd[PF];
+  bool gok[PF];
 #pragma unroll
-  for (int p = 0; p < PF; ++p) gd[p] = sdof[gr + p * RPP];
+  for (int p = 0; p < PF; ++p) {
+    const int d = sdof[gr + p * RPP];
+    gok[p] = d >= 0;
+    gd[p] = d >= 0 ? d : 0;
+  }
   double pf[PF];
+  auto gather = [&](int c) {
+    const int col = min(c + gj, N - 1);
 #pragma unroll
-  for (int p = 0; p < PF; ++p) pf[p] = (gd[p] >= 0 && gj < N) ? X[(int64_t)gd[p] * ldx + gj] : 0.0;
+    for (int p = 0; p < PF; ++p) pf[p] = X[gd[p] * ldx + col];
+  };
+  gather(0);
   const bool finish = f.Out != nullptr;
   int od[4];
   bool ofirst[4], ofin[4];
@@ -127,6 +146,11 @@ __global__ __launch_bounds__(512, 2) void k_cell_gemm(
     ofin[r] = finish && od[r] >= 0 && (sflag[row] & CELL_FINISH) != 0;
   }
 
+  // the scaled inverse mass of the finishing rows, read once
+  double dv[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) dv[r] = ofin[r] ? f.c1 * f.dinv[od[r]] : 0.0;
+
   // old Y (and Yp of finishing rows) of a tile, loaded one tile ahead into
   // one of two register sets
   auto load_y = [&](double (&yo)[4], double (&yp)[4], int c) {
@@ -137,44 +161,57 @@ __global__ __launch_bounds__(512, 2) void k_cell_gemm(
       yp[r] = (ofin[r] && f.Yp && cv) ? f.Yp[(int64_t)od[r] * f.ldyp + c + li] : 0.0;
     }
   };
+  // A tile's results are stored during the next tile, after that tile's
+  // gathered rows have gone to LDS: global stores and loads pending together
+  // make the wave wait for all of its memory operations, so a store issued
+  // at the end of a tile would hold up the next tile's LDS fill by its own
+  // latency.  Issued one tile later they have a whole MFMA loop to complete.
+  double out[4];
+  auto store_out = [&](int c0) {
+    if (c0 + li >= N) return;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      if (od[r] < 0) continue;
+      if (ofin[r])
+        f.Out[(int64_t)od[r] * f.ldo + c0 + li] = out[r];
+      else
+        Y[(int64_t)od[r] * ldy + c0 + li] = out[r];
+    }
+  };
   auto tile = [&](double (&yo)[4], double (&yp)[4], double (&yo2)[4], double (&yp2)[4],
                   int c0) {
-    const int ncol = min(NT, N - c0);
 #pragma unroll
-    for (int p = 0; p < PF; ++p) xs[(gr + p * RPP) * LDX + gj] = pf[p];
+    for (int p = 0; p < PF; ++p) xs[(gr + p * RPP) * LDX + gj] = (gok[p] && c0 + gj < N) ? pf[p] : 0.0;
+    if (c0 > 0) store_out(c0 - NT);
     __syncthreads();
     const int c1 = c0 + NT;
     if (c1 < N) {
-#pragma unroll
-      for (int p = 0; p < PF; ++p)
-        pf[p] = (gd[p] >= 0 && c1 + gj < N) ? X[(int64_t)gd[p] * ldx + c1 + gj] : 0.0;
+      gather(c1);
       load_y(yo2, yp2, c1);
     }
-    const bool cv = li < ncol;
     d4 acc = d4zero();
 #pragma unroll
     for (int ks = 0; ks < 32; ++ks) acc = mfma_f64(a[ks], xs[(4 * ks + kq) * LDX + li], acc);
-    if (cv) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        if (od[r] < 0) continue;
-        const double v = acc[r] + yo[r];
-        if (ofin[r]) {
-          const double xk = xs[(16 * w + kq + 4 * r) * LDX + li];
-          f.Out[(int64_t)od[r] * f.ldo + c0 + li] = f.c1 * f.dinv[od[r]] * v + f.c2 * xk + f.c3 * yp[r];
-        } else {
-          Y[(int64_t)od[r] * ldy + c0 + li] = v;
-        }
-      }
+    for (int r = 0; r < 4; ++r) {
+      const double v = acc[r] + yo[r];
+      const double xk = xs[(16 * w + kq + 4 * r) * LDX + li];
+      out[r] = ofin[r] ? dv[r] * v + f.c2 * xk + f.c3 * yp[r] : v;
     }
     __syncthreads();
   };
   double ya[4], pa[4], yb[4], pb[4];
   load_y(ya, pa, 0);
+  int clast = 0;
   for (int c0 = 0; c0 < N; c0 += 2 * NT) {
     tile(ya, pa, yb, pb, c0);
-    if (c0 + NT < N) tile(yb, pb, ya, pa, c0 + NT);
+    clast = c0;
+    if (c0 + NT < N) {
+      tile(yb, pb, ya, pa, c0 + NT);
+      clast = c0 + NT;
+    }
   }
+  store_out(clast);
 }
 
 hipError_t launch_cell_gemm(hipStream_t s, const double *Hp, const int32_t *dofp,
@@ -187,8 +224,10 @@ hipError_t launch_cell_gemm(hipStream_t s, const double *Hp, const int32_t *dofp
                        ldx, Y, ldy, f);
     return hipGetLastError();
   }
-  hipLaunchKernelGGL(k_cell_gemm, dim3(ncells), dim3(512), 0, s, Hp, dofp, flagp, cells, X, ldx,
-                     Y, ldy, N, f);
+  // two workgroups (each 64 output rows) per cell, ids laid out by k_cell_gemm
+  const int nblk = 16 * ((ncells + 7) / 8);
+  hipLaunchKernelGGL(k_cell_gemm, dim3(nblk), dim3(256), 0, s, Hp, dofp, flagp, cells, ncells, X,
+                     ldx, Y, ldy, N, f);
   return hipGetLastError();
 }
 
@@ -213,8 +252,8 @@ hipError_t launch_cell_gemm(hipStream_t s, const double *Hp, const int32_t *dofp
 // so every wave (and every SIMD) carries products whatever the block count.
 // A wave keeps the A fragments of both terms for its k part in registers
 // while the column tiles stream by; the KP = 8 / B partial sums are added
-// through LDS in k-part order.  The gathered rows of a tile are loaded two
-// tiles ahead into one of two register sets.
+// through LDS in k-part order.  The gathered rows of a tile are loaded one
+// tile ahead into registers.
 template <int B>
 __device__ __forceinline__ void enr_part_body(
     const double *__restrict__ ht, const double *__restrict__ mt, int nap, int nmb, int na,
@@ -238,25 +277,43 @@ __device__ __forceinline__ void enr_part_body(
       aH[ks] = (act && ht) ? ht[off] : 0.0;
       aM[ks] = (act && mt) ? mt[off] : 0.0;
     }
-    // two register sets of gathered rows, each refilled two tiles ahead
-    double xa[PF], ra[PF], xb[PF], rb[PF];
-    auto gather = [&](double (&qx)[PF], double (&qr)[PF], int c) {
+    // the gathered rows of the next tile, loaded during this tile's MFMAs.
+    // The loads are unconditional (row and column clamped into the block) and
+    // nothing touches their values before the LDS store, where the masking and
+    // the R scaling are applied.  A tile's partial sums are stored during the
+    // next tile, after its LDS fill: pending global stores make the wave wait
+    // for all of its memory operations, so stores issued at the end of a tile
+    // would hold up the next fill by their own latency.
+    double qx[PF], qr[PF], out[4];
+    auto gather = [&](int c) {
+      const int col = min(c + gj, cend - 1);
 #pragma unroll
       for (int p = 0; p < PF; ++p) {
-        const bool v = gd[p] >= 0 && c + gj < cend;
-        qx[p] = (X && v) ? X[(int64_t)gd[p] * ldx + c + gj] : 0.0;
-        qr[p] = (R && v) ? R[(int64_t)gd[p] * ldr + c + gj] * gsc[p] : 0.0;
+        const int64_t row = gd[p] >= 0 ? gd[p] : 0;
+        if (X) qx[p] = X[row * ldx + col];
+        if (R) qr[p] = R[row * ldr + col];
       }
     };
-    auto tile = [&](double (&qx)[PF], double (&qr)[PF], int c0) {
-      const int ncol = min(PT, cend - c0);
+    auto store_out = [&](int c0) {
+      if (act && h == 0 && c0 + li < cend) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int orow = 16 * mb + kq + 4 * r;
+          if (orow < na) P[(k0 + orow) * ldp + c0 + li] = out[r];
+        }
+      }
+    };
+    gather(cbeg);
+    for (int c0 = cbeg; c0 < cend; c0 += PT) {
 #pragma unroll
       for (int p = 0; p < PF; ++p) {
-        xs[(gr + p * RPP) * LDX + gj] = qx[p];
-        rsm[(gr + p * RPP) * LDX + gj] = qr[p];
+        const bool v = gd[p] >= 0 && c0 + gj < cend;
+        xs[(gr + p * RPP) * LDX + gj] = (X && v) ? qx[p] : 0.0;
+        rsm[(gr + p * RPP) * LDX + gj] = (R && v) ? qr[p] * gsc[p] : 0.0;
       }
+      if (c0 > cbeg) store_out(c0 - PT);
       __syncthreads();
-      if (c0 + 2 * PT < cend) gather(qx, qr, c0 + 2 * PT);
+      if (c0 + PT < cend) gather(c0 + PT);
       d4 acc = d4zero();
       if (act) {
         d4 accH = d4zero(), accM = d4zero();
@@ -278,23 +335,17 @@ __device__ __forceinline__ void enr_part_body(
         }
       }
       __syncthreads();
-      if (act && h == 0 && li < ncol) {
+      if (act && h == 0) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           double v = acc[r];
 #pragma unroll
           for (int q = 1; q < KP; ++q) v += xch[(((q - 1) * B + wb) * 4 + r) * 64 + lane];
-          const int orow = 16 * mb + kq + 4 * r;
-          if (orow < na) P[(k0 + orow) * ldp + c0 + li] = v;
+          out[r] = v;
         }
       }
-    };
-    gather(xa, ra, cbeg);
-    if (cbeg + PT < cend) gather(xb, rb, cbeg + PT);
-    for (int c0 = cbeg; c0 < cend; c0 += 2 * PT) {
-      tile(xa, ra, c0);
-      if (c0 + PT < cend) tile(xb, rb, c0 + PT);
     }
+    store_out(cbeg + PT * ((cend - cbeg - 1) / PT));
     __syncthreads();
   }
 }
@@ -412,12 +463,15 @@ hipError_t launch_enr_part(hipStream_t s, const double *HT, const double *MT, co
 //   Q[128 e' + a] = sum_k (cU H^ec_e[k][a] U[idx_k] + cV M^ec_e[k][a] V[idx_k])
 // e' is the position of the cell in the enriched-cell list, a its local node.
 // The enrichment functions of the cell are taken in chunks of 64 (16 or 32
-// for cells with at most that many): wave w keeps the A fragments of rows 32w .. 32w+32 of both transposed blocks for
-// the chunk in registers while the column tiles stream by (the blocks are read
-// from memory once per call); the gathered rows cU U[idx_k], cV V[idx_k] of
-// the chunk pass through LDS, prefetched one tile ahead in registers; chunks
-// after the first add into Q.  Either term is skipped when its input is null.  The epilogue sums, for each
-// classical DOF, the (at most 8) Q rows of the enriched cells that contain it.
+// for cells with at most that many).  Two workgroups of 4 waves share a cell
+// (blockIdx.y picks 64 of its 128 local nodes): wave w keeps the A fragments of
+// rows 16w .. 16w+16 of both transposed blocks for the chunk in registers
+// while the column tiles stream by (the blocks are read from memory once per
+// call); the gathered rows cU U[idx_k], cV V[idx_k] of the chunk pass through
+// LDS, loaded one tile ahead into registers; chunks after the first add into
+// Q.  Either term is skipped when its input is null.  The epilogue sums, for
+// each classical DOF, the (at most 8) Q rows of the enriched cells that
+// contain it.
 // ---------------------------------------------------------------------------
 // Cells with at most 16 or 32 enrichment functions take chunks of that size
 // (KC = 16 or 32), so their waves run only the k steps that carry products.
@@ -426,99 +480,94 @@ __device__ __forceinline__ void enr_q_body(
     const double *__restrict__ Hec, const double *__restrict__ Mec, int64_t k0, int na,
     const int32_t *__restrict__ eidx, const double *__restrict__ U, int64_t ldu, double cU,
     const double *__restrict__ V, int64_t ldv, double cV, double *__restrict__ qb, int64_t ldq,
-    int N, double *zu, double *zv) {
+    int N, double *zu, double *zv, double *qs) {
   constexpr int PT = 16, LDZ = 16, KS = KC / 4;
-  constexpr int GV = KC * PT / 256;        // gathered values per thread per term and tile
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  constexpr int GR = 256 / PT;             // gathered rows per pass
+  constexpr int GV = (KC + GR - 1) / GR;   // passes per term and tile
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = (tid >> 6) + 4 * (int)blockIdx.y;   // 16-row block of the 128 local nodes
   const int li = lane & 15, kq = lane >> 4;
-  const int gj = tid % PT, gk = tid / PT;   // gather: column gj, rows gk + 16 p
-  // chunks of KC enrichment functions: the A fragments of the chunk (rows
-  // 32w .. 32w+32 of both transposed blocks) stay in registers while the
-  // column tiles stream by; chunks after the first add into Q
+  const int gj = tid % PT, gk = tid / PT;   // gather: column gj, rows gk + GR p
   for (int kc = 0; kc < na; kc += KC) {
-    double aH0[KS], aH1[KS], aM0[KS], aM1[KS];
+    double aH[KS], aM[KS];
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
       const int k = kc + 4 * ks + kq;
       const bool v = k < na;
-      const double *hr = Hec + (k0 + (v ? k : 0)) * NPAD + 32 * w;
-      const double *mr = Mec + (k0 + (v ? k : 0)) * NPAD + 32 * w;
-      aH0[ks] = (U && v) ? hr[li] : 0.0;
-      aH1[ks] = (U && v) ? hr[16 + li] : 0.0;
-      aM0[ks] = (V && v) ? mr[li] : 0.0;
-      aM1[ks] = (V && v) ? mr[16 + li] : 0.0;
+      const int64_t off = (k0 + (v ? k : 0)) * NPAD + 16 * w + li;
+      aH[ks] = (U && v) ? Hec[off] : 0.0;
+      aM[ks] = (V && v) ? Mec[off] : 0.0;
     }
     int64_t gal[GV];
     bool gv[GV];
 #pragma unroll
     for (int p = 0; p < GV; ++p) {
-      const int k = kc + gk + 16 * p;
-      gv[p] = k < na;
+      const int k = kc + gk + GR * p;
+      gv[p] = gk + GR * p < KC && k < na;
       gal[p] = gv[p] ? eidx[k0 + k] : 0;
     }
+    // the next tile's gathered rows, loaded during this tile's MFMAs; the
+    // loads are unconditional (column clamped) and their values untouched
+    // until the LDS store.  A tile's Q values are parked in LDS (each lane
+    // reads back only what it wrote) and stored to memory during the next
+    // tile, after its LDS fill: pending global stores make the wave wait for
+    // all of its memory operations, so stores issued at the end of a tile
+    // would hold up the next fill by their own latency.
     double pu[GV], pv[GV];
-#pragma unroll
-    for (int p = 0; p < GV; ++p) {
-      const bool v = gv[p] && gj < N;
-      pu[p] = (U && v) ? cU * U[gal[p] * ldu + gj] : 0.0;
-      pv[p] = (V && v) ? cV * V[gal[p] * ldv + gj] : 0.0;
-    }
-    for (int c0 = 0; c0 < N; c0 += PT) {
-      const int ncol = min(PT, N - c0);
+    auto gather = [&](int c) {
+      const int col = min(c + gj, N - 1);
 #pragma unroll
       for (int p = 0; p < GV; ++p) {
-        zu[(gk + 16 * p) * LDZ + gj] = pu[p];
-        zv[(gk + 16 * p) * LDZ + gj] = pv[p];
+        if (U) pu[p] = U[gal[p] * ldu + col];
+        if (V) pv[p] = V[gal[p] * ldv + col];
       }
-      __syncthreads();
-      const int c1 = c0 + PT;
-      if (c1 < N) {
-#pragma unroll
-        for (int p = 0; p < GV; ++p) {
-          const bool v = gv[p] && c1 + gj < N;
-          pu[p] = (U && v) ? cU * U[gal[p] * ldu + c1 + gj] : 0.0;
-          pv[p] = (V && v) ? cV * V[gal[p] * ldv + c1 + gj] : 0.0;
-        }
-      }
-      // chunks after the first add into Q: its old values, loaded before the
-      // products so that their latency overlaps them
-      double qo0[4], qo1[4];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const bool ld = kc > 0 && li < ncol;
-        const double *q = qb + c0 + li;
-        qo0[r] = ld ? q[(int64_t)(32 * w + kq + 4 * r) * ldq] : 0.0;
-        qo1[r] = ld ? q[(int64_t)(32 * w + 16 + kq + 4 * r) * ldq] : 0.0;
-      }
-      d4 acc0 = d4zero(), acc1 = d4zero();
-      if (U) {
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-          const double b = zu[(4 * ks + kq) * LDZ + li];
-          acc0 = mfma_f64(aH0[ks], b, acc0);
-          acc1 = mfma_f64(aH1[ks], b, acc1);
-        }
-      }
-      if (V) {
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-          const double b = zv[(4 * ks + kq) * LDZ + li];
-          acc0 = mfma_f64(aM0[ks], b, acc0);
-          acc1 = mfma_f64(aM1[ks], b, acc1);
-        }
-      }
-      if (li < ncol) {
+    };
+    auto store_q = [&](int c0) {
+      if (c0 + li < N) {
         double *q = qb + c0 + li;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          double *q0 = q + (int64_t)(32 * w + kq + 4 * r) * ldq;
-          double *q1 = q + (int64_t)(32 * w + 16 + kq + 4 * r) * ldq;
-          *q0 = acc0[r] + qo0[r];
-          *q1 = acc1[r] + qo1[r];
+          const int row = 16 * w + kq + 4 * r;
+          q[(int64_t)row * ldq] = qs[row * PT + li];
         }
       }
+    };
+    gather(0);
+    for (int c0 = 0; c0 < N; c0 += PT) {
+#pragma unroll
+      for (int p = 0; p < GV; ++p) {
+        if (gk + GR * p < KC) {
+          const bool v = gv[p] && c0 + gj < N;
+          zu[(gk + GR * p) * LDZ + gj] = (U && v) ? cU * pu[p] : 0.0;
+          zv[(gk + GR * p) * LDZ + gj] = (V && v) ? cV * pv[p] : 0.0;
+        }
+      }
+      if (c0 > 0) store_q(c0 - PT);
+      __syncthreads();
+      if (c0 + PT < N) gather(c0 + PT);
+      // chunks after the first add into Q: its old values, loaded before the
+      // products so that their latency overlaps them
+      double qo[4];
+      if (kc > 0) {
+        const double *q = qb + min(c0 + li, N - 1);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) qo[r] = q[(int64_t)(16 * w + kq + 4 * r) * ldq];
+      }
+      d4 acc = d4zero();
+      if (U) {
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) acc = mfma_f64(aH[ks], zu[(4 * ks + kq) * LDZ + li], acc);
+      }
+      if (V) {
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) acc = mfma_f64(aM[ks], zv[(4 * ks + kq) * LDZ + li], acc);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        qs[(16 * w + kq + 4 * r) * PT + li] = acc[r] + (kc > 0 ? qo[r] : 0.0);
       __syncthreads();
     }
+    store_q(PT * ((N - 1) / PT));
   }
 }
 
@@ -532,6 +581,7 @@ __global__ __launch_bounds__(256, 2) void k_enr_q(
   constexpr int PT = 16, LDZ = 16, KC = 64;
   __shared__ double zu[KC * LDZ];
   __shared__ double zv[KC * LDZ];
+  __shared__ double qs[NPAD * PT];         // a tile's Q values until their store
   const int tid = threadIdx.x;
   const int pos = order ? order[blockIdx.x] : (int)blockIdx.x;   // position in the cell list
   const int cell = cells[pos];
@@ -539,16 +589,16 @@ __global__ __launch_bounds__(256, 2) void k_enr_q(
   const int na = (int)(eptr[cell + 1] - k0);
   double *qb = Q + ((int64_t)pos * NPAD) * ldq;
   if (na > 32)
-    enr_q_body<64>(Hec, Mec, k0, na, eidx, U, ldu, cU, V, ldv, cV, qb, ldq, N, zu, zv);
+    enr_q_body<64>(Hec, Mec, k0, na, eidx, U, ldu, cU, V, ldv, cV, qb, ldq, N, zu, zv, qs);
   else if (na > 16)
-    enr_q_body<32>(Hec, Mec, k0, na, eidx, U, ldu, cU, V, ldv, cV, qb, ldq, N, zu, zv);
+    enr_q_body<32>(Hec, Mec, k0, na, eidx, U, ldu, cU, V, ldv, cV, qb, ldq, N, zu, zv, qs);
   else if (na > 0)
-    enr_q_body<16>(Hec, Mec, k0, na, eidx, U, ldu, cU, V, ldv, cV, qb, ldq, N, zu, zv);
+    enr_q_body<16>(Hec, Mec, k0, na, eidx, U, ldu, cU, V, ldv, cV, qb, ldq, N, zu, zv, qs);
   if (na == 0) {
-    // no enrichment functions: the cell's buffer rows are zero
+    // no enrichment functions: the workgroup's 64 buffer rows are zero
     for (int c0 = 0; c0 < N; c0 += PT)
-      for (int idx = tid; idx < NPAD * PT; idx += 256) {
-        const int a = idx / PT, j = idx % PT;
+      for (int idx = tid; idx < 64 * PT; idx += 256) {
+        const int a = 64 * (int)blockIdx.y + idx / PT, j = idx % PT;
         if (c0 + j < N) qb[(int64_t)a * ldq + c0 + j] = 0.0;
       }
   }
@@ -606,7 +656,7 @@ hipError_t launch_enr_q(hipStream_t s, const double *Hec, const double *Mec, con
                        order, U, ldu, cU, V, ldv, cV, Q, ldq);
     return hipGetLastError();
   }
-  hipLaunchKernelGGL(k_enr_q, dim3(ncells), dim3(256), 0, s, Hec, Mec, eptr, eidx, cells, order, U,
+  hipLaunchKernelGGL(k_enr_q, dim3(ncells, 2), dim3(256), 0, s, Hec, Mec, eptr, eidx, cells, order, U,
                      ldu, cU, V, ldv, cV, Q, ldq, N);
   return hipGetLastError();
 }

@@ -100,13 +100,25 @@ __device__ __forceinline__ void cell_gemm_lp_body(
   }
   __syncthreads();
 
+  // gathered X rows: the loads are unconditional (Dirichlet rows and columns
+  // past N clamped into the block) and their values untouched until the LDS
+  // store, where they are masked
   const int gj = tid % NT, gr = tid / NT;
-  int gd[PF];
+  int64_t gd[PF];
+  bool gok[PF];
 #pragma unroll
-  for (int p = 0; p < PF; ++p) gd[p] = sdof[gr + p * RPP];
+  for (int p = 0; p < PF; ++p) {
+    const int d = sdof[gr + p * RPP];
+    gok[p] = d >= 0;
+    gd[p] = d >= 0 ? d : 0;
+  }
   float pf[PF];
+  auto gather = [&](int c) {
+    const int col = min(c + gj, N - 1);
 #pragma unroll
-  for (int p = 0; p < PF; ++p) pf[p] = (gd[p] >= 0 && gj < N) ? X[(int64_t)gd[p] * ldx + gj] : 0.f;
+    for (int p = 0; p < PF; ++p) pf[p] = X[gd[p] * ldx + col];
+  };
+  gather(0);
   const bool finish = f.Out != nullptr;
   float fc1 = f.c1, fc2 = f.c2, fc3 = f.c3;
   if (f.mult) {
@@ -123,6 +135,10 @@ __device__ __forceinline__ void cell_gemm_lp_body(
     ofirst[r] = (sflag[row] & CELL_FIRST) != 0;
     ofin[r] = finish && od[r] >= 0 && (sflag[row] & CELL_FINISH) != 0;
   }
+  // the scaled inverse mass of the finishing rows, read once
+  float dv[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) dv[r] = ofin[r] ? fc1 * (float)f.dinv[od[r]] : 0.f;
 
   // old Y (and Yp of finishing rows) of a tile's two column blocks, loaded
   // one tile ahead into one of two register sets
@@ -138,24 +154,43 @@ __device__ __forceinline__ void cell_gemm_lp_body(
       }
     }
   };
+  // A tile's results are stored during the next tile, after that tile's
+  // gathered rows have gone to LDS (pending global stores make the wave wait
+  // for all of its memory operations before the fill).
+  float out[NSB][4];
+  auto store_out = [&](int c0) {
+#pragma unroll
+    for (int sb = 0; sb < NSB; ++sb) {
+      const int col = c0 + 16 * sb + li;
+      if (col >= N) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        if (od[r] < 0) continue;
+        if (ofin[r])
+          f.Out[(int64_t)od[r] * f.ldo + col] = out[sb][r];
+        else
+          Y[(int64_t)od[r] * ldy + col] = out[sb][r];
+      }
+    }
+  };
   auto tile = [&](float (&yo)[NSB][4], float (&yp)[NSB][4], float (&yo2)[NSB][4],
                   float (&yp2)[NSB][4], int c0) {
 #pragma unroll
     for (int p = 0; p < PF; ++p) {
       const int row = gr + p * RPP;
+      const float v = (gok[p] && c0 + gj < N) ? pf[p] : 0.f;
       if constexpr (BF16) {
-        xt[gj * LDT + row] = (__bf16)pf[p];
-        xk_tile[row * NT + gj] = pf[p];
+        xt[gj * LDT + row] = (__bf16)v;
+        xk_tile[row * NT + gj] = v;
       } else {
-        xs[row * LDX + gj] = pf[p];
+        xs[row * LDX + gj] = v;
       }
     }
+    if (c0 > 0) store_out(c0 - NT);
     __syncthreads();
     const int c1 = c0 + NT;
     if (c1 < N) {
-#pragma unroll
-      for (int p = 0; p < PF; ++p)
-        pf[p] = (gd[p] >= 0 && c1 + gj < N) ? X[(int64_t)gd[p] * ldx + c1 + gj] : 0.f;
+      gather(c1);
       load_y(yo2, yp2, c1);
     }
     f4 acc[NSB];
@@ -176,33 +211,34 @@ __device__ __forceinline__ void cell_gemm_lp_body(
     }
 #pragma unroll
     for (int sb = 0; sb < NSB; ++sb) {
-      const int col = c0 + 16 * sb + li;
-      if (col >= N) continue;
+      const bool cv = c0 + 16 * sb + li < N;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        if (od[r] < 0) continue;
         const float v = acc[sb][r] + yo[sb][r];
-        if (ofin[r]) {
-          const int row = 16 * w + 4 * kq + r;
-          float xk;
-          if constexpr (BF16) xk = xk_tile[row * NT + 16 * sb + li];
-          else xk = xs[row * LDX + 16 * sb + li];
-          const float o = fc1 * (float)f.dinv[od[r]] * v + fc2 * xk + fc3 * yp[sb][r];
-          f.Out[(int64_t)od[r] * f.ldo + col] = o;
-          omax = absmax(omax, o);
-        } else {
-          Y[(int64_t)od[r] * ldy + col] = v;
-        }
+        const int row = 16 * w + 4 * kq + r;
+        float xk;
+        if constexpr (BF16) xk = xk_tile[row * NT + 16 * sb + li];
+        else xk = xs[row * LDX + 16 * sb + li];
+        // explicit fused steps: the rounding is the same in every tile shape
+        const float o = fmaf(fc3, yp[sb][r], fmaf(fc2, xk, dv[r] * v));
+        out[sb][r] = ofin[r] ? o : v;
+        if (ofin[r] && cv) omax = absmax(omax, o);
       }
     }
     __syncthreads();
   };
   float ya[NSB][4], pa[NSB][4], yb[NSB][4], pb[NSB][4];
   load_y(ya, pa, 0);
+  int clast = 0;
   for (int c0 = 0; c0 < N; c0 += 2 * NT) {
     tile(ya, pa, yb, pb, c0);
-    if (c0 + NT < N) tile(yb, pb, ya, pa, c0 + NT);
+    clast = c0;
+    if (c0 + NT < N) {
+      tile(yb, pb, ya, pa, c0 + NT);
+      clast = c0 + NT;
+    }
   }
+  store_out(clast);
   if (f.mx) gather_max(f.mx, omax, (float *)sdof, slot);   // sdof is free after the tile loop
 }
 
@@ -217,8 +253,8 @@ __device__ __forceinline__ void cell_gemm_lp_body(
 // registers; the parts are added through LDS in k-part order.  B is chosen
 // per cell from its number of row blocks by the map `bmap` (2 bits per
 // bucket of 1, 2, 3, >= 4 row blocks: 0 -> B = 1, 1 -> 2, 2 -> 4), which the
-// autotuner sets.  The gathered rows of a tile are loaded two tiles ahead
-// into one of two register sets.
+// autotuner sets.  The gathered rows of a tile are loaded one tile ahead into
+// registers.
 __device__ __forceinline__ int cpl_b(int bmap, int nmb) {
   const int q = nmb < 4 ? nmb - 1 : 3;
   return 1 << ((bmap >> (2 * q)) & 3);
@@ -246,24 +282,40 @@ __device__ __forceinline__ void enr_part_f32_impl(
       aH[ks] = (act && ht) ? ht[off] : 0.f;
       aM[ks] = (act && mt) ? mt[off] : 0.f;
     }
-    float xa[PF], ra[PF], xb[PF], rb[PF];
-    auto gather = [&](float (&qx)[PF], float (&qr)[PF], int c) {
+    // the gathered rows of the next tile, loaded during this tile's MFMAs;
+    // the loads are unconditional (row and column clamped) and their values
+    // untouched until the LDS store (masking and R scaling there).  A tile's
+    // partial sums are stored during the next tile, after its LDS fill.
+    float qx[PF], qr[PF], out[4];
+    auto gather = [&](int c) {
+      const int col = min(c + gj, N - 1);
 #pragma unroll
       for (int p = 0; p < PF; ++p) {
-        const bool v = gd[p] >= 0 && c + gj < N;
-        qx[p] = (X && v) ? X[(int64_t)gd[p] * ldx + c + gj] : 0.f;
-        qr[p] = (R && v) ? R[(int64_t)gd[p] * ldr + c + gj] * gsc[p] : 0.f;
+        const int64_t row = gd[p] >= 0 ? gd[p] : 0;
+        if (X) qx[p] = X[row * ldx + col];
+        if (R) qr[p] = R[row * ldr + col];
       }
     };
-    auto tile = [&](float (&qx)[PF], float (&qr)[PF], int c0) {
-      const int ncol = min(PT, N - c0);
+    auto store_out = [&](int c0) {
+      if (act && h == 0 && c0 + li < N) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int orow = 16 * mb + 4 * kq + r;
+          if (orow < na) P[(k0 + orow) * ldp + c0 + li] = out[r];
+        }
+      }
+    };
+    gather(0);
+    for (int c0 = 0; c0 < N; c0 += PT) {
 #pragma unroll
       for (int p = 0; p < PF; ++p) {
-        xs[(gr + p * RPP) * LDX + gj] = qx[p];
-        rsm[(gr + p * RPP) * LDX + gj] = qr[p];
+        const bool v = gd[p] >= 0 && c0 + gj < N;
+        xs[(gr + p * RPP) * LDX + gj] = (X && v) ? qx[p] : 0.f;
+        rsm[(gr + p * RPP) * LDX + gj] = (R && v) ? qr[p] * gsc[p] : 0.f;
       }
+      if (c0 > 0) store_out(c0 - PT);
       __syncthreads();
-      if (c0 + 2 * PT < N) gather(qx, qr, c0 + 2 * PT);
+      if (c0 + PT < N) gather(c0 + PT);
       f4 acc = f4zero();
       if (act) {
         f4 accH = f4zero(), accM = f4zero();
@@ -285,23 +337,17 @@ __device__ __forceinline__ void enr_part_f32_impl(
         }
       }
       __syncthreads();
-      if (act && h == 0 && li < ncol) {
+      if (act && h == 0) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           float v = acc[r];
 #pragma unroll
           for (int q = 1; q < KP; ++q) v += xch[(((q - 1) * B + wb) * 4 + r) * 64 + lane];
-          const int orow = 16 * mb + 4 * kq + r;
-          if (orow < na) P[(k0 + orow) * ldp + c0 + li] = v;
+          out[r] = v;
         }
       }
-    };
-    gather(xa, ra, 0);
-    if (PT < N) gather(xb, rb, PT);
-    for (int c0 = 0; c0 < N; c0 += 2 * PT) {
-      tile(xa, ra, c0);
-      if (c0 + PT < N) tile(xb, rb, c0 + PT);
     }
+    store_out(PT * ((N - 1) / PT));
     __syncthreads();
   }
 }
@@ -391,30 +437,42 @@ __device__ __forceinline__ void enr_q_f32_body(
       gv[p] = k < na;
       gal[p] = gv[p] ? eidx[k0 + k] : 0;
     }
-    float pu[GV], pv[GV];
+    // the next tile's gathered rows, loaded during this tile's MFMAs
+    // (unconditional loads, column clamped; scaled and masked at the LDS
+    // store); a tile's Q values are stored during the next tile, after its
+    // LDS fill
+    float pu[GV], o0[4], o1[4];
+    double pv[GV];
+    auto gather = [&](int c) {
+      const int col = min(c + gj, N - 1);
 #pragma unroll
-    for (int p = 0; p < GV; ++p) {
-      const bool v = gv[p] && gj < N;
-      pu[p] = (U && v) ? cU * U[gal[p] * ldu + gj] : 0.f;
-      pv[p] = (V && v) ? cV * (float)V[gal[p] * ldv + gj] : 0.f;
-    }
+      for (int p = 0; p < GV; ++p) {
+        if (U) pu[p] = U[gal[p] * ldu + col];
+        if (V) pv[p] = V[gal[p] * ldv + col];
+      }
+    };
+    auto store_q = [&](int c0) {
+      if (c0 + li < N) {
+        float *q = qb + c0 + li;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          q[(int64_t)(32 * w + 4 * kq + r) * ldq] = o0[r];
+          q[(int64_t)(32 * w + 16 + 4 * kq + r) * ldq] = o1[r];
+        }
+      }
+    };
+    gather(0);
     for (int c0 = 0; c0 < N; c0 += PT) {
       const int ncol = min(PT, N - c0);
 #pragma unroll
       for (int p = 0; p < GV; ++p) {
-        zu[(gk + 16 * p) * LDZ + gj] = pu[p];
-        zv[(gk + 16 * p) * LDZ + gj] = pv[p];
+        const bool v = gv[p] && c0 + gj < N;
+        zu[(gk + 16 * p) * LDZ + gj] = (U && v) ? cU * pu[p] : 0.f;
+        zv[(gk + 16 * p) * LDZ + gj] = (V && v) ? cV * (float)pv[p] : 0.f;
       }
+      if (c0 > 0) store_q(c0 - PT);
       __syncthreads();
-      const int c1 = c0 + PT;
-      if (c1 < N) {
-#pragma unroll
-        for (int p = 0; p < GV; ++p) {
-          const bool v = gv[p] && c1 + gj < N;
-          pu[p] = (U && v) ? cU * U[gal[p] * ldu + c1 + gj] : 0.f;
-          pv[p] = (V && v) ? cV * (float)V[gal[p] * ldv + c1 + gj] : 0.f;
-        }
-      }
+      if (c0 + PT < N) gather(c0 + PT);
       // chunks after the first add into Q: its old values, loaded before the
       // products so that their latency overlaps them
       float qo0[4], qo1[4];
@@ -442,18 +500,14 @@ __device__ __forceinline__ void enr_q_f32_body(
           acc1 = mfma_f32(aM1[ks], b, acc1);
         }
       }
-      if (li < ncol) {
-        float *q = qb + c0 + li;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          float *q0 = q + (int64_t)(32 * w + 4 * kq + r) * ldq;
-          float *q1 = q + (int64_t)(32 * w + 16 + 4 * kq + r) * ldq;
-          *q0 = acc0[r] + qo0[r];
-          *q1 = acc1[r] + qo1[r];
-        }
+      for (int r = 0; r < 4; ++r) {
+        o0[r] = acc0[r] + qo0[r];
+        o1[r] = acc1[r] + qo1[r];
       }
       __syncthreads();
     }
+    store_q(PT * ((N - 1) / PT));
   }
   if (na == 0) {
     for (int c0 = 0; c0 < N; c0 += PT)

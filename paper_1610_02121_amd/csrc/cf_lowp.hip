@@ -79,13 +79,26 @@ hipError_t launch_enr_q_f32(hipStream_t s, const float *Hec, const float *Mec,
   return hipGetLastError();
 }
 
-__global__ __launch_bounds__(64) void k_enr_reduce_f32(
+// One wave per quarter of each element's sums (see enr_reduce_f32_elem),
+// combined in quarter order: the same bits as the batched form.
+__global__ __launch_bounds__(256) void k_enr_reduce_f32(
     int n_e, const int64_t *__restrict__ aptr, const int32_t *__restrict__ alist,
     const float *__restrict__ P, int64_t ldp, const double *__restrict__ Dn,
     const float *__restrict__ Zd, int64_t ldzd, double *__restrict__ out, int64_t ldo, int N) {
-  const int col = blockIdx.x * 64 + threadIdx.x;
-  if (col >= N) return;
-  enr_reduce_f32_elem(n_e, aptr, alist, P, ldp, Dn, Zd, ldzd, out, ldo, blockIdx.y, col);
+  __shared__ double part[2][4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int col = blockIdx.x * 64 + lane;
+  const int al = blockIdx.y;
+  double sp = 0.0, sd = 0.0;
+  if (col < N)
+    enr_reduce_f32_quarter(n_e, aptr, alist, P, ldp, Dn, Zd, ldzd, al, col, w, sp, sd);
+  part[0][w][lane] = sp;
+  part[1][w][lane] = sd;
+  __syncthreads();
+  if (w == 0 && col < N)
+    out[(int64_t)al * ldo + col] =
+        (((part[0][0][lane] + part[0][1][lane]) + part[0][2][lane]) + part[0][3][lane]) +
+        (((part[1][0][lane] + part[1][1][lane]) + part[1][2][lane]) + part[1][3][lane]);
 }
 
 hipError_t launch_enr_reduce_f32(hipStream_t s, int n_e, const int64_t *aptr,
@@ -94,7 +107,7 @@ hipError_t launch_enr_reduce_f32(hipStream_t s, int n_e, const int64_t *aptr,
                                  int64_t ldo, int N) {
   if (n_e <= 0 || N <= 0) return hipSuccess;
   dim3 grid((N + 63) / 64, n_e);
-  hipLaunchKernelGGL(k_enr_reduce_f32, grid, dim3(64), 0, s, n_e, aptr, alist, P, ldp, Dn, Zd, ldzd,
+  hipLaunchKernelGGL(k_enr_reduce_f32, grid, dim3(256), 0, s, n_e, aptr, alist, P, ldp, Dn, Zd, ldzd,
                      out, ldo, N);
   return hipGetLastError();
 }

@@ -522,17 +522,53 @@ __device__ __forceinline__ void enr_q_f32_body(
 // Enrichment rows from FP32 partials, accumulated in FP64:
 //   out[al,:] = sum_{k in list(al)} P[k,:] + sum_be Dn[al,be] Zd[be,:]     (Zd FP32)
 // ---------------------------------------------------------------------------
+// The sums of one element are split into 4 contiguous quarters of the
+// partial list and of the dense product, each summed in index order from zero
+// and combined as ((q0 + q1) + q2) + q3: the batched form adds the quarters
+// one after the other, the single-problem kernel gives each quarter a wave;
+// the bits are the same.  Loads are issued 8 at a time before their adds.
+__device__ __forceinline__ void enr_reduce_f32_quarter(
+    int n_e, const int64_t *__restrict__ aptr, const int32_t *__restrict__ alist,
+    const float *__restrict__ P, int64_t ldp, const double *__restrict__ Dn,
+    const float *__restrict__ Zd, int64_t ldzd, int al, int col, int w, double &sp, double &sd) {
+  constexpr int U = 8;
+  sp = 0.0;
+  sd = 0.0;
+  const int64_t a0 = aptr[al], len = aptr[al + 1] - a0;
+  const int64_t q0 = a0 + (len * w) / 4, q1 = a0 + (len * (w + 1)) / 4;
+  int64_t k = q0;
+  for (; k + U <= q1; k += U) {
+    float t[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) t[u] = P[(int64_t)alist[k + u] * ldp + col];
+#pragma unroll
+    for (int u = 0; u < U; ++u) sp += (double)t[u];
+  }
+  for (; k < q1; ++k) sp += (double)P[(int64_t)alist[k] * ldp + col];
+  const double *drow = Dn + (int64_t)al * n_e;
+  const int b0 = (n_e * w) / 4, b1 = (n_e * (w + 1)) / 4;
+  int be = b0;
+  for (; be + U <= b1; be += U) {
+    float t[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) t[u] = Zd[(int64_t)(be + u) * ldzd + col];
+#pragma unroll
+    for (int u = 0; u < U; ++u) sd += drow[be + u] * (double)t[u];
+  }
+  for (; be < b1; ++be) sd += drow[be] * (double)Zd[(int64_t)be * ldzd + col];
+}
+
 __device__ __forceinline__ void enr_reduce_f32_elem(
     int n_e, const int64_t *__restrict__ aptr, const int32_t *__restrict__ alist,
     const float *__restrict__ P, int64_t ldp, const double *__restrict__ Dn,
     const float *__restrict__ Zd, int64_t ldzd, double *__restrict__ out, int64_t ldo, int al,
     int col) {
-  double acc = 0.0;
-  for (int64_t k = aptr[al]; k < aptr[al + 1]; ++k) acc += (double)P[(int64_t)alist[k] * ldp + col];
-  const double *drow = Dn + (int64_t)al * n_e;
-  double sd = 0.0;
-  for (int be = 0; be < n_e; ++be) sd += drow[be] * (double)Zd[(int64_t)be * ldzd + col];
-  out[(int64_t)al * ldo + col] = acc + sd;
+  double sp[4], sd[4];
+#pragma unroll
+  for (int w = 0; w < 4; ++w)
+    enr_reduce_f32_quarter(n_e, aptr, alist, P, ldp, Dn, Zd, ldzd, al, col, w, sp[w], sd[w]);
+  out[(int64_t)al * ldo + col] =
+      (((sp[0] + sp[1]) + sp[2]) + sp[3]) + (((sd[0] + sd[1]) + sd[2]) + sd[3]);
 }
 
 // ---------------------------------------------------------------------------
@@ -540,7 +576,12 @@ __device__ __forceinline__ void enr_reduce_f32_elem(
 // enrichment rows (Ee FP64, converted).
 // ---------------------------------------------------------------------------
 // Block of 64 x 4 threads; this block takes rows t = 4 b0 + threadIdx.y,
-// t += 4 bstride.
+// t += 4 bstride.  When every block's rows start on 16-byte boundaries a lane
+// takes 4 adjacent columns with vector loads, and a DOF's (at most 8) buffer
+// rows are loaded before any of them is added, so the loads of an element are
+// all in flight together; the arithmetic of an element (sum order included)
+// is the same in both mappings.
+constexpr int EPI_F32_QMAX = 8;
 __device__ __forceinline__ void epilogue_f32_body(const EpiArgsF &g, int64_t b0, int64_t bstride,
                                                   int slot) {
   const int64_t ncls = g.rows ? g.nrows : g.n_h;
@@ -550,6 +591,11 @@ __device__ __forceinline__ void epilogue_f32_body(const EpiArgsF &g, int64_t b0,
     const float al = g.mult[0], be = g.mult[1];
     gc1 *= al; gc2 *= al; gc3 *= be;
   }
+  auto a16 = [](const void *ptr, int64_t ld, int64_t elems) {
+    return ptr == nullptr || (((uintptr_t)ptr & 15) == 0 && (ld * elems) % 16 == 0);
+  };
+  const bool vec = a16(g.R, g.ldr, 4) && a16(g.Q, g.ldq, 4) && a16(g.Ee, g.lde, 8) &&
+                   a16(g.Yk, g.ldyk, 4) && a16(g.Yp, g.ldyp, 4) && a16(g.Out, g.ldo, 4);
   float omax = 0.f;
   for (int64_t t = b0 * 4 + threadIdx.y; t < nt; t += bstride * 4) {
     const bool cls = t < ncls;
@@ -560,20 +606,85 @@ __device__ __forceinline__ void epilogue_f32_body(const EpiArgsF &g, int64_t b0,
       if (g.dinv) dr = (float)g.dinv[i];
       if (g.qptr) { p0 = g.qptr[i]; p1 = g.qptr[i + 1]; }
     }
-    for (int j = threadIdx.x; j < g.N; j += 64) {
+    const int nq = p1 - p0;
+    // one element, the loads of its buffer rows given
+    auto elem = [&](int j, float r, const float *qv, double e, float yk, float yp) {
       float v;
       if (cls) {
-        float s = g.R[i * g.ldr + j];
-        for (int p = p0; p < p1; ++p) s += g.Q[(int64_t)g.qidx[p] * g.ldq + j];
+        float s = r;
+        for (int u = 0; u < nq; ++u) s += qv[u];
         v = dr * s;
       } else {
-        v = (float)g.Ee[(i - g.n_h) * g.lde + j];
+        v = (float)e;
       }
       v *= gc1;
-      if (g.Yk) v += gc2 * g.Yk[i * g.ldyk + j];
-      if (g.Yp) v += gc3 * g.Yp[i * g.ldyp + j];
+      if (g.Yk) v += gc2 * yk;
+      if (g.Yp) v += gc3 * yp;
       g.Out[i * g.ldo + j] = v;
       omax = absmax(omax, v);
+    };
+    if (vec && nq <= EPI_F32_QMAX) {
+      int64_t qo[EPI_F32_QMAX];
+#pragma unroll
+      for (int u = 0; u < EPI_F32_QMAX; ++u) qo[u] = u < nq ? (int64_t)g.qidx[p0 + u] * g.ldq : 0;
+      for (int j = 4 * threadIdx.x; j < g.N; j += 256) {
+        if (j + 3 < g.N) {
+          const float4 r = cls ? *reinterpret_cast<const float4 *>(g.R + i * g.ldr + j)
+                               : float4{0.f, 0.f, 0.f, 0.f};
+          double2 e0{0.0, 0.0}, e1{0.0, 0.0};
+          if (!cls) {
+            e0 = *reinterpret_cast<const double2 *>(g.Ee + (i - g.n_h) * g.lde + j);
+            e1 = *reinterpret_cast<const double2 *>(g.Ee + (i - g.n_h) * g.lde + j + 2);
+          }
+          float4 q[EPI_F32_QMAX];
+#pragma unroll
+          for (int u = 0; u < EPI_F32_QMAX; ++u)
+            q[u] = u < nq ? *reinterpret_cast<const float4 *>(g.Q + qo[u] + j)
+                          : float4{0.f, 0.f, 0.f, 0.f};
+          const float4 yk = g.Yk ? *reinterpret_cast<const float4 *>(g.Yk + i * g.ldyk + j)
+                                 : float4{0.f, 0.f, 0.f, 0.f};
+          const float4 yp = g.Yp ? *reinterpret_cast<const float4 *>(g.Yp + i * g.ldyp + j)
+                                 : float4{0.f, 0.f, 0.f, 0.f};
+          float qv[EPI_F32_QMAX];
+#pragma unroll
+          for (int u = 0; u < EPI_F32_QMAX; ++u) qv[u] = q[u].x;
+          elem(j, r.x, qv, e0.x, yk.x, yp.x);
+#pragma unroll
+          for (int u = 0; u < EPI_F32_QMAX; ++u) qv[u] = q[u].y;
+          elem(j + 1, r.y, qv, e0.y, yk.y, yp.y);
+#pragma unroll
+          for (int u = 0; u < EPI_F32_QMAX; ++u) qv[u] = q[u].z;
+          elem(j + 2, r.z, qv, e1.x, yk.z, yp.z);
+#pragma unroll
+          for (int u = 0; u < EPI_F32_QMAX; ++u) qv[u] = q[u].w;
+          elem(j + 3, r.w, qv, e1.y, yk.w, yp.w);
+        } else {
+          for (int jj = j; jj < g.N; ++jj) {
+            float qv[EPI_F32_QMAX];
+#pragma unroll
+            for (int u = 0; u < EPI_F32_QMAX; ++u) qv[u] = u < nq ? g.Q[qo[u] + jj] : 0.f;
+            elem(jj, cls ? g.R[i * g.ldr + jj] : 0.f, qv,
+                 cls ? 0.0 : g.Ee[(i - g.n_h) * g.lde + jj], g.Yk ? g.Yk[i * g.ldyk + jj] : 0.f,
+                 g.Yp ? g.Yp[i * g.ldyp + jj] : 0.f);
+          }
+        }
+      }
+    } else {
+      for (int j = threadIdx.x; j < g.N; j += 64) {
+        float v;
+        if (cls) {
+          float s = g.R[i * g.ldr + j];
+          for (int p = p0; p < p1; ++p) s += g.Q[(int64_t)g.qidx[p] * g.ldq + j];
+          v = dr * s;
+        } else {
+          v = (float)g.Ee[(i - g.n_h) * g.lde + j];
+        }
+        v *= gc1;
+        if (g.Yk) v += gc2 * g.Yk[i * g.ldyk + j];
+        if (g.Yp) v += gc3 * g.Yp[i * g.ldyp + j];
+        g.Out[i * g.ldo + j] = v;
+        omax = absmax(omax, v);
+      }
     }
   }
   if (g.mx) {

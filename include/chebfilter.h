@@ -17,7 +17,9 @@
  *    chebfilter_last_error() returns a message for the last failure.
  *  - Block arguments (X, Y) are DEVICE pointers to FP64 matrices, row-major
  *    [n][ld] with n = n_h + n_e rows (classical rows first) and ld >= N
- *    columns; the caller owns them.  Y must not overlap X.
+ *    columns; the caller owns them.  Y must not overlap X.  Any ld works; an
+ *    ld that is a multiple of 16 (with 128-byte aligned blocks) puts every
+ *    row segment the kernels gather on a cache-line boundary, which is faster.
  *  - Work is enqueued on the context's stream and is asynchronous unless an
  *    entry point says it synchronises.  Calls on one context must not
  *    overlap (the context is not thread-safe).
@@ -77,7 +79,9 @@ typedef struct {
                                 col_chunk columns (the filter and the products are
                                 column-independent; the projection works on column
                                 slabs), so device workspace grows with col_chunk, not
-                                with N.  Batches ignore it.                             */
+                                with N.  The work blocks' leading dimension is
+                                col_chunk rounded up to a multiple of 16.  Batches
+                                ignore it.                                             */
   int32_t check_finite;      /* nonzero: filter/rayleigh_ritz check outputs for NaN/Inf */
 } cf_options;
 

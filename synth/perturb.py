@@ -68,3 +68,37 @@ def sequence(prob, steps: int, seed: int = 0):
     rng = np.random.default_rng(seed)
     for _ in range(steps):
         yield perturbed_H_cc(prob, smooth_field(rng, mesh.lo, mesh.length))
+
+
+# ---------------------------------------------------------------------------
+# The same field recipe evaluated on the device at the plain cells' Gauss
+# points, for sequences whose operator is rebuilt on the device each step
+# (the consistent quadrature term of the perturbation instead of a lumped
+# diagonal; cells sharing a DOF with an enriched cell keep the unperturbed
+# potential, for the reason given in the module notes).
+# ---------------------------------------------------------------------------
+def field_draw(rng: np.random.Generator, lo: float, length: float, n_gauss: int = 8,
+               sigma: float = 6.0, amp: float = 0.05):
+    """One step's field parameters, drawn in the order smooth_field draws them."""
+    centres = lo + length * rng.uniform(size=(n_gauss, 3))
+    amps = rng.uniform(-amp, amp, size=n_gauss)
+    return centres, amps, sigma
+
+
+def field_at(pts, centres, amps, sigma):
+    """dV at device points pts [Q, 3] (float64 CUDA tensor) for drawn parameters."""
+    import torch
+    out = torch.zeros(pts.shape[0], dtype=pts.dtype, device=pts.device)
+    for c, a in zip(np.asarray(centres, dtype=np.float64), np.asarray(amps, dtype=np.float64)):
+        d2 = ((pts - torch.as_tensor(c, dtype=pts.dtype, device=pts.device)) ** 2).sum(dim=1)
+        out += float(a) * torch.exp(d2 * (-0.5 / sigma ** 2))
+    return out
+
+
+def plain_cell_sets(prob):
+    """(plain cells, far plain cells): cells without enrichment functions, and
+    those of them that share no DOF with a cell carrying enrichment functions."""
+    ep = np.asarray(prob.enr_ptr)
+    plain = np.nonzero(ep[1:] == ep[:-1])[0].astype(np.int32)
+    far = far_cells(prob)
+    return plain, plain[far[plain]]

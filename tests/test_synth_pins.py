@@ -245,3 +245,22 @@ def test_generation_is_deterministic_in_worker_count():
     for f in ("H_cc", "H_ec", "M_ec", "H_ee", "M_ee"):
         assert np.array_equal(getattr(b, f), getattr(c, f))
         assert np.allclose(getattr(a, f), getattr(b, f), rtol=1e-12, atol=1e-14)
+
+
+def test_device_field_recipe_matches_host_field():
+    """The perturbation field evaluated as tensors (used where the operator is
+    rebuilt on the device each step) is the host recipe: same draws in the
+    same order, the same values to rounding."""
+    import torch
+    from synth import perturb
+    rng_a, rng_b = np.random.default_rng(5), np.random.default_rng(5)
+    f = perturb.smooth_field(rng_a, -24.0, 48.0)
+    c, a, sg = perturb.field_draw(rng_b, -24.0, 48.0)
+    pts = np.random.default_rng(6).uniform(-24.0, 24.0, (500, 3))
+    ref = f(pts)
+    got = perturb.field_at(torch.tensor(pts), c, a, sg).numpy()
+    assert np.abs(got - ref).max() <= 1e-15 * max(1.0, np.abs(ref).max())
+    # the next draws continue in step
+    f2 = perturb.smooth_field(rng_a, -24.0, 48.0)
+    c2, a2, sg2 = perturb.field_draw(rng_b, -24.0, 48.0)
+    assert np.abs(perturb.field_at(torch.tensor(pts), c2, a2, sg2).numpy() - f2(pts)).max() < 1e-15

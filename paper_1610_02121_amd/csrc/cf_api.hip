@@ -76,6 +76,10 @@ struct cf_ctx {
   // launches take them in this order, so the longest workgroups start first
   // (their output rows do not depend on the order)
   int32_t *ecells_part = nullptr;
+  // work items of the FP64 coupling partials: (position in ecells_part) * 32
+  // + row-block group, laid out so that a cell's groups share an XCD; -1 pads
+  int32_t *epitems = nullptr;
+  int nepitems = 0;
   int32_t *epos_part = nullptr;             // positions in ecells of the cells of ecells_part
   int necells = 0;
   int64_t *aptr = nullptr;
@@ -303,7 +307,7 @@ static cf_status core_apply_H(cf_ctx *c, const double *X, int64_t ldx, double *Y
   {
     Scope sc(c, "enr_gemm");
     HIPCHK(c, launch_enr_part(c->stream, c->HT, c->MT, c->toff, c->tld, c->eptr, c->dofp, c->ecells_part,
-                              c->necells, X, ldx, 1.0, nullptr, 0, nullptr, 0.0, c->P, c->ldw,
+                              c->necells, c->epitems, c->nepitems, X, ldx, 1.0, nullptr, 0, nullptr, 0.0, c->P, c->ldw,
                               N));
     HIPCHK(c, launch_enr_reduce(c->stream, (int)c->n_e, c->aptr, c->alist, c->P, c->ldw, 1.0,
                                 nullptr, 0, 0.0, c->Hee, Xe, ldx, Ye, ldy, N));
@@ -326,7 +330,7 @@ static cf_status core_apply_M(cf_ctx *c, const double *X, int64_t ldx, double *Y
   if (c->n_e > 0) {
     Scope sc(c, "enr_gemm");
     HIPCHK(c, launch_enr_part(c->stream, c->HT, c->MT, c->toff, c->tld, c->eptr, c->dofp, c->ecells_part,
-                              c->necells, nullptr, 0, 0.0, X, ldx, nullptr, 1.0, c->P, c->ldw,
+                              c->necells, c->epitems, c->nepitems, nullptr, 0, 0.0, X, ldx, nullptr, 1.0, c->P, c->ldw,
                               N));
     HIPCHK(c, launch_enr_reduce(c->stream, (int)c->n_e, c->aptr, c->alist, c->P, c->ldw, 1.0,
                                 nullptr, 0, 0.0, c->Mee, Xe, ldx, Ye, ldy, N));
@@ -356,7 +360,7 @@ static cf_status core_apply_Sinv(cf_ctx *c, const double *X, int64_t ldx, double
   if (c->n_e > 0) {
     Scope sc(c, "enr_gemm");
     HIPCHK(c, launch_enr_part(c->stream, c->HT, c->MT, c->toff, c->tld, c->eptr, c->dofp, c->ecells_part,
-                              c->necells, nullptr, 0, 0.0, X, ldx, c->dinv, -1.0, c->P, c->ldw,
+                              c->necells, c->epitems, c->nepitems, nullptr, 0, 0.0, X, ldx, c->dinv, -1.0, c->P, c->ldw,
                               n));
     HIPCHK(c, launch_enr_reduce(c->stream, (int)c->n_e, c->aptr, c->alist, c->P, c->ldw, 1.0,
                                 X + c->n_h * ldx, ldx, 1.0, nullptr, nullptr, 0, c->Wb, c->ldw,
@@ -397,8 +401,8 @@ static cf_status core_htilde_step(cf_ctx *c, const double *Xin, int64_t ldxin, i
     {
       Scope sc(c, "enr_part");
       HIPCHK(c, launch_enr_part(c->stream, c->HT, c->MT, c->toff, c->tld, c->eptr, c->dofp,
-                                c->ecells_part, c->necells, Xin, ldxin, 1.0, c->R, ldr, c->dinv, -1.0,
-                                c->P, c->ldw, N));
+                                c->ecells_part, c->necells, c->epitems, c->nepitems, Xin, ldxin,
+                                1.0, c->R, ldr, c->dinv, -1.0, c->P, c->ldw, N));
     }
     {
       Scope sc(c, "enr_reduce");
@@ -1055,6 +1059,31 @@ static cf_status do_init(const cf_problem *pr, const cf_options *opt, cf_ctx *c)
         return ep[elist[x] + 1] - ep[elist[x]] > ep[elist[y] + 1] - ep[elist[y]];
       });
       for (size_t q = 0; q < perm.size(); ++q) plist[q] = elist[perm[q]];
+      // items of the coupling partials: cells of 3 or more 16-row blocks take
+      // one workgroup per group of 4 blocks.  Each cell (heaviest first) goes
+      // to the least loaded of 8 queues, one per XCD (workgroup id mod 8), so
+      // the groups of a cell gather their rows through one L2.
+      {
+        std::vector<std::vector<int32_t>> xq(8);
+        std::vector<int64_t> xw(8, 0);
+        for (size_t q = 0; q < plist.size(); ++q) {
+          const int nmb = tld[plist[q]] >> 4;
+          const int ng = nmb >= 3 ? (nmb + 3) / 4 : 1;
+          const int x = (int)(std::min_element(xw.begin(), xw.end()) - xw.begin());
+          for (int g = 0; g < ng; ++g) xq[x].push_back((int32_t)(q << 5) | g);
+          xw[x] += nmb;
+        }
+        size_t len = 0;
+        for (auto &v : xq) len = std::max(len, v.size());
+        std::vector<int32_t> items(8 * len, -1);
+        for (int x = 0; x < 8; ++x)
+          for (size_t i = 0; i < xq[x].size(); ++i) items[8 * i + x] = xq[x][i];
+        c->nepitems = (int)items.size();
+        STCHK(dalloc(c, &c->epitems, std::max<size_t>(items.size(), 1)));
+        if (!items.empty())
+          HIPCHK(c, hipMemcpy(c->epitems, items.data(), items.size() * sizeof(int32_t),
+                              hipMemcpyHostToDevice));
+      }
       STCHK(dalloc(c, &c->ecells_part, std::max<size_t>(plist.size(), 1)));
       STCHK(dalloc(c, &c->epos_part, std::max<size_t>(perm.size(), 1)));
       if (!plist.empty()) {
@@ -2880,7 +2909,8 @@ static cf_status rebuild_hmod(cf_ctx *c) {
     g.Out = c->U; g.ldo = lw;
     HIPCHK(c, launch_epilogue(c->stream, g));
     HIPCHK(c, launch_enr_part(c->stream, c->HT, c->MT, c->toff, c->tld, c->eptr, c->dofp,
-                              c->ecells_part, c->necells, nullptr, 0, 0.0, c->U, lw, nullptr, 1.0,
+                              c->ecells_part, c->necells, c->epitems, c->nepitems, nullptr, 0, 0.0,
+                              c->U, lw, nullptr, 1.0,
                               c->P, lw, nb));
     HIPCHK(c, launch_enr_reduce(c->stream, (int)n_e, c->aptr, c->alist, c->P, lw, -1.0,
                                 c->Hee + j0, n_e, 1.0, nullptr, nullptr, 0, c->Hmod + j0, n_e, nb));

@@ -67,11 +67,13 @@ hipError_t launch_cell_gemm(hipStream_t s, const double *Hp, const int32_t *dofp
 // Coupling partials of the enriched cells (transposed per-cell blocks HT, MT at
 // offsets toff with row length tld):
 //   P[k0+k, :] = cH sum_a H^ec_e[k,a] X[dof(e,a), :] + cM sum_a M^ec_e[k,a] rs[dof] R[dof(e,a), :]
+// Single columns take one workgroup per cell of `cells`; blocks take one per
+// item of `items` (position in `cells` * 32 + row-block group, -1 = padding).
 hipError_t launch_enr_part(hipStream_t s, const double *HT, const double *MT, const int64_t *toff,
                            const int32_t *tld, const int64_t *eptr, const int32_t *dofp,
-                           const int32_t *cells, int ncells, const double *X, int64_t ldx,
-                           double cH, const double *R, int64_t ldr, const double *rs, double cM,
-                           double *P, int64_t ldp, int N);
+                           const int32_t *cells, int ncells, const int32_t *items, int nitems,
+                           const double *X, int64_t ldx, double cH, const double *R, int64_t ldr,
+                           const double *rs, double cM, double *P, int64_t ldp, int N);
 
 // Transposed coupling products of the enriched cells into the cell-local buffer:
 //   Q[128 e' + a, :] = sum_k (cU H^ec_e[k,a] U[idx_k, :] + cV M^ec_e[k,a] V[idx_k, :])

@@ -608,7 +608,7 @@ __device__ __forceinline__ void epilogue_f32_body(const EpiArgsF &g, int64_t b0,
     }
     const int nq = p1 - p0;
     // one element, the loads of its buffer rows given
-    auto elem = [&](int j, float r, const float *qv, double e, float yk, float yp) {
+    auto elem = [&](float r, const float *qv, double e, float yk, float yp) {
       float v;
       if (cls) {
         float s = r;
@@ -620,8 +620,8 @@ __device__ __forceinline__ void epilogue_f32_body(const EpiArgsF &g, int64_t b0,
       v *= gc1;
       if (g.Yk) v += gc2 * yk;
       if (g.Yp) v += gc3 * yp;
-      g.Out[i * g.ldo + j] = v;
       omax = absmax(omax, v);
+      return v;
     };
     if (vec && nq <= EPI_F32_QMAX) {
       int64_t qo[EPI_F32_QMAX];
@@ -646,26 +646,28 @@ __device__ __forceinline__ void epilogue_f32_body(const EpiArgsF &g, int64_t b0,
           const float4 yp = g.Yp ? *reinterpret_cast<const float4 *>(g.Yp + i * g.ldyp + j)
                                  : float4{0.f, 0.f, 0.f, 0.f};
           float qv[EPI_F32_QMAX];
+          float4 o;
 #pragma unroll
           for (int u = 0; u < EPI_F32_QMAX; ++u) qv[u] = q[u].x;
-          elem(j, r.x, qv, e0.x, yk.x, yp.x);
+          o.x = elem(r.x, qv, e0.x, yk.x, yp.x);
 #pragma unroll
           for (int u = 0; u < EPI_F32_QMAX; ++u) qv[u] = q[u].y;
-          elem(j + 1, r.y, qv, e0.y, yk.y, yp.y);
+          o.y = elem(r.y, qv, e0.y, yk.y, yp.y);
 #pragma unroll
           for (int u = 0; u < EPI_F32_QMAX; ++u) qv[u] = q[u].z;
-          elem(j + 2, r.z, qv, e1.x, yk.z, yp.z);
+          o.z = elem(r.z, qv, e1.x, yk.z, yp.z);
 #pragma unroll
           for (int u = 0; u < EPI_F32_QMAX; ++u) qv[u] = q[u].w;
-          elem(j + 3, r.w, qv, e1.y, yk.w, yp.w);
+          o.w = elem(r.w, qv, e1.y, yk.w, yp.w);
+          *reinterpret_cast<float4 *>(g.Out + i * g.ldo + j) = o;
         } else {
           for (int jj = j; jj < g.N; ++jj) {
             float qv[EPI_F32_QMAX];
 #pragma unroll
             for (int u = 0; u < EPI_F32_QMAX; ++u) qv[u] = u < nq ? g.Q[qo[u] + jj] : 0.f;
-            elem(jj, cls ? g.R[i * g.ldr + jj] : 0.f, qv,
-                 cls ? 0.0 : g.Ee[(i - g.n_h) * g.lde + jj], g.Yk ? g.Yk[i * g.ldyk + jj] : 0.f,
-                 g.Yp ? g.Yp[i * g.ldyp + jj] : 0.f);
+            g.Out[i * g.ldo + jj] =
+                elem(cls ? g.R[i * g.ldr + jj] : 0.f, qv, cls ? 0.0 : g.Ee[(i - g.n_h) * g.lde + jj],
+                     g.Yk ? g.Yk[i * g.ldyk + jj] : 0.f, g.Yp ? g.Yp[i * g.ldyp + jj] : 0.f);
           }
         }
       }

@@ -232,17 +232,17 @@ hipError_t launch_cell_gemm(hipStream_t s, const double *Hp, const int32_t *dofp
 }
 
 // ---------------------------------------------------------------------------
-// Enriched-cell coupling partials (one workgroup per enriched cell, walking
-// column tiles of 16):
+// Enriched-cell coupling partials (one workgroup per group of at most 4
+// output row blocks of an enriched cell, walking column tiles of 16):
 //   P[k0+k] = cH * sum_a H^ec_e[k][a] X[dof(e,a)]
 //           + cM * sum_a M^ec_e[k][a] s(dof) R[dof(e,a)]
 // The cell blocks are stored transposed, [NPAD][nap] with nap = the cell's
 // enrichment count padded to 16, so A-fragment loads are contiguous.  The
 // blocks are read from memory once per call: every wave keeps its A fragments
 // in registers while the column tiles stream by (cells with more than 64
-// enrichment functions take several passes over the gathered rows, 64 output
-// rows per pass).  The next tile's gathered rows are loaded into registers
-// during the current tile's MFMAs.
+// enrichment functions take one workgroup per 64 output rows, placed on one
+// XCD so that they gather the cell's rows through one L2).  The next tile's
+// gathered rows are loaded into registers during the current tile's MFMAs.
 // Either term is skipped when its input block is null.
 // ---------------------------------------------------------------------------
 // 8 waves split between the cell's 16-row output blocks and the 128 k (local
@@ -259,7 +259,7 @@ __device__ __forceinline__ void enr_part_body(
     const double *__restrict__ ht, const double *__restrict__ mt, int nap, int nmb, int na,
     int64_t k0, const int (&gd)[4], const double (&gsc)[4], const double *__restrict__ X,
     int64_t ldx, double cH, const double *__restrict__ R, int64_t ldr, double cM,
-    double *__restrict__ P, int64_t ldp, int cbeg, int cend, double *xs, double *rsm,
+    double *__restrict__ P, int64_t ldp, int cbeg, int cend, int g, double *xs, double *rsm,
     double *xch) {
   constexpr int PT = 16, LDX = PT + 1, PF = 4, RPP = 32;
   constexpr int KP = 8 / B, KS = NPAD / KP, NKS = KS / 4;
@@ -267,7 +267,7 @@ __device__ __forceinline__ void enr_part_body(
   const int li = lane & 15, kq = lane >> 4;
   const int wb = w % B, h = w / B;
   const int gj = tid % PT, gr = tid / PT;
-  for (int g = 0; B * g < nmb; ++g) {
+  {
     const int mb = B * g + wb;
     const bool act = mb < nmb;
     double aH[NKS], aM[NKS];
@@ -350,12 +350,16 @@ __device__ __forceinline__ void enr_part_body(
   }
 }
 
-// blockIdx.y picks one of gridDim.y contiguous ranges of column tiles.
+// A workgroup takes one item: a group of (at most) 4 output row blocks of one
+// enriched cell, item = (position in `cells`) * 32 + group; -1 items are
+// padding.  blockIdx.y picks one of gridDim.y contiguous ranges of column
+// tiles.
 __global__ __launch_bounds__(512, 2) void k_enr_part(
     const double *__restrict__ HT, const double *__restrict__ MT,
     const int64_t *__restrict__ toff, const int32_t *__restrict__ tld,
     const int64_t *__restrict__ eptr, const int32_t *__restrict__ dofp,
-    const int32_t *__restrict__ cells, const double *__restrict__ X, int64_t ldx, double cH,
+    const int32_t *__restrict__ cells, const int32_t *__restrict__ items,
+    const double *__restrict__ X, int64_t ldx, double cH,
     const double *__restrict__ R, int64_t ldr, const double *__restrict__ rs, double cM,
     double *__restrict__ P, int64_t ldp, int N) {
   constexpr int PT = 16, LDX = PT + 1, PF = 4, RPP = 32;
@@ -363,7 +367,9 @@ __global__ __launch_bounds__(512, 2) void k_enr_part(
   __shared__ double rsm[NPAD * LDX];
   __shared__ double xch[7 * 4 * 64];      // partial sums of k parts 1..KP-1
   const int tid = threadIdx.x;
-  const int cell = cells[blockIdx.x];
+  const int item = items[blockIdx.x];
+  if (item < 0) return;                  // uniform for the workgroup
+  const int cell = cells[item >> 5], grp = item & 31;
   const int ntile = (N + PT - 1) / PT;
   const int cbeg = PT * ((ntile * (int)blockIdx.y) / (int)gridDim.y);
   const int cend = min(N, PT * ((ntile * ((int)blockIdx.y + 1)) / (int)gridDim.y));
@@ -384,13 +390,13 @@ __global__ __launch_bounds__(512, 2) void k_enr_part(
   if (cbeg >= cend) return;              // uniform for the workgroup
   if (nmb >= 3)
     enr_part_body<4>(ht, mt, nap, nmb, na, k0, gd, gsc, X, ldx, cH, R, ldr, cM, P, ldp, cbeg, cend,
-                     xs, rsm, xch);
+                     grp, xs, rsm, xch);
   else if (nmb == 2)
     enr_part_body<2>(ht, mt, nap, nmb, na, k0, gd, gsc, X, ldx, cH, R, ldr, cM, P, ldp, cbeg, cend,
-                     xs, rsm, xch);
+                     0, xs, rsm, xch);
   else
     enr_part_body<1>(ht, mt, nap, nmb, na, k0, gd, gsc, X, ldx, cH, R, ldr, cM, P, ldp, cbeg, cend,
-                     xs, rsm, xch);
+                     0, xs, rsm, xch);
 }
 
 // Single-column form (the Lanczos vectors): the coupling blocks stream
@@ -440,19 +446,19 @@ __global__ __launch_bounds__(256) void k_enr_part_vec(
 
 hipError_t launch_enr_part(hipStream_t s, const double *HT, const double *MT, const int64_t *toff,
                            const int32_t *tld, const int64_t *eptr, const int32_t *dofp,
-                           const int32_t *cells, int ncells, const double *X, int64_t ldx,
-                           double cH, const double *R, int64_t ldr, const double *rs, double cM,
-                           double *P, int64_t ldp, int N) {
+                           const int32_t *cells, int ncells, const int32_t *items, int nitems,
+                           const double *X, int64_t ldx, double cH, const double *R, int64_t ldr,
+                           const double *rs, double cM, double *P, int64_t ldp, int N) {
   if (ncells <= 0 || N <= 0) return hipSuccess;
   if (N == 1) {
     hipLaunchKernelGGL(k_enr_part_vec, dim3(ncells), dim3(256), 0, s, HT, MT, toff, tld, eptr,
                        dofp, cells, X, ldx, cH, R, ldr, rs, cM, P, ldp);
     return hipGetLastError();
   }
-  // one column range per cell (splitting the columns over 2-4 workgroups per
+  // one column range per item (splitting the columns over 2-4 workgroups per
   // cell measured slower on the 30-atom workload: the blocks are re-read)
-  hipLaunchKernelGGL(k_enr_part, dim3(ncells, 1), dim3(512), 0, s, HT, MT, toff, tld, eptr, dofp,
-                     cells, X, ldx, cH, R, ldr, rs, cM, P, ldp, N);
+  hipLaunchKernelGGL(k_enr_part, dim3(nitems, 1), dim3(512), 0, s, HT, MT, toff, tld, eptr, dofp,
+                     cells, items, X, ldx, cH, R, ldr, rs, cM, P, ldp, N);
   return hipGetLastError();
 }
 

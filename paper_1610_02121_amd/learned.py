@@ -69,24 +69,34 @@ def init_params(seed: int = 0, n_in: int = N_IN, width: int = WIDTH, depth: int 
 
 
 def run_sequence(ctx, prob, N: int, wanted: int, steps: int, seed: int, chooser, v0,
-                 label_k: int = 0, X0=None, log=None, lanczos_fallback=None):
+                 label_k: int = 0, X0=None, log=None, lanczos_fallback=None, apply_step=None):
     """One self-consistent-step sequence on a context.  chooser(step, feats,
     theta) -> (a, b, m, used_lanczos).  If the projection after the filter
     finds the block rank deficient and lanczos_fallback is given, the step is
-    redone with it ("rescued").  Returns per-step records with the features,
-    the bounds used, timings and (if label_k) the labels."""
+    redone with it ("rescued").  The operator of step s is the host
+    perturbation sequence of `seed` (re-uploaded cell blocks), or whatever
+    apply_step(s) sets on the device.  Returns per-step records with the
+    features, the bounds used, timings and (if label_k) the labels."""
     import torch
-    from .binding import ChebFilterError
+    from .binding import ChebFilterError, empty_block
     from synth import configs, perturb
     dev = v0.device
-    X = torch.tensor(configs.initial_block(prob, N, seed=seed) if X0 is None else X0,
-                     dtype=torch.float64, device=dev)
-    Y = torch.empty_like(X)
+    X = empty_block(prob.n, N, dev)
+    X.copy_(torch.as_tensor(configs.initial_block(prob, N, seed=seed) if X0 is None else X0))
+    Y = empty_block(prob.n, N, dev)
     theta = ctx.rayleigh_ritz(X)
     feats, recs = [], []
-    seq = perturb.sequence(prob, steps, seed=seed)
-    for s, Hs in enumerate(seq):
-        ctx.update_H_cc(Hs)
+    if apply_step is None:
+        def host_steps():
+            for Hs in perturb.sequence(prob, steps, seed=seed):
+                ctx.update_H_cc(Hs)
+                yield
+    else:
+        def host_steps():
+            for s in range(steps):
+                apply_step(s)
+                yield
+    for s, _ in enumerate(host_steps()):
         # the projection of the new operator on the current subspace
         theta_cur = ctx.rayleigh_ritz(X)
         if not feats:
@@ -128,6 +138,124 @@ def run_sequence(ctx, prob, N: int, wanted: int, steps: int, seed: int, chooser,
             log(f"step {s}: a={a:.4f} b={b:.3f} m={m} lanczos={bool(fb)} "
                 f"res_max={rec['res_max']:.3e}")
     return recs, X
+
+
+class DeviceSteps:
+    """Operator update of a self-consistent-step sequence on the device: every
+    plain cell's block assembled once from the base potential V0 at its Gauss
+    points (chebfilter_assemble_cells), then per step the far plain cells'
+    blocks (cells sharing no DOF with an enriched cell) from V0 + dV, dV a
+    fresh seeded smooth field (synth.perturb.field_draw / field_at)."""
+
+    def __init__(self, ctx, prob, plain, far, V0_plain):
+        import torch
+        from synth.assemble import plain_points, plain_tables
+        B, w, K, _ = plain_tables(prob)
+        ctx.assembly_tables(B, w, K)
+        dev = torch.device("cuda", torch.cuda.current_device())
+        V0 = torch.tensor(np.asarray(V0_plain).reshape(len(plain), -1), dtype=torch.float64,
+                          device=dev)
+        ctx.assemble_cells(plain, V0)
+        pos = torch.as_tensor(np.searchsorted(plain, far), device=dev)
+        self.V0f = V0[pos].contiguous()
+        del V0
+        self.pts = torch.tensor(plain_points(prob, far).reshape(-1, 3), dtype=torch.float64,
+                                device=dev)
+        self.ctx, self.far, self.nq = ctx, np.asarray(far, dtype=np.int32), B.shape[0]
+        mesh = prob.meta["mesh"]
+        self.lo, self.length = mesh.lo, mesh.length
+        self.rng = np.random.default_rng(0)
+
+    def start(self, seed: int):
+        """Begin a new sequence (its fields drawn from `seed`)."""
+        self.rng = np.random.default_rng(seed)
+        return self
+
+    def __call__(self, s: int):
+        from synth import perturb
+        c, a, sg = perturb.field_draw(self.rng, self.lo, self.length)
+        dV = perturb.field_at(self.pts, c, a, sg).reshape(len(self.far), self.nq)
+        self.ctx.assemble_cells(self.far, self.V0f + dV)
+
+
+def run_paths(ctx, prob, N: int, wanted: int, steps: int, seed: int, choosers: dict, v0,
+              apply_step, ref_steps=(), ref_passes: int = 10, ref_tol: float = 1e-9, log=None,
+              lanczos_fallback=None):
+    """Several choosers on one operator sequence in lockstep (one context, one
+    block per path plus a spare): at each step the operator is updated once,
+    then every path takes its filter pass and projection from its own
+    subspace.  At the steps in ref_steps (1-based) a reference is formed from
+    a copy of the first path's block: FP64 passes with the Lanczos bound and
+    the degree rule until the wanted Ritz values change by < ref_tol.
+    Returns ({name: records}, {step: reference Ritz values})."""
+    import torch
+    from .binding import ChebFilterError, empty_block
+    from synth import configs
+    dev = v0.device
+    X0 = torch.as_tensor(configs.initial_block(prob, N, seed=seed))
+    st = {}
+    for name in choosers:
+        X = empty_block(prob.n, N, dev)
+        X.copy_(X0)
+        st[name] = {"X": X, "feats": [], "recs": [], "theta": ctx.rayleigh_ritz(X)}
+    del X0
+    spare = empty_block(prob.n, N, dev)
+    refs = {}
+    first = next(iter(choosers))
+    for s in range(steps):
+        apply_step(s)
+        for name, chooser in choosers.items():
+            p = st[name]
+            theta_cur = ctx.rayleigh_ritz(p["X"])
+            if not p["feats"]:
+                res = ctx.residual_norms(p["X"], theta_cur)
+                _, b0 = ctx.lanczos_bounds(v0, 10)
+                p["feats"].append(step_features(theta_cur, theta_cur, wanted, b0, 40, res))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            a, b, m, fb = chooser(s, p["feats"], theta_cur)
+            t1 = time.perf_counter()
+            ctx.filter(p["X"], m, a, b, Y=spare)
+            rescued = False
+            try:
+                th = ctx.rayleigh_ritz(spare)
+            except ChebFilterError as exc:
+                if exc.status != 3 or lanczos_fallback is None:
+                    raise
+                a, b, m, fb = lanczos_fallback(s, p["feats"], theta_cur)
+                ctx.filter(p["X"], m, a, b, Y=spare)
+                th = ctx.rayleigh_ritz(spare)
+                rescued = True
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            res = ctx.residual_norms(spare, th)
+            p["feats"].append(step_features(th, theta_cur, wanted, b, m, res))
+            p["recs"].append(dict(step=s, a=a, b=b, m=m, fallback=bool(fb), rescued=rescued,
+                                  t_bounds=t1 - t0, t_pass=t2 - t1, theta=th.copy(),
+                                  res_max=float(np.max(res[:wanted]))))
+            p["X"], spare = spare, p["X"]
+            if log:
+                log(f"step {s} {name}: a={a:.4f} b={b:.3f} m={m} lanczos={bool(fb)} "
+                    f"res_max={p['recs'][-1]['res_max']:.3e} pass {t2 - t1:.2f}s")
+        if s + 1 in ref_steps:
+            R = empty_block(prob.n, N, dev)
+            R.copy_(st[first]["X"])
+            th = ctx.rayleigh_ritz(R)
+            for it in range(ref_passes):
+                _, b = ctx.lanczos_bounds(v0, 10)
+                mref = degree_rule(float(th[0]), float(th[wanted - 1]), float(th[-1]), b)
+                ctx.filter(R, mref, float(th[-1]), b, Y=spare)
+                thn = ctx.rayleigh_ritz(spare)
+                R, spare = spare, R
+                d = float(np.abs(thn[:wanted] - th[:wanted]).max())
+                th = thn
+                if d < ref_tol and it >= 1:
+                    break
+            refs[s + 1] = th[:wanted].copy()
+            del R                       # the other of the two buffers stays the spare
+            if log:
+                log(f"reference at step {s + 1}: {it + 1} passes, last change {d:.2e}")
+    return {k: v["recs"] for k, v in st.items()}, refs
 
 
 def lanczos_chooser(ctx, v0, wanted: int, k: int = 10):

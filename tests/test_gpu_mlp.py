@@ -200,3 +200,52 @@ def test_learned_sequence_against_oracle_eigenvalues(hydrogen_cfg1):
     assert errs["learned"][-1] <= max(errs["lanczos"][-1], 1e-8)
     assert used["learned"] > 0, "the guard rejected every prediction"
     ctx.close()
+
+
+def test_device_steps_and_lockstep_paths(si_small):
+    """The device-side operator update of the self-consistent-step studies
+    (learned.DeviceSteps): after set-up every plain cell's block equals the
+    host-assembled one (the same Gauss rule and potential); after a step the
+    far plain cells carry the base potential plus that step's field and the
+    other plain cells are unchanged.  The lockstep runner (learned.run_paths)
+    gives two paths with the same chooser the same Ritz values bit for bit,
+    and its reference agrees with them once converged."""
+    from paper_1610_02121_amd import Context
+    from paper_1610_02121_amd import learned as L
+    from synth import perturb
+    from synth.assemble import plain_points, plain_tables, potential_at_points
+    prob = si_small
+    plain, far = perturb.plain_cell_sets(prob)
+    near = np.setdiff1d(plain, far)
+    assert far.size and near.size
+    V0 = potential_at_points(prob.meta["potential"], plain_points(prob, plain).reshape(-1, 3))
+    ctx = Context(prob, max_cols=24)
+    steps = L.DeviceSteps(ctx, prob, plain, far, V0)
+    H_all = np.asarray(prob.H_cc)
+    H0 = ctx.get_H_cc(plain)
+    assert np.abs(H0 - H_all[plain]).max() < 1e-12 * np.abs(H_all[plain]).max()
+    # one step: far cells from V0 + dV (the field drawn from the step's seed)
+    steps.start(11)(0)
+    mesh = prob.meta["mesh"]
+    c, a, sg = perturb.field_draw(np.random.default_rng(11), mesh.lo, mesh.length)
+    B, w, K, _ = plain_tables(prob)
+    pts = plain_points(prob, far)
+    dV = perturb.field_at(torch.tensor(pts.reshape(-1, 3)), c, a, sg).numpy().reshape(len(far), -1)
+    pos = np.searchsorted(plain, far)
+    Vf = np.asarray(V0).reshape(len(plain), -1)[pos] + dV
+    want = K[None] + np.einsum("qa,cq,qb->cab", B, Vf * w[None, :], B)
+    Hf = ctx.get_H_cc(far)
+    assert np.abs(Hf - want).max() < 1e-12 * np.abs(want).max()
+    assert np.array_equal(ctx.get_H_cc(near), H0[np.searchsorted(plain, near)])
+    # lockstep paths
+    v0 = dev(np.random.default_rng(12).standard_normal(prob.n)).reshape(-1)
+    ch = {"p": L.lanczos_chooser(ctx, v0, 20), "q": L.lanczos_chooser(ctx, v0, 20)}
+    recs, refs = L.run_paths(ctx, prob, 24, 20, 4, seed=13, choosers=ch, v0=v0,
+                             apply_step=steps.start(14), ref_steps=(4,))
+    for rp, rq in zip(recs["p"], recs["q"]):
+        assert np.array_equal(rp["theta"], rq["theta"])
+        assert rp["m"] == rq["m"] and rp["b"] == rq["b"]
+    err = np.abs(recs["p"][-1]["theta"][:20] - refs[4]).max()
+    print(f"[device steps] far {far.size}, near {near.size}; path vs reference at step 4: {err:.2e}")
+    assert err < 1e-3 * np.abs(refs[4]).max()
+    ctx.close()

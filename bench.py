@@ -715,7 +715,7 @@ def run_scf(args):
     import numpy as np
     import torch
 
-    from paper_1610_02121_amd import Context, fermi_level
+    from paper_1610_02121_amd import Context, empty_block, fermi_level
     from synth import configs
     from synth.assemble import plain_tables
     from synth.basis import gll_rule

@@ -1079,7 +1079,7 @@ def learned_eval280(args):
     280-atom cluster: 30 self-consistent steps (a fresh seeded smooth field on
     the far plain cells' potential each step, rebuilt on the device), both
     paths in lockstep on one context from the atomic-orbital start, N = 600
-    vectors (560 wanted: the 1s and 2s bands), 256-column work blocks.  Judge:
+    vectors (560 wanted: the 1s and 2s bands), 256-column work blocks.  Accuracy:
     references at steps 10, 20 and 30 from the Lanczos path's block (FP64
     passes until the wanted Ritz values settle), and every step's largest
     residual norm of the wanted pairs."""

@@ -34,3 +34,39 @@ def test_traffic_reported_only_for_the_profiled_kernel_source(monkeypatch):
     assert bench.measured_traffic() is None
     monkeypatch.setattr(bench, "cell_kernel_source_hash", lambda: m.group(2))
     assert bench.measured_traffic() == int(m.group(1))
+
+
+def _undefined_globals(path):
+    """Names a function of the file reads as globals that the module never
+    binds and that are not builtins (what would raise NameError only when
+    that code path runs)."""
+    import builtins
+    import symtable
+    src = open(path).read()
+    top = symtable.symtable(src, path, "exec")
+    bound = {s.get_name() for s in top.get_symbols() if s.is_assigned() or s.is_imported()}
+    bound |= set(dir(builtins)) | {"__file__", "__name__"}
+    missing = set()
+
+    def walk(t):
+        for ch in t.get_children():
+            if ch.get_type() == "function":
+                for s in ch.get_symbols():
+                    if s.is_global() and s.is_referenced() and s.get_name() not in bound:
+                        missing.add((ch.get_name(), s.get_name()))
+            walk(ch)
+    walk(top)
+    return missing
+
+
+def test_host_scripts_bind_every_name_they_use():
+    """bench.py, the binding and the learned-bounds driver: every name a
+    function reads is bound somewhere (a local import in an enclosing scope
+    counts), so the rarely run modes fail on their arithmetic, not on a
+    missing import."""
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    for rel in ("bench.py", "__graft_entry__.py",
+                os.path.join("paper_1610_02121_amd", "binding.py"),
+                os.path.join("paper_1610_02121_amd", "learned.py")):
+        missing = _undefined_globals(os.path.join(root, rel))
+        assert not missing, (rel, sorted(missing))

@@ -60,13 +60,17 @@ def _undefined_globals(path):
 
 
 def test_host_scripts_bind_every_name_they_use():
-    """bench.py, the binding and the learned-bounds driver: every name a
-    function reads is bound somewhere (a local import in an enclosing scope
+    """bench.py, the binding, the learned-bounds driver, the generators and
+    the oracle: every name a function reads is bound somewhere (a local import in an enclosing scope
     counts), so the rarely run modes fail on their arithmetic, not on a
     missing import."""
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-    for rel in ("bench.py", "__graft_entry__.py",
-                os.path.join("paper_1610_02121_amd", "binding.py"),
-                os.path.join("paper_1610_02121_amd", "learned.py")):
+    import glob
+    rels = ["bench.py", "__graft_entry__.py",
+            os.path.join("paper_1610_02121_amd", "binding.py"),
+            os.path.join("paper_1610_02121_amd", "learned.py")]
+    for d in ("synth", "oracle"):
+        rels += sorted(os.path.relpath(f, root) for f in glob.glob(os.path.join(root, d, "*.py")))
+    for rel in rels:
         missing = _undefined_globals(os.path.join(root, rel))
         assert not missing, (rel, sorted(missing))
